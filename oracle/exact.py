@@ -1,0 +1,192 @@
+"""Exactly k-sparse recovery: Algorithm 1 (NoiselessSparseFFT) in FP64.
+
+Per round r (NoiselessSparseFFTInner), with B_r = max(B >> r, b_min) bins and a
+w_r = w B_r / B window (params.round_bins):
+  * draw sigma odd and b uniform (rng.py, counter (r, 0, 0));
+  * u  = HashToBins(x, zhat, P_{sigma,0,b}),  u' = HashToBins(x, zhat, P_{sigma,1,b});
+  * J  = { j : |u_j| > theta };  stop after `patience` consecutive rounds with
+    J empty (or after `rounds` rounds);
+  * for j in J: the phase of u_j / u'_j equals 2 pi sigma i / n for an isolated
+    coefficient (the exact-estimation lemma of Section 3), so
+        p = round(phi(u_j / u'_j) n / (2 pi)) mod n,   i = sigma^{-1} p mod n;
+    accept i only if h(i) = j and G'_{-o(i)} >= g_min, with value
+        v = u_j / G'_{-o(i)}
+    (the HashToBins lemma with a single term; equals the paper's round(u_j)
+    when G' = 1 and the spectrum is integral);
+  * zhat_i += v.
+Readings: phi is taken in [0, 2 pi); round() is half-up; the bin check keeps
+every accepted i tied to the one bin that can hold it, so the writes of one
+round never conflict.  The phase is computed as the argument of
+u_j * conj(u'_j), which has the phase of u_j / u'_j.
+
+After the last round the values are re-estimated in FP64: for each i in
+supp(zhat) and each round r whose window value G'_{-o_r(i)} >= g_min,
+    e_r = (u_raw_r[h_r(i)] - sum_{i' != i, h_r(i') = h_r(i)} G'_{-o_r(i')} zhat_{i'}) / G'_{-o_r(i)}
+(the EstimateValues estimate of Algorithm 2 with a = 0, applied to x minus the
+other recovered coefficients) and the value is the coordinate-wise median of
+the e_r.  The output keeps entries with |value| > theta/2, at most cap of them
+(largest magnitude first, then smaller index), in ascending index order.
+
+The paper-literal variant (params.literal) keeps v = round(u_j) and writes
+without the bin/window checks; conflicting writes keep the larger |u_j|,
+then the smaller j.
+"""
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .hashing import bin_offset, hash_to_bins_raw, subtract_zhat
+from .params import SfftParams, complex_median
+from .rng import draw_b, draw_sigma, inverse_mod
+from .window import gprime, window_time
+
+TWO_PI = 2.0 * math.pi
+
+
+@dataclass
+class Margins:
+    """Smallest distance of any floating-point decision from its threshold."""
+
+    threshold: float = math.inf   # | |u_j| - theta |
+    rounding: float = math.inf    # distance of phi n / 2pi from a half-integer
+    gmin: float = math.inf        # | G' - g_min | for decoded candidates
+    output: float = math.inf      # | |value| - theta/2 |
+
+    def smallest(self):
+        return min(self.threshold, self.rounding, self.gmin, self.output)
+
+
+@dataclass
+class ExactResult:
+    indices: np.ndarray
+    values: np.ndarray
+    rounds_used: int
+    truncated: bool
+    zhat_decoded: dict
+    round_log: list = field(default_factory=list)   # (|J|, accepted) per round
+    raw: list = field(default_factory=list)         # (sigma, b, u0_raw, u1_raw) per round
+    margins: Margins = field(default_factory=Margins)
+
+
+def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Margins):
+    """Location and value of bin j of a B-bin hashing; returns (i, v) or None."""
+    n = p.n
+    z = u0j * np.conj(u1j)
+    phi = math.atan2(z.imag, z.real)
+    if phi < 0.0:
+        phi += TWO_PI
+    q = phi / TWO_PI * n
+    margins.rounding = min(margins.rounding, abs(q - math.floor(q) - 0.5))
+    pos = int(math.floor(q + 0.5)) % n
+    i = (sigma_inv * pos) % n
+    if p.literal:
+        return i, complex(round(u0j.real), round(u0j.imag))
+    h, o = bin_offset(i, sigma, b, n, B)
+    if h != j:
+        return None
+    g = gprime(-o, n, B, p.alpha, p.delta)
+    margins.gmin = min(margins.gmin, abs(g - p.g_min))
+    if g < p.g_min:
+        return None
+    return i, u0j / g
+
+
+def noiseless_sparse_fft(x, p: SfftParams) -> ExactResult:
+    x = np.asarray(x)
+    n = x.shape[-1]
+    assert n == p.n
+    zhat = {}
+    res = ExactResult(np.zeros(0, np.int64), np.zeros(0, np.complex128), 0, False, {})
+    rounds_used = p.rounds
+    empty_run = 0
+    for r in range(p.rounds):
+        sigma = draw_sigma(p.seed, n, r)
+        b = draw_b(p.seed, n, r)
+        sigma_inv = inverse_mod(sigma, n)
+        Br, wr = p.round_bins(r)
+        G = window_time(n, Br, wr, p.alpha, p.delta)
+        u0_raw = hash_to_bins_raw(x, sigma, 0, b, Br, G)
+        u1_raw = hash_to_bins_raw(x, sigma, 1, b, Br, G)
+        res.raw.append((sigma, b, u0_raw, u1_raw))
+        u0 = subtract_zhat(u0_raw, zhat, sigma, 0, b, Br, n, p.alpha, p.delta)
+        u1 = subtract_zhat(u1_raw, zhat, sigma, 1, b, Br, n, p.alpha, p.delta)
+        mag = np.abs(u0)
+        res.margins.threshold = min(res.margins.threshold, float(np.min(np.abs(mag - p.theta))))
+        J = [j for j in range(Br) if mag[j] > p.theta]
+        if not J:
+            res.round_log.append((0, 0))
+            empty_run += 1
+            if empty_run >= p.patience:
+                rounds_used = r + 1
+                break
+            continue
+        empty_run = 0
+        updates = {}
+        best = {}
+        for j in J:
+            got = decode_bin(u0[j], u1[j], j, sigma, sigma_inv, b, Br, p, res.margins)
+            if got is None:
+                continue
+            i, v = got
+            if p.literal and i in updates:
+                # conflicting writes: larger |u_j| wins, then the smaller j
+                if (mag[j], -j) <= best[i]:
+                    continue
+            updates[i] = v
+            best[i] = (mag[j], -j)
+        for i in sorted(updates):
+            zhat[i] = zhat.get(i, 0.0 + 0.0j) + updates[i]
+        res.round_log.append((len(J), len(updates)))
+    res.rounds_used = rounds_used
+    res.zhat_decoded = dict(zhat)
+    values = reestimate(zhat, res.raw[:rounds_used], p) if not p.literal else dict(zhat)
+    _finish(res, values, p)
+    return res
+
+
+def reestimate(zhat, raw, p: SfftParams):
+    """FP64 median re-estimation of every zhat entry over the given rounds."""
+    n = p.n
+    keys = sorted(zhat)
+    out = {}
+    per_round = []
+    for (sigma, b, u0_raw, _u1) in raw:
+        B = len(u0_raw)
+        hg = {}
+        members = {}
+        for i in keys:
+            h, o = bin_offset(i, sigma, b, n, B)
+            hg[i] = (h, gprime(-o, n, B, p.alpha, p.delta))
+            members.setdefault(h, []).append(i)   # ascending index within a bin
+        per_round.append((u0_raw, hg, members))
+    for i in keys:
+        vals = []
+        for u0_raw, hg, members in per_round:
+            h, g = hg[i]
+            if g < p.g_min:
+                continue
+            others = 0.0 + 0.0j
+            for i2 in members[h]:
+                if i2 != i:
+                    others += hg[i2][1] * zhat[i2]
+            vals.append((u0_raw[h] - others) / g)
+        out[i] = complex_median(vals) if vals else zhat[i]
+    return out
+
+
+def _finish(res: ExactResult, values: dict, p: SfftParams):
+    half = 0.5 * p.theta
+    kept = []
+    for i, v in values.items():
+        res.margins.output = min(res.margins.output, abs(abs(v) - half))
+        if abs(v) > half:
+            kept.append((i, v))
+    cap = p.out_cap
+    if len(kept) > cap:
+        kept.sort(key=lambda e: (-abs(e[1]), e[0]))
+        kept = kept[:cap]
+        res.truncated = True
+    kept.sort(key=lambda e: e[0])
+    res.indices = np.array([e[0] for e in kept], dtype=np.int64)
+    res.values = np.array([e[1] for e in kept], dtype=np.complex128)

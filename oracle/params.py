@@ -1,0 +1,82 @@
+"""Parameters of one sparse FFT run (readings of the paper's Theta(.) constants).
+
+n, k      problem size and sparsity (Section 1 problem statement; n = 2^m per
+          Section 2 Assumptions)
+B, w      number of bins and window length (w a multiple of B)
+alpha     flat-window transition fraction (Section 2 flat window definition)
+delta     window accuracy (Section 2; the paper's 1/(4 n^2 L) is replaced by a
+          fixed floating-point level)
+theta     bin threshold; the paper's 1/2 for integer spectra (Algorithm 1) is a
+          plan parameter here because coefficients need not be integers.  The
+          default 1/4 (and g_min 0.4) avoid 1/2: with alpha = 1/2 and n/B a power
+          of two, the offset o = C n is an integer where G' equals 1/2 up to
+          rounding, which would make both tests exact ties.
+g_min     smallest G'_{-o(i)} accepted when a bin value is divided by the window
+b_min     exact mode: round r hashes into B_r = max(B >> r, b_min) bins with a
+          window of w_r = w B_r / B samples (NoiselessSparseFFT of Algorithm 1
+          shrinks the bin count with the remaining sparsity k_t = k / 2^t; alpha
+          stays fixed, so w_r shrinks with B_r).  b_min = B keeps B fixed.
+patience  exact mode: stop after this many consecutive rounds with J empty.  One
+          empty round is weak evidence: a remaining coefficient whose offset
+          falls where G' is small is hidden in that round (the large-offset
+          event of Section 3) with probability about alpha / 2.
+rounds    exact mode: maximum number of NoiselessSparseFFTInner rounds
+          general mode: number of SparseFFT rounds
+t, s      LocateInner region count and vote tolerance (Algorithm 3)
+R_loc     LocateInner measurements per level (Algorithm 3)
+R_est     EstimateValues measurements (Algorithm 2)
+cap       largest output size (defaults to k)
+literal   exact mode only: the paper-literal decode v = round(u_j) for integer
+          spectra, without the bin and window checks
+"""
+from dataclasses import dataclass
+
+
+@dataclass
+class SfftParams:
+    n: int
+    k: int
+    B: int
+    w: int
+    seed: int
+    alpha: float = 0.5
+    delta: float = 1e-9
+    theta: float = 0.25
+    g_min: float = 0.4
+    rounds: int = 8
+    b_min: int = 0
+    patience: int = 3
+    t: int = 16
+    s: float = 0.125
+    R_loc: int = 3
+    R_est: int = 7
+    cap: int = 0
+    literal: bool = False
+
+    def round_bins(self, r):
+        """(B_r, w_r) of exact-mode round r."""
+        floor = self.b_min if self.b_min > 0 else max(2, self.B >> 4)
+        Br = max(self.B >> r, min(floor, self.B))
+        return Br, self.w * Br // self.B
+
+    @property
+    def out_cap(self):
+        return self.cap if self.cap > 0 else self.k
+
+
+def complex_median(vals):
+    """Coordinate-wise median (separately in real and imaginary parts, as the
+    comment of EstimateValues in Algorithm 2 says); an even count takes the
+    mean of the two middle values."""
+    import numpy as np
+
+    v = np.asarray(vals, dtype=np.complex128)
+    return complex(_median_real(v.real), _median_real(v.imag))
+
+
+def _median_real(a):
+    s = sorted(float(x) for x in a)
+    m = len(s)
+    if m % 2:
+        return s[m // 2]
+    return 0.5 * (s[m // 2 - 1] + s[m // 2])

@@ -1,0 +1,192 @@
+"""Pins of exactly sparse recovery (Algorithm 1; Section 3 claims and lemmas;
+Section 5 reduction)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.exact import noiseless_sparse_fft
+from oracle.fft import naive_dft, unitary_dft
+from oracle.hashing import bin_offset, hash_to_bins_raw, perm_position
+from oracle.params import SfftParams, complex_median
+from oracle.rng import draw_b, draw_sigma
+from oracle.window import default_w, gprime, window_time
+
+import siggen
+
+
+def c1_params(seed, **kw):
+    n, k, B = 1 << 14, 16, 64
+    kw.setdefault("delta", 1e-12)
+    return SfftParams(n=n, k=k, B=B, w=default_w(n, B, 0.5, kw["delta"]), seed=seed,
+                      rounds=12, **kw)
+
+
+def test_isolated_flat_coefficient_decodes_exactly():
+    """The exact-estimation lemma: no collision and no large offset => exact i, v;
+    and |u_j| = |u'_j|."""
+    n, B, alpha, delta = 1 << 14, 64, 0.5, 1e-12
+    w = default_w(n, B, alpha, delta)
+    G = window_time(n, B, w, alpha, delta)
+    rng = np.random.default_rng(0)
+    for trial in range(20):
+        i0 = int(rng.integers(0, n))
+        c = complex(rng.standard_normal(), rng.standard_normal())
+        X = np.zeros(n, complex)
+        X[i0] = c
+        x = np.fft.ifft(X) * np.sqrt(n)
+        sigma, b = 2 * int(rng.integers(0, n // 2)) + 1, int(rng.integers(0, n))
+        h, o = bin_offset(i0, sigma, b, n, B)
+        if gprime(-o, n, B, alpha, delta) < 1.0:
+            continue
+        u0 = hash_to_bins_raw(x, sigma, 0, b, B, G)
+        u1 = hash_to_bins_raw(x, sigma, 1, b, B, G)
+        assert abs(abs(u0[h]) - abs(u1[h])) < 1e-12
+        assert abs(u0[h] - c) < 1e-11
+        phi = math.atan2((u0[h] * np.conj(u1[h])).imag, (u0[h] * np.conj(u1[h])).real) % (2 * math.pi)
+        p = int(math.floor(phi * n / (2 * math.pi) + 0.5)) % n
+        assert (pow(sigma, -1, n) * p) % n == i0
+
+
+def test_decode_rejects_location_outside_its_bin():
+    """A bin whose phase points at an index hashed to a different bin (a
+    collision's garbage phase) is rejected; the same phase is accepted in the
+    bin it belongs to."""
+    from oracle.exact import Margins, decode_bin
+    n, B = 1 << 14, 64
+    p = SfftParams(n=n, k=4, B=B, w=default_w(n, B, 0.5, 1e-12), seed=0, delta=1e-12)
+    sigma, b = 12345, 678
+    sinv = pow(sigma, -1, n)
+    for i in (5, 999, 7777, 16000):
+        h, o = bin_offset(i, sigma, b, n, B)
+        if gprime(-o, n, B, 0.5, 1e-12) < p.g_min:
+            continue
+        u0 = 1.0 + 0.0j
+        u1 = u0 * np.exp(-2j * np.pi * ((sigma * i) % n) / n)     # u'/u = omega^{sigma i}
+        got = decode_bin(u0, u1, h, sigma, sinv, b, B, p, Margins())
+        assert got is not None and got[0] == i
+        assert decode_bin(u0, u1, (h + 1) % B, sigma, sinv, b, B, p, Margins()) is None
+
+
+def test_limited_independence_by_brute_force():
+    """Pr over odd sigma of sigma j in [-C, C] (mod n) is at most 4C/n."""
+    n = 1 << 10
+    odd = np.arange(1, n, 2)
+    for j in (1, 2, 3, 12, 64, 255, 512):
+        for C in (1, 4, 16, 100):
+            v = (odd * j) % n
+            v = np.where(v > n // 2, v - n, v)
+            assert np.mean(np.abs(v) <= C) <= 4 * C / n + 1e-12
+
+
+def test_collision_and_offset_rates():
+    """Claims on E_coll (<= 4|S|/B) and E_off (<= alpha), estimated over draws."""
+    n, B, alpha = 1 << 14, 64, 0.5
+    rng = np.random.default_rng(1)
+    S = rng.choice(n, size=8, replace=False)
+    coll = off = 0
+    trials = 2000
+    for _ in range(trials):
+        sigma, b = 2 * int(rng.integers(0, n // 2)) + 1, int(rng.integers(0, n))
+        hs = [bin_offset(int(i), sigma, b, n, B) for i in S]
+        h0, o0 = hs[0]
+        coll += any(h == h0 for h, _ in hs[1:])
+        off += abs(o0) >= (1 - alpha) * n / (2 * B)
+    assert coll / trials <= 4 * len(S) / B
+    assert off / trials <= alpha + 0.03
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_planted_sparse_recovered_exactly(seed):
+    """Exact recovery of a planted k-sparse spectrum (the exact-case theorem);
+    values to the window accuracy."""
+    p = c1_params(seed)
+    x, sup, val = siggen.planted_signal(p.n, p.k, 100 + seed, np.complex128)
+    r = noiseless_sparse_fft(x, p)
+    assert np.array_equal(r.indices, sup)
+    assert np.max(np.abs(r.values - val)) < 1e-6
+
+
+def test_success_rate_at_least_two_thirds():
+    ok = 0
+    for seed in range(12, 24):
+        p = c1_params(seed)
+        x, sup, _ = siggen.planted_signal(p.n, p.k, 100 + seed, np.complex128)
+        ok += np.array_equal(noiseless_sparse_fft(x, p).indices, sup)
+    assert ok >= 8
+
+
+def test_matches_naive_dft_on_small_n():
+    n, k, B = 1 << 12, 5, 16
+    delta = 1e-12
+    w = default_w(n, B, 0.5, delta)
+    assert w < n
+    for seed in range(3):
+        x, sup, val = siggen.planted_signal(n, k, 7 + seed, np.complex128)
+        xhat = naive_dft(x) / np.sqrt(n)
+        r = noiseless_sparse_fft(x, SfftParams(n=n, k=k, B=B, w=w, seed=seed, delta=delta, rounds=12))
+        big = np.flatnonzero(np.abs(xhat) > 0.5)
+        assert np.array_equal(r.indices, big)
+        assert np.max(np.abs(r.values - xhat[big])) < 1e-8
+
+
+def test_paper_literal_decode_on_integer_spectrum():
+    """Algorithm 1 as printed (v = round(u_j), threshold 1/2) on an integer spectrum."""
+    n, k, B = 1 << 14, 10, 64
+    p = SfftParams(n=n, k=k, B=B, w=default_w(n, B, 0.5, 1e-12), seed=5, delta=1e-12,
+                   theta=0.5, rounds=12, literal=True)
+    sup, val = siggen.planted_spectrum(n, k, 77, magnitude="integer")
+    x = siggen.time_signal(n, sup, val)
+    r = noiseless_sparse_fft(x, p)
+    assert np.array_equal(r.indices, sup)
+    assert np.array_equal(r.values, val)
+
+
+def test_reduction_from_k_point_dft():
+    """Section 5: y_t = x_{t mod k} has yhat = sqrt(n/k) * xhat_k on multiples
+    of n/k and zero elsewhere."""
+    n, k, B = 1 << 14, 16, 64
+    y, xk = siggen.periodic_signal(n, k, 3)
+    xk_hat = naive_dft(xk) / np.sqrt(k)
+    expect_idx = np.arange(k) * (n // k)
+    expect_val = np.sqrt(n / k) * xk_hat
+    p = SfftParams(n=n, k=k, B=B, w=default_w(n, B, 0.5, 1e-12), seed=1, delta=1e-12,
+                   theta=0.05 * np.min(np.abs(expect_val)), rounds=16)
+    r = noiseless_sparse_fft(y, p)
+    assert np.array_equal(r.indices, expect_idx)
+    assert np.max(np.abs(r.values - expect_val)) < 1e-8 * np.max(np.abs(expect_val))
+
+
+def test_adversarial_collision_is_recovered_later():
+    """Two coefficients placed in the same round-0 bin (pi(i2) = pi(i1) + 1):
+    round 0 can decode at most one location, with the merged value, and the
+    later rounds (fresh sigma, b) recover both exactly."""
+    p = c1_params(3)
+    n, B = p.n, p.B
+    sigma, b = draw_sigma(p.seed, n, 0), draw_b(p.seed, n, 0)
+    sinv = pow(sigma, -1, n)
+    i1 = 1000
+    while True:
+        h1, o1 = bin_offset(i1, sigma, b, n, B)
+        if abs(o1) < n // (8 * B):
+            break
+        i1 += 1
+    i2 = (sinv * (perm_position(i1, sigma, b, n) + 1) + b) % n
+    assert bin_offset(i2, sigma, b, n, B)[0] == h1
+    sup = np.array(sorted([i1, i2]), dtype=np.int64)
+    val = np.array([1.0 + 0.5j, -0.7 + 0.8j])
+    x = siggen.time_signal(n, sup, val)
+    r = noiseless_sparse_fft(x, p)
+    assert r.round_log[0][1] <= 1
+    assert r.rounds_used >= 2
+    assert np.array_equal(r.indices, sup)
+    assert np.max(np.abs(r.values - val)) < 1e-8
+
+
+def test_median_exact_when_majority_exact():
+    """EstimateValues' median (the index-estimate lemma of Section 4): exact if a
+    majority of the values are exact."""
+    good = 0.3 - 1.2j
+    vals = [good] * 4 + [5 + 5j, -9 + 0j, 100j]
+    assert complex_median(vals) == good
+    assert complex_median([1 + 1j, 3 + 0j]) == (2 + 0.5j)
