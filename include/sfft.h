@@ -1,0 +1,233 @@
+/*
+ * sfft.h -- C ABI of an MI355X (gfx950) sparse FFT.
+ *
+ * The library recovers the k largest Fourier coefficients of an n-point
+ * complex signal with the method of Hassanieh, Indyk, Katabi and Price,
+ * "Nearly Optimal Sparse Fourier Transform":
+ *   problem     given sample access to x in C^n (n = 2^m) and k, output a
+ *               k-sparse xhat' with ||xhat - xhat'||_2 <= C * Err(xhat, k),
+ *               exactly xhat when xhat is k-sparse, with constant success
+ *               probability (Section 1, eq. (1); Section 2 Assumptions).
+ *   convention  xhat_f = n^{-1/2} sum_j omega^{f j} x_j, omega = e^{-2 pi i/n}
+ *               (Section 2, Notation).  Values are returned in this unitary
+ *               convention unless SFFT_FLAG_NUMPY_NORM is set (then * sqrt(n)).
+ *   hot path    HashToBins (Algorithm 1; computed as in the proof of the
+ *               HashToBins lemma of Section 3): permuted gather
+ *               x[sigma (t - a) mod n], flat-window multiply and modulation,
+ *               fold into B buckets, B-point FFT; then exact phase decoding
+ *               (Algorithm 1) or LocateInner voting and EstimateValues medians
+ *               (Algorithms 2 and 3), and a final FP64 median re-estimation.
+ *
+ * Conventions of every entry point:
+ *   * Pointers named *_dev are device pointers on the current HIP device;
+ *     pointers named *_host are host pointers.  `stream` is a hipStream_t
+ *     passed as void* (NULL = the default stream).
+ *   * Nothing throws across the ABI.  On error a status code is returned,
+ *     outputs are left untouched (asynchronous entry points: the status
+ *     covers the launch), and sfft_last_error() describes the failure.
+ *   * Input signals are contiguous, interleaved (re, im) complex64
+ *     (SFFT_C64) or complex128 (SFFT_C128) arrays of n elements; a batch is
+ *     [count][n] with signal stride n.  The caller owns them and must keep
+ *     them alive until the stream has passed the call.
+ *   * Output values are complex128, interleaved (re, im), i.e. double[2].
+ *   * A plan is immutable after creation and may be shared by threads;
+ *     calls that use the same plan on different streams at the same time
+ *     race on the plan's workspace (one execute in flight per plan).
+ */
+#ifndef SFFT_H
+#define SFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SFFT_OK = 0,
+    SFFT_EINVAL = 1,     /* an argument is out of range or inconsistent      */
+    SFFT_ENOTPOW2 = 2,   /* n or B is not a power of two                     */
+    SFFT_ENOMEM = 3,     /* device or host allocation failed                 */
+    SFFT_EBUDGET = 4,    /* the request does not fit the memory budget       */
+    SFFT_EHIP = 5,       /* a HIP runtime call failed                        */
+    SFFT_ETRUNC = 6,     /* more coefficients than cap; the top cap returned  */
+    SFFT_EUNSUPPORTED = 7/* parameters valid but not supported by a kernel   */
+} sfft_status_t;
+
+typedef enum { SFFT_MODE_EXACT = 0, SFFT_MODE_GENERAL = 1 } sfft_mode_t;
+typedef enum { SFFT_C64 = 0, SFFT_C128 = 1 } sfft_dtype_t;
+typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
+
+/* flags */
+#define SFFT_FLAG_NUMPY_NORM 0x1u   /* return values scaled by sqrt(n)                  */
+
+/* per-signal info words written by the batched entry point (4 x uint32)     */
+#define SFFT_INFO_ROUNDS 0          /* rounds whose bins were decoded                 */
+#define SFFT_INFO_FLAGS 1           /* bit 0: output truncated to cap; bit 1: zhat full */
+#define SFFT_INFO_ZHAT 2            /* number of zhat entries before the output filter */
+#define SFFT_INFO_LOCATED 3         /* general mode: candidates located (last round)   */
+
+/*
+ * Plan description.  sfft_desc_init fills every field with its default;
+ * change fields, then call sfft_plan_ex.  Parameter readings (the paper only
+ * fixes Theta(.) constants):
+ *   n, k      signal length (2^m, 2 <= m <= 40) and sparsity (1 <= k < n)
+ *   B         bins of the first hashing round (power of two, 2 <= B <= n)
+ *   w         window length, a multiple of B, B <= w <= n; 0 = the smallest
+ *             multiple of B whose window tail sum_{|t| >= w/2} |G*(t)| <= delta
+ *   seed      seed of the counter-based draws (SplitMix64; see below)
+ *   mode      SFFT_MODE_EXACT (Algorithm 1) or SFFT_MODE_GENERAL (Algs 2, 3)
+ *   in_dtype  storage type of the input signal
+ *   loc_prec  arithmetic of the location hashings (exact pairs, LocateInner
+ *             pairs): at large n the phase step 2 pi / n is below FP32
+ *             resolution, so the default is SFFT_F64 for n >= 2^20
+ *   est_prec  arithmetic of the EstimateValues hashings (general mode)
+ *   alpha     flat-window transition fraction (Section 2 definition)
+ *   delta     window accuracy; sets the Gaussian width sigma_g =
+ *             (4B/alpha) sqrt(2 ln(n/delta)) (Section 7 construction)
+ *   theta     bin threshold of the exact decode (the paper's 1/2 for
+ *             integer spectra, Algorithm 1)
+ *   g_min     smallest window value G'_{-o(i)} a bin value is divided by
+ *   rounds    exact: most NoiselessSparseFFTInner rounds; general: SparseFFT
+ *             rounds
+ *   b_min     exact: round r uses B_r = max(B >> r, b_min) bins and a window
+ *             of w B_r / B samples (Algorithm 1 shrinks B with k_t = k/2^t);
+ *             0 = B/16 (at least 2); b_min = B keeps B fixed
+ *   patience  exact: stop after this many consecutive rounds whose bins are
+ *             all below theta
+ *   t, s      LocateInner regions per level and vote tolerance (Algorithm 3)
+ *   R_loc     LocateInner measurements per level (Algorithm 3)
+ *   R_est     EstimateValues measurements per round (Algorithm 2)
+ *   cap       output capacity (0 = k)
+ *   flags     SFFT_FLAG_*
+ *   max_batch largest count accepted by sfft_execute_batch (workspace size)
+ */
+typedef struct {
+    uint64_t n;
+    uint64_t w;
+    uint64_t seed;
+    uint32_t k;
+    uint32_t B;
+    int32_t mode;
+    int32_t in_dtype;
+    int32_t loc_prec;
+    int32_t est_prec;
+    double alpha;
+    double delta;
+    double theta;
+    double g_min;
+    double s;
+    uint32_t rounds;
+    uint32_t b_min;
+    uint32_t patience;
+    uint32_t t;
+    uint32_t R_loc;
+    uint32_t R_est;
+    uint32_t cap;
+    uint32_t flags;
+    uint32_t max_batch;
+    uint32_t reserved;
+} sfft_plan_desc_t;
+
+typedef struct sfft_plan_s* sfft_plan_t;
+
+/* Fill *d with the defaults for (n, k, B, w, seed); exact mode, complex64.
+ * Pure host function: no device is touched.  Errors: SFFT_EINVAL if d is NULL. */
+sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32_t B,
+                             uint64_t w, uint64_t seed);
+
+/* Check a description against the limits listed above (and the kernels'
+ * LDS limits: B <= 4096 for FP64 pairs, B <= 8192 for FP32).  Pure host
+ * function.  Returns SFFT_OK, SFFT_ENOTPOW2, SFFT_EINVAL or
+ * SFFT_EUNSUPPORTED. */
+sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d);
+
+/* Default window length for (n, B, alpha, delta), as described for w above;
+ * returns n when no shorter window meets delta.  Pure host function. */
+uint64_t sfft_default_w(uint64_t n, uint32_t B, double alpha, double delta);
+
+/* Create a plan: validates, builds the FP64 window tables G (Section 7
+ * construction) and FFT twiddles on the host, copies them to the current
+ * device and allocates the workspace for max_batch signals.  The plan owns
+ * all of its device memory.  Errors: validation codes, SFFT_ENOMEM, SFFT_EHIP. */
+sfft_status_t sfft_plan_ex(const sfft_plan_desc_t* d, sfft_plan_t* out);
+
+/* sfft_plan_ex with the defaults of sfft_desc_init (spec signature). */
+sfft_status_t sfft_plan(uint64_t n, uint32_t k, uint32_t B, uint64_t w, uint64_t seed,
+                        sfft_plan_t* out);
+
+/* Copy of the plan's (resolved) description; w is the resolved window. */
+sfft_status_t sfft_plan_get_desc(sfft_plan_t p, sfft_plan_desc_t* out);
+
+/* Release every device and host resource of the plan.  NULL is allowed. */
+sfft_status_t sfft_destroy(sfft_plan_t p);
+
+/*
+ * One signal, one request at a time ("plain" path).  Each hashing is
+ * launched on its own, split over many workgroups with a fixed-order
+ * two-level reduction; the host drives the rounds and stops early
+ * (exact mode: `patience` empty rounds).  Synchronises `stream` before
+ * returning.
+ *   x_dev      n input samples (in_dtype)
+ *   idx_host   [cap] output indices, ascending
+ *   val_host   [2*cap] output values (complex128)
+ *   cap        capacity of idx_host/val_host (>= 1)
+ *   count_host number of coefficients written
+ *   info_host  optional [4] info words (SFFT_INFO_*), may be NULL
+ * Returns SFFT_ETRUNC (outputs valid) when more than cap coefficients were
+ * recovered; then the cap largest by magnitude are returned.
+ */
+sfft_status_t sfft_execute(sfft_plan_t p, const void* x_dev, uint64_t* idx_host,
+                           double* val_host, uint32_t cap, uint32_t* count_host,
+                           uint32_t* info_host, void* stream);
+
+/*
+ * A batch of independent signals ("batched" path): every hashing of every
+ * signal runs in one launch, the per-signal rounds are decoded by a
+ * persistent device loop, and the launch sequence is captured once into a
+ * hipGraph and replayed (keyed by the argument pointers and count).
+ * Asynchronous on `stream`; nothing is copied to the host.
+ *   x_dev      [count][n] signals (in_dtype)
+ *   count      1 <= count <= max_batch
+ *   seeds_dev  [count] per-signal seeds (uint64) or NULL for the plan seed
+ *   idx_dev    [count][cap] indices (ascending per signal; unused slots 0)
+ *   val_dev    [count][cap][2] values (complex128)
+ *   count_dev  [count] number of coefficients per signal
+ *   info_dev   [count][4] info words (SFFT_INFO_*), may be NULL
+ * Results of one signal depend only on (its samples, its seed, the plan),
+ * never on the other signals of the batch.
+ */
+sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t count,
+                                 const uint64_t* seeds_dev, uint64_t* idx_dev, double* val_dev,
+                                 uint32_t* count_dev, uint32_t* info_dev, void* stream);
+
+/*
+ * Raw HashToBins of one signal at two shifts of one permutation (steps 1-3
+ * of the HashToBins computation in Section 3): bins of P_{sigma,a,b} x and of
+ * P_{sigma,a+beta,b} x with B_r bins and a window of w * B_r / B samples
+ * (plan alpha, delta), scaled by sqrt(n), in `prec` arithmetic.  Exposed for
+ * parity tests of the gather/fold/FFT kernels.  out0_dev/out1_dev are
+ * [B_r][2] doubles.  sigma must be odd; a, b, beta < n; B_r a power of two
+ * dividing the plan's B schedule (B_r <= B).
+ */
+sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigma, uint64_t a,
+                                 uint64_t beta, uint64_t b, uint32_t B_r, int32_t prec,
+                                 double* out0_dev, double* out1_dev, void* stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* sfft_status_string(sfft_status_t s);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* sfft_last_error(void);
+
+/* SplitMix64 counter draw used for every random choice of the method:
+ * the (c+1)-th output of SplitMix64 started at `seed` (Steele, Lea and Flood,
+ * OOPSLA 2014).  Counter layout c = round<<32 | level<<20 | rep<<8 | purpose.
+ * Pure host function, exported so that callers can reproduce a plan's draws. */
+uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFFT_H */

@@ -1,0 +1,607 @@
+// Host runtime of the sparse FFT library: parameter validation and defaults,
+// the flat-window tables (Section 7 construction, built in FP64 on the host),
+// FFT twiddles, device workspaces, the plain (one signal, host round loop)
+// and batched (hipGraph-replayed) execution paths, and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sfft_internal.hpp"
+
+using namespace sfft;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sfft_status_t fail(sfft_status_t s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(SFFT_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+    } while (0)
+
+bool is_pow2(uint64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
+
+uint32_t log2u(uint64_t v) {
+    uint32_t l = 0;
+    while ((1ull << l) < v) ++l;
+    return l;
+}
+
+// ------------------------------------------------------------ window ------
+// Gaussian width and boxcar half-width of the Section 7 construction.
+WindowShape window_shape(uint64_t n, uint64_t B, double alpha, double delta) {
+    WindowShape ws;
+    ws.sigma_g = (4.0 * (double)B / alpha) * std::sqrt(2.0 * std::log((double)n / delta));
+    ws.C = (1.0 - alpha / 2.0) / (2.0 * (double)B);
+    ws.alpha = alpha;
+    return ws;
+}
+
+// G*(t) = exp(-2 pi^2 t^2 / sigma_g^2) * sin(2 pi C t) / (pi t), G*(0) = 2C.
+double g_star(double t, const WindowShape& ws) {
+    const double pi = 3.14159265358979323846;
+    const double gauss = std::exp(-2.0 * pi * pi * t * t / (ws.sigma_g * ws.sigma_g));
+    const double box = t == 0.0 ? 2.0 * ws.C : std::sin(2.0 * pi * ws.C * t) / (pi * t);
+    return gauss * box;
+}
+
+double tail_mass(uint64_t T, const WindowShape& ws) {
+    const uint64_t span = (uint64_t)(12.0 * ws.sigma_g) + 2;
+    double total = 0.0;
+    for (uint64_t t = T; t < T + span; ++t) total += std::fabs(g_star((double)t, ws));
+    return 2.0 * total;
+}
+
+uint64_t default_w(uint64_t n, uint64_t B, double alpha, double delta) {
+    const WindowShape ws = window_shape(n, B, alpha, delta);
+    uint64_t lo = 1, hi = n / B;
+    if (tail_mass(hi * B / 2, ws) > delta) return n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (tail_mass(mid * B / 2, ws) <= delta) hi = mid; else lo = mid + 1;
+    }
+    return lo * B;
+}
+
+uint32_t exact_round_bins(const sfft_plan_desc_t& d, uint32_t r) {
+    const uint32_t floor_b = d.b_min ? d.b_min : std::max<uint32_t>(2u, d.B >> 4);
+    const uint32_t f = std::min(floor_b, d.B);
+    const uint32_t shifted = r >= 31 ? 0u : (d.B >> r);
+    return std::max(shifted, f);
+}
+
+uint32_t zhat_capacity(const sfft_plan_desc_t& d) {
+    uint64_t c = 4ull * std::max<uint32_t>(d.k, 16u);
+    return (uint32_t)std::min<uint64_t>(c, kMaxZ);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan ---
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    const void* x = nullptr;
+    const void* seeds = nullptr;
+    const void* o1 = nullptr;
+    const void* o2 = nullptr;
+    const void* o3 = nullptr;
+    const void* o4 = nullptr;
+    uint32_t count = 0;
+};
+
+struct sfft_plan_s {
+    sfft_plan_desc_t d;
+    int device = 0;
+    uint32_t R = 0;            // rounds with geometry
+    uint32_t Bmax = 0;
+    uint32_t logBmax = 0;
+    uint32_t capz = 0;
+    uint32_t cap = 0;
+    uint32_t mcap = 0;         // largest modulation table of the pair kernel
+    std::vector<RoundDev> geom;
+    RoundDev* d_geom = nullptr;
+    double* d_g64 = nullptr;
+    float* d_g32 = nullptr;
+    double* d_tw64 = nullptr;  // Bmax complex
+    float* d_tw32 = nullptr;
+    // batched workspace (max_batch signals)
+    double* raw = nullptr;
+    double* work = nullptr;
+    uint64_t* cand_i = nullptr;
+    double* cand_v = nullptr;
+    uint64_t* zidx = nullptr;
+    double* zval = nullptr;
+    double* est = nullptr;
+    double* fin = nullptr;
+    double* gtmp = nullptr;
+    uint32_t* ecount = nullptr;
+    uint32_t* state = nullptr;
+    // plain-path workspace (one signal)
+    double* p_raw = nullptr;
+    double* p_partial = nullptr;
+    uint32_t p_parts_max = 0;
+    uint64_t* p_idx = nullptr;
+    double* p_val = nullptr;
+    uint32_t* p_count = nullptr;
+    uint32_t* p_info = nullptr;
+    hipStream_t capture_stream = nullptr;
+    GraphCache graph;
+    std::mutex mu;
+    std::vector<void*> allocations;
+};
+
+namespace {
+
+template <class T>
+sfft_status_t dev_alloc(sfft_plan_s* p, T** ptr, size_t count) {
+    void* q = nullptr;
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(SFFT_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    p->allocations.push_back(q);
+    *ptr = reinterpret_cast<T*>(q);
+    return SFFT_OK;
+}
+
+#define ST_TRY(expr)                      \
+    do {                                  \
+        sfft_status_t s_ = (expr);        \
+        if (s_ != SFFT_OK) return s_;     \
+    } while (0)
+
+sfft_status_t resolve_and_validate(sfft_plan_desc_t& d) {
+    sfft_status_t s = sfft_validate_params(&d);
+    if (s != SFFT_OK) return s;
+    if (d.w == 0) d.w = default_w(d.n, d.B, d.alpha, d.delta);
+    if (d.cap == 0) d.cap = d.k;
+    return SFFT_OK;
+}
+
+sfft_status_t build_plan(sfft_plan_s* p) {
+    const sfft_plan_desc_t& d = p->d;
+    HIP_TRY(hipGetDevice(&p->device));
+    // round geometry (exact mode schedule)
+    p->R = d.rounds;
+    p->Bmax = d.B;
+    p->logBmax = log2u(d.B);
+    p->capz = zhat_capacity(d);
+    p->cap = d.cap;
+    std::vector<double> g64;
+    std::vector<uint32_t> seenB;
+    std::vector<uint64_t> seenOfs;
+    p->mcap = 4;
+    for (uint32_t r = 0; r < p->R; ++r) {
+        RoundDev g;
+        g.B = exact_round_bins(d, r);
+        g.logB = log2u(g.B);
+        g.w = d.w / d.B * g.B;
+        g.t0 = -(int64_t)(g.w / 2);
+        g.ws = window_shape(d.n, g.B, d.alpha, d.delta);
+        auto it = std::find(seenB.begin(), seenB.end(), g.B);
+        if (it == seenB.end()) {
+            g.gofs = g64.size();
+            for (uint64_t u = 0; u < g.w; ++u) g64.push_back(g_star((double)(g.t0 + (int64_t)u), g.ws));
+            seenB.push_back(g.B);
+            seenOfs.push_back(g.gofs);
+        } else {
+            g.gofs = seenOfs[it - seenB.begin()];
+        }
+        // pair (a = 0, beta = 1) modulation table length
+        const int64_t iB = g.B;
+        const int64_t Llo = floordiv(g.t0 - 1 - (iB - 1), iB);
+        const int64_t Lhi = floordiv(g.t0 + (int64_t)g.w - 1, iB);
+        p->mcap = std::max<uint32_t>(p->mcap, (uint32_t)(Lhi - Llo + 1));
+        p->geom.push_back(g);
+    }
+    std::vector<float> g32(g64.begin(), g64.end());
+    // twiddles exp(-2 pi i m / Bmax), m < Bmax
+    std::vector<double> tw64(2 * (size_t)p->Bmax);
+    std::vector<float> tw32(2 * (size_t)p->Bmax);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (uint32_t m = 0; m < p->Bmax; ++m) {
+        const double ang = two_pi * (double)m / (double)p->Bmax;
+        tw64[2 * m] = std::cos(ang);
+        tw64[2 * m + 1] = -std::sin(ang);
+        tw32[2 * m] = (float)tw64[2 * m];
+        tw32[2 * m + 1] = (float)tw64[2 * m + 1];
+    }
+    ST_TRY(dev_alloc(p, &p->d_geom, p->geom.size()));
+    ST_TRY(dev_alloc(p, &p->d_g64, g64.size()));
+    ST_TRY(dev_alloc(p, &p->d_g32, g32.size()));
+    ST_TRY(dev_alloc(p, &p->d_tw64, tw64.size()));
+    ST_TRY(dev_alloc(p, &p->d_tw32, tw32.size()));
+    HIP_TRY(hipMemcpy(p->d_geom, p->geom.data(), p->geom.size() * sizeof(RoundDev), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_g64, g64.data(), g64.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_g32, g32.data(), g32.size() * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_tw64, tw64.data(), tw64.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_tw32, tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
+    // batched workspace
+    const size_t S = d.max_batch;
+    const size_t Bm = p->Bmax, R = p->R, Z = p->capz;
+    ST_TRY(dev_alloc(p, &p->raw, S * R * 4 * Bm));
+    ST_TRY(dev_alloc(p, &p->work, S * 4 * Bm));
+    ST_TRY(dev_alloc(p, &p->cand_i, S * Bm));
+    ST_TRY(dev_alloc(p, &p->cand_v, S * 2 * Bm));
+    ST_TRY(dev_alloc(p, &p->zidx, S * 2 * Z));
+    ST_TRY(dev_alloc(p, &p->zval, S * 4 * Z));
+    ST_TRY(dev_alloc(p, &p->est, S * Z * R * 2));
+    ST_TRY(dev_alloc(p, &p->fin, S * Z * 2));
+    ST_TRY(dev_alloc(p, &p->gtmp, S * Z));
+    ST_TRY(dev_alloc(p, &p->ecount, S * Z));
+    ST_TRY(dev_alloc(p, &p->state, S * kStateWords));
+    // plain path (one signal): raw bins of every round, split partials
+    p->p_parts_max = 64;
+    ST_TRY(dev_alloc(p, &p->p_raw, R * 4 * Bm));
+    ST_TRY(dev_alloc(p, &p->p_partial, (size_t)p->p_parts_max * 4 * Bm));
+    ST_TRY(dev_alloc(p, &p->p_idx, p->cap));
+    ST_TRY(dev_alloc(p, &p->p_val, 2 * (size_t)p->cap));
+    ST_TRY(dev_alloc(p, &p->p_count, 1));
+    ST_TRY(dev_alloc(p, &p->p_info, 4));
+    HIP_TRY(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+    return SFFT_OK;
+}
+
+bool loc_f64(const sfft_plan_s* p) { return p->d.loc_prec == SFFT_F64; }
+bool in_c128(const sfft_plan_s* p) { return p->d.in_dtype == SFFT_C128; }
+
+H2BArgs base_h2b(const sfft_plan_s* p, const void* x) {
+    H2BArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.x = x;
+    a.n = p->d.n;
+    a.sig_stride = p->d.n;
+    a.plan_seed = p->d.seed;
+    a.Bmax = p->Bmax;
+    a.logBmax = p->logBmax;
+    a.geom = p->d_geom;
+    a.gtab = loc_f64(p) ? (const void*)p->d_g64 : (const void*)p->d_g32;
+    a.tw = loc_f64(p) ? (const void*)p->d_tw64 : (const void*)p->d_tw32;
+    a.sqrt_n = std::sqrt((double)p->d.n);
+    a.mcap = p->mcap;
+    return a;
+}
+
+DecodeArgs base_decode(const sfft_plan_s* p, uint32_t count, const uint64_t* seeds, const double* raw,
+                       uint64_t* oidx, double* oval, uint32_t* ocount, uint32_t* oinfo) {
+    DecodeArgs D;
+    std::memset(&D, 0, sizeof(D));
+    D.n = p->d.n;
+    D.count = count;
+    D.rounds = p->R;
+    D.r_begin = 0;
+    D.r_end = p->R;
+    D.patience = p->d.patience;
+    D.Bmax = p->Bmax;
+    D.capz = p->capz;
+    D.cap = p->cap;
+    D.geom = p->d_geom;
+    D.seeds = seeds;
+    D.plan_seed = p->d.seed;
+    D.raw = raw;
+    D.work = p->work;
+    D.cand_i = p->cand_i;
+    D.cand_v = p->cand_v;
+    D.zidx = p->zidx;
+    D.zval = p->zval;
+    D.est = p->est;
+    D.fin = p->fin;
+    D.gtmp = p->gtmp;
+    D.ecount = p->ecount;
+    D.state = p->state;
+    D.theta = p->d.theta;
+    D.g_min = p->d.g_min;
+    D.out_scale = (p->d.flags & SFFT_FLAG_NUMPY_NORM) ? std::sqrt((double)p->d.n) : 1.0;
+    D.out_idx = oidx;
+    D.out_val = oval;
+    D.out_count = ocount;
+    D.out_info = oinfo;
+    return D;
+}
+
+sfft_status_t enqueue_batch(sfft_plan_s* p, const void* x, uint32_t count, const uint64_t* seeds,
+                            uint64_t* idx, double* val, uint32_t* cnt, uint32_t* info, hipStream_t s) {
+    DecodeArgs D = base_decode(p, count, seeds, p->raw, idx, val, cnt, info);
+    HIP_TRY(launch_exact_init(D, s));
+    H2BArgs a = base_h2b(p, x);
+    a.seeds = seeds;
+    a.count = count;
+    a.round_lo = 0;
+    a.nrounds = p->R;
+    a.raw = p->raw;
+    a.raw_rounds = p->R;
+    HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
+    HIP_TRY(launch_exact_decode(D, s));
+    HIP_TRY(launch_exact_finish(D, s));
+    return SFFT_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI ==
+extern "C" {
+
+const char* sfft_status_string(sfft_status_t s) {
+    switch (s) {
+        case SFFT_OK: return "SFFT_OK";
+        case SFFT_EINVAL: return "SFFT_EINVAL";
+        case SFFT_ENOTPOW2: return "SFFT_ENOTPOW2";
+        case SFFT_ENOMEM: return "SFFT_ENOMEM";
+        case SFFT_EBUDGET: return "SFFT_EBUDGET";
+        case SFFT_EHIP: return "SFFT_EHIP";
+        case SFFT_ETRUNC: return "SFFT_ETRUNC";
+        case SFFT_EUNSUPPORTED: return "SFFT_EUNSUPPORTED";
+    }
+    return "SFFT_UNKNOWN";
+}
+
+const char* sfft_last_error(void) { return g_last_error.c_str(); }
+
+uint64_t sfft_splitmix64(uint64_t seed, uint64_t c) { return splitmix64(seed, c); }
+
+uint64_t sfft_default_w(uint64_t n, uint32_t B, double alpha, double delta) {
+    if (!is_pow2(n) || !is_pow2(B) || B > n || !(alpha > 0 && alpha < 1) || !(delta > 0 && delta < 1)) return 0;
+    return default_w(n, B, alpha, delta);
+}
+
+sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32_t B, uint64_t w, uint64_t seed) {
+    if (!d) return fail(SFFT_EINVAL, "desc is NULL");
+    std::memset(d, 0, sizeof(*d));
+    d->n = n;
+    d->k = k;
+    d->B = B;
+    d->w = w;
+    d->seed = seed;
+    d->mode = SFFT_MODE_EXACT;
+    d->in_dtype = SFFT_C64;
+    d->loc_prec = n >= (1ull << 20) ? SFFT_F64 : SFFT_F32;
+    d->est_prec = SFFT_F32;
+    d->alpha = 0.5;
+    d->delta = 1e-9;
+    d->theta = 0.25;
+    d->g_min = 0.4;
+    d->s = 0.125;
+    d->rounds = 16;
+    d->b_min = 0;
+    d->patience = 3;
+    d->t = 16;
+    d->R_loc = 3;
+    d->R_est = 7;
+    d->cap = 0;
+    d->flags = 0;
+    d->max_batch = 1;
+    return SFFT_OK;
+}
+
+sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
+    if (!d) return fail(SFFT_EINVAL, "desc is NULL");
+    if (!is_pow2(d->n) || d->n < 4) return fail(SFFT_ENOTPOW2, "n must be a power of two >= 4");
+    if (d->n > (1ull << 40)) return fail(SFFT_EINVAL, "n must be at most 2^40");
+    if (d->k < 1 || d->k >= d->n) return fail(SFFT_EINVAL, "k must satisfy 1 <= k < n");
+    if (!is_pow2(d->B) || d->B < 2) return fail(SFFT_ENOTPOW2, "B must be a power of two >= 2");
+    if (d->B > d->n) return fail(SFFT_EINVAL, "B must be at most n");
+    if (d->w != 0 && (d->w % d->B != 0 || d->w < d->B || d->w > d->n))
+        return fail(SFFT_EINVAL, "w must be a multiple of B with B <= w <= n (or 0)");
+    if (d->mode != SFFT_MODE_EXACT && d->mode != SFFT_MODE_GENERAL) return fail(SFFT_EINVAL, "bad mode");
+    if (d->in_dtype != SFFT_C64 && d->in_dtype != SFFT_C128) return fail(SFFT_EINVAL, "bad in_dtype");
+    if ((d->loc_prec != SFFT_F32 && d->loc_prec != SFFT_F64) || (d->est_prec != SFFT_F32 && d->est_prec != SFFT_F64))
+        return fail(SFFT_EINVAL, "bad precision");
+    if (!(d->alpha > 0.0 && d->alpha < 1.0)) return fail(SFFT_EINVAL, "alpha must be in (0, 1)");
+    if (!(d->delta > 0.0 && d->delta < 1.0)) return fail(SFFT_EINVAL, "delta must be in (0, 1)");
+    if (!(d->theta > 0.0)) return fail(SFFT_EINVAL, "theta must be positive");
+    if (!(d->g_min > 0.0 && d->g_min <= 1.0)) return fail(SFFT_EINVAL, "g_min must be in (0, 1]");
+    if (d->rounds < 1 || d->rounds > kMaxRounds) return fail(SFFT_EINVAL, "rounds must be in [1, 32]");
+    if (d->patience < 1) return fail(SFFT_EINVAL, "patience must be >= 1");
+    if (d->b_min != 0 && (!is_pow2(d->b_min) || d->b_min < 2)) return fail(SFFT_EINVAL, "b_min must be 0 or a power of two >= 2");
+    if (d->max_batch < 1 || d->max_batch > (1u << 20)) return fail(SFFT_EINVAL, "max_batch must be in [1, 2^20]");
+    const uint32_t cap = d->cap ? d->cap : d->k;
+    if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");
+    if (d->mode == SFFT_MODE_GENERAL) {
+        if (d->t < 4 || !is_pow2(d->t) || d->R_loc < 1 || d->R_est < 1 || !(d->s > 0 && d->s < 1))
+            return fail(SFFT_EINVAL, "bad LocateInner/EstimateValues parameters");
+        return fail(SFFT_EUNSUPPORTED, "general mode is not available in this build");
+    }
+    if (d->B > kMaxZ) return fail(SFFT_EUNSUPPORTED, "B exceeds 4096, the LDS limit of the pair and decode kernels");
+    return SFFT_OK;
+}
+
+sfft_status_t sfft_plan_ex(const sfft_plan_desc_t* desc, sfft_plan_t* out) {
+    if (!desc || !out) return fail(SFFT_EINVAL, "NULL argument");
+    sfft_plan_desc_t d = *desc;
+    ST_TRY(resolve_and_validate(d));
+    if (d.w < d.B || d.w % d.B) return fail(SFFT_EINVAL, "resolved window is not a multiple of B");
+    sfft_plan_s* p = new (std::nothrow) sfft_plan_s();
+    if (!p) return fail(SFFT_ENOMEM, "host allocation failed");
+    p->d = d;
+    sfft_status_t s = build_plan(p);
+    if (s != SFFT_OK) {
+        sfft_destroy(p);
+        return s;
+    }
+    *out = p;
+    return SFFT_OK;
+}
+
+sfft_status_t sfft_plan(uint64_t n, uint32_t k, uint32_t B, uint64_t w, uint64_t seed, sfft_plan_t* out) {
+    sfft_plan_desc_t d;
+    sfft_desc_init(&d, n, k, B, w, seed);
+    return sfft_plan_ex(&d, out);
+}
+
+sfft_status_t sfft_plan_get_desc(sfft_plan_t p, sfft_plan_desc_t* out) {
+    if (!p || !out) return fail(SFFT_EINVAL, "NULL argument");
+    *out = p->d;
+    return SFFT_OK;
+}
+
+sfft_status_t sfft_destroy(sfft_plan_t p) {
+    if (!p) return SFFT_OK;
+    if (p->graph.exec) (void)hipGraphExecDestroy(p->graph.exec);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    for (void* q : p->allocations) (void)hipFree(q);
+    delete p;
+    return SFFT_OK;
+}
+
+sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigma, uint64_t a, uint64_t beta,
+                                 uint64_t b, uint32_t B_r, int32_t prec, double* out0_dev, double* out1_dev,
+                                 void* stream) {
+    if (!p || !x_dev || !out0_dev || !out1_dev) return fail(SFFT_EINVAL, "NULL argument");
+    const uint64_t n = p->d.n;
+    if ((sigma & 1) == 0 || sigma >= n || a >= n || b >= n || beta >= n)
+        return fail(SFFT_EINVAL, "sigma must be odd and sigma, a, b, beta < n");
+    if (prec != SFFT_F32 && prec != SFFT_F64) return fail(SFFT_EINVAL, "bad precision");
+    uint32_t round = p->R;
+    for (uint32_t r = 0; r < p->R; ++r)
+        if (p->geom[r].B == B_r) {
+            round = r;
+            break;
+        }
+    if (round == p->R) return fail(SFFT_EINVAL, "B_r is not a bin count of the plan's schedule");
+    const RoundDev& g = p->geom[round];
+    std::lock_guard<std::mutex> lock(p->mu);
+    H2BArgs A = base_h2b(p, x_dev);
+    A.gtab = prec == SFFT_F64 ? (const void*)p->d_g64 : (const void*)p->d_g32;
+    A.tw = prec == SFFT_F64 ? (const void*)p->d_tw64 : (const void*)p->d_tw32;
+    A.explicit_job = 1;
+    A.sigma = sigma;
+    A.a = a;
+    A.beta = beta;
+    A.b = b;
+    A.count = 1;
+    A.round_lo = round;
+    A.nrounds = 1;
+    A.raw = p->p_raw;
+    A.raw_rounds = 1;
+    const int64_t iB = g.B, iw = (int64_t)g.w, ib = (int64_t)beta;
+    uint64_t mc;
+    if (beta < g.w) {
+        mc = (uint64_t)(floordiv(g.t0 + iw - 1, iB) - floordiv(g.t0 - ib - (iB - 1), iB) + 1);
+    } else {   // two disjoint segments, each with its own table
+        const int64_t s0 = floordiv(g.t0 - ib + iw - 1, iB) - floordiv(g.t0 - ib - (iB - 1), iB) + 1;
+        const int64_t s1 = floordiv(g.t0 + iw - 1, iB) - floordiv(g.t0 - (iB - 1), iB) + 1;
+        mc = (uint64_t)std::max(s0, s1);
+    }
+    A.mcap = (uint32_t)mc;
+    if (h2b_pair_lds_bytes(p->Bmax, A.mcap, prec == SFFT_F64) > 160 * 1024)
+        return fail(SFFT_EUNSUPPORTED, "pair does not fit in LDS");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(launch_h2b_pair(A, in_c128(p), prec == SFFT_F64, s));
+    HIP_TRY(hipMemcpyAsync(out0_dev, p->p_raw, 2 * sizeof(double) * g.B, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(out1_dev, p->p_raw + 2 * (size_t)p->Bmax, 2 * sizeof(double) * g.B,
+                           hipMemcpyDeviceToDevice, s));
+    return SFFT_OK;
+}
+
+sfft_status_t sfft_execute(sfft_plan_t p, const void* x_dev, uint64_t* idx_host, double* val_host, uint32_t cap,
+                           uint32_t* count_host, uint32_t* info_host, void* stream) {
+    if (!p || !x_dev || !idx_host || !val_host || !count_host || cap < 1) return fail(SFFT_EINVAL, "bad argument");
+    std::lock_guard<std::mutex> lock(p->mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const uint64_t n = p->d.n;
+    DecodeArgs D = base_decode(p, 1, nullptr, p->p_raw, p->p_idx, p->p_val, p->p_count, p->p_info);
+    HIP_TRY(launch_exact_init(D, s));
+    uint32_t st[kStateWords];
+    for (uint32_t r = 0; r < p->R; ++r) {
+        const RoundDev& g = p->geom[r];
+        H2BArgs a = base_h2b(p, x_dev);
+        a.sigma = draw_sigma(p->d.seed, n, r);
+        a.b = draw_b(p->d.seed, n, r);
+        a.a = 0;
+        a.beta = 1;
+        a.raw = p->p_raw;
+        a.raw_rounds = p->R;
+        a.partial = p->p_partial;
+        const int64_t iB = g.B;
+        const int64_t Lmin = floordiv(g.t0 - 1 - (iB - 1), iB);
+        const int64_t Lmax = floordiv(g.t0 + (int64_t)g.w - 1, iB);
+        const uint64_t nL = (uint64_t)(Lmax - Lmin + 1);
+        a.lchunk = (uint32_t)((nL + p->p_parts_max - 1) / p->p_parts_max);
+        a.parts = (uint32_t)((nL + a.lchunk - 1) / a.lchunk);
+        a.mcap = a.lchunk + 2;
+        HIP_TRY(launch_h2b_split(a, r, in_c128(p), loc_f64(p), s));
+        HIP_TRY(launch_h2b_reduce(a, r, loc_f64(p), s));
+        D.r_begin = r;
+        D.r_end = r + 1;
+        HIP_TRY(launch_exact_decode(D, s));
+        HIP_TRY(hipMemcpyAsync(st, p->state, sizeof(st), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (st[ST_DONE]) break;
+    }
+    HIP_TRY(launch_exact_finish(D, s));
+    uint32_t cnt = 0, info[4];
+    HIP_TRY(hipMemcpyAsync(&cnt, p->p_count, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(info, p->p_info, sizeof(info), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const uint32_t take = std::min(cnt, cap);
+    std::vector<uint64_t> hidx(p->cap);
+    std::vector<double> hval(2 * (size_t)p->cap);
+    HIP_TRY(hipMemcpy(hidx.data(), p->p_idx, sizeof(uint64_t) * p->cap, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hval.data(), p->p_val, sizeof(double) * 2 * p->cap, hipMemcpyDeviceToHost));
+    std::copy(hidx.begin(), hidx.begin() + take, idx_host);
+    std::copy(hval.begin(), hval.begin() + 2 * take, val_host);
+    *count_host = take;
+    if (info_host) std::copy(info, info + 4, info_host);
+    if ((info[SFFT_INFO_FLAGS] & 1u) || cnt > cap) return fail(SFFT_ETRUNC, "more coefficients than cap");
+    return SFFT_OK;
+}
+
+sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t count, const uint64_t* seeds_dev,
+                                 uint64_t* idx_dev, double* val_dev, uint32_t* count_dev, uint32_t* info_dev,
+                                 void* stream) {
+    if (!p || !x_dev || !idx_dev || !val_dev || !count_dev) return fail(SFFT_EINVAL, "NULL argument");
+    if (count < 1 || count > p->d.max_batch) return fail(SFFT_EINVAL, "count must be in [1, max_batch]");
+    std::lock_guard<std::mutex> lock(p->mu);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const char* nog = std::getenv("SFFT_NO_GRAPH");
+    if (nog && nog[0] == '1') return enqueue_batch(p, x_dev, count, seeds_dev, idx_dev, val_dev, count_dev, info_dev, s);
+    GraphCache& gc = p->graph;
+    const bool hit = gc.exec && gc.x == x_dev && gc.count == count && gc.seeds == seeds_dev && gc.o1 == idx_dev &&
+                     gc.o2 == val_dev && gc.o3 == count_dev && gc.o4 == info_dev;
+    if (!hit) {
+        if (gc.exec) {
+            HIP_TRY(hipGraphExecDestroy(gc.exec));
+            gc.exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+        sfft_status_t st = enqueue_batch(p, x_dev, count, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
+                                         p->capture_stream);
+        hipError_t ee = hipStreamEndCapture(p->capture_stream, &graph);
+        if (st != SFFT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        if (ee != hipSuccess) return fail(SFFT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+        hipError_t ie = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            gc.exec = nullptr;
+            return fail(SFFT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        }
+        gc.x = x_dev;
+        gc.count = count;
+        gc.seeds = seeds_dev;
+        gc.o1 = idx_dev;
+        gc.o2 = val_dev;
+        gc.o3 = count_dev;
+        gc.o4 = info_dev;
+    }
+    HIP_TRY(hipGraphLaunch(gc.exec, s));
+    return SFFT_OK;
+}
+
+}  // extern "C"

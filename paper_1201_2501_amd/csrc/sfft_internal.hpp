@@ -1,0 +1,110 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sfft.h"
+#include "sfft_common.hpp"
+
+namespace sfft {
+
+constexpr uint32_t kThreads = 256;        // workgroup size of every kernel
+constexpr uint32_t kMaxRounds = 32;
+constexpr uint32_t kMaxZ = 4096;          // zhat capacity and bin-count limit (LDS sort space)
+constexpr uint32_t kStateWords = 8;       // per-signal decode state words
+
+// Per-signal decode state (uint32 words in device memory).
+enum : uint32_t {
+    ST_ZCOUNT = 0,    // entries of zhat
+    ST_ZBUF = 1,      // which of the two zhat buffers is current
+    ST_EMPTY = 2,     // consecutive rounds with J empty
+    ST_ROUNDS = 3,    // rounds decoded
+    ST_DONE = 4,      // 1 once the stopping rule fired
+    ST_FLAGS = 5,     // bit 0 truncated output, bit 1 zhat overflow
+    ST_LASTJ = 6,     // |J| of the last decoded round
+    ST_ACCEPT = 7     // accepted candidates of the last decoded round
+};
+
+// Geometry of one hashing round (device copy).
+struct RoundDev {
+    uint32_t B;
+    uint32_t logB;
+    uint64_t w;
+    int64_t t0;          // window support t in [t0, t0 + w), t0 = -w/2
+    uint64_t gofs;       // offset of this round's window in the window tables
+    WindowShape ws;
+};
+
+// Arguments of the HashToBins pair kernels.
+struct H2BArgs {
+    const void* x;
+    uint64_t n;
+    uint64_t sig_stride;       // elements between signals
+    const uint64_t* seeds;     // [count] or nullptr
+    uint64_t plan_seed;
+    uint32_t count;            // signals
+    uint32_t round_lo;         // rounds [round_lo, round_lo + nrounds)
+    uint32_t nrounds;
+    uint32_t Bmax;
+    uint32_t logBmax;
+    uint32_t explicit_job;     // 1: use sigma/a/beta/b below for every block
+    uint64_t sigma, a, beta, b;
+    const RoundDev* geom;      // indexed by round
+    const void* gtab;          // window tables (double or float)
+    const void* tw;            // twiddles e^{-2 pi i m / Bmax}, m < Bmax/2 (double2/float2)
+    double* raw;               // [sig][round][2][Bmax] complex128 out
+    uint32_t raw_rounds;       // rounds dimension of raw
+    double sqrt_n;
+    // split (plain path): partial sums [part][2][B] complex128
+    double* partial;
+    uint32_t parts;
+    uint32_t lchunk;
+    uint32_t mcap;             // entries of the LDS modulation table
+};
+
+struct DecodeArgs {
+    uint64_t n;
+    uint32_t count;
+    uint32_t rounds;           // rounds with raw bins available (raw dimension)
+    uint32_t r_begin, r_end;   // rounds decoded by this launch
+    uint32_t patience;
+    uint32_t Bmax;
+    uint32_t capz;             // capacity of each zhat buffer
+    uint32_t cap;              // output capacity
+    const RoundDev* geom;
+    const uint64_t* seeds;
+    uint64_t plan_seed;
+    const double* raw;         // [sig][rounds][2][Bmax]
+    double* work;              // [sig][2][Bmax] working bins
+    uint64_t* cand_i;          // [sig][Bmax]
+    double* cand_v;            // [sig][Bmax][2]
+    uint64_t* zidx;            // [sig][2][capz]
+    double* zval;              // [sig][2][capz][2]
+    double* est;               // [sig][capz][rounds][2] re-estimation samples
+    double* fin;               // [sig][capz][2] re-estimated values
+    double* gtmp;              // [sig][capz] window values of one round
+    uint32_t* ecount;          // [sig][capz] samples per entry
+    uint32_t* state;           // [sig][kStateWords]
+    double theta, g_min;
+    double out_scale;
+    uint64_t* out_idx;         // [sig][cap]
+    double* out_val;           // [sig][cap][2]
+    uint32_t* out_count;       // [sig]
+    uint32_t* out_info;        // [sig][4] or nullptr
+};
+
+// kernel launchers (sfft_kernels.hip); return hipError_t of the launch
+hipError_t launch_h2b_pair(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s);
+hipError_t launch_h2b_split(const H2BArgs& a, uint32_t round, bool in_c128, bool acc_f64, hipStream_t s);
+hipError_t launch_h2b_reduce(const H2BArgs& a, uint32_t round, bool acc_f64, hipStream_t s);
+hipError_t launch_exact_init(const DecodeArgs& a, hipStream_t s);
+hipError_t launch_exact_decode(const DecodeArgs& a, hipStream_t s);
+hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s);
+
+size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64);
+
+}  // namespace sfft

@@ -1,0 +1,239 @@
+"""ctypes binding of the sparse FFT C ABI (include/sfft.h).
+
+The functions below carry the C names and only marshal arguments: every step
+of the transform runs in the HIP library.  torch is used for device memory
+and streams only.  Importing works without a GPU (the pure host functions
+can then be called); a missing library raises at load time - there is no
+fallback implementation.
+"""
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsfft.so")
+
+SFFT_OK, SFFT_EINVAL, SFFT_ENOTPOW2, SFFT_ENOMEM, SFFT_EBUDGET, SFFT_EHIP, SFFT_ETRUNC, SFFT_EUNSUPPORTED = range(8)
+SFFT_MODE_EXACT, SFFT_MODE_GENERAL = 0, 1
+SFFT_C64, SFFT_C128 = 0, 1
+SFFT_F32, SFFT_F64 = 0, 1
+SFFT_FLAG_NUMPY_NORM = 0x1
+INFO_ROUNDS, INFO_FLAGS, INFO_ZHAT, INFO_LOCATED = range(4)
+
+# every symbol declared in include/sfft.h
+EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_plan_ex", "sfft_plan",
+           "sfft_plan_get_desc", "sfft_destroy", "sfft_execute", "sfft_execute_batch",
+           "sfft_hash_pair_raw", "sfft_status_string", "sfft_last_error", "sfft_splitmix64"]
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("n", c_uint64), ("w", c_uint64), ("seed", c_uint64), ("k", c_uint32), ("B", c_uint32),
+                ("mode", c_int32), ("in_dtype", c_int32), ("loc_prec", c_int32), ("est_prec", c_int32),
+                ("alpha", c_double), ("delta", c_double), ("theta", c_double), ("g_min", c_double),
+                ("s", c_double), ("rounds", c_uint32), ("b_min", c_uint32), ("patience", c_uint32),
+                ("t", c_uint32), ("R_loc", c_uint32), ("R_est", c_uint32), ("cap", c_uint32),
+                ("flags", c_uint32), ("max_batch", c_uint32), ("reserved", c_uint32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libsfft.so (built by paper_1201_2501_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("sparse FFT HIP library not built: run `python -m paper_1201_2501_amd.build` "
+                           "(expected %s)" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    lib.sfft_desc_init.argtypes = [POINTER(PlanDesc), c_uint64, c_uint32, c_uint32, c_uint64, c_uint64]
+    lib.sfft_validate_params.argtypes = [POINTER(PlanDesc)]
+    lib.sfft_default_w.argtypes = [c_uint64, c_uint32, c_double, c_double]
+    lib.sfft_default_w.restype = c_uint64
+    lib.sfft_plan_ex.argtypes = [POINTER(PlanDesc), POINTER(P)]
+    lib.sfft_plan.argtypes = [c_uint64, c_uint32, c_uint32, c_uint64, c_uint64, POINTER(P)]
+    lib.sfft_plan_get_desc.argtypes = [P, POINTER(PlanDesc)]
+    lib.sfft_destroy.argtypes = [P]
+    lib.sfft_execute.argtypes = [P, P, P, P, c_uint32, P, P, P]
+    lib.sfft_execute_batch.argtypes = [P, P, c_uint32, P, P, P, P, P, P]
+    lib.sfft_hash_pair_raw.argtypes = [P, P, c_uint64, c_uint64, c_uint64, c_uint64, c_uint32, c_int32, P, P, P]
+    lib.sfft_status_string.argtypes = [c_int32]
+    lib.sfft_status_string.restype = c_char_p
+    lib.sfft_last_error.argtypes = []
+    lib.sfft_last_error.restype = c_char_p
+    lib.sfft_splitmix64.argtypes = [c_uint64, c_uint64]
+    lib.sfft_splitmix64.restype = c_uint64
+    for name in EXPORTS:
+        if name not in ("sfft_default_w", "sfft_status_string", "sfft_last_error", "sfft_splitmix64"):
+            getattr(lib, name).restype = c_int32
+    _lib = lib
+    return lib
+
+
+class SfftError(RuntimeError):
+    def __init__(self, status, where):
+        lib = load()
+        self.status = status
+        super().__init__("%s: %s (%s)" % (where, lib.sfft_status_string(status).decode(),
+                                          lib.sfft_last_error().decode()))
+
+
+def _check(status, where, allow=()):
+    if status != SFFT_OK and status not in allow:
+        raise SfftError(status, where)
+    return status
+
+
+# ---- thin wrappers with the C names ---------------------------------------
+def sfft_desc_init(n, k, B, w=0, seed=0):
+    d = PlanDesc()
+    _check(load().sfft_desc_init(ctypes.byref(d), n, k, B, w, seed), "sfft_desc_init")
+    return d
+
+
+def sfft_validate_params(desc):
+    return load().sfft_validate_params(ctypes.byref(desc))
+
+
+def sfft_default_w(n, B, alpha=0.5, delta=1e-9):
+    return int(load().sfft_default_w(n, B, alpha, delta))
+
+
+def sfft_plan_ex(desc):
+    p = c_void_p()
+    _check(load().sfft_plan_ex(ctypes.byref(desc), ctypes.byref(p)), "sfft_plan_ex")
+    return p
+
+
+def sfft_plan(n, k, B, w=0, seed=0):
+    p = c_void_p()
+    _check(load().sfft_plan(n, k, B, w, seed, ctypes.byref(p)), "sfft_plan")
+    return p
+
+
+def sfft_plan_get_desc(plan):
+    d = PlanDesc()
+    _check(load().sfft_plan_get_desc(plan, ctypes.byref(d)), "sfft_plan_get_desc")
+    return d
+
+
+def sfft_destroy(plan):
+    return load().sfft_destroy(plan)
+
+
+def sfft_splitmix64(seed, c):
+    return int(load().sfft_splitmix64(seed, c))
+
+
+def sfft_status_string(status):
+    return load().sfft_status_string(status).decode()
+
+
+def sfft_last_error():
+    return load().sfft_last_error().decode()
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def sfft_execute(plan, x, cap, stream=None):
+    """Plain path on one device signal x (torch tensor).  Returns
+    (indices int64[count], values complex128[count], info uint32[4], status)."""
+    idx = np.zeros(cap, dtype=np.uint64)
+    val = np.zeros(2 * cap, dtype=np.float64)
+    cnt = np.zeros(1, dtype=np.uint32)
+    info = np.zeros(4, dtype=np.uint32)
+    st = load().sfft_execute(plan, c_void_p(x.data_ptr()), idx.ctypes.data_as(c_void_p),
+                             val.ctypes.data_as(c_void_p), cap, cnt.ctypes.data_as(c_void_p),
+                             info.ctypes.data_as(c_void_p), _stream_handle(stream))
+    _check(st, "sfft_execute", allow=(SFFT_ETRUNC,))
+    c = int(cnt[0])
+    return idx[:c].astype(np.int64), val[: 2 * c].view(np.complex128).copy(), info, st
+
+
+def sfft_execute_batch(plan, x, count, seeds, idx, val, counts, info, stream=None):
+    """Batched path; every argument is a device tensor (seeds may be None)."""
+    st = load().sfft_execute_batch(plan, c_void_p(x.data_ptr()), count,
+                                   c_void_p(seeds.data_ptr() if seeds is not None else None),
+                                   c_void_p(idx.data_ptr()), c_void_p(val.data_ptr()),
+                                   c_void_p(counts.data_ptr()),
+                                   c_void_p(info.data_ptr() if info is not None else None),
+                                   _stream_handle(stream))
+    return _check(st, "sfft_execute_batch")
+
+
+def sfft_hash_pair_raw(plan, x, sigma, a, beta, b, B_r, prec, out0, out1, stream=None):
+    st = load().sfft_hash_pair_raw(plan, c_void_p(x.data_ptr()), sigma, a, beta, b, B_r, prec,
+                                   c_void_p(out0.data_ptr()), c_void_p(out1.data_ptr()),
+                                   _stream_handle(stream))
+    return _check(st, "sfft_hash_pair_raw")
+
+
+# ---- convenience object ------------------------------------------------------
+class Plan:
+    """Owns one sfft plan; fields of PlanDesc can be overridden by keyword."""
+
+    def __init__(self, n, k, B, w=0, seed=0, **fields):
+        d = sfft_desc_init(n, k, B, w, seed)
+        for key, v in fields.items():
+            if not hasattr(d, key):
+                raise TypeError("unknown plan field %r" % key)
+            setattr(d, key, v)
+        self.handle = sfft_plan_ex(d)
+        self.desc = sfft_plan_get_desc(self.handle)
+        self._batch_bufs = None
+
+    def close(self):
+        if self.handle:
+            sfft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def cap(self):
+        return self.desc.cap
+
+    def execute(self, x, stream=None):
+        return sfft_execute(self.handle, x, self.cap, stream)
+
+    def batch_buffers(self, count, device):
+        import torch
+
+        key = (count, str(device))
+        if self._batch_bufs is None or self._batch_bufs[0] != key:
+            cap = self.cap
+            self._batch_bufs = (key, dict(
+                idx=torch.zeros((count, cap), dtype=torch.int64, device=device),
+                val=torch.zeros((count, cap), dtype=torch.complex128, device=device),
+                counts=torch.zeros(count, dtype=torch.int32, device=device),
+                info=torch.zeros((count, 4), dtype=torch.int32, device=device)))
+        return self._batch_bufs[1]
+
+    def execute_batch(self, x, seeds=None, stream=None, bufs=None):
+        """x: [count, n] device tensor; seeds: int64 device tensor or None.
+        Returns the device buffers dict (idx, val, counts, info)."""
+        count = x.shape[0]
+        b = bufs if bufs is not None else self.batch_buffers(count, x.device)
+        sfft_execute_batch(self.handle, x, count, seeds, b["idx"], b["val"], b["counts"], b["info"], stream)
+        return b
+
+    def hash_pair_raw(self, x, sigma, a, beta, b, B_r, prec=SFFT_F64, stream=None):
+        import torch
+
+        out0 = torch.empty(B_r, dtype=torch.complex128, device=x.device)
+        out1 = torch.empty(B_r, dtype=torch.complex128, device=x.device)
+        sfft_hash_pair_raw(self.handle, x, sigma, a, beta, b, B_r, prec, out0, out1, stream)
+        return out0, out1

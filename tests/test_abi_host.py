@@ -1,0 +1,74 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol that include/sfft.h declares, and its pure host functions agree
+with the oracle's independent implementations."""
+import os
+import re
+
+import pytest
+
+from paper_1201_2501_amd import sfft
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "sfft.h")).read()
+    return sorted(set(re.findall(r"\b(sfft_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_symbols() == sorted(sfft.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = sfft.load()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+
+
+def test_splitmix64_matches_golden_vectors():
+    from tests.test_oracle_rng import golden_rows
+    for seed, c, expect in golden_rows():
+        assert sfft.sfft_splitmix64(seed, c) == expect
+
+
+def test_desc_defaults():
+    d = sfft.sfft_desc_init(1 << 22, 256, 1024, 0, 7)
+    assert (d.n, d.k, d.B, d.w, d.seed) == (1 << 22, 256, 1024, 0, 7)
+    assert d.mode == sfft.SFFT_MODE_EXACT and d.in_dtype == sfft.SFFT_C64
+    assert d.loc_prec == sfft.SFFT_F64          # n >= 2^20: FP64 location decoding
+    assert sfft.sfft_desc_init(1 << 14, 16, 64).loc_prec == sfft.SFFT_F32
+    assert d.alpha == 0.5 and d.patience == 3 and d.rounds == 16
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n", 3000, sfft.SFFT_ENOTPOW2), ("n", 2, sfft.SFFT_ENOTPOW2), ("k", 0, sfft.SFFT_EINVAL),
+    ("B", 1000, sfft.SFFT_ENOTPOW2), ("B", 1 << 23, sfft.SFFT_EINVAL), ("w", 1000, sfft.SFFT_EINVAL),
+    ("alpha", 1.5, sfft.SFFT_EINVAL), ("delta", 0.0, sfft.SFFT_EINVAL), ("rounds", 0, sfft.SFFT_EINVAL),
+    ("rounds", 33, sfft.SFFT_EINVAL), ("b_min", 3, sfft.SFFT_EINVAL), ("max_batch", 0, sfft.SFFT_EINVAL),
+    ("in_dtype", 5, sfft.SFFT_EINVAL), ("g_min", 0.0, sfft.SFFT_EINVAL),
+])
+def test_validation_errors(field, value, status):
+    d = sfft.sfft_desc_init(1 << 22, 256, 1024, 0, 7)
+    setattr(d, field, value)
+    assert sfft.sfft_validate_params(d) == status
+    assert sfft.sfft_last_error() != ""
+
+
+def test_lds_limit_is_reported_as_unsupported():
+    d = sfft.sfft_desc_init(1 << 22, 256, 8192, 0, 7)
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EUNSUPPORTED
+    d.B = 4096
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK
+
+
+@pytest.mark.parametrize("n,B,alpha,delta", [(1 << 14, 64, 0.5, 1e-12), (1 << 20, 1024, 0.5, 1e-6),
+                                             (1 << 16, 256, 0.25, 1e-9)])
+def test_default_window_matches_oracle_definition(n, B, alpha, delta):
+    from oracle.window import default_w
+    assert sfft.sfft_default_w(n, B, alpha, delta) == default_w(n, B, alpha, delta)
+
+
+def test_status_strings():
+    assert sfft.sfft_status_string(sfft.SFFT_ETRUNC) == "SFFT_ETRUNC"

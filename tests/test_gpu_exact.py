@@ -1,0 +1,224 @@
+"""GPU parity of the exact-mode hot path against the FP64 oracle.
+
+Bars: raw bins within 1e-12 (FP64 arithmetic) / 2e-5 (FP32) of the oracle's,
+relative to the largest bin; recovered supports bit-exact; values within
+1e-10 (FP64) relative to the coefficient magnitude.  Every case prints its
+name, shape and seed before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+import siggen
+from oracle.exact import noiseless_sparse_fft
+from oracle.hashing import hash_to_bins_raw
+from oracle.params import SfftParams
+from oracle.window import default_w, window_time
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    from paper_1201_2501_amd import sfft
+    sfft.load()
+    return torch, torch.device("cuda:0")
+
+
+def plan_for(n, k, B, w, seed, **kw):
+    from paper_1201_2501_amd.sfft import Plan
+    return Plan(n, k, B, w, seed, **kw)
+
+
+def oracle_params(plan, seed=None):
+    d = plan.desc
+    return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=d.seed if seed is None else seed, alpha=d.alpha,
+                      delta=d.delta, theta=d.theta, g_min=d.g_min, rounds=d.rounds, b_min=d.b_min,
+                      patience=d.patience, cap=d.cap)
+
+
+RAW_CASES = [
+    # (name, n, B, dtype, prec, beta, B_r)
+    ("c1-pair", 1 << 14, 64, np.complex128, 1, 1, 64),
+    ("c1-pair-B16", 1 << 14, 64, np.complex128, 1, 1, 16),
+    ("c3-pair-f64", 1 << 22, 1024, np.complex64, 1, 1, 1024),
+    ("c3-pair-f32", 1 << 22, 1024, np.complex64, 0, 1, 1024),
+    ("c3-small-round", 1 << 22, 1024, np.complex64, 1, 1, 64),
+    ("beta-inside", 1 << 18, 512, np.complex64, 1, 777, 512),
+    ("beta-beyond-w", 1 << 18, 512, np.complex64, 1, 100003, 512),
+]
+
+
+@pytest.mark.parametrize("name,n,B,dtype,prec,beta,B_r", RAW_CASES)
+def test_raw_bins_match_oracle(torch_dev, name, n, B, dtype, prec, beta, B_r):
+    torch, dev = torch_dev
+    delta = 1e-12 if dtype == np.complex128 else 1e-9
+    w = default_w(n, B, 0.5, delta)
+    x, sup, val = siggen.planted_signal(n, 40, 11, dtype, noise_ratio=0.01)
+    in_dtype = 1 if dtype == np.complex128 else 0
+    say(name, "n", n, "B", B, "B_r", B_r, "w", w, "prec", prec, "beta", beta)
+    plan = plan_for(n, 40, B, w, 5, delta=delta, in_dtype=in_dtype, loc_prec=prec, b_min=16)
+    xd = torch.from_numpy(x).to(dev)
+    rng = np.random.default_rng(hash(name) % 1000)
+    sigma = int(rng.integers(0, n // 2)) * 2 + 1
+    a = int(rng.integers(0, n))
+    b = int(rng.integers(0, n))
+    u0, u1 = plan.hash_pair_raw(xd, sigma, a, beta, b, B_r, prec)
+    torch.cuda.synchronize()
+    u0 = u0.cpu().numpy()
+    u1 = u1.cpu().numpy()
+    G = window_time(n, B_r, w * B_r // B, 0.5, delta)
+    e0 = hash_to_bins_raw(x, sigma, a, b, B_r, G)
+    e1 = hash_to_bins_raw(x, sigma, (a + beta) % n, b, B_r, G)
+    tol = 1e-12 if prec == 1 else 2e-5
+    scale = max(np.max(np.abs(e0)), np.max(np.abs(e1)))
+    assert np.max(np.abs(u0 - e0)) <= tol * scale
+    assert np.max(np.abs(u1 - e1)) <= tol * scale
+    plan.close()
+
+
+def c1_case(seed):
+    n, k, B = 1 << 14, 16, 64
+    return n, k, B, default_w(n, B, 0.5, 1e-12)
+
+
+def compare(res_idx, res_val, ref, rel=1e-10):
+    assert np.array_equal(res_idx, ref.indices), (res_idx, ref.indices, ref.margins)
+    mag = np.maximum(np.abs(ref.values), 1e-300)
+    assert np.all(np.abs(res_val - ref.values) <= rel * mag + 1e-14)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_plain_exact_c1_matches_oracle(torch_dev, seed):
+    torch, dev = torch_dev
+    n, k, B, w = c1_case(seed)
+    say("plain-c1", "n", n, "k", k, "seed", seed)
+    plan = plan_for(n, k, B, w, seed, delta=1e-12, in_dtype=1, loc_prec=1)
+    x, sup, val = siggen.planted_signal(n, k, 100 + seed, np.complex128)
+    idx, v, info, st = plan.execute(torch.from_numpy(x).to(dev))
+    ref = noiseless_sparse_fft(x, oracle_params(plan))
+    assert int(info[0]) == ref.rounds_used
+    compare(idx, v, ref)
+    assert np.array_equal(idx, sup)
+    plan.close()
+
+
+def run_batch(torch, dev, plan, xs, seeds):
+    X = torch.from_numpy(np.stack(xs)).to(dev)
+    S = torch.tensor(seeds, dtype=torch.int64, device=dev)
+    bufs = plan.execute_batch(X, S)
+    torch.cuda.synchronize()
+    out = []
+    for r in range(len(xs)):
+        c = int(bufs["counts"][r])
+        out.append((bufs["idx"][r, :c].cpu().numpy(), bufs["val"][r, :c].cpu().numpy(),
+                    bufs["info"][r].cpu().numpy()))
+    return out
+
+
+def test_batched_exact_c1_matches_oracle_per_seed(torch_dev):
+    torch, dev = torch_dev
+    n, k, B, w = c1_case(0)
+    count = 8
+    say("batched-c1", "n", n, "count", count)
+    plan = plan_for(n, k, B, w, 0, delta=1e-12, in_dtype=1, loc_prec=1, max_batch=count)
+    xs, seeds = [], []
+    for s in range(count):
+        x, _, _ = siggen.planted_signal(n, k, 200 + s, np.complex128)
+        xs.append(x)
+        seeds.append(1000 + 17 * s)
+    out = run_batch(torch, dev, plan, xs, seeds)
+    for s in range(count):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        assert int(out[s][2][0]) == ref.rounds_used
+        compare(out[s][0], out[s][1], ref)
+    plan.close()
+
+
+def test_graph_replays_are_identical_and_batch_independent(torch_dev):
+    torch, dev = torch_dev
+    n, k, B, w = c1_case(0)
+    count = 6
+    say("graph-replay", "n", n, "count", count)
+    plan = plan_for(n, k, B, w, 0, delta=1e-12, in_dtype=1, loc_prec=1, max_batch=count)
+    xs = [siggen.planted_signal(n, k, 300 + s, np.complex128)[0] for s in range(count)]
+    seeds = [5 + s for s in range(count)]
+    X = torch.from_numpy(np.stack(xs)).to(dev)
+    S = torch.tensor(seeds, dtype=torch.int64, device=dev)
+    first = None
+    for rep in range(3):
+        bufs = plan.execute_batch(X, S)
+        torch.cuda.synchronize()
+        snap = {key: t.clone() for key, t in bufs.items()}
+        _ = (X.abs() * 2).sum().item()          # eager work between replays
+        if first is None:
+            first = snap
+        else:
+            for key in snap:
+                assert torch.equal(snap[key], first[key]), key
+    # the same signal alone (different batch) gives the same answer
+    alone = plan_for(n, k, B, w, 0, delta=1e-12, in_dtype=1, loc_prec=1, max_batch=1)
+    for s in (0, 3):
+        o = run_batch(torch, dev, alone, [xs[s]], [seeds[s]])[0]
+        c = int(first["counts"][s])
+        assert np.array_equal(o[0], first["idx"][s, :c].cpu().numpy())
+        assert np.allclose(o[1], first["val"][s, :c].cpu().numpy(), rtol=1e-12, atol=0)
+    plan.close()
+    alone.close()
+
+
+def test_plain_and_batched_agree(torch_dev):
+    torch, dev = torch_dev
+    n, k, B, w = c1_case(0)
+    say("plain-vs-batched", "n", n)
+    plan = plan_for(n, k, B, w, 42, delta=1e-12, in_dtype=1, loc_prec=1, max_batch=2)
+    x, _, _ = siggen.planted_signal(n, k, 77, np.complex128)
+    idx, v, info, st = plan.execute(torch.from_numpy(x).to(dev))
+    o = run_batch(torch, dev, plan, [x, x], [42, 42])
+    for r in range(2):
+        assert np.array_equal(o[r][0], idx)
+        assert np.allclose(o[r][1], v, rtol=1e-11, atol=1e-14)
+
+
+def test_zero_signal_and_truncation(torch_dev):
+    torch, dev = torch_dev
+    n, k, B, w = c1_case(0)
+    say("edge-zero-trunc", "n", n)
+    plan = plan_for(n, 4, B, w, 3, delta=1e-12, in_dtype=1, loc_prec=1)
+    idx, v, info, st = plan.execute(torch.zeros(n, dtype=torch.complex128, device=dev))
+    assert len(idx) == 0 and int(info[0]) == plan.desc.patience
+    # 12 planted coefficients with cap 4: the 4 largest are returned, flagged
+    sup, val = siggen.planted_spectrum(n, 12, 9, magnitude="loguniform")
+    x = siggen.time_signal(n, sup, val)
+    idx, v, info, st = plan.execute(torch.from_numpy(x).to(dev))
+    ref = noiseless_sparse_fft(x, oracle_params(plan))
+    assert ref.truncated and (int(info[1]) & 1) == 1
+    assert st == 6    # SFFT_ETRUNC
+    compare(idx, v, ref)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_c3_shape_matches_oracle(torch_dev, seed):
+    """n = 2^22, k = 256, log-uniform magnitudes, complex64, FP64 location
+    decoding: the bench's plan parameters on a few signals."""
+    torch, dev = torch_dev
+    n, k, B = 1 << 22, 256, 1024
+    w = default_w(n, B, 0.5, 1e-9)
+    say("c3-shape", "n", n, "k", k, "B", B, "w", w, "seed", seed)
+    plan = plan_for(n, k, B, w, 0, delta=1e-9, theta=0.02, loc_prec=1, max_batch=2)
+    xs, sups, seeds = [], [], []
+    for s in range(2):
+        x, sup, val = siggen.planted_signal(n, k, 300 + 2 * seed + s, np.complex64, magnitude="loguniform")
+        xs.append(x)
+        sups.append(sup)
+        seeds.append(10 * seed + s)
+    out = run_batch(torch, dev, plan, xs, seeds)
+    for s in range(2):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        compare(out[s][0], out[s][1], ref)
+        assert np.array_equal(out[s][0], sups[s])
+    plan.close()
