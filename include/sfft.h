@@ -60,6 +60,7 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
 
 /* flags */
 #define SFFT_FLAG_NUMPY_NORM 0x1u   /* return values scaled by sqrt(n)                  */
+#define SFFT_FLAG_TIMING 0x2u       /* record HIP events around each batched phase     */
 
 /* per-signal info words written by the batched entry point (4 x uint32)     */
 #define SFFT_INFO_ROUNDS 0          /* rounds whose bins were decoded                 */
@@ -137,8 +138,7 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
                              uint64_t w, uint64_t seed);
 
 /* Check a description against the limits listed above (and the kernels'
- * LDS limits: B <= 4096 for FP64 pairs, B <= 8192 for FP32).  Pure host
- * function.  Returns SFFT_OK, SFFT_ENOTPOW2, SFFT_EINVAL or
+ * LDS limit B <= 4096).  Pure host function.  Returns SFFT_OK, SFFT_ENOTPOW2, SFFT_EINVAL or
  * SFFT_EUNSUPPORTED. */
 sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d);
 
@@ -184,8 +184,9 @@ sfft_status_t sfft_execute(sfft_plan_t p, const void* x_dev, uint64_t* idx_host,
 /*
  * A batch of independent signals ("batched" path): every hashing of every
  * signal runs in one launch, the per-signal rounds are decoded by a
- * persistent device loop, and the launch sequence is captured once into a
- * hipGraph and replayed (keyed by the argument pointers and count).
+ * persistent device loop, and the launch sequence is captured once into
+ * three hipGraphs (HashToBins, decode, output) and replayed (keyed by the
+ * argument pointers and count).
  * Asynchronous on `stream`; nothing is copied to the host.
  *   x_dev      [count][n] signals (in_dtype)
  *   count      1 <= count <= max_batch
@@ -213,6 +214,25 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
 sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigma, uint64_t a,
                                  uint64_t beta, uint64_t b, uint32_t B_r, int32_t prec,
                                  double* out0_dev, double* out1_dev, void* stream);
+
+/*
+ * Phase durations of the last sfft_execute_batch on a plan created with
+ * SFFT_FLAG_TIMING, measured by HIP events recorded on the launch stream
+ * between the three replayed graphs of a batch.  The caller must have
+ * synchronised that stream.  ms_host[0..3] = HashToBins phase (state reset +
+ * the pair kernel), decode loop, re-estimation and output, whole batch
+ * (milliseconds); n_out >= 4.  Errors: SFFT_EINVAL when
+ * the flag is not set or nothing ran yet, SFFT_EHIP.
+ */
+sfft_status_t sfft_plan_timings(sfft_plan_t p, double* ms_host, uint32_t n_out);
+
+/*
+ * Algorithmic HBM bytes of one batched HashToBins launch for `count`
+ * signals: every distinct input sample read once per hashing pair
+ * ((w_r + 1) samples of in_dtype per round) plus the raw bins written
+ * (2 B_r complex128 per round).  Pure host function.
+ */
+uint64_t sfft_plan_h2b_bytes(sfft_plan_t p, uint32_t count);
 
 /* Human-readable name of a status code (static storage). */
 const char* sfft_status_string(sfft_status_t s);

@@ -93,7 +93,7 @@ uint32_t zhat_capacity(const sfft_plan_desc_t& d) {
 
 // ------------------------------------------------------------------ plan ---
 struct GraphCache {
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
     const void* x = nullptr;
     const void* seeds = nullptr;
     const void* o1 = nullptr;
@@ -139,6 +139,8 @@ struct sfft_plan_s {
     uint32_t* p_count = nullptr;
     uint32_t* p_info = nullptr;
     hipStream_t capture_stream = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool timed_once = false;
     GraphCache graph;
     std::mutex mu;
     std::vector<void*> allocations;
@@ -252,6 +254,8 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     ST_TRY(dev_alloc(p, &p->p_count, 1));
     ST_TRY(dev_alloc(p, &p->p_info, 4));
     HIP_TRY(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+    if (d.flags & SFFT_FLAG_TIMING)
+        for (auto& e : p->ev) HIP_TRY(hipEventCreate(&e));
     return SFFT_OK;
 }
 
@@ -312,20 +316,26 @@ DecodeArgs base_decode(const sfft_plan_s* p, uint32_t count, const uint64_t* see
     return D;
 }
 
-sfft_status_t enqueue_batch(sfft_plan_s* p, const void* x, uint32_t count, const uint64_t* seeds,
-                            uint64_t* idx, double* val, uint32_t* cnt, uint32_t* info, hipStream_t s) {
+// The batched sequence in three parts: 0 = init + HashToBins of every round
+// of every signal, 1 = decode loop, 2 = re-estimation and output.
+sfft_status_t enqueue_batch_part(sfft_plan_s* p, int part, const void* x, uint32_t count, const uint64_t* seeds,
+                                 uint64_t* idx, double* val, uint32_t* cnt, uint32_t* info, hipStream_t s) {
     DecodeArgs D = base_decode(p, count, seeds, p->raw, idx, val, cnt, info);
-    HIP_TRY(launch_exact_init(D, s));
-    H2BArgs a = base_h2b(p, x);
-    a.seeds = seeds;
-    a.count = count;
-    a.round_lo = 0;
-    a.nrounds = p->R;
-    a.raw = p->raw;
-    a.raw_rounds = p->R;
-    HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
-    HIP_TRY(launch_exact_decode(D, s));
-    HIP_TRY(launch_exact_finish(D, s));
+    if (part == 0) {
+        HIP_TRY(launch_exact_init(D, s));
+        H2BArgs a = base_h2b(p, x);
+        a.seeds = seeds;
+        a.count = count;
+        a.round_lo = 0;
+        a.nrounds = p->R;
+        a.raw = p->raw;
+        a.raw_rounds = p->R;
+        HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
+    } else if (part == 1) {
+        HIP_TRY(launch_exact_decode(D, s));
+    } else {
+        HIP_TRY(launch_exact_finish(D, s));
+    }
     return SFFT_OK;
 }
 
@@ -449,11 +459,34 @@ sfft_status_t sfft_plan_get_desc(sfft_plan_t p, sfft_plan_desc_t* out) {
 
 sfft_status_t sfft_destroy(sfft_plan_t p) {
     if (!p) return SFFT_OK;
-    if (p->graph.exec) (void)hipGraphExecDestroy(p->graph.exec);
+    for (auto& ge : p->graph.exec)
+        if (ge) (void)hipGraphExecDestroy(ge);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    for (auto& e : p->ev)
+        if (e) (void)hipEventDestroy(e);
     for (void* q : p->allocations) (void)hipFree(q);
     delete p;
     return SFFT_OK;
+}
+
+sfft_status_t sfft_plan_timings(sfft_plan_t p, double* ms_host, uint32_t n_out) {
+    if (!p || !ms_host || n_out < 4) return fail(SFFT_EINVAL, "bad argument");
+    if (!(p->d.flags & SFFT_FLAG_TIMING) || !p->timed_once) return fail(SFFT_EINVAL, "timing not enabled or nothing ran");
+    float ms[4];
+    HIP_TRY(hipEventElapsedTime(&ms[0], p->ev[0], p->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&ms[1], p->ev[1], p->ev[2]));
+    HIP_TRY(hipEventElapsedTime(&ms[2], p->ev[2], p->ev[3]));
+    HIP_TRY(hipEventElapsedTime(&ms[3], p->ev[0], p->ev[3]));
+    for (int q = 0; q < 4; ++q) ms_host[q] = ms[q];
+    return SFFT_OK;
+}
+
+uint64_t sfft_plan_h2b_bytes(sfft_plan_t p, uint32_t count) {
+    if (!p) return 0;
+    const uint64_t s_in = p->d.in_dtype == SFFT_C128 ? 16 : 8;
+    uint64_t per = 0;
+    for (const RoundDev& g : p->geom) per += (g.w + 1) * s_in + 2ull * g.B * 16ull;
+    return per * count;
 }
 
 sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigma, uint64_t a, uint64_t beta,
@@ -566,41 +599,61 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
     if (count < 1 || count > p->d.max_batch) return fail(SFFT_EINVAL, "count must be in [1, max_batch]");
     std::lock_guard<std::mutex> lock(p->mu);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const bool timing = (p->d.flags & SFFT_FLAG_TIMING) != 0;
     const char* nog = std::getenv("SFFT_NO_GRAPH");
-    if (nog && nog[0] == '1') return enqueue_batch(p, x_dev, count, seeds_dev, idx_dev, val_dev, count_dev, info_dev, s);
+    const bool use_graph = !(nog && nog[0] == '1');
     GraphCache& gc = p->graph;
-    const bool hit = gc.exec && gc.x == x_dev && gc.count == count && gc.seeds == seeds_dev && gc.o1 == idx_dev &&
-                     gc.o2 == val_dev && gc.o3 == count_dev && gc.o4 == info_dev;
-    if (!hit) {
-        if (gc.exec) {
-            HIP_TRY(hipGraphExecDestroy(gc.exec));
-            gc.exec = nullptr;
+    if (use_graph) {
+        const bool hit = gc.exec[0] && gc.x == x_dev && gc.count == count && gc.seeds == seeds_dev &&
+                         gc.o1 == idx_dev && gc.o2 == val_dev && gc.o3 == count_dev && gc.o4 == info_dev;
+        if (!hit) {
+            for (auto& ge : gc.exec)
+                if (ge) {
+                    HIP_TRY(hipGraphExecDestroy(ge));
+                    ge = nullptr;
+                }
+            for (int part = 0; part < 3; ++part) {
+                hipGraph_t graph = nullptr;
+                HIP_TRY(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+                sfft_status_t st = enqueue_batch_part(p, part, x_dev, count, seeds_dev, idx_dev, val_dev,
+                                                      count_dev, info_dev, p->capture_stream);
+                hipError_t ee = hipStreamEndCapture(p->capture_stream, &graph);
+                if (st != SFFT_OK) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return st;
+                }
+                if (ee != hipSuccess)
+                    return fail(SFFT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+                hipError_t ie = hipGraphInstantiate(&gc.exec[part], graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ie != hipSuccess) {
+                    gc.exec[part] = nullptr;
+                    return fail(SFFT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+                }
+            }
+            gc.x = x_dev;
+            gc.count = count;
+            gc.seeds = seeds_dev;
+            gc.o1 = idx_dev;
+            gc.o2 = val_dev;
+            gc.o3 = count_dev;
+            gc.o4 = info_dev;
         }
-        hipGraph_t graph = nullptr;
-        HIP_TRY(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
-        sfft_status_t st = enqueue_batch(p, x_dev, count, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
-                                         p->capture_stream);
-        hipError_t ee = hipStreamEndCapture(p->capture_stream, &graph);
-        if (st != SFFT_OK) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return st;
-        }
-        if (ee != hipSuccess) return fail(SFFT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
-        hipError_t ie = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ie != hipSuccess) {
-            gc.exec = nullptr;
-            return fail(SFFT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-        }
-        gc.x = x_dev;
-        gc.count = count;
-        gc.seeds = seeds_dev;
-        gc.o1 = idx_dev;
-        gc.o2 = val_dev;
-        gc.o3 = count_dev;
-        gc.o4 = info_dev;
     }
-    HIP_TRY(hipGraphLaunch(gc.exec, s));
+    for (int part = 0; part < 3; ++part) {
+        if (timing) HIP_TRY(hipEventRecord(p->ev[part], s));
+        if (use_graph) {
+            HIP_TRY(hipGraphLaunch(gc.exec[part], s));
+        } else {
+            sfft_status_t st = enqueue_batch_part(p, part, x_dev, count, seeds_dev, idx_dev, val_dev, count_dev,
+                                                  info_dev, s);
+            if (st != SFFT_OK) return st;
+        }
+    }
+    if (timing) {
+        HIP_TRY(hipEventRecord(p->ev[3], s));
+        p->timed_once = true;
+    }
     return SFFT_OK;
 }
 

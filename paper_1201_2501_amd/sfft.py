@@ -19,12 +19,14 @@ SFFT_MODE_EXACT, SFFT_MODE_GENERAL = 0, 1
 SFFT_C64, SFFT_C128 = 0, 1
 SFFT_F32, SFFT_F64 = 0, 1
 SFFT_FLAG_NUMPY_NORM = 0x1
+SFFT_FLAG_TIMING = 0x2
 INFO_ROUNDS, INFO_FLAGS, INFO_ZHAT, INFO_LOCATED = range(4)
 
 # every symbol declared in include/sfft.h
 EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_plan_ex", "sfft_plan",
            "sfft_plan_get_desc", "sfft_destroy", "sfft_execute", "sfft_execute_batch",
-           "sfft_hash_pair_raw", "sfft_status_string", "sfft_last_error", "sfft_splitmix64"]
+           "sfft_hash_pair_raw", "sfft_plan_timings", "sfft_plan_h2b_bytes", "sfft_status_string",
+           "sfft_last_error", "sfft_splitmix64"]
 
 
 class PlanDesc(ctypes.Structure):
@@ -60,6 +62,9 @@ def load():
     lib.sfft_execute.argtypes = [P, P, P, P, c_uint32, P, P, P]
     lib.sfft_execute_batch.argtypes = [P, P, c_uint32, P, P, P, P, P, P]
     lib.sfft_hash_pair_raw.argtypes = [P, P, c_uint64, c_uint64, c_uint64, c_uint64, c_uint32, c_int32, P, P, P]
+    lib.sfft_plan_timings.argtypes = [P, P, c_uint32]
+    lib.sfft_plan_h2b_bytes.argtypes = [P, c_uint32]
+    lib.sfft_plan_h2b_bytes.restype = c_uint64
     lib.sfft_status_string.argtypes = [c_int32]
     lib.sfft_status_string.restype = c_char_p
     lib.sfft_last_error.argtypes = []
@@ -67,7 +72,8 @@ def load():
     lib.sfft_splitmix64.argtypes = [c_uint64, c_uint64]
     lib.sfft_splitmix64.restype = c_uint64
     for name in EXPORTS:
-        if name not in ("sfft_default_w", "sfft_status_string", "sfft_last_error", "sfft_splitmix64"):
+        if name not in ("sfft_default_w", "sfft_status_string", "sfft_last_error", "sfft_splitmix64",
+                        "sfft_plan_h2b_bytes"):
             getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -122,6 +128,17 @@ def sfft_plan_get_desc(plan):
 
 def sfft_destroy(plan):
     return load().sfft_destroy(plan)
+
+
+def sfft_plan_timings(plan):
+    """[h2b_ms, decode_ms, finish_ms, total_ms] of the last batched execute."""
+    out = np.zeros(4, dtype=np.float64)
+    _check(load().sfft_plan_timings(plan, out.ctypes.data_as(c_void_p), 4), "sfft_plan_timings")
+    return out
+
+
+def sfft_plan_h2b_bytes(plan, count):
+    return int(load().sfft_plan_h2b_bytes(plan, count))
 
 
 def sfft_splitmix64(seed, c):
@@ -229,6 +246,12 @@ class Plan:
         b = bufs if bufs is not None else self.batch_buffers(count, x.device)
         sfft_execute_batch(self.handle, x, count, seeds, b["idx"], b["val"], b["counts"], b["info"], stream)
         return b
+
+    def timings(self):
+        return sfft_plan_timings(self.handle)
+
+    def h2b_bytes(self, count):
+        return sfft_plan_h2b_bytes(self.handle, count)
 
     def hash_pair_raw(self, x, sigma, a, beta, b, B_r, prec=SFFT_F64, stream=None):
         import torch
