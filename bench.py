@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--parity-signals", type=int, default=4)
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device-to-device tensor copy first (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -107,6 +109,15 @@ def main():
     n, k, S = 1 << args.log2n, args.k, args.signals
     w = args.w or sfft.sfft_default_w(n, args.B, 0.5, 1e-9)
     cfg_key = "n=2^%d,k=%d,B=%d,w=%d,signals=%d" % (args.log2n, k, args.B, w, S)
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1073741824 bytes read and written")
+        del src, dst
 
     # ---------------------------------------------------------------- inputs
     t = time.time()

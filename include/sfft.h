@@ -84,8 +84,9 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *             resolution, so the default is SFFT_F64 for n >= 2^20
  *   est_prec  arithmetic of the EstimateValues hashings (general mode)
  *   alpha     flat-window transition fraction (Section 2 definition)
- *   delta     window accuracy; sets the Gaussian width sigma_g =
- *             (4B/alpha) sqrt(2 ln(n/delta)) (Section 7 construction)
+ *   delta     window accuracy ||Ghat - G'||_inf < delta; sets the Gaussian
+ *             width sigma_g = (4B/alpha) sqrt(2 ln(3/delta)) (Section 7
+ *             construction without its delta -> delta/n normalisation step)
  *   theta     bin threshold of the exact decode (the paper's 1/2 for
  *             integer spectra, Algorithm 1)
  *   g_min     smallest window value G'_{-o(i)} a bin value is divided by

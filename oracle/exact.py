@@ -24,7 +24,10 @@ supp(zhat) and each round r whose window value G'_{-o_r(i)} >= g_min,
     e_r = (u_raw_r[h_r(i)] - sum_{i' != i, h_r(i') = h_r(i)} G'_{-o_r(i')} zhat_{i'}) / G'_{-o_r(i)}
 (the EstimateValues estimate of Algorithm 2 with a = 0, applied to x minus the
 other recovered coefficients) and the value is the coordinate-wise median of
-the e_r.  The output keeps entries with |value| > theta/2, at most cap of them
+the e_r over the rounds where i is the only zhat entry of its bin (the
+no-collision case of the estimation lemmas), or over all such rounds when i
+never was alone.  Preferring isolated rounds keeps the error of one entry from
+leaking into another through shared bins of the small late rounds.  The output keeps entries with |value| > theta/2, at most cap of them
 (largest magnitude first, then smaller index), in ascending index order.
 
 The paper-literal variant (params.literal) keeps v = round(u_j) and writes
@@ -161,7 +164,7 @@ def reestimate(zhat, raw, p: SfftParams):
             members.setdefault(h, []).append(i)   # ascending index within a bin
         per_round.append((u0_raw, hg, members))
     for i in keys:
-        vals = []
+        vals, alone = [], []
         for u0_raw, hg, members in per_round:
             h, g = hg[i]
             if g < p.g_min:
@@ -171,7 +174,10 @@ def reestimate(zhat, raw, p: SfftParams):
                 if i2 != i:
                     others += hg[i2][1] * zhat[i2]
             vals.append((u0_raw[h] - others) / g)
-        out[i] = complex_median(vals) if vals else zhat[i]
+            if len(members[h]) == 1:
+                alone.append(vals[-1])
+        use = alone if alone else vals
+        out[i] = complex_median(use) if use else zhat[i]
     return out
 
 

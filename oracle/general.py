@@ -33,7 +33,9 @@ biases it whenever the offset is large).
 
 Final FP64 re-estimation: every zhat entry is re-estimated from all stored
 EstimateValues measurements, with the other zhat entries of the same bin
-subtracted; the output is the top-cap entries by magnitude, ascending index.
+subtracted, preferring (as in exact mode) the measurements where the entry is
+alone in its bin; the output is the top-cap entries by magnitude, ascending
+index.
 
 Parity unpinned: which noisy heads a run finds has no closed form; the oracle
 run itself and the statistical l2/l2 guarantee of Section 1 eq. (1) are what
@@ -195,7 +197,7 @@ def reestimate_general(zhat, est_raw, p: SfftParams):
         per.append((sigma, a, b, raw, info, members))
     out = {}
     for i in keys:
-        vals = []
+        vals, alone = [], []
         for sigma, a, b, raw, info, members in per:
             h, g = info[i]
             if g < p.g_min:
@@ -205,7 +207,10 @@ def reestimate_general(zhat, est_raw, p: SfftParams):
                 if i2 != i:
                     others += info[i2][1] * zhat[i2] * omega_pow(a * sigma * i2, n)
             vals.append((raw[h] - others) * omega_pow(-(a * sigma * i), n) / g)
-        out[i] = complex_median(vals) if vals else zhat[i]
+            if len(members[h]) == 1:
+                alone.append(vals[-1])
+        use = alone if alone else vals
+        out[i] = complex_median(use) if use else zhat[i]
     return out
 
 

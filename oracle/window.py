@@ -8,10 +8,16 @@ so that
     G*(t)     = exp(-2 pi^2 t^2 / sigma_g^2) * sin(2 pi C t) / (pi t),  G*(0) = 2C
     Ghat*(s)  = Phi(sigma_g (s + C)) - Phi(sigma_g (s - C))
 
-with sigma_g = (4B/alpha) sqrt(2 ln(n/delta)) and C = (1 - alpha/2)/(2B)
-(the parameter choice at the end of the Section 7 lemma).  Reading of the
-garbled passages: F(t) is 2C*sinc(2Ct), D(t) is the Gaussian above, and the
-G' argument is sigma_g*(f/n +- C).
+with C = (1 - alpha/2)/(2B) and sigma_g = (4B/alpha) sqrt(2 ln(3/delta)).
+Reading of the parameter choice at the end of the Section 7 lemma: the paper
+takes sigma_g = (4B/alpha) sqrt(2 log(n/delta)) after replacing delta by
+delta/n, a step that only absorbs the sqrt(n) its normalisation puts into G
+(its (8 sqrt(n) + 6) delta bound).  Here G carries no sqrt(n), so the lemma's
+own requirement - Phi below delta beyond sqrt(2 log(3/delta)) (the CDF claim,
+item 4) - is met with log(3/delta); the result still satisfies
+||Ghat - G'||_inf < delta (pinned by test) with a shorter window.  Reading of
+the garbled passages: F(t) is 2C*sinc(2Ct), D(t) is the Gaussian above, and
+the G' argument is sigma_g*(f/n +- C).
 
 Discrete window: G_t = G*(t) for integer t in [-w/2, w/2), zero elsewhere.
 The paper folds sqrt(n) into G; we instead apply sqrt(n) once to the bins
@@ -31,8 +37,9 @@ import numpy as np
 
 
 def window_shape(n, B, alpha, delta):
-    """(sigma_g, C) of the Section 7 lemma."""
-    sigma_g = (4.0 * B / alpha) * math.sqrt(2.0 * math.log(n / delta))
+    """(sigma_g, C) of the Section 7 lemma (n enters only through the caller's
+    delta; see the module docstring)."""
+    sigma_g = (4.0 * B / alpha) * math.sqrt(2.0 * math.log(3.0 / delta))
     C = (1.0 - alpha / 2.0) / (2.0 * B)
     return sigma_g, C
 

@@ -42,10 +42,16 @@ uint32_t log2u(uint64_t v) {
 }
 
 // ------------------------------------------------------------ window ------
-// Gaussian width and boxcar half-width of the Section 7 construction.
+// Gaussian width and boxcar half-width of the Section 7 construction:
+// C = (1 - alpha/2)/(2B) and sigma_g = (4B/alpha) sqrt(2 ln(3/delta)).  The
+// paper's ln(n/delta) comes from replacing delta by delta/n to absorb the
+// sqrt(n) its normalisation puts into G; G here carries no sqrt(n), and the
+// CDF-tail requirement of the lemma (beyond sqrt(2 ln(3/delta))) is met
+// directly, which keeps ||Ghat - G'||_inf < delta with a shorter window.
 WindowShape window_shape(uint64_t n, uint64_t B, double alpha, double delta) {
+    (void)n;
     WindowShape ws;
-    ws.sigma_g = (4.0 * (double)B / alpha) * std::sqrt(2.0 * std::log((double)n / delta));
+    ws.sigma_g = (4.0 * (double)B / alpha) * std::sqrt(2.0 * std::log(3.0 / delta));
     ws.C = (1.0 - alpha / 2.0) / (2.0 * (double)B);
     ws.alpha = alpha;
     return ws;

@@ -647,16 +647,22 @@ __global__ void __launch_bounds__(kThreads) k_exact_finish(DecodeArgs D) {
             uint32_t s0 = p;
             while (s0 > 0 && (S.key[s0 - 1] >> kKeyBinShift) == h) --s0;
             double orr = 0.0, oii = 0.0;
+            uint32_t members = 0;
             for (uint32_t q = s0; q < zc && (S.key[q] >> kKeyBinShift) == h; ++q) {
+                ++members;
                 const uint32_t e2 = (uint32_t)(S.key[q] & kEntryMask);
                 if (e2 == e) continue;
                 orr += gtmp[e2] * zv[2 * e2];
                 oii += gtmp[e2] * zv[2 * e2 + 1];
             }
+            // samples of rounds where e is alone in its bin fill the count from
+            // the front, the others from the back of the entry's slot range
             const uint32_t c = ecount[e];
-            est[((uint64_t)e * D.rounds + c) * 2] = (r0[2 * h] - orr) / ge;
-            est[((uint64_t)e * D.rounds + c) * 2 + 1] = (r0[2 * h + 1] - oii) / ge;
-            ecount[e] = c + 1;
+            const uint32_t na = c & 0xFFFFu, nb = c >> 16;
+            const uint32_t slot = members == 1 ? na : D.rounds - 1 - nb;
+            est[((uint64_t)e * D.rounds + slot) * 2] = (r0[2 * h] - orr) / ge;
+            est[((uint64_t)e * D.rounds + slot) * 2 + 1] = (r0[2 * h + 1] - oii) / ge;
+            ecount[e] = members == 1 ? c + 1 : c + (1u << 16);
         }
     }
     __syncthreads();
@@ -665,13 +671,16 @@ __global__ void __launch_bounds__(kThreads) k_exact_finish(DecodeArgs D) {
     const double half_theta = 0.5 * D.theta;
     double* fin = D.fin + (uint64_t)sig * D.capz * 2;
     for (uint32_t e = tid; e < zc; e += kThreads) {
-        const uint32_t c = ecount[e];
+        // median over the rounds where e was alone in its bin, else over all
+        const uint32_t na = ecount[e] & 0xFFFFu, nb = ecount[e] >> 16;
+        const uint32_t c = na ? na : nb;
+        const uint32_t first = na ? 0u : D.rounds - nb;
         double vr = zv[2 * e], vi = zv[2 * e + 1];
         if (c > 0) {
             double re[kMaxRounds], im[kMaxRounds];
             for (uint32_t q = 0; q < c; ++q) {
-                re[q] = est[((uint64_t)e * D.rounds + q) * 2];
-                im[q] = est[((uint64_t)e * D.rounds + q) * 2 + 1];
+                re[q] = est[((uint64_t)e * D.rounds + first + q) * 2];
+                im[q] = est[((uint64_t)e * D.rounds + first + q) * 2 + 1];
             }
             for (uint32_t q = 1; q < c; ++q) {
                 const double a = re[q], bq = im[q];
