@@ -90,8 +90,8 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *   theta     bin threshold of the exact decode (the paper's 1/2 for
  *             integer spectra, Algorithm 1)
  *   g_min     smallest window value G'_{-o(i)} a bin value is divided by
- *   rounds    exact: most NoiselessSparseFFTInner rounds; general: SparseFFT
- *             rounds
+ *   rounds    exact: most NoiselessSparseFFTInner rounds (0 = 16); general:
+ *             SparseFFT rounds (0 = 5)
  *   b_min     exact: round r uses B_r = max(B >> r, b_min) bins and a window
  *             of w B_r / B samples (Algorithm 1 shrinks B with k_t = k/2^t);
  *             0 = B/16 (at least 2); b_min = B keeps B fixed
@@ -234,6 +234,18 @@ sfft_status_t sfft_plan_timings(sfft_plan_t p, double* ms_host, uint32_t n_out);
  * (2 B_r complex128 per round).  Pure host function.
  */
 uint64_t sfft_plan_h2b_bytes(sfft_plan_t p, uint32_t count);
+
+/*
+ * Copy the raw bins of one hashing slot of one signal from the batched
+ * workspace (after sfft_execute_batch has completed on `stream`), for parity
+ * tests of the batched HashToBins jobs.  Slots: exact mode, slot = round;
+ * general mode, slot = first slot of round r + (level - 1) * R_loc + rep for
+ * LocateInner pairs, then the R_est EstimateValues hashings.  out_dev is
+ * [2][B_r][2] doubles (the two hashings of the slot); *B_r_out receives B_r.
+ * Errors: SFFT_EINVAL for a signal beyond max_batch or a slot out of range.
+ */
+sfft_status_t sfft_plan_raw_slot(sfft_plan_t p, uint32_t sig, uint32_t slot, double* out_dev, uint32_t* B_r_out,
+                                 void* stream);
 
 /* Human-readable name of a status code (static storage). */
 const char* sfft_status_string(sfft_status_t s);

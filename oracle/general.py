@@ -107,6 +107,8 @@ def phase_of_ratio(u, u2):
 
 def locate_signal(x, zhat, r, B, G, p: SfftParams, res: GeneralResult):
     n = p.n
+    # beta * (angle numerator) must stay below 2^63 in int64
+    assert n <= (1 << 26), "oracle general mode supports n <= 2^26"
     scale = 1 << FRAC_BITS
     mod = n * scale
     sigma = draw_sigma(p.seed, n, r, 0, 0)

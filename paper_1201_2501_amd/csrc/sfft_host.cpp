@@ -120,6 +120,16 @@ struct sfft_plan_s {
     uint32_t mcap = 0;         // largest modulation table of the pair kernel
     std::vector<RoundDev> geom;
     RoundDev* d_geom = nullptr;
+    // general mode
+    std::vector<GenRoundDev> groundv;
+    std::vector<GenJob> jobs_loc, jobs_est;
+    std::vector<uint32_t> loc_first, loc_count, est_first, est_count;
+    GenRoundDev* d_groundv = nullptr;
+    GenJob* d_jobs_loc = nullptr;
+    GenJob* d_jobs_est = nullptr;
+    uint32_t nslots = 0;
+    double* cand_e = nullptr;
+    uint32_t* cand_n = nullptr;
     double* d_g64 = nullptr;
     float* d_g32 = nullptr;
     double* d_tw64 = nullptr;  // Bmax complex
@@ -176,7 +186,47 @@ sfft_status_t resolve_and_validate(sfft_plan_desc_t& d) {
     if (s != SFFT_OK) return s;
     if (d.w == 0) d.w = default_w(d.n, d.B, d.alpha, d.delta);
     if (d.cap == 0) d.cap = d.k;
+    if (d.rounds == 0) d.rounds = d.mode == SFFT_MODE_GENERAL ? 5 : 16;
     return SFFT_OK;
+}
+
+uint32_t pow2_ceil(uint64_t v) {
+    uint32_t f = 1;
+    while (f < v) f <<= 1;
+    return f;
+}
+
+bool general_mode(const sfft_plan_s* p) { return p->d.mode == SFFT_MODE_GENERAL; }
+
+// Round r of SparseFFT (Algorithm 2), practical schedule: k_r = k >> 2r,
+// B_r = max(B >> r, 4 k_r rounded up to a power of two), capped at B.
+void general_round_shape(const sfft_plan_desc_t& d, uint32_t r, uint32_t* k_r, uint32_t* B_r) {
+    const uint32_t kr = std::max<uint32_t>(1u, r >= 16 ? 0u : (d.k >> (2 * r)));
+    const uint32_t floor_b = pow2_ceil(4ull * kr);
+    const uint32_t shifted = r >= 31 ? 0u : (d.B >> r);
+    *k_r = kr;
+    *B_r = std::min<uint32_t>(d.B, std::max(shifted, floor_b));
+}
+
+// LocateInner levels of a round with B_r bins: widths W (fixed point) while
+// W > 1, shrinking by t/4; beta in [ceil(s n t / (4W)), floor(s n t / (2W))].
+void general_levels(const sfft_plan_desc_t& d, uint32_t B_r, GenRoundDev& gr) {
+    const uint64_t scale = 1ull << kFracBits;
+    uint64_t W = (d.n / B_r) * scale;
+    gr.nlev = 0;
+    while (W > scale && gr.nlev < kMaxLevels) {
+        const double Wr = (double)W / (double)scale;
+        const double snt = d.s * (double)d.n * (double)d.t;
+        uint64_t lo = (uint64_t)std::ceil(snt / (4.0 * Wr));
+        uint64_t hi = (uint64_t)std::floor(snt / (2.0 * Wr));
+        lo = std::max<uint64_t>(lo, 1);
+        hi = std::max(hi, lo);
+        gr.Wfp[gr.nlev] = W;
+        gr.blo[gr.nlev] = lo;
+        gr.bhi[gr.nlev] = hi;
+        ++gr.nlev;
+        W = W * 4 / d.t;
+    }
 }
 
 sfft_status_t build_plan(sfft_plan_s* p) {
@@ -194,7 +244,24 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     p->mcap = 4;
     for (uint32_t r = 0; r < p->R; ++r) {
         RoundDev g;
-        g.B = exact_round_bins(d, r);
+        if (general_mode(p)) {
+            GenRoundDev gr;
+            std::memset(&gr, 0, sizeof(gr));
+            general_round_shape(d, r, &gr.k_r, &g.B);
+            general_levels(d, g.B, gr);
+            gr.nloc = gr.nlev * d.R_loc;
+            gr.slot0 = p->nslots;
+            p->loc_first.push_back((uint32_t)p->jobs_loc.size());
+            p->est_first.push_back((uint32_t)p->jobs_est.size());
+            for (uint32_t q = 0; q < gr.nloc; ++q) p->jobs_loc.push_back(GenJob{r, q, gr.slot0 + q, 0});
+            for (uint32_t e = 0; e < d.R_est; ++e) p->jobs_est.push_back(GenJob{r, gr.nloc + e, gr.slot0 + gr.nloc + e, 0});
+            p->loc_count.push_back(gr.nloc);
+            p->est_count.push_back(d.R_est);
+            p->nslots += gr.nloc + d.R_est;
+            p->groundv.push_back(gr);
+        } else {
+            g.B = exact_round_bins(d, r);
+        }
         g.logB = log2u(g.B);
         g.w = d.w / d.B * g.B;
         g.t0 = -(int64_t)(g.w / 2);
@@ -208,11 +275,14 @@ sfft_status_t build_plan(sfft_plan_s* p) {
         } else {
             g.gofs = seenOfs[it - seenB.begin()];
         }
-        // pair (a = 0, beta = 1) modulation table length
+        // modulation table length: the exact pair (a = 0, beta = 1); general
+        // pairs need at most 2 w_r / B_r + 4 (beta below w) or w_r / B_r + 2
+        // per segment (beta at least w)
         const int64_t iB = g.B;
         const int64_t Llo = floordiv(g.t0 - 1 - (iB - 1), iB);
         const int64_t Lhi = floordiv(g.t0 + (int64_t)g.w - 1, iB);
         p->mcap = std::max<uint32_t>(p->mcap, (uint32_t)(Lhi - Llo + 1));
+        if (general_mode(p)) p->mcap = std::max<uint32_t>(p->mcap, (uint32_t)(2 * (g.w / g.B) + 4));
         p->geom.push_back(g);
     }
     std::vector<float> g32(g64.begin(), g64.end());
@@ -237,23 +307,38 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     HIP_TRY(hipMemcpy(p->d_g32, g32.data(), g32.size() * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->d_tw64, tw64.data(), tw64.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(p->d_tw32, tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (general_mode(p)) {
+        ST_TRY(dev_alloc(p, &p->d_groundv, p->groundv.size()));
+        ST_TRY(dev_alloc(p, &p->d_jobs_loc, p->jobs_loc.size()));
+        ST_TRY(dev_alloc(p, &p->d_jobs_est, p->jobs_est.size()));
+        HIP_TRY(hipMemcpy(p->d_groundv, p->groundv.data(), p->groundv.size() * sizeof(GenRoundDev),
+                          hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_jobs_loc, p->jobs_loc.data(), p->jobs_loc.size() * sizeof(GenJob), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_jobs_est, p->jobs_est.data(), p->jobs_est.size() * sizeof(GenJob), hipMemcpyHostToDevice));
+    }
     // batched workspace
     const size_t S = d.max_batch;
     const size_t Bm = p->Bmax, R = p->R, Z = p->capz;
-    ST_TRY(dev_alloc(p, &p->raw, S * R * 4 * Bm));
+    const size_t raw_slots = general_mode(p) ? p->nslots : p->R;
+    const size_t meas = general_mode(p) ? (size_t)p->R * d.R_est : p->R;
+    ST_TRY(dev_alloc(p, &p->raw, S * raw_slots * 4 * Bm));
+    if (general_mode(p)) {
+        ST_TRY(dev_alloc(p, &p->cand_e, S * d.R_est * 2 * Bm));
+        ST_TRY(dev_alloc(p, &p->cand_n, S * Bm));
+    }
     ST_TRY(dev_alloc(p, &p->work, S * 4 * Bm));
     ST_TRY(dev_alloc(p, &p->cand_i, S * Bm));
     ST_TRY(dev_alloc(p, &p->cand_v, S * 2 * Bm));
     ST_TRY(dev_alloc(p, &p->zidx, S * 2 * Z));
     ST_TRY(dev_alloc(p, &p->zval, S * 4 * Z));
-    ST_TRY(dev_alloc(p, &p->est, S * Z * R * 2));
+    ST_TRY(dev_alloc(p, &p->est, S * Z * meas * 2));
     ST_TRY(dev_alloc(p, &p->fin, S * Z * 2));
     ST_TRY(dev_alloc(p, &p->gtmp, S * Z));
     ST_TRY(dev_alloc(p, &p->ecount, S * Z));
     ST_TRY(dev_alloc(p, &p->state, S * kStateWords));
     // plain path (one signal): raw bins of every round, split partials
     p->p_parts_max = 64;
-    ST_TRY(dev_alloc(p, &p->p_raw, R * 4 * Bm));
+    ST_TRY(dev_alloc(p, &p->p_raw, raw_slots * 4 * Bm));
     ST_TRY(dev_alloc(p, &p->p_partial, (size_t)p->p_parts_max * 4 * Bm));
     ST_TRY(dev_alloc(p, &p->p_idx, p->cap));
     ST_TRY(dev_alloc(p, &p->p_val, 2 * (size_t)p->cap));
@@ -322,11 +407,91 @@ DecodeArgs base_decode(const sfft_plan_s* p, uint32_t count, const uint64_t* see
     return D;
 }
 
+GeneralArgs base_general(const sfft_plan_s* p, uint32_t count, const uint64_t* seeds, const double* raw,
+                         uint64_t* oidx, double* oval, uint32_t* ocount, uint32_t* oinfo) {
+    GeneralArgs G;
+    std::memset(&G, 0, sizeof(G));
+    G.n = p->d.n;
+    G.count = count;
+    G.R = p->R;
+    G.nslots = p->nslots;
+    G.Bmax = p->Bmax;
+    G.capz = p->capz;
+    G.cap = p->cap;
+    G.t = p->d.t;
+    G.R_loc = p->d.R_loc;
+    G.R_est = p->d.R_est;
+    G.s = p->d.s;
+    G.g_min = p->d.g_min;
+    G.out_scale = (p->d.flags & SFFT_FLAG_NUMPY_NORM) ? std::sqrt((double)p->d.n) : 1.0;
+    G.geom = p->d_geom;
+    G.groundv = p->d_groundv;
+    G.seeds = seeds;
+    G.plan_seed = p->d.seed;
+    G.raw = raw;
+    G.cand_i = p->cand_i;
+    G.cand_v = p->cand_v;
+    G.cand_e = p->cand_e;
+    G.cand_n = p->cand_n;
+    G.zidx = p->zidx;
+    G.zval = p->zval;
+    G.est = p->est;
+    G.fin = p->fin;
+    G.gtmp = p->gtmp;
+    G.ecount = p->ecount;
+    G.state = p->state;
+    G.out_idx = oidx;
+    G.out_val = oval;
+    G.out_count = ocount;
+    G.out_info = oinfo;
+    return G;
+}
+
+// General-mode HashToBins for rounds [r0, r1): every LocateInner pair in
+// loc_prec arithmetic, every EstimateValues hashing in est_prec.
+sfft_status_t enqueue_general_hash(sfft_plan_s* p, const void* x, uint32_t count, const uint64_t* seeds, double* raw,
+                                   uint32_t r0, uint32_t r1, hipStream_t s) {
+    for (int kind = 0; kind < 2; ++kind) {
+        const std::vector<uint32_t>& first = kind == 0 ? p->loc_first : p->est_first;
+        const std::vector<uint32_t>& cnt = kind == 0 ? p->loc_count : p->est_count;
+        const uint32_t j0 = first[r0];
+        uint32_t nj = 0;
+        for (uint32_t r = r0; r < r1; ++r) nj += cnt[r];
+        if (nj == 0) continue;
+        const bool f64 = (kind == 0 ? p->d.loc_prec : p->d.est_prec) == SFFT_F64;
+        H2BArgs a = base_h2b(p, x);
+        a.gtab = f64 ? (const void*)p->d_g64 : (const void*)p->d_g32;
+        a.tw = f64 ? (const void*)p->d_tw64 : (const void*)p->d_tw32;
+        a.seeds = seeds;
+        a.count = count;
+        a.jobs = (kind == 0 ? p->d_jobs_loc : p->d_jobs_est) + j0;
+        a.njobs = nj;
+        a.groundv = p->d_groundv;
+        a.R_loc = p->d.R_loc;
+        a.raw = raw;
+        a.raw_rounds = p->nslots;
+        HIP_TRY(launch_h2b_pair(a, in_c128(p), f64, s));
+    }
+    return SFFT_OK;
+}
+
 // The batched sequence in three parts: 0 = init + HashToBins of every round
 // of every signal, 1 = decode loop, 2 = re-estimation and output.
 sfft_status_t enqueue_batch_part(sfft_plan_s* p, int part, const void* x, uint32_t count, const uint64_t* seeds,
                                  uint64_t* idx, double* val, uint32_t* cnt, uint32_t* info, hipStream_t s) {
     DecodeArgs D = base_decode(p, count, seeds, p->raw, idx, val, cnt, info);
+    if (general_mode(p)) {
+        GeneralArgs G = base_general(p, count, seeds, p->raw, idx, val, cnt, info);
+        if (part == 0) {
+            HIP_TRY(launch_exact_init(D, s));
+            ST_TRY(enqueue_general_hash(p, x, count, seeds, p->raw, 0, p->R, s));
+        } else if (part == 1) {
+            HIP_TRY(launch_general_decode(G, 0, p->R, s));
+        } else {
+            HIP_TRY(launch_general_finish(G, s));
+        }
+        return SFFT_OK;
+    }
     if (part == 0) {
         HIP_TRY(launch_exact_init(D, s));
         H2BArgs a = base_h2b(p, x);
@@ -390,7 +555,7 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->theta = 0.25;
     d->g_min = 0.4;
     d->s = 0.125;
-    d->rounds = 16;
+    d->rounds = 0;
     d->b_min = 0;
     d->patience = 3;
     d->t = 16;
@@ -419,16 +584,20 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (!(d->delta > 0.0 && d->delta < 1.0)) return fail(SFFT_EINVAL, "delta must be in (0, 1)");
     if (!(d->theta > 0.0)) return fail(SFFT_EINVAL, "theta must be positive");
     if (!(d->g_min > 0.0 && d->g_min <= 1.0)) return fail(SFFT_EINVAL, "g_min must be in (0, 1]");
-    if (d->rounds < 1 || d->rounds > kMaxRounds) return fail(SFFT_EINVAL, "rounds must be in [1, 32]");
+    if (d->rounds > kMaxRounds) return fail(SFFT_EINVAL, "rounds must be in [1, 32] (0 = mode default)");
     if (d->patience < 1) return fail(SFFT_EINVAL, "patience must be >= 1");
     if (d->b_min != 0 && (!is_pow2(d->b_min) || d->b_min < 2)) return fail(SFFT_EINVAL, "b_min must be 0 or a power of two >= 2");
     if (d->max_batch < 1 || d->max_batch > (1u << 20)) return fail(SFFT_EINVAL, "max_batch must be in [1, 2^20]");
     const uint32_t cap = d->cap ? d->cap : d->k;
     if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");
     if (d->mode == SFFT_MODE_GENERAL) {
-        if (d->t < 4 || !is_pow2(d->t) || d->R_loc < 1 || d->R_est < 1 || !(d->s > 0 && d->s < 1))
-            return fail(SFFT_EINVAL, "bad LocateInner/EstimateValues parameters");
-        return fail(SFFT_EUNSUPPORTED, "general mode is not available in this build");
+        if (d->t < 4 || d->t > kMaxT || !is_pow2(d->t) || d->R_loc < 1 || d->R_loc > 255 || d->R_est < 1 ||
+            !(d->s > 0 && d->s < 1))
+            return fail(SFFT_EINVAL, "bad LocateInner/EstimateValues parameters (t a power of two in [4, 64])");
+        const uint32_t R = d->rounds ? d->rounds : 5;
+        if ((uint64_t)R * d->R_est > 64) return fail(SFFT_EINVAL, "rounds * R_est must be at most 64");
+        if (4ull * std::max<uint32_t>(d->k, 16u) > kMaxZ) return fail(SFFT_EUNSUPPORTED, "general mode needs k <= 1024");
+        if ((d->n / d->B) > (1ull << 40)) return fail(SFFT_EINVAL, "n / B too large");
     }
     if (d->B > kMaxZ) return fail(SFFT_EUNSUPPORTED, "B exceeds 4096, the LDS limit of the pair and decode kernels");
     return SFFT_OK;
@@ -484,6 +653,27 @@ sfft_status_t sfft_plan_timings(sfft_plan_t p, double* ms_host, uint32_t n_out) 
     HIP_TRY(hipEventElapsedTime(&ms[2], p->ev[2], p->ev[3]));
     HIP_TRY(hipEventElapsedTime(&ms[3], p->ev[0], p->ev[3]));
     for (int q = 0; q < 4; ++q) ms_host[q] = ms[q];
+    return SFFT_OK;
+}
+
+sfft_status_t sfft_plan_raw_slot(sfft_plan_t p, uint32_t sig, uint32_t slot, double* out_dev, uint32_t* B_r_out,
+                                 void* stream) {
+    if (!p || !out_dev || !B_r_out) return fail(SFFT_EINVAL, "NULL argument");
+    const uint32_t nslots = general_mode(p) ? p->nslots : p->R;
+    if (sig >= p->d.max_batch || slot >= nslots) return fail(SFFT_EINVAL, "signal or slot out of range");
+    uint32_t round = slot;
+    if (general_mode(p)) {
+        round = 0;
+        for (uint32_t r = 0; r < p->R; ++r)
+            if (p->groundv[r].slot0 <= slot) round = r;
+    }
+    const uint32_t B = p->geom[round].B;
+    const double* src = p->raw + ((uint64_t)sig * nslots + slot) * 4 * (uint64_t)p->Bmax;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(out_dev, src, 2 * sizeof(double) * B, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(out_dev + 2 * (size_t)B, src + 2 * (size_t)p->Bmax, 2 * sizeof(double) * B,
+                           hipMemcpyDeviceToDevice, s));
+    *B_r_out = B;
     return SFFT_OK;
 }
 
@@ -554,7 +744,16 @@ sfft_status_t sfft_execute(sfft_plan_t p, const void* x_dev, uint64_t* idx_host,
     DecodeArgs D = base_decode(p, 1, nullptr, p->p_raw, p->p_idx, p->p_val, p->p_count, p->p_info);
     HIP_TRY(launch_exact_init(D, s));
     uint32_t st[kStateWords];
-    for (uint32_t r = 0; r < p->R; ++r) {
+    if (general_mode(p)) {
+        // one request: each round's hashings in one launch pair, then its decode
+        GeneralArgs G = base_general(p, 1, nullptr, p->p_raw, p->p_idx, p->p_val, p->p_count, p->p_info);
+        for (uint32_t r = 0; r < p->R; ++r) {
+            ST_TRY(enqueue_general_hash(p, x_dev, 1, nullptr, p->p_raw, r, r + 1, s));
+            HIP_TRY(launch_general_decode(G, r, r + 1, s));
+        }
+        HIP_TRY(launch_general_finish(G, s));
+    }
+    for (uint32_t r = 0; r < p->R && !general_mode(p); ++r) {
         const RoundDev& g = p->geom[r];
         H2BArgs a = base_h2b(p, x_dev);
         a.sigma = draw_sigma(p->d.seed, n, r);
@@ -580,7 +779,7 @@ sfft_status_t sfft_execute(sfft_plan_t p, const void* x_dev, uint64_t* idx_host,
         HIP_TRY(hipStreamSynchronize(s));
         if (st[ST_DONE]) break;
     }
-    HIP_TRY(launch_exact_finish(D, s));
+    if (!general_mode(p)) HIP_TRY(launch_exact_finish(D, s));
     uint32_t cnt = 0, info[4];
     HIP_TRY(hipMemcpyAsync(&cnt, p->p_count, sizeof(cnt), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(info, p->p_info, sizeof(info), hipMemcpyDeviceToHost, s));

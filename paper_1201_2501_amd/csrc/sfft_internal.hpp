@@ -39,6 +39,30 @@ struct RoundDev {
     WindowShape ws;
 };
 
+// ------------------------------------------------------------------ general
+constexpr uint32_t kMaxLevels = 24;
+constexpr uint32_t kFracBits = 8;          // fixed-point bits of region coordinates
+constexpr uint32_t kMaxT = 64;             // LocateInner regions per level
+
+// One SparseFFT round (Algorithm 2) of the general mode.
+struct GenRoundDev {
+    uint32_t k_r;
+    uint32_t nlev;               // LocateInner levels
+    uint32_t slot0;              // first raw-bin slot of this round
+    uint32_t nloc;               // nlev * R_loc location pairs, then R_est estimation slots
+    uint64_t Wfp[kMaxLevels];    // region width of each level (fixed point)
+    uint64_t blo[kMaxLevels];    // beta range of each level
+    uint64_t bhi[kMaxLevels];
+};
+
+// One hashing job of the general mode: round, index within the round, slot.
+struct GenJob {
+    uint32_t round;
+    uint32_t index;              // < nloc: location pair (level, rep); else estimation
+    uint32_t slot;
+    uint32_t pad;
+};
+
 // Arguments of the HashToBins pair kernels.
 struct H2BArgs {
     const void* x;
@@ -64,6 +88,11 @@ struct H2BArgs {
     uint32_t parts;
     uint32_t lchunk;
     uint32_t mcap;             // entries of the LDS modulation table
+    // general mode: block b = job * count + sig; jobs[job] names round/index/slot
+    const GenJob* jobs;
+    const GenRoundDev* groundv;
+    uint32_t R_loc;
+    uint32_t njobs;
 };
 
 struct DecodeArgs {
@@ -97,6 +126,42 @@ struct DecodeArgs {
     uint32_t* out_info;        // [sig][4] or nullptr
 };
 
+struct GeneralArgs {
+    uint64_t n;
+    uint32_t count;
+    uint32_t R;                  // rounds
+    uint32_t nslots;             // raw-bin slots per signal
+    uint32_t Bmax;
+    uint32_t capz;
+    uint32_t cap;
+    uint32_t t;
+    uint32_t R_loc;
+    uint32_t R_est;
+    double s;
+    double g_min;
+    double out_scale;
+    const RoundDev* geom;        // per round
+    const GenRoundDev* groundv;  // per round
+    const uint64_t* seeds;
+    uint64_t plan_seed;
+    const double* raw;           // [sig][nslots][2][Bmax]
+    uint64_t* cand_i;            // [sig][Bmax] located candidates
+    double* cand_v;              // [sig][Bmax][2] estimates
+    double* cand_e;              // [sig][R_est][Bmax][2] per-measurement estimates
+    uint32_t* cand_n;            // [sig][Bmax] valid measurements per candidate
+    uint64_t* zidx;              // [sig][2][capz]
+    double* zval;                // [sig][2][capz][2]
+    double* est;                 // [sig][capz][R * R_est][2]
+    double* fin;                 // [sig][capz][2]
+    double* gtmp;                // [sig][capz]
+    uint32_t* ecount;            // [sig][capz]
+    uint32_t* state;             // [sig][kStateWords]
+    uint64_t* out_idx;
+    double* out_val;
+    uint32_t* out_count;
+    uint32_t* out_info;
+};
+
 // kernel launchers (sfft_kernels.hip); return hipError_t of the launch
 hipError_t launch_h2b_pair(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s);
 hipError_t launch_h2b_split(const H2BArgs& a, uint32_t round, bool in_c128, bool acc_f64, hipStream_t s);
@@ -104,6 +169,9 @@ hipError_t launch_h2b_reduce(const H2BArgs& a, uint32_t round, bool acc_f64, hip
 hipError_t launch_exact_init(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_exact_decode(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s);
+
+hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_t r_end, hipStream_t s);
+hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s);
 
 size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64);
 

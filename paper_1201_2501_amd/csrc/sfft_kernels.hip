@@ -220,30 +220,51 @@ __device__ void store_bins(const cx<TA>* VA, const cx<TA>* VB, uint32_t B, uint3
 template <class TIn, class TA>
 __global__ void __launch_bounds__(kThreads) k_h2b_pair(H2BArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t sig, r;
-    if (A.explicit_job) {
-        sig = 0;
-        r = A.round_lo;
-    } else {
-        const uint32_t rr = blockIdx.x / A.count;
-        sig = blockIdx.x - rr * A.count;
-        r = A.round_lo + rr;
-    }
-    const RoundDev g = A.geom[r];
+    uint32_t sig, r, ro;
     const uint64_t n = A.n;
     uint64_t sigma, a, beta, b;
     if (A.explicit_job) {
+        sig = 0;
+        r = A.round_lo;
+        ro = 0;
         sigma = A.sigma;
         a = A.a;
         beta = A.beta;
         b = A.b;
+    } else if (A.jobs) {
+        // general mode: LocateInner pair (level, rep) or EstimateValues hashing
+        const uint32_t job = blockIdx.x / A.count;
+        sig = blockIdx.x - job * A.count;
+        const GenJob jb = A.jobs[job];
+        r = jb.round;
+        ro = jb.slot;
+        const uint64_t seed = A.seeds ? A.seeds[sig] : A.plan_seed;
+        const GenRoundDev& gr = A.groundv[r];
+        if (jb.index < gr.nloc) {
+            const uint32_t D = jb.index / A.R_loc + 1, q = jb.index % A.R_loc;
+            sigma = draw_sigma(seed, n, r, 0, 0);
+            b = draw_b(seed, n, r, 0, 0);
+            a = draw_a(seed, n, r, D, q);
+            beta = draw_beta(seed, gr.blo[D - 1], gr.bhi[D - 1], r, D, q);
+        } else {
+            const uint32_t e = jb.index - gr.nloc;
+            sigma = draw_sigma(seed, n, r, LEVEL_EST, e);
+            a = draw_a(seed, n, r, LEVEL_EST, e);
+            b = draw_b(seed, n, r, LEVEL_EST, e);
+            beta = 0;
+        }
     } else {
+        const uint32_t rr = blockIdx.x / A.count;
+        sig = blockIdx.x - rr * A.count;
+        r = A.round_lo + rr;
+        ro = r;
         const uint64_t seed = A.seeds ? A.seeds[sig] : A.plan_seed;
         sigma = draw_sigma(seed, n, r);
         b = draw_b(seed, n, r);
         a = 0;
         beta = 1;
     }
+    const RoundDev g = A.geom[r];
     const TIn* x = reinterpret_cast<const TIn*>(A.x) + (uint64_t)sig * A.sig_stride;
     const TA* G = reinterpret_cast<const TA*>(A.gtab) + g.gofs;
     const auto* tw = reinterpret_cast<const typename TwTraits<TA>::V*>(A.tw);
@@ -262,7 +283,6 @@ __global__ void __launch_bounds__(kThreads) k_h2b_pair(H2BArgs A) {
     finalize_folds<TA>(VA, VB, n, sigma, b, beta, B, parts);
     __syncthreads();
     lds_fft2<TA>(VA, VB, B, A.Bmax, tw);
-    const uint32_t ro = r - (A.explicit_job ? A.round_lo : 0u);
     double* out0 = A.raw + (((uint64_t)sig * A.raw_rounds + ro) * 2) * (uint64_t)A.Bmax * 2;
     store_bins<TA>(VA, VB, B, g.logB, A.Bmax, beta, tw, A.sqrt_n, out0, out0 + 2 * (uint64_t)A.Bmax);
 }
@@ -424,6 +444,74 @@ __device__ void sort_entries_by_bin(DecodeShared& S, const uint64_t* zi, uint32_
     bitonic_sort_u64(S.key, N);
 }
 
+// zhat += candidates.  S.key[0, NB) holds candidate keys i << 13 | slot
+// (kNone for empty slots), sorted ascending; cv[slot] is the value.  Existing
+// indices are updated in place, new ones are merged (by index) into the other
+// zhat buffer, which becomes current.  Returns the number of new entries.
+__device__ uint32_t merge_candidates(DecodeShared& S, uint32_t NB, const double* cv, uint64_t* zidx_all,
+                                     double* zval_all, uint32_t sig, uint32_t capz, uint32_t* st) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t zc = st[ST_ZCOUNT];
+    const uint32_t zb = st[ST_ZBUF];
+    uint64_t* zi = zidx_all + ((uint64_t)sig * 2 + zb) * capz;
+    double* zv = zval_all + ((uint64_t)sig * 2 + zb) * capz * 2;
+    const uint64_t slot_mask = (1ull << kCandShift) - 1;
+    for (uint32_t q = tid; q < NB; q += kThreads) {
+        const uint64_t k = S.key[q];
+        if (k == kNone) continue;
+        const uint64_t i = k >> kCandShift;
+        const uint32_t j = (uint32_t)(k & slot_mask);
+        const uint32_t e = lower_bound_g(zi, zc, i);
+        if (e < zc && zi[e] == i) {
+            zv[2 * e] += cv[2 * j];
+            zv[2 * e + 1] += cv[2 * j + 1];
+            S.key[q] = kNone;
+        }
+    }
+    __syncthreads();
+    bitonic_sort_u64(S.key, NB);   // new entries first, ascending index
+    uint32_t mycnt = 0;
+    for (uint32_t q = tid; q < NB; q += kThreads) mycnt += S.key[q] != kNone;
+    if (tid == 0) S.flag = 0;
+    __syncthreads();
+    if (mycnt) atomicAdd(&S.flag, mycnt);
+    __syncthreads();
+    uint32_t mnew = S.flag;
+    if (zc + mnew > capz) {
+        mnew = capz - zc;
+        if (tid == 0) st[ST_FLAGS] |= 2u;
+    }
+    uint64_t* zo = zidx_all + ((uint64_t)sig * 2 + (zb ^ 1)) * capz;
+    double* zov = zval_all + ((uint64_t)sig * 2 + (zb ^ 1)) * capz * 2;
+    for (uint32_t e = tid; e < zc; e += kThreads) {
+        const uint64_t i = zi[e];
+        uint32_t lo = 0, hi = mnew;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((S.key[mid] >> kCandShift) < i) lo = mid + 1; else hi = mid;
+        }
+        const uint32_t pos = e + lo;
+        zo[pos] = i;
+        zov[2 * pos] = zv[2 * e];
+        zov[2 * pos + 1] = zv[2 * e + 1];
+    }
+    for (uint32_t q = tid; q < mnew; q += kThreads) {
+        const uint64_t i = S.key[q] >> kCandShift;
+        const uint32_t j = (uint32_t)(S.key[q] & slot_mask);
+        const uint32_t pos = q + lower_bound_g(zi, zc, i);
+        zo[pos] = i;
+        zov[2 * pos] = cv[2 * j];
+        zov[2 * pos + 1] = cv[2 * j + 1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        st[ST_ZCOUNT] = zc + mnew;
+        st[ST_ZBUF] = zb ^ 1;
+    }
+    __syncthreads();
+    return mnew;
+}
+
 // One round of NoiselessSparseFFTInner on signal `sig` (Algorithm 1).
 __device__ void exact_round(const DecodeArgs& D, DecodeShared& S, uint32_t sig, uint32_t r, uint64_t seed) {
     const uint32_t tid = threadIdx.x;
@@ -528,60 +616,8 @@ __device__ void exact_round(const DecodeArgs& D, DecodeShared& S, uint32_t sig, 
         S.key[j] = ci == kNone ? kNone : ((ci << kCandShift) | j);
     }
     bitonic_sort_u64(S.key, NB);
-    // existing entries: add in place; consumed candidates become kNone
-    for (uint32_t q = tid; q < NB; q += kThreads) {
-        const uint64_t k = S.key[q];
-        if (k == kNone) continue;
-        const uint64_t i = k >> kCandShift;
-        const uint32_t j = (uint32_t)(k & ((1u << kCandShift) - 1));
-        const uint32_t e = lower_bound_g(zi, zc, i);
-        if (e < zc && zi[e] == i) {
-            zv[2 * e] += cv_arr[2 * j];
-            zv[2 * e + 1] += cv_arr[2 * j + 1];
-            S.key[q] = kNone;
-        }
-    }
-    __syncthreads();
-    bitonic_sort_u64(S.key, NB);   // new entries first, ascending index
-    uint32_t mycnt = 0;
-    for (uint32_t q = tid; q < NB; q += kThreads) mycnt += S.key[q] != kNone;
-    if (tid == 0) S.flag = 0;
-    __syncthreads();
-    if (mycnt) atomicAdd(&S.flag, mycnt);
-    __syncthreads();
-    uint32_t mnew = S.flag;
-    if (zc + mnew > D.capz) {
-        mnew = D.capz - zc;
-        if (tid == 0) st[ST_FLAGS] |= 2u;
-    }
-    // merge old (zc) and new (mnew) into the other buffer
-    uint64_t* zo = D.zidx + ((uint64_t)sig * 2 + (zb ^ 1)) * D.capz;
-    double* zov = D.zval + ((uint64_t)sig * 2 + (zb ^ 1)) * D.capz * 2;
-    for (uint32_t e = tid; e < zc; e += kThreads) {
-        const uint64_t i = zi[e];
-        // number of new indices below i
-        uint32_t lo = 0, hi = mnew;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if ((S.key[mid] >> kCandShift) < i) lo = mid + 1; else hi = mid;
-        }
-        const uint32_t pos = e + lo;
-        zo[pos] = i;
-        zov[2 * pos] = zv[2 * e];
-        zov[2 * pos + 1] = zv[2 * e + 1];
-    }
-    for (uint32_t q = tid; q < mnew; q += kThreads) {
-        const uint64_t i = S.key[q] >> kCandShift;
-        const uint32_t j = (uint32_t)(S.key[q] & ((1u << kCandShift) - 1));
-        const uint32_t pos = q + lower_bound_g(zi, zc, i);
-        zo[pos] = i;
-        zov[2 * pos] = cv_arr[2 * j];
-        zov[2 * pos + 1] = cv_arr[2 * j + 1];
-    }
-    __syncthreads();
+    const uint32_t mnew = merge_candidates(S, NB, cv_arr, D.zidx, D.zval, sig, D.capz, st);
     if (tid == 0) {
-        st[ST_ZCOUNT] = zc + mnew;
-        st[ST_ZBUF] = zb ^ 1;
         st[ST_EMPTY] = 0;
         st[ST_ROUNDS] = r + 1;
         st[ST_LASTJ] = J;
@@ -781,6 +817,369 @@ __global__ void __launch_bounds__(kThreads) k_exact_finish(DecodeArgs D) {
     }
 }
 
+// ------------------------------------------------------------------ general
+// General (noisy) recovery, Algorithms 2 and 3.  One workgroup per signal
+// runs the SparseFFT rounds on raw bins computed up front: LocateSignal with
+// one thread per bin carrying that bin's region through every LocateInner
+// level, EstimateValues medians over the candidates, the top-3k_r selection
+// and the merge into zhat; the finish kernel re-estimates every zhat entry
+// over all EstimateValues measurements in FP64.
+
+constexpr uint32_t kMaxMeas = 64;   // measurements per entry in the final re-estimation
+
+struct GenShared {
+    DecodeShared d;
+    uint16_t binfirst[kMaxZ];       // first sorted position of each bin, 0xFFFF = none
+};
+
+__device__ __forceinline__ const double* gen_raw(const GeneralArgs& G, uint32_t sig, uint32_t slot, uint32_t a) {
+    return G.raw + (((uint64_t)sig * G.nslots + slot) * 2 + a) * (uint64_t)G.Bmax * 2;
+}
+
+// Sort the zhat entries by bin of (sigma, b, B) and index each bin's first entry.
+__device__ void index_bins(GenShared& S, const uint64_t* zi, uint32_t zc, uint64_t sigma, uint64_t b, uint64_t n,
+                           uint32_t B) {
+    sort_entries_by_bin(S.d, zi, zc, sigma, b, n, B);
+    for (uint32_t j = threadIdx.x; j < B; j += kThreads) S.binfirst[j] = 0xFFFF;
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < zc; p += kThreads) {
+        const uint32_t h = (uint32_t)(S.d.key[p] >> kKeyBinShift);
+        if (p == 0 || (uint32_t)(S.d.key[p - 1] >> kKeyBinShift) != h) S.binfirst[h] = (uint16_t)p;
+    }
+    __syncthreads();
+}
+
+// HashToBins step 4 for one bin: u_h - sum over the zhat entries of bin h,
+// in ascending index order, of G'_{-o(i)} zhat_i omega^{shift sigma i}.
+__device__ cx<double> corrected_bin(const GenShared& S, const double* rawv, uint32_t h, uint64_t shift,
+                                    const uint64_t* zi, const double* zv, uint32_t zc, uint64_t sigma, uint64_t b,
+                                    uint64_t n, uint32_t B, const WindowShape& ws) {
+    cx<double> u{rawv[2 * h], rawv[2 * h + 1]};
+    const uint32_t p0 = S.binfirst[h];
+    if (p0 == 0xFFFF) return u;
+    const uint64_t mask = n - 1;
+    const uint64_t as = (shift * sigma) & mask;
+    for (uint32_t q = p0; q < zc && (uint32_t)(S.d.key[q] >> kKeyBinShift) == h; ++q) {
+        const uint32_t e = (uint32_t)(S.d.key[q] & kEntryMask);
+        const uint64_t i = zi[e];
+        const BinOffset bo = bin_offset(i, sigma, b, n, B);
+        const double gp = gprime(-bo.o, n, B, ws);
+        const cx<double> c0{gp * zv[2 * e], gp * zv[2 * e + 1]};
+        u = csub(u, cmul(c0, omega_d((as * i) & mask, n)));
+    }
+    return u;
+}
+
+__device__ __forceinline__ double phase_of(cx<double> u, cx<double> u2) {
+    const double zr = u.r * u2.r + u.i * u2.i;
+    const double zi = u.i * u2.r - u.r * u2.i;
+    double ph = atan2(zi, zr);
+    if (ph < 0.0) ph += 6.283185307179586;
+    return ph;
+}
+
+// Median of c values (re and im separately; even counts average the middle two).
+__device__ cx<double> median_cx(double* re, double* im, uint32_t c) {
+    for (uint32_t q = 1; q < c; ++q) {
+        const double a = re[q], bq = im[q];
+        int32_t s = (int32_t)q - 1;
+        while (s >= 0 && re[s] > a) { re[s + 1] = re[s]; --s; }
+        re[s + 1] = a;
+        s = (int32_t)q - 1;
+        while (s >= 0 && im[s] > bq) { im[s + 1] = im[s]; --s; }
+        im[s + 1] = bq;
+    }
+    if (c & 1) return {re[c / 2], im[c / 2]};
+    return {0.5 * (re[c / 2 - 1] + re[c / 2]), 0.5 * (im[c / 2 - 1] + im[c / 2])};
+}
+
+// Magnitude-descending sort key with 13 bits of tie-break slot (ascending).
+__device__ __forceinline__ uint64_t mag_key(double vr, double vi, uint32_t slot) {
+    const double m = sqrt(vr * vr + vi * vi);
+    const uint64_t mb = (uint64_t)__double_as_longlong(m) >> 12;
+    return ((~mb & ((1ull << 51) - 1)) << 13) | slot;
+}
+
+// One SparseFFT round: LocateSignal, EstimateValues, zhat update.
+__device__ void general_round(const GeneralArgs& G, GenShared& S, uint32_t sig, uint32_t r, uint64_t seed) {
+    const uint32_t tid = threadIdx.x;
+    const RoundDev g = G.geom[r];
+    const GenRoundDev& gr = G.groundv[r];
+    const uint64_t n = G.n, mask = n - 1;
+    const uint32_t B = g.B;
+    uint32_t* st = G.state + (uint64_t)sig * kStateWords;
+    const uint32_t zc = st[ST_ZCOUNT];
+    const uint32_t zb = st[ST_ZBUF];
+    const uint64_t* zi = G.zidx + ((uint64_t)sig * 2 + zb) * G.capz;
+    const double* zv = G.zval + ((uint64_t)sig * 2 + zb) * G.capz * 2;
+    uint64_t* cand = G.cand_i + (uint64_t)sig * G.Bmax;
+    double* candv = G.cand_v + (uint64_t)sig * G.Bmax * 2;
+    uint32_t* candn = G.cand_n + (uint64_t)sig * G.Bmax;
+    const double two_pi = 6.283185307179586;
+
+    // ---- LocateSignal (Algorithm 3): one (sigma, b); regions per bin
+    {
+        const uint64_t scale = 1ull << kFracBits;
+        const uint64_t modfp = n << kFracBits;
+        const uint64_t mmask = modfp - 1;
+        const uint64_t sigma = draw_sigma(seed, n, r, 0, 0);
+        const uint64_t b = draw_b(seed, n, r, 0, 0);
+        const uint64_t sinv = inverse_odd(sigma) & mask;
+        const uint64_t sbs = ((sigma * b) & mask) << kFracBits;
+        const double tol = G.s * 3.141592653589793;
+        index_bins(S, zi, zc, sigma, b, n, B);
+        for (uint32_t j = tid; j < B; j += kThreads) {
+            uint64_t l = ((uint64_t)j * (n / B) * scale + modfp - (n / (2 * (uint64_t)B)) * scale) & mmask;
+            bool alive = true;
+            for (uint32_t D = 1; D <= gr.nlev && alive; ++D) {
+                const uint64_t W = gr.Wfp[D - 1];
+                const uint64_t half = W / (2 * G.t);
+                const uint64_t step = W / G.t;
+                uint8_t votes[kMaxT];
+                for (uint32_t qq = 0; qq < G.t; ++qq) votes[qq] = 0;
+                for (uint32_t q = 0; q < G.R_loc; ++q) {
+                    const uint64_t a = draw_a(seed, n, r, D, q);
+                    const uint64_t beta = draw_beta(seed, gr.blo[D - 1], gr.bhi[D - 1], r, D, q);
+                    const uint32_t slot = gr.slot0 + (D - 1) * G.R_loc + q;
+                    const cx<double> u = corrected_bin(S, gen_raw(G, sig, slot, 0), j, a, zi, zv, zc, sigma, b, n, B, g.ws);
+                    const cx<double> u2 = corrected_bin(S, gen_raw(G, sig, slot, 1), j, (a + beta) & mask, zi, zv, zc,
+                                                        sigma, b, n, B, g.ws);
+                    const double c = phase_of(u, u2);
+                    for (uint32_t qq = 0; qq < G.t; ++qq) {
+                        const uint64_t M = (l + (2 * (uint64_t)qq + 1) * half) & mmask;
+                        const uint64_t num = (beta * ((M + sbs) & mmask)) & mmask;
+                        const double ang = two_pi * (double)num / (double)modfp;
+                        const double d = fabs(ang - c);
+                        const double dist = d < two_pi - d ? d : two_pi - d;
+                        votes[qq] += dist < tol;
+                    }
+                }
+                uint32_t first = G.t;
+                for (uint32_t qq = 0; qq < G.t; ++qq)
+                    if (2u * votes[qq] > G.R_loc) {
+                        first = qq;
+                        break;
+                    }
+                if (first == G.t) alive = false;
+                else l = (l + first * step) & mmask;
+            }
+            uint64_t ci = kNone;
+            if (alive) {
+                const uint64_t pos = ((l + scale - 1) >> kFracBits) & mask;
+                ci = (sinv * pos + b) & mask;
+            }
+            cand[j] = ci;
+        }
+    }
+    __syncthreads();
+    // L: sorted, unique candidate indices
+    const uint32_t NB = pow2_at_least(B);
+    for (uint32_t j = tid; j < NB; j += kThreads) S.d.key[j] = j < B ? cand[j] : kNone;
+    bitonic_sort_u64(S.d.key, NB);
+    {
+        const uint32_t chunk = (NB + kThreads - 1) / kThreads;
+        const uint32_t p0 = tid * chunk, p1 = p0 + chunk < NB ? p0 + chunk : NB;
+        uint32_t cnt = 0;
+        for (uint32_t p = p0; p < p1; ++p)
+            cnt += S.d.key[p] != kNone && (p == 0 || S.d.key[p] != S.d.key[p - 1]);
+        uint32_t pre;
+        const uint32_t total = block_exclusive_scan(cnt, S.d.scan, &pre);
+        for (uint32_t p = p0; p < p1; ++p)
+            if (S.d.key[p] != kNone && (p == 0 || S.d.key[p] != S.d.key[p - 1])) cand[pre++] = S.d.key[p];
+        if (tid == 0) S.d.flag = total;
+        __syncthreads();
+    }
+    const uint32_t nL = S.d.flag;
+    __syncthreads();
+
+    // ---- EstimateValues (Algorithm 2): R_est fresh hashings, medians
+    for (uint32_t c = tid; c < nL; c += kThreads) candn[c] = 0;
+    for (uint32_t e = 0; e < G.R_est; ++e) {
+        const uint64_t sigma = draw_sigma(seed, n, r, LEVEL_EST, e);
+        const uint64_t a = draw_a(seed, n, r, LEVEL_EST, e);
+        const uint64_t b = draw_b(seed, n, r, LEVEL_EST, e);
+        const uint32_t slot = gr.slot0 + gr.nloc + e;
+        __syncthreads();
+        index_bins(S, zi, zc, sigma, b, n, B);
+        const double* rawv = gen_raw(G, sig, slot, 0);
+        for (uint32_t c = tid; c < nL; c += kThreads) {
+            const uint64_t i = cand[c];
+            const BinOffset bo = bin_offset(i, sigma, b, n, B);
+            const double gp = gprime(-bo.o, n, B, g.ws);
+            if (gp < G.g_min) continue;
+            const cx<double> u = corrected_bin(S, rawv, bo.h, a, zi, zv, zc, sigma, b, n, B, g.ws);
+            const uint64_t p = (((a * sigma) & mask) * i) & mask;
+            const cx<double> v = cmul(u, omega_d((n - p) & mask, n));
+            const uint32_t k = candn[c];
+            double* dst = G.cand_e + (((uint64_t)sig * G.R_est + k) * G.Bmax + c) * 2;
+            dst[0] = v.r / gp;
+            dst[1] = v.i / gp;
+            candn[c] = k + 1;
+        }
+    }
+    __syncthreads();
+    for (uint32_t c = tid; c < nL; c += kThreads) {
+        const uint32_t k = candn[c];
+        if (k == 0) continue;
+        double re[kMaxMeas], im[kMaxMeas];
+        for (uint32_t q = 0; q < k; ++q) {
+            const double* src = G.cand_e + (((uint64_t)sig * G.R_est + q) * G.Bmax + c) * 2;
+            re[q] = src[0];
+            im[q] = src[1];
+        }
+        const cx<double> m = median_cx(re, im, k);
+        candv[2 * c] = m.r;
+        candv[2 * c + 1] = m.i;
+    }
+    __syncthreads();
+    // top-k' by (|w| desc, index asc); candidates are in index order
+    const uint32_t kprime = 3 * gr.k_r;
+    const uint32_t NL = pow2_at_least(nL > 0 ? nL : 1);
+    for (uint32_t c = tid; c < NL; c += kThreads)
+        S.d.key[c] = (c < nL && candn[c] > 0) ? mag_key(candv[2 * c], candv[2 * c + 1], c) : kNone;
+    bitonic_sort_u64(S.d.key, NL);
+    for (uint32_t q = tid; q < NL; q += kThreads) {
+        const uint64_t k = S.d.key[q];
+        if (q >= kprime || k == kNone) {
+            S.d.key[q] = kNone;
+        } else {
+            const uint32_t c = (uint32_t)(k & 0x1FFFull);
+            S.d.key[q] = (cand[c] << kCandShift) | c;
+        }
+    }
+    bitonic_sort_u64(S.d.key, NL);
+    merge_candidates(S.d, NL, candv, G.zidx, G.zval, sig, G.capz, st);
+    if (tid == 0) {
+        st[ST_ROUNDS] = r + 1;
+        st[ST_LASTJ] = nL;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kThreads) k_general_decode(GeneralArgs G, uint32_t r_begin, uint32_t r_end) {
+    __shared__ GenShared S;
+    const uint32_t sig = blockIdx.x;
+    const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
+    for (uint32_t r = r_begin; r < r_end; ++r) {
+        __syncthreads();
+        general_round(G, S, sig, r, seed);
+    }
+}
+
+// Final FP64 re-estimation over every EstimateValues measurement of every
+// round (isolated measurements first), then the top-cap entries by magnitude
+// in ascending index order.
+__global__ void __launch_bounds__(kThreads) k_general_finish(GeneralArgs G) {
+    __shared__ GenShared S;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sig = blockIdx.x;
+    const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
+    uint32_t* st = G.state + (uint64_t)sig * kStateWords;
+    const uint64_t n = G.n, mask = n - 1;
+    const uint32_t zc = st[ST_ZCOUNT];
+    const uint32_t zb = st[ST_ZBUF];
+    const uint32_t R = st[ST_ROUNDS];
+    const uint64_t* zi = G.zidx + ((uint64_t)sig * 2 + zb) * G.capz;
+    const double* zv = G.zval + ((uint64_t)sig * 2 + zb) * G.capz * 2;
+    const uint32_t nmeas = G.R * G.R_est;
+    double* est = G.est + (uint64_t)sig * G.capz * nmeas * 2;
+    uint32_t* ecount = G.ecount + (uint64_t)sig * G.capz;
+    double* gtmp = G.gtmp + (uint64_t)sig * G.capz;
+    double* fin = G.fin + (uint64_t)sig * G.capz * 2;
+    for (uint32_t e = tid; e < zc; e += kThreads) ecount[e] = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        const RoundDev g = G.geom[r];
+        const GenRoundDev& gr = G.groundv[r];
+        const uint32_t B = g.B;
+        for (uint32_t m = 0; m < G.R_est; ++m) {
+            const uint64_t sigma = draw_sigma(seed, n, r, LEVEL_EST, m);
+            const uint64_t a = draw_a(seed, n, r, LEVEL_EST, m);
+            const uint64_t b = draw_b(seed, n, r, LEVEL_EST, m);
+            const double* rawv = gen_raw(G, sig, gr.slot0 + gr.nloc + m, 0);
+            const uint64_t as = (a * sigma) & mask;
+            __syncthreads();
+            for (uint32_t e = tid; e < zc; e += kThreads) {
+                const BinOffset bo = bin_offset(zi[e], sigma, b, n, B);
+                gtmp[e] = gprime(-bo.o, n, B, g.ws);
+            }
+            index_bins(S, zi, zc, sigma, b, n, B);
+            for (uint32_t p = tid; p < zc; p += kThreads) {
+                const uint32_t e = (uint32_t)(S.d.key[p] & kEntryMask);
+                const double ge = gtmp[e];
+                if (ge < G.g_min) continue;
+                const uint32_t h = (uint32_t)(S.d.key[p] >> kKeyBinShift);
+                const uint32_t s0 = S.binfirst[h];
+                cx<double> others{0.0, 0.0};
+                uint32_t members = 0;
+                for (uint32_t q = s0; q < zc && (uint32_t)(S.d.key[q] >> kKeyBinShift) == h; ++q) {
+                    ++members;
+                    const uint32_t e2 = (uint32_t)(S.d.key[q] & kEntryMask);
+                    if (e2 == e) continue;
+                    const cx<double> c0{gtmp[e2] * zv[2 * e2], gtmp[e2] * zv[2 * e2 + 1]};
+                    others = cadd(others, cmul(c0, omega_d((as * zi[e2]) & mask, n)));
+                }
+                const cx<double> u = csub(cx<double>{rawv[2 * h], rawv[2 * h + 1]}, others);
+                const uint64_t pe = (as * zi[e]) & mask;
+                const cx<double> v = cmul(u, omega_d((n - pe) & mask, n));
+                const uint32_t c = ecount[e];
+                const uint32_t na = c & 0xFFFFu, nb = c >> 16;
+                const uint32_t slot = members == 1 ? na : nmeas - 1 - nb;
+                est[((uint64_t)e * nmeas + slot) * 2] = v.r / ge;
+                est[((uint64_t)e * nmeas + slot) * 2 + 1] = v.i / ge;
+                ecount[e] = members == 1 ? c + 1 : c + (1u << 16);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < zc; e += kThreads) {
+        const uint32_t na = ecount[e] & 0xFFFFu, nb = ecount[e] >> 16;
+        const uint32_t c = na ? na : nb;
+        const uint32_t first = na ? 0u : nmeas - nb;
+        cx<double> v{zv[2 * e], zv[2 * e + 1]};
+        if (c > 0) {
+            double re[kMaxMeas], im[kMaxMeas];
+            for (uint32_t q = 0; q < c; ++q) {
+                re[q] = est[((uint64_t)e * nmeas + first + q) * 2];
+                im[q] = est[((uint64_t)e * nmeas + first + q) * 2 + 1];
+            }
+            v = median_cx(re, im, c);
+        }
+        fin[2 * e] = v.r;
+        fin[2 * e + 1] = v.i;
+    }
+    __syncthreads();
+    // top cap by (|v| desc, index asc), output in index order
+    const uint32_t N = pow2_at_least(zc > 0 ? zc : 1);
+    for (uint32_t e = tid; e < N; e += kThreads) S.d.key[e] = e < zc ? mag_key(fin[2 * e], fin[2 * e + 1], e) : kNone;
+    bitonic_sort_u64(S.d.key, N);
+    const uint32_t nout = zc < G.cap ? zc : G.cap;
+    for (uint32_t q = tid; q < N; q += kThreads) S.d.key[q] = q < nout ? (S.d.key[q] & 0x1FFFull) : kNone;
+    bitonic_sort_u64(S.d.key, N);
+    uint64_t* oidx = G.out_idx + (uint64_t)sig * G.cap;
+    double* oval = G.out_val + (uint64_t)sig * G.cap * 2;
+    for (uint32_t q = tid; q < G.cap; q += kThreads) {
+        if (q < nout) {
+            const uint32_t e = (uint32_t)S.d.key[q];
+            oidx[q] = zi[e];
+            oval[2 * q] = fin[2 * e] * G.out_scale;
+            oval[2 * q + 1] = fin[2 * e + 1] * G.out_scale;
+        } else {
+            oidx[q] = 0;
+            oval[2 * q] = 0.0;
+            oval[2 * q + 1] = 0.0;
+        }
+    }
+    if (tid == 0) {
+        G.out_count[sig] = nout;
+        if (G.out_info) {
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_ROUNDS] = R;
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_FLAGS] = st[ST_FLAGS];
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_ZHAT] = zc;
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_LOCATED] = st[ST_LASTJ];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launch --
 size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64) {
     const size_t csz = acc_f64 ? 16 : 8;
@@ -816,7 +1215,7 @@ static hipError_t launch_split_t(const H2BArgs& a, uint32_t round, size_t lds, h
 hipError_t launch_h2b_pair(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s) {
     // LDS: two fold arrays of max(Bmax, threads) plus the modulation table
     const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, acc_f64);
-    const uint32_t grid = a.explicit_job ? 1u : a.count * a.nrounds;
+    const uint32_t grid = a.explicit_job ? 1u : (a.jobs ? a.count * a.njobs : a.count * a.nrounds);
     if (in_c128) return acc_f64 ? launch_pair_t<double2, double>(a, lds, grid, s)
                                 : launch_pair_t<double2, float>(a, lds, grid, s);
     return acc_f64 ? launch_pair_t<float2, double>(a, lds, grid, s) : launch_pair_t<float2, float>(a, lds, grid, s);
@@ -850,6 +1249,16 @@ hipError_t launch_exact_decode(const DecodeArgs& a, hipStream_t s) {
 
 hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_exact_finish, dim3(a.count), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_t r_end, hipStream_t s) {
+    hipLaunchKernelGGL(k_general_decode, dim3(a.count), dim3(kThreads), 0, s, a, r_begin, r_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_general_finish, dim3(a.count), dim3(kThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ INFO_ROUNDS, INFO_FLAGS, INFO_ZHAT, INFO_LOCATED = range(4)
 # every symbol declared in include/sfft.h
 EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_plan_ex", "sfft_plan",
            "sfft_plan_get_desc", "sfft_destroy", "sfft_execute", "sfft_execute_batch",
-           "sfft_hash_pair_raw", "sfft_plan_timings", "sfft_plan_h2b_bytes", "sfft_status_string",
+           "sfft_hash_pair_raw", "sfft_plan_timings", "sfft_plan_h2b_bytes", "sfft_plan_raw_slot",
+           "sfft_status_string",
            "sfft_last_error", "sfft_splitmix64"]
 
 
@@ -65,6 +66,7 @@ def load():
     lib.sfft_plan_timings.argtypes = [P, P, c_uint32]
     lib.sfft_plan_h2b_bytes.argtypes = [P, c_uint32]
     lib.sfft_plan_h2b_bytes.restype = c_uint64
+    lib.sfft_plan_raw_slot.argtypes = [P, c_uint32, c_uint32, P, P, P]
     lib.sfft_status_string.argtypes = [c_int32]
     lib.sfft_status_string.restype = c_char_p
     lib.sfft_last_error.argtypes = []
@@ -139,6 +141,14 @@ def sfft_plan_timings(plan):
 
 def sfft_plan_h2b_bytes(plan, count):
     return int(load().sfft_plan_h2b_bytes(plan, count))
+
+
+def sfft_plan_raw_slot(plan, sig, slot, out, stream=None):
+    """Copy raw bins of (signal, slot) into out (device complex128 [2 * B_r]); returns B_r."""
+    br = np.zeros(1, dtype=np.uint32)
+    _check(load().sfft_plan_raw_slot(plan, sig, slot, c_void_p(out.data_ptr()), br.ctypes.data_as(c_void_p),
+                                     _stream_handle(stream)), "sfft_plan_raw_slot")
+    return int(br[0])
 
 
 def sfft_splitmix64(seed, c):
@@ -246,6 +256,15 @@ class Plan:
         b = bufs if bufs is not None else self.batch_buffers(count, x.device)
         sfft_execute_batch(self.handle, x, count, seeds, b["idx"], b["val"], b["counts"], b["info"], stream)
         return b
+
+    def raw_slot(self, sig, slot, device):
+        import torch
+
+        out = torch.zeros(2 * self.desc.B, dtype=torch.complex128, device=device)
+        br = sfft_plan_raw_slot(self.handle, sig, slot, out)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy()
+        return o[:br], o[br:2 * br]
 
     def timings(self):
         return sfft_plan_timings(self.handle)

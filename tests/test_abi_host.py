@@ -38,14 +38,14 @@ def test_desc_defaults():
     assert d.mode == sfft.SFFT_MODE_EXACT and d.in_dtype == sfft.SFFT_C64
     assert d.loc_prec == sfft.SFFT_F64          # n >= 2^20: FP64 location decoding
     assert sfft.sfft_desc_init(1 << 14, 16, 64).loc_prec == sfft.SFFT_F32
-    assert d.alpha == 0.5 and d.patience == 3 and d.rounds == 16
+    assert d.alpha == 0.5 and d.patience == 3 and d.rounds == 0     # 0 = mode default
     assert sfft.sfft_validate_params(d) == sfft.SFFT_OK
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("n", 3000, sfft.SFFT_ENOTPOW2), ("n", 2, sfft.SFFT_ENOTPOW2), ("k", 0, sfft.SFFT_EINVAL),
     ("B", 1000, sfft.SFFT_ENOTPOW2), ("B", 1 << 23, sfft.SFFT_EINVAL), ("w", 1000, sfft.SFFT_EINVAL),
-    ("alpha", 1.5, sfft.SFFT_EINVAL), ("delta", 0.0, sfft.SFFT_EINVAL), ("rounds", 0, sfft.SFFT_EINVAL),
+    ("alpha", 1.5, sfft.SFFT_EINVAL), ("delta", 0.0, sfft.SFFT_EINVAL), ("mode", 7, sfft.SFFT_EINVAL),
     ("rounds", 33, sfft.SFFT_EINVAL), ("b_min", 3, sfft.SFFT_EINVAL), ("max_batch", 0, sfft.SFFT_EINVAL),
     ("in_dtype", 5, sfft.SFFT_EINVAL), ("g_min", 0.0, sfft.SFFT_EINVAL),
 ])
@@ -54,6 +54,20 @@ def test_validation_errors(field, value, status):
     setattr(d, field, value)
     assert sfft.sfft_validate_params(d) == status
     assert sfft.sfft_last_error() != ""
+
+
+def test_general_mode_validation():
+    d = sfft.sfft_desc_init(1 << 20, 64, 1024, 0, 7)
+    d.mode = sfft.SFFT_MODE_GENERAL
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK
+    d.t = 12
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
+    d.t = 16
+    d.rounds, d.R_est = 10, 7
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL        # 70 measurements > 64
+    d.rounds = 5
+    d.k = 2000
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EUNSUPPORTED  # zhat capacity
 
 
 def test_lds_limit_is_reported_as_unsupported():

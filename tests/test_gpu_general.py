@@ -1,0 +1,149 @@
+"""GPU parity of the general-mode path (Algorithms 2 and 3) against the FP64
+oracle.
+
+FP64 location and estimation arithmetic: supports bit-exact, values within
+1e-10 relative.  FP32 arithmetic: values within 1e-4 relative; a support
+difference is accepted only when the oracle run has a near-tie decision
+(a vote within 1e-4 rad of s*pi, or a top-k' boundary gap below 1e-4 of the
+compared magnitudes), reported by the oracle's margins.
+"""
+import numpy as np
+import pytest
+
+import siggen
+from oracle.general import sparse_fft
+from oracle.metrics import l2l2_ratio
+from oracle.params import SfftParams
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    from paper_1201_2501_amd import sfft
+    sfft.load()
+    return torch, torch.device("cuda:0")
+
+
+def make_plan(n, k, B, seed, prec, max_batch=1, delta=1e-6):
+    from paper_1201_2501_amd.sfft import Plan, SFFT_MODE_GENERAL
+    return Plan(n, k, B, 0, seed, mode=SFFT_MODE_GENERAL, delta=delta, loc_prec=prec, est_prec=prec,
+                max_batch=max_batch)
+
+
+def oracle_params(plan, seed=None):
+    d = plan.desc
+    return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=d.seed if seed is None else seed, alpha=d.alpha,
+                      delta=d.delta, g_min=d.g_min, rounds=d.rounds, t=d.t, s=d.s, R_loc=d.R_loc,
+                      R_est=d.R_est, cap=d.cap)
+
+
+def check(idx, val, ref, rel, allow_near_tie=False):
+    if not np.array_equal(idx, ref.indices):
+        assert allow_near_tie and (ref.vote_margin < 1e-4 or ref.select_margin < 1e-4), \
+            (idx, ref.indices, ref.vote_margin, ref.select_margin)
+        return False
+    mag = np.maximum(np.abs(ref.values), 1e-300)
+    assert np.all(np.abs(val - ref.values) <= rel * mag + 1e-12), np.max(np.abs(val - ref.values) / mag)
+    return True
+
+
+CASES = [
+    # name, n, k, B, noise, prec
+    ("small-noiseless-f64", 1 << 16, 12, 256, 0.0, 1),
+    ("small-noisy-f64", 1 << 16, 12, 256, 0.05, 1),
+    ("small-noisy-f32", 1 << 16, 12, 256, 0.05, 0),
+    ("c2-f64", 1 << 20, 64, 1024, 0.05, 1),
+    ("c2-f32", 1 << 20, 64, 1024, 0.05, 0),
+]
+
+
+@pytest.mark.parametrize("name,n,k,B,noise,prec", CASES)
+def test_plain_general_matches_oracle(torch_dev, name, n, k, B, noise, prec):
+    torch, dev = torch_dev
+    seed = 3
+    say("plain-general", name, "n", n, "k", k, "B", B)
+    plan = make_plan(n, k, B, seed, prec)
+    x, sup, val = siggen.planted_signal(n, k, 500 + k, np.complex64, noise_ratio=noise)
+    idx, v, info, st = plan.execute(torch.from_numpy(x).to(dev))
+    ref = sparse_fft(x, oracle_params(plan))
+    same = check(idx, v, ref, 1e-10 if prec == 1 else 1e-4, allow_near_tie=(prec == 0))
+    ratio, err = l2l2_ratio(x, k, idx, v)
+    if noise > 0:
+        assert ratio <= 2.0
+    elif same:
+        assert np.array_equal(idx, sup)
+    plan.close()
+
+
+def test_batched_general_matches_oracle_per_seed(torch_dev):
+    torch, dev = torch_dev
+    n, k, B = 1 << 16, 12, 256
+    count = 4
+    say("batched-general", "n", n, "count", count)
+    plan = make_plan(n, k, B, 0, 1, max_batch=count)
+    xs, seeds = [], []
+    for s in range(count):
+        xs.append(siggen.planted_signal(n, k, 700 + s, np.complex64, noise_ratio=0.05)[0])
+        seeds.append(11 + 5 * s)
+    X = torch.from_numpy(np.stack(xs)).to(dev)
+    S = torch.tensor(seeds, dtype=torch.int64, device=dev)
+    bufs = plan.execute_batch(X, S)
+    torch.cuda.synchronize()
+    for s in range(count):
+        c = int(bufs["counts"][s])
+        ref = sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        check(bufs["idx"][s, :c].cpu().numpy(), bufs["val"][s, :c].cpu().numpy(), ref, 1e-10)
+    # plain path with the same seed gives the same answer as the batch
+    plain = make_plan(n, k, B, seeds[1], 1)
+    idx, v, info, st = plain.execute(X[1])
+    c = int(bufs["counts"][1])
+    assert np.array_equal(idx, bufs["idx"][1, :c].cpu().numpy())
+    assert np.allclose(v, bufs["val"][1, :c].cpu().numpy(), rtol=1e-11, atol=1e-14)
+    plan.close()
+    plain.close()
+
+
+def test_batched_general_raw_slots_match_oracle(torch_dev):
+    """Every batched HashToBins job of round 0 (LocateInner pairs and
+    EstimateValues hashings) against the oracle's bins for the same draws."""
+    from oracle.general import beta_range, level_widths
+    from oracle.hashing import hash_to_bins_raw
+    from oracle.rng import LEVEL_EST, draw_a, draw_b, draw_beta, draw_sigma
+    from oracle.window import window_time
+    torch, dev = torch_dev
+    n, k, B = 1 << 16, 12, 256
+    say("general-raw-slots", "n", n)
+    plan = make_plan(n, k, B, 9, 1, max_batch=1)
+    x = siggen.planted_signal(n, k, 800, np.complex64, noise_ratio=0.05)[0]
+    X = torch.from_numpy(x[None, :]).to(dev)
+    S = torch.tensor([9], dtype=torch.int64, device=dev)
+    plan.execute_batch(X, S)
+    torch.cuda.synchronize()
+    d = plan.desc
+    G = window_time(n, B, d.w, d.alpha, d.delta)
+    sigma, b = draw_sigma(9, n, 0, 0, 0), draw_b(9, n, 0, 0, 0)
+    slot = 0
+    for D, W in enumerate(level_widths(n, B, d.t), start=1):
+        lo, hi = beta_range(n, W, d.t, d.s)
+        for q in range(d.R_loc):
+            a, beta = draw_a(9, n, 0, D, q), draw_beta(9, lo, hi, 0, D, q)
+            g0, g1 = plan.raw_slot(0, slot, dev)
+            e0 = hash_to_bins_raw(x, sigma, a, b, B, G)
+            e1 = hash_to_bins_raw(x, sigma, (a + beta) % n, b, B, G)
+            sc = max(np.abs(e0).max(), np.abs(e1).max())
+            assert np.abs(g0 - e0).max() <= 1e-12 * sc, ("loc", D, q, 0)
+            assert np.abs(g1 - e1).max() <= 1e-12 * sc, ("loc", D, q, 1)
+            slot += 1
+    for e in range(d.R_est):
+        se, ae, be = draw_sigma(9, n, 0, LEVEL_EST, e), draw_a(9, n, 0, LEVEL_EST, e), draw_b(9, n, 0, LEVEL_EST, e)
+        g0, _ = plan.raw_slot(0, slot, dev)
+        e0 = hash_to_bins_raw(x, se, ae, be, B, G)
+        assert np.abs(g0 - e0).max() <= 1e-12 * np.abs(e0).max(), ("est", e)
+        slot += 1
+    plan.close()
