@@ -136,7 +136,7 @@ def main():
     for _ in range(args.warmup):
         plan.execute_batch(X, seeds, bufs=bufs)
     torch.cuda.synchronize()
-    h2b_ms, step_ms = [], []
+    h2b_ms, dec_ms, tail_ms, step_ms = [], [], [], []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record()
@@ -145,13 +145,17 @@ def main():
         torch.cuda.synchronize()
         tm = plan.timings()
         h2b_ms.append(tm[0])
+        dec_ms.append(tm[1])
+        tail_ms.append(tm[2])
         step_ms.append(tm[3])
+        chunks = int(tm[4])
     ev1.record()
     torch.cuda.synchronize()
     elapsed_ms = ev0.elapsed_time(ev1)
     ms_per_step = elapsed_ms / args.steps
     value = S * args.steps / (elapsed_ms / 1e3)
-    log("batched: %.3f ms/step, %.0f sFFTs/s (h2b %.3f ms)" % (ms_per_step, value, np.mean(h2b_ms)))
+    log("batched: %.3f ms/step, %.0f sFFTs/s (hash %.3f ms, decode %.3f ms overlapped, tail %.3f ms, %d chunks)"
+        % (ms_per_step, value, np.mean(h2b_ms), np.mean(dec_ms), np.mean(tail_ms), chunks))
 
     counts = bufs["counts"].cpu().numpy()
     info = bufs["info"].cpu().numpy()
@@ -159,16 +163,20 @@ def main():
     val_all = bufs["val"].cpu().numpy()
     exact_vs_planted = int(sum(np.array_equal(idx_all[s, :counts[s]], supports[s]) for s in range(S)))
 
-    # roofline of the dominant kernel (HashToBins pair launch)
-    alg_bytes = plan.h2b_bytes(S)
-    h2b_avg = float(np.mean(h2b_ms))
+    # roofline of the dominant kernel (HashToBins pair launch; one per chunk)
+    per_launch = S // chunks
+    alg_bytes = plan.h2b_bytes(per_launch)
+    h2b_avg = float(np.mean(h2b_ms)) / chunks
     achieved = alg_bytes / (h2b_avg * 1e-3) / 1e9
-    traffic = load_traffic(S, cfg_key)
+    traffic = load_traffic(per_launch, cfg_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_h2b_pair", "alg_bytes_per_launch": alg_bytes, "avg_launch_ms": round(h2b_avg, 4)}
+                "kernel": "k_h2b_pair", "signals_per_launch": per_launch, "alg_bytes_per_launch": alg_bytes,
+                "avg_launch_ms": round(h2b_avg, 4)}
     hbm = {"algorithmic_GBps": round(achieved, 1),
            "counter_GBps": None if traffic is None else round(traffic / (h2b_avg * 1e-3) / 1e9, 1)}
+    phases = {"hash_ms": round(float(np.mean(h2b_ms)), 4), "decode_ms_overlapped": round(float(np.mean(dec_ms)), 4),
+              "tail_ms": round(float(np.mean(tail_ms)), 4), "chunks": chunks}
 
     # ---------------------------------------------------------------- plain
     plain = None
@@ -272,6 +280,7 @@ def main():
                    "b_min": desc.b_min or max(2, args.B >> 4), "loc_prec": "f64", "input": "complex64"},
         "latency_ms": {"p50": round(percentile(step_ms, 50), 4), "p99": round(percentile(step_ms, 99), 4),
                        "what": "per batch step (graph replay), HIP events"},
+        "phases": phases,
         "plain": plain,
         "dense": dense,
         "hbm": hbm,

@@ -183,11 +183,15 @@ sfft_status_t sfft_execute(sfft_plan_t p, const void* x_dev, uint64_t* idx_host,
                            uint32_t* info_host, void* stream);
 
 /*
- * A batch of independent signals ("batched" path): every hashing of every
- * signal runs in one launch, the per-signal rounds are decoded by a
- * persistent device loop, and the launch sequence is captured once into
- * three hipGraphs (HashToBins, decode, output) and replayed (keyed by the
- * argument pointers and count).
+ * A batch of independent signals ("batched" path).  The batch runs as one
+ * chunk (SFFT_BATCH_CHUNKS=c splits it into c); for each chunk one launch runs every hashing
+ * round of every signal (HashToBins), and a decode workgroup per signal runs
+ * the rounds on the device (exact: NoiselessSparseFFTInner; general:
+ * SparseFFT) followed by the FP64 re-estimation and the output.  Chunk c's
+ * decode runs on the plan's auxiliary stream while chunk c+1's HashToBins
+ * runs on `stream`; `stream` waits for the last decode before the call's
+ * work is complete.  Each chunk's launch sequences are captured once into
+ * hipGraphs and replayed (keyed by the argument pointers and count).
  * Asynchronous on `stream`; nothing is copied to the host.
  *   x_dev      [count][n] signals (in_dtype)
  *   count      1 <= count <= max_batch
@@ -197,7 +201,7 @@ sfft_status_t sfft_execute(sfft_plan_t p, const void* x_dev, uint64_t* idx_host,
  *   count_dev  [count] number of coefficients per signal
  *   info_dev   [count][4] info words (SFFT_INFO_*), may be NULL
  * Results of one signal depend only on (its samples, its seed, the plan),
- * never on the other signals of the batch.
+ * never on the other signals of the batch or on the chunking.
  */
 sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t count,
                                  const uint64_t* seeds_dev, uint64_t* idx_dev, double* val_dev,
@@ -218,12 +222,15 @@ sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigm
 
 /*
  * Phase durations of the last sfft_execute_batch on a plan created with
- * SFFT_FLAG_TIMING, measured by HIP events recorded on the launch stream
- * between the three replayed graphs of a batch.  The caller must have
- * synchronised that stream.  ms_host[0..3] = HashToBins phase (state reset +
- * the pair kernel), decode loop, re-estimation and output, whole batch
- * (milliseconds); n_out >= 4.  Errors: SFFT_EINVAL when
- * the flag is not set or nothing ran yet, SFFT_EHIP.
+ * SFFT_FLAG_TIMING, from HIP events recorded between the replayed graphs on
+ * the streams they run on.  The caller must have synchronised the launch
+ * stream.  ms_host[0] = HashToBins (state reset + pair kernel) summed over
+ * the batch's chunks, [1] = decode + output summed over the chunks (these run
+ * on the plan's auxiliary stream, overlapped with the next chunk's
+ * HashToBins), [2] = time from the end of the last HashToBins to the end of
+ * the batch, [3] = whole batch (milliseconds); [4] (if n_out > 4) = number of
+ * chunks.  Errors: SFFT_EINVAL when the flag is not set or nothing ran yet,
+ * SFFT_EHIP.
  */
 sfft_status_t sfft_plan_timings(sfft_plan_t p, double* ms_host, uint32_t n_out);
 

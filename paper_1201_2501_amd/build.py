@@ -12,7 +12,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsfft.so")
-SOURCES = ["sfft_host.cpp", "sfft_kernels.hip"]
+SOURCES = ["sfft_host.cpp", "sfft_kernels.hip", "sfft_decode.hip"]
 ARCH = "gfx950"
 
 

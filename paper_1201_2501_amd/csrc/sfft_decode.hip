@@ -1,0 +1,842 @@
+// Decoders of the sparse FFT for gfx950: exact mode (Algorithm 1,
+// NoiselessSparseFFT) and general mode (Algorithms 2 and 3, SparseFFT with
+// LocateSignal/LocateInner and EstimateValues), each followed by the FP64
+// median re-estimation of the recovered coefficients and the output.
+//
+// One workgroup per signal walks the rounds on raw bins computed up front
+// (HashToBins steps 1-3 do not depend on zhat).  zhat is a sorted index list
+// with values in HBM, double buffered.  Every per-round grouping of zhat
+// entries by bin is an LDS counting sort (atomic counts, block scan,
+// scatter, insertion sort inside each bin by entry), so the subtraction of
+// HashToBins step 4 runs per bin in ascending index order - a fixed order,
+// without float atomics.  Candidates are compacted before they are sorted,
+// and zhat merges use binary search in LDS plus one block scan.
+#include "sfft_device.hpp"
+
+namespace sfft {
+
+namespace {
+
+constexpr uint64_t kNone = ~0ull;
+constexpr uint32_t kCandShift = 13;                        // candidate key: index << 13 | slot
+constexpr uint64_t kSlotMask = (1ull << kCandShift) - 1;
+constexpr uint64_t kFound = 1ull << 63;
+constexpr uint32_t kMaxMeas = 64;                          // medians over at most 64 values
+// One wave per signal: the decode is a chain of short dependent steps, so
+// its speed is set by barrier and memory latency, which a single-wave
+// workgroup keeps minimal; 512 signals fit on the chip at once.
+constexpr uint32_t kDec = 64;
+
+}  // namespace
+
+// ------------------------------------------------------------- LDS layout --
+struct DecodeLds {
+    uint64_t* zl;      // [capz]      indices of the current zhat buffer
+    uint32_t* hk;      // [capz]      bin of each zhat entry under the current hashing
+    uint32_t* ent;     // [capz]      zhat entries grouped by bin, ascending within a bin
+    uint32_t* first;   // [Bmax + 1]  first grouped position of each bin
+    uint32_t* cnt;     // [Bmax]      bin counters (shares storage with nkey)
+    uint64_t* ckey;    // [NK]        sort space
+    uint64_t* nkey;    // [NK]        new zhat keys of a merge (shares storage with cnt)
+    uint32_t* scan;    // [kDec]
+    uint32_t* misc;    // [8]
+};
+
+__host__ __device__ inline uint32_t pow2_ceil_u32(uint32_t v) {
+    uint32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+__host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// Bytes of the decode kernels' dynamic LDS; fills *L when base is given.
+__host__ __device__ inline size_t decode_lds_layout(uint32_t capz, uint32_t Bmax, unsigned char* base, DecodeLds* L) {
+    const uint32_t NK = pow2_ceil_u32(capz > Bmax ? capz : Bmax);
+    size_t off = 0;
+    const size_t o_zl = off;
+    off = align16(off + (size_t)capz * 8);
+    const size_t o_hk = off;
+    off = align16(off + (size_t)capz * 4);
+    const size_t o_ent = off;
+    off = align16(off + (size_t)capz * 4);
+    const size_t o_first = off;
+    off = align16(off + ((size_t)Bmax + 1) * 4);
+    const size_t o_ckey = off;
+    off = align16(off + (size_t)NK * 8);
+    const size_t o_union = off;
+    const size_t ubytes = (size_t)NK * 8 > (size_t)Bmax * 4 ? (size_t)NK * 8 : (size_t)Bmax * 4;
+    off = align16(off + ubytes);
+    const size_t o_scan = off;
+    off = align16(off + kDec * 4);
+    const size_t o_misc = off;
+    off = align16(off + 8 * 4);
+    if (base) {
+        L->zl = reinterpret_cast<uint64_t*>(base + o_zl);
+        L->hk = reinterpret_cast<uint32_t*>(base + o_hk);
+        L->ent = reinterpret_cast<uint32_t*>(base + o_ent);
+        L->first = reinterpret_cast<uint32_t*>(base + o_first);
+        L->ckey = reinterpret_cast<uint64_t*>(base + o_ckey);
+        L->cnt = reinterpret_cast<uint32_t*>(base + o_union);
+        L->nkey = reinterpret_cast<uint64_t*>(base + o_union);
+        L->scan = reinterpret_cast<uint32_t*>(base + o_scan);
+        L->misc = reinterpret_cast<uint32_t*>(base + o_misc);
+    }
+    return off;
+}
+
+size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax) { return decode_lds_layout(capz, Bmax, nullptr, nullptr); }
+
+// Group entries e < zc by L.hk[e] < B: afterwards the entries of bin h are
+// L.ent[L.first[h] .. L.first[h + 1]) in ascending order of e.
+__device__ void group_by_bin(DecodeLds& L, uint32_t zc, uint32_t B) {
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t h = tid; h < B; h += kDec) L.cnt[h] = 0;
+    __syncthreads();
+    for (uint32_t e = tid; e < zc; e += kDec) atomicAdd(&L.cnt[L.hk[e]], 1u);
+    __syncthreads();
+    const uint32_t per = (B + kDec - 1) / kDec;
+    const uint32_t h0 = tid * per < B ? tid * per : B;
+    const uint32_t h1 = h0 + per < B ? h0 + per : B;
+    uint32_t local = 0;
+    for (uint32_t h = h0; h < h1; ++h) local += L.cnt[h];
+    uint32_t pre;
+    block_exclusive_scan<kDec>(local, L.scan, &pre);
+    for (uint32_t h = h0; h < h1; ++h) {
+        L.first[h] = pre;
+        pre += L.cnt[h];
+    }
+    if (tid == 0) L.first[B] = zc;
+    __syncthreads();
+    for (uint32_t h = tid; h < B; h += kDec) L.cnt[h] = L.first[h];
+    __syncthreads();
+    for (uint32_t e = tid; e < zc; e += kDec) L.ent[atomicAdd(&L.cnt[L.hk[e]], 1u)] = e;
+    __syncthreads();
+    for (uint32_t h = tid; h < B; h += kDec) {
+        const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
+        for (uint32_t q = p0 + 1; q < p1; ++q) {
+            const uint32_t v = L.ent[q];
+            uint32_t s = q;
+            while (s > p0 && L.ent[s - 1] > v) {
+                L.ent[s] = L.ent[s - 1];
+                --s;
+            }
+            L.ent[s] = v;
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t lower_bound_lds(const uint64_t* a, uint32_t len, uint64_t v) {
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// zhat += candidates.  L.ckey[0, m) holds keys index << 13 | slot (unsorted,
+// unique indices) and cv[slot] the values.  Existing indices are updated in
+// place; new ones are merged by index into the other zhat buffer, which
+// becomes current.  Expects L.zl to hold the current indices.  Returns the
+// number of new entries.
+__device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv, uint64_t* zidx_all, double* zval_all,
+                                     uint32_t sig, uint32_t capz, uint32_t* st) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t zc = st[ST_ZCOUNT];
+    const uint32_t zb = st[ST_ZBUF];
+    double* zv = zval_all + ((uint64_t)sig * 2 + zb) * capz * 2;
+    const uint32_t NM = pow2_ceil_u32(m > 0 ? m : 1);
+    for (uint32_t q = m + tid; q < NM; q += kDec) L.ckey[q] = kNone;
+    bitonic_sort_u64<kDec>(L.ckey, NM);
+    const uint32_t per = (m + kDec - 1) / kDec;
+    const uint32_t q0 = tid * per < m ? tid * per : m;
+    const uint32_t q1 = q0 + per < m ? q0 + per : m;
+    uint32_t fresh = 0;
+    for (uint32_t q = q0; q < q1; ++q) {
+        const uint64_t k = L.ckey[q];
+        const uint64_t i = k >> kCandShift;
+        const uint32_t j = (uint32_t)(k & kSlotMask);
+        const uint32_t e = lower_bound_lds(L.zl, zc, i);
+        if (e < zc && L.zl[e] == i) {
+            zv[2 * e] += cv[2 * j];
+            zv[2 * e + 1] += cv[2 * j + 1];
+            L.ckey[q] = k | kFound;
+        } else {
+            ++fresh;
+        }
+    }
+    uint32_t pre;
+    const uint32_t total = block_exclusive_scan<kDec>(fresh, L.scan, &pre);
+    for (uint32_t q = q0; q < q1; ++q)
+        if (!(L.ckey[q] & kFound)) L.nkey[pre++] = L.ckey[q];
+    __syncthreads();
+    uint32_t mnew = total;
+    if (zc + mnew > capz) {
+        mnew = capz - zc;
+        if (tid == 0) st[ST_FLAGS] |= 2u;
+    }
+    uint64_t* zo = zidx_all + ((uint64_t)sig * 2 + (zb ^ 1)) * capz;
+    double* zov = zval_all + ((uint64_t)sig * 2 + (zb ^ 1)) * capz * 2;
+    for (uint32_t e = tid; e < zc; e += kDec) {
+        const uint64_t i = L.zl[e];
+        uint32_t lo = 0, hi = mnew;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((L.nkey[mid] >> kCandShift) < i) lo = mid + 1; else hi = mid;
+        }
+        const uint32_t pos = e + lo;
+        zo[pos] = i;
+        zov[2 * pos] = zv[2 * e];
+        zov[2 * pos + 1] = zv[2 * e + 1];
+    }
+    for (uint32_t q = tid; q < mnew; q += kDec) {
+        const uint64_t i = L.nkey[q] >> kCandShift;
+        const uint32_t j = (uint32_t)(L.nkey[q] & kSlotMask);
+        const uint32_t pos = q + lower_bound_lds(L.zl, zc, i);
+        zo[pos] = i;
+        zov[2 * pos] = cv[2 * j];
+        zov[2 * pos + 1] = cv[2 * j + 1];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        st[ST_ZCOUNT] = zc + mnew;
+        st[ST_ZBUF] = zb ^ 1;
+    }
+    __syncthreads();
+    return mnew;
+}
+
+// Stage the current zhat indices into LDS; returns zc.
+__device__ uint32_t stage_zhat(DecodeLds& L, const uint32_t* st, const uint64_t* zidx_all, uint32_t sig, uint32_t capz) {
+    const uint32_t zc = st[ST_ZCOUNT];
+    const uint64_t* zi = zidx_all + ((uint64_t)sig * 2 + st[ST_ZBUF]) * capz;
+    for (uint32_t e = threadIdx.x; e < zc; e += kDec) L.zl[e] = zi[e];
+    __syncthreads();
+    return zc;
+}
+
+// Bins of every staged entry under (sigma, b, B), grouped.
+__device__ void bin_zhat(DecodeLds& L, uint32_t zc, uint64_t sigma, uint64_t b, uint64_t n, uint32_t B) {
+    for (uint32_t e = threadIdx.x; e < zc; e += kDec) L.hk[e] = bin_offset(L.zl[e], sigma, b, n, B).h;
+    __syncthreads();
+    group_by_bin(L, zc, B);
+}
+
+// HashToBins step 4 for bin h: u_h - sum over the zhat entries of bin h, in
+// ascending index order, of G'_{-o(i)} zhat_i omega^{shift sigma i}.
+__device__ cx<double> corrected_bin(const DecodeLds& L, const double* rawv, uint32_t h, uint64_t shift,
+                                    const double* zv, uint64_t sigma, uint64_t b, uint64_t n, uint32_t B,
+                                    const WindowShape& ws) {
+    cx<double> u{rawv[2 * h], rawv[2 * h + 1]};
+    const uint64_t mask = n - 1;
+    const uint64_t as = (shift * sigma) & mask;
+    for (uint32_t q = L.first[h]; q < L.first[h + 1]; ++q) {
+        const uint32_t e = L.ent[q];
+        const uint64_t i = L.zl[e];
+        const double gp = gprime(-bin_offset(i, sigma, b, n, B).o, n, B, ws);
+        const cx<double> c0{gp * zv[2 * e], gp * zv[2 * e + 1]};
+        u = csub(u, cmul(c0, omega_d((as * i) & mask, n)));
+    }
+    return u;
+}
+
+__device__ __forceinline__ double phase_of(cx<double> u, cx<double> u2) {
+    const double zr = u.r * u2.r + u.i * u2.i;
+    const double zi = u.i * u2.r - u.r * u2.i;
+    double ph = atan2(zi, zr);
+    if (ph < 0.0) ph += 6.283185307179586;
+    return ph;
+}
+
+// Median of c values (real and imaginary parts separately; an even count
+// averages the two middle values).  Sorts re/im in place.
+__device__ cx<double> median_cx(double* re, double* im, uint32_t c) {
+    for (uint32_t q = 1; q < c; ++q) {
+        const double a = re[q], bq = im[q];
+        int32_t s = (int32_t)q - 1;
+        while (s >= 0 && re[s] > a) {
+            re[s + 1] = re[s];
+            --s;
+        }
+        re[s + 1] = a;
+        s = (int32_t)q - 1;
+        while (s >= 0 && im[s] > bq) {
+            im[s + 1] = im[s];
+            --s;
+        }
+        im[s + 1] = bq;
+    }
+    if (c & 1) return {re[c / 2], im[c / 2]};
+    return {0.5 * (re[c / 2 - 1] + re[c / 2]), 0.5 * (im[c / 2 - 1] + im[c / 2])};
+}
+
+// Sort key ordering by |v| descending, then slot ascending (51 magnitude bits).
+__device__ __forceinline__ uint64_t mag_key(double vr, double vi, uint32_t slot) {
+    const double mg = sqrt(vr * vr + vi * vi);
+    const uint64_t mb = (uint64_t)__double_as_longlong(mg) >> 12;
+    return ((~mb & ((1ull << 51) - 1)) << 13) | slot;
+}
+
+// Median over the samples est[e][...]: the `na` isolated ones at the front
+// when there are any, else the `nb` others at the back.
+__device__ cx<double> entry_median(const double* est, uint32_t nmeas, uint32_t count_word, cx<double> fallback) {
+    const uint32_t na = count_word & 0xFFFFu, nb = count_word >> 16;
+    const uint32_t c = na ? na : nb;
+    if (c == 0) return fallback;
+    const uint32_t first = na ? 0u : nmeas - nb;
+    double re[kMaxMeas], im[kMaxMeas];
+    for (uint32_t q = 0; q < c; ++q) {
+        re[q] = est[(first + q) * 2];
+        im[q] = est[(first + q) * 2 + 1];
+    }
+    return median_cx(re, im, c);
+}
+
+// Record one re-estimation sample of entry e: isolated samples from the
+// front of its slot range, the others from the back.
+__device__ __forceinline__ void push_sample(double* est, uint32_t nmeas, uint32_t* count_word, bool isolated,
+                                            cx<double> v) {
+    const uint32_t c = *count_word;
+    const uint32_t na = c & 0xFFFFu, nb = c >> 16;
+    const uint32_t slot = isolated ? na : nmeas - 1 - nb;
+    est[slot * 2] = v.r;
+    est[slot * 2 + 1] = v.i;
+    *count_word = isolated ? c + 1 : c + (1u << 16);
+}
+
+// Write the output of one signal from re-estimated values fin[e] (e < zc,
+// ascending index): all of them when keep_all, else those with
+// |v| > half_theta; at most cap by (|v| desc, index asc); ascending index.
+__device__ uint32_t write_output(DecodeLds& L, const uint64_t* zi, const double* fin, uint32_t zc, bool keep_all,
+                                 double half_theta, uint32_t cap, double scale, uint64_t* oidx, double* oval,
+                                 uint32_t* flags) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (zc + kDec - 1) / kDec;
+    const uint32_t e0 = tid * per < zc ? tid * per : zc;
+    const uint32_t e1 = e0 + per < zc ? e0 + per : zc;
+    uint32_t cnt = 0;
+    for (uint32_t e = e0; e < e1; ++e)
+        cnt += keep_all || sqrt(fin[2 * e] * fin[2 * e] + fin[2 * e + 1] * fin[2 * e + 1]) > half_theta;
+    uint32_t pre;
+    const uint32_t nsurv = block_exclusive_scan<kDec>(cnt, L.scan, &pre);
+    uint32_t nout;
+    if (nsurv <= cap) {
+        for (uint32_t e = e0; e < e1; ++e) {
+            const double vr = fin[2 * e], vi = fin[2 * e + 1];
+            if (keep_all || sqrt(vr * vr + vi * vi) > half_theta) {
+                oidx[pre] = zi[e];
+                oval[2 * pre] = vr * scale;
+                oval[2 * pre + 1] = vi * scale;
+                ++pre;
+            }
+        }
+        nout = nsurv;
+    } else {
+        *flags |= 1u;
+        const uint32_t N = pow2_ceil_u32(zc);
+        for (uint32_t e = tid; e < N; e += kDec) {
+            bool keep = false;
+            if (e < zc) keep = keep_all || sqrt(fin[2 * e] * fin[2 * e] + fin[2 * e + 1] * fin[2 * e + 1]) > half_theta;
+            L.ckey[e] = keep ? mag_key(fin[2 * e], fin[2 * e + 1], e) : kNone;
+        }
+        bitonic_sort_u64<kDec>(L.ckey, N);
+        for (uint32_t q = tid; q < N; q += kDec) L.ckey[q] = q < cap ? (L.ckey[q] & kSlotMask) : kNone;
+        bitonic_sort_u64<kDec>(L.ckey, N);
+        for (uint32_t q = tid; q < cap; q += kDec) {
+            const uint32_t e = (uint32_t)L.ckey[q];
+            oidx[q] = zi[e];
+            oval[2 * q] = fin[2 * e] * scale;
+            oval[2 * q + 1] = fin[2 * e + 1] * scale;
+        }
+        nout = cap;
+    }
+    __syncthreads();
+    for (uint32_t q = nout + tid; q < cap; q += kDec) {
+        oidx[q] = 0;
+        oval[2 * q] = 0.0;
+        oval[2 * q + 1] = 0.0;
+    }
+    return nout;
+}
+
+// =================================================================== exact
+__device__ __forceinline__ const double* raw_bins(const DecodeArgs& D, uint32_t sig, uint32_t r, uint32_t a) {
+    return D.raw + (((uint64_t)sig * D.rounds + r) * 2 + a) * (uint64_t)D.Bmax * 2;
+}
+
+// One round of NoiselessSparseFFTInner on signal `sig` (Algorithm 1).
+__device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uint32_t r, uint64_t seed) {
+    const uint32_t tid = threadIdx.x;
+    const RoundDev g = D.geom[r];
+    const uint64_t n = D.n, mask = n - 1;
+    const uint32_t B = g.B;
+    const uint64_t sigma = draw_sigma(seed, n, r);
+    const uint64_t b = draw_b(seed, n, r);
+    const uint64_t sinv = inverse_odd(sigma) & mask;
+    uint32_t* st = D.state + (uint64_t)sig * kStateWords;
+    const uint32_t zc = stage_zhat(L, st, D.zidx, sig, D.capz);
+    const double* zv = D.zval + ((uint64_t)sig * 2 + st[ST_ZBUF]) * D.capz * 2;
+    double* cv = D.cand_v + (uint64_t)sig * D.Bmax * 2;
+    bin_zhat(L, zc, sigma, b, n, B);
+    if (tid == 0) {
+        L.misc[0] = 0;
+        L.misc[1] = 0;
+    }
+    __syncthreads();
+    const double* r0 = raw_bins(D, sig, r, 0);
+    const double* r1 = raw_bins(D, sig, r, 1);
+    const double two_pi = 6.283185307179586;
+    uint32_t myJ = 0;
+    for (uint32_t j = tid; j < B; j += kDec) {
+        double u0r = r0[2 * j], u0i = r0[2 * j + 1];
+        double u1r = r1[2 * j], u1i = r1[2 * j + 1];
+        for (uint32_t q = L.first[j]; q < L.first[j + 1]; ++q) {
+            const uint32_t e = L.ent[q];
+            const uint64_t i = L.zl[e];
+            const double gp = gprime(-bin_offset(i, sigma, b, n, B).o, n, B, g.ws);
+            const double c0r = gp * zv[2 * e], c0i = gp * zv[2 * e + 1];
+            const cx<double> c1 = cmul(cx<double>{c0r, c0i}, omega_d((sigma * i) & mask, n));
+            u0r -= c0r;
+            u0i -= c0i;
+            u1r -= c1.r;
+            u1i -= c1.i;
+        }
+        const double mag = sqrt(u0r * u0r + u0i * u0i);
+        if (!(mag > D.theta)) continue;
+        ++myJ;
+        const double zr = u0r * u1r + u0i * u1i;
+        const double zim = u0i * u1r - u0r * u1i;
+        double phi = atan2(zim, zr);
+        if (phi < 0.0) phi += two_pi;
+        const double q = phi / two_pi * (double)n;
+        const uint64_t pos = ((uint64_t)floor(q + 0.5)) & mask;
+        const uint64_t i = (sinv * pos) & mask;
+        const BinOffset bo = bin_offset(i, sigma, b, n, B);
+        if (bo.h != j) continue;
+        const double gp = gprime(-bo.o, n, B, g.ws);
+        if (!(gp >= D.g_min)) continue;
+        cv[2 * j] = u0r / gp;
+        cv[2 * j + 1] = u0i / gp;
+        L.ckey[atomicAdd(&L.misc[1], 1u)] = (i << kCandShift) | j;
+    }
+    if (myJ) atomicAdd(&L.misc[0], myJ);
+    __syncthreads();
+    const uint32_t J = L.misc[0], m = L.misc[1];
+    if (J == 0) {
+        if (tid == 0) {
+            st[ST_EMPTY] += 1;
+            if (st[ST_EMPTY] >= D.patience) st[ST_DONE] = 1;
+            st[ST_ROUNDS] = r + 1;
+            st[ST_LASTJ] = 0;
+            st[ST_ACCEPT] = 0;
+        }
+        __syncthreads();
+        return;
+    }
+    const uint32_t mnew = merge_candidates(L, m, cv, D.zidx, D.zval, sig, D.capz, st);
+    if (tid == 0) {
+        st[ST_EMPTY] = 0;
+        st[ST_ROUNDS] = r + 1;
+        st[ST_LASTJ] = J;
+        st[ST_ACCEPT] = mnew;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kDec) k_exact_init(DecodeArgs D) {
+    const uint32_t sig = blockIdx.x * kDec + threadIdx.x;
+    if (sig >= D.count) return;
+    uint32_t* st = D.state + (uint64_t)sig * kStateWords;
+    for (uint32_t q = 0; q < kStateWords; ++q) st[q] = 0;
+}
+
+__global__ void __launch_bounds__(kDec) k_exact_decode(DecodeArgs D) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    DecodeLds L;
+    decode_lds_layout(D.capz, D.Bmax, smem, &L);
+    const uint32_t sig = blockIdx.x;
+    const uint64_t seed = D.seeds ? D.seeds[sig] : D.plan_seed;
+    const uint32_t* st = D.state + (uint64_t)sig * kStateWords;
+    for (uint32_t r = D.r_begin; r < D.r_end; ++r) {
+        __syncthreads();
+        if (st[ST_DONE]) break;
+        exact_round(D, L, sig, r, seed);
+    }
+}
+
+// Final FP64 re-estimation of every zhat entry over the decoded rounds
+// (EstimateValues' estimate with a = 0 on x minus the other entries; rounds
+// where the entry is alone in its bin first), then the output.
+__global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    DecodeLds L;
+    decode_lds_layout(D.capz, D.Bmax, smem, &L);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sig = blockIdx.x;
+    const uint64_t seed = D.seeds ? D.seeds[sig] : D.plan_seed;
+    uint32_t* st = D.state + (uint64_t)sig * kStateWords;
+    const uint64_t n = D.n;
+    const uint32_t R = st[ST_ROUNDS];
+    const uint32_t zc = stage_zhat(L, st, D.zidx, sig, D.capz);
+    const uint64_t* zi = D.zidx + ((uint64_t)sig * 2 + st[ST_ZBUF]) * D.capz;
+    const double* zv = D.zval + ((uint64_t)sig * 2 + st[ST_ZBUF]) * D.capz * 2;
+    const uint32_t nmeas = D.rounds;
+    double* est = D.est + (uint64_t)sig * D.capz * nmeas * 2;
+    uint32_t* ecount = D.ecount + (uint64_t)sig * D.capz;
+    double* gl = D.gtmp + (uint64_t)sig * D.capz;
+    double* fin = D.fin + (uint64_t)sig * D.capz * 2;
+    for (uint32_t e = tid; e < zc; e += kDec) ecount[e] = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        const RoundDev g = D.geom[r];
+        const uint32_t B = g.B;
+        const uint64_t sigma = draw_sigma(seed, n, r);
+        const uint64_t b = draw_b(seed, n, r);
+        __syncthreads();
+        for (uint32_t e = tid; e < zc; e += kDec) {
+            const BinOffset bo = bin_offset(L.zl[e], sigma, b, n, B);
+            L.hk[e] = bo.h;
+            gl[e] = gprime(-bo.o, n, B, g.ws);
+        }
+        __syncthreads();
+        group_by_bin(L, zc, B);
+        const double* r0 = raw_bins(D, sig, r, 0);
+        for (uint32_t e = tid; e < zc; e += kDec) {
+            const double ge = gl[e];
+            if (ge < D.g_min) continue;
+            const uint32_t h = L.hk[e];
+            const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
+            double orr = 0.0, oii = 0.0;
+            for (uint32_t q = p0; q < p1; ++q) {
+                const uint32_t e2 = L.ent[q];
+                if (e2 == e) continue;
+                orr += gl[e2] * zv[2 * e2];
+                oii += gl[e2] * zv[2 * e2 + 1];
+            }
+            push_sample(est + (uint64_t)e * nmeas * 2, nmeas, &ecount[e], p1 - p0 == 1,
+                        cx<double>{(r0[2 * h] - orr) / ge, (r0[2 * h + 1] - oii) / ge});
+        }
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < zc; e += kDec) {
+        const cx<double> v = entry_median(est + (uint64_t)e * nmeas * 2, nmeas, ecount[e],
+                                          cx<double>{zv[2 * e], zv[2 * e + 1]});
+        fin[2 * e] = v.r;
+        fin[2 * e + 1] = v.i;
+    }
+    __syncthreads();
+    uint32_t flags = st[ST_FLAGS];
+    const uint32_t nout = write_output(L, zi, fin, zc, false, 0.5 * D.theta, D.cap, D.out_scale,
+                                       D.out_idx + (uint64_t)sig * D.cap, D.out_val + (uint64_t)sig * D.cap * 2,
+                                       &flags);
+    if (tid == 0) {
+        D.out_count[sig] = nout;
+        st[ST_FLAGS] = flags;
+        if (D.out_info) {
+            D.out_info[(uint64_t)sig * 4 + SFFT_INFO_ROUNDS] = R;
+            D.out_info[(uint64_t)sig * 4 + SFFT_INFO_FLAGS] = flags;
+            D.out_info[(uint64_t)sig * 4 + SFFT_INFO_ZHAT] = zc;
+            D.out_info[(uint64_t)sig * 4 + SFFT_INFO_LOCATED] = 0;
+        }
+    }
+}
+
+// ================================================================= general
+__device__ __forceinline__ const double* gen_raw(const GeneralArgs& G, uint32_t sig, uint32_t slot, uint32_t a) {
+    return G.raw + (((uint64_t)sig * G.nslots + slot) * 2 + a) * (uint64_t)G.Bmax * 2;
+}
+
+// One SparseFFT round (Algorithm 2): LocateSignal, EstimateValues, zhat update.
+__device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, uint32_t r, uint64_t seed) {
+    const uint32_t tid = threadIdx.x;
+    const RoundDev g = G.geom[r];
+    const GenRoundDev& gr = G.groundv[r];
+    const uint64_t n = G.n, mask = n - 1;
+    const uint32_t B = g.B;
+    uint32_t* st = G.state + (uint64_t)sig * kStateWords;
+    const uint32_t zc = stage_zhat(L, st, G.zidx, sig, G.capz);
+    const double* zv = G.zval + ((uint64_t)sig * 2 + st[ST_ZBUF]) * G.capz * 2;
+    uint64_t* cand = G.cand_i + (uint64_t)sig * G.Bmax;
+    double* candv = G.cand_v + (uint64_t)sig * G.Bmax * 2;
+    uint32_t* candn = G.cand_n + (uint64_t)sig * G.Bmax;
+    const double two_pi = 6.283185307179586;
+
+    // ---- LocateSignal (Algorithm 3): one (sigma, b); one thread per bin
+    // carries its region through every LocateInner level.
+    {
+        const uint64_t scale = 1ull << kFracBits;
+        const uint64_t modfp = n << kFracBits;
+        const uint64_t mmask = modfp - 1;
+        const uint64_t sigma = draw_sigma(seed, n, r, 0, 0);
+        const uint64_t b = draw_b(seed, n, r, 0, 0);
+        const uint64_t sinv = inverse_odd(sigma) & mask;
+        const uint64_t sbs = ((sigma * b) & mask) << kFracBits;
+        const double tol = G.s * 3.141592653589793;
+        bin_zhat(L, zc, sigma, b, n, B);
+        if (tid == 0) L.misc[0] = 0;
+        __syncthreads();
+        for (uint32_t j = tid; j < B; j += kDec) {
+            uint64_t l = ((uint64_t)j * (n / B) * scale + modfp - (n / (2 * (uint64_t)B)) * scale) & mmask;
+            bool alive = true;
+            for (uint32_t D = 1; D <= gr.nlev && alive; ++D) {
+                const uint64_t W = gr.Wfp[D - 1];
+                const uint64_t half = W / (2 * (uint64_t)G.t);
+                const uint64_t step = W / G.t;
+                uint8_t votes[kMaxT];
+                for (uint32_t qq = 0; qq < G.t; ++qq) votes[qq] = 0;
+                for (uint32_t q = 0; q < G.R_loc; ++q) {
+                    const uint64_t a = draw_a(seed, n, r, D, q);
+                    const uint64_t beta = draw_beta(seed, gr.blo[D - 1], gr.bhi[D - 1], r, D, q);
+                    const uint32_t slot = gr.slot0 + (D - 1) * G.R_loc + q;
+                    const cx<double> u = corrected_bin(L, gen_raw(G, sig, slot, 0), j, a, zv, sigma, b, n, B, g.ws);
+                    const cx<double> u2 =
+                        corrected_bin(L, gen_raw(G, sig, slot, 1), j, (a + beta) & mask, zv, sigma, b, n, B, g.ws);
+                    const double c = phase_of(u, u2);
+                    for (uint32_t qq = 0; qq < G.t; ++qq) {
+                        const uint64_t M = (l + (2 * (uint64_t)qq + 1) * half) & mmask;
+                        const uint64_t num = (beta * ((M + sbs) & mmask)) & mmask;
+                        const double ang = two_pi * (double)num / (double)modfp;
+                        const double d = fabs(ang - c);
+                        const double dist = d < two_pi - d ? d : two_pi - d;
+                        votes[qq] += dist < tol;
+                    }
+                }
+                uint32_t firstq = G.t;
+                for (uint32_t qq = 0; qq < G.t; ++qq)
+                    if (2u * votes[qq] > G.R_loc) {
+                        firstq = qq;
+                        break;
+                    }
+                if (firstq == G.t) alive = false;
+                else l = (l + firstq * step) & mmask;
+            }
+            if (alive) {
+                const uint64_t pos = ((l + scale - 1) >> kFracBits) & mask;
+                L.ckey[atomicAdd(&L.misc[0], 1u)] = (sinv * pos + b) & mask;
+            }
+        }
+    }
+    __syncthreads();
+    // L: sorted, unique candidate indices
+    uint32_t nL;
+    {
+        const uint32_t m = L.misc[0];
+        const uint32_t NM = pow2_ceil_u32(m > 0 ? m : 1);
+        for (uint32_t q = m + tid; q < NM; q += kDec) L.ckey[q] = kNone;
+        bitonic_sort_u64<kDec>(L.ckey, NM);
+        const uint32_t per = (m + kDec - 1) / kDec;
+        const uint32_t p0 = tid * per < m ? tid * per : m;
+        const uint32_t p1 = p0 + per < m ? p0 + per : m;
+        uint32_t cnt = 0;
+        for (uint32_t p = p0; p < p1; ++p) cnt += (p == 0 || L.ckey[p] != L.ckey[p - 1]);
+        uint32_t pre;
+        nL = block_exclusive_scan<kDec>(cnt, L.scan, &pre);
+        for (uint32_t p = p0; p < p1; ++p)
+            if (p == 0 || L.ckey[p] != L.ckey[p - 1]) cand[pre++] = L.ckey[p];
+        __syncthreads();
+    }
+
+    // ---- EstimateValues (Algorithm 2): R_est fresh hashings, medians
+    for (uint32_t c = tid; c < nL; c += kDec) candn[c] = 0;
+    for (uint32_t e = 0; e < G.R_est; ++e) {
+        const uint64_t sigma = draw_sigma(seed, n, r, LEVEL_EST, e);
+        const uint64_t a = draw_a(seed, n, r, LEVEL_EST, e);
+        const uint64_t b = draw_b(seed, n, r, LEVEL_EST, e);
+        const double* rawv = gen_raw(G, sig, gr.slot0 + gr.nloc + e, 0);
+        __syncthreads();
+        bin_zhat(L, zc, sigma, b, n, B);
+        for (uint32_t c = tid; c < nL; c += kDec) {
+            const uint64_t i = cand[c];
+            const BinOffset bo = bin_offset(i, sigma, b, n, B);
+            const double gp = gprime(-bo.o, n, B, g.ws);
+            if (gp < G.g_min) continue;
+            const cx<double> u = corrected_bin(L, rawv, bo.h, a, zv, sigma, b, n, B, g.ws);
+            const uint64_t p = (((a * sigma) & mask) * i) & mask;
+            const cx<double> v = cmul(u, omega_d((n - p) & mask, n));
+            const uint32_t k = candn[c];
+            double* dst = G.cand_e + (((uint64_t)sig * G.R_est + k) * G.Bmax + c) * 2;
+            dst[0] = v.r / gp;
+            dst[1] = v.i / gp;
+            candn[c] = k + 1;
+        }
+    }
+    __syncthreads();
+    for (uint32_t c = tid; c < nL; c += kDec) {
+        const uint32_t k = candn[c];
+        if (k == 0) continue;
+        double re[kMaxMeas], im[kMaxMeas];
+        for (uint32_t q = 0; q < k; ++q) {
+            const double* src = G.cand_e + (((uint64_t)sig * G.R_est + q) * G.Bmax + c) * 2;
+            re[q] = src[0];
+            im[q] = src[1];
+        }
+        const cx<double> med = median_cx(re, im, k);
+        candv[2 * c] = med.r;
+        candv[2 * c + 1] = med.i;
+    }
+    __syncthreads();
+    // top-k' by (|w| desc, index asc); candidates are in index order
+    const uint32_t kprime = 3 * gr.k_r;
+    const uint32_t NL = pow2_ceil_u32(nL > 0 ? nL : 1);
+    for (uint32_t c = tid; c < NL; c += kDec)
+        L.ckey[c] = (c < nL && candn[c] > 0) ? mag_key(candv[2 * c], candv[2 * c + 1], c) : kNone;
+    bitonic_sort_u64<kDec>(L.ckey, NL);
+    uint32_t take = 0;
+    {
+        uint32_t mine = 0;
+        for (uint32_t q = tid; q < NL; q += kDec) mine += (q < kprime && L.ckey[q] != kNone);
+        if (tid == 0) L.misc[1] = 0;
+        __syncthreads();
+        if (mine) atomicAdd(&L.misc[1], mine);
+        __syncthreads();
+        take = L.misc[1];
+    }
+    // selected entries occupy ckey[0, take); rewrite them as index keys
+    for (uint32_t q = tid; q < take; q += kDec) {
+        const uint32_t c = (uint32_t)(L.ckey[q] & kSlotMask);
+        L.ckey[q] = (cand[c] << kCandShift) | c;
+    }
+    __syncthreads();
+    merge_candidates(L, take, candv, G.zidx, G.zval, sig, G.capz, st);
+    if (tid == 0) {
+        st[ST_ROUNDS] = r + 1;
+        st[ST_LASTJ] = nL;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kDec) k_general_decode(GeneralArgs G, uint32_t r_begin, uint32_t r_end) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    DecodeLds L;
+    decode_lds_layout(G.capz, G.Bmax, smem, &L);
+    const uint32_t sig = blockIdx.x;
+    const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
+    for (uint32_t r = r_begin; r < r_end; ++r) {
+        __syncthreads();
+        general_round(G, L, sig, r, seed);
+    }
+}
+
+// FP64 re-estimation over every EstimateValues hashing of every round
+// (isolated measurements first), then the top-cap entries by magnitude in
+// ascending index order.
+__global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    DecodeLds L;
+    decode_lds_layout(G.capz, G.Bmax, smem, &L);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sig = blockIdx.x;
+    const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
+    uint32_t* st = G.state + (uint64_t)sig * kStateWords;
+    const uint64_t n = G.n, mask = n - 1;
+    const uint32_t R = st[ST_ROUNDS];
+    const uint32_t zc = stage_zhat(L, st, G.zidx, sig, G.capz);
+    const uint64_t* zi = G.zidx + ((uint64_t)sig * 2 + st[ST_ZBUF]) * G.capz;
+    const double* zv = G.zval + ((uint64_t)sig * 2 + st[ST_ZBUF]) * G.capz * 2;
+    const uint32_t nmeas = G.R * G.R_est;
+    double* est = G.est + (uint64_t)sig * G.capz * nmeas * 2;
+    uint32_t* ecount = G.ecount + (uint64_t)sig * G.capz;
+    double* gl = G.gtmp + (uint64_t)sig * G.capz;
+    double* fin = G.fin + (uint64_t)sig * G.capz * 2;
+    for (uint32_t e = tid; e < zc; e += kDec) ecount[e] = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+        const RoundDev g = G.geom[r];
+        const GenRoundDev& gr = G.groundv[r];
+        const uint32_t B = g.B;
+        for (uint32_t m = 0; m < G.R_est; ++m) {
+            const uint64_t sigma = draw_sigma(seed, n, r, LEVEL_EST, m);
+            const uint64_t a = draw_a(seed, n, r, LEVEL_EST, m);
+            const uint64_t b = draw_b(seed, n, r, LEVEL_EST, m);
+            const double* rawv = gen_raw(G, sig, gr.slot0 + gr.nloc + m, 0);
+            const uint64_t as = (a * sigma) & mask;
+            __syncthreads();
+            for (uint32_t e = tid; e < zc; e += kDec) {
+                const BinOffset bo = bin_offset(L.zl[e], sigma, b, n, B);
+                L.hk[e] = bo.h;
+                gl[e] = gprime(-bo.o, n, B, g.ws);
+            }
+            __syncthreads();
+            group_by_bin(L, zc, B);
+            for (uint32_t e = tid; e < zc; e += kDec) {
+                const double ge = gl[e];
+                if (ge < G.g_min) continue;
+                const uint32_t h = L.hk[e];
+                const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
+                cx<double> others{0.0, 0.0};
+                for (uint32_t q = p0; q < p1; ++q) {
+                    const uint32_t e2 = L.ent[q];
+                    if (e2 == e) continue;
+                    const cx<double> c0{gl[e2] * zv[2 * e2], gl[e2] * zv[2 * e2 + 1]};
+                    others = cadd(others, cmul(c0, omega_d((as * L.zl[e2]) & mask, n)));
+                }
+                const cx<double> u = csub(cx<double>{rawv[2 * h], rawv[2 * h + 1]}, others);
+                const uint64_t pe = (as * L.zl[e]) & mask;
+                const cx<double> v = cmul(u, omega_d((n - pe) & mask, n));
+                push_sample(est + (uint64_t)e * nmeas * 2, nmeas, &ecount[e], p1 - p0 == 1,
+                            cx<double>{v.r / ge, v.i / ge});
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t e = tid; e < zc; e += kDec) {
+        const cx<double> v = entry_median(est + (uint64_t)e * nmeas * 2, nmeas, ecount[e],
+                                          cx<double>{zv[2 * e], zv[2 * e + 1]});
+        fin[2 * e] = v.r;
+        fin[2 * e + 1] = v.i;
+    }
+    __syncthreads();
+    uint32_t flags = st[ST_FLAGS];
+    const uint32_t nout = write_output(L, zi, fin, zc, true, 0.0, G.cap, G.out_scale,
+                                       G.out_idx + (uint64_t)sig * G.cap, G.out_val + (uint64_t)sig * G.cap * 2,
+                                       &flags);
+    if (tid == 0) {
+        G.out_count[sig] = nout;
+        if (G.out_info) {
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_ROUNDS] = R;
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_FLAGS] = st[ST_FLAGS];
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_ZHAT] = zc;
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_LOCATED] = st[ST_LASTJ];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ launch --
+hipError_t launch_exact_init(const DecodeArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_exact_init, dim3((a.count + kDec - 1) / kDec), dim3(kDec), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_exact_decode(const DecodeArgs& a, hipStream_t s) {
+    const size_t lds = decode_lds_bytes(a.capz, a.Bmax);
+    hipError_t e = allow_lds(k_exact_decode, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_exact_decode, dim3(a.count), dim3(kDec), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s) {
+    const size_t lds = decode_lds_bytes(a.capz, a.Bmax);
+    hipError_t e = allow_lds(k_exact_finish, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_exact_finish, dim3(a.count), dim3(kDec), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_t r_end, hipStream_t s) {
+    const size_t lds = decode_lds_bytes(a.capz, a.Bmax);
+    hipError_t e = allow_lds(k_general_decode, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_general_decode, dim3(a.count), dim3(kDec), lds, s, a, r_begin, r_end);
+    return hipGetLastError();
+}
+
+hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s) {
+    const size_t lds = decode_lds_bytes(a.capz, a.Bmax);
+    hipError_t e = allow_lds(k_general_finish, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_general_finish, dim3(a.count), dim3(kDec), lds, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace sfft

@@ -98,8 +98,15 @@ uint32_t zhat_capacity(const sfft_plan_desc_t& d) {
 }  // namespace
 
 // ------------------------------------------------------------------ plan ---
+constexpr uint32_t kMaxChunks = 8;
+
+// Captured graphs of one batch shape: per chunk c, exec_h[c] = state reset +
+// HashToBins of the chunk (launch stream), exec_d[c] = decode + output of the
+// chunk (auxiliary stream), keyed by every argument pointer and the count.
 struct GraphCache {
-    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t exec_h[kMaxChunks] = {};
+    hipGraphExec_t exec_d[kMaxChunks] = {};
+    uint32_t chunks = 0;
     const void* x = nullptr;
     const void* seeds = nullptr;
     const void* o1 = nullptr;
@@ -155,7 +162,12 @@ struct sfft_plan_s {
     uint32_t* p_count = nullptr;
     uint32_t* p_info = nullptr;
     hipStream_t capture_stream = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipStream_t aux_stream = nullptr;          // decode of chunk c overlaps HashToBins of chunk c+1
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_ready[kMaxChunks] = {};
+    hipEvent_t ev_h0[kMaxChunks] = {}, ev_h1[kMaxChunks] = {}, ev_d0[kMaxChunks] = {}, ev_d1[kMaxChunks] = {};
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;
+    uint32_t timed_chunks = 0;
     bool timed_once = false;
     GraphCache graph;
     std::mutex mu;
@@ -345,8 +357,20 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     ST_TRY(dev_alloc(p, &p->p_count, 1));
     ST_TRY(dev_alloc(p, &p->p_info, 4));
     HIP_TRY(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
-    if (d.flags & SFFT_FLAG_TIMING)
-        for (auto& e : p->ev) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+    for (auto& e : p->ev_ready) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (d.flags & SFFT_FLAG_TIMING) {
+        for (uint32_t c = 0; c < kMaxChunks; ++c) {
+            HIP_TRY(hipEventCreate(&p->ev_h0[c]));
+            HIP_TRY(hipEventCreate(&p->ev_h1[c]));
+            HIP_TRY(hipEventCreate(&p->ev_d0[c]));
+            HIP_TRY(hipEventCreate(&p->ev_d1[c]));
+        }
+        HIP_TRY(hipEventCreate(&p->ev_t0));
+        HIP_TRY(hipEventCreate(&p->ev_t1));
+    }
     return SFFT_OK;
 }
 
@@ -475,37 +499,117 @@ sfft_status_t enqueue_general_hash(sfft_plan_s* p, const void* x, uint32_t count
     return SFFT_OK;
 }
 
-// The batched sequence in three parts: 0 = init + HashToBins of every round
-// of every signal, 1 = decode loop, 2 = re-estimation and output.
-sfft_status_t enqueue_batch_part(sfft_plan_s* p, int part, const void* x, uint32_t count, const uint64_t* seeds,
-                                 uint64_t* idx, double* val, uint32_t* cnt, uint32_t* info, hipStream_t s) {
-    DecodeArgs D = base_decode(p, count, seeds, p->raw, idx, val, cnt, info);
+// Per-signal workspace and output pointers advanced to signal `off`.
+void offset_decode(const sfft_plan_s* p, DecodeArgs& D, uint32_t off) {
+    const uint64_t Bm = p->Bmax, Z = p->capz, o = off;
+    D.raw += o * p->R * 4 * Bm;
+    D.work += o * 4 * Bm;
+    D.cand_i += o * Bm;
+    D.cand_v += o * 2 * Bm;
+    D.zidx += o * 2 * Z;
+    D.zval += o * 4 * Z;
+    D.est += o * Z * p->R * 2;
+    D.fin += o * 2 * Z;
+    D.gtmp += o * Z;
+    D.ecount += o * Z;
+    D.state += o * kStateWords;
+    if (D.seeds) D.seeds += o;
+    D.out_idx += o * p->cap;
+    D.out_val += o * 2 * p->cap;
+    D.out_count += o;
+    if (D.out_info) D.out_info += o * 4;
+}
+
+void offset_general(const sfft_plan_s* p, GeneralArgs& G, uint32_t off) {
+    const uint64_t Bm = p->Bmax, Z = p->capz, o = off;
+    const uint64_t meas = (uint64_t)p->R * p->d.R_est;
+    G.raw += o * p->nslots * 4 * Bm;
+    G.cand_i += o * Bm;
+    G.cand_v += o * 2 * Bm;
+    G.cand_e += o * p->d.R_est * 2 * Bm;
+    G.cand_n += o * Bm;
+    G.zidx += o * 2 * Z;
+    G.zval += o * 4 * Z;
+    G.est += o * Z * meas * 2;
+    G.fin += o * 2 * Z;
+    G.gtmp += o * Z;
+    G.ecount += o * Z;
+    G.state += o * kStateWords;
+    if (G.seeds) G.seeds += o;
+    G.out_idx += o * p->cap;
+    G.out_val += o * 2 * p->cap;
+    G.out_count += o;
+    if (G.out_info) G.out_info += o * 4;
+}
+
+// Part 0 of a chunk [off, off + cnt): state reset + HashToBins of every
+// round; part 1: decode loop + re-estimation and output.
+sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt, const void* x,
+                            const uint64_t* seeds, uint64_t* idx, double* val, uint32_t* ocnt, uint32_t* info,
+                            hipStream_t s) {
+    const size_t elem = in_c128(p) ? 16 : 8;
+    const void* xc = static_cast<const char*>(x) + (size_t)off * p->d.n * elem;
+    const uint64_t* sc = seeds ? seeds + off : nullptr;
+    DecodeArgs D = base_decode(p, cnt, seeds, p->raw, idx, val, ocnt, info);
+    offset_decode(p, D, off);
     if (general_mode(p)) {
-        GeneralArgs G = base_general(p, count, seeds, p->raw, idx, val, cnt, info);
+        GeneralArgs G = base_general(p, cnt, seeds, p->raw, idx, val, ocnt, info);
+        offset_general(p, G, off);
         if (part == 0) {
             HIP_TRY(launch_exact_init(D, s));
-            ST_TRY(enqueue_general_hash(p, x, count, seeds, p->raw, 0, p->R, s));
-        } else if (part == 1) {
-            HIP_TRY(launch_general_decode(G, 0, p->R, s));
+            double* rawc = p->raw + (uint64_t)off * p->nslots * 4 * p->Bmax;
+            ST_TRY(enqueue_general_hash(p, xc, cnt, sc, rawc, 0, p->R, s));
         } else {
+            HIP_TRY(launch_general_decode(G, 0, p->R, s));
             HIP_TRY(launch_general_finish(G, s));
         }
         return SFFT_OK;
     }
     if (part == 0) {
         HIP_TRY(launch_exact_init(D, s));
-        H2BArgs a = base_h2b(p, x);
-        a.seeds = seeds;
-        a.count = count;
+        H2BArgs a = base_h2b(p, xc);
+        a.seeds = sc;
+        a.count = cnt;
         a.round_lo = 0;
         a.nrounds = p->R;
-        a.raw = p->raw;
+        a.raw = p->raw + (uint64_t)off * p->R * 4 * p->Bmax;
         a.raw_rounds = p->R;
         HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
-    } else if (part == 1) {
-        HIP_TRY(launch_exact_decode(D, s));
     } else {
+        HIP_TRY(launch_exact_decode(D, s));
         HIP_TRY(launch_exact_finish(D, s));
+    }
+    return SFFT_OK;
+}
+
+// Chunks of a batch (default one).  Several chunks let the decode of chunk c
+// run beside the HashToBins of chunk c+1, but the decode is latency bound
+// and slows sharply next to a kernel that saturates HBM: measured at
+// 512 x 2^22, k = 256, one chunk 3.69 ms, two 4.17 ms, four 5.50 ms.
+// SFFT_BATCH_CHUNKS overrides the count.
+uint32_t batch_chunks(uint32_t count) {
+    const char* e = std::getenv("SFFT_BATCH_CHUNKS");
+    uint32_t c = e ? (uint32_t)std::atoi(e) : 1u;
+    return std::max(1u, std::min({c, kMaxChunks, count}));
+}
+
+sfft_status_t capture_part(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt, const void* x,
+                           const uint64_t* seeds, uint64_t* idx, double* val, uint32_t* ocnt, uint32_t* info,
+                           hipGraphExec_t* out) {
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+    sfft_status_t st = enqueue_chunk(p, part, off, cnt, x, seeds, idx, val, ocnt, info, p->capture_stream);
+    hipError_t ee = hipStreamEndCapture(p->capture_stream, &graph);
+    if (st != SFFT_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (ee != hipSuccess) return fail(SFFT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+    hipError_t ie = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+        *out = nullptr;
+        return fail(SFFT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     }
     return SFFT_OK;
 }
@@ -634,11 +738,18 @@ sfft_status_t sfft_plan_get_desc(sfft_plan_t p, sfft_plan_desc_t* out) {
 
 sfft_status_t sfft_destroy(sfft_plan_t p) {
     if (!p) return SFFT_OK;
-    for (auto& ge : p->graph.exec)
-        if (ge) (void)hipGraphExecDestroy(ge);
+    for (uint32_t c = 0; c < kMaxChunks; ++c) {
+        if (p->graph.exec_h[c]) (void)hipGraphExecDestroy(p->graph.exec_h[c]);
+        if (p->graph.exec_d[c]) (void)hipGraphExecDestroy(p->graph.exec_d[c]);
+    }
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
-    for (auto& e : p->ev)
-        if (e) (void)hipEventDestroy(e);
+    if (p->aux_stream) (void)hipStreamDestroy(p->aux_stream);
+    hipEvent_t* evs[] = {&p->ev_fork, &p->ev_join, &p->ev_t0, &p->ev_t1};
+    for (hipEvent_t* e : evs)
+        if (*e) (void)hipEventDestroy(*e);
+    for (uint32_t c = 0; c < kMaxChunks; ++c)
+        for (hipEvent_t e : {p->ev_ready[c], p->ev_h0[c], p->ev_h1[c], p->ev_d0[c], p->ev_d1[c]})
+            if (e) (void)hipEventDestroy(e);
     for (void* q : p->allocations) (void)hipFree(q);
     delete p;
     return SFFT_OK;
@@ -647,12 +758,22 @@ sfft_status_t sfft_destroy(sfft_plan_t p) {
 sfft_status_t sfft_plan_timings(sfft_plan_t p, double* ms_host, uint32_t n_out) {
     if (!p || !ms_host || n_out < 4) return fail(SFFT_EINVAL, "bad argument");
     if (!(p->d.flags & SFFT_FLAG_TIMING) || !p->timed_once) return fail(SFFT_EINVAL, "timing not enabled or nothing ran");
-    float ms[4];
-    HIP_TRY(hipEventElapsedTime(&ms[0], p->ev[0], p->ev[1]));
-    HIP_TRY(hipEventElapsedTime(&ms[1], p->ev[1], p->ev[2]));
-    HIP_TRY(hipEventElapsedTime(&ms[2], p->ev[2], p->ev[3]));
-    HIP_TRY(hipEventElapsedTime(&ms[3], p->ev[0], p->ev[3]));
-    for (int q = 0; q < 4; ++q) ms_host[q] = ms[q];
+    double h = 0.0, d = 0.0;
+    for (uint32_t c = 0; c < p->timed_chunks; ++c) {
+        float a = 0.f, b = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, p->ev_h0[c], p->ev_h1[c]));
+        HIP_TRY(hipEventElapsedTime(&b, p->ev_d0[c], p->ev_d1[c]));
+        h += a;
+        d += b;
+    }
+    float tail = 0.f, tot = 0.f;
+    HIP_TRY(hipEventElapsedTime(&tail, p->ev_h1[p->timed_chunks - 1], p->ev_t1));
+    HIP_TRY(hipEventElapsedTime(&tot, p->ev_t0, p->ev_t1));
+    ms_host[0] = h;
+    ms_host[1] = d;
+    ms_host[2] = tail;
+    ms_host[3] = tot;
+    if (n_out > 4) ms_host[4] = (double)p->timed_chunks;
     return SFFT_OK;
 }
 
@@ -807,35 +928,28 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
     const bool timing = (p->d.flags & SFFT_FLAG_TIMING) != 0;
     const char* nog = std::getenv("SFFT_NO_GRAPH");
     const bool use_graph = !(nog && nog[0] == '1');
+    const uint32_t C = batch_chunks(count);
+    const uint32_t per = (count + C - 1) / C;
     GraphCache& gc = p->graph;
     if (use_graph) {
-        const bool hit = gc.exec[0] && gc.x == x_dev && gc.count == count && gc.seeds == seeds_dev &&
-                         gc.o1 == idx_dev && gc.o2 == val_dev && gc.o3 == count_dev && gc.o4 == info_dev;
+        const bool hit = gc.exec_h[0] && gc.chunks == C && gc.x == x_dev && gc.count == count &&
+                         gc.seeds == seeds_dev && gc.o1 == idx_dev && gc.o2 == val_dev && gc.o3 == count_dev &&
+                         gc.o4 == info_dev;
         if (!hit) {
-            for (auto& ge : gc.exec)
-                if (ge) {
-                    HIP_TRY(hipGraphExecDestroy(ge));
-                    ge = nullptr;
-                }
-            for (int part = 0; part < 3; ++part) {
-                hipGraph_t graph = nullptr;
-                HIP_TRY(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
-                sfft_status_t st = enqueue_batch_part(p, part, x_dev, count, seeds_dev, idx_dev, val_dev,
-                                                      count_dev, info_dev, p->capture_stream);
-                hipError_t ee = hipStreamEndCapture(p->capture_stream, &graph);
-                if (st != SFFT_OK) {
-                    if (graph) (void)hipGraphDestroy(graph);
-                    return st;
-                }
-                if (ee != hipSuccess)
-                    return fail(SFFT_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
-                hipError_t ie = hipGraphInstantiate(&gc.exec[part], graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                if (ie != hipSuccess) {
-                    gc.exec[part] = nullptr;
-                    return fail(SFFT_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-                }
+            for (uint32_t c = 0; c < kMaxChunks; ++c) {
+                if (gc.exec_h[c]) HIP_TRY(hipGraphExecDestroy(gc.exec_h[c]));
+                if (gc.exec_d[c]) HIP_TRY(hipGraphExecDestroy(gc.exec_d[c]));
+                gc.exec_h[c] = gc.exec_d[c] = nullptr;
             }
+            gc.exec_h[0] = nullptr;
+            for (uint32_t c = 0; c < C; ++c) {
+                const uint32_t off = c * per, cnt = std::min(per, count - off);
+                ST_TRY(capture_part(p, 0, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
+                                    &gc.exec_h[c]));
+                ST_TRY(capture_part(p, 1, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
+                                    &gc.exec_d[c]));
+            }
+            gc.chunks = C;
             gc.x = x_dev;
             gc.count = count;
             gc.seeds = seeds_dev;
@@ -845,18 +959,36 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
             gc.o4 = info_dev;
         }
     }
-    for (int part = 0; part < 3; ++part) {
-        if (timing) HIP_TRY(hipEventRecord(p->ev[part], s));
+    // fork: the auxiliary stream follows everything already queued on s
+    if (timing) HIP_TRY(hipEventRecord(p->ev_t0, s));
+    HIP_TRY(hipEventRecord(p->ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0));
+    for (uint32_t c = 0; c < C; ++c) {
+        const uint32_t off = c * per, cnt = std::min(per, count - off);
+        if (timing) HIP_TRY(hipEventRecord(p->ev_h0[c], s));
         if (use_graph) {
-            HIP_TRY(hipGraphLaunch(gc.exec[part], s));
+            HIP_TRY(hipGraphLaunch(gc.exec_h[c], s));
         } else {
-            sfft_status_t st = enqueue_batch_part(p, part, x_dev, count, seeds_dev, idx_dev, val_dev, count_dev,
-                                                  info_dev, s);
-            if (st != SFFT_OK) return st;
+            ST_TRY(enqueue_chunk(p, 0, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev, s));
         }
+        if (timing) HIP_TRY(hipEventRecord(p->ev_h1[c], s));
+        HIP_TRY(hipEventRecord(p->ev_ready[c], s));
+        HIP_TRY(hipStreamWaitEvent(p->aux_stream, p->ev_ready[c], 0));
+        if (timing) HIP_TRY(hipEventRecord(p->ev_d0[c], p->aux_stream));
+        if (use_graph) {
+            HIP_TRY(hipGraphLaunch(gc.exec_d[c], p->aux_stream));
+        } else {
+            ST_TRY(enqueue_chunk(p, 1, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
+                                 p->aux_stream));
+        }
+        if (timing) HIP_TRY(hipEventRecord(p->ev_d1[c], p->aux_stream));
     }
+    // join: s waits for the last decode
+    HIP_TRY(hipEventRecord(p->ev_join, p->aux_stream));
+    HIP_TRY(hipStreamWaitEvent(s, p->ev_join, 0));
     if (timing) {
-        HIP_TRY(hipEventRecord(p->ev[3], s));
+        HIP_TRY(hipEventRecord(p->ev_t1, s));
+        p->timed_chunks = C;
         p->timed_once = true;
     }
     return SFFT_OK;

@@ -174,5 +174,6 @@ hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_
 hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s);
 
 size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64);
+size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax);
 
 }  // namespace sfft

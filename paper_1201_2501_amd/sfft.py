@@ -133,9 +133,10 @@ def sfft_destroy(plan):
 
 
 def sfft_plan_timings(plan):
-    """[h2b_ms, decode_ms, finish_ms, total_ms] of the last batched execute."""
-    out = np.zeros(4, dtype=np.float64)
-    _check(load().sfft_plan_timings(plan, out.ctypes.data_as(c_void_p), 4), "sfft_plan_timings")
+    """[hash_ms, decode_ms, tail_ms, total_ms, chunks] of the last batched execute
+    (hash/decode summed over the chunks of the batch)."""
+    out = np.zeros(5, dtype=np.float64)
+    _check(load().sfft_plan_timings(plan, out.ctypes.data_as(c_void_p), 5), "sfft_plan_timings")
     return out
 
 
