@@ -59,7 +59,8 @@ SFFT_HD uint64_t inverse_odd(uint64_t sigma) {
 
 // ------------------------------------------------------------ bin map -----
 // pi(i) = sigma (i - b) mod n; h = floor((pi B + n/2) / n) mod B (round half
-// up); o = pi - h_unwrapped n / B in [-n/(2B), n/(2B)).  Requires n B < 2^64.
+// up); o = pi - h_unwrapped n / B in [-n/(2B), n/(2B)).  n and B are powers of
+// two with B <= n and n B < 2^64, so both divisions are shifts.
 struct BinOffset {
     uint32_t h;
     int64_t o;
@@ -67,11 +68,12 @@ struct BinOffset {
 
 SFFT_HD BinOffset bin_offset(uint64_t i, uint64_t sigma, uint64_t b, uint64_t n, uint64_t B) {
     const uint64_t mask = n - 1;
+    const uint32_t ln = (uint32_t)__builtin_ctzll(n), lb = (uint32_t)__builtin_ctzll(B);
     const uint64_t pi = (sigma * ((i - b) & mask)) & mask;
-    const uint64_t hu = (pi * B + (n >> 1)) / n;
+    const uint64_t hu = ((pi << lb) + (n >> 1)) >> ln;
     BinOffset r;
     r.h = (uint32_t)(hu & (B - 1));
-    r.o = (int64_t)pi - (int64_t)(hu * (n / B));
+    r.o = (int64_t)pi - (int64_t)(hu << (ln - lb));
     return r;
 }
 
@@ -79,11 +81,14 @@ SFFT_HD BinOffset bin_offset(uint64_t i, uint64_t sigma, uint64_t b, uint64_t n,
 // G'_f of the flat window (Section 2 definition; Section 7 evaluation):
 // 1 for |f| <= (1 - alpha) n / (2B), 0 for |f| >= n / (2B), otherwise
 // Phi(sg (s + C)) - Phi(sg (s - C)) with s = |f| / n, evaluated as
-// [erfc(sg (s - C)/sqrt 2) - erfc(sg (s + C)/sqrt 2)] / 2.
+// [erfc(sg (s - C)/sqrt 2) - erfc(sg (s + C)/sqrt 2)] / 2.  two_term = 0
+// records that the second erfc is below 2^-60 of the first over the whole
+// transition band, so subtracting it cannot change the FP64 result.
 struct WindowShape {
     double sigma_g;
     double C;
     double alpha;
+    uint32_t two_term;
 };
 
 SFFT_HD double gprime(int64_t f, uint64_t n, uint64_t B, WindowShape ws) {
@@ -92,7 +97,8 @@ SFFT_HD double gprime(int64_t f, uint64_t n, uint64_t B, WindowShape ws) {
     if (af * 2 * B >= n) return 0.0;
     const double s = (double)af / (double)n;
     const double r2 = 1.4142135623730951;
-    return 0.5 * (erfc(ws.sigma_g * (s - ws.C) / r2) - erfc(ws.sigma_g * (s + ws.C) / r2));
+    const double lead = erfc(ws.sigma_g * (s - ws.C) / r2);
+    return 0.5 * (ws.two_term ? lead - erfc(ws.sigma_g * (s + ws.C) / r2) : lead);
 }
 
 SFFT_HD int64_t floordiv(int64_t a, int64_t b) {   // b > 0

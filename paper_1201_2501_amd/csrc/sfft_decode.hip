@@ -22,10 +22,16 @@ constexpr uint32_t kCandShift = 13;                        // candidate key: ind
 constexpr uint64_t kSlotMask = (1ull << kCandShift) - 1;
 constexpr uint64_t kFound = 1ull << 63;
 constexpr uint32_t kMaxMeas = 64;                          // medians over at most 64 values
-// One wave per signal: the decode is a chain of short dependent steps, so
-// its speed is set by barrier and memory latency, which a single-wave
-// workgroup keeps minimal; 512 signals fit on the chip at once.
-constexpr uint32_t kDec = 64;
+// Threads per signal.  The decode is a chain of short dependent steps; a
+// block of several waves spreads each step's bins and entries over more
+// SIMDs and hides the latency of one wave behind the others.
+#ifndef SFFT_DECODE_THREADS
+#define SFFT_DECODE_THREADS 256
+#endif
+constexpr uint32_t kDec = SFFT_DECODE_THREADS;
+static_assert(kDec % 64 == 0 && kDec <= 1024, "decode blocks are whole waves");
+constexpr uint32_t kUnroll = 4;                            // bins/entries per lane with loads in flight together
+constexpr size_t kLdsLimit = 160 * 1024;
 
 }  // namespace
 
@@ -38,8 +44,9 @@ struct DecodeLds {
     uint32_t* cnt;     // [Bmax]      bin counters (shares storage with nkey)
     uint64_t* ckey;    // [NK]        sort space
     uint64_t* nkey;    // [NK]        new zhat keys of a merge (shares storage with cnt)
-    uint32_t* scan;    // [kDec]
+    uint32_t* scan;    // [kDec / 64]
     uint32_t* misc;    // [8]
+    cx<double>* t;     // [capz][2]   per-entry terms of one hashing (LDS, or HBM when they do not fit)
 };
 
 __host__ __device__ inline uint32_t pow2_ceil_u32(uint32_t v) {
@@ -51,7 +58,9 @@ __host__ __device__ inline uint32_t pow2_ceil_u32(uint32_t v) {
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 // Bytes of the decode kernels' dynamic LDS; fills *L when base is given.
-__host__ __device__ inline size_t decode_lds_layout(uint32_t capz, uint32_t Bmax, unsigned char* base, DecodeLds* L) {
+// with_terms places the per-entry terms in LDS too.
+__host__ __device__ inline size_t decode_lds_layout(uint32_t capz, uint32_t Bmax, unsigned char* base, DecodeLds* L,
+                                                    bool with_terms) {
     const uint32_t NK = pow2_ceil_u32(capz > Bmax ? capz : Bmax);
     size_t off = 0;
     const size_t o_zl = off;
@@ -68,9 +77,11 @@ __host__ __device__ inline size_t decode_lds_layout(uint32_t capz, uint32_t Bmax
     const size_t ubytes = (size_t)NK * 8 > (size_t)Bmax * 4 ? (size_t)NK * 8 : (size_t)Bmax * 4;
     off = align16(off + ubytes);
     const size_t o_scan = off;
-    off = align16(off + kDec * 4);
+    off = align16(off + (kDec / 64) * 4);
     const size_t o_misc = off;
     off = align16(off + 8 * 4);
+    const size_t o_t = off;
+    if (with_terms) off = align16(off + (size_t)capz * 32);
     if (base) {
         L->zl = reinterpret_cast<uint64_t*>(base + o_zl);
         L->hk = reinterpret_cast<uint32_t*>(base + o_hk);
@@ -81,11 +92,58 @@ __host__ __device__ inline size_t decode_lds_layout(uint32_t capz, uint32_t Bmax
         L->nkey = reinterpret_cast<uint64_t*>(base + o_union);
         L->scan = reinterpret_cast<uint32_t*>(base + o_scan);
         L->misc = reinterpret_cast<uint32_t*>(base + o_misc);
+        L->t = with_terms ? reinterpret_cast<cx<double>*>(base + o_t) : nullptr;
     }
     return off;
 }
 
-size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax) { return decode_lds_layout(capz, Bmax, nullptr, nullptr); }
+__host__ __device__ inline bool terms_in_lds(uint32_t capz, uint32_t Bmax) {
+    return decode_lds_layout(capz, Bmax, nullptr, nullptr, true) <= kLdsLimit;
+}
+
+size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax) {
+    return decode_lds_layout(capz, Bmax, nullptr, nullptr, terms_in_lds(capz, Bmax));
+}
+
+// Lays out the dynamic LDS of one decode block; the terms go to the
+// signal's HBM scratch `spill` ([capz][2] complex) when LDS cannot hold them.
+__device__ __forceinline__ DecodeLds decode_lds(unsigned char* smem, uint32_t capz, uint32_t Bmax, double* spill) {
+    DecodeLds L;
+    const bool tl = terms_in_lds(capz, Bmax);
+    decode_lds_layout(capz, Bmax, smem, &L, tl);
+    if (!tl) L.t = reinterpret_cast<cx<double>*>(spill);
+    return L;
+}
+
+// Exclusive prefix sum of one value per thread of the block (kDec threads);
+// returns the block total.  Wave scans by lane shuffles, then one pass over
+// the per-wave totals.
+__device__ uint32_t wave_block_scan(uint32_t v, uint32_t* scratch, uint32_t* out_prefix) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    uint32_t inc = v;
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if constexpr (kDec == 64) {
+        __syncthreads();
+        *out_prefix = inc - v;
+        return __shfl(inc, 63, 64);
+    } else {
+        __syncthreads();
+        if (lane == 63) scratch[wave] = inc;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (uint32_t w = 0; w < kDec / 64; ++w) {
+            const uint32_t c = scratch[w];
+            before += w < wave ? c : 0u;
+            total += c;
+        }
+        *out_prefix = before + inc - v;
+        return total;
+    }
+}
 
 // Group entries e < zc by L.hk[e] < B: afterwards the entries of bin h are
 // L.ent[L.first[h] .. L.first[h + 1]) in ascending order of e.
@@ -101,7 +159,7 @@ __device__ void group_by_bin(DecodeLds& L, uint32_t zc, uint32_t B) {
     uint32_t local = 0;
     for (uint32_t h = h0; h < h1; ++h) local += L.cnt[h];
     uint32_t pre;
-    block_exclusive_scan<kDec>(local, L.scan, &pre);
+    wave_block_scan(local, L.scan, &pre);
     for (uint32_t h = h0; h < h1; ++h) {
         L.first[h] = pre;
         pre += L.cnt[h];
@@ -168,7 +226,7 @@ __device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv,
         }
     }
     uint32_t pre;
-    const uint32_t total = block_exclusive_scan<kDec>(fresh, L.scan, &pre);
+    const uint32_t total = wave_block_scan(fresh, L.scan, &pre);
     for (uint32_t q = q0; q < q1; ++q)
         if (!(L.ckey[q] & kFound)) L.nkey[pre++] = L.ckey[q];
     __syncthreads();
@@ -250,26 +308,54 @@ __device__ __forceinline__ double phase_of(cx<double> u, cx<double> u2) {
     return ph;
 }
 
-// Median of c values (real and imaginary parts separately; an even count
-// averages the two middle values).  Sorts re/im in place.
-__device__ cx<double> median_cx(double* re, double* im, uint32_t c) {
-    for (uint32_t q = 1; q < c; ++q) {
-        const double a = re[q], bq = im[q];
-        int32_t s = (int32_t)q - 1;
-        while (s >= 0 && re[s] > a) {
-            re[s + 1] = re[s];
-            --s;
+// Median of the c <= K values src[q * 2] (q < c) by a bitonic network on
+// registers; slots q >= c hold +inf and sort last.  An even count averages
+// the two middle values.
+template <uint32_t K>
+__device__ __forceinline__ double median_net(const double* src, uint32_t c) {
+    double a[K];
+#pragma unroll
+    for (uint32_t q = 0; q < K; ++q) a[q] = q < c ? src[2 * q] : __builtin_huge_val();
+#pragma unroll
+    for (uint32_t k = 2; k <= K; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (uint32_t i = 0; i < K; ++i) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const double lo = fmin(a[i], a[l]), hi = fmax(a[i], a[l]);
+                    const bool up = (i & k) == 0;
+                    a[i] = up ? lo : hi;
+                    a[l] = up ? hi : lo;
+                }
+            }
         }
-        re[s + 1] = a;
-        s = (int32_t)q - 1;
-        while (s >= 0 && im[s] > bq) {
-            im[s + 1] = im[s];
-            --s;
-        }
-        im[s + 1] = bq;
     }
-    if (c & 1) return {re[c / 2], im[c / 2]};
-    return {0.5 * (re[c / 2 - 1] + re[c / 2]), 0.5 * (im[c / 2 - 1] + im[c / 2])};
+    double m0 = 0.0, m1 = 0.0;
+#pragma unroll
+    for (uint32_t q = 0; q < K; ++q) {
+        if (q + 1 == c / 2) m0 = a[q];
+        if (q == c / 2) m1 = a[q];
+    }
+    return (c & 1) ? m1 : 0.5 * (m0 + m1);
+}
+
+// The 64-value network holds 128 VGPRs per part: kept out of line so that
+// its register demand stays out of the callers.
+__device__ __noinline__ cx<double> median_cx64(const double* src, uint32_t c) {
+    return {median_net<64>(src, c), median_net<64>(src + 1, c)};
+}
+
+// Median of c <= KMAX complex samples stored as (re, im) pairs, real and
+// imaginary parts separately.
+template <uint32_t KMAX>
+__device__ cx<double> median_cx(const double* src, uint32_t c) {
+    static_assert(KMAX == 32 || KMAX == 64, "median bound");
+    if (c <= 8) return {median_net<8>(src, c), median_net<8>(src + 1, c)};
+    if (c <= 16) return {median_net<16>(src, c), median_net<16>(src + 1, c)};
+    if (KMAX == 32 || c <= 32) return {median_net<32>(src, c), median_net<32>(src + 1, c)};
+    return median_cx64(src, c);
 }
 
 // Sort key ordering by |v| descending, then slot ascending (51 magnitude bits).
@@ -281,17 +367,13 @@ __device__ __forceinline__ uint64_t mag_key(double vr, double vi, uint32_t slot)
 
 // Median over the samples est[e][...]: the `na` isolated ones at the front
 // when there are any, else the `nb` others at the back.
+template <uint32_t KMAX>
 __device__ cx<double> entry_median(const double* est, uint32_t nmeas, uint32_t count_word, cx<double> fallback) {
     const uint32_t na = count_word & 0xFFFFu, nb = count_word >> 16;
     const uint32_t c = na ? na : nb;
     if (c == 0) return fallback;
     const uint32_t first = na ? 0u : nmeas - nb;
-    double re[kMaxMeas], im[kMaxMeas];
-    for (uint32_t q = 0; q < c; ++q) {
-        re[q] = est[(first + q) * 2];
-        im[q] = est[(first + q) * 2 + 1];
-    }
-    return median_cx(re, im, c);
+    return median_cx<KMAX>(est + 2 * first, c);
 }
 
 // Record one re-estimation sample of entry e: isolated samples from the
@@ -320,7 +402,7 @@ __device__ uint32_t write_output(DecodeLds& L, const uint64_t* zi, const double*
     for (uint32_t e = e0; e < e1; ++e)
         cnt += keep_all || sqrt(fin[2 * e] * fin[2 * e] + fin[2 * e + 1] * fin[2 * e + 1]) > half_theta;
     uint32_t pre;
-    const uint32_t nsurv = block_exclusive_scan<kDec>(cnt, L.scan, &pre);
+    const uint32_t nsurv = wave_block_scan(cnt, L.scan, &pre);
     uint32_t nout;
     if (nsurv <= cap) {
         for (uint32_t e = e0; e < e1; ++e) {
@@ -366,6 +448,62 @@ __device__ __forceinline__ const double* raw_bins(const DecodeArgs& D, uint32_t 
     return D.raw + (((uint64_t)sig * D.rounds + r) * 2 + a) * (uint64_t)D.Bmax * 2;
 }
 
+// Per-entry terms of HashToBins step 4 under (sigma, b, B): the bin hk[e]
+// of every staged entry, t[2e] = G'_{-o(i)} zhat_i and t[2e+1] =
+// t[2e] omega^{sigma i} (the same term under the hashing with a = 1); then
+// the entries are grouped by bin.
+__device__ void stage_terms(DecodeLds& L, uint32_t zc, const double* zv, uint64_t sigma, uint64_t b, uint64_t n,
+                            uint32_t B, const WindowShape& ws) {
+    const uint64_t mask = n - 1;
+    for (uint32_t e = threadIdx.x; e < zc; e += kDec) {
+        const uint64_t i = L.zl[e];
+        const BinOffset bo = bin_offset(i, sigma, b, n, B);
+        L.hk[e] = bo.h;
+        const double gp = gprime(-bo.o, n, B, ws);
+        const cx<double> c0{gp * zv[2 * e], gp * zv[2 * e + 1]};
+        L.t[2 * e] = c0;
+        L.t[2 * e + 1] = cmul(c0, omega_d((sigma * i) & mask, n));
+    }
+    __syncthreads();
+    group_by_bin(L, zc, B);
+}
+
+// Decode bin j of one round from its raw pair (u0, u1): subtract the zhat
+// terms of the bin in ascending index order, then, when |u0| > theta, the
+// phase of u1 / u0 names the frequency.  Returns whether |u0| > theta.
+__device__ __forceinline__ bool exact_bin(const DecodeArgs& D, DecodeLds& L, uint32_t j, double2 a0, double2 a1,
+                                          uint64_t sigma, uint64_t sinv, uint64_t b, uint64_t n, uint32_t B,
+                                          const WindowShape& ws, double* cv) {
+    const double two_pi = 6.283185307179586;
+    const uint64_t mask = n - 1;
+    double u0r = a0.x, u0i = a0.y, u1r = a1.x, u1i = a1.y;
+    for (uint32_t q = L.first[j]; q < L.first[j + 1]; ++q) {
+        const uint32_t e = L.ent[q];
+        const cx<double> c0 = L.t[2 * e], c1 = L.t[2 * e + 1];
+        u0r -= c0.r;
+        u0i -= c0.i;
+        u1r -= c1.r;
+        u1i -= c1.i;
+    }
+    const double mag = sqrt(u0r * u0r + u0i * u0i);
+    if (!(mag > D.theta)) return false;
+    const double zr = u0r * u1r + u0i * u1i;
+    const double zim = u0i * u1r - u0r * u1i;
+    double phi = atan2(zim, zr);
+    if (phi < 0.0) phi += two_pi;
+    const double qf = phi / two_pi * (double)n;
+    const uint64_t pos = ((uint64_t)floor(qf + 0.5)) & mask;
+    const uint64_t i = (sinv * pos) & mask;
+    const BinOffset bo = bin_offset(i, sigma, b, n, B);
+    if (bo.h != j) return true;
+    const double gp = gprime(-bo.o, n, B, ws);
+    if (!(gp >= D.g_min)) return true;
+    cv[2 * j] = u0r / gp;
+    cv[2 * j + 1] = u0i / gp;
+    L.ckey[atomicAdd(&L.misc[1], 1u)] = (i << kCandShift) | j;
+    return true;
+}
+
 // One round of NoiselessSparseFFTInner on signal `sig` (Algorithm 1).
 __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uint32_t r, uint64_t seed) {
     const uint32_t tid = threadIdx.x;
@@ -379,47 +517,30 @@ __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uin
     const uint32_t zc = stage_zhat(L, st, D.zidx, sig, D.capz);
     const double* zv = D.zval + ((uint64_t)sig * 2 + st[ST_ZBUF]) * D.capz * 2;
     double* cv = D.cand_v + (uint64_t)sig * D.Bmax * 2;
-    bin_zhat(L, zc, sigma, b, n, B);
+    stage_terms(L, zc, zv, sigma, b, n, B, g.ws);
     if (tid == 0) {
         L.misc[0] = 0;
         L.misc[1] = 0;
     }
     __syncthreads();
-    const double* r0 = raw_bins(D, sig, r, 0);
-    const double* r1 = raw_bins(D, sig, r, 1);
-    const double two_pi = 6.283185307179586;
+    const double2* r0 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 0));
+    const double2* r1 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 1));
     uint32_t myJ = 0;
-    for (uint32_t j = tid; j < B; j += kDec) {
-        double u0r = r0[2 * j], u0i = r0[2 * j + 1];
-        double u1r = r1[2 * j], u1i = r1[2 * j + 1];
-        for (uint32_t q = L.first[j]; q < L.first[j + 1]; ++q) {
-            const uint32_t e = L.ent[q];
-            const uint64_t i = L.zl[e];
-            const double gp = gprime(-bin_offset(i, sigma, b, n, B).o, n, B, g.ws);
-            const double c0r = gp * zv[2 * e], c0i = gp * zv[2 * e + 1];
-            const cx<double> c1 = cmul(cx<double>{c0r, c0i}, omega_d((sigma * i) & mask, n));
-            u0r -= c0r;
-            u0i -= c0i;
-            u1r -= c1.r;
-            u1i -= c1.i;
+    for (uint32_t j0 = tid; j0 < B; j0 += kUnroll * kDec) {
+        double2 a0[kUnroll], a1[kUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            const uint32_t j = j0 + u * kDec;
+            if (j < B) {
+                a0[u] = r0[j];
+                a1[u] = r1[j];
+            }
         }
-        const double mag = sqrt(u0r * u0r + u0i * u0i);
-        if (!(mag > D.theta)) continue;
-        ++myJ;
-        const double zr = u0r * u1r + u0i * u1i;
-        const double zim = u0i * u1r - u0r * u1i;
-        double phi = atan2(zim, zr);
-        if (phi < 0.0) phi += two_pi;
-        const double q = phi / two_pi * (double)n;
-        const uint64_t pos = ((uint64_t)floor(q + 0.5)) & mask;
-        const uint64_t i = (sinv * pos) & mask;
-        const BinOffset bo = bin_offset(i, sigma, b, n, B);
-        if (bo.h != j) continue;
-        const double gp = gprime(-bo.o, n, B, g.ws);
-        if (!(gp >= D.g_min)) continue;
-        cv[2 * j] = u0r / gp;
-        cv[2 * j + 1] = u0i / gp;
-        L.ckey[atomicAdd(&L.misc[1], 1u)] = (i << kCandShift) | j;
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            const uint32_t j = j0 + u * kDec;
+            if (j < B) myJ += exact_bin(D, L, j, a0[u], a1[u], sigma, sinv, b, n, B, g.ws, cv);
+        }
     }
     if (myJ) atomicAdd(&L.misc[0], myJ);
     __syncthreads();
@@ -454,9 +575,8 @@ __global__ void __launch_bounds__(kDec) k_exact_init(DecodeArgs D) {
 
 __global__ void __launch_bounds__(kDec) k_exact_decode(DecodeArgs D) {
     extern __shared__ __align__(16) unsigned char smem[];
-    DecodeLds L;
-    decode_lds_layout(D.capz, D.Bmax, smem, &L);
     const uint32_t sig = blockIdx.x;
+    DecodeLds L = decode_lds(smem, D.capz, D.Bmax, D.gtmp + (uint64_t)sig * D.capz * 4);
     const uint64_t seed = D.seeds ? D.seeds[sig] : D.plan_seed;
     const uint32_t* st = D.state + (uint64_t)sig * kStateWords;
     for (uint32_t r = D.r_begin; r < D.r_end; ++r) {
@@ -471,10 +591,9 @@ __global__ void __launch_bounds__(kDec) k_exact_decode(DecodeArgs D) {
 // where the entry is alone in its bin first), then the output.
 __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
     extern __shared__ __align__(16) unsigned char smem[];
-    DecodeLds L;
-    decode_lds_layout(D.capz, D.Bmax, smem, &L);
     const uint32_t tid = threadIdx.x;
     const uint32_t sig = blockIdx.x;
+    DecodeLds L = decode_lds(smem, D.capz, D.Bmax, D.gtmp + (uint64_t)sig * D.capz * 4);
     const uint64_t seed = D.seeds ? D.seeds[sig] : D.plan_seed;
     uint32_t* st = D.state + (uint64_t)sig * kStateWords;
     const uint64_t n = D.n;
@@ -485,7 +604,6 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
     const uint32_t nmeas = D.rounds;
     double* est = D.est + (uint64_t)sig * D.capz * nmeas * 2;
     uint32_t* ecount = D.ecount + (uint64_t)sig * D.capz;
-    double* gl = D.gtmp + (uint64_t)sig * D.capz;
     double* fin = D.fin + (uint64_t)sig * D.capz * 2;
     for (uint32_t e = tid; e < zc; e += kDec) ecount[e] = 0;
     for (uint32_t r = 0; r < R; ++r) {
@@ -494,33 +612,48 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
         const uint64_t sigma = draw_sigma(seed, n, r);
         const uint64_t b = draw_b(seed, n, r);
         __syncthreads();
+        // t[2e] = G' zhat_e, t[2e+1].r = G' of entry e
         for (uint32_t e = tid; e < zc; e += kDec) {
             const BinOffset bo = bin_offset(L.zl[e], sigma, b, n, B);
             L.hk[e] = bo.h;
-            gl[e] = gprime(-bo.o, n, B, g.ws);
+            const double gp = gprime(-bo.o, n, B, g.ws);
+            L.t[2 * e] = cx<double>{gp * zv[2 * e], gp * zv[2 * e + 1]};
+            L.t[2 * e + 1] = cx<double>{gp, 0.0};
         }
         __syncthreads();
         group_by_bin(L, zc, B);
-        const double* r0 = raw_bins(D, sig, r, 0);
-        for (uint32_t e = tid; e < zc; e += kDec) {
-            const double ge = gl[e];
-            if (ge < D.g_min) continue;
-            const uint32_t h = L.hk[e];
-            const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
-            double orr = 0.0, oii = 0.0;
-            for (uint32_t q = p0; q < p1; ++q) {
-                const uint32_t e2 = L.ent[q];
-                if (e2 == e) continue;
-                orr += gl[e2] * zv[2 * e2];
-                oii += gl[e2] * zv[2 * e2 + 1];
+        const double2* r0 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 0));
+        for (uint32_t e0 = tid; e0 < zc; e0 += kUnroll * kDec) {
+            double2 a0[kUnroll];
+#pragma unroll
+            for (uint32_t u = 0; u < kUnroll; ++u) {
+                const uint32_t e = e0 + u * kDec;
+                if (e < zc) a0[u] = r0[L.hk[e]];
             }
-            push_sample(est + (uint64_t)e * nmeas * 2, nmeas, &ecount[e], p1 - p0 == 1,
-                        cx<double>{(r0[2 * h] - orr) / ge, (r0[2 * h + 1] - oii) / ge});
+#pragma unroll
+            for (uint32_t u = 0; u < kUnroll; ++u) {
+                const uint32_t e = e0 + u * kDec;
+                if (e >= zc) continue;
+                const double ge = L.t[2 * e + 1].r;
+                if (ge < D.g_min) continue;
+                const uint32_t h = L.hk[e];
+                const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
+                double orr = 0.0, oii = 0.0;
+                for (uint32_t q = p0; q < p1; ++q) {
+                    const uint32_t e2 = L.ent[q];
+                    if (e2 == e) continue;
+                    const cx<double> c2 = L.t[2 * e2];
+                    orr += c2.r;
+                    oii += c2.i;
+                }
+                push_sample(est + (uint64_t)e * nmeas * 2, nmeas, &ecount[e], p1 - p0 == 1,
+                            cx<double>{(a0[u].x - orr) / ge, (a0[u].y - oii) / ge});
+            }
         }
     }
     __syncthreads();
     for (uint32_t e = tid; e < zc; e += kDec) {
-        const cx<double> v = entry_median(est + (uint64_t)e * nmeas * 2, nmeas, ecount[e],
+        const cx<double> v = entry_median<kMaxRounds>(est + (uint64_t)e * nmeas * 2, nmeas, ecount[e],
                                           cx<double>{zv[2 * e], zv[2 * e + 1]});
         fin[2 * e] = v.r;
         fin[2 * e + 1] = v.i;
@@ -631,7 +764,7 @@ __device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, 
         uint32_t cnt = 0;
         for (uint32_t p = p0; p < p1; ++p) cnt += (p == 0 || L.ckey[p] != L.ckey[p - 1]);
         uint32_t pre;
-        nL = block_exclusive_scan<kDec>(cnt, L.scan, &pre);
+        nL = wave_block_scan(cnt, L.scan, &pre);
         for (uint32_t p = p0; p < p1; ++p)
             if (p == 0 || L.ckey[p] != L.ckey[p - 1]) cand[pre++] = L.ckey[p];
         __syncthreads();
@@ -655,7 +788,7 @@ __device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, 
             const uint64_t p = (((a * sigma) & mask) * i) & mask;
             const cx<double> v = cmul(u, omega_d((n - p) & mask, n));
             const uint32_t k = candn[c];
-            double* dst = G.cand_e + (((uint64_t)sig * G.R_est + k) * G.Bmax + c) * 2;
+            double* dst = G.cand_e + (((uint64_t)sig * G.Bmax + c) * G.R_est + k) * 2;
             dst[0] = v.r / gp;
             dst[1] = v.i / gp;
             candn[c] = k + 1;
@@ -665,13 +798,7 @@ __device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, 
     for (uint32_t c = tid; c < nL; c += kDec) {
         const uint32_t k = candn[c];
         if (k == 0) continue;
-        double re[kMaxMeas], im[kMaxMeas];
-        for (uint32_t q = 0; q < k; ++q) {
-            const double* src = G.cand_e + (((uint64_t)sig * G.R_est + q) * G.Bmax + c) * 2;
-            re[q] = src[0];
-            im[q] = src[1];
-        }
-        const cx<double> med = median_cx(re, im, k);
+        const cx<double> med = median_cx<kMaxREst>(G.cand_e + (((uint64_t)sig * G.Bmax + c) * G.R_est) * 2, k);
         candv[2 * c] = med.r;
         candv[2 * c + 1] = med.i;
     }
@@ -708,9 +835,8 @@ __device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, 
 
 __global__ void __launch_bounds__(kDec) k_general_decode(GeneralArgs G, uint32_t r_begin, uint32_t r_end) {
     extern __shared__ __align__(16) unsigned char smem[];
-    DecodeLds L;
-    decode_lds_layout(G.capz, G.Bmax, smem, &L);
     const uint32_t sig = blockIdx.x;
+    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, G.gtmp + (uint64_t)sig * G.capz * 4);
     const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
     for (uint32_t r = r_begin; r < r_end; ++r) {
         __syncthreads();
@@ -723,10 +849,9 @@ __global__ void __launch_bounds__(kDec) k_general_decode(GeneralArgs G, uint32_t
 // ascending index order.
 __global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
     extern __shared__ __align__(16) unsigned char smem[];
-    DecodeLds L;
-    decode_lds_layout(G.capz, G.Bmax, smem, &L);
     const uint32_t tid = threadIdx.x;
     const uint32_t sig = blockIdx.x;
+    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, G.gtmp + (uint64_t)sig * G.capz * 4);
     const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
     uint32_t* st = G.state + (uint64_t)sig * kStateWords;
     const uint64_t n = G.n, mask = n - 1;
@@ -737,7 +862,6 @@ __global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
     const uint32_t nmeas = G.R * G.R_est;
     double* est = G.est + (uint64_t)sig * G.capz * nmeas * 2;
     uint32_t* ecount = G.ecount + (uint64_t)sig * G.capz;
-    double* gl = G.gtmp + (uint64_t)sig * G.capz;
     double* fin = G.fin + (uint64_t)sig * G.capz * 2;
     for (uint32_t e = tid; e < zc; e += kDec) ecount[e] = 0;
     for (uint32_t r = 0; r < R; ++r) {
@@ -751,15 +875,19 @@ __global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
             const double* rawv = gen_raw(G, sig, gr.slot0 + gr.nloc + m, 0);
             const uint64_t as = (a * sigma) & mask;
             __syncthreads();
+            // t[2e] = G' zhat_e omega^{a sigma i_e}, t[2e+1].r = G' of entry e
             for (uint32_t e = tid; e < zc; e += kDec) {
                 const BinOffset bo = bin_offset(L.zl[e], sigma, b, n, B);
                 L.hk[e] = bo.h;
-                gl[e] = gprime(-bo.o, n, B, g.ws);
+                const double gp = gprime(-bo.o, n, B, g.ws);
+                const cx<double> c0{gp * zv[2 * e], gp * zv[2 * e + 1]};
+                L.t[2 * e] = cmul(c0, omega_d((as * L.zl[e]) & mask, n));
+                L.t[2 * e + 1] = cx<double>{gp, 0.0};
             }
             __syncthreads();
             group_by_bin(L, zc, B);
             for (uint32_t e = tid; e < zc; e += kDec) {
-                const double ge = gl[e];
+                const double ge = L.t[2 * e + 1].r;
                 if (ge < G.g_min) continue;
                 const uint32_t h = L.hk[e];
                 const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
@@ -767,8 +895,7 @@ __global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
                 for (uint32_t q = p0; q < p1; ++q) {
                     const uint32_t e2 = L.ent[q];
                     if (e2 == e) continue;
-                    const cx<double> c0{gl[e2] * zv[2 * e2], gl[e2] * zv[2 * e2 + 1]};
-                    others = cadd(others, cmul(c0, omega_d((as * L.zl[e2]) & mask, n)));
+                    others = cadd(others, L.t[2 * e2]);
                 }
                 const cx<double> u = csub(cx<double>{rawv[2 * h], rawv[2 * h + 1]}, others);
                 const uint64_t pe = (as * L.zl[e]) & mask;
@@ -780,7 +907,7 @@ __global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
     }
     __syncthreads();
     for (uint32_t e = tid; e < zc; e += kDec) {
-        const cx<double> v = entry_median(est + (uint64_t)e * nmeas * 2, nmeas, ecount[e],
+        const cx<double> v = entry_median<kMaxMeas>(est + (uint64_t)e * nmeas * 2, nmeas, ecount[e],
                                           cx<double>{zv[2 * e], zv[2 * e + 1]});
         fin[2 * e] = v.r;
         fin[2 * e + 1] = v.i;

@@ -54,6 +54,12 @@ WindowShape window_shape(uint64_t n, uint64_t B, double alpha, double delta) {
     ws.sigma_g = (4.0 * (double)B / alpha) * std::sqrt(2.0 * std::log(3.0 / delta));
     ws.C = (1.0 - alpha / 2.0) / (2.0 * (double)B);
     ws.alpha = alpha;
+    // Over the transition band s < 1/(2B) the leading erfc is smallest at the
+    // band's edge and the trailing one largest at its start.
+    const double r2 = std::sqrt(2.0);
+    const double lead_min = std::erfc(ws.sigma_g * (0.5 / (double)B - ws.C) / r2);
+    const double tail_max = std::erfc(ws.sigma_g * ((1.0 - alpha) * 0.5 / (double)B + ws.C) / r2);
+    ws.two_term = !(tail_max < std::ldexp(lead_min, -60));
     return ws;
 }
 
@@ -345,7 +351,7 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     ST_TRY(dev_alloc(p, &p->zval, S * 4 * Z));
     ST_TRY(dev_alloc(p, &p->est, S * Z * meas * 2));
     ST_TRY(dev_alloc(p, &p->fin, S * Z * 2));
-    ST_TRY(dev_alloc(p, &p->gtmp, S * Z));
+    ST_TRY(dev_alloc(p, &p->gtmp, S * Z * 4));
     ST_TRY(dev_alloc(p, &p->ecount, S * Z));
     ST_TRY(dev_alloc(p, &p->state, S * kStateWords));
     // plain path (one signal): raw bins of every round, split partials
@@ -510,7 +516,7 @@ void offset_decode(const sfft_plan_s* p, DecodeArgs& D, uint32_t off) {
     D.zval += o * 4 * Z;
     D.est += o * Z * p->R * 2;
     D.fin += o * 2 * Z;
-    D.gtmp += o * Z;
+    D.gtmp += o * Z * 4;
     D.ecount += o * Z;
     D.state += o * kStateWords;
     if (D.seeds) D.seeds += o;
@@ -532,7 +538,7 @@ void offset_general(const sfft_plan_s* p, GeneralArgs& G, uint32_t off) {
     G.zval += o * 4 * Z;
     G.est += o * Z * meas * 2;
     G.fin += o * 2 * Z;
-    G.gtmp += o * Z;
+    G.gtmp += o * Z * 4;
     G.ecount += o * Z;
     G.state += o * kStateWords;
     if (G.seeds) G.seeds += o;
@@ -696,8 +702,8 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");
     if (d->mode == SFFT_MODE_GENERAL) {
         if (d->t < 4 || d->t > kMaxT || !is_pow2(d->t) || d->R_loc < 1 || d->R_loc > 255 || d->R_est < 1 ||
-            !(d->s > 0 && d->s < 1))
-            return fail(SFFT_EINVAL, "bad LocateInner/EstimateValues parameters (t a power of two in [4, 64])");
+            d->R_est > kMaxREst || !(d->s > 0 && d->s < 1))
+            return fail(SFFT_EINVAL, "bad LocateInner/EstimateValues parameters (t a power of two in [4, 64], R_est in [1, 32])");
         const uint32_t R = d->rounds ? d->rounds : 5;
         if ((uint64_t)R * d->R_est > 64) return fail(SFFT_EINVAL, "rounds * R_est must be at most 64");
         if (4ull * std::max<uint32_t>(d->k, 16u) > kMaxZ) return fail(SFFT_EUNSUPPORTED, "general mode needs k <= 1024");

@@ -43,6 +43,7 @@ struct RoundDev {
 constexpr uint32_t kMaxLevels = 24;
 constexpr uint32_t kFracBits = 8;          // fixed-point bits of region coordinates
 constexpr uint32_t kMaxT = 64;             // LocateInner regions per level
+constexpr uint32_t kMaxREst = 32;          // EstimateValues hashings per round
 
 // One SparseFFT round (Algorithm 2) of the general mode.
 struct GenRoundDev {
@@ -115,7 +116,7 @@ struct DecodeArgs {
     double* zval;              // [sig][2][capz][2]
     double* est;               // [sig][capz][rounds][2] re-estimation samples
     double* fin;               // [sig][capz][2] re-estimated values
-    double* gtmp;              // [sig][capz] window values of one round
+    double* gtmp;              // [sig][capz][4] per-entry terms when LDS cannot hold them
     uint32_t* ecount;          // [sig][capz] samples per entry
     uint32_t* state;           // [sig][kStateWords]
     double theta, g_min;
@@ -147,13 +148,13 @@ struct GeneralArgs {
     const double* raw;           // [sig][nslots][2][Bmax]
     uint64_t* cand_i;            // [sig][Bmax] located candidates
     double* cand_v;              // [sig][Bmax][2] estimates
-    double* cand_e;              // [sig][R_est][Bmax][2] per-measurement estimates
+    double* cand_e;              // [sig][Bmax][R_est][2] per-measurement estimates
     uint32_t* cand_n;            // [sig][Bmax] valid measurements per candidate
     uint64_t* zidx;              // [sig][2][capz]
     double* zval;                // [sig][2][capz][2]
     double* est;                 // [sig][capz][R * R_est][2]
     double* fin;                 // [sig][capz][2]
-    double* gtmp;                // [sig][capz]
+    double* gtmp;                // [sig][capz][4] per-entry terms when LDS cannot hold them
     uint32_t* ecount;            // [sig][capz]
     uint32_t* state;             // [sig][kStateWords]
     uint64_t* out_idx;
