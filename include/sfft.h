@@ -184,10 +184,14 @@ sfft_status_t sfft_execute(sfft_plan_t p, const void* x_dev, uint64_t* idx_host,
 
 /*
  * A batch of independent signals ("batched" path).  The batch runs as one
- * chunk (SFFT_BATCH_CHUNKS=c splits it into c); for each chunk one launch runs every hashing
- * round of every signal (HashToBins), and a decode workgroup per signal runs
- * the rounds on the device (exact: NoiselessSparseFFTInner; general:
- * SparseFFT) followed by the FP64 re-estimation and the output.  Chunk c's
+ * chunk (SFFT_BATCH_CHUNKS=c splits it into c).  For each chunk, one launch
+ * hashes every signal (HashToBins): general mode every round; exact mode the
+ * first round group (up to patience + 1 rounds past the first round at
+ * b_min bins).  A decode workgroup per signal runs the rounds on the device
+ * (exact: NoiselessSparseFFTInner; general: SparseFFT).  In exact mode each
+ * later group of two rounds is hashed, then decoded, only for signals whose
+ * decode has not stopped.  The FP64 re-estimation and the output follow.
+ * Chunk c's
  * decode runs on the plan's auxiliary stream while chunk c+1's HashToBins
  * runs on `stream`; `stream` waits for the last decode before the call's
  * work is complete.  Each chunk's launch sequences are captured once into
@@ -224,10 +228,13 @@ sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigm
  * Phase durations of the last sfft_execute_batch on a plan created with
  * SFFT_FLAG_TIMING, from HIP events recorded between the replayed graphs on
  * the streams they run on.  The caller must have synchronised the launch
- * stream.  ms_host[0] = HashToBins (state reset + pair kernel) summed over
- * the batch's chunks, [1] = decode + output summed over the chunks (these run
- * on the plan's auxiliary stream, overlapped with the next chunk's
- * HashToBins), [2] = time from the end of the last HashToBins to the end of
+ * stream.  ms_host[0] = state reset + the first HashToBins launch summed over
+ * the batch's chunks (exact mode: the first round group, hashed for every
+ * signal; general mode: every round), [1] = the rest summed over the chunks:
+ * decode, the HashToBins of later exact round groups (only for signals whose
+ * decode has not stopped), re-estimation and output (these run on the plan's
+ * auxiliary stream, overlapped with the next chunk's first HashToBins),
+ * [2] = time from the end of the last first-launch HashToBins to the end of
  * the batch, [3] = whole batch (milliseconds); [4] (if n_out > 4) = number of
  * chunks.  Errors: SFFT_EINVAL when the flag is not set or nothing ran yet,
  * SFFT_EHIP.
@@ -235,12 +242,23 @@ sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigm
 sfft_status_t sfft_plan_timings(sfft_plan_t p, double* ms_host, uint32_t n_out);
 
 /*
- * Algorithmic HBM bytes of one batched HashToBins launch for `count`
- * signals: every distinct input sample read once per hashing pair
- * ((w_r + 1) samples of in_dtype per round) plus the raw bins written
- * (2 B_r complex128 per round).  Pure host function.
+ * Algorithmic HBM bytes of the first batched HashToBins launch for `count`
+ * signals (exact mode: the rounds of the first round group, which every
+ * signal hashes; general mode: every round): every distinct input sample
+ * read once per hashing pair ((w_r + 1) samples of in_dtype per round) plus
+ * the raw bins written (2 B_r complex128 per round).  Pure host function.
  */
 uint64_t sfft_plan_h2b_bytes(sfft_plan_t p, uint32_t count);
+
+/*
+ * Round groups of the batched exact path: ends_host[g] = one past the last
+ * round of group g (ascending, the last equals the plan's rounds).  Group 0
+ * is hashed for every signal; each later group only for signals whose decode
+ * has not stopped.  Writes min(*n_groups, max) ends and sets *n_groups to the
+ * number of groups (general mode: one group of every round).  Pure host
+ * function.  Errors: SFFT_EINVAL for NULL p or n_groups.
+ */
+sfft_status_t sfft_plan_round_groups(sfft_plan_t p, uint32_t* ends_host, uint32_t max, uint32_t* n_groups);
 
 /*
  * Copy the raw bins of one hashing slot of one signal from the batched

@@ -31,23 +31,30 @@ constexpr uint32_t kMaxMeas = 64;                          // medians over at mo
 constexpr uint32_t kDec = SFFT_DECODE_THREADS;
 static_assert(kDec % 64 == 0 && kDec <= 1024, "decode blocks are whole waves");
 constexpr uint32_t kUnroll = 4;                            // bins/entries per lane with loads in flight together
-constexpr size_t kLdsLimit = 160 * 1024;
+constexpr size_t kLdsLimit = 160 * 1024;                  // per CU
+constexpr size_t kLdsTarget = kLdsLimit / 2;               // optional parts keep two decode blocks per CU
 
 }  // namespace
 
 // ------------------------------------------------------------- LDS layout --
 struct DecodeLds {
     uint64_t* zl;      // [capz]      indices of the current zhat buffer
-    uint32_t* hk;      // [capz]      bin of each zhat entry under the current hashing
-    uint32_t* ent;     // [capz]      zhat entries grouped by bin, ascending within a bin
+    uint64_t* zl2;     // [capz]      the next zhat indices, written by a merge (nullptr: restage from HBM)
+    uint16_t* hk;      // [capz]      bin of each zhat entry under the current hashing (B <= 4096)
+    uint16_t* ent;     // [capz]      zhat entries grouped by bin, ascending within a bin (capz <= 4096)
     uint32_t* first;   // [Bmax + 1]  first grouped position of each bin
     uint32_t* cnt;     // [Bmax]      bin counters (shares storage with nkey)
     uint64_t* ckey;    // [NK]        sort space
     uint64_t* nkey;    // [NK]        new zhat keys of a merge (shares storage with cnt)
     uint32_t* scan;    // [kDec / 64]
     uint32_t* misc;    // [8]
+    uint32_t* sw;      // [kStateWords] the signal's decode state while a kernel runs
     cx<double>* t;     // [capz][2]   per-entry terms of one hashing (LDS, or HBM when they do not fit)
+    uint32_t* ec;      // [capz]      re-estimation sample counts (LDS, or HBM when they do not fit)
 };
+
+// Optional LDS parts, placed in this order while they fit.
+enum : uint32_t { LDS_TERMS = 1, LDS_ZL2 = 2, LDS_EC = 4 };
 
 __host__ __device__ inline uint32_t pow2_ceil_u32(uint32_t v) {
     uint32_t p = 1;
@@ -57,18 +64,18 @@ __host__ __device__ inline uint32_t pow2_ceil_u32(uint32_t v) {
 
 __host__ __device__ inline size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-// Bytes of the decode kernels' dynamic LDS; fills *L when base is given.
-// with_terms places the per-entry terms in LDS too.
+// Bytes of the decode kernels' dynamic LDS with the optional parts `parts`;
+// fills *L when base is given (absent parts left nullptr).
 __host__ __device__ inline size_t decode_lds_layout(uint32_t capz, uint32_t Bmax, unsigned char* base, DecodeLds* L,
-                                                    bool with_terms) {
+                                                    uint32_t parts) {
     const uint32_t NK = pow2_ceil_u32(capz > Bmax ? capz : Bmax);
     size_t off = 0;
     const size_t o_zl = off;
     off = align16(off + (size_t)capz * 8);
     const size_t o_hk = off;
-    off = align16(off + (size_t)capz * 4);
+    off = align16(off + (size_t)capz * 2);
     const size_t o_ent = off;
-    off = align16(off + (size_t)capz * 4);
+    off = align16(off + (size_t)capz * 2);
     const size_t o_first = off;
     off = align16(off + ((size_t)Bmax + 1) * 4);
     const size_t o_ckey = off;
@@ -80,39 +87,65 @@ __host__ __device__ inline size_t decode_lds_layout(uint32_t capz, uint32_t Bmax
     off = align16(off + (kDec / 64) * 4);
     const size_t o_misc = off;
     off = align16(off + 8 * 4);
+    const size_t o_sw = off;
+    off = align16(off + kStateWords * 4);
     const size_t o_t = off;
-    if (with_terms) off = align16(off + (size_t)capz * 32);
+    if (parts & LDS_TERMS) off = align16(off + (size_t)capz * 32);
+    const size_t o_zl2 = off;
+    if (parts & LDS_ZL2) off = align16(off + (size_t)capz * 8);
+    const size_t o_ec = off;
+    if (parts & LDS_EC) off = align16(off + (size_t)capz * 4);
     if (base) {
         L->zl = reinterpret_cast<uint64_t*>(base + o_zl);
-        L->hk = reinterpret_cast<uint32_t*>(base + o_hk);
-        L->ent = reinterpret_cast<uint32_t*>(base + o_ent);
+        L->hk = reinterpret_cast<uint16_t*>(base + o_hk);
+        L->ent = reinterpret_cast<uint16_t*>(base + o_ent);
         L->first = reinterpret_cast<uint32_t*>(base + o_first);
         L->ckey = reinterpret_cast<uint64_t*>(base + o_ckey);
         L->cnt = reinterpret_cast<uint32_t*>(base + o_union);
         L->nkey = reinterpret_cast<uint64_t*>(base + o_union);
         L->scan = reinterpret_cast<uint32_t*>(base + o_scan);
         L->misc = reinterpret_cast<uint32_t*>(base + o_misc);
-        L->t = with_terms ? reinterpret_cast<cx<double>*>(base + o_t) : nullptr;
+        L->sw = reinterpret_cast<uint32_t*>(base + o_sw);
+        L->t = (parts & LDS_TERMS) ? reinterpret_cast<cx<double>*>(base + o_t) : nullptr;
+        L->zl2 = (parts & LDS_ZL2) ? reinterpret_cast<uint64_t*>(base + o_zl2) : nullptr;
+        L->ec = (parts & LDS_EC) ? reinterpret_cast<uint32_t*>(base + o_ec) : nullptr;
     }
     return off;
 }
 
-__host__ __device__ inline bool terms_in_lds(uint32_t capz, uint32_t Bmax) {
-    return decode_lds_layout(capz, Bmax, nullptr, nullptr, true) <= kLdsLimit;
+// The optional parts placed in LDS, in priority order, while two blocks
+// still fit on a CU (512 signals resident at once on 256 CUs).
+__host__ __device__ inline uint32_t decode_lds_parts(uint32_t capz, uint32_t Bmax) {
+    uint32_t parts = 0;
+    for (uint32_t p : {(uint32_t)LDS_TERMS, (uint32_t)LDS_ZL2, (uint32_t)LDS_EC})
+        if (decode_lds_layout(capz, Bmax, nullptr, nullptr, parts | p) <= kLdsTarget) parts |= p;
+    return parts;
 }
 
 size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax) {
-    return decode_lds_layout(capz, Bmax, nullptr, nullptr, terms_in_lds(capz, Bmax));
+    return decode_lds_layout(capz, Bmax, nullptr, nullptr, decode_lds_parts(capz, Bmax));
 }
 
-// Lays out the dynamic LDS of one decode block; the terms go to the
-// signal's HBM scratch `spill` ([capz][2] complex) when LDS cannot hold them.
-__device__ __forceinline__ DecodeLds decode_lds(unsigned char* smem, uint32_t capz, uint32_t Bmax, double* spill) {
+// Lays out the dynamic LDS of one decode block.  Terms that do not fit go
+// to the signal's HBM scratch `spill` ([capz][2] complex), sample counts to
+// `ec_spill` ([capz]).
+__device__ __forceinline__ DecodeLds decode_lds(unsigned char* smem, uint32_t capz, uint32_t Bmax, double* spill,
+                                                uint32_t* ec_spill) {
     DecodeLds L;
-    const bool tl = terms_in_lds(capz, Bmax);
-    decode_lds_layout(capz, Bmax, smem, &L, tl);
-    if (!tl) L.t = reinterpret_cast<cx<double>*>(spill);
+    decode_lds_layout(capz, Bmax, smem, &L, decode_lds_parts(capz, Bmax));
+    if (!L.t) L.t = reinterpret_cast<cx<double>*>(spill);
+    if (!L.ec) L.ec = ec_spill;
     return L;
+}
+
+// The signal's state words into LDS (start of a kernel) and back (end).
+__device__ __forceinline__ void load_state(DecodeLds& L, const uint32_t* st) {
+    if (threadIdx.x < kStateWords) L.sw[threadIdx.x] = st[threadIdx.x];
+    __syncthreads();
+}
+__device__ __forceinline__ void store_state(const DecodeLds& L, uint32_t* st) {
+    __syncthreads();
+    if (threadIdx.x < kStateWords) st[threadIdx.x] = L.sw[threadIdx.x];
 }
 
 // Exclusive prefix sum of one value per thread of the block (kDec threads);
@@ -168,19 +201,25 @@ __device__ void group_by_bin(DecodeLds& L, uint32_t zc, uint32_t B) {
     __syncthreads();
     for (uint32_t h = tid; h < B; h += kDec) L.cnt[h] = L.first[h];
     __syncthreads();
-    for (uint32_t e = tid; e < zc; e += kDec) L.ent[atomicAdd(&L.cnt[L.hk[e]], 1u)] = e;
+    for (uint32_t e = tid; e < zc; e += kDec) L.ent[atomicAdd(&L.cnt[L.hk[e]], 1u)] = (uint16_t)e;
     __syncthreads();
-    for (uint32_t h = tid; h < B; h += kDec) {
+    // The atomic scatter leaves each bin in arbitrary order: every grouped
+    // position ranks its entry within its bin's segment (entries are
+    // distinct) and the entries are rewritten in ascending order.  The
+    // targets pass through the candidate key space, idle while grouping.
+    uint32_t* move = reinterpret_cast<uint32_t*>(L.ckey);
+    for (uint32_t q = tid; q < zc; q += kDec) {
+        const uint32_t v = L.ent[q];
+        const uint32_t h = L.hk[v];
         const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
-        for (uint32_t q = p0 + 1; q < p1; ++q) {
-            const uint32_t v = L.ent[q];
-            uint32_t s = q;
-            while (s > p0 && L.ent[s - 1] > v) {
-                L.ent[s] = L.ent[s - 1];
-                --s;
-            }
-            L.ent[s] = v;
-        }
+        uint32_t rank = 0;
+        for (uint32_t q2 = p0; q2 < p1; ++q2) rank += L.ent[q2] < v;
+        move[q] = ((p0 + rank) << 16) | v;
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < zc; q += kDec) {
+        const uint32_t mv = move[q];
+        L.ent[mv >> 16] = (uint16_t)(mv & 0xFFFFu);
     }
     __syncthreads();
 }
@@ -200,10 +239,10 @@ __device__ __forceinline__ uint32_t lower_bound_lds(const uint64_t* a, uint32_t 
 // becomes current.  Expects L.zl to hold the current indices.  Returns the
 // number of new entries.
 __device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv, uint64_t* zidx_all, double* zval_all,
-                                     uint32_t sig, uint32_t capz, uint32_t* st) {
+                                     uint32_t sig, uint32_t capz) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t zc = st[ST_ZCOUNT];
-    const uint32_t zb = st[ST_ZBUF];
+    const uint32_t zc = L.sw[ST_ZCOUNT];
+    const uint32_t zb = L.sw[ST_ZBUF];
     double* zv = zval_all + ((uint64_t)sig * 2 + zb) * capz * 2;
     const uint32_t NM = pow2_ceil_u32(m > 0 ? m : 1);
     for (uint32_t q = m + tid; q < NM; q += kDec) L.ckey[q] = kNone;
@@ -233,10 +272,11 @@ __device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv,
     uint32_t mnew = total;
     if (zc + mnew > capz) {
         mnew = capz - zc;
-        if (tid == 0) st[ST_FLAGS] |= 2u;
+        if (tid == 0) L.sw[ST_FLAGS] |= 2u;
     }
     uint64_t* zo = zidx_all + ((uint64_t)sig * 2 + (zb ^ 1)) * capz;
     double* zov = zval_all + ((uint64_t)sig * 2 + (zb ^ 1)) * capz * 2;
+    uint64_t* zl2 = L.zl2;
     for (uint32_t e = tid; e < zc; e += kDec) {
         const uint64_t i = L.zl[e];
         uint32_t lo = 0, hi = mnew;
@@ -246,6 +286,7 @@ __device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv,
         }
         const uint32_t pos = e + lo;
         zo[pos] = i;
+        if (zl2) zl2[pos] = i;
         zov[2 * pos] = zv[2 * e];
         zov[2 * pos + 1] = zv[2 * e + 1];
     }
@@ -254,30 +295,43 @@ __device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv,
         const uint32_t j = (uint32_t)(L.nkey[q] & kSlotMask);
         const uint32_t pos = q + lower_bound_lds(L.zl, zc, i);
         zo[pos] = i;
+        if (zl2) zl2[pos] = i;
         zov[2 * pos] = cv[2 * j];
         zov[2 * pos + 1] = cv[2 * j + 1];
     }
     __syncthreads();
     if (tid == 0) {
-        st[ST_ZCOUNT] = zc + mnew;
-        st[ST_ZBUF] = zb ^ 1;
+        L.sw[ST_ZCOUNT] = zc + mnew;
+        L.sw[ST_ZBUF] = zb ^ 1;
+    }
+    if (zl2) {
+        L.zl2 = L.zl;
+        L.zl = zl2;
     }
     __syncthreads();
     return mnew;
 }
 
-// Stage the current zhat indices into LDS; returns zc.
-__device__ uint32_t stage_zhat(DecodeLds& L, const uint32_t* st, const uint64_t* zidx_all, uint32_t sig, uint32_t capz) {
-    const uint32_t zc = st[ST_ZCOUNT];
-    const uint64_t* zi = zidx_all + ((uint64_t)sig * 2 + st[ST_ZBUF]) * capz;
+// Stage the current zhat indices (named by the LDS state words) into LDS;
+// returns zc.
+__device__ uint32_t stage_zhat(DecodeLds& L, const uint64_t* zidx_all, uint32_t sig, uint32_t capz) {
+    const uint32_t zc = L.sw[ST_ZCOUNT];
+    const uint64_t* zi = zidx_all + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * capz;
     for (uint32_t e = threadIdx.x; e < zc; e += kDec) L.zl[e] = zi[e];
     __syncthreads();
     return zc;
 }
 
+// zc at the start of a round: L.zl is current when merges keep it in LDS,
+// otherwise it is staged again.
+__device__ __forceinline__ uint32_t round_zhat(DecodeLds& L, const uint64_t* zidx_all, uint32_t sig, uint32_t capz) {
+    if (L.zl2) return L.sw[ST_ZCOUNT];
+    return stage_zhat(L, zidx_all, sig, capz);
+}
+
 // Bins of every staged entry under (sigma, b, B), grouped.
 __device__ void bin_zhat(DecodeLds& L, uint32_t zc, uint64_t sigma, uint64_t b, uint64_t n, uint32_t B) {
-    for (uint32_t e = threadIdx.x; e < zc; e += kDec) L.hk[e] = bin_offset(L.zl[e], sigma, b, n, B).h;
+    for (uint32_t e = threadIdx.x; e < zc; e += kDec) L.hk[e] = (uint16_t)bin_offset(L.zl[e], sigma, b, n, B).h;
     __syncthreads();
     group_by_bin(L, zc, B);
 }
@@ -451,19 +505,28 @@ __device__ __forceinline__ const double* raw_bins(const DecodeArgs& D, uint32_t 
 // Per-entry terms of HashToBins step 4 under (sigma, b, B): the bin hk[e]
 // of every staged entry, t[2e] = G'_{-o(i)} zhat_i and t[2e+1] =
 // t[2e] omega^{sigma i} (the same term under the hashing with a = 1); then
-// the entries are grouped by bin.
-__device__ void stage_terms(DecodeLds& L, uint32_t zc, const double* zv, uint64_t sigma, uint64_t b, uint64_t n,
-                            uint32_t B, const WindowShape& ws) {
-    const uint64_t mask = n - 1;
-    for (uint32_t e = threadIdx.x; e < zc; e += kDec) {
-        const uint64_t i = L.zl[e];
-        const BinOffset bo = bin_offset(i, sigma, b, n, B);
-        L.hk[e] = bo.h;
-        const double gp = gprime(-bo.o, n, B, ws);
-        const cx<double> c0{gp * zv[2 * e], gp * zv[2 * e + 1]};
-        L.t[2 * e] = c0;
-        L.t[2 * e + 1] = cmul(c0, omega_d((sigma * i) & mask, n));
+// the entries are grouped by bin.  zp holds zhat of this lane's first
+// kUnroll entries (e = tid + u kDec), loaded ahead by the caller.
+__device__ __forceinline__ void term_entry(DecodeLds& L, uint32_t e, double2 z, uint64_t sigma, uint64_t b,
+                                           uint64_t n, uint32_t B, const WindowShape& ws) {
+    const uint64_t i = L.zl[e];
+    const BinOffset bo = bin_offset(i, sigma, b, n, B);
+    L.hk[e] = (uint16_t)bo.h;
+    const double gp = gprime(-bo.o, n, B, ws);
+    const cx<double> c0{gp * z.x, gp * z.y};
+    L.t[2 * e] = c0;
+    L.t[2 * e + 1] = cmul(c0, omega_d((sigma * i) & (n - 1), n));
+}
+
+__device__ void stage_terms(DecodeLds& L, uint32_t zc, const double2 (&zp)[kUnroll], const double2* zv2,
+                            uint64_t sigma, uint64_t b, uint64_t n, uint32_t B, const WindowShape& ws) {
+    const uint32_t tid = threadIdx.x;
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+        const uint32_t e = tid + u * kDec;
+        if (e < zc) term_entry(L, e, zp[u], sigma, b, n, B, ws);
     }
+    for (uint32_t e = tid + kUnroll * kDec; e < zc; e += kDec) term_entry(L, e, zv2[e], sigma, b, n, B, ws);
     __syncthreads();
     group_by_bin(L, zc, B);
 }
@@ -504,7 +567,9 @@ __device__ __forceinline__ bool exact_bin(const DecodeArgs& D, DecodeLds& L, uin
     return true;
 }
 
-// One round of NoiselessSparseFFTInner on signal `sig` (Algorithm 1).
+// One round of NoiselessSparseFFTInner on signal `sig` (Algorithm 1).  The
+// HBM loads of the round (this lane's first raw bins and zhat values) are
+// issued first, so that their latency overlaps the staging.
 __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uint32_t r, uint64_t seed) {
     const uint32_t tid = threadIdx.x;
     const RoundDev g = D.geom[r];
@@ -513,21 +578,38 @@ __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uin
     const uint64_t sigma = draw_sigma(seed, n, r);
     const uint64_t b = draw_b(seed, n, r);
     const uint64_t sinv = inverse_odd(sigma) & mask;
-    uint32_t* st = D.state + (uint64_t)sig * kStateWords;
-    const uint32_t zc = stage_zhat(L, st, D.zidx, sig, D.capz);
-    const double* zv = D.zval + ((uint64_t)sig * 2 + st[ST_ZBUF]) * D.capz * 2;
-    double* cv = D.cand_v + (uint64_t)sig * D.Bmax * 2;
-    stage_terms(L, zc, zv, sigma, b, n, B, g.ws);
+    const double2* r0 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 0));
+    const double2* r1 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 1));
+    double2 a0[kUnroll], a1[kUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+        const uint32_t j = tid + u * kDec;
+        if (j < B) {
+            a0[u] = r0[j];
+            a1[u] = r1[j];
+        }
+    }
+    const uint32_t zc = round_zhat(L, D.zidx, sig, D.capz);
+    const double2* zv2 = reinterpret_cast<const double2*>(D.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * D.capz * 2);
+    double2 zp[kUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+        const uint32_t e = tid + u * kDec;
+        if (e < zc) zp[u] = zv2[e];
+    }
     if (tid == 0) {
         L.misc[0] = 0;
         L.misc[1] = 0;
     }
-    __syncthreads();
-    const double2* r0 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 0));
-    const double2* r1 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 1));
+    double* cv = D.cand_v + (uint64_t)sig * D.Bmax * 2;
+    stage_terms(L, zc, zp, zv2, sigma, b, n, B, g.ws);
     uint32_t myJ = 0;
-    for (uint32_t j0 = tid; j0 < B; j0 += kUnroll * kDec) {
-        double2 a0[kUnroll], a1[kUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+        const uint32_t j = tid + u * kDec;
+        if (j < B) myJ += exact_bin(D, L, j, a0[u], a1[u], sigma, sinv, b, n, B, g.ws, cv);
+    }
+    for (uint32_t j0 = tid + kUnroll * kDec; j0 < B; j0 += kUnroll * kDec) {
 #pragma unroll
         for (uint32_t u = 0; u < kUnroll; ++u) {
             const uint32_t j = j0 + u * kDec;
@@ -545,23 +627,24 @@ __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uin
     if (myJ) atomicAdd(&L.misc[0], myJ);
     __syncthreads();
     const uint32_t J = L.misc[0], m = L.misc[1];
+    uint32_t* sw = L.sw;
     if (J == 0) {
         if (tid == 0) {
-            st[ST_EMPTY] += 1;
-            if (st[ST_EMPTY] >= D.patience) st[ST_DONE] = 1;
-            st[ST_ROUNDS] = r + 1;
-            st[ST_LASTJ] = 0;
-            st[ST_ACCEPT] = 0;
+            sw[ST_EMPTY] += 1;
+            if (sw[ST_EMPTY] >= D.patience) sw[ST_DONE] = 1;
+            sw[ST_ROUNDS] = r + 1;
+            sw[ST_LASTJ] = 0;
+            sw[ST_ACCEPT] = 0;
         }
         __syncthreads();
         return;
     }
-    const uint32_t mnew = merge_candidates(L, m, cv, D.zidx, D.zval, sig, D.capz, st);
+    const uint32_t mnew = merge_candidates(L, m, cv, D.zidx, D.zval, sig, D.capz);
     if (tid == 0) {
-        st[ST_EMPTY] = 0;
-        st[ST_ROUNDS] = r + 1;
-        st[ST_LASTJ] = J;
-        st[ST_ACCEPT] = mnew;
+        sw[ST_EMPTY] = 0;
+        sw[ST_ROUNDS] = r + 1;
+        sw[ST_LASTJ] = J;
+        sw[ST_ACCEPT] = mnew;
     }
     __syncthreads();
 }
@@ -576,14 +659,18 @@ __global__ void __launch_bounds__(kDec) k_exact_init(DecodeArgs D) {
 __global__ void __launch_bounds__(kDec) k_exact_decode(DecodeArgs D) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t sig = blockIdx.x;
-    DecodeLds L = decode_lds(smem, D.capz, D.Bmax, D.gtmp + (uint64_t)sig * D.capz * 4);
+    DecodeLds L = decode_lds(smem, D.capz, D.Bmax, D.gtmp + (uint64_t)sig * D.capz * 4, D.ecount + (uint64_t)sig * D.capz);
     const uint64_t seed = D.seeds ? D.seeds[sig] : D.plan_seed;
-    const uint32_t* st = D.state + (uint64_t)sig * kStateWords;
+    uint32_t* st = D.state + (uint64_t)sig * kStateWords;
+    load_state(L, st);
+    if (L.sw[ST_DONE]) return;
+    stage_zhat(L, D.zidx, sig, D.capz);
     for (uint32_t r = D.r_begin; r < D.r_end; ++r) {
         __syncthreads();
-        if (st[ST_DONE]) break;
+        if (L.sw[ST_DONE]) break;
         exact_round(D, L, sig, r, seed);
     }
+    store_state(L, st);
 }
 
 // Final FP64 re-estimation of every zhat entry over the decoded rounds
@@ -593,19 +680,36 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x;
     const uint32_t sig = blockIdx.x;
-    DecodeLds L = decode_lds(smem, D.capz, D.Bmax, D.gtmp + (uint64_t)sig * D.capz * 4);
+    DecodeLds L = decode_lds(smem, D.capz, D.Bmax, D.gtmp + (uint64_t)sig * D.capz * 4, D.ecount + (uint64_t)sig * D.capz);
     const uint64_t seed = D.seeds ? D.seeds[sig] : D.plan_seed;
     uint32_t* st = D.state + (uint64_t)sig * kStateWords;
     const uint64_t n = D.n;
-    const uint32_t R = st[ST_ROUNDS];
-    const uint32_t zc = stage_zhat(L, st, D.zidx, sig, D.capz);
-    const uint64_t* zi = D.zidx + ((uint64_t)sig * 2 + st[ST_ZBUF]) * D.capz;
-    const double* zv = D.zval + ((uint64_t)sig * 2 + st[ST_ZBUF]) * D.capz * 2;
+    load_state(L, st);
+    const uint32_t R = L.sw[ST_ROUNDS];
+    const uint32_t zc = stage_zhat(L, D.zidx, sig, D.capz);
+    const uint64_t* zi = D.zidx + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * D.capz;
+    const double* zv = D.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * D.capz * 2;
+    const double2* zv2 = reinterpret_cast<const double2*>(zv);
     const uint32_t nmeas = D.rounds;
     double* est = D.est + (uint64_t)sig * D.capz * nmeas * 2;
-    uint32_t* ecount = D.ecount + (uint64_t)sig * D.capz;
     double* fin = D.fin + (uint64_t)sig * D.capz * 2;
-    for (uint32_t e = tid; e < zc; e += kDec) ecount[e] = 0;
+    for (uint32_t e = tid; e < zc; e += kDec) L.ec[e] = 0;
+    // zhat of this lane's first entries (fixed), and their raw bins of round 0
+    double2 zp[kUnroll], pre[kUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+        const uint32_t e = tid + u * kDec;
+        if (e < zc) zp[u] = zv2[e];
+    }
+    if (R > 0) {
+        const uint64_t sigma = draw_sigma(seed, n, 0), b = draw_b(seed, n, 0);
+        const double2* r0 = reinterpret_cast<const double2*>(raw_bins(D, sig, 0, 0));
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            const uint32_t e = tid + u * kDec;
+            if (e < zc) pre[u] = r0[bin_offset(L.zl[e], sigma, b, n, D.geom[0].B).h];
+        }
+    }
     for (uint32_t r = 0; r < R; ++r) {
         const RoundDev g = D.geom[r];
         const uint32_t B = g.B;
@@ -613,53 +717,63 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
         const uint64_t b = draw_b(seed, n, r);
         __syncthreads();
         // t[2e] = G' zhat_e, t[2e+1].r = G' of entry e
-        for (uint32_t e = tid; e < zc; e += kDec) {
+        auto stage = [&](uint32_t e, double2 z) {
             const BinOffset bo = bin_offset(L.zl[e], sigma, b, n, B);
-            L.hk[e] = bo.h;
+            L.hk[e] = (uint16_t)bo.h;
             const double gp = gprime(-bo.o, n, B, g.ws);
-            L.t[2 * e] = cx<double>{gp * zv[2 * e], gp * zv[2 * e + 1]};
+            L.t[2 * e] = cx<double>{gp * z.x, gp * z.y};
             L.t[2 * e + 1] = cx<double>{gp, 0.0};
-        }
+        };
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u)
+            if (tid + u * kDec < zc) stage(tid + u * kDec, zp[u]);
+        for (uint32_t e = tid + kUnroll * kDec; e < zc; e += kDec) stage(e, zv2[e]);
         __syncthreads();
         group_by_bin(L, zc, B);
         const double2* r0 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 0));
-        for (uint32_t e0 = tid; e0 < zc; e0 += kUnroll * kDec) {
-            double2 a0[kUnroll];
+        double2 cur[kUnroll];
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) cur[u] = pre[u];
+        if (r + 1 < R) {   // next round's raw bins, in flight during this round's work
+            const uint64_t sn = draw_sigma(seed, n, r + 1), bn = draw_b(seed, n, r + 1);
+            const uint32_t Bn = D.geom[r + 1].B;
+            const double2* rn = reinterpret_cast<const double2*>(raw_bins(D, sig, r + 1, 0));
 #pragma unroll
             for (uint32_t u = 0; u < kUnroll; ++u) {
-                const uint32_t e = e0 + u * kDec;
-                if (e < zc) a0[u] = r0[L.hk[e]];
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kUnroll; ++u) {
-                const uint32_t e = e0 + u * kDec;
-                if (e >= zc) continue;
-                const double ge = L.t[2 * e + 1].r;
-                if (ge < D.g_min) continue;
-                const uint32_t h = L.hk[e];
-                const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
-                double orr = 0.0, oii = 0.0;
-                for (uint32_t q = p0; q < p1; ++q) {
-                    const uint32_t e2 = L.ent[q];
-                    if (e2 == e) continue;
-                    const cx<double> c2 = L.t[2 * e2];
-                    orr += c2.r;
-                    oii += c2.i;
-                }
-                push_sample(est + (uint64_t)e * nmeas * 2, nmeas, &ecount[e], p1 - p0 == 1,
-                            cx<double>{(a0[u].x - orr) / ge, (a0[u].y - oii) / ge});
+                const uint32_t e = tid + u * kDec;
+                if (e < zc) pre[u] = rn[bin_offset(L.zl[e], sn, bn, n, Bn).h];
             }
         }
+        auto sample = [&](uint32_t e, double2 a0) {
+            const double ge = L.t[2 * e + 1].r;
+            if (ge < D.g_min) return;
+            const uint32_t h = L.hk[e];
+            const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
+            double orr = 0.0, oii = 0.0;
+            for (uint32_t q = p0; q < p1; ++q) {
+                const uint32_t e2 = L.ent[q];
+                if (e2 == e) continue;
+                const cx<double> c2 = L.t[2 * e2];
+                orr += c2.r;
+                oii += c2.i;
+            }
+            push_sample(est + (uint64_t)e * nmeas * 2, nmeas, &L.ec[e], p1 - p0 == 1,
+                        cx<double>{(a0.x - orr) / ge, (a0.y - oii) / ge});
+        };
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u)
+            if (tid + u * kDec < zc) sample(tid + u * kDec, cur[u]);
+        for (uint32_t e = tid + kUnroll * kDec; e < zc; e += kDec) sample(e, r0[L.hk[e]]);
     }
     __syncthreads();
     for (uint32_t e = tid; e < zc; e += kDec) {
-        const cx<double> v = entry_median<kMaxRounds>(est + (uint64_t)e * nmeas * 2, nmeas, ecount[e],
-                                          cx<double>{zv[2 * e], zv[2 * e + 1]});
+        const cx<double> v = entry_median<kMaxRounds>(est + (uint64_t)e * nmeas * 2, nmeas, L.ec[e],
+                                                      cx<double>{zv[2 * e], zv[2 * e + 1]});
         fin[2 * e] = v.r;
         fin[2 * e + 1] = v.i;
     }
     __syncthreads();
-    uint32_t flags = st[ST_FLAGS];
+    uint32_t flags = L.sw[ST_FLAGS];
     const uint32_t nout = write_output(L, zi, fin, zc, false, 0.5 * D.theta, D.cap, D.out_scale,
                                        D.out_idx + (uint64_t)sig * D.cap, D.out_val + (uint64_t)sig * D.cap * 2,
                                        &flags);
@@ -687,9 +801,8 @@ __device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, 
     const GenRoundDev& gr = G.groundv[r];
     const uint64_t n = G.n, mask = n - 1;
     const uint32_t B = g.B;
-    uint32_t* st = G.state + (uint64_t)sig * kStateWords;
-    const uint32_t zc = stage_zhat(L, st, G.zidx, sig, G.capz);
-    const double* zv = G.zval + ((uint64_t)sig * 2 + st[ST_ZBUF]) * G.capz * 2;
+    const uint32_t zc = round_zhat(L, G.zidx, sig, G.capz);
+    const double* zv = G.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * G.capz * 2;
     uint64_t* cand = G.cand_i + (uint64_t)sig * G.Bmax;
     double* candv = G.cand_v + (uint64_t)sig * G.Bmax * 2;
     uint32_t* candn = G.cand_n + (uint64_t)sig * G.Bmax;
@@ -825,10 +938,10 @@ __device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, 
         L.ckey[q] = (cand[c] << kCandShift) | c;
     }
     __syncthreads();
-    merge_candidates(L, take, candv, G.zidx, G.zval, sig, G.capz, st);
+    merge_candidates(L, take, candv, G.zidx, G.zval, sig, G.capz);
     if (tid == 0) {
-        st[ST_ROUNDS] = r + 1;
-        st[ST_LASTJ] = nL;
+        L.sw[ST_ROUNDS] = r + 1;
+        L.sw[ST_LASTJ] = nL;
     }
     __syncthreads();
 }
@@ -836,12 +949,16 @@ __device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, 
 __global__ void __launch_bounds__(kDec) k_general_decode(GeneralArgs G, uint32_t r_begin, uint32_t r_end) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t sig = blockIdx.x;
-    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, G.gtmp + (uint64_t)sig * G.capz * 4);
+    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, G.gtmp + (uint64_t)sig * G.capz * 4, G.ecount + (uint64_t)sig * G.capz);
     const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
+    uint32_t* st = G.state + (uint64_t)sig * kStateWords;
+    load_state(L, st);
+    stage_zhat(L, G.zidx, sig, G.capz);
     for (uint32_t r = r_begin; r < r_end; ++r) {
         __syncthreads();
         general_round(G, L, sig, r, seed);
     }
+    store_state(L, st);
 }
 
 // FP64 re-estimation over every EstimateValues hashing of every round
@@ -851,17 +968,18 @@ __global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x;
     const uint32_t sig = blockIdx.x;
-    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, G.gtmp + (uint64_t)sig * G.capz * 4);
+    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, G.gtmp + (uint64_t)sig * G.capz * 4, G.ecount + (uint64_t)sig * G.capz);
     const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
     uint32_t* st = G.state + (uint64_t)sig * kStateWords;
     const uint64_t n = G.n, mask = n - 1;
-    const uint32_t R = st[ST_ROUNDS];
-    const uint32_t zc = stage_zhat(L, st, G.zidx, sig, G.capz);
-    const uint64_t* zi = G.zidx + ((uint64_t)sig * 2 + st[ST_ZBUF]) * G.capz;
-    const double* zv = G.zval + ((uint64_t)sig * 2 + st[ST_ZBUF]) * G.capz * 2;
+    load_state(L, st);
+    const uint32_t R = L.sw[ST_ROUNDS];
+    const uint32_t zc = stage_zhat(L, G.zidx, sig, G.capz);
+    const uint64_t* zi = G.zidx + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * G.capz;
+    const double* zv = G.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * G.capz * 2;
     const uint32_t nmeas = G.R * G.R_est;
     double* est = G.est + (uint64_t)sig * G.capz * nmeas * 2;
-    uint32_t* ecount = G.ecount + (uint64_t)sig * G.capz;
+    uint32_t* ecount = L.ec;
     double* fin = G.fin + (uint64_t)sig * G.capz * 2;
     for (uint32_t e = tid; e < zc; e += kDec) ecount[e] = 0;
     for (uint32_t r = 0; r < R; ++r) {
@@ -878,7 +996,7 @@ __global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
             // t[2e] = G' zhat_e omega^{a sigma i_e}, t[2e+1].r = G' of entry e
             for (uint32_t e = tid; e < zc; e += kDec) {
                 const BinOffset bo = bin_offset(L.zl[e], sigma, b, n, B);
-                L.hk[e] = bo.h;
+                L.hk[e] = (uint16_t)bo.h;
                 const double gp = gprime(-bo.o, n, B, g.ws);
                 const cx<double> c0{gp * zv[2 * e], gp * zv[2 * e + 1]};
                 L.t[2 * e] = cmul(c0, omega_d((as * L.zl[e]) & mask, n));
@@ -913,7 +1031,7 @@ __global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
         fin[2 * e + 1] = v.i;
     }
     __syncthreads();
-    uint32_t flags = st[ST_FLAGS];
+    uint32_t flags = L.sw[ST_FLAGS];
     const uint32_t nout = write_output(L, zi, fin, zc, true, 0.0, G.cap, G.out_scale,
                                        G.out_idx + (uint64_t)sig * G.cap, G.out_val + (uint64_t)sig * G.cap * 2,
                                        &flags);
@@ -921,9 +1039,9 @@ __global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
         G.out_count[sig] = nout;
         if (G.out_info) {
             G.out_info[(uint64_t)sig * 4 + SFFT_INFO_ROUNDS] = R;
-            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_FLAGS] = st[ST_FLAGS];
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_FLAGS] = L.sw[ST_FLAGS];
             G.out_info[(uint64_t)sig * 4 + SFFT_INFO_ZHAT] = zc;
-            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_LOCATED] = st[ST_LASTJ];
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_LOCATED] = L.sw[ST_LASTJ];
         }
     }
 }

@@ -126,6 +126,9 @@ struct sfft_plan_s {
     sfft_plan_desc_t d;
     int device = 0;
     uint32_t R = 0;            // rounds with geometry
+    // exact batched mode: ends of the round groups.  Group 0 is hashed for
+    // every signal; each later group only for signals still decoding.
+    std::vector<uint32_t> group_end;
     uint32_t Bmax = 0;
     uint32_t logBmax = 0;
     uint32_t capz = 0;
@@ -302,6 +305,24 @@ sfft_status_t build_plan(sfft_plan_s* p) {
         p->mcap = std::max<uint32_t>(p->mcap, (uint32_t)(Lhi - Llo + 1));
         if (general_mode(p)) p->mcap = std::max<uint32_t>(p->mcap, (uint32_t)(2 * (g.w / g.B) + 4));
         p->geom.push_back(g);
+    }
+    // Round groups of the batched exact path: a signal stops at the earliest
+    // `patience` rounds after the first round at the smallest bin count, so
+    // group 0 runs to there; later groups take 2, 2, 4, 8, ... rounds (few
+    // signals need the long tail, and every group costs two launches).
+    if (!general_mode(p)) {
+        uint32_t first_floor = p->R;
+        for (uint32_t r = 0; r < p->R; ++r)
+            if (r + 1 == p->R || p->geom[r + 1].B == p->geom[r].B) {
+                first_floor = r;
+                break;
+            }
+        uint32_t e = std::min<uint32_t>(p->R, first_floor + d.patience + 1);
+        p->group_end.push_back(e);
+        for (uint32_t g = 1; e < p->R; ++g) {
+            e = std::min<uint32_t>(p->R, e + (g <= 2 ? 2u : 1u << (g - 1)));
+            p->group_end.push_back(e);
+        }
     }
     std::vector<float> g32(g64.begin(), g64.end());
     // twiddles exp(-2 pi i m / Bmax), m < Bmax
@@ -571,20 +592,33 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
         }
         return SFFT_OK;
     }
+    H2BArgs a = base_h2b(p, xc);
+    a.seeds = sc;
+    a.count = cnt;
+    a.raw = p->raw + (uint64_t)off * p->R * 4 * p->Bmax;
+    a.raw_rounds = p->R;
     if (part == 0) {
         HIP_TRY(launch_exact_init(D, s));
-        H2BArgs a = base_h2b(p, xc);
-        a.seeds = sc;
-        a.count = cnt;
         a.round_lo = 0;
-        a.nrounds = p->R;
-        a.raw = p->raw + (uint64_t)off * p->R * 4 * p->Bmax;
-        a.raw_rounds = p->R;
+        a.nrounds = p->group_end[0];
         HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
-    } else {
-        HIP_TRY(launch_exact_decode(D, s));
-        HIP_TRY(launch_exact_finish(D, s));
+        return SFFT_OK;
     }
+    a.state = D.state;
+    uint32_t r0 = 0;
+    for (size_t g = 0; g < p->group_end.size(); ++g) {
+        const uint32_t r1 = p->group_end[g];
+        if (g > 0) {
+            a.round_lo = r0;
+            a.nrounds = r1 - r0;
+            HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
+        }
+        D.r_begin = r0;
+        D.r_end = r1;
+        HIP_TRY(launch_exact_decode(D, s));
+        r0 = r1;
+    }
+    HIP_TRY(launch_exact_finish(D, s));
     return SFFT_OK;
 }
 
@@ -807,9 +841,21 @@ sfft_status_t sfft_plan_raw_slot(sfft_plan_t p, uint32_t sig, uint32_t slot, dou
 uint64_t sfft_plan_h2b_bytes(sfft_plan_t p, uint32_t count) {
     if (!p) return 0;
     const uint64_t s_in = p->d.in_dtype == SFFT_C128 ? 16 : 8;
+    // exact mode: the first launch covers round group 0; general mode: every round
+    const uint32_t R = p->group_end.empty() ? p->R : p->group_end[0];
     uint64_t per = 0;
-    for (const RoundDev& g : p->geom) per += (g.w + 1) * s_in + 2ull * g.B * 16ull;
+    for (uint32_t r = 0; r < R; ++r) per += (p->geom[r].w + 1) * s_in + 2ull * p->geom[r].B * 16ull;
     return per * count;
+}
+
+sfft_status_t sfft_plan_round_groups(sfft_plan_t p, uint32_t* ends_host, uint32_t max, uint32_t* n_groups) {
+    if (!p || !n_groups) return fail(SFFT_EINVAL, "NULL argument");
+    std::vector<uint32_t> ends = p->group_end;
+    if (ends.empty()) ends.push_back(p->R);
+    for (uint32_t g = 0; g < ends.size() && g < max; ++g)
+        if (ends_host) ends_host[g] = ends[g];
+    *n_groups = (uint32_t)ends.size();
+    return SFFT_OK;
 }
 
 sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigma, uint64_t a, uint64_t beta,

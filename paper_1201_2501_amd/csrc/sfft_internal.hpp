@@ -94,6 +94,9 @@ struct H2BArgs {
     const GenRoundDev* groundv;
     uint32_t R_loc;
     uint32_t njobs;
+    // exact batched mode: when set, blocks of signals whose decode has
+    // stopped (state word ST_DONE) return before gathering
+    const uint32_t* state;     // [sig][kStateWords] or nullptr
 };
 
 struct DecodeArgs {

@@ -16,6 +16,12 @@
 
 namespace sfft {
 
+// Samples each thread keeps in flight in the gather loop.
+#ifndef SFFT_GATHER_UNROLL
+#define SFFT_GATHER_UNROLL 4
+#endif
+constexpr int kGatherUnroll = SFFT_GATHER_UNROLL;
+
 // In-place radix-2 decimation-in-frequency FFT of VA and VB (B points each,
 // natural-order input, bit-reversed output), unnormalised, sign -:
 // X_j = sum_r V_r exp(-2 pi i j r / B).  tw holds exp(-2 pi i m / Bmax),
@@ -107,7 +113,7 @@ __device__ void accumulate_pair(const TIn* __restrict__ x, const TA* __restrict_
             TA aAr = 0, aAi = 0, aBr = 0, aBi = 0;
             const cx<TA>* Mp = M + (L0 - Llo);
             const int64_t cnt = L1 - L0 + 1;
-#pragma unroll 4
+#pragma unroll kGatherUnroll
             for (int64_t q = 0; q < cnt; ++q) {
                 const TIn xv = x[idx];
                 const int64_t uA = tA - t0;
@@ -213,6 +219,9 @@ __global__ void __launch_bounds__(kThreads) k_h2b_pair(H2BArgs A) {
     } else {
         const uint32_t rr = blockIdx.x / A.count;
         sig = blockIdx.x - rr * A.count;
+        // the method stops a signal after `patience` empty rounds: its later
+        // hashings are never decoded
+        if (A.state && A.state[(uint64_t)sig * kStateWords + ST_DONE]) return;
         r = A.round_lo + rr;
         ro = r;
         const uint64_t seed = A.seeds ? A.seeds[sig] : A.plan_seed;

@@ -25,7 +25,8 @@ INFO_ROUNDS, INFO_FLAGS, INFO_ZHAT, INFO_LOCATED = range(4)
 # every symbol declared in include/sfft.h
 EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_plan_ex", "sfft_plan",
            "sfft_plan_get_desc", "sfft_destroy", "sfft_execute", "sfft_execute_batch",
-           "sfft_hash_pair_raw", "sfft_plan_timings", "sfft_plan_h2b_bytes", "sfft_plan_raw_slot",
+           "sfft_hash_pair_raw", "sfft_plan_timings", "sfft_plan_h2b_bytes", "sfft_plan_round_groups",
+           "sfft_plan_raw_slot",
            "sfft_status_string",
            "sfft_last_error", "sfft_splitmix64"]
 
@@ -66,6 +67,7 @@ def load():
     lib.sfft_plan_timings.argtypes = [P, P, c_uint32]
     lib.sfft_plan_h2b_bytes.argtypes = [P, c_uint32]
     lib.sfft_plan_h2b_bytes.restype = c_uint64
+    lib.sfft_plan_round_groups.argtypes = [P, POINTER(c_uint32), c_uint32, POINTER(c_uint32)]
     lib.sfft_plan_raw_slot.argtypes = [P, c_uint32, c_uint32, P, P, P]
     lib.sfft_status_string.argtypes = [c_int32]
     lib.sfft_status_string.restype = c_char_p
@@ -142,6 +144,16 @@ def sfft_plan_timings(plan):
 
 def sfft_plan_h2b_bytes(plan, count):
     return int(load().sfft_plan_h2b_bytes(plan, count))
+
+
+def sfft_plan_round_groups(plan):
+    """Ends of the batched round groups (list of ints)."""
+    lib = load()
+    ng = c_uint32(0)
+    _check(lib.sfft_plan_round_groups(plan, None, 0, ctypes.byref(ng)), "sfft_plan_round_groups")
+    ends = (c_uint32 * max(1, ng.value))()
+    _check(lib.sfft_plan_round_groups(plan, ends, ng.value, ctypes.byref(ng)), "sfft_plan_round_groups")
+    return [int(e) for e in ends[:ng.value]]
 
 
 def sfft_plan_raw_slot(plan, sig, slot, out, stream=None):
@@ -272,6 +284,9 @@ class Plan:
 
     def h2b_bytes(self, count):
         return sfft_plan_h2b_bytes(self.handle, count)
+
+    def round_groups(self):
+        return sfft_plan_round_groups(self.handle)
 
     def hash_pair_raw(self, x, sigma, a, beta, b, B_r, prec=SFFT_F64, stream=None):
         import torch

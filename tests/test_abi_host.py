@@ -86,3 +86,12 @@ def test_default_window_matches_oracle_definition(n, B, alpha, delta):
 
 def test_status_strings():
     assert sfft.sfft_status_string(sfft.SFFT_ETRUNC) == "SFFT_ETRUNC"
+
+
+def test_plan_queries_reject_null_plan():
+    import ctypes
+    lib = sfft.load()
+    ng = ctypes.c_uint32(99)
+    assert lib.sfft_plan_round_groups(None, None, 0, ctypes.byref(ng)) == sfft.SFFT_EINVAL
+    assert ng.value == 99
+    assert lib.sfft_plan_h2b_bytes(None, 4) == 0

@@ -201,15 +201,19 @@ def test_zero_signal_and_truncation(torch_dev):
     compare(idx, v, ref)
 
 
-@pytest.mark.parametrize("seed", range(3))
-def test_c3_shape_matches_oracle(torch_dev, seed):
+@pytest.mark.parametrize("seed,sched", [(0, "default"), (1, "default"), (2, "tuned"), (3, "tuned")])
+def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     """n = 2^22, k = 256, log-uniform magnitudes, complex64, FP64 location
-    decoding: the bench's plan parameters on a few signals."""
+    decoding; the default schedule (b_min = B/16, 16 rounds) and the bench's
+    tuned one (b_min = 32, 24 rounds) on a few signals."""
     torch, dev = torch_dev
     n, k, B = 1 << 22, 256, 1024
     w = default_w(n, B, 0.5, 1e-9)
-    say("c3-shape", "n", n, "k", k, "B", B, "w", w, "seed", seed)
-    plan = plan_for(n, k, B, w, 0, delta=1e-9, theta=0.02, loc_prec=1, max_batch=2)
+    kw = {} if sched == "default" else dict(b_min=32, rounds=24)
+    say("c3-shape", sched, "n", n, "k", k, "B", B, "w", w, "seed", seed)
+    plan = plan_for(n, k, B, w, 0, delta=1e-9, theta=0.02, loc_prec=1, max_batch=2, **kw)
+    if sched == "tuned":
+        assert plan.round_groups() == [9, 11, 13, 17, 24]
     xs, sups, seeds = [], [], []
     for s in range(2):
         x, sup, val = siggen.planted_signal(n, k, 300 + 2 * seed + s, np.complex64, magnitude="loguniform")
@@ -219,6 +223,34 @@ def test_c3_shape_matches_oracle(torch_dev, seed):
     out = run_batch(torch, dev, plan, xs, seeds)
     for s in range(2):
         ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        assert int(out[s][2][0]) == ref.rounds_used
         compare(out[s][0], out[s][1], ref)
         assert np.array_equal(out[s][0], sups[s])
+    plan.close()
+
+
+def test_c3_round_groups_skip_only_undecoded_rounds(torch_dev):
+    """The batched exact path hashes round group 0 for every signal and each
+    later group only for signals still decoding: a batch whose signals stop
+    in different groups still matches the oracle signal by signal."""
+    torch, dev = torch_dev
+    n, k, B = 1 << 22, 256, 1024
+    w = default_w(n, B, 0.5, 1e-9)
+    count = 6
+    say("c3-round-groups", "n", n, "k", k, "count", count)
+    plan = plan_for(n, k, B, w, 0, delta=1e-9, theta=0.02, loc_prec=1, max_batch=count)
+    # the schedule 1024, 512, 256, 128, 64, 64, ... reaches b_min at round 4;
+    # patience 3 => group 0 ends at round 8, then groups of 2, 2, 4 rounds
+    assert plan.round_groups() == [8, 10, 12, 16]
+    xs = [siggen.planted_signal(n, k, 1_000_003 + s, np.complex64, magnitude="loguniform")[0]
+          for s in range(count)]
+    seeds = [s * 7919 + 12345 for s in range(count)]
+    out = run_batch(torch, dev, plan, xs, seeds)
+    used = []
+    for s in range(count):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        assert int(out[s][2][0]) == ref.rounds_used
+        compare(out[s][0], out[s][1], ref)
+        used.append(ref.rounds_used)
+    assert len({next(e for e in [8, 10, 12, 16] if e >= r) for r in used}) >= 2, used
     plan.close()
