@@ -3,10 +3,11 @@
 
 Workload (one step): a batch of 512 independent exactly-sparse signals,
 n = 2^22, k = 256, complex64 storage, log-uniform |coefficient| in [0.1, 10],
-uniform phases, each signal with its own seed; every hashing round of every
-signal runs through the batched path (one HashToBins launch for all rounds of
-all signals, device decode loop, FP64 re-estimation), replayed from a
-hipGraph.  Inputs are resident in HBM before the timed region.
+uniform phases, each signal with its own seed, through the batched path: one
+HashToBins launch for the first round group of every signal, the device decode
+loop, HashToBins of later round groups for the signals still decoding, FP64
+re-estimation; replayed from hipGraphs.  Inputs are resident in HBM before the
+timed region.
 
 Printed: ONE JSON line with the batched sFFTs/s as `value`, plus the plain
 one-signal-at-a-time path, a dense full-length FFT + top-k on the same GPU
@@ -16,7 +17,6 @@ event-timed duration), sampled parity against the FP64 oracle, and the oracle
 itself timed on the host (cpu_baseline).
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -29,22 +29,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from paper_1201_2501_amd.prof import kernel_source_hash  # noqa: E402
+
 METRIC = "sFFTs/s at n=2^22,k=256 (batched vs plain), HBM GB/s, p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "h2b_pair_c3_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1201_2501_amd", "csrc", f)
-                  for f in ("sfft_kernels.hip", "sfft_common.hpp", "sfft_internal.hpp")]
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
-
-
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(f, "rb").read())
-    return h.hexdigest()[:16]
 
 
 def percentile(vals, q):
@@ -94,6 +87,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device tensor copy first (counter calibration)")
+    ap.add_argument("--config-key", action="store_true",
+                    help="print the key that names this configuration in the traffic record, then exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -112,7 +107,11 @@ def main():
     dev = torch.device("cuda:0")
     n, k, S = 1 << args.log2n, args.k, args.signals
     w = args.w or sfft.sfft_default_w(n, args.B, 0.5, 1e-9)
-    cfg_key = "n=2^%d,k=%d,B=%d,w=%d,signals=%d" % (args.log2n, k, args.B, w, S)
+    cfg_key = "n=2^%d,k=%d,B=%d,w=%d,b_min=%d,rounds=%d,signals=%d" % (args.log2n, k, args.B, w, args.b_min,
+                                                                       args.rounds, S)
+    if args.config_key:
+        print(cfg_key)
+        return
 
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)      # 1 GiB
