@@ -51,7 +51,8 @@ typedef enum {
     SFFT_EBUDGET = 4,    /* the request does not fit the memory budget       */
     SFFT_EHIP = 5,       /* a HIP runtime call failed                        */
     SFFT_ETRUNC = 6,     /* more coefficients than cap; the top cap returned  */
-    SFFT_EUNSUPPORTED = 7/* parameters valid but not supported by a kernel   */
+    SFFT_EUNSUPPORTED = 7,/* parameters valid but not supported by a kernel  */
+    SFFT_EAGAIN = 8      /* a served request has not finished yet            */
 } sfft_status_t;
 
 typedef enum { SFFT_MODE_EXACT = 0, SFFT_MODE_GENERAL = 1 } sfft_mode_t;
@@ -132,6 +133,11 @@ typedef struct {
 } sfft_plan_desc_t;
 
 typedef struct sfft_plan_s* sfft_plan_t;
+
+/* Device bytes a plan created from *d would allocate (window tables,
+ * twiddles, the workspace for max_batch signals and the plain path's
+ * buffers); 0 when *d does not validate.  Pure host function. */
+uint64_t sfft_plan_device_bytes(const sfft_plan_desc_t* d);
 
 /* Fill *d with the defaults for (n, k, B, w, seed); exact mode, complex64.
  * Pure host function: no device is touched.  Errors: SFFT_EINVAL if d is NULL. */
@@ -283,6 +289,109 @@ const char* sfft_last_error(void);
  * OOPSLA 2014).  Counter layout c = round<<32 | level<<20 | rep<<8 | purpose.
  * Pure host function, exported so that callers can reproduce a plan's draws. */
 uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
+
+/* ================================================================ serving ==
+ *
+ * A server runs sparse FFT requests of mixed n, k and mode on one GPU with
+ * continuous batching (the serving pattern of the problem statement: requests
+ * admitted as they arrive, against a device-memory budget, with plans and
+ * window tables kept resident):
+ *   * a request (n, k, mode) maps to a shape: k rounded up to a power of two
+ *     (at least 8), B = 4k' (exact) or 16k' (general) within [64 or 256,
+ *     min(4096, n/16)], the default window for the mode's delta; exact shapes
+ *     use b_min = max(8, B/32) and at most 24 rounds.  Where that window
+ *     would cover the whole signal (w >= n) the request takes the dense path:
+ *     a full-length FP32 FFT (hipFFT, loaded on first use) and the k bins of
+ *     largest magnitude (exact mode: those above theta/2);
+ *   * each shape gets up to `instances` resident plan instances (workspace
+ *     for `slots` signals each), created when needed; idle instances of other
+ *     shapes are evicted, least recently used first, when a new one would
+ *     exceed `budget_bytes`;
+ *   * a scheduler thread batches the waiting requests of each shape (oldest
+ *     shape first) onto idle instances, one stream per instance, so batches
+ *     of different shapes overlap on the device.
+ * A request's result depends only on its samples, its seed and its shape:
+ * it is the same alone and in any mix.  Inputs are complex64.
+ */
+typedef struct sfft_server_s* sfft_server_t;
+
+typedef struct {
+    uint64_t budget_bytes;   /* device memory the server may hold (instances)   */
+    uint32_t slots;          /* signals per batch of one instance, 1..1024      */
+    uint32_t instances;      /* instances per shape (batches in flight), 1..16  */
+    int32_t device;          /* HIP device the server runs on                  */
+    uint32_t reserved;
+    double delta_exact;      /* window accuracy of exact-mode shapes            */
+    double delta_general;    /* window accuracy of general-mode shapes          */
+    double theta;            /* exact-mode bin threshold                        */
+} sfft_server_desc_t;
+
+typedef struct {
+    const void* x_dev;       /* n complex64 samples on the server's device;
+                                caller-owned until the request has finished  */
+    uint64_t n;              /* 2^10 .. 2^30                                    */
+    uint64_t seed;           /* the request's draws                             */
+    uint32_t k;              /* 1 .. 1024                                       */
+    int32_t mode;            /* SFFT_MODE_EXACT or SFFT_MODE_GENERAL            */
+    uint64_t* idx_host;      /* [k] indices, ascending (caller-owned, or NULL)  */
+    double* val_host;        /* [k][2] values, unitary convention (or NULL)     */
+} sfft_request_t;
+
+typedef struct {
+    int32_t status;          /* SFFT_OK or the failure                          */
+    uint32_t count;          /* coefficients written (<= k)                     */
+    uint32_t flags;          /* SFFT_INFO_FLAGS word (sparse path)              */
+    uint32_t rounds;         /* rounds decoded (sparse path)                    */
+    int32_t path;            /* 0 sparse, 1 dense                               */
+    uint32_t reserved;
+    double queue_ms;         /* submit -> launch                                */
+    double service_ms;       /* launch -> results on the host                   */
+    double latency_ms;       /* submit -> results on the host                   */
+} sfft_request_result_t;
+
+typedef struct {
+    uint64_t completed, dense, failed, batches, evictions;
+    uint64_t bytes_in_use;   /* device bytes held by instances now              */
+    uint64_t peak_bytes;     /* largest bytes_in_use since the last reset       */
+    uint32_t pending, inflight, instances, reserved;
+    double mean_batch;       /* requests per launched batch                     */
+    double p50_ms, p99_ms;   /* latency percentiles (completed since reset)     */
+    double queue_p50_ms, service_p50_ms;
+    double rate;             /* completed per second, first submit -> last completion */
+} sfft_server_stats_t;
+
+/* Defaults: 16 GiB budget, 32 slots, 2 instances per shape, device 0,
+ * delta 1e-9 (exact) / 1e-6 (general), theta 0.25.  Errors: SFFT_EINVAL. */
+sfft_status_t sfft_server_desc_init(sfft_server_desc_t* d);
+
+/* The shape a request (n, k, mode) maps to: its plan description, whether it
+ * takes the dense path, and the device bytes of one instance.  Pure host
+ * function.  Errors: SFFT_ENOTPOW2, SFFT_EINVAL. */
+sfft_status_t sfft_server_shape(const sfft_server_desc_t* d, uint64_t n, uint32_t k, int32_t mode,
+                                sfft_plan_desc_t* plan_out, int32_t* dense_out, uint64_t* bytes_out);
+
+/* Start a server (its scheduler thread).  Errors: SFFT_EINVAL, SFFT_ENOMEM. */
+sfft_status_t sfft_server_create(const sfft_server_desc_t* d, sfft_server_t* out);
+
+/* Queue one request; *ticket names it.  The output buffers are written when
+ * it finishes.  Errors: SFFT_EINVAL, SFFT_ENOTPOW2 (bad request), SFFT_EBUDGET
+ * (one instance of its shape exceeds the budget). */
+sfft_status_t sfft_server_submit(sfft_server_t s, const sfft_request_t* req, uint64_t* ticket);
+
+/* SFFT_EAGAIN while the request runs; otherwise its status, with *res filled
+ * (may be NULL) and the ticket released. */
+sfft_status_t sfft_server_poll(sfft_server_t s, uint64_t ticket, sfft_request_result_t* res);
+
+/* Block until the request finishes (timeout_ms < 0: no limit; SFFT_EAGAIN on
+ * timeout), then as sfft_server_poll. */
+sfft_status_t sfft_server_wait(sfft_server_t s, uint64_t ticket, double timeout_ms, sfft_request_result_t* res);
+
+/* Counters and latency percentiles since the last reset. */
+sfft_status_t sfft_server_stats(sfft_server_t s, sfft_server_stats_t* st);
+sfft_status_t sfft_server_reset_stats(sfft_server_t s);
+
+/* Finish every queued request, stop the scheduler and free all instances. */
+sfft_status_t sfft_server_destroy(sfft_server_t s);
 
 #ifdef __cplusplus
 }

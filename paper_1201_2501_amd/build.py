@@ -12,7 +12,7 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsfft.so")
-SOURCES = ["sfft_host.cpp", "sfft_kernels.hip", "sfft_decode.hip"]
+SOURCES = ["sfft_host.cpp", "sfft_kernels.hip", "sfft_decode.hip", "sfft_dense.hip", "sfft_server.cpp"]
 ARCH = "gfx950"
 
 
@@ -37,7 +37,7 @@ def build(verbose=False):
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp] + objs + ["-ldl"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

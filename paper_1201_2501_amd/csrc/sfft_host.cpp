@@ -126,6 +126,8 @@ struct sfft_plan_s {
     sfft_plan_desc_t d;
     int device = 0;
     uint32_t R = 0;            // rounds with geometry
+    size_t device_bytes = 0;   // device memory held by the plan
+    bool dry = false;          // size the plan without touching a device
     // exact batched mode: ends of the round groups.  Group 0 is hashed for
     // every signal; each later group only for signals still decoding.
     std::vector<uint32_t> group_end;
@@ -189,9 +191,15 @@ template <class T>
 sfft_status_t dev_alloc(sfft_plan_s* p, T** ptr, size_t count) {
     void* q = nullptr;
     const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    if (p->dry) {
+        p->device_bytes += bytes;
+        *ptr = nullptr;
+        return SFFT_OK;
+    }
     hipError_t e = hipMalloc(&q, bytes);
     if (e != hipSuccess) return fail(SFFT_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     p->allocations.push_back(q);
+    p->device_bytes += bytes;
     *ptr = reinterpret_cast<T*>(q);
     return SFFT_OK;
 }
@@ -252,7 +260,7 @@ void general_levels(const sfft_plan_desc_t& d, uint32_t B_r, GenRoundDev& gr) {
 
 sfft_status_t build_plan(sfft_plan_s* p) {
     const sfft_plan_desc_t& d = p->d;
-    HIP_TRY(hipGetDevice(&p->device));
+    if (!p->dry) HIP_TRY(hipGetDevice(&p->device));
     // round geometry (exact mode schedule)
     p->R = d.rounds;
     p->Bmax = d.B;
@@ -341,19 +349,25 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     ST_TRY(dev_alloc(p, &p->d_g32, g32.size()));
     ST_TRY(dev_alloc(p, &p->d_tw64, tw64.size()));
     ST_TRY(dev_alloc(p, &p->d_tw32, tw32.size()));
-    HIP_TRY(hipMemcpy(p->d_geom, p->geom.data(), p->geom.size() * sizeof(RoundDev), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(p->d_g64, g64.data(), g64.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(p->d_g32, g32.data(), g32.size() * sizeof(float), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(p->d_tw64, tw64.data(), tw64.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(p->d_tw32, tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (!p->dry) {
+        HIP_TRY(hipMemcpy(p->d_geom, p->geom.data(), p->geom.size() * sizeof(RoundDev), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_g64, g64.data(), g64.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_g32, g32.data(), g32.size() * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_tw64, tw64.data(), tw64.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_tw32, tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
     if (general_mode(p)) {
         ST_TRY(dev_alloc(p, &p->d_groundv, p->groundv.size()));
         ST_TRY(dev_alloc(p, &p->d_jobs_loc, p->jobs_loc.size()));
         ST_TRY(dev_alloc(p, &p->d_jobs_est, p->jobs_est.size()));
-        HIP_TRY(hipMemcpy(p->d_groundv, p->groundv.data(), p->groundv.size() * sizeof(GenRoundDev),
-                          hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(p->d_jobs_loc, p->jobs_loc.data(), p->jobs_loc.size() * sizeof(GenJob), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(p->d_jobs_est, p->jobs_est.data(), p->jobs_est.size() * sizeof(GenJob), hipMemcpyHostToDevice));
+        if (!p->dry) {
+            HIP_TRY(hipMemcpy(p->d_groundv, p->groundv.data(), p->groundv.size() * sizeof(GenRoundDev),
+                              hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(p->d_jobs_loc, p->jobs_loc.data(), p->jobs_loc.size() * sizeof(GenJob),
+                              hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(p->d_jobs_est, p->jobs_est.data(), p->jobs_est.size() * sizeof(GenJob),
+                              hipMemcpyHostToDevice));
+        }
     }
     // batched workspace
     const size_t S = d.max_batch;
@@ -383,6 +397,7 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     ST_TRY(dev_alloc(p, &p->p_val, 2 * (size_t)p->cap));
     ST_TRY(dev_alloc(p, &p->p_count, 1));
     ST_TRY(dev_alloc(p, &p->p_info, 4));
+    if (p->dry) return SFFT_OK;
     HIP_TRY(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamCreateWithFlags(&p->aux_stream, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
@@ -501,7 +516,7 @@ GeneralArgs base_general(const sfft_plan_s* p, uint32_t count, const uint64_t* s
 // General-mode HashToBins for rounds [r0, r1): every LocateInner pair in
 // loc_prec arithmetic, every EstimateValues hashing in est_prec.
 sfft_status_t enqueue_general_hash(sfft_plan_s* p, const void* x, uint32_t count, const uint64_t* seeds, double* raw,
-                                   uint32_t r0, uint32_t r1, hipStream_t s) {
+                                   uint32_t r0, uint32_t r1, hipStream_t s, const void* const* xptrs = nullptr) {
     for (int kind = 0; kind < 2; ++kind) {
         const std::vector<uint32_t>& first = kind == 0 ? p->loc_first : p->est_first;
         const std::vector<uint32_t>& cnt = kind == 0 ? p->loc_count : p->est_count;
@@ -511,6 +526,7 @@ sfft_status_t enqueue_general_hash(sfft_plan_s* p, const void* x, uint32_t count
         if (nj == 0) continue;
         const bool f64 = (kind == 0 ? p->d.loc_prec : p->d.est_prec) == SFFT_F64;
         H2BArgs a = base_h2b(p, x);
+        a.xptrs = xptrs;
         a.gtab = f64 ? (const void*)p->d_g64 : (const void*)p->d_g32;
         a.tw = f64 ? (const void*)p->d_tw64 : (const void*)p->d_tw32;
         a.seeds = seeds;
@@ -573,9 +589,10 @@ void offset_general(const sfft_plan_s* p, GeneralArgs& G, uint32_t off) {
 // round; part 1: decode loop + re-estimation and output.
 sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt, const void* x,
                             const uint64_t* seeds, uint64_t* idx, double* val, uint32_t* ocnt, uint32_t* info,
-                            hipStream_t s) {
+                            hipStream_t s, const void* const* xptrs = nullptr) {
     const size_t elem = in_c128(p) ? 16 : 8;
-    const void* xc = static_cast<const char*>(x) + (size_t)off * p->d.n * elem;
+    const void* xc = xptrs ? nullptr : static_cast<const char*>(x) + (size_t)off * p->d.n * elem;
+    const void* const* xpc = xptrs ? xptrs + off : nullptr;
     const uint64_t* sc = seeds ? seeds + off : nullptr;
     DecodeArgs D = base_decode(p, cnt, seeds, p->raw, idx, val, ocnt, info);
     offset_decode(p, D, off);
@@ -585,7 +602,7 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
         if (part == 0) {
             HIP_TRY(launch_exact_init(D, s));
             double* rawc = p->raw + (uint64_t)off * p->nslots * 4 * p->Bmax;
-            ST_TRY(enqueue_general_hash(p, xc, cnt, sc, rawc, 0, p->R, s));
+            ST_TRY(enqueue_general_hash(p, xc, cnt, sc, rawc, 0, p->R, s, xpc));
         } else {
             HIP_TRY(launch_general_decode(G, 0, p->R, s));
             HIP_TRY(launch_general_finish(G, s));
@@ -593,6 +610,7 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
         return SFFT_OK;
     }
     H2BArgs a = base_h2b(p, xc);
+    a.xptrs = xpc;
     a.seeds = sc;
     a.count = cnt;
     a.raw = p->raw + (uint64_t)off * p->R * 4 * p->Bmax;
@@ -669,6 +687,7 @@ const char* sfft_status_string(sfft_status_t s) {
         case SFFT_EHIP: return "SFFT_EHIP";
         case SFFT_ETRUNC: return "SFFT_ETRUNC";
         case SFFT_EUNSUPPORTED: return "SFFT_EUNSUPPORTED";
+        case SFFT_EAGAIN: return "SFFT_EAGAIN";
     }
     return "SFFT_UNKNOWN";
 }
@@ -762,6 +781,17 @@ sfft_status_t sfft_plan_ex(const sfft_plan_desc_t* desc, sfft_plan_t* out) {
     }
     *out = p;
     return SFFT_OK;
+}
+
+uint64_t sfft_plan_device_bytes(const sfft_plan_desc_t* desc) {
+    if (!desc) return 0;
+    sfft_plan_desc_t d = *desc;
+    if (resolve_and_validate(d) != SFFT_OK || d.w < d.B || d.w % d.B) return 0;
+    sfft_plan_s p;
+    p.d = d;
+    p.dry = true;
+    if (build_plan(&p) != SFFT_OK) return 0;
+    return p.device_bytes;
 }
 
 sfft_status_t sfft_plan(uint64_t n, uint32_t k, uint32_t B, uint64_t w, uint64_t seed, sfft_plan_t* out) {
@@ -1047,3 +1077,22 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
 }
 
 }  // extern "C"
+
+namespace sfft {
+
+sfft_status_t set_last_error(sfft_status_t s, const std::string& msg) { return fail(s, msg); }
+
+size_t plan_device_bytes(const sfft_plan_s* p) { return p ? p->device_bytes : 0; }
+
+sfft_status_t plan_enqueue_ptrs(sfft_plan_s* p, const void* const* xptrs_dev, uint32_t count,
+                                const uint64_t* seeds_dev, uint64_t* idx_dev, double* val_dev, uint32_t* count_dev,
+                                uint32_t* info_dev, hipStream_t s) {
+    if (!p || !xptrs_dev || !idx_dev || !val_dev || !count_dev) return fail(SFFT_EINVAL, "NULL argument");
+    if (count < 1 || count > p->d.max_batch) return fail(SFFT_EINVAL, "count must be in [1, max_batch]");
+    std::lock_guard<std::mutex> lock(p->mu);
+    ST_TRY(enqueue_chunk(p, 0, 0, count, nullptr, seeds_dev, idx_dev, val_dev, count_dev, info_dev, s, xptrs_dev));
+    ST_TRY(enqueue_chunk(p, 1, 0, count, nullptr, seeds_dev, idx_dev, val_dev, count_dev, info_dev, s, xptrs_dev));
+    return SFFT_OK;
+}
+
+}  // namespace sfft

@@ -67,6 +67,7 @@ struct GenJob {
 // Arguments of the HashToBins pair kernels.
 struct H2BArgs {
     const void* x;
+    const void* const* xptrs;  // [count] per-signal inputs (batched mode) or nullptr: x + sig * sig_stride
     uint64_t n;
     uint64_t sig_stride;       // elements between signals
     const uint64_t* seeds;     // [count] or nullptr
@@ -180,4 +181,23 @@ hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s);
 size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64);
 size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax);
 
+// dense path (sfft_dense.hip): top `cap` bins by magnitude of `count`
+// spectra [count][n] complex64, ascending index, values * scale in
+// complex128; with keep_half_theta > 0 only magnitudes above it are kept.
+hipError_t launch_dense_topk(const float2* spec, uint64_t n, uint32_t count, uint32_t cap, double scale,
+                             double keep_above, uint64_t* out_idx, double* out_val, uint32_t* out_count,
+                             hipStream_t s);
+
+}  // namespace sfft
+
+// Host runtime entry points used by the server (sfft_host.cpp).
+struct sfft_plan_s;
+namespace sfft {
+// Both parts of the batched path for `count` signals given by device
+// pointers, on stream s, without graphs or timing events.
+sfft_status_t plan_enqueue_ptrs(sfft_plan_s* p, const void* const* xptrs_dev, uint32_t count,
+                                const uint64_t* seeds_dev, uint64_t* idx_dev, double* val_dev, uint32_t* count_dev,
+                                uint32_t* info_dev, hipStream_t s);
+size_t plan_device_bytes(const sfft_plan_s* p);
+sfft_status_t set_last_error(sfft_status_t s, const std::string& msg);
 }  // namespace sfft

@@ -231,7 +231,8 @@ __global__ void __launch_bounds__(kThreads) k_h2b_pair(H2BArgs A) {
         beta = 1;
     }
     const RoundDev g = A.geom[r];
-    const TIn* x = reinterpret_cast<const TIn*>(A.x) + (uint64_t)sig * A.sig_stride;
+    const TIn* x = A.xptrs ? reinterpret_cast<const TIn*>(A.xptrs[sig])
+                           : reinterpret_cast<const TIn*>(A.x) + (uint64_t)sig * A.sig_stride;
     const TA* G = reinterpret_cast<const TA*>(A.gtab) + g.gofs;
     const auto* tw = reinterpret_cast<const typename TwTraits<TA>::V*>(A.tw);
     const uint32_t B = g.B;

@@ -14,7 +14,8 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsfft.so")
 
-SFFT_OK, SFFT_EINVAL, SFFT_ENOTPOW2, SFFT_ENOMEM, SFFT_EBUDGET, SFFT_EHIP, SFFT_ETRUNC, SFFT_EUNSUPPORTED = range(8)
+(SFFT_OK, SFFT_EINVAL, SFFT_ENOTPOW2, SFFT_ENOMEM, SFFT_EBUDGET, SFFT_EHIP, SFFT_ETRUNC, SFFT_EUNSUPPORTED,
+ SFFT_EAGAIN) = range(9)
 SFFT_MODE_EXACT, SFFT_MODE_GENERAL = 0, 1
 SFFT_C64, SFFT_C128 = 0, 1
 SFFT_F32, SFFT_F64 = 0, 1
@@ -26,9 +27,12 @@ INFO_ROUNDS, INFO_FLAGS, INFO_ZHAT, INFO_LOCATED = range(4)
 EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_plan_ex", "sfft_plan",
            "sfft_plan_get_desc", "sfft_destroy", "sfft_execute", "sfft_execute_batch",
            "sfft_hash_pair_raw", "sfft_plan_timings", "sfft_plan_h2b_bytes", "sfft_plan_round_groups",
-           "sfft_plan_raw_slot",
+           "sfft_plan_raw_slot", "sfft_plan_device_bytes",
            "sfft_status_string",
-           "sfft_last_error", "sfft_splitmix64"]
+           "sfft_last_error", "sfft_splitmix64",
+           "sfft_server_desc_init", "sfft_server_shape", "sfft_server_create", "sfft_server_submit",
+           "sfft_server_poll", "sfft_server_wait", "sfft_server_stats", "sfft_server_reset_stats",
+           "sfft_server_destroy"]
 
 
 class PlanDesc(ctypes.Structure):
@@ -38,6 +42,30 @@ class PlanDesc(ctypes.Structure):
                 ("s", c_double), ("rounds", c_uint32), ("b_min", c_uint32), ("patience", c_uint32),
                 ("t", c_uint32), ("R_loc", c_uint32), ("R_est", c_uint32), ("cap", c_uint32),
                 ("flags", c_uint32), ("max_batch", c_uint32), ("reserved", c_uint32)]
+
+
+class ServerDesc(ctypes.Structure):
+    _fields_ = [("budget_bytes", c_uint64), ("slots", c_uint32), ("instances", c_uint32), ("device", c_int32),
+                ("reserved", c_uint32), ("delta_exact", c_double), ("delta_general", c_double), ("theta", c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("x_dev", c_void_p), ("n", c_uint64), ("seed", c_uint64), ("k", c_uint32), ("mode", c_int32),
+                ("idx_host", c_void_p), ("val_host", c_void_p)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("status", c_int32), ("count", c_uint32), ("flags", c_uint32), ("rounds", c_uint32),
+                ("path", c_int32), ("reserved", c_uint32), ("queue_ms", c_double), ("service_ms", c_double),
+                ("latency_ms", c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", c_uint64), ("dense", c_uint64), ("failed", c_uint64), ("batches", c_uint64),
+                ("evictions", c_uint64), ("bytes_in_use", c_uint64), ("peak_bytes", c_uint64),
+                ("pending", c_uint32), ("inflight", c_uint32), ("instances", c_uint32), ("reserved", c_uint32),
+                ("mean_batch", c_double), ("p50_ms", c_double), ("p99_ms", c_double), ("queue_p50_ms", c_double),
+                ("service_p50_ms", c_double), ("rate", c_double)]
 
 
 _lib = None
@@ -75,9 +103,21 @@ def load():
     lib.sfft_last_error.restype = c_char_p
     lib.sfft_splitmix64.argtypes = [c_uint64, c_uint64]
     lib.sfft_splitmix64.restype = c_uint64
+    lib.sfft_plan_device_bytes.argtypes = [POINTER(PlanDesc)]
+    lib.sfft_plan_device_bytes.restype = c_uint64
+    lib.sfft_server_desc_init.argtypes = [POINTER(ServerDesc)]
+    lib.sfft_server_shape.argtypes = [POINTER(ServerDesc), c_uint64, c_uint32, c_int32, POINTER(PlanDesc),
+                                      POINTER(c_int32), POINTER(c_uint64)]
+    lib.sfft_server_create.argtypes = [POINTER(ServerDesc), POINTER(P)]
+    lib.sfft_server_submit.argtypes = [P, POINTER(Request), POINTER(c_uint64)]
+    lib.sfft_server_poll.argtypes = [P, c_uint64, POINTER(RequestResult)]
+    lib.sfft_server_wait.argtypes = [P, c_uint64, c_double, POINTER(RequestResult)]
+    lib.sfft_server_stats.argtypes = [P, POINTER(ServerStats)]
+    lib.sfft_server_reset_stats.argtypes = [P]
+    lib.sfft_server_destroy.argtypes = [P]
     for name in EXPORTS:
         if name not in ("sfft_default_w", "sfft_status_string", "sfft_last_error", "sfft_splitmix64",
-                        "sfft_plan_h2b_bytes"):
+                        "sfft_plan_h2b_bytes", "sfft_plan_device_bytes"):
             getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -295,3 +335,128 @@ class Plan:
         out1 = torch.empty(B_r, dtype=torch.complex128, device=x.device)
         sfft_hash_pair_raw(self.handle, x, sigma, a, beta, b, B_r, prec, out0, out1, stream)
         return out0, out1
+
+
+# ---- serving -------------------------------------------------------------------
+def sfft_plan_device_bytes(desc):
+    return int(load().sfft_plan_device_bytes(ctypes.byref(desc)))
+
+
+def sfft_server_desc_init():
+    d = ServerDesc()
+    _check(load().sfft_server_desc_init(ctypes.byref(d)), "sfft_server_desc_init")
+    return d
+
+
+def sfft_server_shape(sdesc, n, k, mode):
+    """(plan description, dense?, instance bytes) of a request shape."""
+    d = PlanDesc()
+    dense = c_int32(0)
+    nbytes = c_uint64(0)
+    _check(load().sfft_server_shape(ctypes.byref(sdesc), n, k, mode, ctypes.byref(d), ctypes.byref(dense),
+                                    ctypes.byref(nbytes)), "sfft_server_shape")
+    return d, bool(dense.value), int(nbytes.value)
+
+
+def sfft_server_create(sdesc):
+    h = c_void_p()
+    _check(load().sfft_server_create(ctypes.byref(sdesc), ctypes.byref(h)), "sfft_server_create")
+    return h
+
+
+def sfft_server_submit(server, req):
+    t = c_uint64(0)
+    _check(load().sfft_server_submit(server, ctypes.byref(req), ctypes.byref(t)), "sfft_server_submit")
+    return int(t.value)
+
+
+def sfft_server_poll(server, ticket):
+    res = RequestResult()
+    st = load().sfft_server_poll(server, ticket, ctypes.byref(res))
+    return st, res
+
+
+def sfft_server_wait(server, ticket, timeout_ms=-1.0):
+    res = RequestResult()
+    st = load().sfft_server_wait(server, ticket, timeout_ms, ctypes.byref(res))
+    return st, res
+
+
+def sfft_server_stats(server):
+    st = ServerStats()
+    _check(load().sfft_server_stats(server, ctypes.byref(st)), "sfft_server_stats")
+    return st
+
+
+def sfft_server_reset_stats(server):
+    _check(load().sfft_server_reset_stats(server), "sfft_server_reset_stats")
+
+
+def sfft_server_destroy(server):
+    _check(load().sfft_server_destroy(server), "sfft_server_destroy")
+
+
+class Server:
+    """Owns one server.  submit() takes a 1-D complex64 device tensor and keeps
+    it (and the request's output arrays) alive until wait()/poll() returns
+    the result."""
+
+    def __init__(self, **fields):
+        d = sfft_server_desc_init()
+        for key, v in fields.items():
+            if not hasattr(d, key):
+                raise TypeError("unknown server field %r" % key)
+            setattr(d, key, v)
+        self.desc = d
+        self.handle = sfft_server_create(d)
+        self._live = {}
+
+    def submit(self, x, k, mode=SFFT_MODE_EXACT, seed=0):
+        import torch
+
+        if x.dtype != torch.complex64 or x.dim() != 1 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous 1-D complex64 device tensor")
+        idx = np.zeros(k, dtype=np.uint64)
+        val = np.zeros((k, 2), dtype=np.float64)
+        req = Request(x_dev=x.data_ptr(), n=x.shape[0], seed=seed, k=k, mode=mode,
+                      idx_host=idx.ctypes.data, val_host=val.ctypes.data)
+        t = sfft_server_submit(self.handle, req)
+        self._live[t] = (x, idx, val)
+        return t
+
+    def _finish(self, t, st, res):
+        x, idx, val = self._live.pop(t)
+        if st != SFFT_OK:
+            raise SfftError(st, "served request")
+        c = res.count
+        return idx[:c].astype(np.int64), val[:c, 0] + 1j * val[:c, 1], res
+
+    def wait(self, ticket, timeout_ms=-1.0):
+        st, res = sfft_server_wait(self.handle, ticket, timeout_ms)
+        if st == SFFT_EAGAIN:
+            return None
+        return self._finish(ticket, st, res)
+
+    def poll(self, ticket):
+        st, res = sfft_server_poll(self.handle, ticket)
+        if st == SFFT_EAGAIN:
+            return None
+        return self._finish(ticket, st, res)
+
+    def stats(self):
+        return sfft_server_stats(self.handle)
+
+    def reset_stats(self):
+        sfft_server_reset_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            sfft_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,159 @@
+"""GPU checks of the serving runtime: served requests match the FP64 oracle
+(sparse path) or numpy's FFT (dense path); every request gives the same
+result alone and inside a mix of shapes; the device-memory budget holds,
+with eviction, when it is smaller than the working set of shapes.  Every case
+prints its name before touching the GPU."""
+import numpy as np
+import pytest
+
+import siggen
+from oracle.exact import noiseless_sparse_fft
+from oracle.general import sparse_fft
+from oracle.params import SfftParams
+
+pytestmark = pytest.mark.gpu
+
+EXACT, GENERAL = 0, 1
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1201_2501_amd import sfft
+    sfft.load()
+    return torch, torch.device("cuda:0"), sfft
+
+
+def make_signal(torch, dev, n, k, seed, mode):
+    noise = 0.0 if mode == EXACT else 0.05
+    x, sup, val = siggen.planted_signal(n, k, seed, np.complex64, magnitude="unit", noise_ratio=noise)
+    return x, sup, val, torch.from_numpy(x).to(dev)
+
+
+def oracle_for(d, seed):
+    rounds = d.rounds or (16 if d.mode == EXACT else 5)     # 0 = the mode's default
+    return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=seed, alpha=d.alpha, delta=d.delta, theta=d.theta,
+                      g_min=d.g_min, rounds=rounds, b_min=d.b_min, patience=d.patience, cap=d.cap, t=d.t,
+                      s=d.s, R_loc=d.R_loc, R_est=d.R_est)
+
+
+# (name, n, k, mode, signal seed, request seed)
+CASES = [
+    ("exact-16-16", 1 << 16, 16, EXACT, 11, 101),
+    ("exact-18-100", 1 << 18, 100, EXACT, 12, 102),
+    ("general-16-8", 1 << 16, 8, GENERAL, 13, 103),
+    ("general-18-20", 1 << 18, 20, GENERAL, 14, 104),
+    ("dense-16-300", 1 << 16, 300, EXACT, 15, 105),
+    ("dense-16-200g", 1 << 16, 200, GENERAL, 16, 106),
+]
+
+
+def test_served_results_match_oracle_or_dense_reference(env):
+    torch, dev, sfft = env
+    srv = sfft.Server(slots=4, instances=2, budget_bytes=4 << 30)
+    sd = srv.desc
+    n_dense = 0
+    try:
+        for name, n, k, mode, gseed, rseed in CASES:
+            say("serve", name, "n", n, "k", k, "mode", mode)
+            x, sup, val, xt = make_signal(torch, dev, n, k, gseed, mode)
+            idx, v, res = srv.wait(srv.submit(xt, k, mode, rseed))
+            d, dense, _ = sfft.sfft_server_shape(sd, n, k, mode)
+            assert res.path == int(dense) and dense == name.startswith("dense")
+            n_dense += int(dense)
+            assert np.all(np.diff(idx) > 0) and len(idx) <= k
+            if dense:
+                # full FFT in FP64 of the same complex64 samples, unitary
+                X = np.fft.fft(x.astype(np.complex128)) / np.sqrt(n)
+                order = np.lexsort((np.arange(n), -np.abs(X)))[:k]
+                if mode == EXACT:
+                    order = order[np.abs(X[order]) > sd.theta / 2]
+                ref = np.sort(order)
+                assert np.array_equal(idx, ref)
+                assert np.max(np.abs(v - X[idx])) <= 1e-4 * np.max(np.abs(X[idx]))
+            elif mode == EXACT:
+                # below n = 2^20 the shape's bins are FP32 (values to 1e-4), above FP64 (1e-10)
+                rel = 1e-10 if d.loc_prec == sfft.SFFT_F64 else 1e-4
+                ref = noiseless_sparse_fft(x.astype(np.complex128), oracle_for(d, rseed))
+                assert np.array_equal(idx, ref.indices)
+                assert np.array_equal(idx, np.sort(sup))
+                assert np.all(np.abs(v - ref.values) <= rel * np.abs(ref.values))
+            else:
+                rel = 1e-10 if d.est_prec == sfft.SFFT_F64 else 1e-4
+                ref = sparse_fft(x.astype(np.complex128), oracle_for(d, rseed))
+                # the shape's cap is k rounded up: the server keeps the request's k largest
+                ri, rv = np.asarray(ref.indices), np.asarray(ref.values)
+                keep = np.sort(np.lexsort((ri, -np.abs(rv)))[:k])
+                ri, rv = ri[keep], rv[keep]
+                if not np.array_equal(idx, ri):   # FP32 decisions may differ only on an oracle near-tie
+                    assert d.loc_prec == sfft.SFFT_F32 and (ref.vote_margin < 1e-4 or ref.select_margin < 1e-4)
+                else:
+                    assert np.all(np.abs(v - rv) <= rel * np.abs(rv) + 1e-12)
+        st = srv.stats()
+        assert st.completed == len(CASES) and st.failed == 0 and st.dense == n_dense == 2
+        assert 0 < st.p50_ms <= st.p99_ms
+    finally:
+        srv.close()
+
+
+def test_each_request_is_the_same_alone_and_in_a_mix(env):
+    torch, dev, sfft = env
+    say("alone-vs-mix", len(CASES), "shapes x 3 requests")
+    reqs = []
+    for name, n, k, mode, gseed, rseed in CASES:
+        for j in range(3):
+            _, _, _, xt = make_signal(torch, dev, n, k, gseed + 100 * j, mode)
+            reqs.append((xt, k, mode, rseed + j))
+    torch.cuda.synchronize()
+    srv = sfft.Server(slots=4, instances=1, budget_bytes=4 << 30)
+    try:
+        alone = [srv.wait(srv.submit(*r)) for r in reqs]
+        srv.reset_stats()
+        # all at once, in another order: with one instance per shape, requests
+        # of a shape that arrive while its first runs are batched together
+        tickets = [srv.submit(*r) for r in reqs[::-1]]
+        mixed = [srv.wait(t) for t in tickets][::-1]
+        for (ia, va, ra), (im, vm, rm) in zip(alone, mixed):
+            assert np.array_equal(ia, im)
+            assert np.array_equal(va, vm)
+            assert ra.path == rm.path and ra.rounds == rm.rounds
+        st = srv.stats()
+        assert st.completed == len(reqs) and st.batches < len(reqs) and st.mean_batch > 1.0
+    finally:
+        srv.close()
+
+
+def test_budget_below_the_working_set_evicts_and_never_overflows(env):
+    torch, dev, sfft = env
+    sd = sfft.sfft_server_desc_init()
+    sd.slots = 2
+    shapes = [(1 << 16, 16, EXACT), (1 << 18, 100, EXACT), (1 << 16, 8, GENERAL)]
+    sizes = [sfft.sfft_server_shape(sd, n, k, m)[2] for n, k, m in shapes]
+    budget = max(sizes) + min(sizes) // 2          # room for one instance at a time
+    say("budget", budget, "instance sizes", sizes)
+    srv = sfft.Server(slots=2, instances=1, budget_bytes=budget)
+    try:
+        sigs = [make_signal(torch, dev, n, k, 40 + i, m)[3] for i, (n, k, m) in enumerate(shapes)]
+        tickets = []
+        for rep in range(3):
+            for i, (n, k, m) in enumerate(shapes):
+                tickets.append(srv.submit(sigs[i], k, m, 500 + 10 * rep + i))
+        outs = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+        assert st.completed == len(tickets) and st.failed == 0
+        assert st.peak_bytes <= budget and st.evictions >= 1
+        # same answers as with room for every shape
+        big = sfft.Server(slots=2, instances=1, budget_bytes=4 << 30)
+        try:
+            for t_out, (rep, i) in zip(outs, [(r, i) for r in range(3) for i in range(len(shapes))]):
+                n, k, m = shapes[i]
+                o = big.wait(big.submit(sigs[i], k, m, 500 + 10 * rep + i))
+                assert np.array_equal(o[0], t_out[0]) and np.array_equal(o[1], t_out[1])
+        finally:
+            big.close()
+    finally:
+        srv.close()
