@@ -59,6 +59,121 @@ def load_traffic(signals, cfg_key):
     return None if per_signal is None else float(per_signal) * signals
 
 
+def serving_bench(args, torch, dev, sfft):
+    """Mixed request stream through the serving runtime: n log-uniform over
+    2^16..2^24, k uniform in [8, 1024], half exactly sparse (unit magnitudes)
+    and half noisy (tail/head 0.05), per-request seeds.  Signals come from a
+    pool of 4 planted signals per (n, mode), each with its own k.  Phases:
+    warm-up (every shape once, plans made resident), saturated (all requests
+    submitted at once: capacity), Poisson arrivals at serve_load x capacity
+    (latency).  Recovery is checked per request against the planted spectra."""
+    import siggen
+
+    rng = np.random.Generator(np.random.PCG64(20241203))
+    sizes = [1 << e for e in range(16, 25)]
+    pool = {}
+    t = time.time()
+    for n in sizes:
+        for mode in (sfft.SFFT_MODE_EXACT, sfft.SFFT_MODE_GENERAL):
+            for j in range(4):
+                kk = int(rng.integers(8, 1025))
+                gseed = 7_000_000 + (n.bit_length() << 8) + (mode << 4) + j
+                x, sups, vals = siggen.torch_planted_batch(n, kk, [gseed], dev, magnitude="unit",
+                                                           noise_ratio=0.05 if mode else 0.0)
+                order = np.argsort(sups[0])
+                pool.setdefault((n, mode), []).append((x[0].contiguous(), sups[0][order], vals[0][order], kk))
+    torch.cuda.synchronize()
+    log("serving: signal pool of %d signals in %.1fs" % (sum(len(v) for v in pool.values()), time.time() - t))
+
+    def draw(count):
+        out = []
+        for _ in range(count):
+            n = sizes[int(rng.integers(0, len(sizes)))]
+            mode = int(rng.integers(0, 2))
+            out.append((n, mode, int(rng.integers(0, 4)), int(rng.integers(1, 1 << 62))))
+        return out
+
+    srv = sfft.Server(budget_bytes=64 << 30, slots=32, instances=2)
+
+    def run(reqs, arrivals=None):
+        tickets = []
+        lag = 0.0
+        t0 = time.perf_counter()
+        for q, (n, mode, j, seed) in enumerate(reqs):
+            if arrivals is not None:
+                due = t0 + arrivals[q]
+                while time.perf_counter() < due:
+                    pass
+                lag = max(lag, time.perf_counter() - due)
+            x, _, _, kk = pool[(n, mode)][j]
+            tickets.append(srv.submit(x, kk, mode, seed))
+        outs = [srv.wait(tk) for tk in tickets]
+        return outs, lag
+
+    misses, worst = [], []
+
+    def recovery(reqs, outs):
+        exact_ok, exact_n, noisy_err = 0, 0, []
+        for (n, mode, j, seed), (idx, val, res) in zip(reqs, outs):
+            _, sup, vals, kk = pool[(n, mode)][j]
+            tag = {"n": n, "k": kk, "seed": seed, "path": "dense" if res.path else "sparse", "rounds": res.rounds,
+                   "count": res.count}
+            if mode == sfft.SFFT_MODE_EXACT:
+                exact_n += 1
+                good = bool(np.array_equal(idx, sup))
+                exact_ok += int(good)
+                if not good and len(misses) < 8:
+                    misses.append(dict(tag, missing=len(set(sup.tolist()) - set(idx.tolist())),
+                                       extra=len(set(idx.tolist()) - set(sup.tolist()))))
+            else:
+                est = dict(zip(idx.tolist(), val))
+                err2 = sum(abs(est.pop(int(i), 0) - v) ** 2 for i, v in zip(sup, vals)) + \
+                    sum(abs(v) ** 2 for v in est.values())
+                e = math.sqrt(err2) / float(np.linalg.norm(vals))
+                noisy_err.append(e)
+                worst.append(dict(tag, err=round(e, 5)))
+                worst.sort(key=lambda r: -r["err"])
+                del worst[4:]
+        return exact_ok, exact_n, noisy_err
+
+    # warm-up: every (n, mode, pool entry) once, so every shape's plans are resident
+    warm = [(n, mode, j, 1 + j) for (n, mode) in pool for j in range(4)]
+    run(warm)
+    srv.reset_stats()
+    # saturated: capacity
+    reqs = draw(args.serve_requests)
+    outs, _ = run(reqs)
+    st = srv.stats()
+    capacity = st.rate
+    ok_s, n_s, err_s = recovery(reqs, outs)
+    log("serving: capacity %.0f requests/s (mean batch %.2f, %d dense)" % (capacity, st.mean_batch, st.dense))
+    # Poisson arrivals
+    srv.reset_stats()
+    rate = args.serve_load * capacity
+    reqs = draw(args.serve_requests)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
+    outs, lag = run(reqs, arrivals)
+    st = srv.stats()
+    ok_p, n_p, err_p = recovery(reqs, outs)
+    log("serving: Poisson %.0f/s -> p50 %.3f ms p99 %.3f ms, %.0f sFFTs/s" % (rate, st.p50_ms, st.p99_ms, st.rate))
+    srv.close()
+    err_all = err_s + err_p
+    return {"requests_per_phase": len(reqs), "capacity_sFFTs_per_s": round(capacity, 1),
+            "arrival_rate_per_s": round(rate, 1), "value": round(st.rate, 1), "unit": "sFFTs/s",
+            "p50_ms": round(st.p50_ms, 3), "p99_ms": round(st.p99_ms, 3),
+            "queue_p50_ms": round(st.queue_p50_ms, 3), "service_p50_ms": round(st.service_p50_ms, 3),
+            "mean_batch": round(st.mean_batch, 2), "dense_fallback": int(st.dense), "failed": int(st.failed),
+            "evictions": int(st.evictions), "peak_device_bytes": int(st.peak_bytes),
+            "max_submit_lag_ms": round(lag * 1e3, 3),
+            "exact_recovered": "%d/%d" % (ok_s + ok_p, n_s + n_p),
+            "exact_misses": misses,
+            "noisy_l2_rel_err_vs_planted": {"median": round(float(np.median(err_all)), 5) if err_all else None,
+                                            "max": round(float(np.max(err_all)), 5) if err_all else None,
+                                            "worst": worst},
+            "what": "Poisson stream, n in 2^16..2^24 log-uniform, k in [8,1024], 50/50 exact/noisy(0.05), "
+                    "complex64, per-request seeds; latency = submit -> results on the host"}
+
+
 def oracle_params(desc, seed):
     from oracle.params import SfftParams
     return SfftParams(n=desc.n, k=desc.k, B=desc.B, w=desc.w, seed=seed, alpha=desc.alpha, delta=desc.delta,
@@ -87,6 +202,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device-to-device tensor copy first (counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests per serving phase (0: skip the serving measurement)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="Poisson arrival rate as a fraction of the measured serving capacity")
     ap.add_argument("--config-key", action="store_true",
                     help="print the key that names this configuration in the traffic record, then exit")
     args = ap.parse_args()
@@ -271,6 +390,14 @@ def main():
                         "sample": "%d signals of the same workload, FP64 numpy oracle, one process" % nsig}
         log("oracle: %d signals in %.1fs, parity mismatches %d" % (nsig, t_cpu, mism))
 
+    # ---------------------------------------------------------------- serving
+    serving = None
+    if args.serve_requests > 0:
+        plan.close()
+        del X, bufs
+        torch.cuda.empty_cache()
+        serving = serving_bench(args, torch, dev, sfft)
+
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -302,6 +429,7 @@ def main():
         "parity": parity,
         "roofline": roofline,
         "cpu_baseline": cpu_baseline,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     plan.close()

@@ -99,7 +99,7 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *   patience  exact: stop after this many consecutive rounds whose bins are
  *             all below theta
  *   t, s      LocateInner regions per level and vote tolerance (Algorithm 3)
- *   R_loc     LocateInner measurements per level (Algorithm 3)
+ *   R_loc     LocateInner measurements per level (Algorithm 3), 1..8
  *   R_est     EstimateValues measurements per round (Algorithm 2), 1..32
  *   cap       output capacity (0 = k)
  *   flags     SFFT_FLAG_*

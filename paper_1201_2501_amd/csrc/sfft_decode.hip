@@ -794,133 +794,269 @@ __device__ __forceinline__ const double* gen_raw(const GeneralArgs& G, uint32_t 
     return G.raw + (((uint64_t)sig * G.nslots + slot) * 2 + a) * (uint64_t)G.Bmax * 2;
 }
 
-// One SparseFFT round (Algorithm 2): LocateSignal, EstimateValues, zhat update.
-__device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, uint32_t r, uint64_t seed) {
+// Term spill region of workgroup `part` of signal `sig` (parts: EstimateValues
+// hashings or re-estimation rounds), used when LDS cannot hold the terms.
+__device__ __forceinline__ double* gen_spill(const GeneralArgs& G, uint32_t sig, uint32_t part) {
+    return G.gterm + ((uint64_t)sig * G.nterm + part) * G.capz * 4;
+}
+
+// ---- SparseFFT round r (Algorithm 2), split into launches so that the
+// independent work of one round (bins of LocateSignal, hashings of
+// EstimateValues) spreads over many workgroups:
+//   stage (signal) -> locate (signal x bin chunk) -> select (signal)
+//   -> estimate (signal x hashing) -> merge (signal)
+
+// LocateSignal staging: for the round's permutation (sigma, b), every zhat
+// entry's G'_{-o(i)} zhat_i and sigma i mod n (HBM, [capz][4] doubles) and
+// the entries grouped by bin, ascending within a bin; the candidate counter
+// reset.
+__global__ void __launch_bounds__(kDec) k_gen_stage(GeneralArgs G, uint32_t r) {
+    extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x;
+    const uint32_t sig = blockIdx.x;
+    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, gen_spill(G, sig, 0), G.ecount + (uint64_t)sig * G.capz);
+    const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
+    load_state(L, G.state + (uint64_t)sig * kStateWords);
+    const uint64_t n = G.n, mask = n - 1;
+    const RoundDev g = G.geom[r];
+    const uint32_t B = g.B;
+    const uint32_t zc = stage_zhat(L, G.zidx, sig, G.capz);
+    const double* zv = G.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * G.capz * 2;
+    const uint64_t sigma = draw_sigma(seed, n, r, 0, 0);
+    const uint64_t b = draw_b(seed, n, r, 0, 0);
+    double* zt = G.gtmp + (uint64_t)sig * G.capz * 4;
+    uint64_t* zp = reinterpret_cast<uint64_t*>(zt);
+    for (uint32_t e = tid; e < zc; e += kDec) {
+        const uint64_t i = L.zl[e];
+        const BinOffset bo = bin_offset(i, sigma, b, n, B);
+        L.hk[e] = (uint16_t)bo.h;
+        const double gp = gprime(-bo.o, n, B, g.ws);
+        zt[4 * e] = gp * zv[2 * e];
+        zt[4 * e + 1] = gp * zv[2 * e + 1];
+        zp[4 * e + 2] = (sigma * i) & mask;
+    }
+    __syncthreads();
+    group_by_bin(L, zc, B);
+    uint32_t* first = G.gfirst + (uint64_t)sig * (G.Bmax + 1);
+    uint32_t* ent = G.gent + (uint64_t)sig * G.capz;
+    for (uint32_t h = tid; h <= B; h += kDec) first[h] = L.first[h];
+    for (uint32_t q = tid; q < zc; q += kDec) ent[q] = L.ent[q];
+    if (tid == 0) G.cand_cnt[sig] = 0;
+}
+
+// LocateSignal (Algorithm 3) with LocateInner at every level: one thread per
+// bin of round r's hashing, `chunks` workgroups per signal.  Each level
+// loads the bin's R_loc measurement pairs first, subtracts the zhat terms of
+// the bin (ascending index order), takes the phase of each pair and finds the
+// first of the t regions with a majority of votes; a bin that survives every
+// level appends its location.
+constexpr uint32_t kLoc = 256;
+
+__global__ void __launch_bounds__(kLoc) k_gen_locate(GeneralArgs G, uint32_t r, uint32_t chunks) {
+    const uint32_t sig = blockIdx.x / chunks;
+    const uint32_t j = (blockIdx.x - sig * chunks) * kLoc + threadIdx.x;
+    const RoundDev g = G.geom[r];
+    const uint32_t B = g.B;
+    if (j >= B) return;
+    const GenRoundDev& gr = G.groundv[r];
+    const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
+    const uint64_t n = G.n, mask = n - 1;
+    const uint64_t scale = 1ull << kFracBits;
+    const uint64_t modfp = n << kFracBits;
+    const uint64_t mmask = modfp - 1;
+    const double two_pi = 6.283185307179586;
+    // 2 pi num / modfp with modfp a power of two: the scaling is exact, so
+    // multiplying by 2 pi 2^-m rounds exactly as the division does
+    const double ang_scale = ldexp(two_pi, -(int)__builtin_ctzll(modfp));
+    const uint64_t sigma = draw_sigma(seed, n, r, 0, 0);
+    const uint64_t b = draw_b(seed, n, r, 0, 0);
+    const uint64_t sinv = inverse_odd(sigma) & mask;
+    const uint64_t sbs = ((sigma * b) & mask) << kFracBits;
+    const double tol = G.s * 3.141592653589793;
+    const double* zt = G.gtmp + (uint64_t)sig * G.capz * 4;
+    const uint64_t* zp = reinterpret_cast<const uint64_t*>(zt);
+    const uint32_t* ent = G.gent + (uint64_t)sig * G.capz;
+    const uint32_t q0 = G.gfirst[(uint64_t)sig * (G.Bmax + 1) + j];
+    const uint32_t q1 = G.gfirst[(uint64_t)sig * (G.Bmax + 1) + j + 1];
+    const uint32_t R_loc = G.R_loc, t = G.t;
+    uint64_t l = ((uint64_t)j * (n / B) * scale + modfp - (n / (2 * (uint64_t)B)) * scale) & mmask;
+    for (uint32_t D = 1; D <= gr.nlev; ++D) {
+        const uint64_t W = gr.Wfp[D - 1];
+        const uint64_t half = W / (2 * (uint64_t)t);
+        const uint64_t step = W / t;
+        double2 u0[kMaxRLoc], u1[kMaxRLoc];
+#pragma unroll
+        for (uint32_t q = 0; q < kMaxRLoc; ++q)
+            if (q < R_loc) {
+                const uint32_t slot = gr.slot0 + (D - 1) * R_loc + q;
+                u0[q] = reinterpret_cast<const double2*>(gen_raw(G, sig, slot, 0))[j];
+                u1[q] = reinterpret_cast<const double2*>(gen_raw(G, sig, slot, 1))[j];
+            }
+        double ph[kMaxRLoc];
+        uint64_t bet[kMaxRLoc];
+#pragma unroll
+        for (uint32_t q = 0; q < kMaxRLoc; ++q)
+            if (q < R_loc) {
+                const uint64_t a = draw_a(seed, n, r, D, q);
+                const uint64_t beta = draw_beta(seed, gr.blo[D - 1], gr.bhi[D - 1], r, D, q);
+                const uint64_t ab = (a + beta) & mask;
+                cx<double> u{u0[q].x, u0[q].y}, u2{u1[q].x, u1[q].y};
+                for (uint32_t qq = q0; qq < q1; ++qq) {
+                    const uint32_t e = ent[qq];
+                    const cx<double> c0{zt[4 * e], zt[4 * e + 1]};
+                    const uint64_t p = zp[4 * e + 2];
+                    u = csub(u, cmul(c0, omega_d((a * p) & mask, n)));
+                    u2 = csub(u2, cmul(c0, omega_d((ab * p) & mask, n)));
+                }
+                ph[q] = phase_of(u, u2);
+                bet[q] = beta;
+            }
+        uint32_t firstq = t;
+        for (uint32_t qq = 0; qq < t; ++qq) {
+            const uint64_t M = (l + (2 * (uint64_t)qq + 1) * half) & mmask;
+            uint32_t votes = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < kMaxRLoc; ++q)
+                if (q < R_loc) {
+                    const uint64_t num = (bet[q] * ((M + sbs) & mmask)) & mmask;
+                    const double ang = (double)num * ang_scale;
+                    const double d = fabs(ang - ph[q]);
+                    const double dist = d < two_pi - d ? d : two_pi - d;
+                    votes += dist < tol;
+                }
+            if (2u * votes > R_loc) {
+                firstq = qq;
+                break;
+            }
+        }
+        if (firstq == t) return;
+        l = (l + firstq * step) & mmask;
+    }
+    const uint64_t pos = ((l + scale - 1) >> kFracBits) & mask;
+    const uint32_t at = atomicAdd(&G.cand_cnt[sig], 1u);
+    G.cand_raw[(uint64_t)sig * G.Bmax + at] = (sinv * pos + b) & mask;
+}
+
+// The located candidates of a signal sorted, duplicates removed (G.cand_i,
+// count in G.cand_cnt); measurement masks cleared.
+__global__ void __launch_bounds__(kDec) k_gen_select(GeneralArgs G) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sig = blockIdx.x;
+    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, gen_spill(G, sig, 0), G.ecount + (uint64_t)sig * G.capz);
+    uint64_t* cand = G.cand_i + (uint64_t)sig * G.Bmax;
+    const uint32_t m = G.cand_cnt[sig];
+    const uint32_t NM = pow2_ceil_u32(m > 0 ? m : 1);
+    const uint64_t* raw = G.cand_raw + (uint64_t)sig * G.Bmax;
+    for (uint32_t q = tid; q < NM; q += kDec) L.ckey[q] = q < m ? raw[q] : kNone;
+    bitonic_sort_u64<kDec>(L.ckey, NM);
+    const uint32_t per = (m + kDec - 1) / kDec;
+    const uint32_t p0 = tid * per < m ? tid * per : m;
+    const uint32_t p1 = p0 + per < m ? p0 + per : m;
+    uint32_t cnt = 0;
+    for (uint32_t p = p0; p < p1; ++p) cnt += (p == 0 || L.ckey[p] != L.ckey[p - 1]);
+    uint32_t pre;
+    const uint32_t nL = wave_block_scan(cnt, L.scan, &pre);
+    for (uint32_t p = p0; p < p1; ++p)
+        if (p == 0 || L.ckey[p] != L.ckey[p - 1]) cand[pre++] = L.ckey[p];
+    uint32_t* mk = G.cand_n + (uint64_t)sig * G.Bmax;
+    for (uint32_t c = tid; c < nL; c += kDec) mk[c] = 0;
+    __syncthreads();
+    if (tid == 0) G.cand_cnt[sig] = nL;
+}
+
+// EstimateValues (Algorithm 2), hashing e of round r for every candidate of
+// one signal (one workgroup per signal and hashing): the estimate
+// (u_h - zhat terms of bin h) omega^{-a sigma i} / G'_{-o(i)} where
+// G' >= g_min, recorded in slot e with bit e of the candidate's mask.
+__global__ void __launch_bounds__(kDec) k_gen_estimate(GeneralArgs G, uint32_t r) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sig = blockIdx.x / G.R_est;
+    const uint32_t e = blockIdx.x - sig * G.R_est;
+    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, gen_spill(G, sig, e), G.ecount + (uint64_t)sig * G.capz);
+    const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
+    load_state(L, G.state + (uint64_t)sig * kStateWords);
+    const uint64_t n = G.n, mask = n - 1;
     const RoundDev g = G.geom[r];
     const GenRoundDev& gr = G.groundv[r];
-    const uint64_t n = G.n, mask = n - 1;
     const uint32_t B = g.B;
-    const uint32_t zc = round_zhat(L, G.zidx, sig, G.capz);
+    const uint32_t zc = stage_zhat(L, G.zidx, sig, G.capz);
     const double* zv = G.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * G.capz * 2;
-    uint64_t* cand = G.cand_i + (uint64_t)sig * G.Bmax;
-    double* candv = G.cand_v + (uint64_t)sig * G.Bmax * 2;
-    uint32_t* candn = G.cand_n + (uint64_t)sig * G.Bmax;
-    const double two_pi = 6.283185307179586;
-
-    // ---- LocateSignal (Algorithm 3): one (sigma, b); one thread per bin
-    // carries its region through every LocateInner level.
-    {
-        const uint64_t scale = 1ull << kFracBits;
-        const uint64_t modfp = n << kFracBits;
-        const uint64_t mmask = modfp - 1;
-        const uint64_t sigma = draw_sigma(seed, n, r, 0, 0);
-        const uint64_t b = draw_b(seed, n, r, 0, 0);
-        const uint64_t sinv = inverse_odd(sigma) & mask;
-        const uint64_t sbs = ((sigma * b) & mask) << kFracBits;
-        const double tol = G.s * 3.141592653589793;
-        bin_zhat(L, zc, sigma, b, n, B);
-        if (tid == 0) L.misc[0] = 0;
-        __syncthreads();
-        for (uint32_t j = tid; j < B; j += kDec) {
-            uint64_t l = ((uint64_t)j * (n / B) * scale + modfp - (n / (2 * (uint64_t)B)) * scale) & mmask;
-            bool alive = true;
-            for (uint32_t D = 1; D <= gr.nlev && alive; ++D) {
-                const uint64_t W = gr.Wfp[D - 1];
-                const uint64_t half = W / (2 * (uint64_t)G.t);
-                const uint64_t step = W / G.t;
-                uint8_t votes[kMaxT];
-                for (uint32_t qq = 0; qq < G.t; ++qq) votes[qq] = 0;
-                for (uint32_t q = 0; q < G.R_loc; ++q) {
-                    const uint64_t a = draw_a(seed, n, r, D, q);
-                    const uint64_t beta = draw_beta(seed, gr.blo[D - 1], gr.bhi[D - 1], r, D, q);
-                    const uint32_t slot = gr.slot0 + (D - 1) * G.R_loc + q;
-                    const cx<double> u = corrected_bin(L, gen_raw(G, sig, slot, 0), j, a, zv, sigma, b, n, B, g.ws);
-                    const cx<double> u2 =
-                        corrected_bin(L, gen_raw(G, sig, slot, 1), j, (a + beta) & mask, zv, sigma, b, n, B, g.ws);
-                    const double c = phase_of(u, u2);
-                    for (uint32_t qq = 0; qq < G.t; ++qq) {
-                        const uint64_t M = (l + (2 * (uint64_t)qq + 1) * half) & mmask;
-                        const uint64_t num = (beta * ((M + sbs) & mmask)) & mmask;
-                        const double ang = two_pi * (double)num / (double)modfp;
-                        const double d = fabs(ang - c);
-                        const double dist = d < two_pi - d ? d : two_pi - d;
-                        votes[qq] += dist < tol;
-                    }
-                }
-                uint32_t firstq = G.t;
-                for (uint32_t qq = 0; qq < G.t; ++qq)
-                    if (2u * votes[qq] > G.R_loc) {
-                        firstq = qq;
-                        break;
-                    }
-                if (firstq == G.t) alive = false;
-                else l = (l + firstq * step) & mmask;
-            }
-            if (alive) {
-                const uint64_t pos = ((l + scale - 1) >> kFracBits) & mask;
-                L.ckey[atomicAdd(&L.misc[0], 1u)] = (sinv * pos + b) & mask;
-            }
-        }
+    const uint64_t sigma = draw_sigma(seed, n, r, LEVEL_EST, e);
+    const uint64_t a = draw_a(seed, n, r, LEVEL_EST, e);
+    const uint64_t b = draw_b(seed, n, r, LEVEL_EST, e);
+    const uint64_t as = (a * sigma) & mask;
+    const double* rawv = gen_raw(G, sig, gr.slot0 + gr.nloc + e, 0);
+    for (uint32_t q = tid; q < zc; q += kDec) {
+        const uint64_t i = L.zl[q];
+        const BinOffset bo = bin_offset(i, sigma, b, n, B);
+        L.hk[q] = (uint16_t)bo.h;
+        const double gp = gprime(-bo.o, n, B, g.ws);
+        const cx<double> c0{gp * zv[2 * q], gp * zv[2 * q + 1]};
+        L.t[2 * q] = cmul(c0, omega_d((as * i) & mask, n));
     }
     __syncthreads();
-    // L: sorted, unique candidate indices
-    uint32_t nL;
-    {
-        const uint32_t m = L.misc[0];
-        const uint32_t NM = pow2_ceil_u32(m > 0 ? m : 1);
-        for (uint32_t q = m + tid; q < NM; q += kDec) L.ckey[q] = kNone;
-        bitonic_sort_u64<kDec>(L.ckey, NM);
-        const uint32_t per = (m + kDec - 1) / kDec;
-        const uint32_t p0 = tid * per < m ? tid * per : m;
-        const uint32_t p1 = p0 + per < m ? p0 + per : m;
-        uint32_t cnt = 0;
-        for (uint32_t p = p0; p < p1; ++p) cnt += (p == 0 || L.ckey[p] != L.ckey[p - 1]);
-        uint32_t pre;
-        nL = wave_block_scan(cnt, L.scan, &pre);
-        for (uint32_t p = p0; p < p1; ++p)
-            if (p == 0 || L.ckey[p] != L.ckey[p - 1]) cand[pre++] = L.ckey[p];
-        __syncthreads();
-    }
-
-    // ---- EstimateValues (Algorithm 2): R_est fresh hashings, medians
-    for (uint32_t c = tid; c < nL; c += kDec) candn[c] = 0;
-    for (uint32_t e = 0; e < G.R_est; ++e) {
-        const uint64_t sigma = draw_sigma(seed, n, r, LEVEL_EST, e);
-        const uint64_t a = draw_a(seed, n, r, LEVEL_EST, e);
-        const uint64_t b = draw_b(seed, n, r, LEVEL_EST, e);
-        const double* rawv = gen_raw(G, sig, gr.slot0 + gr.nloc + e, 0);
-        __syncthreads();
-        bin_zhat(L, zc, sigma, b, n, B);
-        for (uint32_t c = tid; c < nL; c += kDec) {
-            const uint64_t i = cand[c];
-            const BinOffset bo = bin_offset(i, sigma, b, n, B);
-            const double gp = gprime(-bo.o, n, B, g.ws);
-            if (gp < G.g_min) continue;
-            const cx<double> u = corrected_bin(L, rawv, bo.h, a, zv, sigma, b, n, B, g.ws);
-            const uint64_t p = (((a * sigma) & mask) * i) & mask;
-            const cx<double> v = cmul(u, omega_d((n - p) & mask, n));
-            const uint32_t k = candn[c];
-            double* dst = G.cand_e + (((uint64_t)sig * G.Bmax + c) * G.R_est + k) * 2;
-            dst[0] = v.r / gp;
-            dst[1] = v.i / gp;
-            candn[c] = k + 1;
-        }
-    }
-    __syncthreads();
+    group_by_bin(L, zc, B);
+    const uint32_t nL = G.cand_cnt[sig];
+    const uint64_t* cand = G.cand_i + (uint64_t)sig * G.Bmax;
+    uint32_t* mk = G.cand_n + (uint64_t)sig * G.Bmax;
     for (uint32_t c = tid; c < nL; c += kDec) {
-        const uint32_t k = candn[c];
+        const uint64_t i = cand[c];
+        const BinOffset bo = bin_offset(i, sigma, b, n, B);
+        const double gp = gprime(-bo.o, n, B, g.ws);
+        if (gp < G.g_min) continue;
+        const uint32_t h = bo.h;
+        cx<double> u{rawv[2 * h], rawv[2 * h + 1]};
+        for (uint32_t q = L.first[h]; q < L.first[h + 1]; ++q) u = csub(u, L.t[2 * L.ent[q]]);
+        const uint64_t p = (as * i) & mask;
+        const cx<double> v = cmul(u, omega_d((n - p) & mask, n));
+        double* dst = G.cand_e + (((uint64_t)sig * G.Bmax + c) * G.R_est + e) * 2;
+        dst[0] = v.r / gp;
+        dst[1] = v.i / gp;
+        atomicOr(&mk[c], 1u << e);
+    }
+}
+
+// Medians of each candidate's estimates, the top 3 k_r by (|w| desc, index
+// asc), and their merge into zhat (one workgroup per signal).
+__global__ void __launch_bounds__(kDec) k_gen_merge(GeneralArgs G, uint32_t r) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sig = blockIdx.x;
+    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, gen_spill(G, sig, 0), G.ecount + (uint64_t)sig * G.capz);
+    uint32_t* st = G.state + (uint64_t)sig * kStateWords;
+    load_state(L, st);
+    const GenRoundDev& gr = G.groundv[r];
+    stage_zhat(L, G.zidx, sig, G.capz);
+    const uint32_t nL = G.cand_cnt[sig];
+    const uint64_t* cand = G.cand_i + (uint64_t)sig * G.Bmax;
+    double* candv = G.cand_v + (uint64_t)sig * G.Bmax * 2;
+    uint32_t* mk = G.cand_n + (uint64_t)sig * G.Bmax;
+    for (uint32_t c = tid; c < nL; c += kDec) {
+        // the valid estimates to the front, in hashing order
+        double* src = G.cand_e + ((uint64_t)sig * G.Bmax + c) * G.R_est * 2;
+        const uint32_t bits = mk[c];
+        uint32_t k = 0;
+        for (uint32_t e = 0; e < G.R_est; ++e)
+            if (bits & (1u << e)) {
+                if (k != e) {
+                    src[2 * k] = src[2 * e];
+                    src[2 * k + 1] = src[2 * e + 1];
+                }
+                ++k;
+            }
+        mk[c] = k;
         if (k == 0) continue;
-        const cx<double> med = median_cx<kMaxREst>(G.cand_e + (((uint64_t)sig * G.Bmax + c) * G.R_est) * 2, k);
+        const cx<double> med = median_cx<kMaxREst>(src, k);
         candv[2 * c] = med.r;
         candv[2 * c + 1] = med.i;
     }
     __syncthreads();
-    // top-k' by (|w| desc, index asc); candidates are in index order
     const uint32_t kprime = 3 * gr.k_r;
     const uint32_t NL = pow2_ceil_u32(nL > 0 ? nL : 1);
     for (uint32_t c = tid; c < NL; c += kDec)
-        L.ckey[c] = (c < nL && candn[c] > 0) ? mag_key(candv[2 * c], candv[2 * c + 1], c) : kNone;
+        L.ckey[c] = (c < nL && mk[c] > 0) ? mag_key(candv[2 * c], candv[2 * c + 1], c) : kNone;
     bitonic_sort_u64<kDec>(L.ckey, NL);
     uint32_t take = 0;
     {
@@ -932,7 +1068,6 @@ __device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, 
         __syncthreads();
         take = L.misc[1];
     }
-    // selected entries occupy ckey[0, take); rewrite them as index keys
     for (uint32_t q = tid; q < take; q += kDec) {
         const uint32_t c = (uint32_t)(L.ckey[q] & kSlotMask);
         L.ckey[q] = (cand[c] << kCandShift) | c;
@@ -943,90 +1078,110 @@ __device__ void general_round(const GeneralArgs& G, DecodeLds& L, uint32_t sig, 
         L.sw[ST_ROUNDS] = r + 1;
         L.sw[ST_LASTJ] = nL;
     }
-    __syncthreads();
-}
-
-__global__ void __launch_bounds__(kDec) k_general_decode(GeneralArgs G, uint32_t r_begin, uint32_t r_end) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const uint32_t sig = blockIdx.x;
-    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, G.gtmp + (uint64_t)sig * G.capz * 4, G.ecount + (uint64_t)sig * G.capz);
-    const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
-    uint32_t* st = G.state + (uint64_t)sig * kStateWords;
-    load_state(L, st);
-    stage_zhat(L, G.zidx, sig, G.capz);
-    for (uint32_t r = r_begin; r < r_end; ++r) {
-        __syncthreads();
-        general_round(G, L, sig, r, seed);
-    }
     store_state(L, st);
 }
 
-// FP64 re-estimation over every EstimateValues hashing of every round
-// (isolated measurements first), then the top-cap entries by magnitude in
-// ascending index order.
-__global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
+// Final FP64 re-estimation, round r (one workgroup per signal and round): for
+// each EstimateValues hashing of the round, every zhat entry's estimate with
+// the other entries of its bin removed, flagged isolated (alone in its bin) or
+// crowded.
+__global__ void __launch_bounds__(kDec) k_gen_reest(GeneralArgs G) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sig = blockIdx.x / G.R;
+    const uint32_t r = blockIdx.x - sig * G.R;
+    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, gen_spill(G, sig, r), G.ecount + (uint64_t)sig * G.capz);
+    const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
+    load_state(L, G.state + (uint64_t)sig * kStateWords);
+    if (r >= L.sw[ST_ROUNDS]) return;
+    const uint64_t n = G.n, mask = n - 1;
+    const RoundDev g = G.geom[r];
+    const GenRoundDev& gr = G.groundv[r];
+    const uint32_t B = g.B;
+    const uint32_t zc = stage_zhat(L, G.zidx, sig, G.capz);
+    const double* zv = G.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * G.capz * 2;
+    const uint32_t nmeas = G.R * G.R_est;
+    double* est = G.est + (uint64_t)sig * G.capz * nmeas * 2;
+    uint8_t* flag = G.eflag + (uint64_t)sig * G.capz * nmeas;
+    for (uint32_t m = 0; m < G.R_est; ++m) {
+        const uint64_t sigma = draw_sigma(seed, n, r, LEVEL_EST, m);
+        const uint64_t a = draw_a(seed, n, r, LEVEL_EST, m);
+        const uint64_t b = draw_b(seed, n, r, LEVEL_EST, m);
+        const double* rawv = gen_raw(G, sig, gr.slot0 + gr.nloc + m, 0);
+        const uint64_t as = (a * sigma) & mask;
+        const uint32_t meas = r * G.R_est + m;
+        __syncthreads();
+        // t[2e] = G' zhat_e omega^{a sigma i_e}, t[2e+1].r = G' of entry e
+        for (uint32_t e = tid; e < zc; e += kDec) {
+            const BinOffset bo = bin_offset(L.zl[e], sigma, b, n, B);
+            L.hk[e] = (uint16_t)bo.h;
+            const double gp = gprime(-bo.o, n, B, g.ws);
+            const cx<double> c0{gp * zv[2 * e], gp * zv[2 * e + 1]};
+            L.t[2 * e] = cmul(c0, omega_d((as * L.zl[e]) & mask, n));
+            L.t[2 * e + 1] = cx<double>{gp, 0.0};
+        }
+        __syncthreads();
+        group_by_bin(L, zc, B);
+        for (uint32_t e = tid; e < zc; e += kDec) {
+            const double ge = L.t[2 * e + 1].r;
+            if (ge < G.g_min) {
+                flag[(uint64_t)e * nmeas + meas] = 0;
+                continue;
+            }
+            const uint32_t h = L.hk[e];
+            const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
+            cx<double> others{0.0, 0.0};
+            for (uint32_t q = p0; q < p1; ++q) {
+                const uint32_t e2 = L.ent[q];
+                if (e2 == e) continue;
+                others = cadd(others, L.t[2 * e2]);
+            }
+            const cx<double> u = csub(cx<double>{rawv[2 * h], rawv[2 * h + 1]}, others);
+            const uint64_t pe = (as * L.zl[e]) & mask;
+            const cx<double> v = cmul(u, omega_d((n - pe) & mask, n));
+            double* dst = est + ((uint64_t)e * nmeas + meas) * 2;
+            dst[0] = v.r / ge;
+            dst[1] = v.i / ge;
+            flag[(uint64_t)e * nmeas + meas] = p1 - p0 == 1 ? 1 : 2;
+        }
+    }
+}
+
+// Medians over every entry's re-estimation samples (isolated ones when there
+// are any, else the crowded ones), then the top-cap entries by magnitude in
+// ascending index order (one workgroup per signal).
+__global__ void __launch_bounds__(kDec) k_gen_output(GeneralArgs G) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x;
     const uint32_t sig = blockIdx.x;
-    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, G.gtmp + (uint64_t)sig * G.capz * 4, G.ecount + (uint64_t)sig * G.capz);
-    const uint64_t seed = G.seeds ? G.seeds[sig] : G.plan_seed;
+    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, gen_spill(G, sig, 0), G.ecount + (uint64_t)sig * G.capz);
     uint32_t* st = G.state + (uint64_t)sig * kStateWords;
-    const uint64_t n = G.n, mask = n - 1;
     load_state(L, st);
     const uint32_t R = L.sw[ST_ROUNDS];
     const uint32_t zc = stage_zhat(L, G.zidx, sig, G.capz);
     const uint64_t* zi = G.zidx + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * G.capz;
     const double* zv = G.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * G.capz * 2;
     const uint32_t nmeas = G.R * G.R_est;
+    const uint32_t used = (R < G.R ? R : G.R) * G.R_est;
     double* est = G.est + (uint64_t)sig * G.capz * nmeas * 2;
-    uint32_t* ecount = L.ec;
+    const uint8_t* flag = G.eflag + (uint64_t)sig * G.capz * nmeas;
     double* fin = G.fin + (uint64_t)sig * G.capz * 2;
-    for (uint32_t e = tid; e < zc; e += kDec) ecount[e] = 0;
-    for (uint32_t r = 0; r < R; ++r) {
-        const RoundDev g = G.geom[r];
-        const GenRoundDev& gr = G.groundv[r];
-        const uint32_t B = g.B;
-        for (uint32_t m = 0; m < G.R_est; ++m) {
-            const uint64_t sigma = draw_sigma(seed, n, r, LEVEL_EST, m);
-            const uint64_t a = draw_a(seed, n, r, LEVEL_EST, m);
-            const uint64_t b = draw_b(seed, n, r, LEVEL_EST, m);
-            const double* rawv = gen_raw(G, sig, gr.slot0 + gr.nloc + m, 0);
-            const uint64_t as = (a * sigma) & mask;
-            __syncthreads();
-            // t[2e] = G' zhat_e omega^{a sigma i_e}, t[2e+1].r = G' of entry e
-            for (uint32_t e = tid; e < zc; e += kDec) {
-                const BinOffset bo = bin_offset(L.zl[e], sigma, b, n, B);
-                L.hk[e] = (uint16_t)bo.h;
-                const double gp = gprime(-bo.o, n, B, g.ws);
-                const cx<double> c0{gp * zv[2 * e], gp * zv[2 * e + 1]};
-                L.t[2 * e] = cmul(c0, omega_d((as * L.zl[e]) & mask, n));
-                L.t[2 * e + 1] = cx<double>{gp, 0.0};
-            }
-            __syncthreads();
-            group_by_bin(L, zc, B);
-            for (uint32_t e = tid; e < zc; e += kDec) {
-                const double ge = L.t[2 * e + 1].r;
-                if (ge < G.g_min) continue;
-                const uint32_t h = L.hk[e];
-                const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
-                cx<double> others{0.0, 0.0};
-                for (uint32_t q = p0; q < p1; ++q) {
-                    const uint32_t e2 = L.ent[q];
-                    if (e2 == e) continue;
-                    others = cadd(others, L.t[2 * e2]);
-                }
-                const cx<double> u = csub(cx<double>{rawv[2 * h], rawv[2 * h + 1]}, others);
-                const uint64_t pe = (as * L.zl[e]) & mask;
-                const cx<double> v = cmul(u, omega_d((n - pe) & mask, n));
-                push_sample(est + (uint64_t)e * nmeas * 2, nmeas, &ecount[e], p1 - p0 == 1,
-                            cx<double>{v.r / ge, v.i / ge});
-            }
-        }
-    }
-    __syncthreads();
     for (uint32_t e = tid; e < zc; e += kDec) {
-        const cx<double> v = entry_median<kMaxMeas>(est + (uint64_t)e * nmeas * 2, nmeas, ecount[e],
-                                          cx<double>{zv[2 * e], zv[2 * e + 1]});
+        const uint8_t* fl = flag + (uint64_t)e * nmeas;
+        double* src = est + (uint64_t)e * nmeas * 2;
+        uint32_t na = 0;
+        for (uint32_t q = 0; q < used; ++q) na += fl[q] == 1;
+        const uint8_t want = na ? 1 : 2;
+        uint32_t c = 0;
+        for (uint32_t q = 0; q < used; ++q)
+            if (fl[q] == want) {
+                if (c != q) {
+                    src[2 * c] = src[2 * q];
+                    src[2 * c + 1] = src[2 * q + 1];
+                }
+                ++c;
+            }
+        const cx<double> v = c ? median_cx<kMaxMeas>(src, c) : cx<double>{zv[2 * e], zv[2 * e + 1]};
         fin[2 * e] = v.r;
         fin[2 * e + 1] = v.i;
     }
@@ -1039,7 +1194,7 @@ __global__ void __launch_bounds__(kDec) k_general_finish(GeneralArgs G) {
         G.out_count[sig] = nout;
         if (G.out_info) {
             G.out_info[(uint64_t)sig * 4 + SFFT_INFO_ROUNDS] = R;
-            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_FLAGS] = L.sw[ST_FLAGS];
+            G.out_info[(uint64_t)sig * 4 + SFFT_INFO_FLAGS] = flags;
             G.out_info[(uint64_t)sig * 4 + SFFT_INFO_ZHAT] = zc;
             G.out_info[(uint64_t)sig * 4 + SFFT_INFO_LOCATED] = L.sw[ST_LASTJ];
         }
@@ -1070,17 +1225,37 @@ hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s) {
 
 hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_t r_end, hipStream_t s) {
     const size_t lds = decode_lds_bytes(a.capz, a.Bmax);
-    hipError_t e = allow_lds(k_general_decode, lds);
+    for (auto k : {k_gen_stage, k_gen_merge}) {
+        hipError_t e = allow_lds(k, lds);
+        if (e != hipSuccess) return e;
+    }
+    for (auto k : {k_gen_select, k_gen_reest, k_gen_output}) {
+        hipError_t e = allow_lds(k, lds);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = allow_lds(k_gen_estimate, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_general_decode, dim3(a.count), dim3(kDec), lds, s, a, r_begin, r_end);
-    return hipGetLastError();
+    const uint32_t chunks = (a.Bmax + kLoc - 1) / kLoc;
+    for (uint32_t r = r_begin; r < r_end; ++r) {
+        hipLaunchKernelGGL(k_gen_stage, dim3(a.count), dim3(kDec), lds, s, a, r);
+        hipLaunchKernelGGL(k_gen_locate, dim3(a.count * chunks), dim3(kLoc), 0, s, a, r, chunks);
+        hipLaunchKernelGGL(k_gen_select, dim3(a.count), dim3(kDec), lds, s, a);
+        hipLaunchKernelGGL(k_gen_estimate, dim3(a.count * a.R_est), dim3(kDec), lds, s, a, r);
+        hipLaunchKernelGGL(k_gen_merge, dim3(a.count), dim3(kDec), lds, s, a, r);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s) {
     const size_t lds = decode_lds_bytes(a.capz, a.Bmax);
-    hipError_t e = allow_lds(k_general_finish, lds);
+    hipError_t e = allow_lds(k_gen_reest, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_general_finish, dim3(a.count), dim3(kDec), lds, s, a);
+    e = allow_lds(k_gen_output, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gen_reest, dim3(a.count * a.R), dim3(kDec), lds, s, a);
+    hipLaunchKernelGGL(k_gen_output, dim3(a.count), dim3(kDec), lds, s, a);
     return hipGetLastError();
 }
 

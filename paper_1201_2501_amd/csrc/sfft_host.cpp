@@ -162,6 +162,12 @@ struct sfft_plan_s {
     double* est = nullptr;
     double* fin = nullptr;
     double* gtmp = nullptr;
+    uint32_t* gfirst = nullptr;
+    uint32_t* gent = nullptr;
+    uint64_t* cand_raw = nullptr;
+    uint32_t* cand_cnt = nullptr;
+    uint8_t* eflag = nullptr;
+    double* gterm = nullptr;
     uint32_t* ecount = nullptr;
     uint32_t* state = nullptr;
     // plain-path workspace (one signal)
@@ -378,6 +384,12 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     if (general_mode(p)) {
         ST_TRY(dev_alloc(p, &p->cand_e, S * d.R_est * 2 * Bm));
         ST_TRY(dev_alloc(p, &p->cand_n, S * Bm));
+        ST_TRY(dev_alloc(p, &p->gfirst, S * (Bm + 1)));
+        ST_TRY(dev_alloc(p, &p->gent, S * Z));
+        ST_TRY(dev_alloc(p, &p->cand_raw, S * Bm));
+        ST_TRY(dev_alloc(p, &p->cand_cnt, S));
+        ST_TRY(dev_alloc(p, &p->eflag, S * Z * meas));
+        ST_TRY(dev_alloc(p, &p->gterm, S * std::max<size_t>(R, d.R_est) * Z * 4));
     }
     ST_TRY(dev_alloc(p, &p->work, S * 4 * Bm));
     ST_TRY(dev_alloc(p, &p->cand_i, S * Bm));
@@ -505,6 +517,13 @@ GeneralArgs base_general(const sfft_plan_s* p, uint32_t count, const uint64_t* s
     G.fin = p->fin;
     G.gtmp = p->gtmp;
     G.ecount = p->ecount;
+    G.gfirst = p->gfirst;
+    G.gent = p->gent;
+    G.cand_raw = p->cand_raw;
+    G.cand_cnt = p->cand_cnt;
+    G.eflag = p->eflag;
+    G.gterm = p->gterm;
+    G.nterm = std::max<uint32_t>(p->R, p->d.R_est);
     G.state = p->state;
     G.out_idx = oidx;
     G.out_val = oval;
@@ -577,6 +596,12 @@ void offset_general(const sfft_plan_s* p, GeneralArgs& G, uint32_t off) {
     G.fin += o * 2 * Z;
     G.gtmp += o * Z * 4;
     G.ecount += o * Z;
+    G.gfirst += o * (Bm + 1);
+    G.gent += o * Z;
+    G.cand_raw += o * Bm;
+    G.cand_cnt += o;
+    G.eflag += o * Z * meas;
+    G.gterm += o * std::max<uint64_t>(p->R, p->d.R_est) * Z * 4;
     G.state += o * kStateWords;
     if (G.seeds) G.seeds += o;
     G.out_idx += o * p->cap;
@@ -754,9 +779,9 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     const uint32_t cap = d->cap ? d->cap : d->k;
     if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");
     if (d->mode == SFFT_MODE_GENERAL) {
-        if (d->t < 4 || d->t > kMaxT || !is_pow2(d->t) || d->R_loc < 1 || d->R_loc > 255 || d->R_est < 1 ||
+        if (d->t < 4 || d->t > kMaxT || !is_pow2(d->t) || d->R_loc < 1 || d->R_loc > kMaxRLoc || d->R_est < 1 ||
             d->R_est > kMaxREst || !(d->s > 0 && d->s < 1))
-            return fail(SFFT_EINVAL, "bad LocateInner/EstimateValues parameters (t a power of two in [4, 64], R_est in [1, 32])");
+            return fail(SFFT_EINVAL, "bad LocateInner/EstimateValues parameters (t a power of two in [4, 64], R_loc in [1, 8], R_est in [1, 32])");
         const uint32_t R = d->rounds ? d->rounds : 5;
         if ((uint64_t)R * d->R_est > 64) return fail(SFFT_EINVAL, "rounds * R_est must be at most 64");
         if (4ull * std::max<uint32_t>(d->k, 16u) > kMaxZ) return fail(SFFT_EUNSUPPORTED, "general mode needs k <= 1024");

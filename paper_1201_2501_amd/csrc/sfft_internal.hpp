@@ -44,6 +44,7 @@ constexpr uint32_t kMaxLevels = 24;
 constexpr uint32_t kFracBits = 8;          // fixed-point bits of region coordinates
 constexpr uint32_t kMaxT = 64;             // LocateInner regions per level
 constexpr uint32_t kMaxREst = 32;          // EstimateValues hashings per round
+constexpr uint32_t kMaxRLoc = 8;           // LocateInner measurements per level
 
 // One SparseFFT round (Algorithm 2) of the general mode.
 struct GenRoundDev {
@@ -158,9 +159,16 @@ struct GeneralArgs {
     double* zval;                // [sig][2][capz][2]
     double* est;                 // [sig][capz][R * R_est][2]
     double* fin;                 // [sig][capz][2]
-    double* gtmp;                // [sig][capz][4] per-entry terms when LDS cannot hold them
+    double* gtmp;                // [sig][capz][4] per-entry terms of the LocateSignal hashing
     uint32_t* ecount;            // [sig][capz]
     uint32_t* state;             // [sig][kStateWords]
+    uint32_t* gfirst;            // [sig][Bmax + 1] LocateSignal grouping: first entry of each bin
+    uint32_t* gent;              // [sig][capz] entries grouped by bin (ascending within a bin)
+    uint64_t* cand_raw;          // [sig][Bmax] located candidates in arrival order
+    uint32_t* cand_cnt;          // [sig] located candidates, then distinct candidates
+    uint8_t* eflag;              // [sig][capz][R * R_est] re-estimation sample: 0 none, 1 isolated, 2 crowded
+    double* gterm;               // [sig][nterm][capz][4] term spill of the per-hashing workgroups
+    uint32_t nterm;              // max(R, R_est)
     uint64_t* out_idx;
     double* out_val;
     uint32_t* out_count;
@@ -175,6 +183,8 @@ hipError_t launch_exact_init(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_exact_decode(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s);
 
+// general mode: every round [r_begin, r_end) as stage, locate, select,
+// estimate and merge launches; the finish as re-estimation and output
 hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_t r_end, hipStream_t s);
 hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s);
 

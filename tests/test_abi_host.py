@@ -95,3 +95,14 @@ def test_plan_queries_reject_null_plan():
     assert lib.sfft_plan_round_groups(None, None, 0, ctypes.byref(ng)) == sfft.SFFT_EINVAL
     assert ng.value == 99
     assert lib.sfft_plan_h2b_bytes(None, 4) == 0
+
+
+def test_general_mode_measurement_limits():
+    d = sfft.sfft_desc_init(1 << 20, 64, 1024, 0, 7)
+    d.mode = sfft.SFFT_MODE_GENERAL
+    d.R_loc = 8
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK
+    d.R_loc = 9
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
+    d.R_loc, d.R_est, d.rounds = 3, 33, 1
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
