@@ -147,3 +147,53 @@ def test_batched_general_raw_slots_match_oracle(torch_dev):
         assert np.abs(g0 - e0).max() <= 1e-12 * np.abs(e0).max(), ("est", e)
         slot += 1
     plan.close()
+
+
+def test_c4_shape_raw_hashings_and_recovery(torch_dev):
+    """n = 2^26, k = 1024, unit magnitudes with 1% noise, B = 4096 (default
+    rounds, FP64 location pairs): round 0's first LocateInner pair and first
+    EstimateValues hashing of signal 0 against the oracle at full size, then
+    supports equal to the planted ones for each signal, l2/l2 <= 2 for the
+    first."""
+    from oracle.general import beta_range, level_widths
+    from oracle.hashing import hash_to_bins_raw
+    from oracle.rng import LEVEL_EST, draw_a, draw_b, draw_beta, draw_sigma
+    from oracle.window import window_time
+    torch, dev = torch_dev
+    n, k, B, count = 1 << 26, 1024, 4096, 2
+    say("c4-shape", "n", n, "k", k, "B", B, "count", count)
+    X, sups, vals = siggen.torch_planted_batch(n, k, [91_000 + s for s in range(count)], dev, magnitude="unit",
+                                               noise_ratio=0.01, chunk=1)
+    seeds = [17, 29]
+    plan = make_plan(n, k, B, 0, 1, max_batch=count, delta=1e-7)
+    d = plan.desc
+    assert d.rounds == 7
+    bufs = plan.execute_batch(X, torch.tensor(seeds, dtype=torch.int64, device=dev))
+    torch.cuda.synchronize()
+    x0 = X[0].cpu().numpy()
+    G = window_time(n, B, d.w, d.alpha, d.delta)
+    sigma, b = draw_sigma(seeds[0], n, 0, 0, 0), draw_b(seeds[0], n, 0, 0, 0)
+    W = level_widths(n, B, d.t)[0]
+    lo, hi = beta_range(n, W, d.t, d.s)
+    a, beta = draw_a(seeds[0], n, 0, 1, 0), draw_beta(seeds[0], lo, hi, 0, 1, 0)
+    g0, g1 = plan.raw_slot(0, 0, dev)
+    e0 = hash_to_bins_raw(x0, sigma, a, b, B, G)
+    e1 = hash_to_bins_raw(x0, sigma, (a + beta) % n, b, B, G)
+    sc = max(np.abs(e0).max(), np.abs(e1).max())
+    assert np.abs(g0 - e0).max() <= 1e-12 * sc and np.abs(g1 - e1).max() <= 1e-12 * sc
+    nloc = len(level_widths(n, B, d.t)) * d.R_loc
+    se, ae, be = (draw_sigma(seeds[0], n, 0, LEVEL_EST, 0), draw_a(seeds[0], n, 0, LEVEL_EST, 0),
+                  draw_b(seeds[0], n, 0, LEVEL_EST, 0))
+    g2, _ = plan.raw_slot(0, nloc, dev)
+    e2 = hash_to_bins_raw(x0, se, ae, be, B, G)
+    rel = 1e-12 if d.est_prec == 1 else 2e-5
+    assert np.abs(g2 - e2).max() <= rel * np.abs(e2).max()
+    for s in range(count):
+        c = int(bufs["counts"][s])
+        idx = bufs["idx"][s, :c].cpu().numpy()
+        v = bufs["val"][s, :c].cpu().numpy()
+        assert np.array_equal(idx, np.sort(sups[s]))
+        if s == 0:   # the oracle's own FFT at 2^26 points takes most of a minute
+            ratio, _ = l2l2_ratio(X[s].cpu().numpy(), k, idx, v)
+            assert ratio <= 2.0, ratio
+    plan.close()
