@@ -254,3 +254,33 @@ def test_c3_round_groups_skip_only_undecoded_rounds(torch_dev):
         used.append(ref.rounds_used)
     assert len({next(e for e in [8, 10, 12, 16] if e >= r) for r in used}) >= 2, used
     plan.close()
+
+
+@pytest.mark.parametrize("n,k,B", [(1 << 18, 64, 256), (1 << 20, 256, 1024)])
+def test_section5_reduction_k_point_dft(torch_dev, n, k, B):
+    """Section 5: the k-point DFT of x_k through the n-point exact sFFT of its
+    periodic extension y_t = x_{t mod k}, whose spectrum is sqrt(n/k) x_k-hat
+    on the multiples of n/k.  The lattice support puts every coefficient at
+    the same offset within its bin in a round (all decoded or none), a
+    structured case of the method: batched GPU = oracle, and = a direct
+    k-point DFT."""
+    torch, dev = torch_dev
+    count = 3
+    say("section5", "n", n, "k", k, "B", B, "count", count)
+    ys, xks = zip(*[siggen.periodic_signal(n, k, 40 + s) for s in range(count)])
+    expect_idx = np.arange(k) * (n // k)
+    w = default_w(n, B, 0.5, 1e-12)
+    theta = 0.05 * min(np.min(np.abs(np.fft.fft(xk) / np.sqrt(k) * np.sqrt(n / k))) for xk in xks)
+    # all coefficients vanish together when the shared offset falls where G'
+    # is near 0 (about 22% of offsets at alpha = 1/2): patience 6 makes an
+    # empty stop at the start (0.22^6) negligible
+    plan = plan_for(n, k, B, w, 0, delta=1e-12, theta=theta, in_dtype=1, loc_prec=1, max_batch=count, patience=6)
+    seeds = [3 + s for s in range(count)]
+    out = run_batch(torch, dev, plan, list(ys), seeds)
+    for s in range(count):
+        ref = noiseless_sparse_fft(ys[s], oracle_params(plan, seeds[s]))
+        compare(out[s][0], out[s][1], ref)
+        expect_val = np.sqrt(n / k) * np.fft.fft(xks[s]) / np.sqrt(k)
+        assert np.array_equal(out[s][0], expect_idx)
+        assert np.max(np.abs(out[s][1] - expect_val)) <= 1e-9 * np.max(np.abs(expect_val))
+    plan.close()
