@@ -299,7 +299,7 @@ uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
  *   * a request (n, k, mode) maps to a shape: k rounded up to a power of two
  *     (at least 8), B = 4k' (exact) or 16k' (general) within [64 or 256,
  *     min(4096, n/16)], the default window for the mode's delta; exact shapes
- *     use b_min = max(8, B/32), at most 24 rounds and patience 5.  Where that window
+ *     use b_min = max(32, B/32) (at most B), at most 24 rounds and patience 5.  Where that window
  *     would cover the whole signal (w >= n) the request takes the dense path:
  *     a full-length FP32 FFT (hipFFT, loaded on first use) and the k bins of
  *     largest magnitude (exact mode: those above theta/2);

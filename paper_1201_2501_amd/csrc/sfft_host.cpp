@@ -35,7 +35,6 @@ sfft_status_t fail(sfft_status_t s, const std::string& msg) {
 
 bool is_pow2(uint64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
 
-
 uint32_t log2u(uint64_t v) {
     uint32_t l = 0;
     while ((1ull << l) < v) ++l;

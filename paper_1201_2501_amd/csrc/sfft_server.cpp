@@ -78,7 +78,9 @@ sfft_status_t shape_for(uint64_t n, uint32_t k, int32_t mode, const sfft_server_
         // is near 0 (about 22% of offsets at alpha = 1/2); five empty rounds
         // before stopping make losing one to that negligible (on the oracle
         // at n = 2^20, k = 600: 797/800 supports exact with 3, 800/800 with 5).
-        d->b_min = std::max<uint32_t>(8, (uint32_t)B / 32);
+        // at least 32 bins in the late rounds: with 8 (B = 256) a few wrong
+        // early locations can no longer be untangled (seen at n = 2^16, k = 59)
+        d->b_min = std::max<uint32_t>(32, (uint32_t)B / 32);
         if (d->b_min > B) d->b_min = (uint32_t)B;
         d->rounds = 24;
         d->patience = 5;
