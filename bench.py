@@ -29,6 +29,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# The serving runtime runs one stream per resident plan instance; with HIP's
+# default of 4 hardware queues per process, batches of different shapes
+# serialise behind each other's launch chains (measured at half load: p50
+# 18.9 ms with 4 queues, 3.9 ms with 16).  Must be set before HIP starts.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
+
 from paper_1201_2501_amd.prof import kernel_source_hash  # noqa: E402
 
 METRIC = "sFFTs/s at n=2^22,k=256 (batched vs plain), HBM GB/s, p50/p99 latency"
@@ -93,7 +100,7 @@ def serving_bench(args, torch, dev, sfft):
             out.append((n, mode, int(rng.integers(0, 4)), int(rng.integers(1, 1 << 62))))
         return out
 
-    srv = sfft.Server(budget_bytes=64 << 30, slots=32, instances=2)
+    srv = sfft.Server(budget_bytes=64 << 30, slots=args.serve_slots, instances=args.serve_instances)
 
     def run(reqs, arrivals=None):
         tickets = []
@@ -169,7 +176,9 @@ def serving_bench(args, torch, dev, sfft):
     srv.close()
     err_all = err_s + err_p
     mid = sweep[len(sweep) // 2]
-    return {"requests_per_phase": len(reqs), "capacity_sFFTs_per_s": round(capacity, 1),
+    return {"requests_per_phase": len(reqs), "slots": args.serve_slots, "instances": args.serve_instances,
+            "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default"),
+            "capacity_sFFTs_per_s": round(capacity, 1),
             "value": mid["sFFTs_per_s"], "unit": "sFFTs/s", "load": mid["load"],
             "p50_ms": mid["p50_ms"], "p99_ms": mid["p99_ms"], "sweep": sweep,
             "failed": failed, "evictions": evict, "peak_device_bytes": peak,
@@ -212,6 +221,8 @@ def main():
                     help="run one 1 GiB device-to-device tensor copy first (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per serving phase (0: skip the serving measurement)")
+    ap.add_argument("--serve-slots", type=int, default=32, help="signals per served batch")
+    ap.add_argument("--serve-instances", type=int, default=2, help="resident plan instances per request shape")
     ap.add_argument("--serve-loads", default="0.25,0.5,0.75",
                     help="Poisson arrival rates as fractions of the measured serving capacity; the p50/p99 "
                          "reported at top level are the middle one's")

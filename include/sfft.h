@@ -311,7 +311,10 @@ uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
  *     shape first) onto idle instances, one stream per instance, so batches
  *     of different shapes overlap on the device.
  * A request's result depends only on its samples, its seed and its shape:
- * it is the same alone and in any mix.  Inputs are complex64.
+ * it is the same alone and in any mix.  Inputs are complex64.  Batches of
+ * different shapes overlap only as far as the process's hardware queues
+ * allow: run servers with GPU_MAX_HW_QUEUES=16 (HIP's default is 4), set
+ * before the process first uses HIP.
  */
 typedef struct sfft_server_s* sfft_server_t;
 
