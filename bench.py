@@ -211,6 +211,9 @@ def main():
                     help="smallest bin count of the shrinking schedule (tuned on the oracle: 512/512 "
                          "recovered with 7%% fewer samples than B/16)")
     ap.add_argument("--rounds", type=int, default=24, help="most exact-mode rounds")
+    ap.add_argument("--loc-prec", choices=["f32", "f64"], default="f64",
+                    help="arithmetic of the location pair's fold and FFT (FP64: the phase step 2 pi / n at "
+                         "n = 2^22 is near FP32 resolution)")
     ap.add_argument("--w", type=int, default=0)
     ap.add_argument("--plain-signals", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -269,7 +272,8 @@ def main():
     torch.cuda.synchronize()
     log("inputs ready: %d x 2^%d complex64 (%.1f GiB) in %.1fs" % (S, args.log2n, X.numel() * 8 / 2**30, time.time() - t))
 
-    plan_kw = dict(delta=1e-9, theta=0.02, loc_prec=sfft.SFFT_F64, b_min=args.b_min, rounds=args.rounds,
+    plan_kw = dict(delta=1e-9, theta=0.02, loc_prec=sfft.SFFT_F64 if args.loc_prec == "f64" else sfft.SFFT_F32,
+                   b_min=args.b_min, rounds=args.rounds,
                    max_batch=S, flags=sfft.SFFT_FLAG_TIMING)
     plan = Plan(n, k, args.B, w, 0, **plan_kw)
     desc = plan.desc
@@ -429,12 +433,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.loc_prec,
         "data": "synthetic",
         "config": {"workload": "batched exactly-sparse sFFT: %d signals, n=2^%d, k=%d, complex64, log-uniform "
                                "|c| in [0.1,10], per-signal seeds" % (S, args.log2n, k),
                    "signals": S, "n": n, "k": k, "B": args.B, "w": w, "rounds": desc.rounds,
-                   "b_min": desc.b_min or max(2, args.B >> 4), "loc_prec": "f64", "input": "complex64"},
+                   "b_min": desc.b_min or max(2, args.B >> 4), "loc_prec": args.loc_prec, "input": "complex64"},
         "latency_ms": {"p50": round(percentile(step_ms, 50), 4), "p99": round(percentile(step_ms, 99), 4),
                        "what": "per batch step (graph replay), HIP events"},
         "phases": phases,
