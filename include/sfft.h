@@ -52,7 +52,8 @@ typedef enum {
     SFFT_EHIP = 5,       /* a HIP runtime call failed                        */
     SFFT_ETRUNC = 6,     /* more coefficients than cap; the top cap returned  */
     SFFT_EUNSUPPORTED = 7,/* parameters valid but not supported by a kernel  */
-    SFFT_EAGAIN = 8      /* a served request has not finished yet            */
+    SFFT_EAGAIN = 8,     /* a served request has not finished yet            */
+    SFFT_ECANCELED = 9   /* a served request was cancelled before it ran     */
 } sfft_status_t;
 
 typedef enum { SFFT_MODE_EXACT = 0, SFFT_MODE_GENERAL = 1 } sfft_mode_t;
@@ -318,15 +319,23 @@ uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
  */
 typedef struct sfft_server_s* sfft_server_t;
 
+/* server flags */
+#define SFFT_SERVER_FAKE_DEVICE 0x1u /* no device work: instances allocate nothing and
+                                        every batch finishes after fake_service_ms on a
+                                        host timer with no coefficients; admission,
+                                        eviction, batching and statistics run as usual
+                                        (for testing the scheduler without a GPU)      */
+
 typedef struct {
     uint64_t budget_bytes;   /* device memory the server may hold (instances)   */
     uint32_t slots;          /* signals per batch of one instance, 1..1024      */
     uint32_t instances;      /* instances per shape (batches in flight), 1..16  */
     int32_t device;          /* HIP device the server runs on                  */
-    uint32_t reserved;
+    uint32_t flags;          /* SFFT_SERVER_*                                   */
     double delta_exact;      /* window accuracy of exact-mode shapes            */
     double delta_general;    /* window accuracy of general-mode shapes          */
     double theta;            /* exact-mode bin threshold                        */
+    double fake_service_ms;  /* batch duration under SFFT_SERVER_FAKE_DEVICE    */
 } sfft_server_desc_t;
 
 typedef struct {
@@ -388,6 +397,12 @@ sfft_status_t sfft_server_poll(sfft_server_t s, uint64_t ticket, sfft_request_re
 /* Block until the request finishes (timeout_ms < 0: no limit; SFFT_EAGAIN on
  * timeout), then as sfft_server_poll. */
 sfft_status_t sfft_server_wait(sfft_server_t s, uint64_t ticket, double timeout_ms, sfft_request_result_t* res);
+
+/* Withdraw a request that has not been launched yet: it finishes at once with
+ * status SFFT_ECANCELED (collected by poll/wait as usual).  Returns SFFT_OK,
+ * SFFT_EAGAIN when it is already running or finished (its result will come),
+ * SFFT_EINVAL for an unknown ticket. */
+sfft_status_t sfft_server_cancel(sfft_server_t s, uint64_t ticket);
 
 /* Counters and latency percentiles since the last reset. */
 sfft_status_t sfft_server_stats(sfft_server_t s, sfft_server_stats_t* st);

@@ -723,6 +723,7 @@ const char* sfft_status_string(sfft_status_t s) {
         case SFFT_ETRUNC: return "SFFT_ETRUNC";
         case SFFT_EUNSUPPORTED: return "SFFT_EUNSUPPORTED";
         case SFFT_EAGAIN: return "SFFT_EAGAIN";
+        case SFFT_ECANCELED: return "SFFT_ECANCELED";
     }
     return "SFFT_UNKNOWN";
 }

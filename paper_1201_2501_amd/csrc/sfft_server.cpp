@@ -153,6 +153,7 @@ struct Request {
     int32_t status = SFFT_EAGAIN;
     uint32_t count = 0, flags = 0, rounds = 0;
     int32_t path = 0;
+    bool launched = false;
     bool done = false;
 };
 
@@ -179,6 +180,7 @@ struct Instance {
     uint32_t* h_cnt = nullptr;
     uint32_t* h_info = nullptr;
     size_t bytes = 0;
+    bool fake = false;
     bool busy = false;
     std::vector<Request*> batch;
     Clock::time_point last_used;
@@ -202,6 +204,10 @@ struct sfft_server_s {
     uint32_t pending = 0, inflight = 0;
     bool stop = false;
     std::thread th;
+    // fake device: batches finish at their due time on this thread
+    std::thread fake_th;
+    std::condition_variable cv_fake;
+    std::multimap<Clock::time_point, Instance*> fake_due;
     // statistics since the last reset
     std::vector<double> lat_ms, queue_ms, service_ms;
     uint64_t completed = 0, dense = 0, failed = 0, batches = 0, batched = 0, evictions = 0;
@@ -247,6 +253,7 @@ sfft_status_t server_shape(sfft_server_s* s, uint64_t n, uint32_t k, int32_t mod
 }
 
 void destroy_instance(Instance* in) {
+    if (in->fake) return;
     if (in->stream) (void)hipStreamSynchronize(in->stream);
     if (in->plan) sfft_destroy(in->plan);
     if (in->fft) fftlib().destroy(in->fft);
@@ -283,6 +290,7 @@ sfft_status_t hmalloc(T** p, size_t count) {
     } while (0)
 
 sfft_status_t build_instance(Instance* in) {
+    if (in->fake) return SFFT_OK;
     const uint32_t S = in->slots, cap = in->cap;
     SRV_HIP(hipStreamCreateWithFlags(&in->stream, hipStreamNonBlocking));
     SRV_TRY(dmalloc(&in->d_xptrs, S));
@@ -319,9 +327,9 @@ void complete_batch(Instance* in) {
     const Clock::time_point now = Clock::now();
     for (size_t q = 0; q < in->batch.size(); ++q) {
         Request* rq = in->batch[q];
-        const uint64_t* idx = in->h_idx + q * in->cap;
-        const double* val = in->h_val + q * in->cap * 2;
-        uint32_t c = std::min(in->h_cnt[q], in->cap);
+        const uint64_t* idx = in->fake ? nullptr : in->h_idx + q * in->cap;
+        const double* val = in->fake ? nullptr : in->h_val + q * in->cap * 2;
+        uint32_t c = in->fake ? 0u : std::min(in->h_cnt[q], in->cap);
         std::vector<uint32_t> order(c);
         for (uint32_t e = 0; e < c; ++e) order[e] = e;
         if (c > rq->r.k) {
@@ -341,8 +349,8 @@ void complete_batch(Instance* in) {
             }
         }
         rq->count = c;
-        rq->flags = in->dense ? 0 : in->h_info[q * 4 + SFFT_INFO_FLAGS];
-        rq->rounds = in->dense ? 0 : in->h_info[q * 4 + SFFT_INFO_ROUNDS];
+        rq->flags = (in->dense || in->fake) ? 0 : in->h_info[q * 4 + SFFT_INFO_FLAGS];
+        rq->rounds = (in->dense || in->fake) ? 0 : in->h_info[q * 4 + SFFT_INFO_ROUNDS];
         rq->path = in->dense;
         rq->status = SFFT_OK;
         rq->t_done = now;
@@ -366,6 +374,15 @@ void on_batch_done(void* arg) { complete_batch(static_cast<Instance*>(arg)); }
 
 // Enqueue one batch on the instance's stream (no server lock held).
 sfft_status_t launch_batch(Instance* in) {
+    if (in->fake) {
+        sfft_server_s* s = in->srv;
+        std::lock_guard<std::mutex> lock(s->mu);
+        s->fake_due.emplace(Clock::now() + std::chrono::duration_cast<Clock::duration>(
+                                                std::chrono::duration<double, std::milli>(s->d.fake_service_ms)),
+                            in);
+        s->cv_fake.notify_all();
+        return SFFT_OK;
+    }
     const uint32_t m = (uint32_t)in->batch.size();
     const uint64_t n = in->desc.n;
     for (uint32_t q = 0; q < m; ++q) {
@@ -459,6 +476,7 @@ Instance* instance_for(sfft_server_s* s, uint64_t key, const Request* head, std:
     in->slots = s->d.slots;
     in->cap = d.cap;
     in->bytes = need;
+    in->fake = (s->d.flags & SFFT_SERVER_FAKE_DEVICE) != 0;
     in->busy = true;   // reserved while it is built
     Instance* raw = in.get();
     s->inst.push_back(std::move(in));
@@ -480,8 +498,30 @@ Instance* instance_for(sfft_server_s* s, uint64_t key, const Request* head, std:
     return raw;
 }
 
+// Fake device: completes each batch when its time has come.
+void fake_device(sfft_server_s* s) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        if (s->fake_due.empty()) {
+            if (s->stop && s->inflight == 0) break;
+            s->cv_fake.wait_for(lk, std::chrono::milliseconds(50));
+            continue;
+        }
+        const auto due = s->fake_due.begin()->first;
+        if (Clock::now() < due) {
+            s->cv_fake.wait_until(lk, due);
+            continue;
+        }
+        Instance* in = s->fake_due.begin()->second;
+        s->fake_due.erase(s->fake_due.begin());
+        lk.unlock();
+        complete_batch(in);
+        lk.lock();
+    }
+}
+
 void scheduler(sfft_server_s* s) {
-    (void)hipSetDevice(s->d.device);
+    if (!(s->d.flags & SFFT_SERVER_FAKE_DEVICE)) (void)hipSetDevice(s->d.device);
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         if (s->stop && s->pending == 0 && s->inflight == 0) break;
@@ -510,6 +550,7 @@ void scheduler(sfft_server_s* s) {
                 Request* r = q.front();
                 q.pop_front();
                 r->t_launch = now;
+                r->launched = true;
                 in->batch.push_back(r);
             }
             s->pending -= (uint32_t)in->batch.size();
@@ -552,6 +593,7 @@ sfft_status_t sfft_server_desc_init(sfft_server_desc_t* d) {
     d->delta_exact = 1e-9;
     d->delta_general = 1e-6;
     d->theta = 0.25;
+    d->fake_service_ms = 1.0;
     return SFFT_OK;
 }
 
@@ -567,12 +609,14 @@ sfft_status_t sfft_server_create(const sfft_server_desc_t* d, sfft_server_t* out
     if (!d || !out) return set_last_error(SFFT_EINVAL, "NULL argument");
     if (d->slots < 1 || d->slots > 1024 || d->instances < 1 || d->instances > 16 || d->budget_bytes == 0 ||
         !(d->theta > 0) || !(d->delta_exact > 0 && d->delta_exact < 1) ||
-        !(d->delta_general > 0 && d->delta_general < 1))
+        !(d->delta_general > 0 && d->delta_general < 1) || (d->flags & ~SFFT_SERVER_FAKE_DEVICE) ||
+        !(d->fake_service_ms >= 0))
         return set_last_error(SFFT_EINVAL, "bad server description");
     auto* s = new (std::nothrow) sfft_server_s();
     if (!s) return set_last_error(SFFT_ENOMEM, "host allocation failed");
     s->d = *d;
     s->th = std::thread(scheduler, s);
+    if (d->flags & SFFT_SERVER_FAKE_DEVICE) s->fake_th = std::thread(fake_device, s);
     *out = s;
     return SFFT_OK;
 }
@@ -620,6 +664,24 @@ static sfft_status_t take_result(sfft_server_s* s, std::unordered_map<uint64_t, 
     const sfft_status_t st = (sfft_status_t)r->status;
     s->reqs.erase(it);
     return st;
+}
+
+sfft_status_t sfft_server_cancel(sfft_server_t srv, uint64_t ticket) {
+    if (!srv) return set_last_error(SFFT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return set_last_error(SFFT_EINVAL, "unknown ticket");
+    Request* r = it->second.get();
+    if (r->launched || r->done) return SFFT_EAGAIN;
+    auto& q = srv->queues[r->key];
+    q.erase(std::find(q.begin(), q.end(), r));
+    --srv->pending;
+    r->status = SFFT_ECANCELED;
+    r->t_done = Clock::now();
+    r->done = true;
+    srv->cv_done.notify_all();
+    srv->cv_sched.notify_all();
+    return SFFT_OK;
 }
 
 sfft_status_t sfft_server_poll(sfft_server_t srv, uint64_t ticket, sfft_request_result_t* res) {
@@ -690,6 +752,11 @@ sfft_status_t sfft_server_destroy(sfft_server_t srv) {
         srv->cv_sched.notify_all();
     }
     if (srv->th.joinable()) srv->th.join();
+    {
+        std::lock_guard<std::mutex> lock(srv->mu);
+        srv->cv_fake.notify_all();
+    }
+    if (srv->fake_th.joinable()) srv->fake_th.join();
     for (auto& up : srv->inst) destroy_instance(up.get());
     delete srv;
     return SFFT_OK;

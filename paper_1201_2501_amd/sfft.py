@@ -15,7 +15,8 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsfft.so")
 
 (SFFT_OK, SFFT_EINVAL, SFFT_ENOTPOW2, SFFT_ENOMEM, SFFT_EBUDGET, SFFT_EHIP, SFFT_ETRUNC, SFFT_EUNSUPPORTED,
- SFFT_EAGAIN) = range(9)
+ SFFT_EAGAIN, SFFT_ECANCELED) = range(10)
+SFFT_SERVER_FAKE_DEVICE = 0x1
 SFFT_MODE_EXACT, SFFT_MODE_GENERAL = 0, 1
 SFFT_C64, SFFT_C128 = 0, 1
 SFFT_F32, SFFT_F64 = 0, 1
@@ -31,8 +32,8 @@ EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_pla
            "sfft_status_string",
            "sfft_last_error", "sfft_splitmix64",
            "sfft_server_desc_init", "sfft_server_shape", "sfft_server_create", "sfft_server_submit",
-           "sfft_server_poll", "sfft_server_wait", "sfft_server_stats", "sfft_server_reset_stats",
-           "sfft_server_destroy"]
+           "sfft_server_poll", "sfft_server_wait", "sfft_server_cancel", "sfft_server_stats",
+           "sfft_server_reset_stats", "sfft_server_destroy"]
 
 
 class PlanDesc(ctypes.Structure):
@@ -46,7 +47,8 @@ class PlanDesc(ctypes.Structure):
 
 class ServerDesc(ctypes.Structure):
     _fields_ = [("budget_bytes", c_uint64), ("slots", c_uint32), ("instances", c_uint32), ("device", c_int32),
-                ("reserved", c_uint32), ("delta_exact", c_double), ("delta_general", c_double), ("theta", c_double)]
+                ("flags", c_uint32), ("delta_exact", c_double), ("delta_general", c_double), ("theta", c_double),
+                ("fake_service_ms", c_double)]
 
 
 class Request(ctypes.Structure):
@@ -112,6 +114,7 @@ def load():
     lib.sfft_server_submit.argtypes = [P, POINTER(Request), POINTER(c_uint64)]
     lib.sfft_server_poll.argtypes = [P, c_uint64, POINTER(RequestResult)]
     lib.sfft_server_wait.argtypes = [P, c_uint64, c_double, POINTER(RequestResult)]
+    lib.sfft_server_cancel.argtypes = [P, c_uint64]
     lib.sfft_server_stats.argtypes = [P, POINTER(ServerStats)]
     lib.sfft_server_reset_stats.argtypes = [P]
     lib.sfft_server_destroy.argtypes = [P]
@@ -382,6 +385,11 @@ def sfft_server_wait(server, ticket, timeout_ms=-1.0):
     return st, res
 
 
+def sfft_server_cancel(server, ticket):
+    """SFFT_OK if withdrawn before launch, SFFT_EAGAIN if already running/finished."""
+    return _check(load().sfft_server_cancel(server, ticket), "sfft_server_cancel", allow=(SFFT_EAGAIN,))
+
+
 def sfft_server_stats(server):
     st = ServerStats()
     _check(load().sfft_server_stats(server, ctypes.byref(st)), "sfft_server_stats")
@@ -442,6 +450,9 @@ class Server:
         if st == SFFT_EAGAIN:
             return None
         return self._finish(ticket, st, res)
+
+    def cancel(self, ticket):
+        return sfft_server_cancel(self.handle, ticket)
 
     def stats(self):
         return sfft_server_stats(self.handle)

@@ -2,6 +2,7 @@
 shape a request maps to, the device-size query that admission relies on, and
 descriptor validation."""
 import ctypes
+import time
 
 import pytest
 
@@ -84,3 +85,112 @@ def test_server_calls_reject_null_server():
     assert lib.sfft_server_wait(None, 1, 0.0, ctypes.byref(res)) == sfft.SFFT_EINVAL
     assert lib.sfft_server_stats(None, ctypes.byref(st)) == sfft.SFFT_EINVAL
     assert lib.sfft_server_destroy(None) == sfft.SFFT_OK
+
+
+# ---- the scheduler on the fake device (no GPU: batches finish on a host timer)
+FAKE_X = 0x1000          # a request's signal pointer is never read on the fake device
+
+
+class FakeServer:
+    def __init__(self, **fields):
+        self.lib = sfft.load()
+        d = sfft.sfft_server_desc_init()
+        d.flags = sfft.SFFT_SERVER_FAKE_DEVICE
+        for k, v in fields.items():
+            setattr(d, k, v)
+        self.desc = d
+        self.h = ctypes.c_void_p()
+        assert self.lib.sfft_server_create(ctypes.byref(d), ctypes.byref(self.h)) == sfft.SFFT_OK
+
+    def submit(self, n, k, mode=sfft.SFFT_MODE_EXACT, seed=0):
+        req = sfft.Request(x_dev=FAKE_X, n=n, seed=seed, k=k, mode=mode, idx_host=None, val_host=None)
+        t = ctypes.c_uint64(0)
+        st = self.lib.sfft_server_submit(self.h, ctypes.byref(req), ctypes.byref(t))
+        return st, t.value
+
+    def wait(self, ticket):
+        res = sfft.RequestResult()
+        st = self.lib.sfft_server_wait(self.h, ticket, 10000.0, ctypes.byref(res))
+        return st, res
+
+    def stats(self):
+        st = sfft.ServerStats()
+        assert self.lib.sfft_server_stats(self.h, ctypes.byref(st)) == sfft.SFFT_OK
+        return st
+
+    def close(self):
+        assert self.lib.sfft_server_destroy(self.h) == sfft.SFFT_OK
+
+
+def test_fake_server_rejects_a_shape_larger_than_the_budget():
+    srv = FakeServer(budget_bytes=1 << 20)
+    try:
+        st, _ = srv.submit(1 << 22, 256)
+        assert st == sfft.SFFT_EBUDGET
+        st, _ = srv.submit(1000, 16)
+        assert st == sfft.SFFT_ENOTPOW2
+        assert srv.stats().completed == 0
+    finally:
+        srv.close()
+
+
+def test_fake_server_budget_eviction_and_peak():
+    sd = sfft.sfft_server_desc_init()
+    sd.slots = 4
+    shapes = [(1 << 16, 16), (1 << 18, 100), (1 << 20, 64)]
+    sizes = [sfft.sfft_server_shape(sd, n, k, 0)[2] for n, k in shapes]
+    budget = max(sizes) + min(sizes) // 2
+    srv = FakeServer(slots=4, instances=1, budget_bytes=budget, fake_service_ms=2.0)
+    try:
+        tickets = []
+        for rep in range(4):
+            for n, k in shapes:
+                st, t = srv.submit(n, k, seed=rep)
+                assert st == sfft.SFFT_OK
+                tickets.append(t)
+        for t in tickets:
+            st, res = srv.wait(t)
+            assert st == sfft.SFFT_OK and res.count == 0 and res.latency_ms >= res.service_ms >= 1.5
+        s = srv.stats()
+        assert s.completed == len(tickets) and s.failed == 0
+        assert s.peak_bytes <= budget and s.evictions >= 2 and s.bytes_in_use <= budget
+    finally:
+        srv.close()
+
+
+def test_fake_server_batches_requests_that_wait():
+    srv = FakeServer(slots=8, instances=1, fake_service_ms=30.0)
+    try:
+        tickets = [srv.submit(1 << 20, 64, seed=s)[1] for s in range(9)]
+        outs = [srv.wait(t) for t in tickets]
+        assert all(st == sfft.SFFT_OK for st, _ in outs)
+        s = srv.stats()
+        # the first request runs alone; the 8 that arrived meanwhile share one batch
+        assert s.batches == 2 and abs(s.mean_batch - 4.5) < 1e-9
+        assert outs[-1][1].queue_ms >= 20.0
+        assert s.p50_ms <= s.p99_ms
+    finally:
+        srv.close()
+
+
+def test_fake_server_cancels_requests_that_have_not_launched():
+    srv = FakeServer(slots=1, instances=1, fake_service_ms=40.0)
+    lib = srv.lib
+    try:
+        tickets = [srv.submit(1 << 20, 64, seed=s)[1] for s in range(4)]
+        assert lib.sfft_server_cancel(srv.h, tickets[3]) == sfft.SFFT_OK
+        assert lib.sfft_server_cancel(srv.h, tickets[2]) == sfft.SFFT_OK
+        assert lib.sfft_server_cancel(srv.h, 10 ** 6) == sfft.SFFT_EINVAL
+        time.sleep(0.01)                    # the first request is running (40 ms of service)
+        assert lib.sfft_server_cancel(srv.h, tickets[0]) == sfft.SFFT_EAGAIN
+        assert srv.wait(tickets[0])[0] == sfft.SFFT_OK
+        # the second is launched when the first finishes: either withdrawn or served
+        st1 = lib.sfft_server_cancel(srv.h, tickets[1])
+        assert st1 in (sfft.SFFT_OK, sfft.SFFT_EAGAIN)
+        assert srv.wait(tickets[1])[0] == (sfft.SFFT_ECANCELED if st1 == sfft.SFFT_OK else sfft.SFFT_OK)
+        assert srv.wait(tickets[2])[0] == sfft.SFFT_ECANCELED
+        assert srv.wait(tickets[3])[0] == sfft.SFFT_ECANCELED
+        s = srv.stats()
+        assert s.completed == (1 if st1 == sfft.SFFT_OK else 2) and s.failed == 0
+    finally:
+        srv.close()
