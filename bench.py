@@ -41,6 +41,7 @@ from paper_1201_2501_amd.prof import kernel_source_hash  # noqa: E402
 METRIC = "sFFTs/s at n=2^22,k=256 (batched vs plain), HBM GB/s, p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "h2b_pair_c3_traffic.json")
+TUNE_FILE = os.path.join(ROOT, "paper_1201_2501_amd", "tuned.json")
 
 
 def log(*a):
@@ -229,6 +230,13 @@ def main():
     ap.add_argument("--serve-loads", default="0.25,0.5,0.75",
                     help="Poisson arrival rates as fractions of the measured serving capacity; the p50/p99 "
                          "reported at top level are the middle one's")
+    ap.add_argument("--tune", choices=["off", "cache", "run"], default="cache",
+                    help="plan parameters: off = the flags above; cache = the autotuner's stored choice for this "
+                         "device, shape and library build, measured now when none is stored; run = measure now")
+    ap.add_argument("--tune-budget", type=float, default=150.0, help="seconds of autotuner measurement at most")
+    ap.add_argument("--tune-out", default="", help="also store the autotuner's choice in this JSON file")
+    ap.add_argument("--tune-confirm", type=int, default=4,
+                    help="fresh batches the fastest accepted candidates must also pass")
     ap.add_argument("--config-key", action="store_true",
                     help="print the key that names this configuration in the traffic record, then exit")
     args = ap.parse_args()
@@ -245,11 +253,47 @@ def main():
     from paper_1201_2501_amd import sfft
     from paper_1201_2501_amd.sfft import Plan
 
+    from paper_1201_2501_amd import autotune
+
     sfft.load()
     dev = torch.device("cuda:0")
     n, k, S = 1 << args.log2n, args.k, args.signals
-    w = args.w or sfft.sfft_default_w(n, args.B, 0.5, 1e-9)
-    cfg_key = "n=2^%d,k=%d,B=%d,w=%d,b_min=%d,rounds=%d,signals=%d" % (args.log2n, k, args.B, w, args.b_min,
+    loc_prec = sfft.SFFT_F64 if args.loc_prec == "f64" else sfft.SFFT_F32
+    base_kw = dict(theta=0.02, loc_prec=loc_prec, rounds=args.rounds)
+
+    # ---------------------------------------------------------- plan choice
+    B, tuned, tune_rec = args.B, dict(delta=1e-9, b_min=args.b_min), None
+    if args.tune != "off" and not args.w:
+        res = None
+        if args.tune == "cache":
+            res = autotune.lookup(TUNE_FILE, n, k, sfft.SFFT_MODE_EXACT, S, sfft.SFFT_C64,
+                                  torch.cuda.get_device_name(dev))
+        if res is None and not args.config_key:
+            t = time.time()
+            cal_seeds = [2_000_003 + s for s in range(S)]
+            Xc, sup_c, _ = siggen.torch_planted_batch(n, k, cal_seeds, dev, magnitude="loguniform")
+            seeds_c = torch.arange(S, dtype=torch.int64, device=dev) * 104729 + 777
+            torch.cuda.synchronize()
+            log("autotune: calibration batch of %d signals (seeds 2000003..) ready in %.1fs" % (S, time.time() - t))
+            def confirm(i):
+                # fresh batches of the same workload, one at a time
+                gs = [3_000_003 + i * S + s for s in range(S)]
+                xb, sb, _ = siggen.torch_planted_batch(n, k, gs, dev, magnitude="loguniform")
+                return xb, torch.arange(S, dtype=torch.int64, device=dev) * 65537 + 99991 * (i + 1), sb
+
+            res = autotune.tune(Xc, k, sfft.SFFT_MODE_EXACT, seeds=seeds_c, truth=sup_c, base=base_kw,
+                                budget_s=args.tune_budget, cache=args.tune_out or None, log=log, force=True,
+                                confirm=confirm, confirm_batches=args.tune_confirm)
+            del Xc
+            torch.cuda.empty_cache()
+            log("autotune: %d candidates in %.1fs" % (len(res.table), time.time() - t))
+        if res is not None:
+            B = res.B
+            tuned = {f: v for f, v in res.fields.items() if f not in base_kw and f != "mode"}
+            tune_rec = res.as_dict()
+    w = args.w or sfft.sfft_default_w(n, B, 0.5, tuned.get("delta", 1e-9))
+    cfg_key = "n=2^%d,k=%d,B=%d,w=%d,b_min=%d,rounds=%d,signals=%d" % (args.log2n, k, B, w,
+                                                                       tuned.get("b_min", args.b_min),
                                                                        args.rounds, S)
     if args.config_key:
         print(cfg_key)
@@ -272,10 +316,9 @@ def main():
     torch.cuda.synchronize()
     log("inputs ready: %d x 2^%d complex64 (%.1f GiB) in %.1fs" % (S, args.log2n, X.numel() * 8 / 2**30, time.time() - t))
 
-    plan_kw = dict(delta=1e-9, theta=0.02, loc_prec=sfft.SFFT_F64 if args.loc_prec == "f64" else sfft.SFFT_F32,
-                   b_min=args.b_min, rounds=args.rounds,
-                   max_batch=S, flags=sfft.SFFT_FLAG_TIMING)
-    plan = Plan(n, k, args.B, w, 0, **plan_kw)
+    plan_kw = dict(base_kw, **tuned, max_batch=S, flags=sfft.SFFT_FLAG_TIMING)
+    log("plan: B=%d w=%d %s" % (B, w, ", ".join("%s=%s" % kv for kv in sorted(tuned.items()))))
+    plan = Plan(n, k, B, w, 0, **plan_kw)
     desc = plan.desc
     bufs = plan.batch_buffers(S, dev)
 
@@ -334,7 +377,7 @@ def main():
     # ---------------------------------------------------------------- plain
     plain = None
     if args.plain_signals > 0:
-        pplan = Plan(n, k, args.B, w, int(seeds[0].item()), **{**plan_kw, "max_batch": 1})
+        pplan = Plan(n, k, B, w, int(seeds[0].item()), **{**plan_kw, "max_batch": 1})
         pplan.execute(X[0])                       # warm-up
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -437,8 +480,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "batched exactly-sparse sFFT: %d signals, n=2^%d, k=%d, complex64, log-uniform "
                                "|c| in [0.1,10], per-signal seeds" % (S, args.log2n, k),
-                   "signals": S, "n": n, "k": k, "B": args.B, "w": w, "rounds": desc.rounds,
-                   "b_min": desc.b_min or max(2, args.B >> 4), "loc_prec": args.loc_prec, "input": "complex64"},
+                   "signals": S, "n": n, "k": k, "B": B, "w": w, "rounds": desc.rounds,
+                   "b_min": desc.b_min or max(2, B >> 4), "patience": desc.patience, "delta": desc.delta,
+                   "hash_threads": desc.hash_threads, "chunks": chunks, "loc_prec": args.loc_prec,
+                   "input": "complex64"},
+        "autotune": tune_rec,
         "latency_ms": {"p50": round(percentile(step_ms, 50), 4), "p99": round(percentile(step_ms, 99), 4),
                        "what": "per batch step (graph replay), HIP events"},
         "phases": phases,

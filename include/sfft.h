@@ -105,6 +105,15 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *   cap       output capacity (0 = k)
  *   flags     SFFT_FLAG_*
  *   max_batch largest count accepted by sfft_execute_batch (workspace size)
+ *   hash_threads  workgroup size of the batched HashToBins pair launches:
+ *             256, 512 or 1024 (0 = 256).  Launch shape only: results are
+ *             the same up to the summation order of a bin's partial sums
+ *             when B_r < hash_threads
+ *   chunks    sfft_execute_batch splits the batch into this many chunks whose
+ *             decode overlaps the next chunk's HashToBins, 1..8 (0 = the
+ *             SFFT_BATCH_CHUNKS environment variable, else 1).  Launch
+ *             shape only: results do not depend on it
+ *   reserved  must be 0
  */
 typedef struct {
     uint64_t n;
@@ -130,6 +139,8 @@ typedef struct {
     uint32_t cap;
     uint32_t flags;
     uint32_t max_batch;
+    uint32_t hash_threads;
+    uint32_t chunks;
     uint32_t reserved;
 } sfft_plan_desc_t;
 

@@ -1,0 +1,345 @@
+"""Autotuner of the batched sparse FFT: chooses the bin count B, the window
+length w (through its accuracy delta), the round schedule and the launch
+shape of a batch of one shape by measuring candidate plans on calibration
+signals on the device.
+
+The method fixes its parameters only up to constants (B = O(k), a window of
+O(B log(n/delta)) samples, the number of rounds), so their best values depend
+on the signals and the device.  A candidate is accepted only if its results
+are as good as those of a conservative reference candidate on the same
+calibration batch:
+
+  * exact mode: every signal's recovered support equals the planted support
+    (when `truth` is given) or the reference candidate's support;
+  * general mode: the mean fraction of planted (or reference) coefficients
+    found is within `recall_slack` of the reference candidate's.
+
+Among accepted candidates the fastest (median time of `reps` replayed batch
+steps, HIP events) wins.  The search is coordinate-wise with a small beam:
+the window and bin count first, then the round schedule, then the launch
+shape (HashToBins workgroup size, batch chunks), each stage varying its
+fields around each of the `beam` fastest accepted candidates so far.
+
+One calibration batch cannot show a per-signal failure rate of 1e-3, and a
+shorter window or an earlier stop can have one.  With `confirm` (a function
+returning fresh batches), the fastest accepted candidates are run again on
+`confirm_batches` new batches, one batch in memory at a time, beside the
+reference candidate; a candidate survives a batch when it recovers every
+signal the reference recovers (exact mode) or stays within recall_slack of
+the reference's recall (general mode).  The fastest survivor wins.
+
+Results are cached in a JSON file keyed by device, shape, batch size and the
+library's kernel sources, so a shape is tuned once per device and build.
+
+    from paper_1201_2501_amd import autotune
+    res = autotune.tune(x, k, truth=supports, cache="tuned.json")
+    plan = Plan(n, k, res.B, 0, 0, max_batch=len(x), **res.fields)
+"""
+import hashlib
+import json
+import os
+import statistics
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import sfft
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+_SOURCES = ("sfft_kernels.hip", "sfft_decode.hip", "sfft_host.cpp", "sfft_common.hpp", "sfft_internal.hpp",
+            "sfft_device.hpp")
+
+
+def library_hash():
+    """Hash of the library sources the tuned timings depend on."""
+    h = hashlib.sha256()
+    for f in _SOURCES:
+        path = os.path.join(PKG, "csrc", f)
+        if os.path.exists(path):
+            h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def pow2_range(lo, hi):
+    out, v = [], 1
+    while v <= hi:
+        if v >= lo:
+            out.append(v)
+        v <<= 1
+    return out
+
+
+def default_space(n, k, mode):
+    """Candidate values per stage.  B stays within the kernels' limit (4096)
+    and at most n/16; exact mode starts at 2k bins, general mode at 4k."""
+    if mode == sfft.SFFT_MODE_EXACT:
+        lo = max(64, 2 * k)
+        Bs = pow2_range(lo, min(4096, n // 16)) or [min(4096, max(2, n // 16))]
+        Bs = [b for b in Bs if b >= 512] or Bs[-2:]
+        return {
+            "window": {"B": Bs, "delta": [1e-10, 1e-9, 1e-8]},
+            "schedule": {"b_min": [16, 32, 64], "patience": [3, 4]},
+            "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
+        }
+    lo = max(256, 4 * k)
+    Bs = pow2_range(lo, min(4096, n // 16)) or [min(4096, max(2, n // 16))]
+    return {
+        "window": {"B": Bs[:3], "delta": [1e-7, 1e-6]},
+        "schedule": {"R_est": [5, 7, 9], "R_loc": [3, 4]},
+        "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
+    }
+
+
+def reference_candidate(space, mode, base):
+    """The conservative candidate every other one is compared with: the
+    largest B, the smallest delta and the slowest-stopping schedule."""
+    c = dict(base)
+    c["B"] = max(space["window"]["B"])
+    c["delta"] = min(space["window"]["delta"])
+    if mode == sfft.SFFT_MODE_EXACT:
+        c["b_min"] = max(space["schedule"]["b_min"])
+        c["patience"] = max(space["schedule"]["patience"])
+    else:
+        c["R_est"] = max(space["schedule"]["R_est"])
+        c["R_loc"] = max(space["schedule"]["R_loc"])
+    c["hash_threads"] = 256
+    c["chunks"] = 1
+    return c
+
+
+@dataclass
+class TuneResult:
+    B: int
+    fields: dict
+    ms: float
+    rate: float
+    quality: float
+    key: str
+    from_cache: bool = False
+    table: list = field(default_factory=list)
+    confirm_batches: int = 0
+
+    def as_dict(self):
+        return {"B": self.B, "fields": self.fields, "ms": self.ms, "rate": self.rate, "quality": self.quality,
+                "key": self.key, "from_cache": self.from_cache, "candidates": len(self.table),
+                "confirm_batches": self.confirm_batches}
+
+
+def cache_key(n, k, mode, count, in_dtype, device_name):
+    return "%s|n=%d|k=%d|mode=%d|count=%d|dtype=%d|lib=%s" % (device_name, n, k, mode, count, in_dtype,
+                                                              library_hash())
+
+
+def lookup(cache, n, k, mode, count, in_dtype, device_name):
+    """The cached TuneResult of a shape, or None."""
+    key = cache_key(n, k, mode, count, in_dtype, device_name)
+    rec = _load_cache(cache).get(key)
+    if not rec:
+        return None
+    return TuneResult(B=rec["B"], fields=rec["fields"], ms=rec["ms"], rate=rec["rate"], quality=rec["quality"],
+                      key=key, from_cache=True, confirm_batches=rec.get("confirm_batches", 0))
+
+
+def _load_cache(path):
+    if not path or not os.path.exists(path):
+        return {}
+    try:
+        return json.load(open(path))
+    except ValueError:
+        return {}
+
+
+def _store_cache(path, key, rec):
+    if not path:
+        return
+    data = _load_cache(path)
+    data[key] = rec
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+class _Runner:
+    """Builds, times and scores candidate plans on one calibration batch."""
+
+    def __init__(self, x, k, mode, seeds, truth, reps, log):
+        import torch
+
+        self.torch = torch
+        self.x, self.k, self.mode, self.seeds = x, k, mode, seeds
+        self.n, self.count = int(x.shape[1]), int(x.shape[0])
+        self.in_dtype = sfft.SFFT_C128 if x.dtype == torch.complex128 else sfft.SFFT_C64
+        self.truth = None if truth is None else [np.sort(np.asarray(t, dtype=np.int64)) for t in truth]
+        self.reps, self.log = reps, log
+        self.ref_supports = None
+        self.table = []
+
+    def run(self, cand, x=None, seeds=None, reps=None):
+        """(median ms per batch step, per-signal supports) of one candidate
+        on the calibration batch (or on x, seeds), or None when its plan is
+        not valid for this shape."""
+        torch = self.torch
+        if x is None:
+            x, seeds = self.x, self.seeds
+        count = int(x.shape[0])
+        fields = {f: v for f, v in cand.items() if f not in ("B", "in_dtype", "max_batch")}
+        try:
+            plan = sfft.Plan(self.n, self.k, cand["B"], 0, 0, in_dtype=self.in_dtype, max_batch=count, **fields)
+        except sfft.SfftError as e:
+            self.table.append({"cand": cand, "error": str(e)})
+            return None
+        try:
+            bufs = plan.batch_buffers(count, x.device)
+            plan.execute_batch(x, seeds, bufs=bufs)                  # capture + warm-up
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(self.reps if reps is None else reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                plan.execute_batch(x, seeds, bufs=bufs)
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            counts = bufs["counts"].cpu().numpy()
+            idx = bufs["idx"].cpu().numpy()
+            sups = [idx[s, :counts[s]].copy() for s in range(count)]
+        finally:
+            plan.close()
+        return (statistics.median(times) if times else float("nan")), sups
+
+    def quality(self, sups, target=None):
+        """Exact mode: fraction of signals whose support equals the target;
+        general mode: mean fraction of target coefficients found."""
+        if target is None:
+            target = self.truth if self.truth is not None else self.ref_supports
+        if self.mode == sfft.SFFT_MODE_EXACT:
+            return float(np.mean([np.array_equal(s, t) for s, t in zip(sups, target)]))
+        return float(np.mean([len(np.intersect1d(s, t)) / max(1, len(t)) for s, t in zip(sups, target)]))
+
+    def survives(self, sups, ref_sups, truth, slack):
+        """Whether a candidate's supports on a confirmation batch are as good
+        as the reference candidate's on the same batch."""
+        if truth is None:
+            if self.mode == sfft.SFFT_MODE_EXACT:
+                return all(np.array_equal(s, r) for s, r in zip(sups, ref_sups))
+            return self.quality(sups, ref_sups) >= 1.0 - slack - 1e-12
+        if self.mode == sfft.SFFT_MODE_EXACT:
+            return all(np.array_equal(s, t) or not np.array_equal(r, t) for s, r, t in zip(sups, ref_sups, truth))
+        return self.quality(sups, truth) >= self.quality(ref_sups, truth) - slack - 1e-12
+
+    def evaluate(self, cand):
+        out = self.run(cand)
+        if out is None:
+            return None
+        ms, sups = out
+        q = self.quality(sups) if (self.truth is not None or self.ref_supports is not None) else 1.0
+        rec = {"cand": dict(cand), "ms": round(ms, 4), "quality": q}
+        self.table.append(rec)
+        if self.log:
+            self.log("autotune: %s -> %.3f ms, quality %.4f" % (
+                ", ".join("%s=%s" % kv for kv in sorted(cand.items())), ms, q))
+        return rec, sups
+
+
+def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, space=None, reps=3,
+         budget_s=120.0, cache=None, recall_slack=0.005, log=None, force=False, confirm=None,
+         confirm_batches=4, confirm_top=16, beam=3):
+    """Tune the plan of a batch x ([count, n] complex device tensor) with
+    sparsity k.  base: plan fields kept fixed (e.g. theta, rounds, loc_prec,
+    flags); space: {"window": {...}, "schedule": {...}, "launch": {...}}
+    lists of candidate values (default_space when None); truth: per-signal
+    planted supports, else the reference candidate's supports are the
+    target; confirm: i -> (x_i, seeds_i, truth_i or None), fresh batches of
+    the same shape for the confirmation phase.  Returns a TuneResult; with
+    `cache`, a stored result for the same key is returned without measuring
+    (unless force)."""
+    import torch
+
+    n, count = int(x.shape[1]), int(x.shape[0])
+    base = dict(base or {})
+    base.setdefault("mode", mode)
+    space = space or default_space(n, k, mode)
+    in_dtype = sfft.SFFT_C128 if x.dtype == torch.complex128 else sfft.SFFT_C64
+    key = cache_key(n, k, mode, count, in_dtype, torch.cuda.get_device_name(x.device))
+    if cache and not force:
+        hit = lookup(cache, n, k, mode, count, in_dtype, torch.cuda.get_device_name(x.device))
+        if hit:
+            return hit
+
+    runner = _Runner(x, k, mode, seeds, truth, reps, log)
+    t_start = time.time()
+    ref = reference_candidate(space, mode, base)
+    out = runner.evaluate(ref)
+    if out is None:
+        raise RuntimeError("autotune: the reference candidate %r is not a valid plan" % ref)
+    ref_rec, ref_sups = out
+    runner.ref_supports = ref_sups
+    if truth is None:
+        ref_rec["quality"] = 1.0
+    floor = ref_rec["quality"] - (recall_slack if mode == sfft.SFFT_MODE_GENERAL else 0.0)
+    best = ref_rec
+
+    def accepted(rec):
+        return rec["quality"] >= floor - 1e-12
+
+    def ranked_accepted():
+        return sorted((r for r in runner.table if "ms" in r and accepted(r)), key=lambda r: r["ms"])
+
+    def stage(name, starts):
+        grid = space.get(name, {})
+        names = sorted(grid)
+        combos = [{}]
+        for f in names:
+            combos = [dict(c, **{f: v}) for c in combos for v in grid[f]]
+        for current in starts:
+            for combo in combos:
+                if time.time() - t_start > budget_s:
+                    return
+                cand = dict(current, **combo)
+                if any(r.get("cand") == cand for r in runner.table):
+                    continue
+                runner.evaluate(cand)
+
+    for name in ("window", "schedule", "launch"):
+        stage(name, [dict(r["cand"]) for r in ranked_accepted()[:beam]])
+    best = ranked_accepted()[0]
+
+    confirmed = 0
+    if confirm is not None and confirm_batches > 0:
+        ranked = [r for r in ranked_accepted() if r is not ref_rec][:confirm_top]
+        for rec in ranked:
+            rec["confirmed"] = 0
+        for i in range(confirm_batches):
+            if not ranked:
+                break
+            xb, sb, tb = confirm(i)
+            tb = None if tb is None else [np.sort(np.asarray(t, dtype=np.int64)) for t in tb]
+            ref_out = runner.run(ref_rec["cand"], xb, sb, reps=0)
+            if ref_out is None:
+                break
+            keep = []
+            for rec in ranked:
+                out = runner.run(rec["cand"], xb, sb, reps=0)
+                if out is not None and runner.survives(out[1], ref_out[1], tb, recall_slack):
+                    rec["confirmed"] += 1
+                    keep.append(rec)
+                elif log:
+                    log("autotune: confirmation batch %d drops %s" % (
+                        i, ", ".join("%s=%s" % kv for kv in sorted(rec["cand"].items()))))
+            ranked = keep
+            del xb, sb
+            confirmed = i + 1
+        best = ranked[0] if ranked else ref_rec
+
+    cand = dict(best["cand"])
+    B = int(cand.pop("B"))
+    res = TuneResult(B=B, fields=cand, ms=best["ms"], rate=count / (best["ms"] * 1e-3), quality=best["quality"],
+                     key=key, table=runner.table)
+    if cache:
+        _store_cache(cache, key, {"B": B, "fields": cand, "ms": res.ms, "rate": round(res.rate, 1),
+                                  "quality": res.quality, "candidates": len(runner.table),
+                                  "reference_ms": ref_rec["ms"], "confirm_batches": confirmed})
+    res.confirm_batches = confirmed
+    return res

@@ -232,6 +232,7 @@ sfft_status_t resolve_and_validate(sfft_plan_desc_t& d) {
     if (d.w == 0) d.w = default_w(d.n, d.B, d.alpha, d.delta);
     if (d.cap == 0) d.cap = d.k;
     if (d.rounds == 0) d.rounds = d.mode == SFFT_MODE_GENERAL ? general_default_rounds(d.k) : 16;
+    if (d.hash_threads == 0) d.hash_threads = 256;
     return SFFT_OK;
 }
 
@@ -455,6 +456,7 @@ H2BArgs base_h2b(const sfft_plan_s* p, const void* x) {
     a.tw = loc_f64(p) ? (const void*)p->d_tw64 : (const void*)p->d_tw32;
     a.sqrt_n = std::sqrt((double)p->d.n);
     a.mcap = p->mcap;
+    a.threads = p->d.hash_threads;
     return a;
 }
 
@@ -679,10 +681,13 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
 // run beside the HashToBins of chunk c+1, but the decode is latency bound
 // and slows sharply next to a kernel that saturates HBM: measured at
 // 512 x 2^22, k = 256, one chunk 3.69 ms, two 4.17 ms, four 5.50 ms.
-// SFFT_BATCH_CHUNKS overrides the count.
-uint32_t batch_chunks(uint32_t count) {
-    const char* e = std::getenv("SFFT_BATCH_CHUNKS");
-    uint32_t c = e ? (uint32_t)std::atoi(e) : 1u;
+// The plan's `chunks` sets the count; 0 takes SFFT_BATCH_CHUNKS, else one.
+uint32_t batch_chunks(const sfft_plan_s* p, uint32_t count) {
+    uint32_t c = p->d.chunks;
+    if (c == 0) {
+        const char* e = std::getenv("SFFT_BATCH_CHUNKS");
+        c = e ? (uint32_t)std::atoi(e) : 1u;
+    }
     return std::max(1u, std::min({c, kMaxChunks, count}));
 }
 
@@ -763,6 +768,9 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->cap = 0;
     d->flags = 0;
     d->max_batch = 1;
+    d->hash_threads = 256;
+    d->chunks = 0;
+    d->reserved = 0;
     return SFFT_OK;
 }
 
@@ -787,6 +795,10 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (d->patience < 1) return fail(SFFT_EINVAL, "patience must be >= 1");
     if (d->b_min != 0 && (!is_pow2(d->b_min) || d->b_min < 2)) return fail(SFFT_EINVAL, "b_min must be 0 or a power of two >= 2");
     if (d->max_batch < 1 || d->max_batch > (1u << 20)) return fail(SFFT_EINVAL, "max_batch must be in [1, 2^20]");
+    if (d->hash_threads != 0 && !h2b_threads_ok(d->hash_threads))
+        return fail(SFFT_EINVAL, "hash_threads must be 256, 512 or 1024 (or 0)");
+    if (d->chunks > kMaxChunks) return fail(SFFT_EINVAL, "chunks must be in [0, 8]");
+    if (d->reserved != 0) return fail(SFFT_EINVAL, "reserved must be 0");
     const uint32_t cap = d->cap ? d->cap : d->k;
     if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");
     if (d->mode == SFFT_MODE_GENERAL) {
@@ -964,7 +976,7 @@ sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigm
         mc = (uint64_t)std::max(s0, s1);
     }
     A.mcap = (uint32_t)mc;
-    if (h2b_pair_lds_bytes(p->Bmax, A.mcap, prec == SFFT_F64) > 160 * 1024)
+    if (h2b_pair_lds_bytes(p->Bmax, A.mcap, prec == SFFT_F64, A.threads) > 160 * 1024)
         return fail(SFFT_EUNSUPPORTED, "pair does not fit in LDS");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(launch_h2b_pair(A, in_c128(p), prec == SFFT_F64, s));
@@ -1046,7 +1058,7 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
     const bool timing = (p->d.flags & SFFT_FLAG_TIMING) != 0;
     const char* nog = std::getenv("SFFT_NO_GRAPH");
     const bool use_graph = !(nog && nog[0] == '1');
-    const uint32_t C = batch_chunks(count);
+    const uint32_t C = batch_chunks(p, count);
     const uint32_t per = (count + C - 1) / C;
     GraphCache& gc = p->graph;
     if (use_graph) {

@@ -99,6 +99,7 @@ struct H2BArgs {
     // exact batched mode: when set, blocks of signals whose decode has
     // stopped (state word ST_DONE) return before gathering
     const uint32_t* state;     // [sig][kStateWords] or nullptr
+    uint32_t threads;          // workgroup size of the pair launch: 256, 512, 1024 (0 = 256)
 };
 
 struct DecodeArgs {
@@ -188,7 +189,8 @@ hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_t r_end, hipStream_t s);
 hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s);
 
-size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64);
+size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64, uint32_t threads);
+bool h2b_threads_ok(uint32_t threads);
 size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax);
 
 // dense path (sfft_dense.hip): top `cap` bins by magnitude of `count`

@@ -26,14 +26,14 @@ constexpr int kGatherUnroll = SFFT_GATHER_UNROLL;
 // natural-order input, bit-reversed output), unnormalised, sign -:
 // X_j = sum_r V_r exp(-2 pi i j r / B).  tw holds exp(-2 pi i m / Bmax),
 // m < Bmax.
-template <class TA>
+template <class TA, uint32_t NT>
 __device__ void lds_fft2(cx<TA>* VA, cx<TA>* VB, uint32_t B, uint32_t Bmax,
                          const typename TwTraits<TA>::V* tw) {
     const uint32_t tid = threadIdx.x;
     const uint32_t hb = B >> 1;
     for (uint32_t half = hb; half >= 1; half >>= 1) {
         const uint32_t tstride = Bmax / (2 * half);
-        for (uint32_t k = tid; k < B; k += kThreads) {
+        for (uint32_t k = tid; k < B; k += NT) {
             cx<TA>* V = k < hb ? VA : VB;
             const uint32_t kk = k & (hb - 1);
             const uint32_t j = kk & (half - 1);
@@ -55,7 +55,7 @@ __device__ void lds_fft2(cx<TA>* VA, cx<TA>* VB, uint32_t B, uint32_t Bmax,
 // The modulation omega^{c t}, c = sigma b, is split as omega^{c r} (applied
 // per residue later) times M_L = omega^{c B L} (table in LDS).  Partial sums
 // are added into VA/VB[part * B + r].
-template <class TIn, class TA>
+template <class TIn, class TA, uint32_t NT>
 __device__ void accumulate_pair(const TIn* __restrict__ x, const TA* __restrict__ G, cx<TA>* VA,
                                 cx<TA>* VB, cx<TA>* M, uint64_t n, uint64_t sigma, uint64_t a,
                                 uint64_t beta, uint64_t b, uint32_t B, uint32_t logB, uint64_t w,
@@ -88,10 +88,10 @@ __device__ void accumulate_pair(const TIn* __restrict__ x, const TA* __restrict_
         Lhi = Lhi < Lwin_hi ? Lhi : Lwin_hi;
         if (Llo > Lhi) continue;   // uniform over the block
         __syncthreads();
-        for (int64_t L = Llo + tid; L <= Lhi; L += kThreads)
+        for (int64_t L = Llo + tid; L <= Lhi; L += NT)
             M[L - Llo] = to_cx<TA>(omega_d((cB * (uint64_t)L) & mask, n));
         __syncthreads();
-        for (uint32_t slot = tid; slot < parts * B; slot += kThreads) {
+        for (uint32_t slot = tid; slot < parts * B; slot += NT) {
             const uint32_t part = slot >> logB;
             const uint32_t r = slot & (B - 1);
             int64_t L0 = floordiv(lo[sg] - (int64_t)r + iB - 1, iB);
@@ -141,12 +141,12 @@ __device__ void accumulate_pair(const TIn* __restrict__ x, const TA* __restrict_
 
 // Sum the parts of column r, apply omega^{c r} (hashing A) and
 // omega^{c (r + beta)} (hashing B), leaving natural-order folds in VA/VB[0, B).
-template <class TA>
+template <class TA, uint32_t NT>
 __device__ void finalize_folds(cx<TA>* VA, cx<TA>* VB, uint64_t n, uint64_t sigma, uint64_t b,
                                uint64_t beta, uint32_t B, uint32_t parts) {
     const uint64_t mask = n - 1;
     const uint64_t c = (sigma * b) & mask;
-    for (uint32_t r = threadIdx.x; r < B; r += kThreads) {
+    for (uint32_t r = threadIdx.x; r < B; r += NT) {
         cx<TA> sa = VA[r], sb = VB[r];
         for (uint32_t p = 1; p < parts; ++p) {
             sa = cadd(sa, VA[p * B + r]);
@@ -161,12 +161,12 @@ __device__ void finalize_folds(cx<TA>* VA, cx<TA>* VB, uint64_t n, uint64_t sigm
 
 // After lds_fft2: bin j of A is VA[bitrev j]; hashing B was folded by the
 // residue of t_A, so its bin j carries the extra factor exp(-2 pi i j beta / B).
-template <class TA>
+template <class TA, uint32_t NT>
 __device__ void store_bins(const cx<TA>* VA, const cx<TA>* VB, uint32_t B, uint32_t logB, uint32_t Bmax,
                            uint64_t beta, const typename TwTraits<TA>::V* tw, double sqrt_n,
                            double* out0, double* out1) {
     const uint32_t bstride = Bmax / B;
-    for (uint32_t j = threadIdx.x; j < B; j += kThreads) {
+    for (uint32_t j = threadIdx.x; j < B; j += NT) {
         const uint32_t br = bitrev(j, logB);
         const cx<TA> va = VA[br];
         cx<TA> vb = VB[br];
@@ -180,8 +180,8 @@ __device__ void store_bins(const cx<TA>* VA, const cx<TA>* VB, uint32_t B, uint3
     }
 }
 
-template <class TIn, class TA>
-__global__ void __launch_bounds__(kThreads) k_h2b_pair(H2BArgs A) {
+template <class TIn, class TA, uint32_t NT>
+__global__ void __launch_bounds__(NT) k_h2b_pair(H2BArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t sig, r, ro;
     const uint64_t n = A.n;
@@ -236,22 +236,22 @@ __global__ void __launch_bounds__(kThreads) k_h2b_pair(H2BArgs A) {
     const TA* G = reinterpret_cast<const TA*>(A.gtab) + g.gofs;
     const auto* tw = reinterpret_cast<const typename TwTraits<TA>::V*>(A.tw);
     const uint32_t B = g.B;
-    const uint32_t parts = B >= kThreads ? 1u : kThreads / B;
+    const uint32_t parts = B >= NT ? 1u : NT / B;
     cx<TA>* VA = reinterpret_cast<cx<TA>*>(smem);
     cx<TA>* VB = VA + parts * B;
     cx<TA>* M = VB + parts * B;
-    for (uint32_t q = threadIdx.x; q < parts * B; q += kThreads) {
+    for (uint32_t q = threadIdx.x; q < parts * B; q += NT) {
         VA[q] = cx<TA>{0, 0};
         VB[q] = cx<TA>{0, 0};
     }
-    accumulate_pair<TIn, TA>(x, G, VA, VB, M, n, sigma, a, beta, b, B, g.logB, g.w, g.t0,
-                             INT64_MIN / 4, INT64_MAX / 4, parts);
+    accumulate_pair<TIn, TA, NT>(x, G, VA, VB, M, n, sigma, a, beta, b, B, g.logB, g.w, g.t0,
+                                 INT64_MIN / 4, INT64_MAX / 4, parts);
     __syncthreads();
-    finalize_folds<TA>(VA, VB, n, sigma, b, beta, B, parts);
+    finalize_folds<TA, NT>(VA, VB, n, sigma, b, beta, B, parts);
     __syncthreads();
-    lds_fft2<TA>(VA, VB, B, A.Bmax, tw);
+    lds_fft2<TA, NT>(VA, VB, B, A.Bmax, tw);
     double* out0 = A.raw + (((uint64_t)sig * A.raw_rounds + ro) * 2) * (uint64_t)A.Bmax * 2;
-    store_bins<TA>(VA, VB, B, g.logB, A.Bmax, beta, tw, A.sqrt_n, out0, out0 + 2 * (uint64_t)A.Bmax);
+    store_bins<TA, NT>(VA, VB, B, g.logB, A.Bmax, beta, tw, A.sqrt_n, out0, out0 + 2 * (uint64_t)A.Bmax);
 }
 
 // Plain path, stage 1: block p accumulates window chunk p (lchunk values of L)
@@ -277,7 +277,8 @@ __global__ void __launch_bounds__(kThreads) k_h2b_split(H2BArgs A, uint32_t roun
     const int64_t Lmin = floordiv(g.t0 - (int64_t)beta - (iB - 1), iB);
     const int64_t Llo = Lmin + (int64_t)blockIdx.x * A.lchunk;
     const int64_t Lhi = Llo + A.lchunk - 1;
-    accumulate_pair<TIn, TA>(x, G, VA, VB, M, n, sigma, a, beta, b, B, g.logB, g.w, g.t0, Llo, Lhi, parts);
+    accumulate_pair<TIn, TA, kThreads>(x, G, VA, VB, M, n, sigma, a, beta, b, B, g.logB, g.w, g.t0, Llo, Lhi,
+                                       parts);
     __syncthreads();
     double* out = A.partial + (uint64_t)blockIdx.x * 4 * B;
     for (uint32_t r = threadIdx.x; r < B; r += kThreads) {
@@ -316,26 +317,42 @@ __global__ void __launch_bounds__(kThreads) k_h2b_reduce(H2BArgs A, uint32_t rou
         VB[r] = cx<TA>{(TA)br, (TA)bi};
     }
     __syncthreads();
-    finalize_folds<TA>(VA, VB, A.n, A.sigma, A.b, A.beta, B, 1);
+    finalize_folds<TA, kThreads>(VA, VB, A.n, A.sigma, A.b, A.beta, B, 1);
     __syncthreads();
-    lds_fft2<TA>(VA, VB, B, A.Bmax, tw);
+    lds_fft2<TA, kThreads>(VA, VB, B, A.Bmax, tw);
     double* out0 = A.raw + ((uint64_t)round * 2) * (uint64_t)A.Bmax * 2;
-    store_bins<TA>(VA, VB, B, g.logB, A.Bmax, A.beta, tw, A.sqrt_n, out0, out0 + 2 * (uint64_t)A.Bmax);
+    store_bins<TA, kThreads>(VA, VB, B, g.logB, A.Bmax, A.beta, tw, A.sqrt_n, out0, out0 + 2 * (uint64_t)A.Bmax);
 }
 
 // ------------------------------------------------------------------ launch --
-size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64) {
+bool h2b_threads_ok(uint32_t threads) { return threads == 256 || threads == 512 || threads == 1024; }
+
+size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64, uint32_t threads) {
     const size_t csz = acc_f64 ? 16 : 8;
-    const size_t slots = Bmax >= kThreads ? Bmax : kThreads;
+    const size_t slots = Bmax >= threads ? Bmax : threads;
     return (2 * slots + max_mcount) * csz;
 }
 
-template <class TIn, class TA>
-static hipError_t launch_pair_t(const H2BArgs& a, size_t lds, uint32_t grid, hipStream_t s) {
-    hipError_t e = allow_lds(k_h2b_pair<TIn, TA>, lds);
+template <class TIn, class TA, uint32_t NT>
+static hipError_t launch_pair_nt(const H2BArgs& a, uint32_t grid, hipStream_t s) {
+    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, sizeof(TA) == 8, NT);
+    hipError_t e = allow_lds(k_h2b_pair<TIn, TA, NT>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_h2b_pair<TIn, TA>), dim3(grid), dim3(kThreads), lds, s, a);
+    hipLaunchKernelGGL((k_h2b_pair<TIn, TA, NT>), dim3(grid), dim3(NT), lds, s, a);
     return hipGetLastError();
+}
+
+// Workgroup size of the batched pair launch: a.threads (256, 512 or 1024;
+// 0 = 256), chosen per plan.
+template <class TIn, class TA>
+static hipError_t launch_pair_t(const H2BArgs& a, uint32_t grid, hipStream_t s) {
+    switch (a.threads) {
+        case 512: return launch_pair_nt<TIn, TA, 512>(a, grid, s);
+        case 1024: return launch_pair_nt<TIn, TA, 1024>(a, grid, s);
+        case 0:
+        case 256: return launch_pair_nt<TIn, TA, 256>(a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <class TIn, class TA>
@@ -348,15 +365,13 @@ static hipError_t launch_split_t(const H2BArgs& a, uint32_t round, size_t lds, h
 
 hipError_t launch_h2b_pair(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s) {
     // LDS: two fold arrays of max(Bmax, threads) plus the modulation table
-    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, acc_f64);
     const uint32_t grid = a.explicit_job ? 1u : (a.jobs ? a.count * a.njobs : a.count * a.nrounds);
-    if (in_c128) return acc_f64 ? launch_pair_t<double2, double>(a, lds, grid, s)
-                                : launch_pair_t<double2, float>(a, lds, grid, s);
-    return acc_f64 ? launch_pair_t<float2, double>(a, lds, grid, s) : launch_pair_t<float2, float>(a, lds, grid, s);
+    if (in_c128) return acc_f64 ? launch_pair_t<double2, double>(a, grid, s) : launch_pair_t<double2, float>(a, grid, s);
+    return acc_f64 ? launch_pair_t<float2, double>(a, grid, s) : launch_pair_t<float2, float>(a, grid, s);
 }
 
 hipError_t launch_h2b_split(const H2BArgs& a, uint32_t round, bool in_c128, bool acc_f64, hipStream_t s) {
-    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, acc_f64);
+    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, acc_f64, kThreads);
     if (in_c128) return acc_f64 ? launch_split_t<double2, double>(a, round, lds, s)
                                 : launch_split_t<double2, float>(a, round, lds, s);
     return acc_f64 ? launch_split_t<float2, double>(a, round, lds, s) : launch_split_t<float2, float>(a, round, lds, s);

@@ -1,0 +1,59 @@
+"""Host-side checks of the autotuner: its candidate space, the conservative
+reference candidate, the cache file, and the plan fields it sets (validated
+by the library without a GPU)."""
+import ctypes
+import json
+
+import pytest
+
+from paper_1201_2501_amd import autotune, sfft
+
+
+def test_default_space_exact_respects_kernel_limits():
+    sp = autotune.default_space(1 << 22, 256, sfft.SFFT_MODE_EXACT)
+    assert sp["window"]["B"] == [512, 1024, 2048, 4096]
+    assert set(sp["launch"]["hash_threads"]) == {256, 512, 1024}
+    small = autotune.default_space(1 << 14, 16, sfft.SFFT_MODE_EXACT)
+    assert max(small["window"]["B"]) <= (1 << 14) // 16
+    gen = autotune.default_space(1 << 26, 1024, sfft.SFFT_MODE_GENERAL)
+    assert gen["window"]["B"] == [4096]
+
+
+def test_reference_candidate_is_the_conservative_corner():
+    sp = autotune.default_space(1 << 22, 256, sfft.SFFT_MODE_EXACT)
+    ref = autotune.reference_candidate(sp, sfft.SFFT_MODE_EXACT, {"theta": 0.02})
+    assert ref["B"] == 4096 and ref["delta"] == 1e-10 and ref["b_min"] == 64 and ref["patience"] == 4
+    assert ref["theta"] == 0.02 and ref["hash_threads"] == 256 and ref["chunks"] == 1
+
+
+def test_every_candidate_field_is_a_plan_field_that_validates():
+    lib = sfft.load()
+    sp = autotune.default_space(1 << 22, 256, sfft.SFFT_MODE_EXACT)
+    for stage in sp.values():
+        for f, values in stage.items():
+            for v in values:
+                d = sfft.sfft_desc_init(1 << 22, 256, 1024)
+                setattr(d, "B" if f == "B" else f, v)
+                assert lib.sfft_validate_params(ctypes.byref(d)) == sfft.SFFT_OK, (f, v)
+
+
+@pytest.mark.parametrize("field,value", [("hash_threads", 128), ("hash_threads", 768), ("chunks", 9),
+                                         ("reserved", 1)])
+def test_launch_shape_fields_are_validated(field, value):
+    lib = sfft.load()
+    d = sfft.sfft_desc_init(1 << 20, 64, 512)
+    setattr(d, field, value)
+    assert lib.sfft_validate_params(ctypes.byref(d)) == sfft.SFFT_EINVAL
+
+
+def test_cache_round_trip(tmp_path):
+    path = str(tmp_path / "tuned.json")
+    key = autotune.cache_key(1 << 20, 64, 0, 32, 0, "test-device")
+    autotune._store_cache(path, key, {"B": 512, "fields": {"b_min": 32, "hash_threads": 512}, "ms": 1.5,
+                                      "rate": 21333.3, "quality": 1.0})
+    hit = autotune.lookup(path, 1 << 20, 64, 0, 32, 0, "test-device")
+    assert hit.from_cache and hit.B == 512 and hit.fields["hash_threads"] == 512
+    assert autotune.lookup(path, 1 << 20, 64, 0, 64, 0, "test-device") is None      # other batch size
+    assert autotune.lookup(path, 1 << 20, 64, 0, 32, 0, "other-device") is None
+    assert json.load(open(path))[key]["ms"] == 1.5
+    assert autotune.lookup(str(tmp_path / "missing.json"), 1 << 20, 64, 0, 32, 0, "test-device") is None

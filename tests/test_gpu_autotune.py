@@ -1,0 +1,56 @@
+"""GPU check of the autotuner on a small exactly-sparse batch: the choice
+recovers every planted support, is no slower than the reference candidate
+measured in the same run, comes back from the cache, and a plan built from
+it reproduces the planted supports.  Every case prints its name first."""
+import numpy as np
+import pytest
+
+import siggen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def test_autotune_small_exact_batch(tmp_path):
+    import torch
+    from paper_1201_2501_amd import autotune, sfft
+
+    sfft.load()
+    dev = torch.device("cuda:0")
+    n, k, count = 1 << 18, 32, 32
+    say("autotune", "n", n, "k", k, "count", count)
+    X, sups, _ = siggen.torch_planted_batch(n, k, [7000 + s for s in range(count)], dev, magnitude="loguniform")
+    seeds = torch.arange(count, dtype=torch.int64, device=dev) * 13 + 5
+    space = {"window": {"B": [128, 256], "delta": [1e-9]},
+             "schedule": {"b_min": [16, 32], "patience": [3]},
+             "launch": {"hash_threads": [256, 512], "chunks": [1]}}
+    base = dict(theta=0.02, rounds=24, loc_prec=sfft.SFFT_F64)
+    cache = str(tmp_path / "tuned.json")
+
+    def confirm(i):
+        xb, sb, _ = siggen.torch_planted_batch(n, k, [8000 + 100 * i + s for s in range(count)], dev,
+                                               magnitude="loguniform")
+        return xb, torch.arange(count, dtype=torch.int64, device=dev) * 29 + 3 + i, sb
+
+    res = autotune.tune(X, k, sfft.SFFT_MODE_EXACT, seeds=seeds, truth=sups, base=base, space=space, reps=2,
+                        cache=cache, confirm=confirm, confirm_batches=2)
+    assert res.quality == 1.0 and res.B in (128, 256) and res.confirm_batches == 2
+    assert res.fields["b_min"] in (16, 32) and res.fields["hash_threads"] in (256, 512)
+    ok = [r for r in res.table if "ms" in r]
+    assert len(ok) >= 4 and all(r["quality"] == 1.0 for r in ok)
+    ref_ms = ok[0]["ms"]                                  # the reference candidate runs first
+    assert res.ms <= ref_ms
+    hit = autotune.tune(X, k, sfft.SFFT_MODE_EXACT, seeds=seeds, truth=sups, base=base, space=space,
+                        cache=cache)
+    assert hit.from_cache and hit.B == res.B and hit.fields == res.fields and hit.confirm_batches == 2
+    plan = sfft.Plan(n, k, res.B, 0, 0, max_batch=count, **{f: v for f, v in res.fields.items()})
+    bufs = plan.execute_batch(X, seeds)
+    torch.cuda.synchronize()
+    counts = bufs["counts"].cpu().numpy()
+    idx = bufs["idx"].cpu().numpy()
+    for s in range(count):
+        assert np.array_equal(idx[s, :counts[s]], np.sort(sups[s]))
+    plan.close()

@@ -229,6 +229,36 @@ def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     plan.close()
 
 
+@pytest.mark.parametrize("threads,chunks", [(512, 1), (1024, 1), (256, 2), (1024, 2)])
+def test_c3_launch_shapes_match_oracle(torch_dev, threads, chunks):
+    """The launch shape the autotuner picks from (HashToBins workgroup size,
+    batch chunks) leaves supports and rounds unchanged and values within the
+    FP64 bar: with B_r < threads a bin's partial sums are only added in
+    another order."""
+    torch, dev = torch_dev
+    n, k, B = 1 << 22, 256, 1024
+    w = default_w(n, B, 0.5, 1e-9)
+    count = 4
+    say("c3-launch-shape", "threads", threads, "chunks", chunks, "count", count)
+    plan = plan_for(n, k, B, w, 0, delta=1e-9, theta=0.02, loc_prec=1, max_batch=count, b_min=32, rounds=24,
+                    hash_threads=threads, chunks=chunks, flags=2)     # SFFT_FLAG_TIMING: chunk count
+    assert plan.desc.hash_threads == threads and plan.desc.chunks == chunks
+    xs, sups, seeds = [], [], []
+    for s in range(count):
+        x, sup, _ = siggen.planted_signal(n, k, 4000 + s, np.complex64, magnitude="loguniform")
+        xs.append(x)
+        sups.append(sup)
+        seeds.append(31 * s + 7)
+    out = run_batch(torch, dev, plan, xs, seeds)
+    assert plan.timings()[4] == chunks
+    for s in range(count):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        assert int(out[s][2][0]) == ref.rounds_used
+        compare(out[s][0], out[s][1], ref)
+        assert np.array_equal(out[s][0], sups[s])
+    plan.close()
+
+
 def test_c3_round_groups_skip_only_undecoded_rounds(torch_dev):
     """The batched exact path hashes round group 0 for every signal and each
     later group only for signals still decoding: a batch whose signals stop
