@@ -266,8 +266,7 @@ def main():
     if args.tune != "off" and not args.w:
         res = None
         if args.tune == "cache":
-            res = autotune.lookup(TUNE_FILE, n, k, sfft.SFFT_MODE_EXACT, S, sfft.SFFT_C64,
-                                  torch.cuda.get_device_name(dev))
+            res = autotune.lookup(TUNE_FILE, n, k, sfft.SFFT_MODE_EXACT, S, sfft.SFFT_C64, autotune.device_tag(dev))
         if res is None and not args.config_key:
             t = time.time()
             cal_seeds = [2_000_003 + s for s in range(S)]

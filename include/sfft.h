@@ -106,9 +106,10 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *   flags     SFFT_FLAG_*
  *   max_batch largest count accepted by sfft_execute_batch (workspace size)
  *   hash_threads  workgroup size of the batched HashToBins pair launches:
- *             256, 512 or 1024 (0 = 256).  Launch shape only: results are
- *             the same up to the summation order of a bin's partial sums
- *             when B_r < hash_threads
+ *             256, 512 or 1024 (0 = 256); an exact-mode launch halves it
+ *             (not below 256) while it exceeds the largest B_r of its
+ *             rounds.  Launch shape only: results are the same up to the
+ *             summation order of a bin's partial sums when B_r < threads
  *   chunks    sfft_execute_batch splits the batch into this many chunks whose
  *             decode overlaps the next chunk's HashToBins, 1..8 (0 = the
  *             SFFT_BATCH_CHUNKS environment variable, else 1).  Launch

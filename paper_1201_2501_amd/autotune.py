@@ -126,6 +126,16 @@ class TuneResult:
                 "confirm_batches": self.confirm_batches}
 
 
+def device_tag(device):
+    """Architecture and compute-unit count of a torch device (stable across
+    runtimes, unlike the marketing name)."""
+    import torch
+
+    pr = torch.cuda.get_device_properties(device)
+    arch = getattr(pr, "gcnArchName", "") or pr.name
+    return "%s-%dcu" % (arch.split(":")[0], pr.multi_processor_count)
+
+
 def cache_key(n, k, mode, count, in_dtype, device_name):
     return "%s|n=%d|k=%d|mode=%d|count=%d|dtype=%d|lib=%s" % (device_name, n, k, mode, count, in_dtype,
                                                               library_hash())
@@ -262,9 +272,10 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
     base.setdefault("mode", mode)
     space = space or default_space(n, k, mode)
     in_dtype = sfft.SFFT_C128 if x.dtype == torch.complex128 else sfft.SFFT_C64
-    key = cache_key(n, k, mode, count, in_dtype, torch.cuda.get_device_name(x.device))
+    tag = device_tag(x.device)
+    key = cache_key(n, k, mode, count, in_dtype, tag)
     if cache and not force:
-        hit = lookup(cache, n, k, mode, count, in_dtype, torch.cuda.get_device_name(x.device))
+        hit = lookup(cache, n, k, mode, count, in_dtype, tag)
         if hit:
             return hit
 

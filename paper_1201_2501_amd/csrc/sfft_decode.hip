@@ -138,6 +138,38 @@ __device__ __forceinline__ DecodeLds decode_lds(unsigned char* smem, uint32_t ca
     return L;
 }
 
+// Dynamic LDS of one per-round re-estimation block (exact mode): the bins
+// of the entries, their grouping by bin and one term G' zhat per entry; the
+// bin counters and the placement targets of group_by_bin share storage.
+__host__ __device__ inline size_t reest_lds_layout(uint32_t capz, uint32_t Bmax, unsigned char* base, DecodeLds* L) {
+    size_t off = 0;
+    const size_t o_hk = off;
+    off = align16(off + (size_t)capz * 2);
+    const size_t o_ent = off;
+    off = align16(off + (size_t)capz * 2);
+    const size_t o_first = off;
+    off = align16(off + ((size_t)Bmax + 1) * 4);
+    const size_t o_union = off;
+    off = align16(off + (size_t)(capz > Bmax ? capz : Bmax) * 4);
+    const size_t o_scan = off;
+    off = align16(off + (kDec / 64) * 4);
+    const size_t o_t = off;
+    off = align16(off + (size_t)capz * 16);
+    if (base) {
+        *L = DecodeLds{};
+        L->hk = reinterpret_cast<uint16_t*>(base + o_hk);
+        L->ent = reinterpret_cast<uint16_t*>(base + o_ent);
+        L->first = reinterpret_cast<uint32_t*>(base + o_first);
+        L->cnt = reinterpret_cast<uint32_t*>(base + o_union);
+        L->ckey = reinterpret_cast<uint64_t*>(base + o_union);
+        L->scan = reinterpret_cast<uint32_t*>(base + o_scan);
+        L->t = reinterpret_cast<cx<double>*>(base + o_t);
+    }
+    return off;
+}
+
+size_t reest_lds_bytes(uint32_t capz, uint32_t Bmax) { return reest_lds_layout(capz, Bmax, nullptr, nullptr); }
+
 // The signal's state words into LDS (start of a kernel) and back (end).
 __device__ __forceinline__ void load_state(DecodeLds& L, const uint32_t* st) {
     if (threadIdx.x < kStateWords) L.sw[threadIdx.x] = st[threadIdx.x];
@@ -410,6 +442,55 @@ __device__ cx<double> median_cx(const double* src, uint32_t c) {
     if (c <= 16) return {median_net<16>(src, c), median_net<16>(src + 1, c)};
     if (KMAX == 32 || c <= 32) return {median_net<32>(src, c), median_net<32>(src + 1, c)};
     return median_cx64(src, c);
+}
+
+// Median of the samples src[r * stride] for the rounds r set in `mask`
+// (popcount <= K), by the network of median_net.
+template <uint32_t K>
+__device__ __forceinline__ double median_net_mask(const double* src, uint32_t mask, uint64_t stride) {
+    double a[K];
+    const uint32_t c = __popc(mask);
+    uint32_t m = mask;
+#pragma unroll
+    for (uint32_t q = 0; q < K; ++q) {
+        a[q] = __builtin_huge_val();
+        if (m) {
+            a[q] = src[(uint64_t)__builtin_ctz(m) * stride];
+            m &= m - 1;
+        }
+    }
+#pragma unroll
+    for (uint32_t k = 2; k <= K; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (uint32_t i = 0; i < K; ++i) {
+                const uint32_t l = i ^ j;
+                if (l > i) {
+                    const double lo = fmin(a[i], a[l]), hi = fmax(a[i], a[l]);
+                    const bool up = (i & k) == 0;
+                    a[i] = up ? lo : hi;
+                    a[l] = up ? hi : lo;
+                }
+            }
+        }
+    }
+    double m0 = 0.0, m1 = 0.0;
+#pragma unroll
+    for (uint32_t q = 0; q < K; ++q) {
+        if (q + 1 == c / 2) m0 = a[q];
+        if (q == c / 2) m1 = a[q];
+    }
+    return (c & 1) ? m1 : 0.5 * (m0 + m1);
+}
+
+// Complex median over the rounds in `mask` (at most 32) of samples stored as
+// (re, im) pairs `stride` doubles apart per round.
+__device__ cx<double> median_cx_mask(const double* src, uint32_t mask, uint64_t stride) {
+    const uint32_t c = __popc(mask);
+    if (c <= 8) return {median_net_mask<8>(src, mask, stride), median_net_mask<8>(src + 1, mask, stride)};
+    if (c <= 16) return {median_net_mask<16>(src, mask, stride), median_net_mask<16>(src + 1, mask, stride)};
+    return {median_net_mask<32>(src, mask, stride), median_net_mask<32>(src + 1, mask, stride)};
 }
 
 // Sort key ordering by |v| descending, then slot ascending (51 magnitude bits).
@@ -769,6 +850,111 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
     for (uint32_t e = tid; e < zc; e += kDec) {
         const cx<double> v = entry_median<kMaxRounds>(est + (uint64_t)e * nmeas * 2, nmeas, L.ec[e],
                                                       cx<double>{zv[2 * e], zv[2 * e + 1]});
+        fin[2 * e] = v.r;
+        fin[2 * e + 1] = v.i;
+    }
+    __syncthreads();
+    uint32_t flags = L.sw[ST_FLAGS];
+    const uint32_t nout = write_output(L, zi, fin, zc, false, 0.5 * D.theta, D.cap, D.out_scale,
+                                       D.out_idx + (uint64_t)sig * D.cap, D.out_val + (uint64_t)sig * D.cap * 2,
+                                       &flags);
+    if (tid == 0) {
+        D.out_count[sig] = nout;
+        st[ST_FLAGS] = flags;
+        if (D.out_info) {
+            D.out_info[(uint64_t)sig * 4 + SFFT_INFO_ROUNDS] = R;
+            D.out_info[(uint64_t)sig * 4 + SFFT_INFO_FLAGS] = flags;
+            D.out_info[(uint64_t)sig * 4 + SFFT_INFO_ZHAT] = zc;
+            D.out_info[(uint64_t)sig * 4 + SFFT_INFO_LOCATED] = 0;
+        }
+    }
+}
+
+// The same re-estimation split over workgroups, where its LDS fits: block
+// (signal, round r) records the estimate of every zhat entry from round r
+// (the other entries of its bin removed, in ascending index order), flagged
+// isolated or crowded; k_exact_output takes the medians and writes the
+// output.  Each sample is computed exactly as in k_exact_finish, and a
+// median does not depend on the order of its samples.  Samples and flags
+// are stored round-major ([sig][round][capz]) so that both kernels access
+// them contiguously across the entries of a wave.
+__global__ void __launch_bounds__(kDec) k_exact_reest(DecodeArgs D) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sig = blockIdx.x / D.rounds;
+    const uint32_t r = blockIdx.x - sig * D.rounds;
+    const uint32_t* st = D.state + (uint64_t)sig * kStateWords;
+    if (r >= st[ST_ROUNDS]) return;
+    const uint32_t zc = st[ST_ZCOUNT], zb = st[ST_ZBUF];
+    DecodeLds L;
+    reest_lds_layout(D.capz, D.Bmax, smem, &L);
+    const uint64_t seed = D.seeds ? D.seeds[sig] : D.plan_seed;
+    const uint64_t n = D.n;
+    const RoundDev g = D.geom[r];
+    const uint32_t B = g.B;
+    const uint64_t sigma = draw_sigma(seed, n, r), b = draw_b(seed, n, r);
+    const uint64_t* zi = D.zidx + ((uint64_t)sig * 2 + zb) * D.capz;
+    const double2* zv2 = reinterpret_cast<const double2*>(D.zval + ((uint64_t)sig * 2 + zb) * D.capz * 2);
+    for (uint32_t e = tid; e < zc; e += kDec) {
+        const BinOffset bo = bin_offset(zi[e], sigma, b, n, B);
+        L.hk[e] = (uint16_t)bo.h;
+        const double gp = gprime(-bo.o, n, B, g.ws);
+        const double2 z = zv2[e];
+        L.t[e] = cx<double>{gp * z.x, gp * z.y};
+    }
+    __syncthreads();
+    group_by_bin(L, zc, B);
+    const double2* r0 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 0));
+    const uint64_t row = ((uint64_t)sig * D.rounds + r) * D.capz;
+    double2* est = reinterpret_cast<double2*>(D.est) + row;
+    uint8_t* flag = D.eflag + row;
+    for (uint32_t e = tid; e < zc; e += kDec) {
+        const uint32_t h = L.hk[e];
+        const double2 a0 = r0[h];
+        const double ge = gprime(-bin_offset(zi[e], sigma, b, n, B).o, n, B, g.ws);
+        if (ge < D.g_min) {
+            flag[e] = 0;
+            continue;
+        }
+        const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
+        double orr = 0.0, oii = 0.0;
+        for (uint32_t q = p0; q < p1; ++q) {
+            const uint32_t e2 = L.ent[q];
+            if (e2 == e) continue;
+            const cx<double> c2 = L.t[e2];
+            orr += c2.r;
+            oii += c2.i;
+        }
+        est[e] = make_double2((a0.x - orr) / ge, (a0.y - oii) / ge);
+        flag[e] = p1 - p0 == 1 ? 1 : 2;
+    }
+}
+
+__global__ void __launch_bounds__(kDec) k_exact_output(DecodeArgs D) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sig = blockIdx.x;
+    DecodeLds L = decode_lds(smem, D.capz, D.Bmax, D.gtmp + (uint64_t)sig * D.capz * 4, D.ecount + (uint64_t)sig * D.capz);
+    uint32_t* st = D.state + (uint64_t)sig * kStateWords;
+    load_state(L, st);
+    const uint32_t R = L.sw[ST_ROUNDS];
+    const uint32_t zc = L.sw[ST_ZCOUNT];
+    const uint64_t* zi = D.zidx + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * D.capz;
+    const double* zv = D.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * D.capz * 2;
+    const uint64_t base = (uint64_t)sig * D.rounds * D.capz;
+    const double* est = D.est + base * 2;
+    const uint8_t* flag = D.eflag + base;
+    double* fin = D.fin + (uint64_t)sig * D.capz * 2;
+    for (uint32_t e = tid; e < zc; e += kDec) {
+        uint32_t iso = 0, crowd = 0;
+        for (uint32_t q = 0; q < R; ++q) {
+            const uint8_t f = flag[(uint64_t)q * D.capz + e];
+            iso |= (f == 1 ? 1u : 0u) << q;
+            crowd |= (f == 2 ? 1u : 0u) << q;
+        }
+        const uint32_t mask = iso ? iso : crowd;
+        const cx<double> v = mask ? median_cx_mask(est + 2 * (uint64_t)e, mask, 2 * (uint64_t)D.capz)
+                                  : cx<double>{zv[2 * e], zv[2 * e + 1]};
         fin[2 * e] = v.r;
         fin[2 * e + 1] = v.i;
     }
@@ -1215,8 +1401,20 @@ hipError_t launch_exact_decode(const DecodeArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The split re-estimation (signal x round workgroups, then one output
+// workgroup per signal) where its LDS fits, else one workgroup per signal.
 hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s) {
     const size_t lds = decode_lds_bytes(a.capz, a.Bmax);
+    const size_t rlds = reest_lds_bytes(a.capz, a.Bmax);
+    if (rlds <= kLdsLimit) {
+        hipError_t e = allow_lds(k_exact_reest, rlds);
+        if (e != hipSuccess) return e;
+        e = allow_lds(k_exact_output, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_exact_reest, dim3(a.count * a.rounds), dim3(kDec), rlds, s, a);
+        hipLaunchKernelGGL(k_exact_output, dim3(a.count), dim3(kDec), lds, s, a);
+        return hipGetLastError();
+    }
     hipError_t e = allow_lds(k_exact_finish, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_exact_finish, dim3(a.count), dim3(kDec), lds, s, a);

@@ -399,7 +399,6 @@ sfft_status_t build_plan(sfft_plan_s* p) {
         ST_TRY(dev_alloc(p, &p->gent, S * Z));
         ST_TRY(dev_alloc(p, &p->cand_raw, S * Bm));
         ST_TRY(dev_alloc(p, &p->cand_cnt, S));
-        ST_TRY(dev_alloc(p, &p->eflag, S * Z * meas));
         ST_TRY(dev_alloc(p, &p->gterm, S * std::max<size_t>(R, d.R_est) * Z * 4));
     }
     ST_TRY(dev_alloc(p, &p->work, S * 4 * Bm));
@@ -408,6 +407,7 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     ST_TRY(dev_alloc(p, &p->zidx, S * 2 * Z));
     ST_TRY(dev_alloc(p, &p->zval, S * 4 * Z));
     ST_TRY(dev_alloc(p, &p->est, S * Z * meas * 2));
+    ST_TRY(dev_alloc(p, &p->eflag, S * Z * meas));
     ST_TRY(dev_alloc(p, &p->fin, S * Z * 2));
     ST_TRY(dev_alloc(p, &p->gtmp, S * Z * 4));
     ST_TRY(dev_alloc(p, &p->ecount, S * Z));
@@ -486,6 +486,7 @@ DecodeArgs base_decode(const sfft_plan_s* p, uint32_t count, const uint64_t* see
     D.fin = p->fin;
     D.gtmp = p->gtmp;
     D.ecount = p->ecount;
+    D.eflag = p->eflag;
     D.state = p->state;
     D.theta = p->d.theta;
     D.g_min = p->d.g_min;
@@ -586,6 +587,7 @@ void offset_decode(const sfft_plan_s* p, DecodeArgs& D, uint32_t off) {
     D.fin += o * 2 * Z;
     D.gtmp += o * Z * 4;
     D.ecount += o * Z;
+    D.eflag += o * Z * p->R;
     D.state += o * kStateWords;
     if (D.seeds) D.seeds += o;
     D.out_idx += o * p->cap;
@@ -622,6 +624,18 @@ void offset_general(const sfft_plan_s* p, GeneralArgs& G, uint32_t off) {
     if (G.out_info) G.out_info += o * 4;
 }
 
+// Workgroup size of an exact-mode pair launch over rounds [r0, r1): the
+// plan's hash_threads, halved (not below 256) while it exceeds the largest
+// B_r of those rounds - more threads than bins only split each residue's
+// sum into more parts.
+uint32_t pair_threads(const sfft_plan_s* p, uint32_t r0, uint32_t r1) {
+    uint32_t maxB = 0;
+    for (uint32_t r = r0; r < r1; ++r) maxB = std::max(maxB, p->geom[r].B);
+    uint32_t t = p->d.hash_threads;
+    while (t > 256 && t > maxB) t >>= 1;
+    return t;
+}
+
 // Part 0 of a chunk [off, off + cnt): state reset + HashToBins of every
 // round; part 1: decode loop + re-estimation and output.
 sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt, const void* x,
@@ -656,6 +670,7 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
         HIP_TRY(launch_exact_init(D, s));
         a.round_lo = 0;
         a.nrounds = p->group_end[0];
+        a.threads = pair_threads(p, 0, p->group_end[0]);
         HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
         return SFFT_OK;
     }
@@ -666,6 +681,7 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
         if (g > 0) {
             a.round_lo = r0;
             a.nrounds = r1 - r0;
+            a.threads = pair_threads(p, r0, r1);
             HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
         }
         D.r_begin = r0;

@@ -124,6 +124,7 @@ struct DecodeArgs {
     double* fin;               // [sig][capz][2] re-estimated values
     double* gtmp;              // [sig][capz][4] per-entry terms when LDS cannot hold them
     uint32_t* ecount;          // [sig][capz] samples per entry
+    uint8_t* eflag;            // [sig][capz][rounds] sample kind: 0 none, 1 isolated, 2 crowded
     uint32_t* state;           // [sig][kStateWords]
     double theta, g_min;
     double out_scale;

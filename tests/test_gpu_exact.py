@@ -259,6 +259,30 @@ def test_c3_launch_shapes_match_oracle(torch_dev, threads, chunks):
     plan.close()
 
 
+@pytest.mark.parametrize("b_min", [1024, 4096])
+def test_large_k_finish_matches_oracle(torch_dev, b_min):
+    """k = 2048 gives 8192 zhat entries, more than the per-round
+    re-estimation blocks hold in LDS: the re-estimation runs as one
+    workgroup per signal over its rounds, with the same results."""
+    torch, dev = torch_dev
+    n, k, B = 1 << 20, 2048, 4096
+    w = default_w(n, B, 0.5, 1e-9)
+    say("large-k-finish", "n", n, "k", k, "B", B, "b_min", b_min)
+    plan = plan_for(n, k, B, w, 0, delta=1e-9, theta=0.25, loc_prec=1, max_batch=2, b_min=b_min, rounds=24)
+    xs, sups = [], []
+    for s in range(2):
+        x, sup, _ = siggen.planted_signal(n, k, 5 + s, np.complex64, magnitude="unit")
+        xs.append(x)
+        sups.append(sup)
+    seeds = [3, 4]
+    out = run_batch(torch, dev, plan, xs, seeds)
+    for s in range(2):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        assert int(out[s][2][0]) == ref.rounds_used
+        compare(out[s][0], out[s][1], ref)
+    plan.close()
+
+
 def test_c3_round_groups_skip_only_undecoded_rounds(torch_dev):
     """The batched exact path hashes round group 0 for every signal and each
     later group only for signals still decoding: a batch whose signals stop
