@@ -212,6 +212,9 @@ def main():
                     help="smallest bin count of the shrinking schedule (tuned on the oracle: 512/512 "
                          "recovered with 7%% fewer samples than B/16)")
     ap.add_argument("--rounds", type=int, default=24, help="most exact-mode rounds")
+    ap.add_argument("--delta", type=float, default=1e-9, help="window accuracy (with --tune off)")
+    ap.add_argument("--patience", type=int, default=3, help="empty rounds before a signal stops (with --tune off)")
+    ap.add_argument("--hash-threads", type=int, default=256, help="HashToBins workgroup size (with --tune off)")
     ap.add_argument("--loc-prec", choices=["f32", "f64"], default="f64",
                     help="arithmetic of the location pair's fold and FFT (FP64: the phase step 2 pi / n at "
                          "n = 2^22 is near FP32 resolution)")
@@ -262,7 +265,8 @@ def main():
     base_kw = dict(theta=0.02, loc_prec=loc_prec, rounds=args.rounds)
 
     # ---------------------------------------------------------- plan choice
-    B, tuned, tune_rec = args.B, dict(delta=1e-9, b_min=args.b_min), None
+    B, tuned, tune_rec = args.B, dict(delta=args.delta, b_min=args.b_min, patience=args.patience,
+                                      hash_threads=args.hash_threads), None
     if args.tune != "off" and not args.w:
         res = None
         if args.tune == "cache":
@@ -290,7 +294,7 @@ def main():
             B = res.B
             tuned = {f: v for f, v in res.fields.items() if f not in base_kw and f != "mode"}
             tune_rec = res.as_dict()
-    w = args.w or sfft.sfft_default_w(n, B, 0.5, tuned.get("delta", 1e-9))
+    w = args.w or sfft.sfft_default_w(n, B, tuned.get("alpha", 0.5), tuned.get("delta", 1e-9))
     cfg_key = "n=2^%d,k=%d,B=%d,w=%d,b_min=%d,rounds=%d,signals=%d" % (args.log2n, k, B, w,
                                                                        tuned.get("b_min", args.b_min),
                                                                        args.rounds, S)
@@ -481,6 +485,7 @@ def main():
                                "|c| in [0.1,10], per-signal seeds" % (S, args.log2n, k),
                    "signals": S, "n": n, "k": k, "B": B, "w": w, "rounds": desc.rounds,
                    "b_min": desc.b_min or max(2, B >> 4), "patience": desc.patience, "delta": desc.delta,
+                   "alpha": desc.alpha,
                    "hash_threads": desc.hash_threads, "chunks": chunks, "loc_prec": args.loc_prec,
                    "input": "complex64"},
         "autotune": tune_rec,

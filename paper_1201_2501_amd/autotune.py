@@ -78,8 +78,8 @@ def default_space(n, k, mode):
         Bs = pow2_range(lo, min(4096, n // 16)) or [min(4096, max(2, n // 16))]
         Bs = [b for b in Bs if b >= 512] or Bs[-2:]
         return {
-            "window": {"B": Bs, "delta": [1e-10, 1e-9, 1e-8]},
-            "schedule": {"b_min": [16, 32, 64], "patience": [3, 4]},
+            "window": {"B": Bs, "delta": [1e-10, 1e-9, 1e-8], "alpha": [0.5, 0.6]},
+            "schedule": {"b_min": [16, 32, 64], "patience": [3, 4, 5]},
             "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
         }
     lo = max(256, 4 * k)
@@ -97,6 +97,8 @@ def reference_candidate(space, mode, base):
     c = dict(base)
     c["B"] = max(space["window"]["B"])
     c["delta"] = min(space["window"]["delta"])
+    if "alpha" in space["window"]:
+        c["alpha"] = min(space["window"]["alpha"])
     if mode == sfft.SFFT_MODE_EXACT:
         c["b_min"] = max(space["schedule"]["b_min"])
         c["patience"] = max(space["schedule"]["patience"])

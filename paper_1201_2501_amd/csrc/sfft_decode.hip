@@ -265,6 +265,27 @@ __device__ __forceinline__ uint32_t lower_bound_lds(const uint64_t* a, uint32_t 
     return lo;
 }
 
+// Ascending sort of the m distinct keys key[0, m) in LDS.  Up to one key
+// per thread, each key's rank is counted against all others (broadcast LDS
+// reads, two barriers); beyond that a bitonic network over the padded
+// power of two.
+__device__ void sort_unique_keys(uint64_t* key, uint32_t m) {
+    const uint32_t tid = threadIdx.x;
+    if (m <= kDec) {
+        const uint64_t mine = tid < m ? key[tid] : 0;
+        uint32_t rank = 0;
+        if (tid < m)
+            for (uint32_t q = 0; q < m; ++q) rank += key[q] < mine ? 1u : 0u;
+        __syncthreads();
+        if (tid < m) key[rank] = mine;
+        __syncthreads();
+        return;
+    }
+    const uint32_t NM = pow2_ceil_u32(m);
+    for (uint32_t q = m + tid; q < NM; q += kDec) key[q] = kNone;
+    bitonic_sort_u64<kDec>(key, NM);
+}
+
 // zhat += candidates.  L.ckey[0, m) holds keys index << 13 | slot (unsorted,
 // unique indices) and cv[slot] the values.  Existing indices are updated in
 // place; new ones are merged by index into the other zhat buffer, which
@@ -276,9 +297,7 @@ __device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv,
     const uint32_t zc = L.sw[ST_ZCOUNT];
     const uint32_t zb = L.sw[ST_ZBUF];
     double* zv = zval_all + ((uint64_t)sig * 2 + zb) * capz * 2;
-    const uint32_t NM = pow2_ceil_u32(m > 0 ? m : 1);
-    for (uint32_t q = m + tid; q < NM; q += kDec) L.ckey[q] = kNone;
-    bitonic_sort_u64<kDec>(L.ckey, NM);
+    sort_unique_keys(L.ckey, m);
     const uint32_t per = (m + kDec - 1) / kDec;
     const uint32_t q0 = tid * per < m ? tid * per : m;
     const uint32_t q1 = q0 + per < m ? q0 + per : m;

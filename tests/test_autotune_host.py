@@ -22,7 +22,8 @@ def test_default_space_exact_respects_kernel_limits():
 def test_reference_candidate_is_the_conservative_corner():
     sp = autotune.default_space(1 << 22, 256, sfft.SFFT_MODE_EXACT)
     ref = autotune.reference_candidate(sp, sfft.SFFT_MODE_EXACT, {"theta": 0.02})
-    assert ref["B"] == 4096 and ref["delta"] == 1e-10 and ref["b_min"] == 64 and ref["patience"] == 4
+    assert ref["B"] == 4096 and ref["delta"] == 1e-10 and ref["b_min"] == 64 and ref["patience"] == 5
+    assert ref["alpha"] == 0.5
     assert ref["theta"] == 0.02 and ref["hash_threads"] == 256 and ref["chunks"] == 1
 
 

@@ -201,17 +201,21 @@ def test_zero_signal_and_truncation(torch_dev):
     compare(idx, v, ref)
 
 
-@pytest.mark.parametrize("seed,sched", [(0, "default"), (1, "default"), (2, "tuned"), (3, "tuned")])
+@pytest.mark.parametrize("seed,sched", [(0, "default"), (1, "default"), (2, "tuned"), (3, "tuned"), (4, "alpha0.6"),
+                                        (5, "alpha0.6")])
 def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     """n = 2^22, k = 256, log-uniform magnitudes, complex64, FP64 location
-    decoding; the default schedule (b_min = B/16, 16 rounds) and the bench's
-    tuned one (b_min = 32, 24 rounds) on a few signals."""
+    decoding; the default schedule (b_min = B/16, 16 rounds), b_min = 32 with
+    24 rounds, and a shorter window (alpha = 0.6, delta = 1e-8, b_min = 64,
+    patience 4) on a few signals."""
     torch, dev = torch_dev
     n, k, B = 1 << 22, 256, 1024
-    w = default_w(n, B, 0.5, 1e-9)
-    kw = {} if sched == "default" else dict(b_min=32, rounds=24)
+    alpha, delta = (0.6, 1e-8) if sched == "alpha0.6" else (0.5, 1e-9)
+    w = default_w(n, B, alpha, delta)
+    kw = {"default": {}, "tuned": dict(b_min=32, rounds=24),
+          "alpha0.6": dict(alpha=0.6, b_min=64, patience=4, rounds=24)}[sched]
     say("c3-shape", sched, "n", n, "k", k, "B", B, "w", w, "seed", seed)
-    plan = plan_for(n, k, B, w, 0, delta=1e-9, theta=0.02, loc_prec=1, max_batch=2, **kw)
+    plan = plan_for(n, k, B, w, 0, delta=delta, theta=0.02, loc_prec=1, max_batch=2, **kw)
     if sched == "tuned":
         assert plan.round_groups() == [9, 11, 13, 17, 24]
     xs, sups, seeds = [], [], []
