@@ -196,7 +196,8 @@ def oracle_params(desc, seed):
     from oracle.params import SfftParams
     return SfftParams(n=desc.n, k=desc.k, B=desc.B, w=desc.w, seed=seed, alpha=desc.alpha, delta=desc.delta,
                       theta=desc.theta, g_min=desc.g_min, rounds=desc.rounds, b_min=desc.b_min,
-                      patience=desc.patience, cap=desc.cap)
+                      patience=desc.patience, stop_count=desc.stop_count,
+                      stop_patience=desc.stop_patience, cap=desc.cap)
 
 
 def main():
@@ -215,6 +216,11 @@ def main():
     ap.add_argument("--delta", type=float, default=1e-9, help="window accuracy (with --tune off)")
     ap.add_argument("--patience", type=int, default=3, help="empty rounds before a signal stops (with --tune off)")
     ap.add_argument("--hash-threads", type=int, default=256, help="HashToBins workgroup size (with --tune off)")
+    ap.add_argument("--alpha", type=float, default=0.5, help="window transition fraction (with --tune off)")
+    ap.add_argument("--stop-count", type=int, default=0,
+                    help="stop after --stop-patience empty rounds once this many entries are found (with --tune "
+                         "off; 0 = off)")
+    ap.add_argument("--stop-patience", type=int, default=2)
     ap.add_argument("--loc-prec", choices=["f32", "f64"], default="f64",
                     help="arithmetic of the location pair's fold and FFT (FP64: the phase step 2 pi / n at "
                          "n = 2^22 is near FP32 resolution)")
@@ -238,7 +244,7 @@ def main():
                          "device, shape and library build, measured now when none is stored; run = measure now")
     ap.add_argument("--tune-budget", type=float, default=150.0, help="seconds of autotuner measurement at most")
     ap.add_argument("--tune-out", default="", help="also store the autotuner's choice in this JSON file")
-    ap.add_argument("--tune-confirm", type=int, default=4,
+    ap.add_argument("--tune-confirm", type=int, default=6,
                     help="fresh batches the fastest accepted candidates must also pass")
     ap.add_argument("--config-key", action="store_true",
                     help="print the key that names this configuration in the traffic record, then exit")
@@ -266,7 +272,8 @@ def main():
 
     # ---------------------------------------------------------- plan choice
     B, tuned, tune_rec = args.B, dict(delta=args.delta, b_min=args.b_min, patience=args.patience,
-                                      hash_threads=args.hash_threads), None
+                                      hash_threads=args.hash_threads, alpha=args.alpha,
+                                      stop_count=args.stop_count, stop_patience=args.stop_patience), None
     if args.tune != "off" and not args.w:
         res = None
         if args.tune == "cache":
@@ -485,7 +492,7 @@ def main():
                                "|c| in [0.1,10], per-signal seeds" % (S, args.log2n, k),
                    "signals": S, "n": n, "k": k, "B": B, "w": w, "rounds": desc.rounds,
                    "b_min": desc.b_min or max(2, B >> 4), "patience": desc.patience, "delta": desc.delta,
-                   "alpha": desc.alpha,
+                   "alpha": desc.alpha, "stop_count": desc.stop_count, "stop_patience": desc.stop_patience,
                    "hash_threads": desc.hash_threads, "chunks": chunks, "loc_prec": args.loc_prec,
                    "input": "complex64"},
         "autotune": tune_rec,

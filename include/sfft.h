@@ -114,6 +114,15 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *             decode overlaps the next chunk's HashToBins, 1..8 (0 = the
  *             SFFT_BATCH_CHUNKS environment variable, else 1).  Launch
  *             shape only: results do not depend on it
+ *   stop_count  exact mode: also stop after stop_patience consecutive
+ *             rounds whose bins are all below theta once at least this many
+ *             zhat entries exceed theta/2 in magnitude (0 = off; k for
+ *             exactly k-sparse input: with k such entries empty bins leave
+ *             nothing to find unless a wrong entry stands in for a
+ *             coefficient that stays invisible).  Ignored in general mode
+ *   stop_patience  empty rounds in a row that end a signal under stop_count
+ *             (>= 1; default 2: one empty round can hide a coefficient
+ *             placed one location off, whose residual pair cancels in a bin)
  *   reserved  must be 0
  */
 typedef struct {
@@ -142,6 +151,8 @@ typedef struct {
     uint32_t max_batch;
     uint32_t hash_threads;
     uint32_t chunks;
+    uint32_t stop_count;
+    uint32_t stop_patience;
     uint32_t reserved;
 } sfft_plan_desc_t;
 

@@ -5,7 +5,8 @@ w_r = w B_r / B window (params.round_bins):
   * draw sigma odd and b uniform (rng.py, counter (r, 0, 0));
   * u  = HashToBins(x, zhat, P_{sigma,0,b}),  u' = HashToBins(x, zhat, P_{sigma,1,b});
   * J  = { j : |u_j| > theta };  stop after `patience` consecutive rounds with
-    J empty (or after `rounds` rounds);
+    J empty, or after `stop_patience` once `stop_count` (> 0) entries of zhat
+    exceed theta/2 in magnitude (or after `rounds` rounds);
   * for j in J: the phase of u_j / u'_j equals 2 pi sigma i / n for an isolated
     coefficient (the exact-estimation lemma of Section 3), so
         p = round(phi(u_j / u'_j) n / (2 pi)) mod n,   i = sigma^{-1} p mod n;
@@ -120,7 +121,9 @@ def noiseless_sparse_fft(x, p: SfftParams) -> ExactResult:
         if not J:
             res.round_log.append((0, 0))
             empty_run += 1
-            if empty_run >= p.patience:
+            found = sum(1 for v in zhat.values() if abs(v) > 0.5 * p.theta)
+            if empty_run >= p.patience or (p.stop_count > 0 and empty_run >= p.stop_patience and
+                                           found >= p.stop_count):
                 rounds_used = r + 1
                 break
             continue

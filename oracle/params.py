@@ -20,6 +20,18 @@ patience  exact mode: stop after this many consecutive rounds with J empty.  One
           empty round is weak evidence: a remaining coefficient whose offset
           falls where G' is small is hidden in that round (the large-offset
           event of Section 3) with probability about alpha / 2.
+stop_count  exact mode: also stop after `stop_patience` consecutive rounds with
+          J empty once at least this many zhat entries exceed theta / 2 in
+          magnitude (0: off).  With stop_count = k on an exactly k-sparse spectrum (the
+          problem Algorithm 1 solves, with k known), k such entries and empty
+          bins leave nothing to find unless a wrong entry stands in for a
+          coefficient that stays invisible: one round is not enough, since a
+          coefficient placed one location off and its residual can share a
+          bin with equal window weight and cancel in the a = 0 hashing, and
+          two can miss a small mislocated coefficient whose offsets fall in
+          the transition band; below k entries the patience rule still
+          applies.
+stop_patience  empty rounds in a row that end a run under stop_count (>= 1).
 rounds    exact mode: maximum number of NoiselessSparseFFTInner rounds
           general mode: number of SparseFFT rounds
 t, s      LocateInner region count and vote tolerance (Algorithm 3)
@@ -46,6 +58,8 @@ class SfftParams:
     rounds: int = 8
     b_min: int = 0
     patience: int = 3
+    stop_count: int = 0
+    stop_patience: int = 2
     t: int = 16
     s: float = 0.125
     R_loc: int = 3

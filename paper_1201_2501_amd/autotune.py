@@ -79,7 +79,8 @@ def default_space(n, k, mode):
         Bs = [b for b in Bs if b >= 512] or Bs[-2:]
         return {
             "window": {"B": Bs, "delta": [1e-10, 1e-9, 1e-8], "alpha": [0.5, 0.6]},
-            "schedule": {"b_min": [16, 32, 64], "patience": [3, 4, 5]},
+            "schedule": {"b_min": [16, 32, 64], "patience": [3, 4, 5], "stop_count": [0, k],
+                         "stop_patience": [2, 3]},
             "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
         }
     lo = max(256, 4 * k)
@@ -89,6 +90,15 @@ def default_space(n, k, mode):
         "schedule": {"R_est": [5, 7, 9], "R_loc": [3, 4]},
         "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
     }
+
+
+def normalize(cand):
+    """Drop fields that do not change the plan (stop_patience without
+    stop_count), so equal plans compare equal."""
+    c = dict(cand)
+    if not c.get("stop_count"):
+        c.pop("stop_patience", None)
+    return c
 
 
 def reference_candidate(space, mode, base):
@@ -102,12 +112,14 @@ def reference_candidate(space, mode, base):
     if mode == sfft.SFFT_MODE_EXACT:
         c["b_min"] = max(space["schedule"]["b_min"])
         c["patience"] = max(space["schedule"]["patience"])
+        if "stop_count" in space["schedule"]:
+            c["stop_count"] = 0
     else:
         c["R_est"] = max(space["schedule"]["R_est"])
         c["R_loc"] = max(space["schedule"]["R_loc"])
     c["hash_threads"] = 256
     c["chunks"] = 1
-    return c
+    return normalize(c)
 
 
 @dataclass
@@ -310,7 +322,7 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
             for combo in combos:
                 if time.time() - t_start > budget_s:
                     return
-                cand = dict(current, **combo)
+                cand = normalize(dict(current, **combo))
                 if any(r.get("cand") == cand for r in runner.table):
                     continue
                 runner.evaluate(cand)

@@ -729,9 +729,25 @@ __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uin
     const uint32_t J = L.misc[0], m = L.misc[1];
     uint32_t* sw = L.sw;
     if (J == 0) {
+        // with stop_count, the stop_patience-th empty round in a row ends the
+        // signal once that many zhat entries exceed theta/2 (block-uniform:
+        // J and the state words are; the barrier below orders these reads
+        // before the update of the state words)
+        bool enough = false;
+        if (D.stop_count && sw[ST_EMPTY] + 1 >= D.stop_patience) {
+            const double half = 0.5 * D.theta;
+            uint32_t c = 0;
+            for (uint32_t e = tid; e < zc; e += kDec) {
+                const double2 v = zv2[e];
+                c += sqrt(v.x * v.x + v.y * v.y) > half ? 1u : 0u;
+            }
+            uint32_t pre;
+            enough = wave_block_scan(c, L.scan, &pre) >= D.stop_count;
+        }
+        __syncthreads();
         if (tid == 0) {
             sw[ST_EMPTY] += 1;
-            if (sw[ST_EMPTY] >= D.patience) sw[ST_DONE] = 1;
+            if (sw[ST_EMPTY] >= D.patience || enough) sw[ST_DONE] = 1;
             sw[ST_ROUNDS] = r + 1;
             sw[ST_LASTJ] = 0;
             sw[ST_ACCEPT] = 0;

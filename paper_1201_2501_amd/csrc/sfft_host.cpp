@@ -470,6 +470,8 @@ DecodeArgs base_decode(const sfft_plan_s* p, uint32_t count, const uint64_t* see
     D.r_begin = 0;
     D.r_end = p->R;
     D.patience = p->d.patience;
+    D.stop_count = p->d.mode == SFFT_MODE_EXACT ? p->d.stop_count : 0;
+    D.stop_patience = p->d.stop_patience;
     D.Bmax = p->Bmax;
     D.capz = p->capz;
     D.cap = p->cap;
@@ -786,6 +788,8 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->max_batch = 1;
     d->hash_threads = 256;
     d->chunks = 0;
+    d->stop_count = 0;
+    d->stop_patience = 2;
     d->reserved = 0;
     return SFFT_OK;
 }
@@ -814,6 +818,7 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (d->hash_threads != 0 && !h2b_threads_ok(d->hash_threads))
         return fail(SFFT_EINVAL, "hash_threads must be 256, 512 or 1024 (or 0)");
     if (d->chunks > kMaxChunks) return fail(SFFT_EINVAL, "chunks must be in [0, 8]");
+    if (d->stop_patience < 1) return fail(SFFT_EINVAL, "stop_patience must be >= 1");
     if (d->reserved != 0) return fail(SFFT_EINVAL, "reserved must be 0");
     const uint32_t cap = d->cap ? d->cap : d->k;
     if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");

@@ -108,6 +108,8 @@ struct DecodeArgs {
     uint32_t rounds;           // rounds with raw bins available (raw dimension)
     uint32_t r_begin, r_end;   // rounds decoded by this launch
     uint32_t patience;
+    uint32_t stop_count;       // stop after stop_patience empty rounds once this many |zhat| > theta/2 (0: off)
+    uint32_t stop_patience;
     uint32_t Bmax;
     uint32_t capz;             // capacity of each zhat buffer
     uint32_t cap;              // output capacity

@@ -43,7 +43,8 @@ class PlanDesc(ctypes.Structure):
                 ("s", c_double), ("rounds", c_uint32), ("b_min", c_uint32), ("patience", c_uint32),
                 ("t", c_uint32), ("R_loc", c_uint32), ("R_est", c_uint32), ("cap", c_uint32),
                 ("flags", c_uint32), ("max_batch", c_uint32), ("hash_threads", c_uint32),
-                ("chunks", c_uint32), ("reserved", c_uint32)]
+                ("chunks", c_uint32), ("stop_count", c_uint32),
+                ("stop_patience", c_uint32), ("reserved", c_uint32)]
 
 
 class ServerDesc(ctypes.Structure):

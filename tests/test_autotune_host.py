@@ -39,7 +39,7 @@ def test_every_candidate_field_is_a_plan_field_that_validates():
 
 
 @pytest.mark.parametrize("field,value", [("hash_threads", 128), ("hash_threads", 768), ("chunks", 9),
-                                         ("reserved", 1)])
+                                         ("stop_patience", 0), ("reserved", 1)])
 def test_launch_shape_fields_are_validated(field, value):
     lib = sfft.load()
     d = sfft.sfft_desc_init(1 << 20, 64, 512)

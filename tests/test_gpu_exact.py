@@ -38,7 +38,7 @@ def oracle_params(plan, seed=None):
     d = plan.desc
     return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=d.seed if seed is None else seed, alpha=d.alpha,
                       delta=d.delta, theta=d.theta, g_min=d.g_min, rounds=d.rounds, b_min=d.b_min,
-                      patience=d.patience, cap=d.cap)
+                      patience=d.patience, stop_count=d.stop_count, stop_patience=d.stop_patience, cap=d.cap)
 
 
 RAW_CASES = [
@@ -202,18 +202,20 @@ def test_zero_signal_and_truncation(torch_dev):
 
 
 @pytest.mark.parametrize("seed,sched", [(0, "default"), (1, "default"), (2, "tuned"), (3, "tuned"), (4, "alpha0.6"),
-                                        (5, "alpha0.6")])
+                                        (5, "alpha0.6"), (6, "stopk"), (7, "stopk")])
 def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     """n = 2^22, k = 256, log-uniform magnitudes, complex64, FP64 location
     decoding; the default schedule (b_min = B/16, 16 rounds), b_min = 32 with
-    24 rounds, and a shorter window (alpha = 0.6, delta = 1e-8, b_min = 64,
-    patience 4) on a few signals."""
+    24 rounds, a shorter window (alpha = 0.6, delta = 1e-8, b_min = 64,
+    patience 4), and the same with the stop at k found entries, on a few
+    signals."""
     torch, dev = torch_dev
     n, k, B = 1 << 22, 256, 1024
-    alpha, delta = (0.6, 1e-8) if sched == "alpha0.6" else (0.5, 1e-9)
+    alpha, delta = (0.6, 1e-8) if sched in ("alpha0.6", "stopk") else (0.5, 1e-9)
     w = default_w(n, B, alpha, delta)
     kw = {"default": {}, "tuned": dict(b_min=32, rounds=24),
-          "alpha0.6": dict(alpha=0.6, b_min=64, patience=4, rounds=24)}[sched]
+          "alpha0.6": dict(alpha=0.6, b_min=64, patience=4, rounds=24),
+          "stopk": dict(alpha=0.6, b_min=64, patience=5, rounds=24, stop_count=k, stop_patience=2 + seed % 2)}[sched]
     say("c3-shape", sched, "n", n, "k", k, "B", B, "w", w, "seed", seed)
     plan = plan_for(n, k, B, w, 0, delta=delta, theta=0.02, loc_prec=1, max_batch=2, **kw)
     if sched == "tuned":

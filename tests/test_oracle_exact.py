@@ -193,3 +193,24 @@ def test_median_exact_when_majority_exact():
     vals = [good] * 4 + [5 + 5j, -9 + 0j, 100j]
     assert complex_median(vals) == good
     assert complex_median([1 + 1j, 3 + 0j]) == (2 + 0.5j)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_stop_count_ends_at_the_first_empty_round_with_k_entries(seed):
+    """stop_count = k stops exactly k-sparse recovery at the second empty
+    round in a row once k entries exceed theta/2: the same support (the
+    planted one), no later round than the patience rule, and the last two
+    rounds are empty; a count that is never reached leaves the patience rule
+    alone."""
+    base = c1_params(seed, patience=4)
+    x, sup, val = siggen.planted_signal(base.n, base.k, 300 + seed, np.complex128)
+    ref = noiseless_sparse_fft(x, base)
+    fast = noiseless_sparse_fft(x, SfftParams(**{**base.__dict__, "stop_count": base.k}))
+    assert np.array_equal(ref.indices, sup) and np.array_equal(fast.indices, sup)
+    assert fast.rounds_used <= ref.rounds_used - (base.patience - 2)
+    assert fast.round_log[fast.rounds_used - 2:fast.rounds_used] == [(0, 0), (0, 0)]
+    # the round before those two found something (else the count, which only
+    # empty rounds leave unchanged, would have stopped the run a round earlier)
+    assert fast.rounds_used == 2 or fast.round_log[fast.rounds_used - 3][0] > 0
+    never = noiseless_sparse_fft(x, SfftParams(**{**base.__dict__, "stop_count": base.k + 1}))
+    assert never.rounds_used == ref.rounds_used and np.array_equal(never.indices, ref.indices)
