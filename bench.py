@@ -299,14 +299,20 @@ def main():
             log("autotune: %d candidates in %.1fs" % (len(res.table), time.time() - t))
         if res is not None:
             B = res.B
-            tuned = {f: v for f, v in res.fields.items() if f not in base_kw and f != "mode"}
+            tuned = {f: v for f, v in res.fields.items() if f != "mode"}
             tune_rec = res.as_dict()
     w = args.w or sfft.sfft_default_w(n, B, tuned.get("alpha", 0.5), tuned.get("delta", 1e-9))
-    cfg_key = "n=2^%d,k=%d,B=%d,w=%d,b_min=%d,rounds=%d,signals=%d" % (args.log2n, k, B, w,
-                                                                       tuned.get("b_min", args.b_min),
-                                                                       args.rounds, S)
+    plan_kw = dict(base_kw, **tuned, max_batch=S, flags=sfft.SFFT_FLAG_TIMING)
+    log("plan: B=%d w=%d %s" % (B, w, ", ".join("%s=%s" % kv for kv in sorted(tuned.items()))))
+    plan = Plan(n, k, B, w, 0, **plan_kw)
+    desc = plan.desc
+    # names the dominant launch for the counter record: its rounds (group 0)
+    # and workgroup size set the gathered samples and the dispatch
+    cfg_key = "n=2^%d,k=%d,B=%d,w=%d,b_min=%d,g0=%d,threads=%d,signals=%d" % (
+        args.log2n, k, B, w, desc.b_min, plan.round_groups()[0], desc.hash_threads, S)
     if args.config_key:
         print(cfg_key)
+        plan.close()
         return
 
     if args.copy_calibration:
@@ -326,10 +332,6 @@ def main():
     torch.cuda.synchronize()
     log("inputs ready: %d x 2^%d complex64 (%.1f GiB) in %.1fs" % (S, args.log2n, X.numel() * 8 / 2**30, time.time() - t))
 
-    plan_kw = dict(base_kw, **tuned, max_batch=S, flags=sfft.SFFT_FLAG_TIMING)
-    log("plan: B=%d w=%d %s" % (B, w, ", ".join("%s=%s" % kv for kv in sorted(tuned.items()))))
-    plan = Plan(n, k, B, w, 0, **plan_kw)
-    desc = plan.desc
     bufs = plan.batch_buffers(S, dev)
 
     # ---------------------------------------------------------------- batched
@@ -492,7 +494,8 @@ def main():
                                "|c| in [0.1,10], per-signal seeds" % (S, args.log2n, k),
                    "signals": S, "n": n, "k": k, "B": B, "w": w, "rounds": desc.rounds,
                    "b_min": desc.b_min or max(2, B >> 4), "patience": desc.patience, "delta": desc.delta,
-                   "alpha": desc.alpha, "stop_count": desc.stop_count, "stop_patience": desc.stop_patience,
+                   "alpha": desc.alpha, "theta": desc.theta, "g_min": desc.g_min,
+                   "stop_count": desc.stop_count, "stop_patience": desc.stop_patience,
                    "hash_threads": desc.hash_threads, "chunks": chunks, "loc_prec": args.loc_prec,
                    "input": "complex64"},
         "autotune": tune_rec,

@@ -15,10 +15,11 @@ calibration batch:
     found is within `recall_slack` of the reference candidate's.
 
 Among accepted candidates the fastest (median time of `reps` replayed batch
-steps, HIP events) wins.  The search is coordinate-wise with a small beam:
-the window and bin count first, then the round schedule, then the launch
-shape (HashToBins workgroup size, batch chunks), each stage varying its
-fields around each of the `beam` fastest accepted candidates so far.
+steps, HIP events) wins.  The search is coordinate-wise with a small beam,
+stage by stage in the order of the space (by default: the window and bin
+count, the round schedule, the decode thresholds, the count stop, the launch
+shape), each stage varying its fields around each of the `beam` fastest
+accepted candidates so far.
 
 One calibration batch cannot show a per-signal failure rate of 1e-3, and a
 shorter window or an earlier stop can have one.  With `confirm` (a function
@@ -70,17 +71,21 @@ def pow2_range(lo, hi):
     return out
 
 
-def default_space(n, k, mode):
-    """Candidate values per stage.  B stays within the kernels' limit (4096)
-    and at most n/16; exact mode starts at 2k bins, general mode at 4k."""
+def default_space(n, k, mode, theta=0.25):
+    """Candidate values per stage, searched in this order.  B stays within
+    the kernels' limit (4096) and at most n/16; exact mode starts at 2k
+    bins, general mode at 4k.  theta: the caller's bin threshold (exact
+    mode also tries half of it: a coefficient is hidden in a round only when
+    G' |c| < theta, so a lower threshold needs fewer empty rounds)."""
     if mode == sfft.SFFT_MODE_EXACT:
         lo = max(64, 2 * k)
         Bs = pow2_range(lo, min(4096, n // 16)) or [min(4096, max(2, n // 16))]
         Bs = [b for b in Bs if b >= 512] or Bs[-2:]
         return {
             "window": {"B": Bs, "delta": [1e-10, 1e-9, 1e-8], "alpha": [0.5, 0.6]},
-            "schedule": {"b_min": [16, 32, 64], "patience": [3, 4, 5], "stop_count": [0, k],
-                         "stop_patience": [2, 3]},
+            "schedule": {"b_min": [16, 32, 64], "patience": [3, 4, 5]},
+            "decode": {"theta": [theta, theta / 2], "g_min": [0.25, 0.4], "patience": [3, 4, 5]},
+            "stop": {"stop_count": [0, k], "stop_patience": [2, 3]},
             "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
         }
     lo = max(256, 4 * k)
@@ -112,8 +117,7 @@ def reference_candidate(space, mode, base):
     if mode == sfft.SFFT_MODE_EXACT:
         c["b_min"] = max(space["schedule"]["b_min"])
         c["patience"] = max(space["schedule"]["patience"])
-        if "stop_count" in space["schedule"]:
-            c["stop_count"] = 0
+        c["stop_count"] = 0
     else:
         c["R_est"] = max(space["schedule"]["R_est"])
         c["R_loc"] = max(space["schedule"]["R_loc"])
@@ -284,7 +288,7 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
     n, count = int(x.shape[1]), int(x.shape[0])
     base = dict(base or {})
     base.setdefault("mode", mode)
-    space = space or default_space(n, k, mode)
+    space = space or default_space(n, k, mode, base.get("theta", 0.25))
     in_dtype = sfft.SFFT_C128 if x.dtype == torch.complex128 else sfft.SFFT_C64
     tag = device_tag(x.device)
     key = cache_key(n, k, mode, count, in_dtype, tag)
@@ -327,7 +331,7 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
                     continue
                 runner.evaluate(cand)
 
-    for name in ("window", "schedule", "launch"):
+    for name in space:
         stage(name, [dict(r["cand"]) for r in ranked_accepted()[:beam]])
     best = ranked_accepted()[0]
 
