@@ -123,7 +123,12 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *   stop_patience  empty rounds in a row that end a signal under stop_count
  *             (>= 1; default 2: one empty round can hide a coefficient
  *             placed one location off, whose residual pair cancels in a bin)
- *   reserved  must be 0
+ *   group0    exact mode, batched: rounds hashed for every signal in the
+ *             first HashToBins launch (0 = up to the first round at b_min
+ *             bins plus patience + 1, the earliest the patience rule can stop
+ *             a signal; capped at rounds).  Later launches hash 2, 2, 4, 8,
+ *             ... rounds for the signals still decoding.  Launch shape only:
+ *             results do not depend on it
  */
 typedef struct {
     uint64_t n;
@@ -153,7 +158,7 @@ typedef struct {
     uint32_t chunks;
     uint32_t stop_count;
     uint32_t stop_patience;
-    uint32_t reserved;
+    uint32_t group0;
 } sfft_plan_desc_t;
 
 typedef struct sfft_plan_s* sfft_plan_t;

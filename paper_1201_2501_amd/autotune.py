@@ -17,15 +17,18 @@ calibration batch:
 Among accepted candidates the fastest (median time of `reps` replayed batch
 steps, HIP events) wins.  The search is coordinate-wise with a small beam,
 stage by stage in the order of the space (by default: the window and bin
-count, the round schedule, the decode thresholds, the count stop, the launch
-shape), each stage varying its fields around each of the `beam` fastest
-accepted candidates so far.
+count, the round schedule, the decode thresholds, the count stop), each
+stage varying its fields around each of the `beam` fastest accepted
+candidates so far; the launch-shape stages (HashToBins workgroup size, batch
+chunks, first round group), which cannot change results, run last, around
+the configuration that survives confirmation.
 
 One calibration batch cannot show a per-signal failure rate of 1e-3, and a
 shorter window or an earlier stop can have one.  With `confirm` (a function
 returning fresh batches), the fastest accepted candidates are run again on
 `confirm_batches` new batches, one batch in memory at a time, beside the
-reference candidate; a candidate survives a batch when it recovers every
+reference candidate (one run per result-affecting configuration, up to
+`confirm_top` of them); a candidate survives a batch when it recovers every
 signal the reference recovers (exact mode) or stays within recall_slack of
 the reference's recall (general mode).  The fastest survivor wins.
 
@@ -87,6 +90,7 @@ def default_space(n, k, mode, theta=0.25):
             "decode": {"theta": [theta, theta / 2], "g_min": [0.25, 0.4], "patience": [3, 4, 5]},
             "stop": {"stop_count": [0, k], "stop_patience": [2, 3]},
             "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
+            "groups": {"group0_offset": [0, -1, 1, 2]},
         }
     lo = max(256, 4 * k)
     Bs = pow2_range(lo, min(4096, n // 16)) or [min(4096, max(2, n // 16))]
@@ -97,12 +101,44 @@ def default_space(n, k, mode, theta=0.25):
     }
 
 
+def first_floor_round(B, b_min):
+    """Exact mode: the first round whose bin count B >> r has reached b_min."""
+    r = 0
+    while (B >> r) > max(b_min, 1) and (B >> (r + 1)) >= max(b_min, 1):
+        r += 1
+    return r
+
+
+# stages and fields that choose only the launch shape: results do not depend on them
+LAUNCH_STAGES = ("launch", "groups")
+LAUNCH_FIELDS = ("hash_threads", "chunks", "group0", "group0_offset")
+
+
+def signature(cand):
+    """The fields of a candidate that can change its results."""
+    return tuple(sorted((f, v) for f, v in cand.items() if f not in LAUNCH_FIELDS))
+
+
+def launch_changes(cand):
+    """Number of launch fields set away from the library defaults."""
+    return (int(cand.get("hash_threads", 256) != 256) + int(cand.get("chunks", 1) not in (0, 1)) +
+            int(bool(cand.get("group0"))))
+
+
 def normalize(cand):
     """Drop fields that do not change the plan (stop_patience without
-    stop_count), so equal plans compare equal."""
+    stop_count) and turn group0_offset (rounds relative to the library's
+    default first round group: first b_min round + patience + 1) into
+    group0, so equal plans compare equal."""
     c = dict(cand)
     if not c.get("stop_count"):
         c.pop("stop_patience", None)
+    off = c.pop("group0_offset", None)
+    if off is not None:
+        c.pop("group0", None)
+        if off:
+            auto = first_floor_round(c["B"], c.get("b_min") or max(2, c["B"] >> 4)) + c.get("patience", 3) + 1
+            c["group0"] = max(1, min(auto + off, c.get("rounds") or 16))
     return c
 
 
@@ -273,7 +309,7 @@ class _Runner:
 
 def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, space=None, reps=3,
          budget_s=120.0, cache=None, recall_slack=0.005, log=None, force=False, confirm=None,
-         confirm_batches=4, confirm_top=16, beam=3):
+         confirm_batches=4, confirm_top=16, beam=3, launch_margin=0.01):
     """Tune the plan of a batch x ([count, n] complex device tensor) with
     sparsity k.  base: plan fields kept fixed (e.g. theta, rounds, loc_prec,
     flags); space: {"window": {...}, "schedule": {...}, "launch": {...}}
@@ -331,17 +367,27 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
                     continue
                 runner.evaluate(cand)
 
-    for name in space:
+    result_stages = [name for name in space if name not in LAUNCH_STAGES]
+    launch_stages = [name for name in space if name in LAUNCH_STAGES]
+    for name in result_stages:
         stage(name, [dict(r["cand"]) for r in ranked_accepted()[:beam]])
-    best = ranked_accepted()[0]
 
+    # confirmation, per result-affecting configuration (launch variants of
+    # one configuration give the same results, so one run stands for all)
+    survivors = None
     confirmed = 0
     if confirm is not None and confirm_batches > 0:
-        ranked = [r for r in ranked_accepted() if r is not ref_rec][:confirm_top]
-        for rec in ranked:
-            rec["confirmed"] = 0
+        pool, seen = [], set()
+        for r in ranked_accepted():
+            sig = signature(r["cand"])
+            if r is ref_rec or sig in seen or sig == signature(ref_rec["cand"]):
+                continue
+            seen.add(sig)
+            pool.append(r)
+            if len(pool) == confirm_top:
+                break
         for i in range(confirm_batches):
-            if not ranked:
+            if not pool:
                 break
             xb, sb, tb = confirm(i)
             tb = None if tb is None else [np.sort(np.asarray(t, dtype=np.int64)) for t in tb]
@@ -349,18 +395,34 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
             if ref_out is None:
                 break
             keep = []
-            for rec in ranked:
+            for rec in pool:
                 out = runner.run(rec["cand"], xb, sb, reps=0)
                 if out is not None and runner.survives(out[1], ref_out[1], tb, recall_slack):
-                    rec["confirmed"] += 1
                     keep.append(rec)
                 elif log:
                     log("autotune: confirmation batch %d drops %s" % (
                         i, ", ".join("%s=%s" % kv for kv in sorted(rec["cand"].items()))))
-            ranked = keep
+            pool = keep
             del xb, sb
             confirmed = i + 1
-        best = ranked[0] if ranked else ref_rec
+        survivors = {signature(r["cand"]) for r in pool} | {signature(ref_rec["cand"])}
+
+    def eligible():
+        return [r for r in ranked_accepted() if survivors is None or signature(r["cand"]) in survivors]
+
+    # launch shape around the fastest surviving configuration; a shape away
+    # from the library defaults must be faster by more than launch_margin
+    winner = eligible()[0]
+    wsig = signature(winner["cand"])
+
+    def variants():
+        return [r for r in eligible() if signature(r["cand"]) == wsig]
+
+    for name in launch_stages:
+        stage(name, [dict(r["cand"]) for r in variants()[:beam]])
+    fastest = variants()[0]["ms"]
+    best = min((r for r in variants() if r["ms"] <= fastest * (1.0 + launch_margin)),
+               key=lambda r: (launch_changes(r["cand"]), r["ms"]))
 
     cand = dict(best["cand"])
     B = int(cand.pop("B"))

@@ -333,8 +333,9 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     }
     // Round groups of the batched exact path: a signal stops at the earliest
     // `patience` rounds after the first round at the smallest bin count, so
-    // group 0 runs to there; later groups take 2, 2, 4, 8, ... rounds (few
-    // signals need the long tail, and every group costs two launches).
+    // group 0 runs to there unless the plan sets `group0`; later groups take
+    // 2, 2, 4, 8, ... rounds (few signals need the long tail, and every
+    // group costs two launches).
     if (!general_mode(p)) {
         uint32_t first_floor = p->R;
         for (uint32_t r = 0; r < p->R; ++r)
@@ -342,7 +343,7 @@ sfft_status_t build_plan(sfft_plan_s* p) {
                 first_floor = r;
                 break;
             }
-        uint32_t e = std::min<uint32_t>(p->R, first_floor + d.patience + 1);
+        uint32_t e = std::min<uint32_t>(p->R, d.group0 ? d.group0 : first_floor + d.patience + 1);
         p->group_end.push_back(e);
         for (uint32_t g = 1; e < p->R; ++g) {
             e = std::min<uint32_t>(p->R, e + (g <= 2 ? 2u : 1u << (g - 1)));
@@ -790,7 +791,7 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->chunks = 0;
     d->stop_count = 0;
     d->stop_patience = 2;
-    d->reserved = 0;
+    d->group0 = 0;
     return SFFT_OK;
 }
 
@@ -819,7 +820,7 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
         return fail(SFFT_EINVAL, "hash_threads must be 256, 512 or 1024 (or 0)");
     if (d->chunks > kMaxChunks) return fail(SFFT_EINVAL, "chunks must be in [0, 8]");
     if (d->stop_patience < 1) return fail(SFFT_EINVAL, "stop_patience must be >= 1");
-    if (d->reserved != 0) return fail(SFFT_EINVAL, "reserved must be 0");
+    if (d->group0 > kMaxRounds) return fail(SFFT_EINVAL, "group0 must be in [0, 32]");
     const uint32_t cap = d->cap ? d->cap : d->k;
     if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");
     if (d->mode == SFFT_MODE_GENERAL) {

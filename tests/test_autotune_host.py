@@ -30,16 +30,27 @@ def test_reference_candidate_is_the_conservative_corner():
 def test_every_candidate_field_is_a_plan_field_that_validates():
     lib = sfft.load()
     sp = autotune.default_space(1 << 22, 256, sfft.SFFT_MODE_EXACT)
+    base = {"B": 1024, "b_min": 64, "patience": 4, "rounds": 24}
     for stage in sp.values():
         for f, values in stage.items():
             for v in values:
+                cand = autotune.normalize(dict(base, **{f: v}))
                 d = sfft.sfft_desc_init(1 << 22, 256, 1024)
-                setattr(d, "B" if f == "B" else f, v)
+                for name, val in cand.items():
+                    setattr(d, name, val)
                 assert lib.sfft_validate_params(ctypes.byref(d)) == sfft.SFFT_OK, (f, v)
 
 
+def test_group0_offset_is_relative_to_the_library_default():
+    # B = 1024 reaches b_min = 64 at round 4; patience 4 -> default group 0 of 9 rounds
+    assert autotune.first_floor_round(1024, 64) == 4 and autotune.first_floor_round(1024, 2048) == 0
+    c = autotune.normalize({"B": 1024, "b_min": 64, "patience": 4, "rounds": 24, "group0_offset": 2})
+    assert c["group0"] == 11 and "group0_offset" not in c
+    assert "group0" not in autotune.normalize({"B": 1024, "b_min": 64, "group0_offset": 0})
+
+
 @pytest.mark.parametrize("field,value", [("hash_threads", 128), ("hash_threads", 768), ("chunks", 9),
-                                         ("stop_patience", 0), ("reserved", 1)])
+                                         ("stop_patience", 0), ("group0", 33)])
 def test_launch_shape_fields_are_validated(field, value):
     lib = sfft.load()
     d = sfft.sfft_desc_init(1 << 20, 64, 512)

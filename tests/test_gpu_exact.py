@@ -239,20 +239,22 @@ def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     plan.close()
 
 
-@pytest.mark.parametrize("threads,chunks", [(512, 1), (1024, 1), (256, 2), (1024, 2)])
-def test_c3_launch_shapes_match_oracle(torch_dev, threads, chunks):
+@pytest.mark.parametrize("threads,chunks,group0", [(512, 1, 0), (1024, 1, 0), (256, 2, 0), (1024, 2, 0), (256, 1, 6),
+                                                  (512, 1, 12)])
+def test_c3_launch_shapes_match_oracle(torch_dev, threads, chunks, group0):
     """The launch shape the autotuner picks from (HashToBins workgroup size,
-    batch chunks) leaves supports and rounds unchanged and values within the
-    FP64 bar: with B_r < threads a bin's partial sums are only added in
-    another order."""
+    batch chunks, size of the first round group) leaves supports and rounds
+    unchanged and values within the FP64 bar: with B_r < threads a bin's
+    partial sums are only added in another order."""
     torch, dev = torch_dev
     n, k, B = 1 << 22, 256, 1024
     w = default_w(n, B, 0.5, 1e-9)
     count = 4
-    say("c3-launch-shape", "threads", threads, "chunks", chunks, "count", count)
+    say("c3-launch-shape", "threads", threads, "chunks", chunks, "group0", group0, "count", count)
     plan = plan_for(n, k, B, w, 0, delta=1e-9, theta=0.02, loc_prec=1, max_batch=count, b_min=32, rounds=24,
-                    hash_threads=threads, chunks=chunks, flags=2)     # SFFT_FLAG_TIMING: chunk count
+                    hash_threads=threads, chunks=chunks, group0=group0, flags=2)     # SFFT_FLAG_TIMING: chunk count
     assert plan.desc.hash_threads == threads and plan.desc.chunks == chunks
+    assert plan.round_groups()[0] == (group0 or 9)
     xs, sups, seeds = [], [], []
     for s in range(count):
         x, sup, _ = siggen.planted_signal(n, k, 4000 + s, np.complex64, magnitude="loguniform")
