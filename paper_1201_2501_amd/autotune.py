@@ -85,7 +85,7 @@ def default_space(n, k, mode, theta=0.25):
         Bs = pow2_range(lo, min(4096, n // 16)) or [min(4096, max(2, n // 16))]
         Bs = [b for b in Bs if b >= 512] or Bs[-2:]
         return {
-            "window": {"B": Bs, "delta": [1e-10, 1e-9, 1e-8], "alpha": [0.5, 0.6]},
+            "window": {"B": Bs, "delta": [1e-10, 1e-9, 1e-8, 1e-7], "alpha": [0.5, 0.6, 0.7]},
             "schedule": {"b_min": [16, 32, 64], "patience": [3, 4, 5]},
             "decode": {"theta": [theta, theta / 2], "g_min": [0.25, 0.4], "patience": [3, 4, 5]},
             "stop": {"stop_count": [0, k], "stop_patience": [2, 3]},

@@ -203,7 +203,7 @@ def test_zero_signal_and_truncation(torch_dev):
 
 @pytest.mark.parametrize("seed,sched", [(0, "default"), (1, "default"), (2, "tuned"), (3, "tuned"), (4, "alpha0.6"),
                                         (5, "alpha0.6"), (6, "stopk"), (7, "stopk"), (8, "lowtheta"),
-                                        (9, "lowtheta")])
+                                        (9, "lowtheta"), (10, "alpha0.7"), (11, "alpha0.7")])
 def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     """n = 2^22, k = 256, log-uniform magnitudes, complex64, FP64 location
     decoding; the default schedule (b_min = B/16, 16 rounds), b_min = 32 with
@@ -213,12 +213,15 @@ def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     signals."""
     torch, dev = torch_dev
     n, k, B = 1 << 22, 256, 1024
-    alpha, delta = (0.6, 1e-8) if sched in ("alpha0.6", "stopk", "lowtheta") else (0.5, 1e-9)
+    alpha, delta = {"alpha0.6": (0.6, 1e-8), "stopk": (0.6, 1e-8), "lowtheta": (0.6, 1e-8),
+                    "alpha0.7": (0.7, 1e-7)}.get(sched, (0.5, 1e-9))
     w = default_w(n, B, alpha, delta)
     kw = {"default": {}, "tuned": dict(b_min=32, rounds=24),
           "alpha0.6": dict(alpha=0.6, b_min=64, patience=4, rounds=24),
           "stopk": dict(alpha=0.6, b_min=64, patience=5, rounds=24, stop_count=k, stop_patience=2 + seed % 2),
-          "lowtheta": dict(alpha=0.6, b_min=64, patience=4, rounds=24, theta=0.01, g_min=0.25)}[sched]
+          "lowtheta": dict(alpha=0.6, b_min=64, patience=4, rounds=24, theta=0.01, g_min=0.25),
+          "alpha0.7": dict(alpha=0.7, b_min=64, patience=4, rounds=24, theta=0.01, g_min=0.25, stop_count=k,
+                           stop_patience=3)}[sched]
     theta = kw.pop("theta", 0.02)
     say("c3-shape", sched, "n", n, "k", k, "B", B, "w", w, "seed", seed)
     plan = plan_for(n, k, B, w, 0, delta=delta, theta=theta, loc_prec=1, max_batch=2, **kw)
