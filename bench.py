@@ -242,7 +242,7 @@ def main():
     ap.add_argument("--tune", choices=["off", "cache", "run"], default="cache",
                     help="plan parameters: off = the flags above; cache = the autotuner's stored choice for this "
                          "device, shape and library build, measured now when none is stored; run = measure now")
-    ap.add_argument("--tune-budget", type=float, default=150.0, help="seconds of autotuner measurement at most")
+    ap.add_argument("--tune-budget", type=float, default=240.0, help="seconds of autotuner measurement at most")
     ap.add_argument("--tune-out", default="", help="also store the autotuner's choice in this JSON file")
     ap.add_argument("--tune-confirm", type=int, default=6,
                     help="fresh batches the fastest accepted candidates must also pass")
@@ -285,16 +285,22 @@ def main():
             seeds_c = torch.arange(S, dtype=torch.int64, device=dev) * 104729 + 777
             torch.cuda.synchronize()
             log("autotune: calibration batch of %d signals (seeds 2000003..) ready in %.1fs" % (S, time.time() - t))
+            confirm_batches = {}
+
             def confirm(i):
-                # fresh batches of the same workload, one at a time
-                gs = [3_000_003 + i * S + s for s in range(S)]
-                xb, sb, _ = siggen.torch_planted_batch(n, k, gs, dev, magnitude="loguniform")
-                return xb, torch.arange(S, dtype=torch.int64, device=dev) * 65537 + 99991 * (i + 1), sb
+                # fresh batches of the same workload, kept in HBM while tuning
+                if i not in confirm_batches:
+                    gs = [3_000_003 + i * S + s for s in range(S)]
+                    xb, sb, _ = siggen.torch_planted_batch(n, k, gs, dev, magnitude="loguniform")
+                    confirm_batches[i] = (xb, torch.arange(S, dtype=torch.int64, device=dev) * 65537 +
+                                          99991 * (i + 1), sb)
+                return confirm_batches[i]
 
             res = autotune.tune(Xc, k, sfft.SFFT_MODE_EXACT, seeds=seeds_c, truth=sup_c, base=base_kw,
                                 budget_s=args.tune_budget, cache=args.tune_out or None, log=log, force=True,
                                 confirm=confirm, confirm_batches=args.tune_confirm)
             del Xc
+            confirm_batches.clear()
             torch.cuda.empty_cache()
             log("autotune: %d candidates in %.1fs" % (len(res.table), time.time() - t))
         if res is not None:

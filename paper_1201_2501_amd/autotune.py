@@ -25,12 +25,15 @@ the configuration that survives confirmation.
 
 One calibration batch cannot show a per-signal failure rate of 1e-3, and a
 shorter window or an earlier stop can have one.  With `confirm` (a function
-returning fresh batches), the fastest accepted candidates are run again on
-`confirm_batches` new batches, one batch in memory at a time, beside the
-reference candidate (one run per result-affecting configuration, up to
-`confirm_top` of them); a candidate survives a batch when it recovers every
-signal the reference recovers (exact mode) or stays within recall_slack of
-the reference's recall (general mode).  The fastest survivor wins.
+returning fresh batches; it is called again for the same index, so it should
+keep them), after every result-affecting stage the `confirm_top` fastest
+accepted configurations not yet confirmed run on `confirm_batches` new
+batches beside the reference candidate (one plan per configuration; launch
+variants of a configuration give the same results).  A configuration
+survives when it recovers every signal the reference recovers (exact mode)
+or stays within recall_slack of the reference's recall (general mode);
+rejected configurations no longer count as accepted, so later stages start
+from confirmed ones.  The fastest confirmed configuration wins.
 
 Results are cached in a JSON file keyed by device, shape, batch size and the
 library's kernel sources, so a shape is tuned once per device and build.
@@ -273,6 +276,28 @@ class _Runner:
             plan.close()
         return (statistics.median(times) if times else float("nan")), sups
 
+    def run_batches(self, cand, batches):
+        """Supports of one candidate on each (x, seeds) of `batches`, from one
+        plan; None when its plan is not valid."""
+        torch = self.torch
+        fields = {f: v for f, v in cand.items() if f not in ("B", "in_dtype", "max_batch")}
+        count = max(int(x.shape[0]) for x, _ in batches)
+        try:
+            plan = sfft.Plan(self.n, self.k, cand["B"], 0, 0, in_dtype=self.in_dtype, max_batch=count, **fields)
+        except sfft.SfftError:
+            return None
+        out = []
+        try:
+            for x, seeds in batches:
+                bufs = plan.execute_batch(x, seeds)
+                torch.cuda.synchronize()
+                counts = bufs["counts"].cpu().numpy()
+                idx = bufs["idx"].cpu().numpy()
+                out.append([idx[s, :counts[s]].copy() for s in range(int(x.shape[0]))])
+        finally:
+            plan.close()
+        return out
+
     def quality(self, sups, target=None):
         """Exact mode: fraction of signals whose support equals the target;
         general mode: mean fraction of target coefficients found."""
@@ -316,7 +341,7 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
     lists of candidate values (default_space when None); truth: per-signal
     planted supports, else the reference candidate's supports are the
     target; confirm: i -> (x_i, seeds_i, truth_i or None), fresh batches of
-    the same shape for the confirmation phase.  Returns a TuneResult; with
+    the same shape for the confirmations (called again for the same i).  Returns a TuneResult; with
     `cache`, a stored result for the same key is returned without measuring
     (unless force)."""
     import torch
@@ -344,10 +369,10 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
     if truth is None:
         ref_rec["quality"] = 1.0
     floor = ref_rec["quality"] - (recall_slack if mode == sfft.SFFT_MODE_GENERAL else 0.0)
-    best = ref_rec
+    rejected = set()
 
     def accepted(rec):
-        return rec["quality"] >= floor - 1e-12
+        return rec["quality"] >= floor - 1e-12 and signature(rec["cand"]) not in rejected
 
     def ranked_accepted():
         return sorted((r for r in runner.table if "ms" in r and accepted(r)), key=lambda r: r["ms"])
@@ -369,43 +394,57 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
 
     result_stages = [name for name in space if name not in LAUNCH_STAGES]
     launch_stages = [name for name in space if name in LAUNCH_STAGES]
-    for name in result_stages:
-        stage(name, [dict(r["cand"]) for r in ranked_accepted()[:beam]])
-
-    # confirmation, per result-affecting configuration (launch variants of
-    # one configuration give the same results, so one run stands for all)
-    survivors = None
+    passed = {signature(ref_rec["cand"])}
+    ref_on_batch = {}
     confirmed = 0
-    if confirm is not None and confirm_batches > 0:
-        pool, seen = [], set()
+
+    def confirm_top_new():
+        """Confirm the fastest accepted configurations not yet confirmed; a
+        configuration that misses a signal the reference recovers on any
+        confirmation batch is rejected (its candidates stop counting as
+        accepted)."""
+        nonlocal confirmed
+        todo, seen = [], set()
         for r in ranked_accepted():
             sig = signature(r["cand"])
-            if r is ref_rec or sig in seen or sig == signature(ref_rec["cand"]):
+            if sig in passed or sig in seen:
                 continue
             seen.add(sig)
-            pool.append(r)
-            if len(pool) == confirm_top:
+            todo.append(r)
+            if len(todo) == confirm_top:
                 break
+        if not todo:
+            return
+        batches, truths = [], []
         for i in range(confirm_batches):
-            if not pool:
-                break
             xb, sb, tb = confirm(i)
-            tb = None if tb is None else [np.sort(np.asarray(t, dtype=np.int64)) for t in tb]
-            ref_out = runner.run(ref_rec["cand"], xb, sb, reps=0)
-            if ref_out is None:
-                break
-            keep = []
-            for rec in pool:
-                out = runner.run(rec["cand"], xb, sb, reps=0)
-                if out is not None and runner.survives(out[1], ref_out[1], tb, recall_slack):
-                    keep.append(rec)
-                elif log:
-                    log("autotune: confirmation batch %d drops %s" % (
-                        i, ", ".join("%s=%s" % kv for kv in sorted(rec["cand"].items()))))
-            pool = keep
-            del xb, sb
-            confirmed = i + 1
-        survivors = {signature(r["cand"]) for r in pool} | {signature(ref_rec["cand"])}
+            batches.append((xb, sb))
+            truths.append(None if tb is None else [np.sort(np.asarray(t, dtype=np.int64)) for t in tb])
+        for i, b in enumerate(batches):
+            if i not in ref_on_batch:
+                got = runner.run_batches(ref_rec["cand"], [b])
+                ref_on_batch[i] = got[0] if got else None
+        for rec in todo:
+            outs = runner.run_batches(rec["cand"], batches)
+            ok = outs is not None and all(
+                ref_on_batch[i] is not None and runner.survives(o, ref_on_batch[i], truths[i], recall_slack)
+                for i, o in enumerate(outs))
+            sig = signature(rec["cand"])
+            if ok:
+                passed.add(sig)
+            else:
+                rejected.add(sig)
+                if log:
+                    log("autotune: confirmation rejects %s" % ", ".join(
+                        "%s=%s" % kv for kv in sorted(rec["cand"].items())))
+        confirmed = confirm_batches
+
+    use_confirm = confirm is not None and confirm_batches > 0
+    for name in result_stages:
+        stage(name, [dict(r["cand"]) for r in ranked_accepted()[:beam]])
+        if use_confirm:
+            confirm_top_new()
+    survivors = passed if use_confirm else None
 
     def eligible():
         return [r for r in ranked_accepted() if survivors is None or signature(r["cand"]) in survivors]

@@ -30,10 +30,14 @@ def test_autotune_small_exact_batch(tmp_path):
     base = dict(theta=0.02, rounds=24, loc_prec=sfft.SFFT_F64)
     cache = str(tmp_path / "tuned.json")
 
+    kept = {}
+
     def confirm(i):
-        xb, sb, _ = siggen.torch_planted_batch(n, k, [8000 + 100 * i + s for s in range(count)], dev,
-                                               magnitude="loguniform")
-        return xb, torch.arange(count, dtype=torch.int64, device=dev) * 29 + 3 + i, sb
+        if i not in kept:
+            xb, sb, _ = siggen.torch_planted_batch(n, k, [8000 + 100 * i + s for s in range(count)], dev,
+                                                   magnitude="loguniform")
+            kept[i] = (xb, torch.arange(count, dtype=torch.int64, device=dev) * 29 + 3 + i, sb)
+        return kept[i]
 
     res = autotune.tune(X, k, sfft.SFFT_MODE_EXACT, seeds=seeds, truth=sups, base=base, space=space, reps=2,
                         cache=cache, confirm=confirm, confirm_batches=2)
