@@ -197,7 +197,7 @@ def oracle_params(desc, seed):
     return SfftParams(n=desc.n, k=desc.k, B=desc.B, w=desc.w, seed=seed, alpha=desc.alpha, delta=desc.delta,
                       theta=desc.theta, g_min=desc.g_min, rounds=desc.rounds, b_min=desc.b_min,
                       patience=desc.patience, stop_count=desc.stop_count,
-                      stop_patience=desc.stop_patience, cap=desc.cap)
+                      stop_patience=desc.stop_patience, ratio_tol=desc.ratio_tol, cap=desc.cap)
 
 
 def main():
@@ -501,7 +501,7 @@ def main():
                    "signals": S, "n": n, "k": k, "B": B, "w": w, "rounds": desc.rounds,
                    "b_min": desc.b_min or max(2, B >> 4), "patience": desc.patience, "delta": desc.delta,
                    "alpha": desc.alpha, "theta": desc.theta, "g_min": desc.g_min,
-                   "stop_count": desc.stop_count, "stop_patience": desc.stop_patience,
+                   "stop_count": desc.stop_count, "stop_patience": desc.stop_patience, "ratio_tol": desc.ratio_tol,
                    "hash_threads": desc.hash_threads, "chunks": chunks, "loc_prec": args.loc_prec,
                    "input": "complex64"},
         "autotune": tune_rec,

@@ -123,6 +123,11 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *   stop_patience  empty rounds in a row that end a signal under stop_count
  *             (>= 1; default 2: one empty round can hide a coefficient
  *             placed one location off, whose residual pair cancels in a bin)
+ *   ratio_tol exact mode: decode only bins whose squared magnitudes at the
+ *             two shifts agree within this fraction, ||u1|^2 - |u0|^2| <=
+ *             ratio_tol |u0|^2 (0 = off): an isolated coefficient gives equal
+ *             magnitudes (exact-estimation lemma), a collision rarely does.
+ *             Such bins still count as nonempty
  *   group0    exact mode, batched: rounds hashed for every signal in the
  *             first HashToBins launch (0 = up to the first round at b_min
  *             bins plus patience + 1, the earliest the patience rule can stop
@@ -159,6 +164,7 @@ typedef struct {
     uint32_t stop_count;
     uint32_t stop_patience;
     uint32_t group0;
+    double ratio_tol;
 } sfft_plan_desc_t;
 
 typedef struct sfft_plan_s* sfft_plan_t;

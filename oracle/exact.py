@@ -7,7 +7,8 @@ w_r = w B_r / B window (params.round_bins):
   * J  = { j : |u_j| > theta };  stop after `patience` consecutive rounds with
     J empty, or after `stop_patience` once `stop_count` (> 0) entries of zhat
     exceed theta/2 in magnitude (or after `rounds` rounds);
-  * for j in J: the phase of u_j / u'_j equals 2 pi sigma i / n for an isolated
+  * for j in J (with ratio_tol > 0, only bins where |u'_j|^2 is within that
+    fraction of |u_j|^2): the phase of u_j / u'_j equals 2 pi sigma i / n for an isolated
     coefficient (the exact-estimation lemma of Section 3), so
         p = round(phi(u_j / u'_j) n / (2 pi)) mod n,   i = sigma^{-1} p mod n;
     accept i only if h(i) = j and G'_{-o(i)} >= g_min, with value
@@ -56,9 +57,10 @@ class Margins:
     rounding: float = math.inf    # distance of phi n / 2pi from a half-integer
     gmin: float = math.inf        # | G' - g_min | for decoded candidates
     output: float = math.inf      # | |value| - theta/2 |
+    ratio: float = math.inf       # | ||u'|^2 - |u|^2| / |u|^2 - ratio_tol | when the check is on
 
     def smallest(self):
-        return min(self.threshold, self.rounding, self.gmin, self.output)
+        return min(self.threshold, self.rounding, self.gmin, self.output, self.ratio)
 
 
 @dataclass
@@ -74,8 +76,18 @@ class ExactResult:
 
 
 def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Margins):
-    """Location and value of bin j of a B-bin hashing; returns (i, v) or None."""
+    """Location and value of bin j of a B-bin hashing; returns (i, v) or None.
+    With ratio_tol > 0 a bin whose two hashings differ in magnitude by more
+    than that fraction is not decoded: an isolated coefficient gives
+    u'_j = u_j omega^{sigma i} (the exact-estimation lemma), equal in
+    magnitude, while a bin shared by several coefficients almost never does."""
     n = p.n
+    if p.ratio_tol > 0.0:
+        m0 = u0j.real * u0j.real + u0j.imag * u0j.imag
+        m1 = u1j.real * u1j.real + u1j.imag * u1j.imag
+        margins.ratio = min(margins.ratio, abs(abs(m1 - m0) / m0 - p.ratio_tol))
+        if abs(m1 - m0) > p.ratio_tol * m0:
+            return None
     z = u0j * np.conj(u1j)
     phi = math.atan2(z.imag, z.real)
     if phi < 0.0:

@@ -32,6 +32,11 @@ stop_count  exact mode: also stop after `stop_patience` consecutive rounds with
           the transition band; below k entries the patience rule still
           applies.
 stop_patience  empty rounds in a row that end a run under stop_count (>= 1).
+ratio_tol  exact mode: decode only bins whose two hashings (shifts 0 and 1) agree
+          in squared magnitude within this fraction (0: off).  An isolated
+          coefficient gives equal magnitudes (the exact-estimation lemma of
+          Section 3); a collision rarely does, and its decode would add a
+          wrong entry that later rounds must take back out.
 rounds    exact mode: maximum number of NoiselessSparseFFTInner rounds
           general mode: number of SparseFFT rounds
 t, s      LocateInner region count and vote tolerance (Algorithm 3)
@@ -60,6 +65,7 @@ class SfftParams:
     patience: int = 3
     stop_count: int = 0
     stop_patience: int = 2
+    ratio_tol: float = 0.0
     t: int = 16
     s: float = 0.125
     R_loc: int = 3

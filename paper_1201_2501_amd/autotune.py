@@ -90,8 +90,8 @@ def default_space(n, k, mode, theta=0.25):
         return {
             "window": {"B": Bs, "delta": [1e-10, 1e-9, 1e-8, 1e-7], "alpha": [0.5, 0.6, 0.7]},
             "schedule": {"b_min": [16, 32, 64], "patience": [3, 4, 5]},
-            "decode": {"theta": [theta, theta / 2], "g_min": [0.25, 0.4], "patience": [3, 4, 5]},
-            "stop": {"stop_count": [0, k], "stop_patience": [2, 3]},
+            "decode": {"theta": [theta, theta / 2], "g_min": [0.25, 0.4], "ratio_tol": [0.0, 0.002, 0.01]},
+            "stop": {"stop_count": [0, k], "stop_patience": [2, 3], "patience": [3, 4, 5]},
             "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
             "groups": {"group0_offset": [0, -1, 1, 2]},
         }

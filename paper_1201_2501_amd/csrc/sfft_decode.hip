@@ -650,6 +650,11 @@ __device__ __forceinline__ bool exact_bin(const DecodeArgs& D, DecodeLds& L, uin
     }
     const double mag = sqrt(u0r * u0r + u0i * u0i);
     if (!(mag > D.theta)) return false;
+    if (D.ratio_tol > 0.0) {
+        // an isolated coefficient has equal magnitudes at both shifts
+        const double m0 = u0r * u0r + u0i * u0i, m1 = u1r * u1r + u1i * u1i;
+        if (fabs(m1 - m0) > D.ratio_tol * m0) return true;
+    }
     const double zr = u0r * u1r + u0i * u1i;
     const double zim = u0i * u1r - u0r * u1i;
     double phi = atan2(zim, zr);

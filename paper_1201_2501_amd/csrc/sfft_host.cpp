@@ -473,6 +473,7 @@ DecodeArgs base_decode(const sfft_plan_s* p, uint32_t count, const uint64_t* see
     D.patience = p->d.patience;
     D.stop_count = p->d.mode == SFFT_MODE_EXACT ? p->d.stop_count : 0;
     D.stop_patience = p->d.stop_patience;
+    D.ratio_tol = p->d.ratio_tol;
     D.Bmax = p->Bmax;
     D.capz = p->capz;
     D.cap = p->cap;
@@ -792,6 +793,7 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->stop_count = 0;
     d->stop_patience = 2;
     d->group0 = 0;
+    d->ratio_tol = 0.0;
     return SFFT_OK;
 }
 
@@ -821,6 +823,7 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (d->chunks > kMaxChunks) return fail(SFFT_EINVAL, "chunks must be in [0, 8]");
     if (d->stop_patience < 1) return fail(SFFT_EINVAL, "stop_patience must be >= 1");
     if (d->group0 > kMaxRounds) return fail(SFFT_EINVAL, "group0 must be in [0, 32]");
+    if (!(d->ratio_tol >= 0.0 && d->ratio_tol < 1.0)) return fail(SFFT_EINVAL, "ratio_tol must be in [0, 1)");
     const uint32_t cap = d->cap ? d->cap : d->k;
     if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");
     if (d->mode == SFFT_MODE_GENERAL) {

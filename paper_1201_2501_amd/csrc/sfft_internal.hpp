@@ -122,13 +122,15 @@ struct DecodeArgs {
     double* cand_v;            // [sig][Bmax][2]
     uint64_t* zidx;            // [sig][2][capz]
     double* zval;              // [sig][2][capz][2]
-    double* est;               // [sig][capz][rounds][2] re-estimation samples
+    double* est;               // re-estimation samples: [sig][rounds][capz][2] (split finish) or
+                               // [sig][capz][rounds][2] (one-workgroup finish)
     double* fin;               // [sig][capz][2] re-estimated values
     double* gtmp;              // [sig][capz][4] per-entry terms when LDS cannot hold them
     uint32_t* ecount;          // [sig][capz] samples per entry
-    uint8_t* eflag;            // [sig][capz][rounds] sample kind: 0 none, 1 isolated, 2 crowded
+    uint8_t* eflag;            // [sig][rounds][capz] sample kind: 0 none, 1 isolated, 2 crowded
     uint32_t* state;           // [sig][kStateWords]
     double theta, g_min;
+    double ratio_tol;          // decode a bin only if its two squared magnitudes agree within this (0: off)
     double out_scale;
     uint64_t* out_idx;         // [sig][cap]
     double* out_val;           // [sig][cap][2]

@@ -38,7 +38,8 @@ def oracle_params(plan, seed=None):
     d = plan.desc
     return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=d.seed if seed is None else seed, alpha=d.alpha,
                       delta=d.delta, theta=d.theta, g_min=d.g_min, rounds=d.rounds, b_min=d.b_min,
-                      patience=d.patience, stop_count=d.stop_count, stop_patience=d.stop_patience, cap=d.cap)
+                      patience=d.patience, stop_count=d.stop_count, stop_patience=d.stop_patience,
+                      ratio_tol=d.ratio_tol, cap=d.cap)
 
 
 RAW_CASES = [
@@ -203,7 +204,8 @@ def test_zero_signal_and_truncation(torch_dev):
 
 @pytest.mark.parametrize("seed,sched", [(0, "default"), (1, "default"), (2, "tuned"), (3, "tuned"), (4, "alpha0.6"),
                                         (5, "alpha0.6"), (6, "stopk"), (7, "stopk"), (8, "lowtheta"),
-                                        (9, "lowtheta"), (10, "alpha0.7"), (11, "alpha0.7")])
+                                        (9, "lowtheta"), (10, "alpha0.7"), (11, "alpha0.7"), (12, "ratio"),
+                                        (13, "ratio")])
 def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     """n = 2^22, k = 256, log-uniform magnitudes, complex64, FP64 location
     decoding; the default schedule (b_min = B/16, 16 rounds), b_min = 32 with
@@ -214,14 +216,16 @@ def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     torch, dev = torch_dev
     n, k, B = 1 << 22, 256, 1024
     alpha, delta = {"alpha0.6": (0.6, 1e-8), "stopk": (0.6, 1e-8), "lowtheta": (0.6, 1e-8),
-                    "alpha0.7": (0.7, 1e-7)}.get(sched, (0.5, 1e-9))
+                    "alpha0.7": (0.7, 1e-7), "ratio": (0.6, 1e-7)}.get(sched, (0.5, 1e-9))
     w = default_w(n, B, alpha, delta)
     kw = {"default": {}, "tuned": dict(b_min=32, rounds=24),
           "alpha0.6": dict(alpha=0.6, b_min=64, patience=4, rounds=24),
           "stopk": dict(alpha=0.6, b_min=64, patience=5, rounds=24, stop_count=k, stop_patience=2 + seed % 2),
           "lowtheta": dict(alpha=0.6, b_min=64, patience=4, rounds=24, theta=0.01, g_min=0.25),
           "alpha0.7": dict(alpha=0.7, b_min=64, patience=4, rounds=24, theta=0.01, g_min=0.25, stop_count=k,
-                           stop_patience=3)}[sched]
+                           stop_patience=3),
+          "ratio": dict(alpha=0.6, b_min=64, patience=4, rounds=24, g_min=0.25, ratio_tol=0.01, stop_count=k,
+                        stop_patience=3)}[sched]
     theta = kw.pop("theta", 0.02)
     say("c3-shape", sched, "n", n, "k", k, "B", B, "w", w, "seed", seed)
     plan = plan_for(n, k, B, w, 0, delta=delta, theta=theta, loc_prec=1, max_batch=2, **kw)

@@ -214,3 +214,56 @@ def test_stop_count_ends_at_the_first_empty_round_with_k_entries(seed):
     assert fast.rounds_used == 2 or fast.round_log[fast.rounds_used - 3][0] > 0
     never = noiseless_sparse_fft(x, SfftParams(**{**base.__dict__, "stop_count": base.k + 1}))
     assert never.rounds_used == ref.rounds_used and np.array_equal(never.indices, ref.indices)
+
+
+def test_ratio_check_keeps_isolated_bins_and_rejects_collisions():
+    """With ratio_tol the decode keeps a bin whose two hashings have equal
+    magnitudes (an isolated coefficient, computed through HashToBins) and
+    rejects one holding two coefficients 100 permuted positions apart, whose
+    magnitudes at shifts 0 and 1 differ by 2 Re(c0 conj(c1) (e^{i d} - 1)),
+    d = 2 pi 100 / n (computed through HashToBins from the two-tone
+    signal).  Coefficients a few positions apart are indistinguishable at
+    these shifts: the check only removes well separated collisions."""
+    from oracle.exact import Margins, decode_bin
+    n, B, alpha, delta = 1 << 14, 64, 0.5, 1e-12
+    w = default_w(n, B, alpha, delta)
+    G = window_time(n, B, w, alpha, delta)
+    p = SfftParams(n=n, k=4, B=B, w=w, seed=0, delta=delta, ratio_tol=0.01)
+    rng = np.random.default_rng(3)
+    kept = rejected = 0
+    for trial in range(400):
+        sigma, b = 2 * int(rng.integers(0, n // 2)) + 1, int(rng.integers(0, n))
+        sinv = pow(sigma, -1, n)
+        i0 = int(rng.integers(0, n))
+        h, o = bin_offset(i0, sigma, b, n, B)
+        i1 = (i0 + 100 * sinv) % n                      # pi(i1) = pi(i0) + 100
+        h1, o1 = bin_offset(i1, sigma, b, n, B)
+        if h1 != h or min(gprime(-o, n, B, alpha, delta), gprime(-o1, n, B, alpha, delta)) < 1.0:
+            continue
+        X = np.zeros(n, complex)
+        X[i0] = 1.0
+        x1 = np.fft.ifft(X) * np.sqrt(n)
+        u0 = hash_to_bins_raw(x1, sigma, 0, b, B, G)[h]
+        u1 = hash_to_bins_raw(x1, sigma, 1, b, B, G)[h]
+        got = decode_bin(u0, u1, h, sigma, sinv, b, B, p, Margins())
+        assert got is not None and got[0] == i0
+        kept += 1
+        X[i1] = 0.8j
+        x2 = np.fft.ifft(X) * np.sqrt(n)
+        v0 = hash_to_bins_raw(x2, sigma, 0, b, B, G)[h]
+        v1 = hash_to_bins_raw(x2, sigma, 1, b, B, G)[h]
+        d = 2 * math.pi * 100 / n
+        expect = abs(2 * (1.0 * np.conj(0.8j) * (np.exp(1j * d) - 1)).real)
+        assert abs(abs(abs(v1) ** 2 - abs(v0) ** 2) - expect) < 1e-9
+        assert decode_bin(v0, v1, h, sigma, sinv, b, B, p, Margins()) is None
+        rejected += 1
+    assert kept >= 10 and rejected == kept
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_ratio_check_keeps_exact_recovery(seed):
+    p = c1_params(seed, ratio_tol=0.01)
+    x, sup, val = siggen.planted_signal(p.n, p.k, 100 + seed, np.complex128)
+    r = noiseless_sparse_fft(x, p)
+    assert np.array_equal(r.indices, sup)
+    assert np.max(np.abs(r.values - val)) < 1e-4
