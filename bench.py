@@ -242,7 +242,7 @@ def main():
     ap.add_argument("--tune", choices=["off", "cache", "run"], default="cache",
                     help="plan parameters: off = the flags above; cache = the autotuner's stored choice for this "
                          "device, shape and library build, measured now when none is stored; run = measure now")
-    ap.add_argument("--tune-budget", type=float, default=240.0, help="seconds of autotuner measurement at most")
+    ap.add_argument("--tune-budget", type=float, default=300.0, help="seconds of autotuner measurement at most")
     ap.add_argument("--tune-out", default="", help="also store the autotuner's choice in this JSON file")
     ap.add_argument("--tune-confirm", type=int, default=6,
                     help="fresh batches the fastest accepted candidates must also pass")

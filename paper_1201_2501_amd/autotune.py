@@ -334,7 +334,7 @@ class _Runner:
 
 def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, space=None, reps=3,
          budget_s=120.0, cache=None, recall_slack=0.005, log=None, force=False, confirm=None,
-         confirm_batches=4, confirm_top=16, beam=3, launch_margin=0.01):
+         confirm_batches=4, confirm_top=16, beam=3, launch_margin=0.01, passes=2):
     """Tune the plan of a batch x ([count, n] complex device tensor) with
     sparsity k.  base: plan fields kept fixed (e.g. theta, rounds, loc_prec,
     flags); space: {"window": {...}, "schedule": {...}, "launch": {...}}
@@ -440,10 +440,13 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
         confirmed = confirm_batches
 
     use_confirm = confirm is not None and confirm_batches > 0
-    for name in result_stages:
-        stage(name, [dict(r["cand"]) for r in ranked_accepted()[:beam]])
-        if use_confirm:
-            confirm_top_new()
+    # the stages interact (a shorter window can pass only with the decode
+    # settings found later), so the result stages are searched `passes` times
+    for _ in range(passes):
+        for name in result_stages:
+            stage(name, [dict(r["cand"]) for r in ranked_accepted()[:beam]])
+            if use_confirm:
+                confirm_top_new()
     survivors = passed if use_confirm else None
 
     def eligible():
