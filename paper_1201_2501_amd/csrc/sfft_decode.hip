@@ -274,8 +274,18 @@ __device__ void sort_unique_keys(uint64_t* key, uint32_t m) {
     if (m <= kDec) {
         const uint64_t mine = tid < m ? key[tid] : 0;
         uint32_t rank = 0;
-        if (tid < m)
-            for (uint32_t q = 0; q < m; ++q) rank += key[q] < mine ? 1u : 0u;
+        if (tid < m) {
+            // independent broadcast reads, eight in flight
+            uint32_t q = 0;
+            for (; q + 8 <= m; q += 8) {
+                uint64_t k8[8];
+#pragma unroll
+                for (uint32_t u = 0; u < 8; ++u) k8[u] = key[q + u];
+#pragma unroll
+                for (uint32_t u = 0; u < 8; ++u) rank += k8[u] < mine ? 1u : 0u;
+            }
+            for (; q < m; ++q) rank += key[q] < mine ? 1u : 0u;
+        }
         __syncthreads();
         if (tid < m) key[rank] = mine;
         __syncthreads();
@@ -291,12 +301,29 @@ __device__ void sort_unique_keys(uint64_t* key, uint32_t m) {
 // place; new ones are merged by index into the other zhat buffer, which
 // becomes current.  Expects L.zl to hold the current indices.  Returns the
 // number of new entries.
+//
+// kByBin (exact mode): the slot is the bin the candidate was decoded from and
+// L.first/L.ent still group this round's entries by bin, so an existing
+// entry with the candidate's index can only be in that bin; an update is
+// marked in L.hk (0x8000 | slot; bins are below 0x8000) and applied by the
+// entry's owner while copying.  The owners load the current values of their
+// first kUnroll entries before the sort, so the copy does not wait on HBM.
+// Otherwise a binary search finds existing entries, which are updated in
+// HBM and read back by the copy.
+template <bool kByBin>
 __device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv, uint64_t* zidx_all, double* zval_all,
                                      uint32_t sig, uint32_t capz) {
     const uint32_t tid = threadIdx.x;
     const uint32_t zc = L.sw[ST_ZCOUNT];
     const uint32_t zb = L.sw[ST_ZBUF];
     double* zv = zval_all + ((uint64_t)sig * 2 + zb) * capz * 2;
+    double2 zcur[kUnroll];
+    if constexpr (kByBin) {
+        const double2* zv2 = reinterpret_cast<const double2*>(zv);
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u)
+            if (tid + u * kDec < zc) zcur[u] = zv2[tid + u * kDec];
+    }
     sort_unique_keys(L.ckey, m);
     const uint32_t per = (m + kDec - 1) / kDec;
     const uint32_t q0 = tid * per < m ? tid * per : m;
@@ -306,10 +333,21 @@ __device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv,
         const uint64_t k = L.ckey[q];
         const uint64_t i = k >> kCandShift;
         const uint32_t j = (uint32_t)(k & kSlotMask);
-        const uint32_t e = lower_bound_lds(L.zl, zc, i);
-        if (e < zc && L.zl[e] == i) {
-            zv[2 * e] += cv[2 * j];
-            zv[2 * e + 1] += cv[2 * j + 1];
+        uint32_t e = zc;
+        if constexpr (kByBin) {
+            for (uint32_t p = L.first[j]; p < L.first[j + 1]; ++p)
+                if (L.zl[L.ent[p]] == i) e = L.ent[p];
+        } else {
+            e = lower_bound_lds(L.zl, zc, i);
+            if (e < zc && L.zl[e] != i) e = zc;
+        }
+        if (e < zc) {
+            if constexpr (kByBin) {
+                L.hk[e] = (uint16_t)(0x8000u | j);
+            } else {
+                zv[2 * e] += cv[2 * j];
+                zv[2 * e + 1] += cv[2 * j + 1];
+            }
             L.ckey[q] = k | kFound;
         } else {
             ++fresh;
@@ -328,7 +366,7 @@ __device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv,
     uint64_t* zo = zidx_all + ((uint64_t)sig * 2 + (zb ^ 1)) * capz;
     double* zov = zval_all + ((uint64_t)sig * 2 + (zb ^ 1)) * capz * 2;
     uint64_t* zl2 = L.zl2;
-    for (uint32_t e = tid; e < zc; e += kDec) {
+    auto copy = [&](uint32_t e, double vr, double vi) {
         const uint64_t i = L.zl[e];
         uint32_t lo = 0, hi = mnew;
         while (lo < hi) {
@@ -338,8 +376,25 @@ __device__ uint32_t merge_candidates(DecodeLds& L, uint32_t m, const double* cv,
         const uint32_t pos = e + lo;
         zo[pos] = i;
         if (zl2) zl2[pos] = i;
-        zov[2 * pos] = zv[2 * e];
-        zov[2 * pos + 1] = zv[2 * e + 1];
+        if constexpr (kByBin) {
+            const uint32_t mk = L.hk[e];
+            if (mk & 0x8000u) {
+                vr += cv[2 * (mk & 0x7FFFu)];
+                vi += cv[2 * (mk & 0x7FFFu) + 1];
+            }
+        }
+        zov[2 * pos] = vr;
+        zov[2 * pos + 1] = vi;
+    };
+    if constexpr (kByBin) {
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            const uint32_t e = tid + u * kDec;
+            if (e < zc) copy(e, zcur[u].x, zcur[u].y);
+        }
+        for (uint32_t e = tid + kUnroll * kDec; e < zc; e += kDec) copy(e, zv[2 * e], zv[2 * e + 1]);
+    } else {
+        for (uint32_t e = tid; e < zc; e += kDec) copy(e, zv[2 * e], zv[2 * e + 1]);
     }
     for (uint32_t q = tid; q < mnew; q += kDec) {
         const uint64_t i = L.nkey[q] >> kCandShift;
@@ -760,7 +815,7 @@ __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uin
         __syncthreads();
         return;
     }
-    const uint32_t mnew = merge_candidates(L, m, cv, D.zidx, D.zval, sig, D.capz);
+    const uint32_t mnew = merge_candidates<true>(L, m, cv, D.zidx, D.zval, sig, D.capz);
     if (tid == 0) {
         sw[ST_EMPTY] = 0;
         sw[ST_ROUNDS] = r + 1;
@@ -1299,7 +1354,7 @@ __global__ void __launch_bounds__(kDec) k_gen_merge(GeneralArgs G, uint32_t r) {
         L.ckey[q] = (cand[c] << kCandShift) | c;
     }
     __syncthreads();
-    merge_candidates(L, take, candv, G.zidx, G.zval, sig, G.capz);
+    merge_candidates<false>(L, take, candv, G.zidx, G.zval, sig, G.capz);
     if (tid == 0) {
         L.sw[ST_ROUNDS] = r + 1;
         L.sw[ST_LASTJ] = nL;
