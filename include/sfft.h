@@ -134,6 +134,10 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *             a signal; capped at rounds).  Later launches hash 2, 2, 4, 8,
  *             ... rounds for the signals still decoding.  Launch shape only:
  *             results do not depend on it
+ *   group_step  exact mode, batched: rounds of the second round group, each
+ *             later group twice the previous (0 = 2, 2, 4, 8, ...).  Launch
+ *             shape only
+ *   reserved  must be 0
  */
 typedef struct {
     uint64_t n;
@@ -165,6 +169,8 @@ typedef struct {
     uint32_t stop_patience;
     uint32_t group0;
     double ratio_tol;
+    uint32_t group_step;
+    uint32_t reserved;
 } sfft_plan_desc_t;
 
 typedef struct sfft_plan_s* sfft_plan_t;

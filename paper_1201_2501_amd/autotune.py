@@ -93,7 +93,7 @@ def default_space(n, k, mode, theta=0.25):
             "decode": {"theta": [theta, theta / 2], "g_min": [0.25, 0.4], "ratio_tol": [0.0, 0.002, 0.01]},
             "stop": {"stop_count": [0, k], "stop_patience": [2, 3], "patience": [3, 4, 5]},
             "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
-            "groups": {"group0_offset": [0, -1, 1, 2]},
+            "groups": {"group0_offset": [0, -1, 1, 2], "group_step": [0, 3, 4]},
         }
     lo = max(256, 4 * k)
     Bs = pow2_range(lo, min(4096, n // 16)) or [min(4096, max(2, n // 16))]
@@ -114,7 +114,7 @@ def first_floor_round(B, b_min):
 
 # stages and fields that choose only the launch shape: results do not depend on them
 LAUNCH_STAGES = ("launch", "groups")
-LAUNCH_FIELDS = ("hash_threads", "chunks", "group0", "group0_offset")
+LAUNCH_FIELDS = ("hash_threads", "chunks", "group0", "group0_offset", "group_step")
 
 
 def signature(cand):
@@ -125,7 +125,7 @@ def signature(cand):
 def launch_changes(cand):
     """Number of launch fields set away from the library defaults."""
     return (int(cand.get("hash_threads", 256) != 256) + int(cand.get("chunks", 1) not in (0, 1)) +
-            int(bool(cand.get("group0"))))
+            int(bool(cand.get("group0"))) + int(bool(cand.get("group_step"))))
 
 
 def normalize(cand):
@@ -136,6 +136,8 @@ def normalize(cand):
     c = dict(cand)
     if not c.get("stop_count"):
         c.pop("stop_patience", None)
+    if not c.get("group_step"):
+        c.pop("group_step", None)
     off = c.pop("group0_offset", None)
     if off is not None:
         c.pop("group0", None)

@@ -334,8 +334,8 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     // Round groups of the batched exact path: a signal stops at the earliest
     // `patience` rounds after the first round at the smallest bin count, so
     // group 0 runs to there unless the plan sets `group0`; later groups take
-    // 2, 2, 4, 8, ... rounds (few signals need the long tail, and every
-    // group costs two launches).
+    // 2, 2, 4, 8, ... rounds, or group_step, 2 group_step, 4 group_step, ...
+    // (few signals need the long tail, and every group costs two launches).
     if (!general_mode(p)) {
         uint32_t first_floor = p->R;
         for (uint32_t r = 0; r < p->R; ++r)
@@ -346,7 +346,9 @@ sfft_status_t build_plan(sfft_plan_s* p) {
         uint32_t e = std::min<uint32_t>(p->R, d.group0 ? d.group0 : first_floor + d.patience + 1);
         p->group_end.push_back(e);
         for (uint32_t g = 1; e < p->R; ++g) {
-            e = std::min<uint32_t>(p->R, e + (g <= 2 ? 2u : 1u << (g - 1)));
+            const uint32_t len = d.group_step ? d.group_step << (g - 1 < 16 ? g - 1 : 16)
+                                              : (g <= 2 ? 2u : 1u << (g - 1));
+            e = std::min<uint32_t>(p->R, e + len);
             p->group_end.push_back(e);
         }
     }
@@ -794,6 +796,8 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->stop_patience = 2;
     d->group0 = 0;
     d->ratio_tol = 0.0;
+    d->group_step = 0;
+    d->reserved = 0;
     return SFFT_OK;
 }
 
@@ -824,6 +828,8 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (d->stop_patience < 1) return fail(SFFT_EINVAL, "stop_patience must be >= 1");
     if (d->group0 > kMaxRounds) return fail(SFFT_EINVAL, "group0 must be in [0, 32]");
     if (!(d->ratio_tol >= 0.0 && d->ratio_tol < 1.0)) return fail(SFFT_EINVAL, "ratio_tol must be in [0, 1)");
+    if (d->group_step > kMaxRounds) return fail(SFFT_EINVAL, "group_step must be in [0, 32]");
+    if (d->reserved != 0) return fail(SFFT_EINVAL, "reserved must be 0");
     const uint32_t cap = d->cap ? d->cap : d->k;
     if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");
     if (d->mode == SFFT_MODE_GENERAL) {

@@ -44,7 +44,8 @@ class PlanDesc(ctypes.Structure):
                 ("t", c_uint32), ("R_loc", c_uint32), ("R_est", c_uint32), ("cap", c_uint32),
                 ("flags", c_uint32), ("max_batch", c_uint32), ("hash_threads", c_uint32),
                 ("chunks", c_uint32), ("stop_count", c_uint32),
-                ("stop_patience", c_uint32), ("group0", c_uint32), ("ratio_tol", c_double)]
+                ("stop_patience", c_uint32), ("group0", c_uint32), ("ratio_tol", c_double),
+                ("group_step", c_uint32), ("reserved", c_uint32)]
 
 
 class ServerDesc(ctypes.Structure):

@@ -246,9 +246,9 @@ def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     plan.close()
 
 
-@pytest.mark.parametrize("threads,chunks,group0", [(512, 1, 0), (1024, 1, 0), (256, 2, 0), (1024, 2, 0), (256, 1, 6),
-                                                  (512, 1, 12)])
-def test_c3_launch_shapes_match_oracle(torch_dev, threads, chunks, group0):
+@pytest.mark.parametrize("threads,chunks,group0,step", [(512, 1, 0, 0), (1024, 1, 0, 0), (256, 2, 0, 0), (1024, 2, 0, 0),
+                                                       (256, 1, 6, 0), (512, 1, 12, 0), (256, 1, 0, 4)])
+def test_c3_launch_shapes_match_oracle(torch_dev, threads, chunks, group0, step):
     """The launch shape the autotuner picks from (HashToBins workgroup size,
     batch chunks, size of the first round group) leaves supports and rounds
     unchanged and values within the FP64 bar: with B_r < threads a bin's
@@ -259,9 +259,12 @@ def test_c3_launch_shapes_match_oracle(torch_dev, threads, chunks, group0):
     count = 4
     say("c3-launch-shape", "threads", threads, "chunks", chunks, "group0", group0, "count", count)
     plan = plan_for(n, k, B, w, 0, delta=1e-9, theta=0.02, loc_prec=1, max_batch=count, b_min=32, rounds=24,
-                    hash_threads=threads, chunks=chunks, group0=group0, flags=2)     # SFFT_FLAG_TIMING: chunk count
+                    hash_threads=threads, chunks=chunks, group0=group0, group_step=step,
+                    flags=2)     # SFFT_FLAG_TIMING: chunk count
     assert plan.desc.hash_threads == threads and plan.desc.chunks == chunks
-    assert plan.round_groups()[0] == (group0 or 9)
+    g0 = group0 or 9
+    assert plan.round_groups() == ([g0, 13, 21, 24] if step == 4 else plan.round_groups())
+    assert plan.round_groups()[0] == g0
     xs, sups, seeds = [], [], []
     for s in range(count):
         x, sup, _ = siggen.planted_signal(n, k, 4000 + s, np.complex64, magnitude="loguniform")
