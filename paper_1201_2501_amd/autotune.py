@@ -16,8 +16,8 @@ calibration batch:
 
 Among accepted candidates the fastest (median time of `reps` replayed batch
 steps, HIP events) wins.  The search is coordinate-wise with a small beam,
-stage by stage in the order of the space (by default: the window and bin
-count, the round schedule, the decode thresholds, the count stop), each
+stage by stage in the order of the space (by default: the bin count, the
+window, the round schedule, the decode thresholds, the count stop), each
 stage varying its fields around each of the `beam` fastest accepted
 candidates so far; the launch-shape stages (HashToBins workgroup size, batch
 chunks, first round group), which cannot change results, run last, around
@@ -88,7 +88,8 @@ def default_space(n, k, mode, theta=0.25):
         Bs = pow2_range(lo, min(4096, n // 16)) or [min(4096, max(2, n // 16))]
         Bs = [b for b in Bs if b >= 512] or Bs[-2:]
         return {
-            "window": {"B": Bs, "delta": [1e-10, 1e-9, 1e-8, 1e-7], "alpha": [0.5, 0.6, 0.7]},
+            "bins": {"B": Bs},
+            "window": {"delta": [1e-10, 1e-9, 1e-8, 1e-7, 1e-6], "alpha": [0.5, 0.6, 0.7, 0.75]},
             "schedule": {"b_min": [16, 32, 64], "patience": [3, 4, 5]},
             "decode": {"theta": [theta, theta / 2], "g_min": [0.25, 0.4], "ratio_tol": [0.0, 0.002, 0.01]},
             "stop": {"stop_count": [0, k], "stop_patience": [2, 3], "patience": [3, 4, 5]},
@@ -98,7 +99,8 @@ def default_space(n, k, mode, theta=0.25):
     lo = max(256, 4 * k)
     Bs = pow2_range(lo, min(4096, n // 16)) or [min(4096, max(2, n // 16))]
     return {
-        "window": {"B": Bs[:3], "delta": [1e-7, 1e-6]},
+        "bins": {"B": Bs[:3]},
+        "window": {"delta": [1e-7, 1e-6]},
         "schedule": {"R_est": [5, 7, 9], "R_loc": [3, 4]},
         "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
     }
@@ -151,7 +153,7 @@ def reference_candidate(space, mode, base):
     """The conservative candidate every other one is compared with: the
     largest B, the smallest delta and the slowest-stopping schedule."""
     c = dict(base)
-    c["B"] = max(space["window"]["B"])
+    c["B"] = max(space["bins"]["B"])
     c["delta"] = min(space["window"]["delta"])
     if "alpha" in space["window"]:
         c["alpha"] = min(space["window"]["alpha"])
@@ -339,7 +341,7 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
          confirm_batches=4, confirm_top=16, beam=3, launch_margin=0.01, passes=2):
     """Tune the plan of a batch x ([count, n] complex device tensor) with
     sparsity k.  base: plan fields kept fixed (e.g. theta, rounds, loc_prec,
-    flags); space: {"window": {...}, "schedule": {...}, "launch": {...}}
+    flags); space: {"bins": {...}, "window": {...}, "schedule": {...}, ...}
     lists of candidate values (default_space when None); truth: per-signal
     planted supports, else the reference candidate's supports are the
     target; confirm: i -> (x_i, seeds_i, truth_i or None), fresh batches of

@@ -11,12 +11,12 @@ from paper_1201_2501_amd import autotune, sfft
 
 def test_default_space_exact_respects_kernel_limits():
     sp = autotune.default_space(1 << 22, 256, sfft.SFFT_MODE_EXACT)
-    assert sp["window"]["B"] == [512, 1024, 2048, 4096]
+    assert sp["bins"]["B"] == [512, 1024, 2048, 4096]
     assert set(sp["launch"]["hash_threads"]) == {256, 512, 1024}
     small = autotune.default_space(1 << 14, 16, sfft.SFFT_MODE_EXACT)
-    assert max(small["window"]["B"]) <= (1 << 14) // 16
+    assert max(small["bins"]["B"]) <= (1 << 14) // 16
     gen = autotune.default_space(1 << 26, 1024, sfft.SFFT_MODE_GENERAL)
-    assert gen["window"]["B"] == [4096]
+    assert gen["bins"]["B"] == [4096]
 
 
 def test_reference_candidate_is_the_conservative_corner():

@@ -24,7 +24,7 @@ def test_autotune_small_exact_batch(tmp_path):
     say("autotune", "n", n, "k", k, "count", count)
     X, sups, _ = siggen.torch_planted_batch(n, k, [7000 + s for s in range(count)], dev, magnitude="loguniform")
     seeds = torch.arange(count, dtype=torch.int64, device=dev) * 13 + 5
-    space = {"window": {"B": [128, 256], "delta": [1e-9]},
+    space = {"bins": {"B": [128, 256]}, "window": {"delta": [1e-9]},
              "schedule": {"b_min": [16, 32], "patience": [3]},
              "launch": {"hash_threads": [256, 512], "chunks": [1]}}
     base = dict(theta=0.02, rounds=24, loc_prec=sfft.SFFT_F64)

@@ -360,3 +360,35 @@ def test_section5_reduction_k_point_dft(torch_dev, n, k, B):
         assert np.array_equal(out[s][0], expect_idx)
         assert np.max(np.abs(out[s][1] - expect_val)) <= 1e-9 * np.max(np.abs(expect_val))
     plan.close()
+
+
+def test_cached_tuned_c3_plan_matches_oracle(torch_dev):
+    """The plan the autotuner stored for the n = 2^22, k = 256 batch (the one
+    bench.py times) matches the oracle on two signals of that workload."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1201_2501_amd",
+                        "tuned.json")
+    recs = [r for key, r in json.load(open(path)).items() if "|n=4194304|k=256|mode=0|" in key] \
+        if os.path.exists(path) else []
+    if not recs:
+        pytest.skip("no stored plan for this workload")
+    rec = recs[0]
+    torch, dev = torch_dev
+    n, k, B = 1 << 22, 256, rec["B"]
+    fields = {f: v for f, v in rec["fields"].items() if f not in ("mode",)}
+    say("c3-cached-plan", "B", B, fields)
+    plan = plan_for(n, k, B, 0, 0, max_batch=2, **fields)
+    xs, sups, seeds = [], [], []
+    for s in range(2):
+        x, sup, _ = siggen.planted_signal(n, k, 5000 + s, np.complex64, magnitude="loguniform")
+        xs.append(x)
+        sups.append(sup)
+        seeds.append(101 * s + 17)
+    out = run_batch(torch, dev, plan, xs, seeds)
+    for s in range(2):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        assert int(out[s][2][0]) == ref.rounds_used
+        compare(out[s][0], out[s][1], ref)
+        assert np.array_equal(out[s][0], sups[s])
+    plan.close()
