@@ -241,7 +241,8 @@ def main():
                          "reported at top level are the middle one's")
     ap.add_argument("--tune", choices=["off", "cache", "run"], default="cache",
                     help="plan parameters: off = the flags above; cache = the autotuner's stored choice for this "
-                         "device, shape and library build, measured now when none is stored; run = measure now")
+                         "device and shape (from this library build if stored, else from another), measured now "
+                         "when none is stored; run = measure now")
     ap.add_argument("--tune-budget", type=float, default=300.0, help="seconds of autotuner measurement at most")
     ap.add_argument("--tune-out", default="", help="also store the autotuner's choice in this JSON file")
     ap.add_argument("--tune-confirm", type=int, default=6,
@@ -277,7 +278,8 @@ def main():
     if args.tune != "off" and not args.w:
         res = None
         if args.tune == "cache":
-            res = autotune.lookup(TUNE_FILE, n, k, sfft.SFFT_MODE_EXACT, S, sfft.SFFT_C64, autotune.device_tag(dev))
+            res = autotune.lookup(TUNE_FILE, n, k, sfft.SFFT_MODE_EXACT, S, sfft.SFFT_C64, autotune.device_tag(dev),
+                                  any_build=True)
         if res is None and not args.config_key:
             t = time.time()
             cal_seeds = [2_000_003 + s for s in range(S)]

@@ -202,14 +202,24 @@ def cache_key(n, k, mode, count, in_dtype, device_name):
                                                               library_hash())
 
 
-def lookup(cache, n, k, mode, count, in_dtype, device_name):
-    """The cached TuneResult of a shape, or None."""
+def lookup(cache, n, k, mode, count, in_dtype, device_name, any_build=False):
+    """The cached TuneResult of a shape, or None.  any_build: without an entry
+    for the current library build, take one stored by another build for the
+    same device and shape (its plan is valid; its timings may not be
+    current); from_cache is then "other build"."""
     key = cache_key(n, k, mode, count, in_dtype, device_name)
-    rec = _load_cache(cache).get(key)
+    data = _load_cache(cache)
+    rec, how = data.get(key), True
+    if not rec and any_build:
+        prefix = key[:key.rindex("|lib=")]
+        others = [(kk, r) for kk, r in data.items() if kk.startswith(prefix + "|lib=")]
+        if others:
+            key, rec = others[-1]
+            how = "other build"
     if not rec:
         return None
     return TuneResult(B=rec["B"], fields=rec["fields"], ms=rec["ms"], rate=rec["rate"], quality=rec["quality"],
-                      key=key, from_cache=True, confirm_batches=rec.get("confirm_batches", 0))
+                      key=key, from_cache=how, confirm_batches=rec.get("confirm_batches", 0))
 
 
 def _load_cache(path):

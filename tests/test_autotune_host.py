@@ -70,3 +70,12 @@ def test_cache_round_trip(tmp_path):
     assert autotune.lookup(path, 1 << 20, 64, 0, 32, 0, "other-device") is None
     assert json.load(open(path))[key]["ms"] == 1.5
     assert autotune.lookup(str(tmp_path / "missing.json"), 1 << 20, 64, 0, 32, 0, "test-device") is None
+    # another build's entry serves when asked, marked as such
+    other = autotune.lookup(path, 1 << 20, 64, 0, 32, 0, "test-device", any_build=True)
+    assert other.from_cache is True
+    data = json.load(open(path))
+    data[key.replace("|lib=", "|lib=old")] = data.pop(key)
+    json.dump(data, open(path, "w"))
+    assert autotune.lookup(path, 1 << 20, 64, 0, 32, 0, "test-device") is None
+    stale = autotune.lookup(path, 1 << 20, 64, 0, 32, 0, "test-device", any_build=True)
+    assert stale.from_cache == "other build" and stale.B == 512
