@@ -58,3 +58,47 @@ def test_autotune_small_exact_batch(tmp_path):
     for s in range(count):
         assert np.array_equal(idx[s, :counts[s]], np.sort(sups[s]))
     plan.close()
+
+
+def test_autotune_small_general_batch(tmp_path):
+    """General mode: candidates are accepted on their recall of the planted
+    heads (within the slack of the reference candidate's), the choice keeps
+    that recall on a fresh batch, and it is no slower than the reference."""
+    import torch
+    from paper_1201_2501_amd import autotune, sfft
+
+    sfft.load()
+    dev = torch.device("cuda:0")
+    n, k, count = 1 << 18, 16, 16
+    say("autotune-general", "n", n, "k", k, "count", count)
+
+    def batch(base):
+        X, sups, _ = siggen.torch_planted_batch(n, k, [base + s for s in range(count)], dev, magnitude="unit",
+                                                noise_ratio=0.05)
+        return X, torch.arange(count, dtype=torch.int64, device=dev) * 7 + base, sups
+
+    X, seeds, sups = batch(12_000)
+    kept = {}
+
+    def confirm(i):
+        if i not in kept:
+            kept[i] = batch(13_000 + 100 * i)
+        return kept[i]
+
+    space = {"bins": {"B": [256, 512]}, "window": {"delta": [1e-6]},
+             "schedule": {"R_est": [5, 7], "R_loc": [3]}, "launch": {"hash_threads": [256, 512]}}
+    res = autotune.tune(X, k, sfft.SFFT_MODE_GENERAL, seeds=seeds, truth=sups, space=space, reps=2,
+                        cache=str(tmp_path / "t.json"), confirm=confirm, confirm_batches=1)
+    ok = [r for r in res.table if "ms" in r]
+    ref = ok[0]
+    assert res.B in (256, 512) and res.fields["R_est"] in (5, 7)
+    assert res.quality >= ref["quality"] - 0.005 and res.ms <= ref["ms"]
+    plan = sfft.Plan(n, k, res.B, 0, 0, max_batch=count, **res.fields)
+    Xc, sc, supc = confirm(0)
+    bufs = plan.execute_batch(Xc, sc)
+    torch.cuda.synchronize()
+    counts = bufs["counts"].cpu().numpy()
+    idx = bufs["idx"].cpu().numpy()
+    recall = np.mean([len(np.intersect1d(idx[s, :counts[s]], supc[s])) / k for s in range(count)])
+    assert recall >= 0.95
+    plan.close()
