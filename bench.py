@@ -322,8 +322,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); multi-GPU sharding is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print("bench.py: runs on one GPU only (--gpus 1); sharding over several GPUs is not built",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

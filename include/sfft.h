@@ -200,7 +200,7 @@ uint64_t sfft_default_w(uint64_t n, uint32_t B, double alpha, double delta);
  * all of its device memory.  Errors: validation codes, SFFT_ENOMEM, SFFT_EHIP. */
 sfft_status_t sfft_plan_ex(const sfft_plan_desc_t* d, sfft_plan_t* out);
 
-/* sfft_plan_ex with the defaults of sfft_desc_init (spec signature). */
+/* sfft_plan_ex with the defaults of sfft_desc_init: plan(n, k, B, w, seed). */
 sfft_status_t sfft_plan(uint64_t n, uint32_t k, uint32_t B, uint64_t w, uint64_t seed,
                         sfft_plan_t* out);
 
