@@ -14,7 +14,9 @@ one-signal-at-a-time path, a dense full-length FFT + top-k on the same GPU
 (the crossover reference), per-step latency percentiles, the roofline of the
 dominant kernel (HashToBins, HBM bound; achieved = algorithmic bytes / its
 event-timed duration), sampled parity against the FP64 oracle, and the oracle
-itself timed on the host (cpu_baseline).
+itself timed on the host (cpu_baseline).  `--workload c4` (the general-mode
+precision split) and `--workload section5` (k-point DFTs through the n-point
+sFFT of the periodic extension) print their own line instead.
 """
 import argparse
 import json
@@ -259,6 +261,90 @@ def precision_split_bench(args, torch, dev, sfft, siggen):
             "variants": variants}
 
 
+def section5_bench(args, torch, dev, sfft):
+    """The Section 5 reduction as a workload: the k-point DFT of x_k computed
+    through the n-point exactly sparse sFFT of its periodic extension
+    y_t = x_{t mod k}, whose unitary spectrum is sqrt(n/k) times the unitary
+    k-point DFT of x_k on the multiples of n/k and zero elsewhere.  512
+    signals, n = 2^22, k = 256, complex64; each k-point spectrum has
+    log-uniform magnitudes (scaled so the n-point coefficients lie in
+    [0.1, 10]) and uniform phases.  The lattice support never collides at
+    B = 4k bins, and every coefficient of a round shares one offset within
+    its bin, so the plan keeps B fixed (b_min = B) and stops once all k are
+    found and a round comes back empty.  Timed against a direct k-point FFT
+    of the same batch (torch.fft, rocFFT).  Checked against the definition:
+    supports equal to the lattice, values against an FP64 k-point DFT."""
+    from paper_1201_2501_amd.sfft import Plan
+    n, k, S = 1 << 22, 256, 512
+    B = 4 * k
+    rng = np.random.Generator(np.random.PCG64(20260501))
+    mags = np.exp(rng.uniform(math.log(0.1), math.log(10.0), size=(S, k)))
+    spec = mags * np.exp(2j * math.pi * rng.uniform(0.0, 1.0, size=(S, k))) / math.sqrt(n / k)
+    xk = torch.fft.ifft(torch.from_numpy(spec).to(dev), dim=-1, norm="ortho")      # FP64, [S, k]
+    Y = xk.to(torch.complex64).repeat(1, n // k)                                       # [S, n], 16 GiB
+    xk64 = xk.to(torch.complex64).contiguous()
+    # expected: the FP64 k-point DFT of the stored (complex64) x_k, on the lattice
+    expect = (torch.fft.fft(xk64.to(torch.complex128), dim=-1, norm="ortho") * math.sqrt(n / k)).cpu().numpy()
+    seeds = torch.arange(S, dtype=torch.int64, device=dev) * 4099 + 11
+    torch.cuda.synchronize()
+    plan = Plan(n, k, B, 0, 0, alpha=0.5, delta=1e-9, theta=0.01, g_min=0.25, rounds=16, b_min=B, patience=8,
+                stop_count=k, stop_patience=1, group0=2, loc_prec=sfft.SFFT_F64, max_batch=S,
+                flags=sfft.SFFT_FLAG_TIMING)
+    bufs = plan.execute_batch(Y, seeds)
+    for _ in range(args.warmup):
+        plan.execute_batch(Y, seeds, bufs=bufs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        plan.execute_batch(Y, seeds, bufs=bufs)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    counts = bufs["counts"].cpu().numpy()
+    idx = bufs["idx"].cpu().numpy()
+    val = bufs["val"].cpu().numpy()
+    rounds = bufs["info"][:, 0].cpu().numpy()          # rounds each signal used
+    lattice = np.arange(k, dtype=np.int64) * (n // k)
+    ok, rel = 0, 0.0
+    for s in range(S):
+        c = int(counts[s])
+        good = c == k and np.array_equal(idx[s, :c], lattice)
+        ok += int(good)
+        if good:
+            rel = max(rel, float(np.max(np.abs(val[s, :c] - expect[s]) / np.abs(expect[s]))))
+    # direct k-point FFT of the same batch
+    out = torch.fft.fft(xk64, dim=-1)
+    for _ in range(args.warmup):
+        torch.fft.fft(xk64, dim=-1, out=out)
+    torch.cuda.synchronize()
+    reps = max(args.steps, 50)
+    e0.record()
+    for _ in range(reps):
+        torch.fft.fft(xk64, dim=-1, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_direct = e0.elapsed_time(e1) / reps
+    log("section5: sFFT %.3f ms/batch, supports %d/%d, max rel err %.2e; direct %d-point FFT %.4f ms/batch"
+        % (ms, ok, S, rel, k, ms_direct))
+    rec = {"metric": "k-point DFTs/s through the n-point sFFT (Section 5 reduction)",
+           "value": round(S / (ms * 1e-3), 1), "unit": "k-point DFTs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "Section 5 reduction: 512 periodic signals y_t = x_{t mod k}, n=2^22, k=256, "
+                                  "complex64, log-uniform k-point spectra", "signals": S, "n": n, "k": k, "B": B,
+                      "w": int(plan.desc.w), "alpha": 0.5, "delta": 1e-9, "theta": 0.01,
+                      "round_groups": list(plan.round_groups())},
+           "supports_equal_lattice": "%d/%d" % (ok, S), "max_rel_err_vs_fp64_dft": float("%.3g" % rel),
+           "mean_rounds": round(float(np.mean(rounds)), 2), "max_rounds": int(np.max(rounds)),
+           "direct_k_point_fft": {"ms_per_batch": round(ms_direct, 5),
+                                  "DFTs_per_s": round(S / (ms_direct * 1e-3), 1),
+                                  "what": "torch.fft.fft over [512, 256] complex64 (rocFFT)"},
+           "sfft_over_direct_time": round(ms / ms_direct, 1)}
+    plan.close()
+    return rec
+
+
 def oracle_params(desc, seed):
     from oracle.params import SfftParams
     return SfftParams(n=desc.n, k=desc.k, B=desc.B, w=desc.w, seed=seed, alpha=desc.alpha, delta=desc.delta,
@@ -314,8 +400,9 @@ def main():
     ap.add_argument("--tune-out", default="", help="also store the autotuner's choice in this JSON file")
     ap.add_argument("--tune-confirm", type=int, default=6,
                     help="fresh batches the fastest accepted candidates must also pass")
-    ap.add_argument("--workload", choices=["c3", "c4"], default="c3",
-                    help="c3: the batched exactly-sparse headline; c4: the general-mode precision split")
+    ap.add_argument("--workload", choices=["c3", "c4", "section5"], default="c3",
+                    help="c3: the batched exactly-sparse headline; c4: the general-mode precision split; "
+                         "section5: k-point DFTs through the n-point sFFT against a direct k-point FFT")
     ap.add_argument("--config-key", action="store_true",
                     help="print the key that names this configuration in the traffic record, then exit")
     args = ap.parse_args()
@@ -338,6 +425,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == "c4":
         print(json.dumps(precision_split_bench(args, torch, dev, sfft, siggen)), flush=True)
+        return
+    if args.workload == "section5":
+        print(json.dumps(section5_bench(args, torch, dev, sfft)), flush=True)
         return
     n, k, S = 1 << args.log2n, args.k, args.signals
     loc_prec = sfft.SFFT_F64 if args.loc_prec == "f64" else sfft.SFFT_F32
