@@ -93,7 +93,7 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *             integer spectra, Algorithm 1)
  *   g_min     smallest window value G'_{-o(i)} a bin value is divided by
  *   rounds    exact: most NoiselessSparseFFTInner rounds (0 = 16); general:
- *             SparseFFT rounds (0 = max(5, ceil(log4 k) + 2))
+ *             SparseFFT rounds (0 = max(7, ceil(log4 k) + 2))
  *   b_min     exact: round r uses B_r = max(B >> r, b_min) bins and a window
  *             of w B_r / B samples (Algorithm 1 shrinks B with k_t = k/2^t);
  *             0 = B/16 (at least 2); b_min = B keeps B fixed

@@ -108,13 +108,15 @@ def test_general_mode_measurement_limits():
     assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
 
 
-def test_general_default_rounds_grow_with_k():
-    # rounds 0 = max(5, ceil(log4 k) + 2): k = 1024 -> 7 rounds, so 10 measurements per round exceed 64
+def test_general_default_rounds():
+    # rounds 0 = max(7, ceil(log4 k) + 2): 7 rounds up to k = 1024, so 10 measurements per round exceed 64
     d = sfft.sfft_desc_init(1 << 22, 1024, 4096, 0, 7)
     d.mode = sfft.SFFT_MODE_GENERAL
     d.R_est = 9
     assert sfft.sfft_validate_params(d) == sfft.SFFT_OK       # 7 * 9 = 63
     d.R_est = 10
     assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL   # 70
-    d.k, d.B = 64, 1024
-    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK       # 5 rounds * 10
+    d.k, d.B = 8, 1024
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL   # still 7 rounds at small k
+    d.rounds = 6
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK       # 6 * 10 given explicitly

@@ -34,8 +34,18 @@ def make_signal(torch, dev, n, k, seed, mode):
     return x, sup, val, torch.from_numpy(x).to(dev)
 
 
+def default_rounds(d):
+    """The mode's round count for rounds = 0: 16 (exact), max(7, ceil(log4 k) + 2) (general)."""
+    if d.mode == EXACT:
+        return 16
+    l4 = 0
+    while 4 ** l4 < d.k:
+        l4 += 1
+    return max(7, l4 + 2)
+
+
 def oracle_for(d, seed):
-    rounds = d.rounds or (16 if d.mode == EXACT else 5)     # 0 = the mode's default
+    rounds = d.rounds or default_rounds(d)
     return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=seed, alpha=d.alpha, delta=d.delta, theta=d.theta,
                       g_min=d.g_min, rounds=rounds, b_min=d.b_min, patience=d.patience, stop_count=d.stop_count,
                       stop_patience=d.stop_patience, ratio_tol=d.ratio_tol, cap=d.cap, t=d.t,
