@@ -146,9 +146,31 @@ def serving_bench(args, torch, dev, sfft):
                 del worst[4:]
         return exact_ok, exact_n, noisy_err
 
+    def tail_classes(reqs, outs):
+        """The slowest 1% of a phase's requests, by (n, mode, path): count,
+        mean service and queue time, mean k."""
+        lat = np.array([res.latency_ms for (_, _, res) in outs])
+        cut = percentile(lat.tolist(), 99)
+        groups = {}
+        for (n, mode, j, seed), (_, _, res) in zip(reqs, outs):
+            if res.latency_ms < cut:
+                continue
+            key = "2^%d %s %s" % (n.bit_length() - 1, "exact" if mode == sfft.SFFT_MODE_EXACT else "general",
+                                  "dense" if res.path else "sparse")
+            g = groups.setdefault(key, [0, 0.0, 0.0, 0])
+            g[0] += 1
+            g[1] += res.service_ms
+            g[2] += res.queue_ms
+            g[3] += pool[(n, mode)][j][3]
+        rows = [{"class": key, "count": c, "service_ms": round(sv / c, 3), "queue_ms": round(qu / c, 3),
+                 "mean_k": round(kk / c)} for key, (c, sv, qu, kk) in groups.items()]
+        return sorted(rows, key=lambda r: -r["count"])[:6]
+
     # warm-up: every (n, mode, pool entry) once, so every shape's plans are resident
     warm = [(n, mode, j, 1 + j) for (n, mode) in pool for j in range(4)]
     run(warm)
+    warm_instances = int(srv.stats().instances)
+    log("serving: warm-up left %d resident instances for %d pool signals" % (warm_instances, len(warm)))
     srv.reset_stats()
     # saturated: capacity
     reqs = draw(args.serve_requests)
@@ -167,19 +189,21 @@ def serving_bench(args, torch, dev, sfft):
         outs, lag = run(reqs, arrivals)
         st = srv.stats()
         o, nn, e = recovery(reqs, outs)
+        tail = tail_classes(reqs, outs)
         ok_p, n_p, err_p = ok_p + o, n_p + nn, err_p + e
         peak, evict, failed = max(peak, int(st.peak_bytes)), evict + int(st.evictions), failed + int(st.failed)
         sweep.append({"load": load, "arrival_rate_per_s": round(rate, 1), "sFFTs_per_s": round(st.rate, 1),
                       "p50_ms": round(st.p50_ms, 3), "p99_ms": round(st.p99_ms, 3),
                       "queue_p50_ms": round(st.queue_p50_ms, 3), "service_p50_ms": round(st.service_p50_ms, 3),
                       "mean_batch": round(st.mean_batch, 2), "dense_fallback": int(st.dense),
-                      "max_submit_lag_ms": round(lag * 1e3, 3)})
+                      "max_submit_lag_ms": round(lag * 1e3, 3), "slowest_1pct": tail})
         log("serving: Poisson %.0f/s (%.2f x capacity) -> p50 %.3f ms p99 %.3f ms, %.0f sFFTs/s"
             % (rate, load, st.p50_ms, st.p99_ms, st.rate))
     srv.close()
     err_all = err_s + err_p
     mid = sweep[len(sweep) // 2]
     return {"requests_per_phase": len(reqs), "slots": args.serve_slots, "instances": args.serve_instances,
+            "resident_instances_after_warmup": warm_instances,
             "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default"),
             "capacity_sFFTs_per_s": round(capacity, 1),
             "value": mid["sFFTs_per_s"], "unit": "sFFTs/s", "load": mid["load"],

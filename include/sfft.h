@@ -180,6 +180,15 @@ typedef struct sfft_plan_s* sfft_plan_t;
  * buffers); 0 when *d does not validate.  Pure host function. */
 uint64_t sfft_plan_device_bytes(const sfft_plan_desc_t* d);
 
+/* Samples of x one signal's sparse transform under *d gathers, counting
+ * every hashing's window: exact mode, the pair of each round up to the
+ * earliest stop (round group 0: w_r + 1 samples per round); general mode,
+ * all rounds, each with its LocateInner pairs (2 w_r per pair) and
+ * EstimateValues hashings (w_r each).  Each sample is a random access that
+ * costs a whole memory line, so this against n sizes the sparse path
+ * against a dense FFT.  0 when *d does not validate.  Pure host function. */
+uint64_t sfft_plan_samples(const sfft_plan_desc_t* d);
+
 /* Fill *d with the defaults for (n, k, B, w, seed); exact mode, complex64.
  * Pure host function: no device is touched.  Errors: SFFT_EINVAL if d is NULL. */
 sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32_t B,
@@ -341,9 +350,11 @@ uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
  *     (at least 8), B = 4k' (exact) or 16k' (general) within [64 or 256,
  *     min(4096, n/16)], the default window for the mode's delta; exact shapes
  *     use b_min = max(32, B/32) (at most B), at most 24 rounds and patience 5.  Where that window
- *     would cover the whole signal (w >= n) the request takes the dense path:
- *     a full-length FP32 FFT (hipFFT, loaded on first use) and the k bins of
- *     largest magnitude (exact mode: those above theta/2);
+ *     would cover the whole signal (w >= n), or the sparse plan would gather
+ *     more than SFFT_SERVER_DENSE_SAMPLES_PER_N x n samples per signal
+ *     (sfft_plan_samples), the request takes the dense path: a full-length
+ *     FP32 FFT (hipFFT, loaded on first use) and the k bins of largest
+ *     magnitude (exact mode: those above theta/2);
  *   * each shape gets up to `instances` resident plan instances (workspace
  *     for `slots` signals each), created when needed; idle instances of other
  *     shapes are evicted, least recently used first, when a new one would
@@ -365,6 +376,13 @@ typedef struct sfft_server_s* sfft_server_t;
                                         host timer with no coefficients; admission,
                                         eviction, batching and statistics run as usual
                                         (for testing the scheduler without a GPU)      */
+#define SFFT_SERVER_DENSE_ONLY 0x2u  /* every request takes the dense path            */
+#define SFFT_SERVER_SPARSE_ONLY 0x4u /* every request whose sparse plan validates with
+                                        w < n takes the sparse path, whatever its
+                                        gathered samples (without either flag a shape
+                                        goes dense when its sparse plan gathers more
+                                        than SFFT_SERVER_DENSE_SAMPLES_PER_N x n samples) */
+#define SFFT_SERVER_DENSE_SAMPLES_PER_N 0.5
 
 typedef struct {
     uint64_t budget_bytes;   /* device memory the server may hold (instances)   */
@@ -411,6 +429,24 @@ typedef struct {
     double queue_p50_ms, service_p50_ms;
     double rate;             /* completed per second, first submit -> last completion */
 } sfft_server_stats_t;
+
+/* The serving runtime's dense-path selection, for callers that run their
+ * own full-length FFT (and for tests): of each of `count` spectra spec_dev
+ * [count][n] complex64 (unnormalised FFT outputs), the `cap` bins of
+ * largest magnitude, ties to the smaller index, in ascending index order,
+ * values times `scale` as complex128.  Magnitudes are ranked by the FP32
+ * key fma(re, re, im*im); with keep_above >= 0 only bins whose key exceeds
+ * the FP32 value of (keep_above / scale)^2 are kept (exact mode: theta/2).
+ * n a power of two in [2^10, 2^30], cap in [1, 8192], count >= 1.  Outputs
+ * as in sfft_execute_batch: idx_dev [count][cap], val_dev [count][cap][2],
+ * count_dev [count]; unused slots are zero.  scratch_dev:
+ * sfft_dense_topk_scratch_bytes(count) bytes of device memory, overwritten.
+ * Asynchronous on `stream` (a hipStream_t, NULL = the null stream).
+ * Errors: SFFT_EINVAL, SFFT_ENOTPOW2, SFFT_EHIP. */
+uint64_t sfft_dense_topk_scratch_bytes(uint32_t count);
+sfft_status_t sfft_dense_topk(const void* spec_dev, uint64_t n, uint32_t count, uint32_t cap, double scale,
+                              double keep_above, uint64_t* idx_dev, double* val_dev, uint32_t* count_dev,
+                              void* scratch_dev, void* stream);
 
 /* Defaults: 16 GiB budget, 32 slots, 2 instances per shape, device 0,
  * delta 1e-9 (exact) / 1e-6 (general), theta 0.25.  Errors: SFFT_EINVAL. */

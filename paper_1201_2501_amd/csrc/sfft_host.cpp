@@ -877,6 +877,26 @@ uint64_t sfft_plan_device_bytes(const sfft_plan_desc_t* desc) {
     return p.device_bytes;
 }
 
+uint64_t sfft_plan_samples(const sfft_plan_desc_t* desc) {
+    if (!desc) return 0;
+    sfft_plan_desc_t d = *desc;
+    if (resolve_and_validate(d) != SFFT_OK || d.w < d.B || d.w % d.B) return 0;
+    sfft_plan_s p;
+    p.d = d;
+    p.dry = true;
+    if (build_plan(&p) != SFFT_OK) return 0;
+    uint64_t samples = 0;
+    if (general_mode(&p)) {
+        // every round: nlev * R_loc location pairs and R_est estimation hashings
+        for (uint32_t r = 0; r < p.R; ++r)
+            samples += (2ull * p.groundv[r].nloc + d.R_est) * p.geom[r].w;
+    } else {
+        // the pair of each round of group 0 (the rounds before the earliest stop)
+        for (uint32_t r = 0; r < p.group_end[0]; ++r) samples += p.geom[r].w + 1;
+    }
+    return samples;
+}
+
 sfft_status_t sfft_plan(uint64_t n, uint32_t k, uint32_t B, uint64_t w, uint64_t seed, sfft_plan_t* out) {
     sfft_plan_desc_t d;
     sfft_desc_init(&d, n, k, B, w, seed);

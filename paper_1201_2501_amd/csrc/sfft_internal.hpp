@@ -199,11 +199,14 @@ bool h2b_threads_ok(uint32_t threads);
 size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax);
 
 // dense path (sfft_dense.hip): top `cap` bins by magnitude of `count`
-// spectra [count][n] complex64, ascending index, values * scale in
-// complex128; with keep_half_theta > 0 only magnitudes above it are kept.
+// spectra [count][n] complex64 (n a power of two >= 2^10), ascending index,
+// values * scale in complex128; with keep_above >= 0 only magnitudes
+// (times scale) above it are kept.  scratch: dense_topk_scratch_bytes(count)
+// of device memory, overwritten.
+size_t dense_topk_scratch_bytes(uint32_t count);
 hipError_t launch_dense_topk(const float2* spec, uint64_t n, uint32_t count, uint32_t cap, double scale,
                              double keep_above, uint64_t* out_idx, double* out_val, uint32_t* out_count,
-                             hipStream_t s);
+                             uint32_t* scratch, hipStream_t s);
 
 }  // namespace sfft
 

@@ -4,13 +4,16 @@
 //  * Shapes.  A request (n, k, mode) maps to a plan shape: k rounded up to a
 //    power of two (at least 8), B from that k, the default window for the
 //    mode's delta.  Where that window would cover the whole signal (w >= n)
-//    the request takes the dense path (full-length FFT + top-k).
+//    the request takes the dense path (full-length FFT + top-k), as it does
+//    where the sparse plan would gather more than half a sample per bin.
 //  * Instances.  Each shape gets up to `instances` resident plan instances
 //    (window tables, workspace for `slots` signals, a stream and pinned
 //    staging), created on demand and kept; idle instances are evicted in
 //    least-recently-used order when a new one would exceed the device-memory
 //    budget.  Sizes come from sfft_plan_device_bytes before anything is
-//    allocated, so the budget is never exceeded.
+//    allocated, so the budget is never exceeded.  An instance is built on a
+//    thread of its own (building a dense-path instance warms its FFT plans
+//    and takes up to tens of milliseconds): only its shape's requests wait.
 //  * Scheduling.  One host thread takes, for every shape with waiting
 //    requests (oldest first), an idle instance and up to `slots` of its
 //    requests, and enqueues that batch on the instance's stream: batches of
@@ -89,6 +92,14 @@ sfft_status_t shape_for(uint64_t n, uint32_t k, int32_t mode, const sfft_server_
     d->max_batch = sd.slots;
     d->w = sfft_default_w(n, (uint32_t)B, d->alpha, d->delta);
     *dense = d->w >= n || sfft_validate_params(d) != SFFT_OK;
+    if (!*dense && !(sd.flags & SFFT_SERVER_SPARSE_ONLY)) {
+        // each gathered sample is a random access costing a whole line, while
+        // the dense path streams the signal: past this many samples per
+        // signal sample the dense FFT is the faster path
+        const uint64_t samples = sfft_plan_samples(d);
+        *dense = samples == 0 || (double)samples > SFFT_SERVER_DENSE_SAMPLES_PER_N * (double)n;
+    }
+    if (sd.flags & SFFT_SERVER_DENSE_ONLY) *dense = 1;
     if (*dense) d->w = n;
     return SFFT_OK;
 }
@@ -164,8 +175,12 @@ struct Instance {
     int32_t dense = 0;
     uint32_t slots = 0, cap = 0;
     sfft_plan_t plan = nullptr;
-    hipfftHandle fft = nullptr;
+    // dense path: FFT plans for batches of 1, 2, 4, ... slots; a batch of m
+    // signals runs as the plans of m's binary digits
+    static constexpr uint32_t kFftPlans = 11;
+    hipfftHandle fft[kFftPlans] = {};
     float2* d_dense = nullptr;      // [slots][n] staging + spectra (dense path)
+    uint32_t* d_topk = nullptr;     // dense path: top-k selection scratch
     hipStream_t stream = nullptr;
     const void** d_xptrs = nullptr;
     uint64_t* d_seeds = nullptr;
@@ -182,6 +197,8 @@ struct Instance {
     size_t bytes = 0;
     bool fake = false;
     bool busy = false;
+    bool building = false;                  // its build thread has not finished
+    sfft_status_t build_status = SFFT_OK;   // what the build returned
     std::vector<Request*> batch;
     Clock::time_point last_used;
 };
@@ -196,12 +213,15 @@ struct sfft_server_s {
     std::map<uint64_t, ShapeInfo> shapes;
     std::mutex mu;
     std::condition_variable cv_sched, cv_done;
+    uint64_t events = 0;   // bumped with every cv_sched notification, so that none is missed
     std::map<uint64_t, std::deque<Request*>> queues;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
     std::vector<std::unique_ptr<Instance>> inst;
     size_t bytes_in_use = 0, peak_bytes = 0;
     uint64_t next_ticket = 1;
     uint32_t pending = 0, inflight = 0;
+    uint32_t builders = 0;   // instance builds in progress
+    std::condition_variable cv_build;
     bool stop = false;
     std::thread th;
     // fake device: batches finish at their due time on this thread
@@ -229,7 +249,7 @@ size_t instance_buffer_bytes(uint32_t slots, uint32_t cap) {
 
 size_t instance_bytes(const sfft_plan_desc_t& d, int32_t dense) {
     const size_t bufs = instance_buffer_bytes(d.max_batch, d.cap);
-    if (dense) return bufs + (size_t)d.max_batch * d.n * sizeof(float2);
+    if (dense) return bufs + (size_t)d.max_batch * d.n * sizeof(float2) + sfft::dense_topk_scratch_bytes(d.max_batch);
     return bufs + sfft_plan_device_bytes(&d);
 }
 
@@ -256,8 +276,9 @@ void destroy_instance(Instance* in) {
     if (in->fake) return;
     if (in->stream) (void)hipStreamSynchronize(in->stream);
     if (in->plan) sfft_destroy(in->plan);
-    if (in->fft) fftlib().destroy(in->fft);
-    for (void* q : {(void*)in->d_dense, (void*)in->d_xptrs, (void*)in->d_seeds, (void*)in->d_idx, (void*)in->d_val,
+    for (hipfftHandle h : in->fft)
+        if (h) fftlib().destroy(h);
+    for (void* q : {(void*)in->d_dense, (void*)in->d_topk, (void*)in->d_xptrs, (void*)in->d_seeds, (void*)in->d_idx, (void*)in->d_val,
                     (void*)in->d_cnt, (void*)in->d_info})
         if (q) (void)hipFree(q);
     for (void* q : {(void*)in->h_xptrs, (void*)in->h_seeds, (void*)in->h_idx, (void*)in->h_val, (void*)in->h_cnt,
@@ -309,9 +330,23 @@ sfft_status_t build_instance(Instance* in) {
         FftLib& f = fftlib();
         if (!f.ok()) return set_last_error(SFFT_EUNSUPPORTED, "dense path needs libhipfft, which could not be loaded");
         SRV_TRY(dmalloc(&in->d_dense, (size_t)S * in->desc.n));
-        if (f.plan1d(&in->fft, (int)in->desc.n, HIPFFT_C2C, (int)S) != HIPFFT_SUCCESS)
-            return set_last_error(SFFT_EHIP, "hipfftPlan1d failed");
-        if (f.set_stream(in->fft, in->stream) != HIPFFT_SUCCESS) return set_last_error(SFFT_EHIP, "hipfftSetStream failed");
+        SRV_TRY(dmalloc(&in->d_topk, sfft::dense_topk_scratch_bytes(S) / sizeof(uint32_t)));
+        for (uint32_t b = 0; b < Instance::kFftPlans && (1u << b) <= S; ++b) {
+            if (f.plan1d(&in->fft[b], (int)in->desc.n, HIPFFT_C2C, (int)(1u << b)) != HIPFFT_SUCCESS)
+                return set_last_error(SFFT_EHIP, "hipfftPlan1d failed");
+            if (f.set_stream(in->fft[b], in->stream) != HIPFFT_SUCCESS)
+                return set_last_error(SFFT_EHIP, "hipfftSetStream failed");
+        }
+        // A plan's first execution loads its kernels and sets up its work
+        // space; run each once now so that no request's service time (and no
+        // other shape's launch, the scheduler being one thread) pays for it.
+        SRV_HIP(hipMemsetAsync(in->d_dense, 0, (size_t)S * in->desc.n * sizeof(float2), in->stream));
+        for (uint32_t b = 0; b < Instance::kFftPlans && in->fft[b]; ++b) {
+            auto* buf = reinterpret_cast<hipfftComplex*>(in->d_dense);
+            if (f.exec_c2c(in->fft[b], buf, buf, HIPFFT_FORWARD) != HIPFFT_SUCCESS)
+                return set_last_error(SFFT_EHIP, "hipfftExecC2C failed");
+        }
+        SRV_HIP(hipStreamSynchronize(in->stream));
     } else {
         SRV_TRY(sfft_plan_ex(&in->desc, &in->plan));
     }
@@ -366,6 +401,7 @@ void complete_batch(Instance* in) {
     in->batch.clear();
     in->busy = false;
     in->last_used = now;
+    ++s->events;
     s->cv_sched.notify_all();
     s->cv_done.notify_all();
 }
@@ -394,12 +430,18 @@ sfft_status_t launch_batch(Instance* in) {
         for (uint32_t q = 0; q < m; ++q)
             SRV_HIP(hipMemcpyAsync(in->d_dense + (size_t)q * n, in->h_xptrs[q], n * sizeof(float2),
                                    hipMemcpyDeviceToDevice, st));
-        auto* buf = reinterpret_cast<hipfftComplex*>(in->d_dense);
-        if (fftlib().exec_c2c(in->fft, buf, buf, HIPFFT_FORWARD) != HIPFFT_SUCCESS)
-            return set_last_error(SFFT_EHIP, "hipfftExecC2C failed");
+        // only the m signals of the batch are transformed
+        uint32_t done = 0;
+        for (int b = (int)Instance::kFftPlans - 1; b >= 0; --b) {
+            if (!(m & (1u << b))) continue;
+            auto* buf = reinterpret_cast<hipfftComplex*>(in->d_dense + (size_t)done * n);
+            if (!in->fft[b] || fftlib().exec_c2c(in->fft[b], buf, buf, HIPFFT_FORWARD) != HIPFFT_SUCCESS)
+                return set_last_error(SFFT_EHIP, "hipfftExecC2C failed");
+            done += 1u << b;
+        }
         const double keep = in->desc.mode == SFFT_MODE_EXACT ? 0.5 * in->desc.theta : -1.0;
         SRV_HIP(sfft::launch_dense_topk(in->d_dense, n, m, in->cap, 1.0 / std::sqrt((double)n), keep, in->d_idx,
-                                        in->d_val, in->d_cnt, st));
+                                        in->d_val, in->d_cnt, in->d_topk, st));
     } else {
         SRV_HIP(hipMemcpyAsync(in->d_xptrs, in->h_xptrs, m * sizeof(void*), hipMemcpyHostToDevice, st));
         SRV_HIP(hipMemcpyAsync(in->d_seeds, in->h_seeds, m * sizeof(uint64_t), hipMemcpyHostToDevice, st));
@@ -430,14 +472,41 @@ void fail_requests(sfft_server_s* s, std::vector<Request*>& rs, sfft_status_t st
 // An idle instance for `key`, creating one (and evicting idle instances of
 // other shapes, least recently used first) when the budget allows.  Called
 // with the lock held; returns nullptr when the shape has to wait.
+// Builds one instance on its own thread, then makes it idle (or records the
+// failure, its resources already released) and wakes the scheduler.
+void build_worker(sfft_server_s* s, Instance* in) {
+    if (!in->fake) (void)hipSetDevice(s->d.device);
+    const sfft_status_t st = build_instance(in);
+    if (st != SFFT_OK) destroy_instance(in);
+    std::lock_guard<std::mutex> lock(s->mu);
+    in->building = false;
+    in->build_status = st;
+    if (st == SFFT_OK) {
+        in->busy = false;
+        in->last_used = Clock::now();
+    }
+    --s->builders;
+    ++s->events;
+    s->cv_sched.notify_all();
+    s->cv_build.notify_all();
+}
+
 Instance* instance_for(sfft_server_s* s, uint64_t key, const Request* head, std::unique_lock<std::mutex>& lk,
                        sfft_status_t* hard_fail) {
     uint32_t have = 0;
-    for (auto& up : s->inst)
-        if (up->key == key) {
-            ++have;
-            if (!up->busy) return up.get();
+    for (auto it = s->inst.begin(); it != s->inst.end(); ++it) {
+        Instance* in = it->get();
+        if (in->key != key) continue;
+        if (!in->building && in->build_status != SFFT_OK) {
+            // a failed build (already released): the shape cannot run
+            *hard_fail = in->build_status;
+            s->bytes_in_use -= in->bytes;
+            s->inst.erase(it);
+            return nullptr;
         }
+        ++have;
+        if (!in->busy) return in;
+    }
     if (have >= s->d.instances) return nullptr;
     const ShapeInfo* shape = head->shape;
     const sfft_plan_desc_t& d = shape->desc;
@@ -452,9 +521,15 @@ Instance* instance_for(sfft_server_s* s, uint64_t key, const Request* head, std:
     // device, and the completion callbacks of running batches take the lock.
     std::vector<std::unique_ptr<Instance>> evicted;
     while (s->bytes_in_use + need > s->d.budget_bytes) {
+        // idle instances whose shape has no waiting request (an instance just
+        // built for waiting requests is about to be used)
         auto victim = s->inst.end();
-        for (auto it = s->inst.begin(); it != s->inst.end(); ++it)
-            if (!(*it)->busy && (victim == s->inst.end() || (*it)->last_used < (*victim)->last_used)) victim = it;
+        for (auto it = s->inst.begin(); it != s->inst.end(); ++it) {
+            if ((*it)->busy) continue;
+            const auto q = s->queues.find((*it)->key);
+            if (q != s->queues.end() && !q->second.empty()) continue;
+            if (victim == s->inst.end() || (*it)->last_used < (*victim)->last_used) victim = it;
+        }
         if (victim == s->inst.end()) break;
         s->bytes_in_use -= (*victim)->bytes;
         ++s->evictions;
@@ -478,24 +553,21 @@ Instance* instance_for(sfft_server_s* s, uint64_t key, const Request* head, std:
     in->bytes = need;
     in->fake = (s->d.flags & SFFT_SERVER_FAKE_DEVICE) != 0;
     in->busy = true;   // reserved while it is built
+    in->building = true;
     Instance* raw = in.get();
     s->inst.push_back(std::move(in));
     s->bytes_in_use += need;
     s->peak_bytes = std::max(s->peak_bytes, s->bytes_in_use);
-    lk.unlock();
-    const sfft_status_t st = build_instance(raw);
-    if (st != SFFT_OK) destroy_instance(raw);
-    lk.lock();
-    if (st != SFFT_OK) {
+    ++s->builders;
+    try {
+        std::thread(build_worker, s, raw).detach();
+    } catch (...) {
+        --s->builders;
         s->bytes_in_use -= need;
-        s->inst.erase(std::find_if(s->inst.begin(), s->inst.end(),
-                                   [&](const std::unique_ptr<Instance>& u) { return u.get() == raw; }));
-        *hard_fail = st;
-        return nullptr;
+        s->inst.pop_back();
+        *hard_fail = SFFT_ENOMEM;
     }
-    raw->busy = false;
-    raw->last_used = Clock::now();
-    return raw;
+    return nullptr;   // the shape's requests wait for the build
 }
 
 // Fake device: completes each batch when its time has come.
@@ -525,6 +597,7 @@ void scheduler(sfft_server_s* s) {
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         if (s->stop && s->pending == 0 && s->inflight == 0) break;
+        const uint64_t seen = s->events;   // events from here on end the wait below
         std::vector<std::pair<Clock::time_point, uint64_t>> order;
         for (auto& kv : s->queues)
             if (!kv.second.empty()) order.emplace_back(kv.second.front()->t_submit, kv.first);
@@ -567,7 +640,7 @@ void scheduler(sfft_server_s* s) {
             }
             launched = true;
         }
-        if (!launched) s->cv_sched.wait(lk);
+        if (!launched) s->cv_sched.wait(lk, [&] { return s->events != seen; });
     }
 }
 
@@ -597,6 +670,22 @@ sfft_status_t sfft_server_desc_init(sfft_server_desc_t* d) {
     return SFFT_OK;
 }
 
+uint64_t sfft_dense_topk_scratch_bytes(uint32_t count) { return sfft::dense_topk_scratch_bytes(count); }
+
+sfft_status_t sfft_dense_topk(const void* spec_dev, uint64_t n, uint32_t count, uint32_t cap, double scale,
+                              double keep_above, uint64_t* idx_dev, double* val_dev, uint32_t* count_dev,
+                              void* scratch_dev, void* stream) {
+    if (!spec_dev || !idx_dev || !val_dev || !count_dev || !scratch_dev || count == 0 || cap == 0 || cap > 8192 ||
+        !(scale > 0))
+        return set_last_error(SFFT_EINVAL, "bad dense top-k arguments");
+    if (!pow2(n) || n < (1ull << 10) || n > (1ull << 30)) return set_last_error(SFFT_ENOTPOW2, "n must be 2^10..2^30");
+    const hipError_t e = sfft::launch_dense_topk(static_cast<const float2*>(spec_dev), n, count, cap, scale, keep_above,
+                                                 idx_dev, val_dev, count_dev, static_cast<uint32_t*>(scratch_dev),
+                                                 static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_last_error(SFFT_EHIP, std::string("dense top-k: ") + hipGetErrorString(e));
+    return SFFT_OK;
+}
+
 sfft_status_t sfft_server_shape(const sfft_server_desc_t* sd, uint64_t n, uint32_t k, int32_t mode,
                                 sfft_plan_desc_t* plan_out, int32_t* dense_out, uint64_t* bytes_out) {
     if (!sd || !plan_out || !dense_out) return set_last_error(SFFT_EINVAL, "NULL argument");
@@ -609,7 +698,9 @@ sfft_status_t sfft_server_create(const sfft_server_desc_t* d, sfft_server_t* out
     if (!d || !out) return set_last_error(SFFT_EINVAL, "NULL argument");
     if (d->slots < 1 || d->slots > 1024 || d->instances < 1 || d->instances > 16 || d->budget_bytes == 0 ||
         !(d->theta > 0) || !(d->delta_exact > 0 && d->delta_exact < 1) ||
-        !(d->delta_general > 0 && d->delta_general < 1) || (d->flags & ~SFFT_SERVER_FAKE_DEVICE) ||
+        !(d->delta_general > 0 && d->delta_general < 1) ||
+        (d->flags & ~(SFFT_SERVER_FAKE_DEVICE | SFFT_SERVER_DENSE_ONLY | SFFT_SERVER_SPARSE_ONLY)) ||
+        ((d->flags & SFFT_SERVER_DENSE_ONLY) && (d->flags & SFFT_SERVER_SPARSE_ONLY)) ||
         !(d->fake_service_ms >= 0))
         return set_last_error(SFFT_EINVAL, "bad server description");
     auto* s = new (std::nothrow) sfft_server_s();
@@ -644,6 +735,7 @@ sfft_status_t sfft_server_submit(sfft_server_t srv, const sfft_request_t* req, u
     srv->queues[r->key].push_back(r.get());
     srv->reqs[r->ticket] = std::move(r);
     ++srv->pending;
+    ++srv->events;
     srv->cv_sched.notify_all();
     return SFFT_OK;
 }
@@ -680,6 +772,7 @@ sfft_status_t sfft_server_cancel(sfft_server_t srv, uint64_t ticket) {
     r->t_done = Clock::now();
     r->done = true;
     srv->cv_done.notify_all();
+    ++srv->events;
     srv->cv_sched.notify_all();
     return SFFT_OK;
 }
@@ -749,15 +842,18 @@ sfft_status_t sfft_server_destroy(sfft_server_t srv) {
     {
         std::lock_guard<std::mutex> lock(srv->mu);
         srv->stop = true;
+        ++srv->events;
         srv->cv_sched.notify_all();
     }
     if (srv->th.joinable()) srv->th.join();
     {
-        std::lock_guard<std::mutex> lock(srv->mu);
+        std::unique_lock<std::mutex> lk(srv->mu);
         srv->cv_fake.notify_all();
+        srv->cv_build.wait(lk, [&] { return srv->builders == 0; });   // builds of canceled requests
     }
     if (srv->fake_th.joinable()) srv->fake_th.join();
-    for (auto& up : srv->inst) destroy_instance(up.get());
+    for (auto& up : srv->inst)
+        if (up->build_status == SFFT_OK) destroy_instance(up.get());   // failed builds are already released
     delete srv;
     return SFFT_OK;
 }

@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsfft.so"
 (SFFT_OK, SFFT_EINVAL, SFFT_ENOTPOW2, SFFT_ENOMEM, SFFT_EBUDGET, SFFT_EHIP, SFFT_ETRUNC, SFFT_EUNSUPPORTED,
  SFFT_EAGAIN, SFFT_ECANCELED) = range(10)
 SFFT_SERVER_FAKE_DEVICE = 0x1
+SFFT_SERVER_DENSE_ONLY = 0x2
+SFFT_SERVER_SPARSE_ONLY = 0x4
+SFFT_SERVER_DENSE_SAMPLES_PER_N = 0.5
 SFFT_MODE_EXACT, SFFT_MODE_GENERAL = 0, 1
 SFFT_C64, SFFT_C128 = 0, 1
 SFFT_F32, SFFT_F64 = 0, 1
@@ -28,9 +31,10 @@ INFO_ROUNDS, INFO_FLAGS, INFO_ZHAT, INFO_LOCATED = range(4)
 EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_plan_ex", "sfft_plan",
            "sfft_plan_get_desc", "sfft_destroy", "sfft_execute", "sfft_execute_batch",
            "sfft_hash_pair_raw", "sfft_plan_timings", "sfft_plan_h2b_bytes", "sfft_plan_round_groups",
-           "sfft_plan_raw_slot", "sfft_plan_device_bytes",
+           "sfft_plan_raw_slot", "sfft_plan_device_bytes", "sfft_plan_samples",
            "sfft_status_string",
            "sfft_last_error", "sfft_splitmix64",
+           "sfft_dense_topk_scratch_bytes", "sfft_dense_topk",
            "sfft_server_desc_init", "sfft_server_shape", "sfft_server_create", "sfft_server_submit",
            "sfft_server_poll", "sfft_server_wait", "sfft_server_cancel", "sfft_server_stats",
            "sfft_server_reset_stats", "sfft_server_destroy"]
@@ -110,9 +114,14 @@ def load():
     lib.sfft_splitmix64.restype = c_uint64
     lib.sfft_plan_device_bytes.argtypes = [POINTER(PlanDesc)]
     lib.sfft_plan_device_bytes.restype = c_uint64
+    lib.sfft_plan_samples.argtypes = [POINTER(PlanDesc)]
+    lib.sfft_plan_samples.restype = c_uint64
     lib.sfft_server_desc_init.argtypes = [POINTER(ServerDesc)]
     lib.sfft_server_shape.argtypes = [POINTER(ServerDesc), c_uint64, c_uint32, c_int32, POINTER(PlanDesc),
                                       POINTER(c_int32), POINTER(c_uint64)]
+    lib.sfft_dense_topk_scratch_bytes.argtypes = [c_uint32]
+    lib.sfft_dense_topk_scratch_bytes.restype = c_uint64
+    lib.sfft_dense_topk.argtypes = [P, c_uint64, c_uint32, c_uint32, c_double, c_double, P, P, P, P, P]
     lib.sfft_server_create.argtypes = [POINTER(ServerDesc), POINTER(P)]
     lib.sfft_server_submit.argtypes = [P, POINTER(Request), POINTER(c_uint64)]
     lib.sfft_server_poll.argtypes = [P, c_uint64, POINTER(RequestResult)]
@@ -348,10 +357,32 @@ def sfft_plan_device_bytes(desc):
     return int(load().sfft_plan_device_bytes(ctypes.byref(desc)))
 
 
+def sfft_plan_samples(desc):
+    return int(load().sfft_plan_samples(ctypes.byref(desc)))
+
+
 def sfft_server_desc_init():
     d = ServerDesc()
     _check(load().sfft_server_desc_init(ctypes.byref(d)), "sfft_server_desc_init")
     return d
+
+
+def dense_topk(spec, cap, scale, keep_above=-1.0, stream=None):
+    """Top-cap bins of each row of spec ([count, n] complex64 device tensor)
+    through sfft_dense_topk; returns device tensors (idx, val, counts)."""
+    import torch
+
+    if spec.dtype != torch.complex64 or spec.dim() != 2 or not spec.is_cuda or not spec.is_contiguous():
+        raise ValueError("spec must be a contiguous [count, n] complex64 device tensor")
+    count, n = spec.shape
+    lib = load()
+    scratch = torch.empty(int(lib.sfft_dense_topk_scratch_bytes(count)), dtype=torch.uint8, device=spec.device)
+    idx = torch.empty((count, cap), dtype=torch.int64, device=spec.device)
+    val = torch.empty((count, cap), dtype=torch.complex128, device=spec.device)
+    cnt = torch.empty(count, dtype=torch.int32, device=spec.device)
+    _check(lib.sfft_dense_topk(spec.data_ptr(), n, count, cap, scale, keep_above, idx.data_ptr(), val.data_ptr(),
+                               cnt.data_ptr(), scratch.data_ptr(), _stream_handle(stream)), "sfft_dense_topk")
+    return idx, val, cnt
 
 
 def sfft_server_shape(sdesc, n, k, mode):

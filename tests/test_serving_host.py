@@ -19,8 +19,10 @@ def test_server_desc_defaults():
 @pytest.mark.parametrize("n,k,mode,B,dense", [
     (1 << 22, 256, sfft.SFFT_MODE_EXACT, 1024, False),
     (1 << 22, 200, sfft.SFFT_MODE_EXACT, 1024, False),     # k rounded up to 256
-    (1 << 20, 64, sfft.SFFT_MODE_GENERAL, 1024, False),
+    (1 << 22, 8, sfft.SFFT_MODE_GENERAL, 256, False),
+    (1 << 20, 64, sfft.SFFT_MODE_GENERAL, 1024, True),     # gathers 4.9 samples per bin
     (1 << 24, 1024, sfft.SFFT_MODE_EXACT, 4096, False),
+    (1 << 20, 1024, sfft.SFFT_MODE_EXACT, 4096, True),     # gathers 0.8 samples per bin
     (1 << 16, 1024, sfft.SFFT_MODE_EXACT, 4096, True),     # window longer than the signal
     (1 << 16, 8, sfft.SFFT_MODE_EXACT, 64, False),
     (1 << 16, 200, sfft.SFFT_MODE_GENERAL, 4096, True),
@@ -32,14 +34,63 @@ def test_server_shape_policy(n, k, mode, B, dense):
     assert d.k == kb and d.cap == kb and d.B == B and d.mode == mode and d.max_batch == sd.slots
     delta = sd.delta_exact if mode == sfft.SFFT_MODE_EXACT else sd.delta_general
     w = default_w(n, B, 0.5, delta)
-    assert is_dense == dense == (w >= n)
+    assert is_dense == dense
+    if w < n:
+        # the sparse plan's gathered samples decide against half a sample per bin
+        sparse = sfft.PlanDesc.from_buffer_copy(d)
+        sparse.w = w
+        samples = sfft.sfft_plan_samples(sparse)
+        assert samples > 0 and dense == (samples > sfft.SFFT_SERVER_DENSE_SAMPLES_PER_N * n)
     if not dense:
         assert d.w == w
         # one instance = the plan's workspace + the server's staging buffers
         staging = sd.slots * (8 + 8 + kb * 8 + kb * 16 + 4 + 16)
         assert nbytes == sfft.sfft_plan_device_bytes(d) + staging
     else:
-        assert nbytes >= sd.slots * n * 8
+        assert d.w == n and nbytes >= sd.slots * n * 8
+
+
+def test_server_flags_force_a_path():
+    n, k = 1 << 20, 64
+    sd = sfft.sfft_server_desc_init()
+    sd.flags = sfft.SFFT_SERVER_SPARSE_ONLY
+    assert not sfft.sfft_server_shape(sd, n, k, sfft.SFFT_MODE_GENERAL)[1]
+    assert sfft.sfft_server_shape(sd, 1 << 16, 1024, sfft.SFFT_MODE_EXACT)[1]    # w >= n: dense anyway
+    sd.flags = sfft.SFFT_SERVER_DENSE_ONLY
+    assert sfft.sfft_server_shape(sd, 1 << 24, 8, sfft.SFFT_MODE_EXACT)[1]
+
+
+def level_count(n, B_r, t=16):
+    """LocateInner levels: region widths n/B_r, shrinking by t/4, while above 1."""
+    W, lev = n // B_r, 0
+    while W > 1:
+        lev += 1
+        W = W * 4 / t
+    return lev
+
+
+def test_plan_samples_closed_forms():
+    # exact: the pair of each round of group 0 (rounds up to the first at b_min
+    # bins, plus patience + 1), w_r + 1 samples each
+    d = sfft.sfft_desc_init(1 << 20, 64, 256, 24576)
+    d.b_min, d.patience, d.rounds = 32, 5, 24
+    Bs = [max(256 >> r, 32) for r in range(24)]
+    first_floor = next(r for r in range(23) if Bs[r + 1] == Bs[r])
+    expect = sum(24576 // 256 * Bs[r] + 1 for r in range(first_floor + 5 + 1))
+    assert sfft.sfft_plan_samples(d) == expect == 61449
+    # general: every round's LocateInner pairs and EstimateValues hashings
+    n, B, w = 1 << 18, 256, 15872
+    g = sfft.sfft_desc_init(n, 8, B, w)
+    g.mode = sfft.SFFT_MODE_GENERAL
+    g.rounds = 7
+    expect = 0
+    for r in range(7):
+        k_r = max(1, 8 >> (2 * r))
+        B_r = min(B, max(B >> r, 1 << (4 * k_r - 1).bit_length()))
+        expect += (2 * level_count(n, B_r) * g.R_loc + g.R_est) * (w // B * B_r)
+    assert sfft.sfft_plan_samples(g) == expect == 1285880
+    bad = sfft.sfft_desc_init(1 << 20, 64, 500)
+    assert sfft.sfft_plan_samples(bad) == 0
 
 
 def test_plan_device_bytes_scales_with_batch_and_rejects_bad_descs():
@@ -56,7 +107,8 @@ def test_plan_device_bytes_scales_with_batch_and_rejects_bad_descs():
 
 
 @pytest.mark.parametrize("field,value", [("slots", 0), ("instances", 0), ("budget_bytes", 0), ("theta", 0.0),
-                                         ("delta_exact", 1.5), ("delta_general", 0.0), ("instances", 17)])
+                                         ("delta_exact", 1.5), ("delta_general", 0.0), ("instances", 17),
+                                         ("flags", 0x6), ("flags", 0x8)])
 def test_server_create_rejects_bad_descs(field, value):
     lib = sfft.load()
     d = sfft.sfft_server_desc_init()
