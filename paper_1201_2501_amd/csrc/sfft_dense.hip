@@ -103,13 +103,16 @@ __global__ void __launch_bounds__(kTk) k_topk_hist(const float2* __restrict__ sp
 // One workgroup per spectrum: the digit of this pass (from the top, the
 // bucket holding the need-th largest matching key), then a cleared histogram.
 __global__ void __launch_bounds__(kTk) k_topk_select(uint32_t* scratch, uint32_t shift) {
+    __shared__ uint32_t hist[256];
     uint32_t* sc = scratch + (size_t)blockIdx.x * kTkStride;
     if (sc[kTkState + ST_ALL]) return;
+    hist[threadIdx.x] = sc[kTkHist + threadIdx.x];   // one coalesced load, then the walk in LDS
+    __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t need = sc[kTkState + ST_NEED];
         uint32_t acc = 0, digit = 0;
         for (int d = 255; d >= 0; --d) {
-            const uint32_t h = sc[kTkHist + d];
+            const uint32_t h = hist[d];
             if (acc + h >= need) {
                 digit = (uint32_t)d;
                 break;
@@ -219,6 +222,8 @@ __global__ void __launch_bounds__(kTk) k_topk_write(const float2* __restrict__ s
         const uint32_t k = mag_bits(v);
         const bool gt = k > s.T && (keep_all || k > KT);
         const bool eq = k == s.T;
+        // a tile with no bin at or above T moves no counter: skip its scans
+        if (!__syncthreads_or((gt || eq) ? 1 : 0)) continue;
         uint32_t tie_pre;
         const uint32_t tie_tot = block_scan_256(eq ? 1u : 0u, wsum, &tie_pre);
         const bool keep = gt || (eq && eq_keep && eq_before + ties + tie_pre < s.take_eq);

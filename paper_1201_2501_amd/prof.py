@@ -40,7 +40,8 @@ def kernel_source_hash():
 
 
 def short_name(name):
-    name = name.replace("void ", "")
+    """Kernel name without return type, anonymous-namespace marker and arguments."""
+    name = name.replace("void ", "").replace("(anonymous namespace)::", "")
     return name.split("(")[0]
 
 

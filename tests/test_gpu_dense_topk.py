@@ -74,6 +74,12 @@ def test_ties_across_many_chunks_large_n(env):
                               int_spectrum(rng, 1 << 20, -2, 2)], 1024, 1.0 / 1024)
 
 
+def test_largest_chunk_layout(env):
+    # 2^24 bins: 1024 chunks of 16,384; 1,023 planted maxima every 16,411th bin, the first 1,000 taken
+    rng = np.random.default_rng(6)
+    check(env, "2^24", [int_spectrum(rng, 1 << 24, -1, 1, plant_every=16411, plant=2 + 2j)], 1000, 2.0 ** -12)
+
+
 def test_keep_above_filters_on_the_key(env):
     # keys of components in [-2, 2] are 0, 1, 2, 4, 5, 8; the threshold's key is 4.5
     rng = np.random.default_rng(4)
