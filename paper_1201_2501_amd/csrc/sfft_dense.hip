@@ -6,12 +6,13 @@
 // Radix select on the FP32 bit pattern of |X_f|^2 (non-negative floats order
 // as unsigned integers), spread over the chip: each spectrum is cut into nb
 // contiguous chunks, one 256-thread workgroup per chunk.  Four 8-bit passes
-// (histogram of the keys that match the prefix found so far, then one
-// workgroup per spectrum picks the digit) find the key T of the cap-th
-// largest bin and how many bins equal to T are taken (the smallest indices).
-// Then every chunk counts the bins it keeps, one workgroup per spectrum scans
-// the counts into output offsets, and every chunk writes its kept bins in
-// index order.  Kept: key > T, and the first take_eq bins with key == T;
+// (each a histogram of the keys that match the prefix found so far; the
+// next pass's workgroups, and after the last one the counting workgroups,
+// first walk that histogram to extend the prefix) find the key T of the
+// cap-th largest bin and how many bins equal to T are taken (the smallest
+// indices).  Then every chunk counts the bins it keeps, one workgroup per
+// spectrum scans the counts into output offsets, and every chunk writes its
+// kept bins in index order.  Kept: key > T, and the first take_eq bins with key == T;
 // with keep_above >= 0 only bins whose key exceeds that of keep_above.
 #include <cstring>
 
@@ -24,11 +25,14 @@ namespace {
 constexpr uint32_t kTk = 256;              // threads per workgroup
 constexpr uint32_t kTkMaxChunks = 1024;    // chunks per spectrum at most
 constexpr uint32_t kTkMinChunk = 4096;     // bins per chunk at least (when n allows)
-// scratch words per spectrum: histogram, state, per-chunk counts and offsets
-constexpr uint32_t kTkHist = 0, kTkState = 256, kTkCnt = 264, kTkOff = kTkCnt + 2 * kTkMaxChunks;
+// scratch words per spectrum: the four passes' histograms; the selection
+// state after 0..4 digits (prefix, mask, need; one slot each, so that no
+// workgroup reads a slot another one is writing); the whole-spectrum flag;
+// per-chunk counts and offsets
+constexpr uint32_t kTkHist = 0, kTkState = 4 * 256, kTkAll = kTkState + 5 * 4, kTkCnt = kTkAll + 4;
+constexpr uint32_t kTkOff = kTkCnt + 2 * kTkMaxChunks;
 constexpr uint32_t kTkStride = kTkOff + 2 * kTkMaxChunks;
-// state words
-constexpr uint32_t ST_PREFIX = 0, ST_MASK = 1, ST_NEED = 2, ST_ALL = 3;
+constexpr uint32_t ST_PREFIX = 0, ST_MASK = 1, ST_NEED = 2;
 
 // The key of a bin, with the rounding spelled out so that every kernel
 // computes the same bits.
@@ -67,25 +71,63 @@ __device__ __forceinline__ uint32_t block_sum_256(uint32_t v, uint32_t* wsum) {
 
 __global__ void __launch_bounds__(kTk) k_topk_init(uint32_t* scratch, uint64_t n, uint32_t cap) {
     uint32_t* sc = scratch + (size_t)blockIdx.x * kTkStride;
-    for (uint32_t d = threadIdx.x; d < 256; d += kTk) sc[kTkHist + d] = 0;
+    for (uint32_t d = threadIdx.x; d < 4 * 256; d += kTk) sc[kTkHist + d] = 0;
     if (threadIdx.x == 0) {
         sc[kTkState + ST_PREFIX] = 0;
         sc[kTkState + ST_MASK] = 0;
         sc[kTkState + ST_NEED] = cap;
-        sc[kTkState + ST_ALL] = (uint64_t)cap >= n ? 1u : 0u;
+        sc[kTkAll] = (uint64_t)cap >= n ? 1u : 0u;
     }
 }
 
-// Histogram of digit (key >> shift) & 255 over the keys of this chunk that
-// match the prefix; one LDS histogram per wave, summed into the spectrum's.
+// The selection state after digit p: the state before it (slot p) extended
+// by the bucket of pass p's histogram that holds the need-th largest
+// matching key.  The histogram is staged in LDS and walked by thread 0;
+// every thread gets the result in st[0..2].
+__device__ void tk_extend(const uint32_t* sc, uint32_t p, uint32_t* walk, uint32_t* st) {
+    walk[threadIdx.x] = sc[kTkHist + 256 * p + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t* before = sc + kTkState + 4 * p;
+        const uint32_t need = before[ST_NEED];
+        uint32_t acc = 0, digit = 0;
+        for (int d = 255; d >= 0; --d) {
+            const uint32_t h = walk[d];
+            if (acc + h >= need) {
+                digit = (uint32_t)d;
+                break;
+            }
+            acc += h;
+        }
+        const uint32_t shift = 24 - 8 * p;
+        st[ST_PREFIX] = before[ST_PREFIX] | (digit << shift);
+        st[ST_MASK] = before[ST_MASK] | (255u << shift);
+        st[ST_NEED] = need - acc;
+    }
+    __syncthreads();
+}
+
+// Pass p: histogram of digit p over the keys of this chunk that match the
+// prefix of digits 0..p-1 (extended here from pass p-1's histogram; chunk 0
+// stores it in slot p); one LDS histogram per wave, summed into the
+// spectrum's histogram of pass p.
 __global__ void __launch_bounds__(kTk) k_topk_hist(const float2* __restrict__ spec, uint64_t n, uint64_t chunk,
-                                                   uint32_t* scratch, uint32_t shift) {
+                                                   uint32_t* scratch, uint32_t p) {
     __shared__ uint32_t hist[kTk / 64][256];
+    __shared__ uint32_t walk[256];
+    __shared__ uint32_t st[3];
     const uint32_t tid = threadIdx.x, wave = tid >> 6;
     const uint32_t sig = blockIdx.y;
     uint32_t* sc = scratch + (size_t)sig * kTkStride;
-    if (sc[kTkState + ST_ALL]) return;
-    const uint32_t prefix = sc[kTkState + ST_PREFIX], mask = sc[kTkState + ST_MASK];
+    if (sc[kTkAll]) return;
+    uint32_t prefix = 0, mask = 0;
+    if (p > 0) {
+        tk_extend(sc, p - 1, walk, st);
+        prefix = st[ST_PREFIX];
+        mask = st[ST_MASK];
+        if (blockIdx.x == 0 && tid < 3) sc[kTkState + 4 * p + tid] = st[tid];
+    }
+    const uint32_t shift = 24 - 8 * p;
     for (uint32_t d = tid; d < 256 * (kTk / 64); d += kTk) (&hist[0][0])[d] = 0;
     __syncthreads();
     const float2* x = spec + (size_t)sig * n + (size_t)blockIdx.x * chunk;
@@ -97,52 +139,34 @@ __global__ void __launch_bounds__(kTk) k_topk_hist(const float2* __restrict__ sp
     uint32_t c = 0;
 #pragma unroll
     for (uint32_t w = 0; w < kTk / 64; ++w) c += hist[w][tid];
-    if (c) atomicAdd(&sc[kTkHist + tid], c);
-}
-
-// One workgroup per spectrum: the digit of this pass (from the top, the
-// bucket holding the need-th largest matching key), then a cleared histogram.
-__global__ void __launch_bounds__(kTk) k_topk_select(uint32_t* scratch, uint32_t shift) {
-    __shared__ uint32_t hist[256];
-    uint32_t* sc = scratch + (size_t)blockIdx.x * kTkStride;
-    if (sc[kTkState + ST_ALL]) return;
-    hist[threadIdx.x] = sc[kTkHist + threadIdx.x];   // one coalesced load, then the walk in LDS
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t need = sc[kTkState + ST_NEED];
-        uint32_t acc = 0, digit = 0;
-        for (int d = 255; d >= 0; --d) {
-            const uint32_t h = hist[d];
-            if (acc + h >= need) {
-                digit = (uint32_t)d;
-                break;
-            }
-            acc += h;
-        }
-        sc[kTkState + ST_PREFIX] |= digit << shift;
-        sc[kTkState + ST_MASK] |= 255u << shift;
-        sc[kTkState + ST_NEED] = need - acc;
-    }
-    __syncthreads();
-    sc[kTkHist + threadIdx.x] = 0;
+    if (c) atomicAdd(&sc[kTkHist + 256 * p + tid], c);
 }
 
 struct TkSel {
     uint32_t T, take_eq;
 };
 
+// The final selection (slot 4, stored by the counting kernel).
 __device__ __forceinline__ TkSel tk_selection(const uint32_t* sc) {
-    if (sc[kTkState + ST_ALL]) return {0u, 0xFFFFFFFFu};
-    return {sc[kTkState + ST_PREFIX], sc[kTkState + ST_NEED]};
+    if (sc[kTkAll]) return {0u, 0xFFFFFFFFu};
+    return {sc[kTkState + 16 + ST_PREFIX], sc[kTkState + 16 + ST_NEED]};
 }
 
-// Per chunk: bins above T that are kept, and bins equal to T.
+// Per chunk: bins above T that are kept, and bins equal to T (T and the
+// ties to take from the last pass's histogram; chunk 0 stores them).
 __global__ void __launch_bounds__(kTk) k_topk_count(const float2* __restrict__ spec, uint64_t n, uint64_t chunk,
                                                     uint32_t* scratch, uint32_t keep_all, uint32_t KT) {
     __shared__ uint32_t wsum[kTk / 64];
+    __shared__ uint32_t walk[256];
+    __shared__ uint32_t st[3];
     const uint32_t sig = blockIdx.y;
     uint32_t* sc = scratch + (size_t)sig * kTkStride;
-    const TkSel s = tk_selection(sc);
+    TkSel s = {0u, 0xFFFFFFFFu};
+    if (!sc[kTkAll]) {
+        tk_extend(sc, 3, walk, st);
+        s = {st[ST_PREFIX], st[ST_NEED]};
+        if (blockIdx.x == 0 && threadIdx.x < 3) sc[kTkState + 16 + threadIdx.x] = st[threadIdx.x];
+    }
     const float2* x = spec + (size_t)sig * n + (size_t)blockIdx.x * chunk;
     uint32_t gt = 0, eq = 0;
     for (uint64_t f = threadIdx.x; f < chunk; f += kTk) {
@@ -264,11 +288,8 @@ hipError_t launch_dense_topk(const float2* spec, uint64_t n, uint32_t count, uin
     uint32_t KT;
     std::memcpy(&KT, &kt, sizeof(KT));
     hipLaunchKernelGGL(k_topk_init, dim3(count), dim3(kTk), 0, s, scratch, n, cap);
-    for (int pass = 0; pass < 4; ++pass) {
-        const uint32_t shift = 24 - 8 * pass;
-        hipLaunchKernelGGL(k_topk_hist, dim3(nb, count), dim3(kTk), 0, s, spec, n, chunk, scratch, shift);
-        hipLaunchKernelGGL(k_topk_select, dim3(count), dim3(kTk), 0, s, scratch, shift);
-    }
+    for (uint32_t pass = 0; pass < 4; ++pass)
+        hipLaunchKernelGGL(k_topk_hist, dim3(nb, count), dim3(kTk), 0, s, spec, n, chunk, scratch, pass);
     hipLaunchKernelGGL(k_topk_count, dim3(nb, count), dim3(kTk), 0, s, spec, n, chunk, scratch, keep_all, KT);
     hipLaunchKernelGGL(k_topk_scan, dim3(count), dim3(kTk), 0, s, scratch, nb, cap, keep_all, KT, out_idx, out_val,
                        out_count);
