@@ -398,6 +398,9 @@ def main():
                     help="stop after --stop-patience empty rounds once this many entries are found (with --tune "
                          "off; 0 = off)")
     ap.add_argument("--stop-patience", type=int, default=2)
+    ap.add_argument("--alpha-decay", type=float, default=0.0,
+                    help="alpha_t schedule on top of the chosen plan: alpha shrinks by this factor per round "
+                         "while B shrinks (0: fixed alpha)")
     ap.add_argument("--loc-prec", choices=["f32", "f64"], default="f64",
                     help="arithmetic of the location pair's fold and FFT (FP64: the phase step 2 pi / n at "
                          "n = 2^22 is near FP32 resolution)")
@@ -497,6 +500,8 @@ def main():
             tune_rec = res.as_dict()
     w = args.w or sfft.sfft_default_w(n, B, tuned.get("alpha", 0.5), tuned.get("delta", 1e-9))
     plan_kw = dict(base_kw, **tuned, max_batch=S, flags=sfft.SFFT_FLAG_TIMING)
+    if args.alpha_decay:
+        plan_kw["alpha_decay"] = args.alpha_decay
     log("plan: B=%d w=%d %s" % (B, w, ", ".join("%s=%s" % kv for kv in sorted(tuned.items()))))
     plan = Plan(n, k, B, w, 0, **plan_kw)
     desc = plan.desc
@@ -504,6 +509,8 @@ def main():
     # and workgroup size set the gathered samples and the dispatch
     cfg_key = "n=2^%d,k=%d,B=%d,w=%d,b_min=%d,g0=%d,threads=%d,signals=%d" % (
         args.log2n, k, B, w, desc.b_min, plan.round_groups()[0], desc.hash_threads, S)
+    if desc.alpha_decay:
+        cfg_key += ",alpha_decay=%g" % desc.alpha_decay
     if args.config_key:
         print(cfg_key)
         plan.close()
@@ -690,6 +697,7 @@ def main():
                    "b_min": desc.b_min or max(2, B >> 4), "patience": desc.patience, "delta": desc.delta,
                    "alpha": desc.alpha, "theta": desc.theta, "g_min": desc.g_min,
                    "stop_count": desc.stop_count, "stop_patience": desc.stop_patience, "ratio_tol": desc.ratio_tol,
+                   "alpha_decay": desc.alpha_decay, "samples_per_signal_group0": sfft.sfft_plan_samples(desc),
                    "hash_threads": desc.hash_threads, "chunks": chunks, "loc_prec": args.loc_prec,
                    "input": "complex64"},
         "autotune": tune_rec,

@@ -138,6 +138,13 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *             later group twice the previous (0 = 2, 2, 4, 8, ...).  Launch
  *             shape only
  *   reserved  must be 0
+ *   alpha_decay  exact mode: 0 (or 1) keeps alpha in every round; a value
+ *             in (0, 1) shrinks it as the bin count shrinks (Section 3's
+ *             alpha_t schedule): round r uses alpha * alpha_decay^m, m = r
+ *             up to the first round at the smallest bin count and fixed
+ *             after it, with a window w * (B_r / B) / alpha_decay^m rounded
+ *             up to a multiple of B_r (the same tail mass) and its own
+ *             window table.  Every round's window must stay within n.
  */
 typedef struct {
     uint64_t n;
@@ -171,6 +178,7 @@ typedef struct {
     double ratio_tol;
     uint32_t group_step;
     uint32_t reserved;
+    double alpha_decay;
 } sfft_plan_desc_t;
 
 typedef struct sfft_plan_s* sfft_plan_t;

@@ -75,7 +75,7 @@ class ExactResult:
     margins: Margins = field(default_factory=Margins)
 
 
-def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Margins):
+def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Margins, alpha=None):
     """Location and value of bin j of a B-bin hashing; returns (i, v) or None.
     With ratio_tol > 0 a bin whose two hashings differ in magnitude by more
     than that fraction is not decoded: an isolated coefficient gives
@@ -101,7 +101,7 @@ def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Marg
     h, o = bin_offset(i, sigma, b, n, B)
     if h != j:
         return None
-    g = gprime(-o, n, B, p.alpha, p.delta)
+    g = gprime(-o, n, B, p.alpha if alpha is None else alpha, p.delta)
     margins.gmin = min(margins.gmin, abs(g - p.g_min))
     if g < p.g_min:
         return None
@@ -121,12 +121,13 @@ def noiseless_sparse_fft(x, p: SfftParams) -> ExactResult:
         b = draw_b(p.seed, n, r)
         sigma_inv = inverse_mod(sigma, n)
         Br, wr = p.round_bins(r)
-        G = window_time(n, Br, wr, p.alpha, p.delta)
+        ar = p.round_alpha(r)
+        G = window_time(n, Br, wr, ar, p.delta)
         u0_raw = hash_to_bins_raw(x, sigma, 0, b, Br, G)
         u1_raw = hash_to_bins_raw(x, sigma, 1, b, Br, G)
         res.raw.append((sigma, b, u0_raw, u1_raw))
-        u0 = subtract_zhat(u0_raw, zhat, sigma, 0, b, Br, n, p.alpha, p.delta)
-        u1 = subtract_zhat(u1_raw, zhat, sigma, 1, b, Br, n, p.alpha, p.delta)
+        u0 = subtract_zhat(u0_raw, zhat, sigma, 0, b, Br, n, ar, p.delta)
+        u1 = subtract_zhat(u1_raw, zhat, sigma, 1, b, Br, n, ar, p.delta)
         mag = np.abs(u0)
         res.margins.threshold = min(res.margins.threshold, float(np.min(np.abs(mag - p.theta))))
         J = [j for j in range(Br) if mag[j] > p.theta]
@@ -143,7 +144,7 @@ def noiseless_sparse_fft(x, p: SfftParams) -> ExactResult:
         updates = {}
         best = {}
         for j in J:
-            got = decode_bin(u0[j], u1[j], j, sigma, sigma_inv, b, Br, p, res.margins)
+            got = decode_bin(u0[j], u1[j], j, sigma, sigma_inv, b, Br, p, res.margins, ar)
             if got is None:
                 continue
             i, v = got
@@ -169,13 +170,14 @@ def reestimate(zhat, raw, p: SfftParams):
     keys = sorted(zhat)
     out = {}
     per_round = []
-    for (sigma, b, u0_raw, _u1) in raw:
+    for r, (sigma, b, u0_raw, _u1) in enumerate(raw):
         B = len(u0_raw)
+        ar = p.round_alpha(r)
         hg = {}
         members = {}
         for i in keys:
             h, o = bin_offset(i, sigma, b, n, B)
-            hg[i] = (h, gprime(-o, n, B, p.alpha, p.delta))
+            hg[i] = (h, gprime(-o, n, B, ar, p.delta))
             members.setdefault(h, []).append(i)   # ascending index within a bin
         per_round.append((u0_raw, hg, members))
     for i in keys:

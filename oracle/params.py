@@ -37,6 +37,10 @@ ratio_tol  exact mode: decode only bins whose two hashings (shifts 0 and 1) agre
           coefficient gives equal magnitudes (the exact-estimation lemma of
           Section 3); a collision rarely does, and its decode would add a
           wrong entry that later rounds must take back out.
+alpha_decay  exact mode: 0 (or 1) keeps alpha fixed; in (0, 1) round r uses
+          alpha_r = alpha * alpha_decay^m, m = r up to the first round at the
+          smallest bin count (alpha shrinking with B, as the alpha_t schedule
+          of Section 3 does), with its window grown by 1 / alpha_decay^m
 rounds    exact mode: maximum number of NoiselessSparseFFTInner rounds
           general mode: number of SparseFFT rounds
 t, s      LocateInner region count and vote tolerance (Algorithm 3)
@@ -46,6 +50,7 @@ cap       largest output size (defaults to k)
 literal   exact mode only: the paper-literal decode v = round(u_j) for integer
           spectra, without the bin and window checks
 """
+import math
 from dataclasses import dataclass
 
 
@@ -66,6 +71,7 @@ class SfftParams:
     stop_count: int = 0
     stop_patience: int = 2
     ratio_tol: float = 0.0
+    alpha_decay: float = 0.0
     t: int = 16
     s: float = 0.125
     R_loc: int = 3
@@ -73,11 +79,33 @@ class SfftParams:
     cap: int = 0
     literal: bool = False
 
-    def round_bins(self, r):
-        """(B_r, w_r) of exact-mode round r."""
+    def _bins(self, r):
         floor = self.b_min if self.b_min > 0 else max(2, self.B >> 4)
-        Br = max(self.B >> r, min(floor, self.B))
-        return Br, self.w * Br // self.B
+        return max(self.B >> r, min(floor, self.B))
+
+    def _decay_factor(self, r):
+        """alpha_r / alpha: alpha_decay^m, m = r up to the first round at the
+        smallest bin count (1 without decay)."""
+        if not (0.0 < self.alpha_decay < 1.0):
+            return 1.0
+        r_floor = 0
+        while r_floor + 1 < self.rounds and self._bins(r_floor + 1) != self._bins(r_floor):
+            r_floor += 1
+        return self.alpha_decay ** min(r, r_floor)
+
+    def round_bins(self, r):
+        """(B_r, w_r) of exact-mode round r.  With alpha_decay the window
+        grows as alpha_r shrinks (sigma_g scales as B_r / alpha_r), rounded up
+        to a multiple of B_r."""
+        Br = self._bins(r)
+        f = self._decay_factor(r)
+        if f == 1.0:
+            return Br, self.w * Br // self.B
+        return Br, math.ceil((self.w // self.B) / f - 1e-9) * Br
+
+    def round_alpha(self, r):
+        """alpha_r of exact-mode round r (the alpha_t schedule of Section 3)."""
+        return self.alpha * self._decay_factor(r)
 
     @property
     def out_cap(self):

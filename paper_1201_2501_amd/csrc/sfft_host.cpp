@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <utility>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -289,9 +290,15 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     p->capz = zhat_capacity(d);
     p->cap = d.cap;
     std::vector<double> g64;
-    std::vector<uint32_t> seenB;
+    std::vector<std::pair<uint32_t, double>> seenB;   // (B_r, alpha_r) of each window table
     std::vector<uint64_t> seenOfs;
     p->mcap = 4;
+    // exact mode with alpha_decay: alpha shrinks with B up to the first
+    // round at the smallest bin count
+    const bool decay = !general_mode(p) && d.alpha_decay > 0.0 && d.alpha_decay < 1.0;
+    uint32_t r_floor = 0;
+    if (decay)
+        while (r_floor + 1 < p->R && exact_round_bins(d, r_floor + 1) != exact_round_bins(d, r_floor)) ++r_floor;
     for (uint32_t r = 0; r < p->R; ++r) {
         RoundDev g;
         if (general_mode(p)) {
@@ -313,14 +320,22 @@ sfft_status_t build_plan(sfft_plan_s* p) {
             g.B = exact_round_bins(d, r);
         }
         g.logB = log2u(g.B);
+        double alpha_r = d.alpha;
         g.w = d.w / d.B * g.B;
+        if (decay) {
+            const double f = std::pow(d.alpha_decay, (double)std::min(r, r_floor));
+            alpha_r = d.alpha * f;
+            // sigma_g scales as B / alpha: the same tail mass needs w scaled alike
+            g.w = (uint64_t)std::ceil((double)(d.w / d.B) / f - 1e-9) * g.B;
+            if (g.w > d.n) return fail(SFFT_EINVAL, "alpha_decay makes a round's window longer than n");
+        }
         g.t0 = -(int64_t)(g.w / 2);
-        g.ws = window_shape(d.n, g.B, d.alpha, d.delta);
-        auto it = std::find(seenB.begin(), seenB.end(), g.B);
+        g.ws = window_shape(d.n, g.B, alpha_r, d.delta);
+        auto it = std::find(seenB.begin(), seenB.end(), std::make_pair(g.B, alpha_r));
         if (it == seenB.end()) {
             g.gofs = g64.size();
             for (uint64_t u = 0; u < g.w; ++u) g64.push_back(g_star((double)(g.t0 + (int64_t)u), g.ws));
-            seenB.push_back(g.B);
+            seenB.emplace_back(g.B, alpha_r);
             seenOfs.push_back(g.gofs);
         } else {
             g.gofs = seenOfs[it - seenB.begin()];
@@ -802,6 +817,7 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->ratio_tol = 0.0;
     d->group_step = 0;
     d->reserved = 0;
+    d->alpha_decay = 0.0;
     return SFFT_OK;
 }
 
@@ -834,6 +850,9 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (!(d->ratio_tol >= 0.0 && d->ratio_tol < 1.0)) return fail(SFFT_EINVAL, "ratio_tol must be in [0, 1)");
     if (d->group_step > kMaxRounds) return fail(SFFT_EINVAL, "group_step must be in [0, 32]");
     if (d->reserved != 0) return fail(SFFT_EINVAL, "reserved must be 0");
+    if (!(d->alpha_decay >= 0.0 && d->alpha_decay <= 1.0)) return fail(SFFT_EINVAL, "alpha_decay must be in [0, 1]");
+    if (d->mode == SFFT_MODE_GENERAL && d->alpha_decay != 0.0 && d->alpha_decay != 1.0)
+        return fail(SFFT_EINVAL, "alpha_decay applies to exact mode only");
     const uint32_t cap = d->cap ? d->cap : d->k;
     if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");
     if (d->mode == SFFT_MODE_GENERAL) {

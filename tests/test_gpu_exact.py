@@ -39,7 +39,7 @@ def oracle_params(plan, seed=None):
     return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=d.seed if seed is None else seed, alpha=d.alpha,
                       delta=d.delta, theta=d.theta, g_min=d.g_min, rounds=d.rounds, b_min=d.b_min,
                       patience=d.patience, stop_count=d.stop_count, stop_patience=d.stop_patience,
-                      ratio_tol=d.ratio_tol, cap=d.cap)
+                      ratio_tol=d.ratio_tol, alpha_decay=d.alpha_decay, cap=d.cap)
 
 
 RAW_CASES = [
@@ -359,6 +359,66 @@ def test_section5_reduction_k_point_dft(torch_dev, n, k, B):
         expect_val = np.sqrt(n / k) * np.fft.fft(xks[s]) / np.sqrt(k)
         assert np.array_equal(out[s][0], expect_idx)
         assert np.max(np.abs(out[s][1] - expect_val)) <= 1e-9 * np.max(np.abs(expect_val))
+    plan.close()
+
+
+@pytest.mark.parametrize("B_r", [64, 32, 16])
+def test_alpha_decay_raw_bins_match_oracle(torch_dev, B_r):
+    """Each round of the alpha_t schedule hashes with its own alpha_r and
+    window length (the oracle's round_bins / round_alpha): raw pair bins in
+    FP64 against the oracle's HashToBins with that round's window."""
+    torch, dev = torch_dev
+    n, k, B, delta = 1 << 14, 16, 64, 1e-12
+    w = default_w(n, B, 0.5, delta)
+    say("alpha-decay-raw", "n", n, "B", B, "B_r", B_r)
+    plan = plan_for(n, k, B, w, 5, delta=delta, in_dtype=1, loc_prec=1, b_min=16, alpha_decay=0.5)
+    p = oracle_params(plan)
+    r = [p.round_bins(q)[0] for q in range(p.rounds)].index(B_r)
+    Br, wr = p.round_bins(r)
+    assert Br == B_r and wr == w              # B and alpha halve together: the window length stays
+    x, _, _ = siggen.planted_signal(n, 40, 12, np.complex128, noise_ratio=0.01)
+    rng = np.random.default_rng(B_r)
+    sigma, a, b = int(rng.integers(0, n // 2)) * 2 + 1, int(rng.integers(0, n)), int(rng.integers(0, n))
+    u0, u1 = plan.hash_pair_raw(torch.from_numpy(x).to(dev), sigma, a, 1, b, B_r, 1)
+    torch.cuda.synchronize()
+    G = window_time(n, Br, wr, p.round_alpha(r), delta)
+    e0 = hash_to_bins_raw(x, sigma, a, b, Br, G)
+    e1 = hash_to_bins_raw(x, sigma, (a + 1) % n, b, Br, G)
+    scale = max(np.max(np.abs(e0)), np.max(np.abs(e1)))
+    assert np.max(np.abs(u0.cpu().numpy() - e0)) <= 1e-12 * scale
+    assert np.max(np.abs(u1.cpu().numpy() - e1)) <= 1e-12 * scale
+    plan.close()
+
+
+@pytest.mark.parametrize("shape", ["c1", "c3"])
+def test_alpha_decay_batched_matches_oracle(torch_dev, shape):
+    """The alpha_t schedule end to end: n = 2^14, k = 16 in FP64 storage, and
+    the n = 2^22, k = 256 batch shape (alpha 0.75 halving with B down to
+    b_min = 64), against the oracle and the planted supports."""
+    torch, dev = torch_dev
+    if shape == "c1":
+        n, k, B, dtype, delta, count = 1 << 14, 16, 64, np.complex128, 1e-12, 4
+        kw = dict(delta=delta, in_dtype=1, loc_prec=1, b_min=16, alpha_decay=0.5, patience=4)
+        w = default_w(n, B, 0.5, delta)
+    else:
+        n, k, B, dtype, delta, count = 1 << 22, 256, 1024, np.complex64, 1e-8, 2
+        kw = dict(delta=delta, alpha=0.75, loc_prec=1, b_min=64, rounds=24, patience=5, theta=0.01, g_min=0.25,
+                  alpha_decay=0.5)
+        w = default_w(n, B, 0.75, delta)
+    say("alpha-decay", shape, "n", n, "k", k, "B", B, "count", count)
+    plan = plan_for(n, k, B, w, 0, max_batch=count, **kw)
+    xs, sups, seeds = [], [], []
+    for s in range(count):
+        x, sup, _ = siggen.planted_signal(n, k, 700 + s, dtype, magnitude="unit" if shape == "c1" else "loguniform")
+        xs.append(x)
+        sups.append(sup)
+        seeds.append(31 * s + 7)
+    out = run_batch(torch, dev, plan, xs, seeds)
+    for s in range(count):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        assert int(out[s][2][0]) == ref.rounds_used
+        compare(out[s][0], out[s][1], ref)
+        assert np.array_equal(out[s][0], sups[s])
     plan.close()
 
 
