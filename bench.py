@@ -398,6 +398,9 @@ def main():
                     help="stop after --stop-patience empty rounds once this many entries are found (with --tune "
                          "off; 0 = off)")
     ap.add_argument("--stop-patience", type=int, default=2)
+    ap.add_argument("--extra-batches", type=int, default=0,
+                    help="also run the plan on this many fresh batches (generator seeds 5000003 + 512 i + s) "
+                         "and report exact recovery over them")
     ap.add_argument("--alpha-decay", type=float, default=0.0,
                     help="alpha_t schedule on top of the chosen plan: alpha shrinks by this factor per round "
                          "while B shrinks (0: fixed alpha)")
@@ -566,6 +569,31 @@ def main():
     val_all = bufs["val"].cpu().numpy()
     exact_vs_planted = int(sum(np.array_equal(idx_all[s, :counts[s]], supports[s]) for s in range(S)))
 
+    # recovery over fresh batches of the same workload (untimed)
+    extra = None
+    if args.extra_batches > 0:
+        ok_x, n_x, miss_x = 0, 0, []
+        for i in range(args.extra_batches):
+            gs = [5_000_003 + i * S + s for s in range(S)]
+            Xe, sup_e, _ = siggen.torch_planted_batch(n, k, gs, dev, magnitude="loguniform")
+            seeds_e = torch.arange(S, dtype=torch.int64, device=dev) * 6151 + 4099 * (i + 1)
+            be = plan.execute_batch(Xe, seeds_e, bufs=bufs)
+            torch.cuda.synchronize()
+            ce = be["counts"].cpu().numpy()
+            ie = be["idx"].cpu().numpy()
+            for s in range(S):
+                good = np.array_equal(ie[s, :ce[s]], sup_e[s])
+                ok_x += int(good)
+                if not good and len(miss_x) < 8:
+                    miss_x.append({"batch": i, "signal": s, "count": int(ce[s]),
+                                   "missing": len(set(sup_e[s].tolist()) - set(ie[s, :ce[s]].tolist()))})
+            n_x += S
+            del Xe
+        torch.cuda.empty_cache()
+        extra = {"batches": args.extra_batches, "recovered_exactly_vs_planted": "%d/%d" % (ok_x, n_x),
+                 "misses": miss_x, "generator_seeds": "5000003 + %d i + s" % S}
+        log("extra batches: %d/%d supports exact" % (ok_x, n_x))
+
     # roofline of the dominant kernel: the first HashToBins pair launch of a
     # chunk (round group 0, hashed for every signal; later groups only for
     # signals still decoding)
@@ -708,6 +736,7 @@ def main():
         "dense": dense,
         "hbm": hbm,
         "recovered_exactly_vs_planted": "%d/%d" % (exact_vs_planted, S),
+        "fresh_batches": extra,
         "rounds_used_max": int(info[:, 0].max()),
         "rounds": {"groups": groups, "used_p50": float(np.median(rounds_used)),
                    "used_hist": {int(r): int(c) for r, c in zip(*np.unique(rounds_used, return_counts=True))},
