@@ -364,9 +364,11 @@ uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
  *     FP32 FFT (hipFFT, loaded on first use) and the k bins of largest
  *     magnitude (exact mode: those above theta/2);
  *   * each shape gets up to `instances` resident plan instances (workspace
- *     for `slots` signals each), created when needed; idle instances of other
- *     shapes are evicted, least recently used first, when a new one would
- *     exceed `budget_bytes`;
+ *     for `slots` signals each), created when needed, each on a thread of
+ *     its own; idle instances of other shapes with no waiting request are
+ *     evicted, least recently used first, when a new one would exceed
+ *     `budget_bytes` (which counts the library's allocations, not the work
+ *     areas hipFFT allocates for the dense path's plans);
  *   * a scheduler thread batches the waiting requests of each shape (oldest
  *     shape first) onto idle instances, one stream per instance, so batches
  *     of different shapes overlap on the device.
