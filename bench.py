@@ -729,8 +729,9 @@ def main():
                    "hash_threads": desc.hash_threads, "chunks": chunks, "loc_prec": args.loc_prec,
                    "input": "complex64"},
         "autotune": tune_rec,
-        "latency_ms": {"p50": round(percentile(step_ms, 50), 4), "p99": round(percentile(step_ms, 99), 4),
-                       "what": "per batch step (graph replay), HIP events"},
+        "latency_ms": {"p10": round(percentile(step_ms, 10), 4), "p50": round(percentile(step_ms, 50), 4),
+                       "p90": round(percentile(step_ms, 90), 4), "p99": round(percentile(step_ms, 99), 4),
+                       "steps": len(step_ms), "what": "per batch step (graph replay), HIP events"},
         "phases": phases,
         "plain": plain,
         "dense": dense,
