@@ -422,6 +422,30 @@ def test_alpha_decay_batched_matches_oracle(torch_dev, shape):
     plan.close()
 
 
+@pytest.mark.parametrize("alpha_decay", [0.0, 0.7])
+def test_launch_bytes_and_gathered_samples_agree(torch_dev, alpha_decay):
+    """The roofline's algorithmic bytes of the first HashToBins launch and the
+    serving policy's gathered samples count the same rounds: for one signal,
+    bytes = 8 (w_r + 1) summed over round group 0 plus the 2 B_r complex128
+    raw bins of each of those rounds."""
+    from paper_1201_2501_amd import sfft
+    n, k, B = 1 << 22, 256, 1024
+    w = default_w(n, B, 0.75, 1e-8)
+    say("launch-bytes", "alpha_decay", alpha_decay)
+    plan = plan_for(n, k, B, w, 0, delta=1e-8, alpha=0.75, b_min=64, rounds=24, patience=5, group0=12,
+                    alpha_decay=alpha_decay)
+    d = plan.desc
+    samples = sfft.sfft_plan_samples(d)
+    p = oracle_params(plan)
+    g0 = plan.round_groups()[0]
+    assert g0 == 12
+    assert samples == sum(p.round_bins(r)[1] + 1 for r in range(g0))
+    bins = sum(p.round_bins(r)[0] for r in range(g0))
+    assert plan.h2b_bytes(1) == 8 * samples + 32 * bins
+    assert plan.h2b_bytes(512) == 512 * plan.h2b_bytes(1)
+    plan.close()
+
+
 def test_cached_tuned_c3_plan_matches_oracle(torch_dev):
     """The plan the autotuner stored for the n = 2^22, k = 256 batch (the one
     bench.py times) matches the oracle on two signals of that workload."""
