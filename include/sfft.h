@@ -145,6 +145,14 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *             after it, with a window w * (B_r / B) / alpha_decay^m rounded
  *             up to a multiple of B_r (the same tail mass) and its own
  *             window table.  Every round's window must stay within n.
+ *   hash_split  exact mode, batched path: 0 or 1 hashes each (signal,
+ *             round) in one workgroup; 2..64 splits its window over that
+ *             many workgroups (partial folds summed in a fixed order, then
+ *             the FFT), for small batches whose few hashings would each walk
+ *             a long window on one CU.  Launch shape only: results equal the
+ *             unsplit ones up to the order of floating-point additions, and
+ *             do not depend on the batch.  Needs chunks <= 1.
+ *   reserved2 must be 0
  */
 typedef struct {
     uint64_t n;
@@ -179,6 +187,8 @@ typedef struct {
     uint32_t group_step;
     uint32_t reserved;
     double alpha_decay;
+    uint32_t hash_split;
+    uint32_t reserved2;
 } sfft_plan_desc_t;
 
 typedef struct sfft_plan_s* sfft_plan_t;

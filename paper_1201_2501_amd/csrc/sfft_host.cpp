@@ -174,6 +174,7 @@ struct sfft_plan_s {
     // plain-path workspace (one signal)
     double* p_raw = nullptr;
     double* p_partial = nullptr;
+    double* split_partial = nullptr;   // batched split hashing: [count * group rounds][parts][4 Bmax]
     uint32_t p_parts_max = 0;
     uint64_t* p_idx = nullptr;
     double* p_val = nullptr;
@@ -434,6 +435,12 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     ST_TRY(dev_alloc(p, &p->gtmp, S * Z * 4));
     ST_TRY(dev_alloc(p, &p->ecount, S * Z));
     ST_TRY(dev_alloc(p, &p->state, S * kStateWords));
+    if (!general_mode(p) && d.hash_split > 1) {
+        size_t longest = 0;
+        for (size_t g = 0, r0 = 0; g < p->group_end.size(); r0 = p->group_end[g], ++g)
+            longest = std::max<size_t>(longest, p->group_end[g] - r0);
+        ST_TRY(dev_alloc(p, &p->split_partial, S * longest * d.hash_split * 4 * Bm));
+    }
     // plain path (one signal): raw bins of every round, split partials
     p->p_parts_max = 64;
     ST_TRY(dev_alloc(p, &p->p_raw, raw_slots * 4 * Bm));
@@ -685,6 +692,17 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
         }
         return SFFT_OK;
     }
+    // one pair launch, or its split form (hash_split)
+    auto hash = [&](H2BArgs& a) -> sfft_status_t {
+        if (p->d.hash_split > 1) {
+            a.parts = p->d.hash_split;
+            a.partial = p->split_partial;
+            HIP_TRY(launch_h2b_pair_split(a, in_c128(p), loc_f64(p), s));
+        } else {
+            HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
+        }
+        return SFFT_OK;
+    };
     H2BArgs a = base_h2b(p, xc);
     a.xptrs = xpc;
     a.seeds = sc;
@@ -696,7 +714,7 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
         a.round_lo = 0;
         a.nrounds = p->group_end[0];
         a.threads = pair_threads(p, 0, p->group_end[0]);
-        HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
+        ST_TRY(hash(a));
         return SFFT_OK;
     }
     a.state = D.state;
@@ -707,7 +725,7 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
             a.round_lo = r0;
             a.nrounds = r1 - r0;
             a.threads = pair_threads(p, r0, r1);
-            HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
+            ST_TRY(hash(a));
         }
         D.r_begin = r0;
         D.r_end = r1;
@@ -818,6 +836,8 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->group_step = 0;
     d->reserved = 0;
     d->alpha_decay = 0.0;
+    d->hash_split = 0;
+    d->reserved2 = 0;
     return SFFT_OK;
 }
 
@@ -853,6 +873,10 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (!(d->alpha_decay >= 0.0 && d->alpha_decay <= 1.0)) return fail(SFFT_EINVAL, "alpha_decay must be in [0, 1]");
     if (d->mode == SFFT_MODE_GENERAL && d->alpha_decay != 0.0 && d->alpha_decay != 1.0)
         return fail(SFFT_EINVAL, "alpha_decay applies to exact mode only");
+    if (d->reserved2 != 0) return fail(SFFT_EINVAL, "reserved2 must be 0");
+    if (d->hash_split > 64) return fail(SFFT_EINVAL, "hash_split must be in [0, 64]");
+    if (d->hash_split > 1 && (d->mode == SFFT_MODE_GENERAL || d->chunks > 1))
+        return fail(SFFT_EINVAL, "hash_split applies to exact mode with at most one chunk");
     const uint32_t cap = d->cap ? d->cap : d->k;
     if (cap > kMaxZ) return fail(SFFT_EINVAL, "cap must be at most 8192");
     if (d->mode == SFFT_MODE_GENERAL) {

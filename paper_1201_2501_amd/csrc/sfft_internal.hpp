@@ -185,6 +185,9 @@ struct GeneralArgs {
 hipError_t launch_h2b_pair(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s);
 hipError_t launch_h2b_split(const H2BArgs& a, uint32_t round, bool in_c128, bool acc_f64, hipStream_t s);
 hipError_t launch_h2b_reduce(const H2BArgs& a, uint32_t round, bool acc_f64, hipStream_t s);
+// exact batched pair launch split over a.parts workgroups per (signal,
+// round): partials in a.partial ([count * nrounds][parts][4 Bmax] doubles)
+hipError_t launch_h2b_pair_split(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s);
 hipError_t launch_exact_init(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_exact_decode(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s);

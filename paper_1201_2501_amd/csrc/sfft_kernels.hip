@@ -11,6 +11,12 @@
 //  * k_h2b_split     the same accumulation split over many workgroups by
 //                    window range (one signal at a time), partial sums to HBM
 //  * k_h2b_reduce    fixed-order sum of the partials, modulation, FFT
+//  * k_h2b_psplit,   the batched exact pair split over `parts` workgroups per
+//    k_h2b_rsplit    (signal, round) by window range, then one workgroup per
+//                    (signal, round) sums the partials in part order,
+//                    modulates, transforms and stores the raw bins: for small
+//                    batches, where one workgroup per hashing leaves the chip
+//                    idle and a long window is walked by one CU
 // The decoders (exact and general mode) are in sfft_decode.hip.
 #include "sfft_device.hpp"
 
@@ -324,6 +330,106 @@ __global__ void __launch_bounds__(kThreads) k_h2b_reduce(H2BArgs A, uint32_t rou
     store_bins<TA, kThreads>(VA, VB, B, g.logB, A.Bmax, A.beta, tw, A.sqrt_n, out0, out0 + 2 * (uint64_t)A.Bmax);
 }
 
+// Exact batched mode with a split hashing: the (signal, round) of job j of a
+// pair launch (j = round offset * count + signal) and whether its signal has
+// stopped decoding.
+struct SplitJob {
+    uint32_t sig, r;
+    uint64_t sigma, b;
+};
+
+__device__ __forceinline__ bool split_job(const H2BArgs& A, uint32_t job, SplitJob& J) {
+    const uint32_t rr = job / A.count;
+    J.sig = job - rr * A.count;
+    if (A.state && A.state[(uint64_t)J.sig * kStateWords + ST_DONE]) return false;
+    J.r = A.round_lo + rr;
+    const uint64_t seed = A.seeds ? A.seeds[J.sig] : A.plan_seed;
+    J.sigma = draw_sigma(seed, A.n, J.r);
+    J.b = draw_b(seed, A.n, J.r);
+    return true;
+}
+
+// Stage 1: part blockIdx.x of job blockIdx.y accumulates its share of the
+// window's segments (shifts 0 and 1) and writes unmodulated partial folds
+// [job][part][2][B] (complex128, slots of Bmax).
+template <class TIn, class TA>
+__global__ void __launch_bounds__(kThreads) k_h2b_psplit(H2BArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t job = blockIdx.y, part = blockIdx.x;
+    SplitJob J;
+    if (!split_job(A, job, J)) return;
+    const uint64_t n = A.n;
+    const RoundDev g = A.geom[J.r];
+    const TIn* x = A.xptrs ? reinterpret_cast<const TIn*>(A.xptrs[J.sig])
+                           : reinterpret_cast<const TIn*>(A.x) + (uint64_t)J.sig * A.sig_stride;
+    const TA* G = reinterpret_cast<const TA*>(A.gtab) + g.gofs;
+    const uint32_t B = g.B;
+    const uint32_t sub = B >= kThreads ? 1u : kThreads / B;
+    cx<TA>* VA = reinterpret_cast<cx<TA>*>(smem);
+    cx<TA>* VB = VA + sub * B;
+    cx<TA>* M = VB + sub * B;
+    for (uint32_t q = threadIdx.x; q < sub * B; q += kThreads) {
+        VA[q] = cx<TA>{0, 0};
+        VB[q] = cx<TA>{0, 0};
+    }
+    // segments L of the window at shifts 0 and 1, cut into A.parts ranges; the
+    // first and last ranges are open so that the ranges cover every L
+    const int64_t iB = (int64_t)B;
+    const int64_t Lmin = floordiv(g.t0 - 1 - (iB - 1), iB);
+    const int64_t Lmax = floordiv(g.t0 + (int64_t)g.w - 1, iB);
+    const int64_t chunk = (Lmax - Lmin + (int64_t)A.parts) / (int64_t)A.parts;
+    const int64_t lo = part == 0 ? INT64_MIN / 4 : Lmin + (int64_t)part * chunk;
+    const int64_t hi = part + 1 == A.parts ? INT64_MAX / 4 : Lmin + (int64_t)(part + 1) * chunk - 1;
+    accumulate_pair<TIn, TA, kThreads>(x, G, VA, VB, M, n, J.sigma, 0, 1, J.b, B, g.logB, g.w, g.t0, lo, hi, sub);
+    __syncthreads();
+    double* out = A.partial + ((uint64_t)job * A.parts + part) * 4 * (uint64_t)A.Bmax;
+    for (uint32_t r = threadIdx.x; r < B; r += kThreads) {
+        cx<TA> sa = VA[r], sb = VB[r];
+        for (uint32_t p = 1; p < sub; ++p) {
+            sa = cadd(sa, VA[p * B + r]);
+            sb = cadd(sb, VB[p * B + r]);
+        }
+        out[2 * r] = (double)sa.r;
+        out[2 * r + 1] = (double)sa.i;
+        out[2 * B + 2 * r] = (double)sb.r;
+        out[2 * B + 2 * r + 1] = (double)sb.i;
+    }
+}
+
+// Stage 2: one workgroup per job sums its partials in part order, applies
+// the modulation, runs the FFT and stores the job's raw bins.
+template <class TA>
+__global__ void __launch_bounds__(kThreads) k_h2b_rsplit(H2BArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t job = blockIdx.x;
+    SplitJob J;
+    if (!split_job(A, job, J)) return;
+    const RoundDev g = A.geom[J.r];
+    const uint32_t B = g.B;
+    cx<TA>* VA = reinterpret_cast<cx<TA>*>(smem);
+    cx<TA>* VB = VA + B;
+    const auto* tw = reinterpret_cast<const typename TwTraits<TA>::V*>(A.tw);
+    const double* base = A.partial + (uint64_t)job * A.parts * 4 * (uint64_t)A.Bmax;
+    for (uint32_t r = threadIdx.x; r < B; r += kThreads) {
+        double ar = 0, ai = 0, br = 0, bi = 0;
+        for (uint32_t p = 0; p < A.parts; ++p) {
+            const double* q = base + (uint64_t)p * 4 * A.Bmax;
+            ar += q[2 * r];
+            ai += q[2 * r + 1];
+            br += q[2 * B + 2 * r];
+            bi += q[2 * B + 2 * r + 1];
+        }
+        VA[r] = cx<TA>{(TA)ar, (TA)ai};
+        VB[r] = cx<TA>{(TA)br, (TA)bi};
+    }
+    __syncthreads();
+    finalize_folds<TA, kThreads>(VA, VB, A.n, J.sigma, J.b, 1, B, 1);
+    __syncthreads();
+    lds_fft2<TA, kThreads>(VA, VB, B, A.Bmax, tw);
+    double* out0 = A.raw + (((uint64_t)J.sig * A.raw_rounds + J.r) * 2) * (uint64_t)A.Bmax * 2;
+    store_bins<TA, kThreads>(VA, VB, B, g.logB, A.Bmax, 1, tw, A.sqrt_n, out0, out0 + 2 * (uint64_t)A.Bmax);
+}
+
 // ------------------------------------------------------------------ launch --
 bool h2b_threads_ok(uint32_t threads) { return threads == 256 || threads == 512 || threads == 1024; }
 
@@ -375,6 +481,31 @@ hipError_t launch_h2b_split(const H2BArgs& a, uint32_t round, bool in_c128, bool
     if (in_c128) return acc_f64 ? launch_split_t<double2, double>(a, round, lds, s)
                                 : launch_split_t<double2, float>(a, round, lds, s);
     return acc_f64 ? launch_split_t<float2, double>(a, round, lds, s) : launch_split_t<float2, float>(a, round, lds, s);
+}
+
+template <class TIn, class TA>
+static hipError_t launch_psplit_t(const H2BArgs& a, uint32_t jobs, size_t lds, hipStream_t s) {
+    hipError_t e = allow_lds(k_h2b_psplit<TIn, TA>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_h2b_psplit<TIn, TA>), dim3(a.parts, jobs), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_h2b_pair_split(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s) {
+    const uint32_t jobs = a.count * a.nrounds;
+    if (jobs == 0 || jobs > 65535 || a.parts < 2 || !a.partial) return hipErrorInvalidValue;
+    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, acc_f64, kThreads);
+    hipError_t e = in_c128 ? (acc_f64 ? launch_psplit_t<double2, double>(a, jobs, lds, s)
+                                      : launch_psplit_t<double2, float>(a, jobs, lds, s))
+                           : (acc_f64 ? launch_psplit_t<float2, double>(a, jobs, lds, s)
+                                      : launch_psplit_t<float2, float>(a, jobs, lds, s));
+    if (e != hipSuccess) return e;
+    const size_t lds2 = 2 * (size_t)a.Bmax * (acc_f64 ? 16 : 8);
+    e = acc_f64 ? allow_lds(k_h2b_rsplit<double>, lds2) : allow_lds(k_h2b_rsplit<float>, lds2);
+    if (e != hipSuccess) return e;
+    if (acc_f64) hipLaunchKernelGGL((k_h2b_rsplit<double>), dim3(jobs), dim3(kThreads), lds2, s, a);
+    else hipLaunchKernelGGL((k_h2b_rsplit<float>), dim3(jobs), dim3(kThreads), lds2, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_h2b_reduce(const H2BArgs& a, uint32_t round, bool acc_f64, hipStream_t s) {

@@ -120,3 +120,17 @@ def test_general_default_rounds():
     assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL   # still 7 rounds at small k
     d.rounds = 6
     assert sfft.sfft_validate_params(d) == sfft.SFFT_OK       # 6 * 10 given explicitly
+
+
+def test_hash_split_validation():
+    d = sfft.sfft_desc_init(1 << 20, 64, 256)
+    d.hash_split = 8
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK
+    d.hash_split = 65
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
+    d.hash_split, d.chunks = 8, 2
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
+    d.chunks, d.mode = 1, sfft.SFFT_MODE_GENERAL
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
+    d.mode, d.reserved2 = sfft.SFFT_MODE_EXACT, 1
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL

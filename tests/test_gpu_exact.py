@@ -446,6 +446,56 @@ def test_launch_bytes_and_gathered_samples_agree(torch_dev, alpha_decay):
     plan.close()
 
 
+@pytest.mark.parametrize("shape,parts", [("c1", 2), ("c1", 8), ("c3", 4), ("c3", 16)])
+def test_split_hashing_matches_oracle(torch_dev, shape, parts):
+    """hash_split: each (signal, round) hashed by several workgroups over
+    window ranges, partials summed in part order: the same supports and
+    values as the oracle, at n = 2^14 (FP64 storage) and at the n = 2^22,
+    k = 256 batch shape."""
+    torch, dev = torch_dev
+    if shape == "c1":
+        n, k, B, dtype, count = 1 << 14, 16, 64, np.complex128, 4
+        w = default_w(n, B, 0.5, 1e-12)
+        kw = dict(delta=1e-12, in_dtype=1, loc_prec=1)
+    else:
+        n, k, B, dtype, count = 1 << 22, 256, 1024, np.complex64, 2
+        w = default_w(n, B, 0.75, 1e-8)
+        kw = dict(delta=1e-8, alpha=0.75, loc_prec=1, b_min=64, rounds=24, patience=5, theta=0.01, g_min=0.25,
+                  stop_count=k, stop_patience=3, ratio_tol=0.002, group0=12, group_step=3)
+    say("split-hash", shape, "parts", parts, "n", n, "count", count)
+    plan = plan_for(n, k, B, w, 0, max_batch=count, hash_split=parts, **kw)
+    xs, sups, seeds = [], [], []
+    for s in range(count):
+        x, sup, _ = siggen.planted_signal(n, k, 820 + s, dtype, magnitude="unit" if shape == "c1" else "loguniform")
+        xs.append(x)
+        sups.append(sup)
+        seeds.append(13 * s + 5)
+    out = run_batch(torch, dev, plan, xs, seeds)
+    for s in range(count):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        assert int(out[s][2][0]) == ref.rounds_used
+        compare(out[s][0], out[s][1], ref)
+        assert np.array_equal(out[s][0], sups[s])
+    plan.close()
+
+
+def test_split_hashing_is_batch_independent(torch_dev):
+    """A signal gives bit-identical results alone and inside a batch under
+    hash_split (the serving runtime relies on this)."""
+    torch, dev = torch_dev
+    n, k, B = 1 << 16, 64, 256
+    w = default_w(n, B, 0.5, 1e-9)
+    say("split-hash-batch-independence", "n", n)
+    plan = plan_for(n, k, B, w, 0, max_batch=4, hash_split=4, b_min=32, rounds=24, patience=5)
+    xs = [siggen.planted_signal(n, k, 840 + s, np.complex64)[0] for s in range(4)]
+    seeds = [3, 4, 5, 6]
+    batch = run_batch(torch, dev, plan, xs, seeds)
+    for s in (0, 3):
+        alone = run_batch(torch, dev, plan, [xs[s]], [seeds[s]])[0]
+        assert np.array_equal(alone[0], batch[s][0]) and np.array_equal(alone[1], batch[s][1])
+    plan.close()
+
+
 def test_cached_tuned_c3_plan_matches_oracle(torch_dev):
     """The plan the autotuner stored for the n = 2^22, k = 256 batch (the one
     bench.py times) matches the oracle on two signals of that workload."""
