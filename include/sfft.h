@@ -367,7 +367,8 @@ uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
  *   * a request (n, k, mode) maps to a shape: k rounded up to a power of two
  *     (at least 8), B = 4k' (exact) or 16k' (general) within [64 or 256,
  *     min(4096, n/16)], the default window for the mode's delta; exact shapes
- *     use b_min = max(32, B/32) (at most B), at most 24 rounds and patience 5.  Where that window
+ *     use b_min = max(32, B/32) (at most B), at most 24 rounds, patience 5
+ *     and hash_split = B/256 (1 to 16 parts).  Where that window
  *     would cover the whole signal (w >= n), or the sparse plan would gather
  *     more than SFFT_SERVER_DENSE_SAMPLES_PER_N x n samples per signal
  *     (sfft_plan_samples), the request takes the dense path: a full-length
