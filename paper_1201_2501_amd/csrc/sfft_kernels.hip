@@ -31,13 +31,17 @@ constexpr int kGatherUnroll = SFFT_GATHER_UNROLL;
 // In-place radix-2 decimation-in-frequency FFT of VA and VB (B points each,
 // natural-order input, bit-reversed output), unnormalised, sign -:
 // X_j = sum_r V_r exp(-2 pi i j r / B).  tw holds exp(-2 pi i m / Bmax),
-// m < Bmax.
+// m < Bmax.  Stages whose butterflies span 64 points or more go through LDS
+// (one barrier each); from B = 64 on, the last six (span 32 .. 1) pair lanes
+// of one wavefront: each wave takes 64-point blocks, one point per lane, and
+// exchanges partners with shuffles.
 template <class TA, uint32_t NT>
 __device__ void lds_fft2(cx<TA>* VA, cx<TA>* VB, uint32_t B, uint32_t Bmax,
                          const typename TwTraits<TA>::V* tw) {
     const uint32_t tid = threadIdx.x;
     const uint32_t hb = B >> 1;
-    for (uint32_t half = hb; half >= 1; half >>= 1) {
+    const uint32_t lds_last = B >= 64 ? 64u : 1u;
+    for (uint32_t half = hb; half >= lds_last; half >>= 1) {
         const uint32_t tstride = Bmax / (2 * half);
         for (uint32_t k = tid; k < B; k += NT) {
             cx<TA>* V = k < hb ? VA : VB;
@@ -49,6 +53,24 @@ __device__ void lds_fft2(cx<TA>* VA, cx<TA>* VB, uint32_t B, uint32_t Bmax,
             const auto t = tw[j * tstride];
             V[i0] = cadd(a, b);
             V[i1] = cmul(csub(a, b), cx<TA>{t.x, t.y});
+        }
+        __syncthreads();
+    }
+    if (B >= 64) {
+        const uint32_t lane = tid & 63u, wave = tid >> 6;
+        const uint32_t per = B >> 6;            // 64-point blocks per transform
+        for (uint32_t blk = wave; blk < 2 * per; blk += NT / 64) {
+            cx<TA>* V = blk < per ? VA : VB;
+            const uint32_t at = ((blk < per ? blk : blk - per) << 6) + lane;
+            cx<TA> v = V[at];
+#pragma unroll
+            for (uint32_t half = 32; half >= 1; half >>= 1) {
+                const cx<TA> u{__shfl_xor(v.r, (int)half, 64), __shfl_xor(v.i, (int)half, 64)};
+                const auto t = tw[(lane & (half - 1)) * (Bmax / (2 * half))];
+                // the lower point of a pair keeps a + b, the upper (a - b) w^j
+                v = (lane & half) ? cmul(csub(u, v), cx<TA>{t.x, t.y}) : cadd(v, u);
+            }
+            V[at] = v;
         }
         __syncthreads();
     }
