@@ -246,3 +246,39 @@ def test_fake_server_cancels_requests_that_have_not_launched():
         assert s.completed == (1 if st1 == sfft.SFFT_OK else 2) and s.failed == 0
     finally:
         srv.close()
+
+
+def test_fake_server_many_shapes_tight_budget_with_cancels():
+    """Instances are built on threads of their own and idle ones are evicted
+    under a budget barely above the largest instance: every request of a
+    stream over 24 shapes (with cancels) ends served or canceled, none fails,
+    and the budget holds."""
+    import random
+    rng = random.Random(7)
+    shapes = [(1 << e, k, m) for e in (16, 18, 20, 22) for k in (8, 100, 600) for m in (0, 1)]
+    sd = sfft.sfft_server_desc_init()
+    sd.slots = 4
+    sizes = [sfft.sfft_server_shape(sd, *s)[2] for s in shapes]
+    for budget_factor, instances, service in ((1.05, 1, 0.5), (1.5, 2, 0.0), (3.0, 3, 2.0)):
+        budget = int(max(sizes) * budget_factor)
+        srv = FakeServer(slots=4, instances=instances, budget_bytes=budget, fake_service_ms=service)
+        try:
+            tickets, canceled = [], 0
+            for i in range(300):
+                n, k, m = rng.choice(shapes)
+                st, t = srv.submit(n, k, m, seed=i)
+                assert st == sfft.SFFT_OK
+                tickets.append(t)
+                if rng.random() < 0.05 and srv.lib.sfft_server_cancel(srv.h, t) == sfft.SFFT_OK:
+                    canceled += 1
+            done = 0
+            for t in tickets:
+                res = sfft.RequestResult()
+                st = srv.lib.sfft_server_wait(srv.h, t, 20000.0, ctypes.byref(res))
+                assert st in (sfft.SFFT_OK, sfft.SFFT_ECANCELED)
+                done += st == sfft.SFFT_OK
+            s = srv.stats()
+            assert done + canceled == len(tickets) and s.completed == done and s.failed == 0
+            assert s.peak_bytes <= budget and s.bytes_in_use <= budget
+        finally:
+            srv.close()
