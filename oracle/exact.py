@@ -21,16 +21,19 @@ every accepted i tied to the one bin that can hold it, so the writes of one
 round never conflict.  The phase is computed as the argument of
 u_j * conj(u'_j), which has the phase of u_j / u'_j.
 
-After the last round the values are re-estimated in FP64: for each i in
-supp(zhat) and each round r whose window value G'_{-o_r(i)} >= g_min,
-    e_r = (u_raw_r[h_r(i)] - sum_{i' != i, h_r(i') = h_r(i)} G'_{-o_r(i')} zhat_{i'}) / G'_{-o_r(i)}
+After the last round the values are re-estimated in FP64 (reestimate.py):
+for each i in supp(zhat) and each round r whose window value
+G'_{-o_r(i)} >= g_min,
+    e_r = (u_raw_r[h_r(i)] - sum_{i' != i, h_r(i') = h_r(i)} G'_{-o_r(i')} v_{i'}) / G'_{-o_r(i)}
 (the EstimateValues estimate of Algorithm 2 with a = 0, applied to x minus the
-other recovered coefficients) and the value is the coordinate-wise median of
-the e_r over the rounds where i is the only zhat entry of its bin (the
-no-collision case of the estimation lemmas), or over all such rounds when i
-never was alone.  Preferring isolated rounds keeps the error of one entry from
-leaking into another through shared bins of the small late rounds.  The output keeps entries with |value| > theta/2, at most cap of them
-(largest magnitude first, then smaller index), in ascending index order.
+other recovered coefficients), and the value is a coordinate-wise median of
+the e_r.  Entries are resolved in passes: first those alone in their bin in
+some round (the no-collision case of the estimation lemmas), then those with
+a round whose other bin members are all resolved, subtracting the resolved
+values v_{i'}; so the window leakage a decoded value picked up from a
+neighbour that was found later does not pass into the estimates.  The
+output keeps entries with |value| > theta/2, at most cap of them (largest
+magnitude first, then smaller index), in ascending index order.
 
 The paper-literal variant (params.literal) keeps v = round(u_j) and writes
 without the bin/window checks; conflicting writes keep the larger |u_j|,
@@ -42,7 +45,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .hashing import bin_offset, hash_to_bins_raw, subtract_zhat
-from .params import SfftParams, complex_median
+from .params import SfftParams
+from .reestimate import peel_reestimate
 from .rng import draw_b, draw_sigma, inverse_mod
 from .window import gprime, window_time
 
@@ -165,37 +169,21 @@ def noiseless_sparse_fft(x, p: SfftParams) -> ExactResult:
 
 
 def reestimate(zhat, raw, p: SfftParams):
-    """FP64 median re-estimation of every zhat entry over the given rounds."""
+    """FP64 median re-estimation of every zhat entry over the given rounds
+    (shift a = 0 of each round's pair), resolved in passes by
+    reestimate.peel_reestimate."""
     n = p.n
-    keys = sorted(zhat)
-    out = {}
-    per_round = []
+    meas = []
     for r, (sigma, b, u0_raw, _u1) in enumerate(raw):
         B = len(u0_raw)
         ar = p.round_alpha(r)
-        hg = {}
-        members = {}
-        for i in keys:
+        terms = {}
+        for i in zhat:
             h, o = bin_offset(i, sigma, b, n, B)
-            hg[i] = (h, gprime(-o, n, B, ar, p.delta))
-            members.setdefault(h, []).append(i)   # ascending index within a bin
-        per_round.append((u0_raw, hg, members))
-    for i in keys:
-        vals, alone = [], []
-        for u0_raw, hg, members in per_round:
-            h, g = hg[i]
-            if g < p.g_min:
-                continue
-            others = 0.0 + 0.0j
-            for i2 in members[h]:
-                if i2 != i:
-                    others += hg[i2][1] * zhat[i2]
-            vals.append((u0_raw[h] - others) / g)
-            if len(members[h]) == 1:
-                alone.append(vals[-1])
-        use = alone if alone else vals
-        out[i] = complex_median(use) if use else zhat[i]
-    return out
+            g = gprime(-o, n, B, ar, p.delta)
+            terms[i] = (h, g, g)
+        meas.append((u0_raw, terms))
+    return peel_reestimate(zhat, meas, p.g_min)
 
 
 def _finish(res: ExactResult, values: dict, p: SfftParams):

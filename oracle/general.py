@@ -33,9 +33,9 @@ biases it whenever the offset is large).
 
 Final FP64 re-estimation: every zhat entry is re-estimated from all stored
 EstimateValues measurements, with the other zhat entries of the same bin
-subtracted, preferring (as in exact mode) the measurements where the entry is
-alone in its bin; the output is the top-cap entries by magnitude, ascending
-index.
+subtracted, resolved in passes as in exact mode (reestimate.py: entries alone
+in a bin first, then entries whose bin neighbours are resolved); the output
+is the top-cap entries by magnitude, ascending index.
 
 Parity unpinned: which noisy heads a run finds has no closed form; the oracle
 run itself and the statistical l2/l2 guarantee of Section 1 eq. (1) are what
@@ -48,6 +48,7 @@ import numpy as np
 
 from .hashing import bin_offset, hash_to_bins_raw, omega_pow, subtract_zhat
 from .params import SfftParams, complex_median
+from .reestimate import peel_reestimate
 from .rng import LEVEL_EST, draw_a, draw_b, draw_beta, draw_sigma, inverse_mod
 from .window import gprime, window_time
 
@@ -186,34 +187,19 @@ def estimate_values(x, zhat, r, kprime, L, B, G, p: SfftParams, res: GeneralResu
 
 
 def reestimate_general(zhat, est_raw, p: SfftParams):
+    """FP64 median re-estimation of every zhat entry over all stored
+    EstimateValues measurements, resolved in passes by
+    reestimate.peel_reestimate (term coefficient G' omega^{a sigma i})."""
     n = p.n
-    keys = sorted(zhat)
-    per = []
+    meas = []
     for sigma, a, b, B, raw in est_raw:
-        info = {}
-        members = {}
-        for i in keys:
+        terms = {}
+        for i in zhat:
             h, o = bin_offset(i, sigma, b, n, B)
-            info[i] = (h, gprime(-o, n, B, p.alpha, p.delta))
-            members.setdefault(h, []).append(i)
-        per.append((sigma, a, b, raw, info, members))
-    out = {}
-    for i in keys:
-        vals, alone = [], []
-        for sigma, a, b, raw, info, members in per:
-            h, g = info[i]
-            if g < p.g_min:
-                continue
-            others = 0.0 + 0.0j
-            for i2 in members[h]:
-                if i2 != i:
-                    others += info[i2][1] * zhat[i2] * omega_pow(a * sigma * i2, n)
-            vals.append((raw[h] - others) * omega_pow(-(a * sigma * i), n) / g)
-            if len(members[h]) == 1:
-                alone.append(vals[-1])
-        use = alone if alone else vals
-        out[i] = complex_median(use) if use else zhat[i]
-    return out
+            g = gprime(-o, n, B, p.alpha, p.delta)
+            terms[i] = (h, g, g * omega_pow(a * sigma * i, n))
+        meas.append((raw, terms))
+    return peel_reestimate(zhat, meas, p.g_min)
 
 
 def sparse_fft(x, p: SfftParams) -> GeneralResult:
