@@ -13,8 +13,9 @@ Printed: ONE JSON line with the batched sFFTs/s as `value`, plus the plain
 one-signal-at-a-time path, a dense full-length FFT + top-k on the same GPU
 (the crossover reference), per-step latency percentiles, the roofline of the
 dominant kernel (HashToBins, HBM bound; achieved = algorithmic bytes / its
-event-timed duration), sampled parity against the FP64 oracle, and the oracle
-itself timed on the host (cpu_baseline).  `--workload c4` (the general-mode
+event-timed duration), parity of every signal against the FP64 oracle, and the
+oracle itself timed on the host (cpu_baseline: a process pool over the host's
+cores, with the one-process rate beside it).  `--workload c4` (the general-mode
 precision split) and `--workload section5` (k-point DFTs through the n-point
 sFFT of the periodic extension) print their own line instead.
 """
@@ -23,6 +24,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -67,6 +69,52 @@ def load_traffic(signals, cfg_key):
         return None
     per_signal = rec.get("bytes_per_signal")
     return None if per_signal is None else float(per_signal) * signals
+
+
+def host_cores():
+    """Cores this process may use, at most 16 (the host share of one GPU)."""
+    try:
+        c = len(os.sched_getaffinity(0))
+    except AttributeError:
+        c = os.cpu_count() or 1
+    return max(1, min(16, c))
+
+
+def _oracle_worker(job):
+    """One oracle run on signal `s` of the memory-mapped batch (pool worker;
+    imports no GPU library)."""
+    path, count, n, fields, seed, s = job
+    from oracle.exact import noiseless_sparse_fft
+    from oracle.params import SfftParams
+    x = np.array(np.memmap(path, dtype=np.complex64, mode="r", shape=(count, n))[s])
+    t = time.perf_counter()
+    noiseless_sparse_fft(x, SfftParams(**{**fields, "seed": seed}))
+    return time.perf_counter() - t
+
+
+def oracle_pool_rate(path, count, n, desc, seeds, procs):
+    """sFFTs/s of the oracle over `count` signals spread over `procs` spawned
+    processes (one numpy thread each); the pool is started and warmed before
+    the clock starts.  Returns (rate, wall seconds)."""
+    import multiprocessing as mp
+    fields = oracle_params(desc, 0).__dict__.copy()
+    env_keep = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_keep:
+        os.environ[k] = "1"
+    try:
+        ctx = mp.get_context("spawn")
+        with ctx.Pool(procs) as pool:
+            pool.map(_oracle_worker, [(path, count, n, fields, seeds[0], 0)] * procs)   # warm-up
+            t = time.perf_counter()
+            pool.map(_oracle_worker, [(path, count, n, fields, seeds[s], s) for s in range(count)], chunksize=1)
+            wall = time.perf_counter() - t
+    finally:
+        for k, v in env_keep.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return count / wall, wall
 
 
 def serving_bench(args, torch, dev, sfft):
@@ -409,8 +457,11 @@ def main():
                          "n = 2^22 is near FP32 resolution)")
     ap.add_argument("--w", type=int, default=0)
     ap.add_argument("--plain-signals", type=int, default=8)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--parity-signals", type=int, default=4)
+    ap.add_argument("--parity-signals", type=int, default=0,
+                    help="signals the oracle runs and checks (0: every signal of the batch)")
+    ap.add_argument("--cpu-procs", type=int, default=0,
+                    help="oracle process pool size for the multi-core CPU baseline (0: the host's cores, at "
+                         "most 16; 1: one process only)")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -658,45 +709,53 @@ def main():
     parity, cpu_baseline = None, None
     if not args.no_cpu:
         from oracle.exact import noiseless_sparse_fft
-        picks = list(dict.fromkeys([0, S - 1] + list(np.linspace(0, S - 1, max(args.parity_signals, 2)).astype(int))))
-        mism, max_rel, l2 = 0, 0.0, []
-        done, t_cpu = 0, 0.0
-        for s in picks:
-            x = X[s].cpu().numpy()
-            t = time.perf_counter()
-            ref = noiseless_sparse_fft(x, oracle_params(desc, int(seeds[s].item())))
-            t_cpu += time.perf_counter() - t
-            done += 1
-            c = counts[s]
-            if not np.array_equal(idx_all[s, :c], ref.indices):
-                mism += 1
-            else:
-                rel = np.abs(val_all[s, :c] - ref.values) / np.maximum(np.abs(ref.values), 1e-300)
-                max_rel = max(max_rel, float(rel.max()) if c else 0.0)
-            truth = np.zeros(len(supports[s]), complex)
-            est = dict(zip(idx_all[s, :c].tolist(), val_all[s, :c]))
-            err = math.sqrt(sum(abs(est.get(int(i), 0) - v) ** 2 for i, v in zip(supports[s], values[s])) +
-                            sum(abs(v) ** 2 for i, v in est.items() if i not in set(supports[s].tolist())))
-            l2.append(err / float(np.linalg.norm(values[s])))
-            if done >= len(picks) and t_cpu >= args.cpu_seconds:
-                break
-        # extend the CPU sample until about cpu_seconds of oracle work
-        extra = 0
-        s = 1
-        while t_cpu < args.cpu_seconds and s < S:
-            if s not in picks:
+        nchk = S if args.parity_signals <= 0 else min(S, args.parity_signals)
+        shm = None
+        if args.cpu_procs != 1:
+            shm = tempfile.NamedTemporaryFile(prefix="sfft_oracle_", suffix=".c64", dir="/dev/shm"
+                                              if os.path.isdir("/dev/shm") else None, delete=False)
+            shm.close()
+            mm = np.memmap(shm.name, dtype=np.complex64, mode="w+", shape=(nchk, n))
+        try:
+            mism, max_rel, l2, t_cpu = 0, 0.0, [], 0.0
+            seed_list = [int(seeds[s].item()) for s in range(nchk)]
+            for s in range(nchk):
                 x = X[s].cpu().numpy()
+                if shm is not None:
+                    mm[s] = x
                 t = time.perf_counter()
-                noiseless_sparse_fft(x, oracle_params(desc, int(seeds[s].item())))
+                ref = noiseless_sparse_fft(x, oracle_params(desc, seed_list[s]))
                 t_cpu += time.perf_counter() - t
-                extra += 1
-            s += 1
-        parity = {"signals_checked": len(picks), "support_mismatches": mism, "max_rel_err": max_rel,
-                  "tolerance": 1e-10, "l2_rel_err_vs_planted_max": max(l2)}
-        nsig = len(picks) + extra
-        cpu_baseline = {"value": round(nsig / t_cpu, 3), "unit": "sFFTs/s", "cores": 1, "kind": "oracle",
-                        "sample": "%d signals of the same workload, FP64 numpy oracle, one process" % nsig}
-        log("oracle: %d signals in %.1fs, parity mismatches %d" % (nsig, t_cpu, mism))
+                c = counts[s]
+                if not np.array_equal(idx_all[s, :c], ref.indices):
+                    mism += 1
+                else:
+                    rel = np.abs(val_all[s, :c] - ref.values) / np.maximum(np.abs(ref.values), 1e-300)
+                    max_rel = max(max_rel, float(rel.max()) if c else 0.0)
+                est = dict(zip(idx_all[s, :c].tolist(), val_all[s, :c]))
+                sup_set = set(supports[s].tolist())
+                err = math.sqrt(sum(abs(est.get(int(i), 0) - v) ** 2 for i, v in zip(supports[s], values[s])) +
+                                sum(abs(v) ** 2 for i, v in est.items() if i not in sup_set))
+                l2.append(err / float(np.linalg.norm(values[s])))
+            parity = {"signals_checked": nchk, "support_mismatches": mism, "max_rel_err": max_rel,
+                      "tolerance": 1e-10, "l2_rel_err_vs_planted_max": max(l2)}
+            one = {"value": round(nchk / t_cpu, 3), "unit": "sFFTs/s", "cores": 1, "seconds": round(t_cpu, 2)}
+            log("oracle: %d signals in %.1fs on one core, parity mismatches %d of %d" % (nchk, t_cpu, mism, nchk))
+            cpu_baseline = {**one, "kind": "oracle",
+                            "sample": "%d signals of the same workload, FP64 numpy oracle, one process" % nchk}
+            if shm is not None:
+                mm.flush()
+                procs = args.cpu_procs if args.cpu_procs > 0 else host_cores()
+                rate, wall = oracle_pool_rate(shm.name, nchk, n, desc, seed_list, procs)
+                log("oracle: %d signals in %.1fs on %d processes" % (nchk, wall, procs))
+                cpu_baseline = {"value": round(rate, 3), "unit": "sFFTs/s", "cores": procs, "kind": "oracle",
+                                "sample": "%d signals of the same workload, FP64 numpy oracle, a pool of %d "
+                                          "processes (one thread each)" % (nchk, procs),
+                                "single_core": one}
+        finally:
+            if shm is not None:
+                del mm
+                os.unlink(shm.name)
 
     # ---------------------------------------------------------------- serving
     serving = None

@@ -518,18 +518,18 @@ __device__ cx<double> median_cx(const double* src, uint32_t c) {
     return median_cx64(src, c);
 }
 
-// Median of the samples src[r * stride] for the rounds r set in `mask`
-// (popcount <= K), by the network of median_net.
+// Median of the samples src[m * stride] for the measurements m set in
+// `mask` (popcount <= K), by the network of median_net.
 template <uint32_t K>
-__device__ __forceinline__ double median_net_mask(const double* src, uint32_t mask, uint64_t stride) {
+__device__ __forceinline__ double median_net_mask(const double* src, uint64_t mask, uint64_t stride) {
     double a[K];
-    const uint32_t c = __popc(mask);
-    uint32_t m = mask;
+    const uint32_t c = __popcll(mask);
+    uint64_t m = mask;
 #pragma unroll
     for (uint32_t q = 0; q < K; ++q) {
         a[q] = __builtin_huge_val();
         if (m) {
-            a[q] = src[(uint64_t)__builtin_ctz(m) * stride];
+            a[q] = src[(uint64_t)__builtin_ctzll(m) * stride];
             m &= m - 1;
         }
     }
@@ -558,13 +558,18 @@ __device__ __forceinline__ double median_net_mask(const double* src, uint32_t ma
     return (c & 1) ? m1 : 0.5 * (m0 + m1);
 }
 
-// Complex median over the rounds in `mask` (at most 32) of samples stored as
-// (re, im) pairs `stride` doubles apart per round.
-__device__ cx<double> median_cx_mask(const double* src, uint32_t mask, uint64_t stride) {
-    const uint32_t c = __popc(mask);
+__device__ __noinline__ cx<double> median_cx_mask64(const double* src, uint64_t mask, uint64_t stride) {
+    return {median_net_mask<64>(src, mask, stride), median_net_mask<64>(src + 1, mask, stride)};
+}
+
+// Complex median over the measurements in `mask` (at most 64) of samples
+// stored as (re, im) pairs `stride` doubles apart per measurement.
+__device__ cx<double> median_cx_mask(const double* src, uint64_t mask, uint64_t stride) {
+    const uint32_t c = __popcll(mask);
     if (c <= 8) return {median_net_mask<8>(src, mask, stride), median_net_mask<8>(src + 1, mask, stride)};
     if (c <= 16) return {median_net_mask<16>(src, mask, stride), median_net_mask<16>(src + 1, mask, stride)};
-    return {median_net_mask<32>(src, mask, stride), median_net_mask<32>(src + 1, mask, stride)};
+    if (c <= 32) return {median_net_mask<32>(src, mask, stride), median_net_mask<32>(src + 1, mask, stride)};
+    return median_cx_mask64(src, mask, stride);
 }
 
 // Sort key ordering by |v| descending, then slot ascending (51 magnitude bits).
@@ -572,29 +577,6 @@ __device__ __forceinline__ uint64_t mag_key(double vr, double vi, uint32_t slot)
     const double mg = sqrt(vr * vr + vi * vi);
     const uint64_t mb = (uint64_t)__double_as_longlong(mg) >> 12;
     return ((~mb & ((1ull << 51) - 1)) << 13) | slot;
-}
-
-// Median over the samples est[e][...]: the `na` isolated ones at the front
-// when there are any, else the `nb` others at the back.
-template <uint32_t KMAX>
-__device__ cx<double> entry_median(const double* est, uint32_t nmeas, uint32_t count_word, cx<double> fallback) {
-    const uint32_t na = count_word & 0xFFFFu, nb = count_word >> 16;
-    const uint32_t c = na ? na : nb;
-    if (c == 0) return fallback;
-    const uint32_t first = na ? 0u : nmeas - nb;
-    return median_cx<KMAX>(est + 2 * first, c);
-}
-
-// Record one re-estimation sample of entry e: isolated samples from the
-// front of its slot range, the others from the back.
-__device__ __forceinline__ void push_sample(double* est, uint32_t nmeas, uint32_t* count_word, bool isolated,
-                                            cx<double> v) {
-    const uint32_t c = *count_word;
-    const uint32_t na = c & 0xFFFFu, nb = c >> 16;
-    const uint32_t slot = isolated ? na : nmeas - 1 - nb;
-    est[slot * 2] = v.r;
-    est[slot * 2 + 1] = v.i;
-    *count_word = isolated ? c + 1 : c + (1u << 16);
 }
 
 // Write the output of one signal from re-estimated values fin[e] (e < zc,
@@ -650,6 +632,130 @@ __device__ uint32_t write_output(DecodeLds& L, const uint64_t* zi, const double*
         oval[2 * q + 1] = 0.0;
     }
     return nout;
+}
+
+// ----------------------------------------------- final re-estimation --
+// Samples of one signal's final re-estimation.  Measurement m is a decoded
+// round (exact mode) or an EstimateValues hashing (general mode); for zhat
+// entry e, slot s = m * ms + e * es holds
+//   est[s]   (u_m[h] - sum over the other entries of the bin of c_m(e') zhat_e') / c_m(e),
+//            complex, with the decoded zhat values
+//   flag[s]  0 when G'_{-o_m(e)} < g_min, 1 when e is the only entry of its
+//            bin, 2 when it shares the bin
+//   grp[s]   first grouped position << 16 | member count of e's bin
+//   coef[s]  c_m(e) = G'_{-o_m(e)} omega^{a sigma i_e}, the term entry e adds
+//            to its bin (HashToBins lemma)
+// (grp and coef written only for entries of shared bins), and
+// ord[m * capz + q] lists measurement m's entries grouped by bin.
+struct PeelView {
+    double* est;
+    const uint8_t* flag;
+    const uint32_t* grp;
+    const uint16_t* ord;
+    const double* coef;
+    uint64_t ms, es;   // slot strides
+    uint32_t capz;
+    uint32_t nmeas;    // measurements in use (<= 64)
+};
+
+constexpr uint32_t kMaxPasses = 8;
+
+// Final values fin[e] of the zhat entries e < zc (decoded values zv), resolved
+// in passes: pass 1 takes the median over the measurements where an entry
+// is alone in its bin; pass p takes, for an unresolved entry, the median over
+// the valid measurements whose other bin members were resolved before pass
+// p, with their resolved values subtracted in place of the decoded ones;
+// passes end when one resolves nothing (at most kMaxPasses).  Entries left
+// take the median over all valid measurements, subtracting resolved values
+// where a neighbour has one; entries without a valid measurement keep the
+// decoded value.  Samples of entries that resolve are rewritten in place.
+// res: [capz] LDS words; misc: one LDS word.
+__device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, double* fin, uint16_t* res,
+                            uint32_t* misc) {
+    const uint32_t tid = threadIdx.x;
+    const uint64_t sstride = 2 * V.ms;
+    auto mask_of = [&](uint32_t e, uint8_t want) {
+        uint64_t m = 0;
+        for (uint32_t q = 0; q < V.nmeas; ++q)
+            m |= (uint64_t)(V.flag[q * V.ms + (uint64_t)e * V.es] == want) << q;
+        return m;
+    };
+    // whether every other member of e's bin in measurement m is resolved
+    auto neighbours_resolved = [&](uint32_t e, uint32_t m) {
+        const uint32_t w = V.grp[m * V.ms + (uint64_t)e * V.es];
+        const uint16_t* o = V.ord + (uint64_t)m * V.capz + (w >> 16);
+        for (uint32_t q = 0; q < (w & 0xFFFFu); ++q)
+            if (o[q] != e && res[o[q]] != 1) return false;
+        return true;
+    };
+    // subtract c_m(e') (v_e' - zhat_e') / c_m(e) over the resolved neighbours
+    auto correct = [&](uint32_t e, uint32_t m) {
+        const uint64_t s = m * V.ms + (uint64_t)e * V.es;
+        const uint32_t w = V.grp[s];
+        const uint16_t* o = V.ord + (uint64_t)m * V.capz + (w >> 16);
+        cx<double> acc{0.0, 0.0};
+        for (uint32_t q = 0; q < (w & 0xFFFFu); ++q) {
+            const uint32_t e2 = o[q];
+            if (e2 == e || res[e2] != 1) continue;
+            const uint64_t s2 = m * V.ms + (uint64_t)e2 * V.es;
+            const cx<double> c2{V.coef[2 * s2], V.coef[2 * s2 + 1]};
+            const cx<double> d{fin[2 * e2] - zv[2 * e2], fin[2 * e2 + 1] - zv[2 * e2 + 1]};
+            acc = cadd(acc, cmul(c2, d));
+        }
+        const cx<double> c{V.coef[2 * s], V.coef[2 * s + 1]};
+        const double n2 = c.r * c.r + c.i * c.i;
+        const cx<double> q = cmul(acc, cx<double>{c.r / n2, -c.i / n2});
+        V.est[2 * s] -= q.r;
+        V.est[2 * s + 1] -= q.i;
+    };
+    for (uint32_t e = tid; e < zc; e += kDec) {
+        const uint64_t iso = mask_of(e, 1);
+        res[e] = iso ? 1 : 0;
+        if (iso) {
+            const cx<double> v = median_cx_mask(V.est + 2 * (uint64_t)e * V.es, iso, sstride);
+            fin[2 * e] = v.r;
+            fin[2 * e + 1] = v.i;
+        }
+    }
+    for (uint32_t pass = 2; pass <= kMaxPasses; ++pass) {
+        if (tid == 0) *misc = 0;
+        __syncthreads();
+        uint32_t mine = 0;
+        for (uint32_t e = tid; e < zc; e += kDec) {
+            if (res[e] != 0) continue;
+            uint64_t ready = 0;
+            for (uint64_t m = mask_of(e, 2); m; m &= m - 1) {
+                const uint32_t q = __builtin_ctzll(m);
+                if (neighbours_resolved(e, q)) ready |= 1ull << q;
+            }
+            if (!ready) continue;
+            for (uint64_t m = ready; m; m &= m - 1) correct(e, __builtin_ctzll(m));
+            const cx<double> v = median_cx_mask(V.est + 2 * (uint64_t)e * V.es, ready, sstride);
+            fin[2 * e] = v.r;
+            fin[2 * e + 1] = v.i;
+            res[e] = 2;   // resolved in this pass: not yet read as resolved
+            ++mine;
+        }
+        if (mine) atomicAdd(misc, mine);
+        __syncthreads();
+        const uint32_t got = *misc;
+        for (uint32_t e = tid; e < zc; e += kDec)
+            if (res[e] == 2) res[e] = 1;
+        __syncthreads();
+        if (!got) break;
+    }
+    for (uint32_t e = tid; e < zc; e += kDec) {
+        if (res[e] != 0) continue;
+        const uint64_t crowd = mask_of(e, 2);
+        cx<double> v{zv[2 * e], zv[2 * e + 1]};
+        if (crowd) {
+            for (uint64_t m = crowd; m; m &= m - 1) correct(e, __builtin_ctzll(m));
+            v = median_cx_mask(V.est + 2 * (uint64_t)e * V.es, crowd, sstride);
+        }
+        fin[2 * e] = v.r;
+        fin[2 * e + 1] = v.i;
+    }
+    __syncthreads();
 }
 
 // =================================================================== exact
@@ -850,8 +956,8 @@ __global__ void __launch_bounds__(kDec) k_exact_decode(DecodeArgs D) {
 }
 
 // Final FP64 re-estimation of every zhat entry over the decoded rounds
-// (EstimateValues' estimate with a = 0 on x minus the other entries; rounds
-// where the entry is alone in its bin first), then the output.
+// (EstimateValues' estimate with a = 0 on x minus the other entries,
+// resolved in passes by peel_values), then the output.
 __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x;
@@ -866,10 +972,8 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
     const uint64_t* zi = D.zidx + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * D.capz;
     const double* zv = D.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * D.capz * 2;
     const double2* zv2 = reinterpret_cast<const double2*>(zv);
-    const uint32_t nmeas = D.rounds;
-    double* est = D.est + (uint64_t)sig * D.capz * nmeas * 2;
+    const uint64_t base = (uint64_t)sig * D.rounds * D.capz;
     double* fin = D.fin + (uint64_t)sig * D.capz * 2;
-    for (uint32_t e = tid; e < zc; e += kDec) L.ec[e] = 0;
     // zhat of this lane's first entries (fixed), and their raw bins of round 0
     double2 zp[kUnroll], pre[kUnroll];
 #pragma unroll
@@ -920,11 +1024,22 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
                 if (e < zc) pre[u] = rn[bin_offset(L.zl[e], sn, bn, n, Bn).h];
             }
         }
+        const uint64_t row = base + (uint64_t)r * D.capz;
+        for (uint32_t q = tid; q < zc; q += kDec) D.eord[row + q] = L.ent[q];
+        // the sample table of round r, as k_exact_reest writes it
         auto sample = [&](uint32_t e, double2 a0) {
             const double ge = L.t[2 * e + 1].r;
-            if (ge < D.g_min) return;
             const uint32_t h = L.hk[e];
             const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
+            if (p1 - p0 > 1) {
+                D.egrp[row + e] = p0 << 16 | (p1 - p0);
+                D.ecoef[2 * (row + e)] = ge;
+                D.ecoef[2 * (row + e) + 1] = 0.0;
+            }
+            if (ge < D.g_min) {
+                D.eflag[row + e] = 0;
+                return;
+            }
             double orr = 0.0, oii = 0.0;
             for (uint32_t q = p0; q < p1; ++q) {
                 const uint32_t e2 = L.ent[q];
@@ -933,8 +1048,9 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
                 orr += c2.r;
                 oii += c2.i;
             }
-            push_sample(est + (uint64_t)e * nmeas * 2, nmeas, &L.ec[e], p1 - p0 == 1,
-                        cx<double>{(a0.x - orr) / ge, (a0.y - oii) / ge});
+            D.est[2 * (row + e)] = (a0.x - orr) / ge;
+            D.est[2 * (row + e) + 1] = (a0.y - oii) / ge;
+            D.eflag[row + e] = p1 - p0 == 1 ? 1 : 2;
         };
 #pragma unroll
         for (uint32_t u = 0; u < kUnroll; ++u)
@@ -942,13 +1058,9 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
         for (uint32_t e = tid + kUnroll * kDec; e < zc; e += kDec) sample(e, r0[L.hk[e]]);
     }
     __syncthreads();
-    for (uint32_t e = tid; e < zc; e += kDec) {
-        const cx<double> v = entry_median<kMaxRounds>(est + (uint64_t)e * nmeas * 2, nmeas, L.ec[e],
-                                                      cx<double>{zv[2 * e], zv[2 * e + 1]});
-        fin[2 * e] = v.r;
-        fin[2 * e + 1] = v.i;
-    }
-    __syncthreads();
+    const PeelView V{D.est + base * 2, D.eflag + base, D.egrp + base, D.eord + base, D.ecoef + base * 2,
+                     D.capz, 1, D.capz, R};
+    peel_values(V, zc, zv, fin, L.hk, &L.misc[0]);
     uint32_t flags = L.sw[ST_FLAGS];
     const uint32_t nout = write_output(L, zi, fin, zc, false, 0.5 * D.theta, D.cap, D.out_scale,
                                        D.out_idx + (uint64_t)sig * D.cap, D.out_val + (uint64_t)sig * D.cap * 2,
@@ -966,13 +1078,13 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
 }
 
 // The same re-estimation split over workgroups, where its LDS fits: block
-// (signal, round r) records the estimate of every zhat entry from round r
-// (the other entries of its bin removed, in ascending index order), flagged
-// isolated or crowded; k_exact_output takes the medians and writes the
-// output.  Each sample is computed exactly as in k_exact_finish, and a
-// median does not depend on the order of its samples.  Samples and flags
-// are stored round-major ([sig][round][capz]) so that both kernels access
-// them contiguously across the entries of a wave.
+// (signal, round r) records the sample table of round r (PeelView: the
+// estimate of every zhat entry with the other entries of its bin removed in
+// ascending index order, its kind, and for shared bins the grouping and
+// the term coefficients); k_exact_output resolves the values and writes the
+// output.  Each sample is computed exactly as in k_exact_finish.  The tables
+// are round-major ([sig][round][capz]) so that both kernels access them
+// contiguously across the entries of a wave.
 __global__ void __launch_bounds__(kDec) k_exact_reest(DecodeArgs D) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x;
@@ -1003,15 +1115,21 @@ __global__ void __launch_bounds__(kDec) k_exact_reest(DecodeArgs D) {
     const uint64_t row = ((uint64_t)sig * D.rounds + r) * D.capz;
     double2* est = reinterpret_cast<double2*>(D.est) + row;
     uint8_t* flag = D.eflag + row;
+    for (uint32_t q = tid; q < zc; q += kDec) D.eord[row + q] = L.ent[q];
     for (uint32_t e = tid; e < zc; e += kDec) {
         const uint32_t h = L.hk[e];
-        const double2 a0 = r0[h];
+        const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
         const double ge = gprime(-bin_offset(zi[e], sigma, b, n, B).o, n, B, g.ws);
+        if (p1 - p0 > 1) {
+            D.egrp[row + e] = p0 << 16 | (p1 - p0);
+            D.ecoef[2 * (row + e)] = ge;
+            D.ecoef[2 * (row + e) + 1] = 0.0;
+        }
         if (ge < D.g_min) {
             flag[e] = 0;
             continue;
         }
-        const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
+        const double2 a0 = r0[h];
         double orr = 0.0, oii = 0.0;
         for (uint32_t q = p0; q < p1; ++q) {
             const uint32_t e2 = L.ent[q];
@@ -1037,23 +1155,10 @@ __global__ void __launch_bounds__(kDec) k_exact_output(DecodeArgs D) {
     const uint64_t* zi = D.zidx + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * D.capz;
     const double* zv = D.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * D.capz * 2;
     const uint64_t base = (uint64_t)sig * D.rounds * D.capz;
-    const double* est = D.est + base * 2;
-    const uint8_t* flag = D.eflag + base;
     double* fin = D.fin + (uint64_t)sig * D.capz * 2;
-    for (uint32_t e = tid; e < zc; e += kDec) {
-        uint32_t iso = 0, crowd = 0;
-        for (uint32_t q = 0; q < R; ++q) {
-            const uint8_t f = flag[(uint64_t)q * D.capz + e];
-            iso |= (f == 1 ? 1u : 0u) << q;
-            crowd |= (f == 2 ? 1u : 0u) << q;
-        }
-        const uint32_t mask = iso ? iso : crowd;
-        const cx<double> v = mask ? median_cx_mask(est + 2 * (uint64_t)e, mask, 2 * (uint64_t)D.capz)
-                                  : cx<double>{zv[2 * e], zv[2 * e + 1]};
-        fin[2 * e] = v.r;
-        fin[2 * e + 1] = v.i;
-    }
-    __syncthreads();
+    const PeelView V{D.est + base * 2, D.eflag + base, D.egrp + base, D.eord + base, D.ecoef + base * 2,
+                     D.capz, 1, D.capz, R};
+    peel_values(V, zc, zv, fin, L.hk, &L.misc[0]);
     uint32_t flags = L.sw[ST_FLAGS];
     const uint32_t nout = write_output(L, zi, fin, zc, false, 0.5 * D.theta, D.cap, D.out_scale,
                                        D.out_idx + (uint64_t)sig * D.cap, D.out_val + (uint64_t)sig * D.cap * 2,
@@ -1403,14 +1508,25 @@ __global__ void __launch_bounds__(kDec) k_gen_reest(GeneralArgs G) {
         }
         __syncthreads();
         group_by_bin(L, zc, B);
+        uint16_t* ord = G.eord + ((uint64_t)sig * nmeas + meas) * G.capz;
+        for (uint32_t q = tid; q < zc; q += kDec) ord[q] = L.ent[q];
+        const uint64_t base = (uint64_t)sig * G.capz * nmeas + meas;
         for (uint32_t e = tid; e < zc; e += kDec) {
             const double ge = L.t[2 * e + 1].r;
+            const uint32_t h = L.hk[e];
+            const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
+            const uint64_t slot = base + (uint64_t)e * nmeas;
+            const uint64_t pe = (as * L.zl[e]) & mask;
+            if (p1 - p0 > 1) {
+                const cx<double> c = cmul(cx<double>{ge, 0.0}, omega_d(pe, n));
+                G.egrp[slot] = p0 << 16 | (p1 - p0);
+                G.ecoef[2 * slot] = c.r;
+                G.ecoef[2 * slot + 1] = c.i;
+            }
             if (ge < G.g_min) {
                 flag[(uint64_t)e * nmeas + meas] = 0;
                 continue;
             }
-            const uint32_t h = L.hk[e];
-            const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
             cx<double> others{0.0, 0.0};
             for (uint32_t q = p0; q < p1; ++q) {
                 const uint32_t e2 = L.ent[q];
@@ -1418,7 +1534,6 @@ __global__ void __launch_bounds__(kDec) k_gen_reest(GeneralArgs G) {
                 others = cadd(others, L.t[2 * e2]);
             }
             const cx<double> u = csub(cx<double>{rawv[2 * h], rawv[2 * h + 1]}, others);
-            const uint64_t pe = (as * L.zl[e]) & mask;
             const cx<double> v = cmul(u, omega_d((n - pe) & mask, n));
             double* dst = est + ((uint64_t)e * nmeas + meas) * 2;
             dst[0] = v.r / ge;
@@ -1444,29 +1559,11 @@ __global__ void __launch_bounds__(kDec) k_gen_output(GeneralArgs G) {
     const double* zv = G.zval + ((uint64_t)sig * 2 + L.sw[ST_ZBUF]) * G.capz * 2;
     const uint32_t nmeas = G.R * G.R_est;
     const uint32_t used = (R < G.R ? R : G.R) * G.R_est;
-    double* est = G.est + (uint64_t)sig * G.capz * nmeas * 2;
-    const uint8_t* flag = G.eflag + (uint64_t)sig * G.capz * nmeas;
+    const uint64_t base = (uint64_t)sig * G.capz * nmeas;
     double* fin = G.fin + (uint64_t)sig * G.capz * 2;
-    for (uint32_t e = tid; e < zc; e += kDec) {
-        const uint8_t* fl = flag + (uint64_t)e * nmeas;
-        double* src = est + (uint64_t)e * nmeas * 2;
-        uint32_t na = 0;
-        for (uint32_t q = 0; q < used; ++q) na += fl[q] == 1;
-        const uint8_t want = na ? 1 : 2;
-        uint32_t c = 0;
-        for (uint32_t q = 0; q < used; ++q)
-            if (fl[q] == want) {
-                if (c != q) {
-                    src[2 * c] = src[2 * q];
-                    src[2 * c + 1] = src[2 * q + 1];
-                }
-                ++c;
-            }
-        const cx<double> v = c ? median_cx<kMaxMeas>(src, c) : cx<double>{zv[2 * e], zv[2 * e + 1]};
-        fin[2 * e] = v.r;
-        fin[2 * e + 1] = v.i;
-    }
-    __syncthreads();
+    const PeelView V{G.est + base * 2, G.eflag + base, G.egrp + base, G.eord + base, G.ecoef + base * 2,
+                     1, nmeas, G.capz, used};
+    peel_values(V, zc, zv, fin, L.hk, &L.misc[0]);
     uint32_t flags = L.sw[ST_FLAGS];
     const uint32_t nout = write_output(L, zi, fin, zc, true, 0.0, G.cap, G.out_scale,
                                        G.out_idx + (uint64_t)sig * G.cap, G.out_val + (uint64_t)sig * G.cap * 2,

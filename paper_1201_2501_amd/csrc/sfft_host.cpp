@@ -168,6 +168,9 @@ struct sfft_plan_s {
     uint64_t* cand_raw = nullptr;
     uint32_t* cand_cnt = nullptr;
     uint8_t* eflag = nullptr;
+    uint32_t* egrp = nullptr;
+    uint16_t* eord = nullptr;
+    double* ecoef = nullptr;
     double* gterm = nullptr;
     uint32_t* ecount = nullptr;
     uint32_t* state = nullptr;
@@ -431,6 +434,9 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     ST_TRY(dev_alloc(p, &p->zval, S * 4 * Z));
     ST_TRY(dev_alloc(p, &p->est, S * Z * meas * 2));
     ST_TRY(dev_alloc(p, &p->eflag, S * Z * meas));
+    ST_TRY(dev_alloc(p, &p->egrp, S * Z * meas));
+    ST_TRY(dev_alloc(p, &p->eord, S * Z * meas));
+    ST_TRY(dev_alloc(p, &p->ecoef, S * Z * meas * 2));
     ST_TRY(dev_alloc(p, &p->fin, S * Z * 2));
     ST_TRY(dev_alloc(p, &p->gtmp, S * Z * 4));
     ST_TRY(dev_alloc(p, &p->ecount, S * Z));
@@ -519,6 +525,9 @@ DecodeArgs base_decode(const sfft_plan_s* p, uint32_t count, const uint64_t* see
     D.gtmp = p->gtmp;
     D.ecount = p->ecount;
     D.eflag = p->eflag;
+    D.egrp = p->egrp;
+    D.eord = p->eord;
+    D.ecoef = p->ecoef;
     D.state = p->state;
     D.theta = p->d.theta;
     D.g_min = p->d.g_min;
@@ -567,6 +576,9 @@ GeneralArgs base_general(const sfft_plan_s* p, uint32_t count, const uint64_t* s
     G.cand_raw = p->cand_raw;
     G.cand_cnt = p->cand_cnt;
     G.eflag = p->eflag;
+    G.egrp = p->egrp;
+    G.eord = p->eord;
+    G.ecoef = p->ecoef;
     G.gterm = p->gterm;
     G.nterm = std::max<uint32_t>(p->R, p->d.R_est);
     G.state = p->state;
@@ -620,6 +632,9 @@ void offset_decode(const sfft_plan_s* p, DecodeArgs& D, uint32_t off) {
     D.gtmp += o * Z * 4;
     D.ecount += o * Z;
     D.eflag += o * Z * p->R;
+    D.egrp += o * Z * p->R;
+    D.eord += o * Z * p->R;
+    D.ecoef += o * Z * p->R * 2;
     D.state += o * kStateWords;
     if (D.seeds) D.seeds += o;
     D.out_idx += o * p->cap;
@@ -647,6 +662,9 @@ void offset_general(const sfft_plan_s* p, GeneralArgs& G, uint32_t off) {
     G.cand_raw += o * Bm;
     G.cand_cnt += o;
     G.eflag += o * Z * meas;
+    G.egrp += o * Z * meas;
+    G.eord += o * Z * meas;
+    G.ecoef += o * Z * meas * 2;
     G.gterm += o * std::max<uint64_t>(p->R, p->d.R_est) * Z * 4;
     G.state += o * kStateWords;
     if (G.seeds) G.seeds += o;

@@ -122,12 +122,14 @@ struct DecodeArgs {
     double* cand_v;            // [sig][Bmax][2]
     uint64_t* zidx;            // [sig][2][capz]
     double* zval;              // [sig][2][capz][2]
-    double* est;               // re-estimation samples: [sig][rounds][capz][2] (split finish) or
-                               // [sig][capz][rounds][2] (one-workgroup finish)
+    double* est;               // re-estimation samples: [sig][rounds][capz][2]
     double* fin;               // [sig][capz][2] re-estimated values
     double* gtmp;              // [sig][capz][4] per-entry terms when LDS cannot hold them
     uint32_t* ecount;          // [sig][capz] samples per entry
     uint8_t* eflag;            // [sig][rounds][capz] sample kind: 0 none, 1 isolated, 2 crowded
+    uint32_t* egrp;            // [sig][rounds][capz] bin of a shared entry: first grouped position << 16 | members
+    uint16_t* eord;            // [sig][rounds][capz] entries grouped by bin
+    double* ecoef;             // [sig][rounds][capz][2] term coefficient G' of a shared entry
     uint32_t* state;           // [sig][kStateWords]
     double theta, g_min;
     double ratio_tol;          // decode a bin only if its two squared magnitudes agree within this (0: off)
@@ -173,6 +175,9 @@ struct GeneralArgs {
     uint64_t* cand_raw;          // [sig][Bmax] located candidates in arrival order
     uint32_t* cand_cnt;          // [sig] located candidates, then distinct candidates
     uint8_t* eflag;              // [sig][capz][R * R_est] re-estimation sample: 0 none, 1 isolated, 2 crowded
+    uint32_t* egrp;              // [sig][capz][R * R_est] bin of a shared entry: first grouped position << 16 | members
+    uint16_t* eord;              // [sig][R * R_est][capz] entries grouped by bin
+    double* ecoef;               // [sig][capz][R * R_est][2] term coefficient G' omega^{a sigma i} of a shared entry
     double* gterm;               // [sig][nterm][capz][4] term spill of the per-hashing workgroups
     uint32_t nterm;              // max(R, R_est)
     uint64_t* out_idx;

@@ -30,10 +30,12 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def make_plan(n, k, B, seed, prec, max_batch=1, delta=1e-6):
+def make_plan(n, k, B, seed, prec, max_batch=1, delta=1e-6, est_prec=None):
+    """General-mode plan: LocateInner pairs in `prec` arithmetic (0 FP32, 1
+    FP64), EstimateValues hashings in `est_prec` (default: the same)."""
     from paper_1201_2501_amd.sfft import Plan, SFFT_MODE_GENERAL
-    return Plan(n, k, B, 0, seed, mode=SFFT_MODE_GENERAL, delta=delta, loc_prec=prec, est_prec=prec,
-                max_batch=max_batch)
+    return Plan(n, k, B, 0, seed, mode=SFFT_MODE_GENERAL, delta=delta, loc_prec=prec,
+                est_prec=prec if est_prec is None else est_prec, max_batch=max_batch)
 
 
 def oracle_params(plan, seed=None):
@@ -196,4 +198,63 @@ def test_c4_shape_raw_hashings_and_recovery(torch_dev):
         if s == 0:   # the oracle's own FFT at 2^26 points takes most of a minute
             ratio, _ = l2l2_ratio(X[s].cpu().numpy(), k, idx, v)
             assert ratio <= 2.0, ratio
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_batched_general_c2_shape_matches_oracle(torch_dev, prec):
+    """Batched general mode at n = 2^20, k = 64, B = 1024, tail/head 0.05:
+    each of four signals (own seeds) against the oracle run with its seed."""
+    torch, dev = torch_dev
+    n, k, B, count = 1 << 20, 64, 1024, 4
+    say("batched-general-c2", "prec", prec, "count", count)
+    plan = make_plan(n, k, B, 0, prec, max_batch=count)
+    xs = [siggen.planted_signal(n, k, 900 + s, np.complex64, noise_ratio=0.05)[0] for s in range(count)]
+    seeds = [101 + 13 * s for s in range(count)]
+    X = torch.from_numpy(np.stack(xs)).to(dev)
+    bufs = plan.execute_batch(X, torch.tensor(seeds, dtype=torch.int64, device=dev))
+    torch.cuda.synchronize()
+    for s in range(count):
+        c = int(bufs["counts"][s])
+        idx, v = bufs["idx"][s, :c].cpu().numpy(), bufs["val"][s, :c].cpu().numpy()
+        ref = sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        check(idx, v, ref, 1e-10 if prec == 1 else 1e-4, allow_near_tie=(prec == 0))
+        ratio, _ = l2l2_ratio(xs[s], k, idx, v)
+        assert ratio <= 2.0, (s, ratio)
+    plan.close()
+
+
+@pytest.fixture(scope="module")
+def c4_case(torch_dev):
+    """One n = 2^26, k = 1024 signal (unit magnitudes, tail/head 0.01) on the
+    device and its oracle run (B = 4096, delta = 1e-7, default rounds)."""
+    torch, dev = torch_dev
+    n, k, B, seed = 1 << 26, 1024, 4096, 17
+    X, sups, _ = siggen.torch_planted_batch(n, k, [91_000], dev, magnitude="unit", noise_ratio=0.01, chunk=1)
+    plan = make_plan(n, k, B, seed, 1, delta=1e-7)
+    params = oracle_params(plan)
+    plan.close()
+    x0 = X[0].cpu().numpy()
+    ref = sparse_fft(x0, params)
+    return X, x0, np.sort(sups[0]), ref, params
+
+
+@pytest.mark.parametrize("loc,est", [(0, 0), (1, 0), (1, 1)], ids=["f32", "f64loc", "f64"])
+def test_c4_precision_variants_match_oracle(torch_dev, c4_case, loc, est):
+    """The precision split at n = 2^26, k = 1024 against the FP64 oracle:
+    FP32 location and estimation hashings, FP64 location with FP32
+    estimation, FP64 throughout (the final re-estimation is FP64 in all
+    three).  Supports bit-exact (FP32 location: or differing only where the
+    oracle has a near-tie decision); values within 1e-10 relative when the
+    estimation hashings are FP64, else 1e-4."""
+    torch, dev = torch_dev
+    X, x0, sup, ref, params = c4_case
+    say("c4-precision", "loc", loc, "est", est)
+    plan = make_plan(params.n, params.k, params.B, params.seed, loc, delta=params.delta, est_prec=est)
+    d = plan.desc
+    assert (d.loc_prec, d.est_prec, d.w, d.rounds) == (loc, est, params.w, params.rounds)
+    idx, v, info, st = plan.execute(X[0])
+    same = check(idx, v, ref, 1e-10 if est == 1 else 1e-4, allow_near_tie=(loc == 0))
+    if same:
+        assert np.array_equal(idx, sup)
     plan.close()
