@@ -376,10 +376,12 @@ uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
  *     magnitude (exact mode: those above theta/2);
  *   * each shape gets up to `instances` resident plan instances (workspace
  *     for `slots` signals each), created when needed, each on a thread of
- *     its own; idle instances of other shapes with no waiting request are
- *     evicted, least recently used first, when a new one would exceed
- *     `budget_bytes` (which counts the library's allocations, not the work
- *     areas hipFFT allocates for the dense path's plans);
+ *     its own; idle sparse-path instances of other shapes with no waiting
+ *     request are evicted, least recently used first, when a new one would
+ *     exceed `budget_bytes` (which counts the library's allocations, not the
+ *     work areas hipFFT allocates for the dense path's plans); no eviction
+ *     runs while an instance is being built; dense-path instances are not
+ *     evicted (see SFFT_SERVER_EVICT_DENSE);
  *   * a scheduler thread batches the waiting requests of each shape (oldest
  *     shape first) onto idle instances, one stream per instance, so batches
  *     of different shapes overlap on the device.
@@ -403,6 +405,13 @@ typedef struct sfft_server_s* sfft_server_t;
                                         gathered samples (without either flag a shape
                                         goes dense when its sparse plan gathers more
                                         than SFFT_SERVER_DENSE_SAMPLES_PER_N x n samples) */
+#define SFFT_SERVER_EVICT_DENSE 0x8u /* also evict idle dense-path instances (by default
+                                        they stay resident until the server is destroyed,
+                                        and a shape that cannot fit beside them fails with
+                                        SFFT_EBUDGET).  Not exercised on the GPU: a run
+                                        that evicted and rebuilt hipFFT-backed instances
+                                        under a small budget once stopped making progress,
+                                        cause not found                                 */
 #define SFFT_SERVER_DENSE_SAMPLES_PER_N 0.5
 
 typedef struct {
@@ -438,6 +447,9 @@ typedef struct {
     double queue_ms;         /* submit -> launch                                */
     double service_ms;       /* launch -> results on the host                   */
     double latency_ms;       /* submit -> results on the host                   */
+    char message[128];       /* why it failed, NUL-terminated (empty on success):
+                                the failing build or launch call and its HIP
+                                error, or the budget reason                     */
 } sfft_request_result_t;
 
 typedef struct {

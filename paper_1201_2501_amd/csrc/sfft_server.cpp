@@ -172,6 +172,7 @@ struct Request {
     int32_t path = 0;
     bool launched = false;
     bool done = false;
+    std::string message;   // why it failed (empty on success)
 };
 
 struct Instance {
@@ -205,6 +206,7 @@ struct Instance {
     bool busy = false;
     bool building = false;                  // its build thread has not finished
     sfft_status_t build_status = SFFT_OK;   // what the build returned
+    std::string build_message;              // and its message, when it failed
     std::vector<Request*> batch;
     Clock::time_point last_used;
 };
@@ -462,10 +464,11 @@ sfft_status_t launch_batch(Instance* in) {
     return SFFT_OK;
 }
 
-void fail_requests(sfft_server_s* s, std::vector<Request*>& rs, sfft_status_t st) {
+void fail_requests(sfft_server_s* s, std::vector<Request*>& rs, sfft_status_t st, const std::string& msg) {
     const Clock::time_point now = Clock::now();
     for (Request* r : rs) {
         r->status = st;
+        r->message = msg;
         r->done = true;
         r->t_done = now;
         ++s->failed;
@@ -483,10 +486,13 @@ void fail_requests(sfft_server_s* s, std::vector<Request*>& rs, sfft_status_t st
 void build_worker(sfft_server_s* s, Instance* in) {
     if (!in->fake) (void)hipSetDevice(s->d.device);
     const sfft_status_t st = build_instance(in);
+    // the message of a failure is thread-local: take it on this thread
+    const std::string msg = st != SFFT_OK ? std::string(sfft_last_error()) : std::string();
     if (st != SFFT_OK) destroy_instance(in);
     std::lock_guard<std::mutex> lock(s->mu);
     in->building = false;
     in->build_status = st;
+    in->build_message = msg;
     if (st == SFFT_OK) {
         in->busy = false;
         in->last_used = Clock::now();
@@ -498,7 +504,7 @@ void build_worker(sfft_server_s* s, Instance* in) {
 }
 
 Instance* instance_for(sfft_server_s* s, uint64_t key, const Request* head, std::unique_lock<std::mutex>& lk,
-                       sfft_status_t* hard_fail) {
+                       sfft_status_t* hard_fail, std::string* why) {
     uint32_t have = 0;
     for (auto it = s->inst.begin(); it != s->inst.end(); ++it) {
         Instance* in = it->get();
@@ -506,6 +512,7 @@ Instance* instance_for(sfft_server_s* s, uint64_t key, const Request* head, std:
         if (!in->building && in->build_status != SFFT_OK) {
             // a failed build (already released): the shape cannot run
             *hard_fail = in->build_status;
+            *why = "instance build failed: " + in->build_message;
             s->bytes_in_use -= in->bytes;
             s->inst.erase(it);
             return nullptr;
@@ -520,18 +527,37 @@ Instance* instance_for(sfft_server_s* s, uint64_t key, const Request* head, std:
     const size_t need = shape->bytes;
     if (need > s->d.budget_bytes) {
         *hard_fail = SFFT_EBUDGET;
+        *why = "one instance of this shape exceeds the server's budget";
         return nullptr;
+    }
+    // Dense-path instances stay resident unless SFFT_SERVER_EVICT_DENSE: their
+    // bytes are held for good, and a shape that cannot fit beside them never
+    // will.
+    const bool evict_dense = (s->d.flags & SFFT_SERVER_EVICT_DENSE) != 0;
+    if (!evict_dense) {
+        size_t pinned = 0;
+        for (auto& up : s->inst)
+            if (up->dense) pinned += up->bytes;
+        if (pinned + need > s->d.budget_bytes) {
+            if (have == 0) {   // else the shape's own instances serve it
+                *hard_fail = SFFT_EBUDGET;
+                *why = "the budget is held by resident dense-path instances, which are not evicted";
+            }
+            return nullptr;
+        }
     }
     // Evict idle instances, least recently used first.  Their memory is
     // released with the lock dropped: freeing device memory synchronises the
     // device, and the completion callbacks of running batches take the lock.
+    // No eviction runs while an instance is being built, so that the frees
+    // never overlap a build's allocations, FFT plan set-up and warm-up.
     std::vector<std::unique_ptr<Instance>> evicted;
-    while (s->bytes_in_use + need > s->d.budget_bytes) {
+    while (s->bytes_in_use + need > s->d.budget_bytes && s->builders == 0) {
         // idle instances whose shape has no waiting request (an instance just
         // built for waiting requests is about to be used)
         auto victim = s->inst.end();
         for (auto it = s->inst.begin(); it != s->inst.end(); ++it) {
-            if ((*it)->busy) continue;
+            if ((*it)->busy || ((*it)->dense && !evict_dense)) continue;
             const auto q = s->queues.find((*it)->key);
             if (q != s->queues.end() && !q->second.empty()) continue;
             if (victim == s->inst.end() || (*it)->last_used < (*victim)->last_used) victim = it;
@@ -572,6 +598,7 @@ Instance* instance_for(sfft_server_s* s, uint64_t key, const Request* head, std:
         s->bytes_in_use -= need;
         s->inst.pop_back();
         *hard_fail = SFFT_ENOMEM;
+        *why = "could not start a build thread";
     }
     return nullptr;   // the shape's requests wait for the build
 }
@@ -613,14 +640,15 @@ void scheduler(sfft_server_s* s) {
             auto& q = s->queues[o.second];
             if (q.empty()) continue;
             sfft_status_t hard = SFFT_OK;
-            Instance* in = instance_for(s, o.second, q.front(), lk, &hard);
+            std::string why;
+            Instance* in = instance_for(s, o.second, q.front(), lk, &hard, &why);
             if (!in) {
                 if (hard != SFFT_OK) {   // the shape can never run: fail its waiting requests
                     std::vector<Request*> rs(q.begin(), q.end());
                     s->pending -= (uint32_t)rs.size();
                     s->inflight += (uint32_t)rs.size();
                     q.clear();
-                    fail_requests(s, rs, hard);
+                    fail_requests(s, rs, hard, why);
                 }
                 continue;
             }
@@ -639,9 +667,11 @@ void scheduler(sfft_server_s* s) {
             s->batched += in->batch.size();
             lk.unlock();
             const sfft_status_t st = launch_batch(in);
+            // launch_batch's message is this thread's: take it before the lock
+            const std::string msg = st != SFFT_OK ? "launch failed: " + std::string(sfft_last_error()) : std::string();
             lk.lock();
             if (st != SFFT_OK) {
-                fail_requests(s, in->batch, st);
+                fail_requests(s, in->batch, st, msg);
                 in->busy = false;
             }
             launched = true;
@@ -705,7 +735,8 @@ sfft_status_t sfft_server_create(const sfft_server_desc_t* d, sfft_server_t* out
     if (d->slots < 1 || d->slots > 1024 || d->instances < 1 || d->instances > 16 || d->budget_bytes == 0 ||
         !(d->theta > 0) || !(d->delta_exact > 0 && d->delta_exact < 1) ||
         !(d->delta_general > 0 && d->delta_general < 1) ||
-        (d->flags & ~(SFFT_SERVER_FAKE_DEVICE | SFFT_SERVER_DENSE_ONLY | SFFT_SERVER_SPARSE_ONLY)) ||
+        (d->flags & ~(SFFT_SERVER_FAKE_DEVICE | SFFT_SERVER_DENSE_ONLY | SFFT_SERVER_SPARSE_ONLY |
+                      SFFT_SERVER_EVICT_DENSE)) ||
         ((d->flags & SFFT_SERVER_DENSE_ONLY) && (d->flags & SFFT_SERVER_SPARSE_ONLY)) ||
         !(d->fake_service_ms >= 0))
         return set_last_error(SFFT_EINVAL, "bad server description");
@@ -758,6 +789,8 @@ static sfft_status_t take_result(sfft_server_s* s, std::unordered_map<uint64_t, 
         res->queue_ms = r->t_launch.time_since_epoch().count() ? ms_between(r->t_submit, r->t_launch) : 0.0;
         res->service_ms = r->t_launch.time_since_epoch().count() ? ms_between(r->t_launch, r->t_done) : 0.0;
         res->latency_ms = ms_between(r->t_submit, r->t_done);
+        std::memset(res->message, 0, sizeof(res->message));
+        std::strncpy(res->message, r->message.c_str(), sizeof(res->message) - 1);
     }
     const sfft_status_t st = (sfft_status_t)r->status;
     s->reqs.erase(it);
@@ -775,6 +808,7 @@ sfft_status_t sfft_server_cancel(sfft_server_t srv, uint64_t ticket) {
     q.erase(std::find(q.begin(), q.end(), r));
     --srv->pending;
     r->status = SFFT_ECANCELED;
+    r->message = "canceled";
     r->t_done = Clock::now();
     r->done = true;
     srv->cv_done.notify_all();

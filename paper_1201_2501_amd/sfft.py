@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsfft.so"
 SFFT_SERVER_FAKE_DEVICE = 0x1
 SFFT_SERVER_DENSE_ONLY = 0x2
 SFFT_SERVER_SPARSE_ONLY = 0x4
+SFFT_SERVER_EVICT_DENSE = 0x8
 SFFT_SERVER_DENSE_SAMPLES_PER_N = 0.5
 SFFT_MODE_EXACT, SFFT_MODE_GENERAL = 0, 1
 SFFT_C64, SFFT_C128 = 0, 1
@@ -67,7 +68,7 @@ class Request(ctypes.Structure):
 class RequestResult(ctypes.Structure):
     _fields_ = [("status", c_int32), ("count", c_uint32), ("flags", c_uint32), ("rounds", c_uint32),
                 ("path", c_int32), ("reserved", c_uint32), ("queue_ms", c_double), ("service_ms", c_double),
-                ("latency_ms", c_double)]
+                ("latency_ms", c_double), ("message", ctypes.c_char * 128)]
 
 
 class ServerStats(ctypes.Structure):
@@ -140,11 +141,14 @@ def load():
 
 
 class SfftError(RuntimeError):
-    def __init__(self, status, where):
+    """A failed call: its status and message (by default this thread's
+    sfft_last_error; a served request brings its own)."""
+
+    def __init__(self, status, where, message=None):
         lib = load()
         self.status = status
-        super().__init__("%s: %s (%s)" % (where, lib.sfft_status_string(status).decode(),
-                                          lib.sfft_last_error().decode()))
+        self.message = lib.sfft_last_error().decode() if message is None else message
+        super().__init__("%s: %s (%s)" % (where, lib.sfft_status_string(status).decode(), self.message))
 
 
 def _check(status, where, allow=()):
@@ -470,7 +474,7 @@ class Server:
     def _finish(self, t, st, res):
         x, idx, val = self._live.pop(t)
         if st != SFFT_OK:
-            raise SfftError(st, "served request")
+            raise SfftError(st, "served request", res.message.decode(errors="replace"))
         c = res.count
         return idx[:c].astype(np.int64), val[:c, 0] + 1j * val[:c, 1], res
 

@@ -108,7 +108,7 @@ def test_plan_device_bytes_scales_with_batch_and_rejects_bad_descs():
 
 @pytest.mark.parametrize("field,value", [("slots", 0), ("instances", 0), ("budget_bytes", 0), ("theta", 0.0),
                                          ("delta_exact", 1.5), ("delta_general", 0.0), ("instances", 17),
-                                         ("flags", 0x6), ("flags", 0x8)])
+                                         ("flags", 0x6), ("flags", 0x10)])
 def test_server_create_rejects_bad_descs(field, value):
     lib = sfft.load()
     d = sfft.sfft_server_desc_init()
@@ -248,11 +248,67 @@ def test_fake_server_cancels_requests_that_have_not_launched():
         srv.close()
 
 
+def test_fake_server_keeps_dense_instances_resident():
+    """Dense-path instances are not evicted: two sparse shapes that fit beside
+    the dense one only one at a time are evicted around it, every request is
+    served and the dense shape is built once."""
+    sd = sfft.sfft_server_desc_init()
+    sd.slots = 2
+    dense = (1 << 16, 600, 0)
+    sparse = [(1 << 20, 64, 0), (1 << 22, 100, 0)]
+    assert sfft.sfft_server_shape(sd, *dense)[1] and not any(sfft.sfft_server_shape(sd, *s)[1] for s in sparse)
+    dbytes = sfft.sfft_server_shape(sd, *dense)[2]
+    sizes = [sfft.sfft_server_shape(sd, *s)[2] for s in sparse]
+    budget = dbytes + max(sizes) + min(sizes) // 2
+    srv = FakeServer(slots=2, instances=1, budget_bytes=budget, fake_service_ms=1.0)
+    try:
+        for rep in range(5):
+            tickets = [srv.submit(*sh, seed=rep)[1] for sh in [dense] + sparse]
+            for t in tickets:
+                st, res = srv.wait(t)
+                assert st == sfft.SFFT_OK, res.message
+        s = srv.stats()
+        assert s.completed == 15 and s.failed == 0 and s.peak_bytes <= budget
+        assert s.evictions >= 4                  # the sparse shapes take turns
+        assert s.instances == 2                  # the dense instance and one sparse
+    finally:
+        srv.close()
+
+
+def test_fake_server_fails_a_shape_that_cannot_fit_beside_dense_instances():
+    """A shape whose instance does not fit beside the resident dense-path
+    instances fails with SFFT_EBUDGET and a message that says why; with
+    SFFT_SERVER_EVICT_DENSE the dense instance is evicted instead."""
+    sd = sfft.sfft_server_desc_init()
+    sd.slots = 2
+    dense = (1 << 16, 600, 0)
+    sparse = (1 << 22, 100, 0)
+    dbytes = sfft.sfft_server_shape(sd, *dense)[2]
+    sbytes = sfft.sfft_server_shape(sd, *sparse)[2]
+    budget = max(dbytes, sbytes) + min(dbytes, sbytes) // 2
+    for flags, expect in ((0, sfft.SFFT_EBUDGET), (sfft.SFFT_SERVER_EVICT_DENSE, sfft.SFFT_OK)):
+        srv = FakeServer(slots=2, instances=1, budget_bytes=budget, fake_service_ms=1.0,
+                         flags=sfft.SFFT_SERVER_FAKE_DEVICE | flags)
+        try:
+            st, res = srv.wait(srv.submit(*dense)[1])
+            assert st == sfft.SFFT_OK and res.message == b""
+            st, res = srv.wait(srv.submit(*sparse)[1])
+            assert st == expect
+            if expect == sfft.SFFT_EBUDGET:
+                assert b"dense-path instances" in res.message
+                assert srv.stats().failed == 1
+            else:
+                assert srv.stats().evictions == 1
+        finally:
+            srv.close()
+
+
 def test_fake_server_many_shapes_tight_budget_with_cancels():
-    """Instances are built on threads of their own and idle ones are evicted
-    under a budget barely above the largest instance: every request of a
-    stream over 24 shapes (with cancels) ends served or canceled, none fails,
-    and the budget holds."""
+    """Instances are built on threads of their own and idle ones (dense-path
+    ones too, with SFFT_SERVER_EVICT_DENSE) are evicted under a budget barely
+    above the largest instance: every request of a stream over 24 shapes
+    (with cancels) ends served or canceled, none fails, and the budget
+    holds."""
     import random
     rng = random.Random(7)
     shapes = [(1 << e, k, m) for e in (16, 18, 20, 22) for k in (8, 100, 600) for m in (0, 1)]
@@ -261,7 +317,8 @@ def test_fake_server_many_shapes_tight_budget_with_cancels():
     sizes = [sfft.sfft_server_shape(sd, *s)[2] for s in shapes]
     for budget_factor, instances, service in ((1.05, 1, 0.5), (1.5, 2, 0.0), (3.0, 3, 2.0)):
         budget = int(max(sizes) * budget_factor)
-        srv = FakeServer(slots=4, instances=instances, budget_bytes=budget, fake_service_ms=service)
+        srv = FakeServer(slots=4, instances=instances, budget_bytes=budget, fake_service_ms=service,
+                         flags=sfft.SFFT_SERVER_FAKE_DEVICE | sfft.SFFT_SERVER_EVICT_DENSE)
         try:
             tickets, canceled = [], 0
             for i in range(300):
