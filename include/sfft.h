@@ -481,6 +481,24 @@ sfft_status_t sfft_dense_topk(const void* spec_dev, uint64_t n, uint32_t count, 
                               double keep_above, uint64_t* idx_dev, double* val_dev, uint32_t* count_dev,
                               void* scratch_dev, void* stream);
 
+/* sfft_dense_topk without the scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same selection and results, with
+ * the scratch taken from a static device array that the library holds on
+ * each device from load to process end (about 1.3 MB, room for
+ * sfft_dense_topk_noalloc_max_count() = 64 spectra).  It calls no
+ * allocating routine; its first call on a device looks up that device's
+ * address of the array.  Every call on one device shares that array, which
+ * keeps the last call's contents (each call clears what it needs with a
+ * kernel, no memset): calls that overlap on one device, on different
+ * streams or threads, race and must be serialised by the caller.
+ * Errors: as sfft_dense_topk, and SFFT_EINVAL for count above the maximum
+ * (nothing is launched). */
+uint32_t sfft_dense_topk_noalloc_max_count(void);
+sfft_status_t sfft_dense_topk_noalloc(const void* spec_dev, uint64_t n, uint32_t count, uint32_t cap, double scale,
+                                      double keep_above, uint64_t* idx_dev, double* val_dev, uint32_t* count_dev,
+                                      void* stream);
+
 /* Defaults: 16 GiB budget, 32 slots, 2 instances per shape, device 0,
  * delta 1e-9 (exact) / 1e-6 (general), theta 0.25.  Errors: SFFT_EINVAL. */
 sfft_status_t sfft_server_desc_init(sfft_server_desc_t* d);

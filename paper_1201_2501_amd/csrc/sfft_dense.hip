@@ -15,6 +15,7 @@
 // kept bins in index order.  Kept: key > T, and the first take_eq bins with key == T;
 // with keep_above >= 0 only bins whose key exceeds that of keep_above.
 #include <cstring>
+#include <mutex>
 
 #include "sfft_device.hpp"
 
@@ -273,6 +274,42 @@ uint32_t topk_chunks(uint64_t n) {
 }  // namespace
 
 size_t dense_topk_scratch_bytes(uint32_t count) { return (size_t)count * kTkStride * sizeof(uint32_t); }
+
+// --------------------------------------------------- no-allocation variant --
+// The scratch of sfft_dense_topk_noalloc: a file-scope device array with room
+// for kNoAllocSpectra spectra (about 1.3 MB), which each device holds from
+// module load to process end.  In host code its name is only a stand-in for
+// the symbol: kernels get the address hipGetSymbolAddress returns for the
+// current device, taken once per device and kept.
+constexpr uint32_t kNoAllocSpectra = 64;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) uint32_t noalloc_scratch[(size_t)kNoAllocSpectra * kTkStride];
+
+namespace {
+std::mutex g_noalloc_mu;
+uint32_t* g_noalloc_ptr[kNoAllocDevices] = {};
+}  // namespace
+
+uint32_t dense_topk_noalloc_max_count() { return kNoAllocSpectra; }
+
+// The current device's address of noalloc_scratch (looked up on the first
+// call on that device).
+hipError_t dense_topk_noalloc_scratch(uint32_t** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoAllocDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_noalloc_ptr[dev] = static_cast<uint32_t*>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_dense_topk(const float2* spec, uint64_t n, uint32_t count, uint32_t cap, double scale,
                              double keep_above, uint64_t* out_idx, double* out_val, uint32_t* out_count,

@@ -212,6 +212,10 @@ size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax);
 // (times scale) above it are kept.  scratch: dense_topk_scratch_bytes(count)
 // of device memory, overwritten.
 size_t dense_topk_scratch_bytes(uint32_t count);
+// the static scratch of the no-allocation top-k: its capacity in spectra and
+// the current device's address of it (looked up once per device)
+uint32_t dense_topk_noalloc_max_count();
+hipError_t dense_topk_noalloc_scratch(uint32_t** out);
 hipError_t launch_dense_topk(const float2* spec, uint64_t n, uint32_t count, uint32_t cap, double scale,
                              double keep_above, uint64_t* out_idx, double* out_val, uint32_t* out_count,
                              uint32_t* scratch, hipStream_t s);

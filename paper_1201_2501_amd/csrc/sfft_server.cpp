@@ -722,6 +722,27 @@ sfft_status_t sfft_dense_topk(const void* spec_dev, uint64_t n, uint32_t count, 
     return SFFT_OK;
 }
 
+uint32_t sfft_dense_topk_noalloc_max_count(void) { return sfft::dense_topk_noalloc_max_count(); }
+
+sfft_status_t sfft_dense_topk_noalloc(const void* spec_dev, uint64_t n, uint32_t count, uint32_t cap, double scale,
+                                      double keep_above, uint64_t* idx_dev, double* val_dev, uint32_t* count_dev,
+                                      void* stream) {
+    if (!spec_dev || !idx_dev || !val_dev || !count_dev || count == 0 || cap == 0 || cap > 8192 || !(scale > 0))
+        return set_last_error(SFFT_EINVAL, "bad dense top-k arguments");
+    if (count > sfft::dense_topk_noalloc_max_count())
+        return set_last_error(SFFT_EINVAL, "count " + std::to_string(count) + " exceeds the static scratch (" +
+                                               std::to_string(sfft::dense_topk_noalloc_max_count()) + " spectra)");
+    if (!pow2(n) || n < (1ull << 10) || n > (1ull << 30)) return set_last_error(SFFT_ENOTPOW2, "n must be 2^10..2^30");
+    uint32_t* scratch = nullptr;
+    hipError_t e = sfft::dense_topk_noalloc_scratch(&scratch);
+    if (e != hipSuccess)
+        return set_last_error(SFFT_EHIP, std::string("static top-k scratch: ") + hipGetErrorString(e));
+    e = sfft::launch_dense_topk(static_cast<const float2*>(spec_dev), n, count, cap, scale, keep_above, idx_dev,
+                               val_dev, count_dev, scratch, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_last_error(SFFT_EHIP, std::string("dense top-k: ") + hipGetErrorString(e));
+    return SFFT_OK;
+}
+
 sfft_status_t sfft_server_shape(const sfft_server_desc_t* sd, uint64_t n, uint32_t k, int32_t mode,
                                 sfft_plan_desc_t* plan_out, int32_t* dense_out, uint64_t* bytes_out) {
     if (!sd || !plan_out || !dense_out) return set_last_error(SFFT_EINVAL, "NULL argument");

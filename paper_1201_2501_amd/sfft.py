@@ -35,7 +35,8 @@ EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_pla
            "sfft_plan_raw_slot", "sfft_plan_device_bytes", "sfft_plan_samples",
            "sfft_status_string",
            "sfft_last_error", "sfft_splitmix64",
-           "sfft_dense_topk_scratch_bytes", "sfft_dense_topk",
+           "sfft_dense_topk_scratch_bytes", "sfft_dense_topk", "sfft_dense_topk_noalloc_max_count",
+           "sfft_dense_topk_noalloc",
            "sfft_server_desc_init", "sfft_server_shape", "sfft_server_create", "sfft_server_submit",
            "sfft_server_poll", "sfft_server_wait", "sfft_server_cancel", "sfft_server_stats",
            "sfft_server_reset_stats", "sfft_server_destroy"]
@@ -118,12 +119,14 @@ def load():
     lib.sfft_plan_device_bytes.restype = c_uint64
     lib.sfft_plan_samples.argtypes = [POINTER(PlanDesc)]
     lib.sfft_plan_samples.restype = c_uint64
+    lib.sfft_dense_topk_noalloc_max_count.restype = c_uint32
     lib.sfft_server_desc_init.argtypes = [POINTER(ServerDesc)]
     lib.sfft_server_shape.argtypes = [POINTER(ServerDesc), c_uint64, c_uint32, c_int32, POINTER(PlanDesc),
                                       POINTER(c_int32), POINTER(c_uint64)]
     lib.sfft_dense_topk_scratch_bytes.argtypes = [c_uint32]
     lib.sfft_dense_topk_scratch_bytes.restype = c_uint64
     lib.sfft_dense_topk.argtypes = [P, c_uint64, c_uint32, c_uint32, c_double, c_double, P, P, P, P, P]
+    lib.sfft_dense_topk_noalloc.argtypes = [P, c_uint64, c_uint32, c_uint32, c_double, c_double, P, P, P, P]
     lib.sfft_server_create.argtypes = [POINTER(ServerDesc), POINTER(P)]
     lib.sfft_server_submit.argtypes = [P, POINTER(Request), POINTER(c_uint64)]
     lib.sfft_server_poll.argtypes = [P, c_uint64, POINTER(RequestResult)]
@@ -134,7 +137,7 @@ def load():
     lib.sfft_server_destroy.argtypes = [P]
     for name in EXPORTS:
         if name not in ("sfft_default_w", "sfft_status_string", "sfft_last_error", "sfft_splitmix64",
-                        "sfft_plan_h2b_bytes", "sfft_plan_device_bytes"):
+                        "sfft_plan_h2b_bytes", "sfft_plan_device_bytes", "sfft_dense_topk_noalloc_max_count"):
             getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
