@@ -240,13 +240,22 @@ def serving_bench(args, torch, dev, sfft):
         tail = tail_classes(reqs, outs)
         ok_p, n_p, err_p = ok_p + o, n_p + nn, err_p + e
         peak, evict, failed = max(peak, int(st.peak_bytes)), evict + int(st.evictions), failed + int(st.failed)
+        by_path = {}
+        for name, want in (("sparse", 0), ("dense", 1)):
+            lat = [res.latency_ms for (_, _, res) in outs if res.path == want]
+            by_path[name] = {"requests": len(lat), "share": round(len(lat) / len(outs), 4),
+                             "p50_ms": round(percentile(lat, 50), 3) if lat else None,
+                             "p99_ms": round(percentile(lat, 99), 3) if lat else None}
         sweep.append({"load": load, "arrival_rate_per_s": round(rate, 1), "sFFTs_per_s": round(st.rate, 1),
-                      "p50_ms": round(st.p50_ms, 3), "p99_ms": round(st.p99_ms, 3),
+                      "p50_ms": round(st.p50_ms, 3), "p99_ms": round(st.p99_ms, 3), "by_path": by_path,
                       "queue_p50_ms": round(st.queue_p50_ms, 3), "service_p50_ms": round(st.service_p50_ms, 3),
                       "mean_batch": round(st.mean_batch, 2), "dense_fallback": int(st.dense),
                       "max_submit_lag_ms": round(lag * 1e3, 3), "slowest_1pct": tail})
-        log("serving: Poisson %.0f/s (%.2f x capacity) -> p50 %.3f ms p99 %.3f ms, %.0f sFFTs/s"
-            % (rate, load, st.p50_ms, st.p99_ms, st.rate))
+        log("serving: Poisson %.0f/s (%.2f x capacity) -> p50 %.3f ms p99 %.3f ms, %.0f sFFTs/s; sparse %.0f%% "
+            "(p50 %s p99 %s ms), dense p50 %s p99 %s ms"
+            % (rate, load, st.p50_ms, st.p99_ms, st.rate, 100 * by_path["sparse"]["share"],
+               by_path["sparse"]["p50_ms"], by_path["sparse"]["p99_ms"], by_path["dense"]["p50_ms"],
+               by_path["dense"]["p99_ms"]))
     srv.close()
     err_all = err_s + err_p
     mid = sweep[len(sweep) // 2]
@@ -255,7 +264,7 @@ def serving_bench(args, torch, dev, sfft):
             "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default"),
             "capacity_sFFTs_per_s": round(capacity, 1),
             "value": mid["sFFTs_per_s"], "unit": "sFFTs/s", "load": mid["load"],
-            "p50_ms": mid["p50_ms"], "p99_ms": mid["p99_ms"], "sweep": sweep,
+            "p50_ms": mid["p50_ms"], "p99_ms": mid["p99_ms"], "by_path": mid["by_path"], "sweep": sweep,
             "failed": failed, "evictions": evict, "peak_device_bytes": peak,
             "exact_recovered": "%d/%d" % (ok_s + ok_p, n_s + n_p),
             "exact_misses": misses,
@@ -331,6 +340,75 @@ def precision_split_bench(args, torch, dev, sfft, siggen):
             "config": {"workload": "general-mode sFFT: 16 signals, n=2^26, k=1024, complex64, unit magnitudes, "
                                    "tail/head noise 0.01, B=4096, delta=1e-7", "signals": S, "n": n, "k": k, "B": B},
             "variants": variants}
+
+
+def general_schedule_bench(args, torch, dev, sfft, siggen):
+    """The general-case round schedule against fixed B and w (SparseFFT,
+    Algorithm 2): the practical schedule (k_r = k / 4^r, B_r halving down to
+    4 k_r, w_r = w B_r / B) and the same plan with b_min = B (B and w fixed
+    in every round), on two workloads: 64 signals of n = 2^20, k = 64,
+    tail/head 0.05, B = 1024, delta = 1e-6; and 16 signals of n = 2^26,
+    k = 1024, tail/head 0.01, B = 4096, delta = 1e-7 (unit magnitudes,
+    complex64).  Each variant reports the samples one signal gathers and their
+    algorithmic bytes, the batch time, the planted heads found, supports
+    equal to the planted ones, and the l2/l2 ratio against Err(xhat, k) from
+    a full FP64 FFT of the same input bytes."""
+    from paper_1201_2501_amd.sfft import Plan
+    out = []
+    for name, n, k, B, S, noise, delta, gen0 in (("c2", 1 << 20, 64, 1024, 64, 0.05, 1e-6, 95_000),
+                                                 ("c4", 1 << 26, 1024, 4096, 16, 0.01, 1e-7, 90_000)):
+        X, sups, vals = siggen.torch_planted_batch(n, k, [gen0 + s for s in range(S)], dev, magnitude="unit",
+                                                   noise_ratio=noise, chunk=4)
+        seeds = torch.arange(S, dtype=torch.int64, device=dev) * 37 + 11
+        errk = []
+        for s in range(S):
+            F = torch.fft.fft(X[s].to(torch.complex128), norm="ortho").abs().pow(2)
+            errk.append(math.sqrt(max(float(F.sum() - torch.topk(F, k).values.sum()), 0.0)))
+            del F
+        for sched, b_min in (("practical", 0), ("fixed_B_w", B)):
+            plan = Plan(n, k, B, 0, 0, mode=sfft.SFFT_MODE_GENERAL, delta=delta, b_min=b_min, max_batch=S)
+            samples = sfft.sfft_plan_samples(plan.desc)
+            bufs = plan.execute_batch(X, seeds)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                plan.execute_batch(X, seeds, bufs=bufs)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            counts, idx, val = bufs["counts"].cpu().numpy(), bufs["idx"].cpu().numpy(), bufs["val"].cpu().numpy()
+            found = exact = 0
+            ratios = []
+            for s in range(S):
+                c = int(counts[s])
+                found += len(np.intersect1d(idx[s, :c], sups[s]))
+                exact += int(np.array_equal(idx[s, :c], np.sort(sups[s])))
+                Xh = torch.fft.fft(X[s].to(torch.complex128), norm="ortho")
+                est = torch.zeros_like(Xh)
+                est[torch.from_numpy(idx[s, :c]).to(dev)] = torch.from_numpy(val[s, :c]).to(dev)
+                ratios.append(float((Xh - est).abs().pow(2).sum().sqrt()) / errk[s])
+                del Xh, est
+            rec = {"workload": name, "schedule": sched, "n": n, "k": k, "B": B, "signals": S, "noise": noise,
+                   "w": int(plan.desc.w), "rounds": int(plan.desc.rounds), "samples_per_signal": samples,
+                   "alg_bytes_per_signal": samples * 8, "ms_per_batch": round(ms, 3),
+                   "sFFTs_per_s": round(S / (ms * 1e-3), 1), "heads_found": "%d/%d" % (found, S * k),
+                   "supports_equal_planted": "%d/%d" % (exact, S), "l2l2_ratio_max": round(max(ratios), 4),
+                   "l2l2_ratio_median": round(float(np.median(ratios)), 4)}
+            log("gsched %s %s: %d samples/signal, %.3f ms/batch, heads %s, supports %s, l2/l2 max %.4f" % (
+                name, sched, samples, ms, rec["heads_found"], rec["supports_equal_planted"], max(ratios)))
+            out.append(rec)
+            plan.close()
+        del X
+        torch.cuda.empty_cache()
+    head = next(r for r in out if r["workload"] == "c2" and r["schedule"] == "practical")
+    return {"metric": "general-mode schedule: samples and sFFTs/s, practical vs fixed B and w",
+            "value": head["sFFTs_per_s"], "unit": "sFFTs/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": head["ms_per_batch"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "general-mode sFFT, practical schedule vs b_min = B: 64 x 2^20 (k=64, 5% noise) "
+                                   "and 16 x 2^26 (k=1024, 1% noise)"},
+            "variants": out}
 
 
 def section5_bench(args, torch, dev, sfft):
@@ -441,6 +519,9 @@ def main():
     ap.add_argument("--delta", type=float, default=1e-9, help="window accuracy (with --tune off)")
     ap.add_argument("--patience", type=int, default=3, help="empty rounds before a signal stops (with --tune off)")
     ap.add_argument("--hash-threads", type=int, default=256, help="HashToBins workgroup size (with --tune off)")
+    ap.add_argument("--hash-order", type=int, default=None,
+                    help="HashToBins workgroup order over (signal, round): 0 round-major, 1 signal-major, "
+                         "2 signal-major per XCD (default: the plan's)")
     ap.add_argument("--alpha", type=float, default=0.5, help="window transition fraction (with --tune off)")
     ap.add_argument("--stop-count", type=int, default=0,
                     help="stop after --stop-patience empty rounds once this many entries are found (with --tune "
@@ -481,9 +562,10 @@ def main():
     ap.add_argument("--tune-out", default="", help="also store the autotuner's choice in this JSON file")
     ap.add_argument("--tune-confirm", type=int, default=6,
                     help="fresh batches the fastest accepted candidates must also pass")
-    ap.add_argument("--workload", choices=["c3", "c4", "section5"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c4", "section5", "gsched"], default="c3",
                     help="c3: the batched exactly-sparse headline; c4: the general-mode precision split; "
-                         "section5: k-point DFTs through the n-point sFFT against a direct k-point FFT")
+                         "section5: k-point DFTs through the n-point sFFT against a direct k-point FFT; "
+                         "gsched: the general-mode round schedule against fixed B and w")
     ap.add_argument("--config-key", action="store_true",
                     help="print the key that names this configuration in the traffic record, then exit")
     args = ap.parse_args()
@@ -509,6 +591,9 @@ def main():
         return
     if args.workload == "section5":
         print(json.dumps(section5_bench(args, torch, dev, sfft)), flush=True)
+        return
+    if args.workload == "gsched":
+        print(json.dumps(general_schedule_bench(args, torch, dev, sfft, siggen)), flush=True)
         return
     n, k, S = 1 << args.log2n, args.k, args.signals
     loc_prec = sfft.SFFT_F64 if args.loc_prec == "f64" else sfft.SFFT_F32
@@ -556,6 +641,8 @@ def main():
     plan_kw = dict(base_kw, **tuned, max_batch=S, flags=sfft.SFFT_FLAG_TIMING)
     if args.alpha_decay:
         plan_kw["alpha_decay"] = args.alpha_decay
+    if args.hash_order is not None:
+        plan_kw["hash_order"] = args.hash_order
     log("plan: B=%d w=%d %s" % (B, w, ", ".join("%s=%s" % kv for kv in sorted(tuned.items()))))
     plan = Plan(n, k, B, w, 0, **plan_kw)
     desc = plan.desc
@@ -565,6 +652,8 @@ def main():
         args.log2n, k, B, w, desc.b_min, plan.round_groups()[0], desc.hash_threads, S)
     if desc.alpha_decay:
         cfg_key += ",alpha_decay=%g" % desc.alpha_decay
+    if desc.hash_order:
+        cfg_key += ",order=%d" % desc.hash_order
     if args.config_key:
         print(cfg_key)
         plan.close()
@@ -785,7 +874,8 @@ def main():
                    "alpha": desc.alpha, "theta": desc.theta, "g_min": desc.g_min,
                    "stop_count": desc.stop_count, "stop_patience": desc.stop_patience, "ratio_tol": desc.ratio_tol,
                    "alpha_decay": desc.alpha_decay, "samples_per_signal_group0": sfft.sfft_plan_samples(desc),
-                   "hash_threads": desc.hash_threads, "chunks": chunks, "loc_prec": args.loc_prec,
+                   "hash_threads": desc.hash_threads, "hash_order": desc.hash_order, "chunks": chunks,
+                   "loc_prec": args.loc_prec,
                    "input": "complex64"},
         "autotune": tune_rec,
         "latency_ms": {"p10": round(percentile(step_ms, 10), 4), "p50": round(percentile(step_ms, 50), 4),

@@ -96,7 +96,9 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *             SparseFFT rounds (0 = max(7, ceil(log4 k) + 2))
  *   b_min     exact: round r uses B_r = max(B >> r, b_min) bins and a window
  *             of w B_r / B samples (Algorithm 1 shrinks B with k_t = k/2^t);
- *             0 = B/16 (at least 2); b_min = B keeps B fixed
+ *             0 = B/16 (at least 2); b_min = B keeps B fixed.  general:
+ *             a further floor on B_r = max(B >> r, 4 k_r, b_min) (0 = none;
+ *             b_min = B keeps B and w fixed in every round)
  *   patience  exact: stop after this many consecutive rounds whose bins are
  *             all below theta
  *   t, s      LocateInner regions per level and vote tolerance (Algorithm 3)
@@ -137,7 +139,17 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *   group_step  exact mode, batched: rounds of the second round group, each
  *             later group twice the previous (0 = 2, 2, 4, 8, ...).  Launch
  *             shape only
- *   reserved  must be 0
+ *   hash_order  exact mode, batched: order of the (signal, round)
+ *             workgroups of a HashToBins pair launch.  0: round-major (all
+ *             signals' round r, then round r + 1, ...: the largest rounds
+ *             first); 1: signal-major (all rounds of signal 0, then of
+ *             signal 1, ...: fewer signals' samples in flight at once);
+ *             2: signal-major per XCD (workgroups are handed to the 8 XCDs
+ *             in turn, so workgroup j runs on XCD j mod 8: the signals
+ *             s = x (mod 8) go to XCD x, each signal's rounds in a row, so
+ *             they share that XCD's L2; batches whose size is not a
+ *             multiple of 8 take order 1).  Launch shape only: results do
+ *             not depend on it
  *   alpha_decay  exact mode: 0 (or 1) keeps alpha in every round; a value
  *             in (0, 1) shrinks it as the bin count shrinks (Section 3's
  *             alpha_t schedule): round r uses alpha * alpha_decay^m, m = r
@@ -152,7 +164,15 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *             a long window on one CU.  Launch shape only: results equal the
  *             unsplit ones up to the order of floating-point additions, and
  *             do not depend on the batch.  Needs chunks <= 1.
- *   reserved2 must be 0
+ *   hash_mode exact mode, batched path (at most one chunk): 0 gathers every
+ *             round's window (w_r + 1 random samples, a memory line each);
+ *             1 reads the whole signal contiguously instead (stream mode:
+ *             each sample is kept where its permuted position falls in the
+ *             window) for the rounds whose window covers at least n/8
+ *             samples, where n contiguous samples cost no more bytes than
+ *             the gathered lines; 2 streams every round.  The raw bins are
+ *             the same up to the order of floating-point additions.  The
+ *             plain path and general mode always gather
  */
 typedef struct {
     uint64_t n;
@@ -185,10 +205,10 @@ typedef struct {
     uint32_t group0;
     double ratio_tol;
     uint32_t group_step;
-    uint32_t reserved;
+    uint32_t hash_order;
     double alpha_decay;
     uint32_t hash_split;
-    uint32_t reserved2;
+    uint32_t hash_mode;
 } sfft_plan_desc_t;
 
 typedef struct sfft_plan_s* sfft_plan_t;
@@ -198,14 +218,20 @@ typedef struct sfft_plan_s* sfft_plan_t;
  * buffers); 0 when *d does not validate.  Pure host function. */
 uint64_t sfft_plan_device_bytes(const sfft_plan_desc_t* d);
 
-/* Samples of x one signal's sparse transform under *d gathers, counting
+/* Samples of x one signal's sparse transform under *d reads, counting
  * every hashing's window: exact mode, the pair of each round up to the
- * earliest stop (round group 0: w_r + 1 samples per round); general mode,
- * all rounds, each with its LocateInner pairs (2 w_r per pair) and
- * EstimateValues hashings (w_r each).  Each sample is a random access that
- * costs a whole memory line, so this against n sizes the sparse path
- * against a dense FFT.  0 when *d does not validate.  Pure host function. */
+ * earliest stop (round group 0: w_r + 1 samples per round, or n for a round
+ * in stream mode); general mode, all rounds, each with its LocateInner
+ * pairs (2 w_r per pair) and EstimateValues hashings (w_r each).  Each
+ * gathered sample is a random access that costs a whole memory line (a
+ * streamed one an eighth of a 64-byte line), so this against n sizes the
+ * sparse path against a dense FFT.  0 when *d does not validate.  Pure host
+ * function. */
 uint64_t sfft_plan_samples(const sfft_plan_desc_t* d);
+
+/* Rounds of round group 0 that *d hashes in stream mode (hash_mode); 0 when
+ * none or when *d does not validate.  Pure host function. */
+uint32_t sfft_plan_stream_rounds(const sfft_plan_desc_t* d);
 
 /* Fill *d with the defaults for (n, k, B, w, seed); exact mode, complex64.
  * Pure host function: no device is touched.  Errors: SFFT_EINVAL if d is NULL. */
@@ -367,11 +393,13 @@ uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
  *   * a request (n, k, mode) maps to a shape: k rounded up to a power of two
  *     (at least 8), B = 4k' (exact) or 16k' (general) within [64 or 256,
  *     min(4096, n/16)], the default window for the mode's delta; exact shapes
- *     use b_min = max(32, B/32) (at most B), at most 24 rounds, patience 5
- *     and hash_split = B/256 (1 to 16 parts).  Where that window
- *     would cover the whole signal (w >= n), or the sparse plan would gather
- *     more than SFFT_SERVER_DENSE_SAMPLES_PER_N x n samples per signal
- *     (sfft_plan_samples), the request takes the dense path: a full-length
+ *     use b_min = max(32, B/32) (at most B), at most 24 rounds, patience 5,
+ *     hash_split = B/256 (1 to 16 parts) and hash_mode 1 (stream mode for
+ *     rounds whose window covers n/8 or more).  Where that window would
+ *     cover the whole signal (w >= n), or the sparse plan would read more
+ *     than SFFT_SERVER_DENSE_SAMPLES_PER_N x n memory lines per signal (a
+ *     gathered sample is one line, a streamed round n/8; sfft_plan_samples,
+ *     sfft_plan_stream_rounds), the request takes the dense path: a full-length
  *     FP32 FFT (hipFFT, loaded on first use) and the k bins of largest
  *     magnitude (exact mode: those above theta/2);
  *   * each shape gets up to `instances` resident plan instances (workspace

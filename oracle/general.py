@@ -4,8 +4,10 @@ EstimateValues, LocateSignal, LocateInner) in FP64.
 SparseFFT (Algorithm 2), practical schedule (reading of the round parameters of
 the general-case theorem, whose constants are only asymptotic): round r uses
     k_r = max(1, k >> 2r)   (the "k -> k/4" step of the Section 4 intuition),
-    B_r = max(B >> r, 4 k_r rounded up to a power of two), capped at B,
+    B_r = max(B >> r, 4 k_r rounded up to a power of two, b_min), capped at B,
     w_r = w B_r / B,
+(b_min = B holds B and w fixed, the comparison the schedule is measured
+against),
 and does  L = LocateSignal(x, zhat, B_r),  zhat += EstimateValues(x, zhat, 3 k_r, L, B_r).
 
 LocateSignal (Algorithm 3): one (sigma, b) per round; regions start at
@@ -57,12 +59,13 @@ FRAC_BITS = 8
 
 
 def round_schedule(p: SfftParams, r):
-    """(k_r, B_r, w_r) of SparseFFT round r."""
+    """(k_r, B_r, w_r) of SparseFFT round r; b_min > 0 is a further floor on
+    B_r (b_min = B keeps B and w fixed in every round)."""
     k_r = max(1, p.k >> (2 * r))
     floor = 1
     while floor < 4 * k_r:
         floor <<= 1
-    B_r = min(p.B, max(p.B >> r, floor))
+    B_r = min(p.B, max(p.B >> r, floor, p.b_min))
     return k_r, B_r, p.w * B_r // p.B
 
 

@@ -16,6 +16,7 @@ b_min     exact mode: round r hashes into B_r = max(B >> r, b_min) bins with a
           window of w_r = w B_r / B samples (NoiselessSparseFFT of Algorithm 1
           shrinks the bin count with the remaining sparsity k_t = k / 2^t; alpha
           stays fixed, so w_r shrinks with B_r).  b_min = B keeps B fixed.
+          General mode: a further floor on B_r (general.round_schedule).
 patience  exact mode: stop after this many consecutive rounds with J empty.  One
           empty round is weak evidence: a remaining coefficient whose offset
           falls where G' is small is hidden in that round (the large-offset

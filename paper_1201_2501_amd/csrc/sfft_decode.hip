@@ -53,6 +53,37 @@ struct DecodeLds {
     uint32_t* ec;      // [capz]      re-estimation sample counts (LDS, or HBM when they do not fit)
 };
 
+// LDS work lists of the passes after the first.  A slot per entry not alone
+// in any valid measurement (unresolved after pass 1), a task per (such
+// entry, shared valid measurement) holding the task's sample with the
+// neighbours pass 1 resolved already subtracted, and per task its
+// neighbours still unresolved (their slot and the ratio c_m(e') / c_m(e)).
+// The lists are read from HBM once; the passes then work in LDS, and an
+// entry's value goes to HBM when it resolves.  Capacities are fixed; a
+// signal that exceeds one takes the direct path (peel_direct), with the
+// same results up to rounding.
+constexpr uint32_t kPeelU = 256, kPeelT = 1536, kPeelNb = 1536;
+constexpr uint16_t kNoSlot = 0xFFFFu;
+struct PeelScratch {
+    uint64_t* crowd;   // [kPeelU]  shared valid measurements of the slot's entry
+    uint64_t* ready;   // [kPeelU]  its tasks whose neighbours are all resolved (this pass)
+    double2* zvu;      // [kPeelU]  its decoded value
+    double2* delta;    // [kPeelU]  resolved value - decoded value
+    uint64_t* task;    // [kPeelT]  slot | measurement << 16 | neighbours << 24 | first neighbour << 32
+    double2* tsamp;    // [kPeelT]  the task's sample
+    double2* ratio;    // [kPeelNb] c_m(e') / c_m(e) of each listed neighbour
+    uint16_t* nbslot;  // [kPeelNb] its slot (kNoSlot: it never resolves)
+    uint16_t* ulist;   // [kPeelU]  entry of each slot
+    uint16_t* tfirst;  // [kPeelU]  first task of each slot
+    uint8_t* ustate;   // [kPeelU]  0 unresolved, 1 resolved, 2 resolved this pass
+    uint32_t* cnt;     // [4]       slots, tasks, neighbours, overflow
+};
+
+__host__ __device__ constexpr size_t peel_scratch_bytes() {
+    return (size_t)kPeelU * (8 + 8 + 16 + 16 + 2 + 2 + 1) + (size_t)kPeelT * (8 + 16) + (size_t)kPeelNb * (16 + 2) +
+           16 + 16;
+}
+
 // Optional LDS parts, placed in this order while they fit.
 enum : uint32_t { LDS_TERMS = 1, LDS_ZL2 = 2, LDS_EC = 4 };
 
@@ -169,6 +200,46 @@ __host__ __device__ inline size_t reest_lds_layout(uint32_t capz, uint32_t Bmax,
 }
 
 size_t reest_lds_bytes(uint32_t capz, uint32_t Bmax) { return reest_lds_layout(capz, Bmax, nullptr, nullptr); }
+
+// Dynamic LDS of the output kernels (k_exact_output, k_gen_output): zhat
+// indices (general mode only: the exact kernel reads them from HBM), the
+// resolution word of each entry (in hk), the state words and, at `peel`,
+// the re-estimation's work lists (PeelScratch, peel_scratch_bytes() bytes),
+// which the sort space of a truncated output overlays (it is used only
+// after the values are resolved).
+__host__ __device__ inline size_t output_lds_layout(uint32_t capz, uint32_t Bmax, bool with_zl, unsigned char* base,
+                                                    DecodeLds* L, unsigned char** peel) {
+    const uint32_t NK = pow2_ceil_u32(capz > Bmax ? capz : Bmax);
+    size_t off = 0;
+    const size_t o_zl = off;
+    if (with_zl) off = align16(off + (size_t)capz * 8);
+    const size_t o_hk = off;
+    off = align16(off + (size_t)capz * 2);
+    const size_t o_scan = off;
+    off = align16(off + (kDec / 64) * 4);
+    const size_t o_misc = off;
+    off = align16(off + 8 * 4);
+    const size_t o_sw = off;
+    off = align16(off + kStateWords * 4);
+    const size_t o_peel = off;
+    const size_t pbytes = peel_scratch_bytes() > (size_t)NK * 8 ? peel_scratch_bytes() : (size_t)NK * 8;
+    off = align16(off + pbytes);
+    if (base) {
+        *L = DecodeLds{};
+        L->zl = with_zl ? reinterpret_cast<uint64_t*>(base + o_zl) : nullptr;
+        L->hk = reinterpret_cast<uint16_t*>(base + o_hk);
+        L->ckey = reinterpret_cast<uint64_t*>(base + o_peel);
+        L->scan = reinterpret_cast<uint32_t*>(base + o_scan);
+        L->misc = reinterpret_cast<uint32_t*>(base + o_misc);
+        L->sw = reinterpret_cast<uint32_t*>(base + o_sw);
+        *peel = base + o_peel;
+    }
+    return off;
+}
+
+size_t output_lds_bytes(uint32_t capz, uint32_t Bmax, bool with_zl) {
+    return output_lds_layout(capz, Bmax, with_zl, nullptr, nullptr, nullptr);
+}
 
 // The signal's state words into LDS (start of a kernel) and back (end).
 __device__ __forceinline__ void load_state(DecodeLds& L, const uint32_t* st) {
@@ -558,18 +629,19 @@ __device__ __forceinline__ double median_net_mask(const double* src, uint64_t ma
     return (c & 1) ? m1 : 0.5 * (m0 + m1);
 }
 
-__device__ __noinline__ cx<double> median_cx_mask64(const double* src, uint64_t mask, uint64_t stride) {
-    return {median_net_mask<64>(src, mask, stride), median_net_mask<64>(src + 1, mask, stride)};
-}
-
-// Complex median over the measurements in `mask` (at most 64) of samples
-// stored as (re, im) pairs `stride` doubles apart per measurement.
-__device__ cx<double> median_cx_mask(const double* src, uint64_t mask, uint64_t stride) {
+// Complex median over the measurements in `mask` (at most KMAX: 32 or 64)
+// of samples stored as (re, im) pairs `stride` doubles apart per
+// measurement.  Out of line, so that the networks' registers do not add to
+// the callers'.
+template <uint32_t KMAX>
+__device__ __noinline__ cx<double> median_cx_mask(const double* src, uint64_t mask, uint64_t stride) {
+    static_assert(KMAX == 32 || KMAX == 64, "median bound");
     const uint32_t c = __popcll(mask);
     if (c <= 8) return {median_net_mask<8>(src, mask, stride), median_net_mask<8>(src + 1, mask, stride)};
     if (c <= 16) return {median_net_mask<16>(src, mask, stride), median_net_mask<16>(src + 1, mask, stride)};
-    if (c <= 32) return {median_net_mask<32>(src, mask, stride), median_net_mask<32>(src + 1, mask, stride)};
-    return median_cx_mask64(src, mask, stride);
+    if (KMAX == 32 || c <= 32)
+        return {median_net_mask<32>(src, mask, stride), median_net_mask<32>(src + 1, mask, stride)};
+    return {median_net_mask<64>(src, mask, stride), median_net_mask<64>(src + 1, mask, stride)};
 }
 
 // Sort key ordering by |v| descending, then slot ascending (51 magnitude bits).
@@ -660,63 +732,62 @@ struct PeelView {
 
 constexpr uint32_t kMaxPasses = 8;
 
-// Final values fin[e] of the zhat entries e < zc (decoded values zv), resolved
-// in passes: pass 1 takes the median over the measurements where an entry
-// is alone in its bin; pass p takes, for an unresolved entry, the median over
-// the valid measurements whose other bin members were resolved before pass
-// p, with their resolved values subtracted in place of the decoded ones;
-// passes end when one resolves nothing (at most kMaxPasses).  Entries left
-// take the median over all valid measurements, subtracting resolved values
-// where a neighbour has one; entries without a valid measurement keep the
-// decoded value.  Samples of entries that resolve are rewritten in place.
-// res: [capz] LDS words; misc: one LDS word.
-__device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, double* fin, uint16_t* res,
+__device__ __forceinline__ PeelScratch peel_scratch(unsigned char* base) {
+    PeelScratch P;
+    P.zvu = reinterpret_cast<double2*>(base);
+    P.delta = P.zvu + kPeelU;
+    P.tsamp = P.delta + kPeelU;
+    P.ratio = P.tsamp + kPeelT;
+    P.crowd = reinterpret_cast<uint64_t*>(P.ratio + kPeelNb);
+    P.ready = P.crowd + kPeelU;
+    P.task = P.ready + kPeelU;
+    P.nbslot = reinterpret_cast<uint16_t*>(P.task + kPeelT);
+    P.ulist = P.nbslot + kPeelNb;
+    P.tfirst = P.ulist + kPeelU;
+    P.ustate = reinterpret_cast<uint8_t*>(P.tfirst + kPeelU);
+    P.cnt = reinterpret_cast<uint32_t*>(base + ((reinterpret_cast<uintptr_t>(P.ustate + kPeelU) - reinterpret_cast<uintptr_t>(base) + 15) & ~(uintptr_t)15));
+    return P;
+}
+
+__device__ __forceinline__ uint64_t peel_mask(const PeelView& V, uint32_t e, uint8_t want) {
+    uint64_t m = 0;
+    for (uint32_t q = 0; q < V.nmeas; ++q) m |= (uint64_t)(V.flag[q * V.ms + (uint64_t)e * V.es] == want) << q;
+    return m;
+}
+
+// est(m, e) -= sum over the neighbours e' of c_m(e') (v_e' - zhat_e') / c_m(e),
+// for the neighbours nb[0, c) that res marks resolved.
+__device__ __forceinline__ void peel_correct(const PeelView& V, uint32_t e, uint32_t m, const uint16_t* nb,
+                                             uint32_t c, const double* zv, const double* fin, const uint16_t* res) {
+    cx<double> acc{0.0, 0.0};
+    for (uint32_t q = 0; q < c; ++q) {
+        const uint32_t e2 = nb[q];
+        if (res[e2] != 1) continue;
+        const uint64_t s2 = m * V.ms + (uint64_t)e2 * V.es;
+        const cx<double> c2{V.coef[2 * s2], V.coef[2 * s2 + 1]};
+        const cx<double> d{fin[2 * e2] - zv[2 * e2], fin[2 * e2 + 1] - zv[2 * e2 + 1]};
+        acc = cadd(acc, cmul(c2, d));
+    }
+    const uint64_t s = m * V.ms + (uint64_t)e * V.es;
+    const cx<double> ce{V.coef[2 * s], V.coef[2 * s + 1]};
+    const double n2 = ce.r * ce.r + ce.i * ce.i;
+    const cx<double> q = cmul(acc, cx<double>{ce.r / n2, -ce.i / n2});
+    V.est[2 * s] -= q.r;
+    V.est[2 * s + 1] -= q.i;
+}
+
+// The passes after the first without LDS work lists: each unresolved entry
+// walks its bins in HBM every pass.
+template <uint32_t KMAX>
+__device__ void peel_direct(const PeelView& V, uint32_t zc, const double* zv, double* fin, uint16_t* res,
                             uint32_t* misc) {
     const uint32_t tid = threadIdx.x;
     const uint64_t sstride = 2 * V.ms;
-    auto mask_of = [&](uint32_t e, uint8_t want) {
-        uint64_t m = 0;
-        for (uint32_t q = 0; q < V.nmeas; ++q)
-            m |= (uint64_t)(V.flag[q * V.ms + (uint64_t)e * V.es] == want) << q;
-        return m;
-    };
-    // whether every other member of e's bin in measurement m is resolved
-    auto neighbours_resolved = [&](uint32_t e, uint32_t m) {
+    auto neighbours = [&](uint32_t e, uint32_t m, uint32_t* c) {
         const uint32_t w = V.grp[m * V.ms + (uint64_t)e * V.es];
-        const uint16_t* o = V.ord + (uint64_t)m * V.capz + (w >> 16);
-        for (uint32_t q = 0; q < (w & 0xFFFFu); ++q)
-            if (o[q] != e && res[o[q]] != 1) return false;
-        return true;
+        *c = w & 0xFFFFu;
+        return V.ord + (uint64_t)m * V.capz + (w >> 16);
     };
-    // subtract c_m(e') (v_e' - zhat_e') / c_m(e) over the resolved neighbours
-    auto correct = [&](uint32_t e, uint32_t m) {
-        const uint64_t s = m * V.ms + (uint64_t)e * V.es;
-        const uint32_t w = V.grp[s];
-        const uint16_t* o = V.ord + (uint64_t)m * V.capz + (w >> 16);
-        cx<double> acc{0.0, 0.0};
-        for (uint32_t q = 0; q < (w & 0xFFFFu); ++q) {
-            const uint32_t e2 = o[q];
-            if (e2 == e || res[e2] != 1) continue;
-            const uint64_t s2 = m * V.ms + (uint64_t)e2 * V.es;
-            const cx<double> c2{V.coef[2 * s2], V.coef[2 * s2 + 1]};
-            const cx<double> d{fin[2 * e2] - zv[2 * e2], fin[2 * e2 + 1] - zv[2 * e2 + 1]};
-            acc = cadd(acc, cmul(c2, d));
-        }
-        const cx<double> c{V.coef[2 * s], V.coef[2 * s + 1]};
-        const double n2 = c.r * c.r + c.i * c.i;
-        const cx<double> q = cmul(acc, cx<double>{c.r / n2, -c.i / n2});
-        V.est[2 * s] -= q.r;
-        V.est[2 * s + 1] -= q.i;
-    };
-    for (uint32_t e = tid; e < zc; e += kDec) {
-        const uint64_t iso = mask_of(e, 1);
-        res[e] = iso ? 1 : 0;
-        if (iso) {
-            const cx<double> v = median_cx_mask(V.est + 2 * (uint64_t)e * V.es, iso, sstride);
-            fin[2 * e] = v.r;
-            fin[2 * e + 1] = v.i;
-        }
-    }
     for (uint32_t pass = 2; pass <= kMaxPasses; ++pass) {
         if (tid == 0) *misc = 0;
         __syncthreads();
@@ -724,13 +795,22 @@ __device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, do
         for (uint32_t e = tid; e < zc; e += kDec) {
             if (res[e] != 0) continue;
             uint64_t ready = 0;
-            for (uint64_t m = mask_of(e, 2); m; m &= m - 1) {
+            for (uint64_t m = peel_mask(V, e, 2); m; m &= m - 1) {
                 const uint32_t q = __builtin_ctzll(m);
-                if (neighbours_resolved(e, q)) ready |= 1ull << q;
+                uint32_t c;
+                const uint16_t* o = neighbours(e, q, &c);
+                bool ok = true;
+                for (uint32_t j = 0; j < c; ++j) ok &= o[j] == e || res[o[j]] == 1;
+                if (ok) ready |= 1ull << q;
             }
             if (!ready) continue;
-            for (uint64_t m = ready; m; m &= m - 1) correct(e, __builtin_ctzll(m));
-            const cx<double> v = median_cx_mask(V.est + 2 * (uint64_t)e * V.es, ready, sstride);
+            for (uint64_t m = ready; m; m &= m - 1) {
+                const uint32_t q = __builtin_ctzll(m);
+                uint32_t c;
+                const uint16_t* o = neighbours(e, q, &c);
+                peel_correct(V, e, q, o, c, zv, fin, res);   // e itself is unresolved: skipped
+            }
+            const cx<double> v = median_cx_mask<KMAX>(V.est + 2 * (uint64_t)e * V.es, ready, sstride);
             fin[2 * e] = v.r;
             fin[2 * e + 1] = v.i;
             res[e] = 2;   // resolved in this pass: not yet read as resolved
@@ -746,12 +826,208 @@ __device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, do
     }
     for (uint32_t e = tid; e < zc; e += kDec) {
         if (res[e] != 0) continue;
-        const uint64_t crowd = mask_of(e, 2);
+        const uint64_t crowd = peel_mask(V, e, 2);
         cx<double> v{zv[2 * e], zv[2 * e + 1]};
         if (crowd) {
-            for (uint64_t m = crowd; m; m &= m - 1) correct(e, __builtin_ctzll(m));
-            v = median_cx_mask(V.est + 2 * (uint64_t)e * V.es, crowd, sstride);
+            for (uint64_t m = crowd; m; m &= m - 1) {
+                const uint32_t q = __builtin_ctzll(m);
+                uint32_t c;
+                const uint16_t* o = neighbours(e, q, &c);
+                peel_correct(V, e, q, o, c, zv, fin, res);
+            }
+            v = median_cx_mask<KMAX>(V.est + 2 * (uint64_t)e * V.es, crowd, sstride);
         }
+        fin[2 * e] = v.r;
+        fin[2 * e + 1] = v.i;
+    }
+    __syncthreads();
+}
+
+// Final values fin[e] of the zhat entries e < zc (decoded values zv), resolved
+// in passes: pass 1 takes the median over the measurements where an entry
+// is alone in its bin; pass p takes, for an unresolved entry, the median over
+// the valid measurements whose other bin members were resolved before pass
+// p, with their resolved values subtracted in place of the decoded ones;
+// passes end when one resolves nothing (at most kMaxPasses).  Entries left
+// take the median over all valid measurements, subtracting resolved values
+// where a neighbour has one; entries without a valid measurement keep the
+// decoded value.  Samples of entries that resolve are rewritten in place.
+// res: [capz] LDS words; misc: one LDS word; P: LDS work lists (or nullptr:
+// the direct path).
+// KMAX: the most measurements of one entry (32 or 64).
+template <uint32_t KMAX>
+__device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, double* fin, uint16_t* res,
+                            uint32_t* misc, const PeelScratch* P) {
+    const uint32_t tid = threadIdx.x;
+    const uint64_t sstride = 2 * V.ms;
+    if (P && tid < 4) P->cnt[tid] = 0;
+    __syncthreads();
+    // pass 1; entries left for later passes get a slot (res = 0x8000 | slot)
+    for (uint32_t e = tid; e < zc; e += kDec) {
+        uint64_t iso = 0, crowd = 0;
+        for (uint32_t q = 0; q < V.nmeas; ++q) {
+            const uint8_t f = V.flag[q * V.ms + (uint64_t)e * V.es];
+            iso |= (uint64_t)(f == 1) << q;
+            crowd |= (uint64_t)(f == 2) << q;
+        }
+        res[e] = iso ? 1 : 0;
+        if (iso) {
+            const cx<double> v = median_cx_mask<KMAX>(V.est + 2 * (uint64_t)e * V.es, iso, sstride);
+            fin[2 * e] = v.r;
+            fin[2 * e + 1] = v.i;
+        } else {
+            fin[2 * e] = zv[2 * e];
+            fin[2 * e + 1] = zv[2 * e + 1];
+            if (crowd && P) {
+                const uint32_t u = atomicAdd(&P->cnt[0], 1u);
+                if (u < kPeelU) {
+                    P->ulist[u] = (uint16_t)e;
+                    P->crowd[u] = crowd;
+                    P->zvu[u] = make_double2(zv[2 * e], zv[2 * e + 1]);
+                    P->delta[u] = make_double2(0.0, 0.0);
+                    P->ustate[u] = 0;
+                    res[e] = 0x8000u | u;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // back to plain resolution words, then the direct path
+    auto give_up = [&]() {
+        for (uint32_t e = tid; e < zc; e += kDec)
+            if (res[e] & 0x8000u) res[e] = 0;
+        __syncthreads();
+        peel_direct<KMAX>(V, zc, zv, fin, res, misc);
+    };
+    if (!P) {
+        peel_direct<KMAX>(V, zc, zv, fin, res, misc);
+        return;
+    }
+    const uint32_t U = P->cnt[0];
+    if (U > kPeelU) return give_up();
+    // one task per (slot, shared valid measurement), a slot's tasks in a row
+    for (uint32_t u = tid; u < U; u += kDec) {
+        const uint64_t crowd = P->crowd[u];
+        uint32_t t = atomicAdd(&P->cnt[1], (uint32_t)__popcll(crowd));
+        P->tfirst[u] = (uint16_t)(t < kPeelT ? t : 0);
+        for (uint64_t m = crowd; m; m &= m - 1, ++t)
+            if (t < kPeelT) P->task[t] = (uint64_t)u | (uint64_t)__builtin_ctzll(m) << 16;
+    }
+    __syncthreads();
+    const uint32_t T = P->cnt[1];
+    if (T > kPeelT) return give_up();
+    // room for each task's unresolved neighbours
+    for (uint32_t t = tid; t < T; t += kDec) {
+        const uint64_t tk = P->task[t];
+        const uint32_t e = P->ulist[tk & 0xFFFFu], q = (uint32_t)(tk >> 16) & 0xFFu;
+        const uint32_t w = V.grp[q * V.ms + (uint64_t)e * V.es];
+        const uint16_t* o = V.ord + (uint64_t)q * V.capz + (w >> 16);
+        uint32_t left = 0;
+#pragma unroll 4
+        for (uint32_t i = 0; i < (w & 0xFFFFu); ++i) left += o[i] != e && res[o[i]] != 1;
+        const uint32_t off = atomicAdd(&P->cnt[2], left);
+        if (left > 255 || off + left > kPeelNb) P->cnt[3] = 1;
+        P->task[t] = tk | (uint64_t)(left & 0xFFu) << 24 | (uint64_t)off << 32;
+    }
+    __syncthreads();
+    if (P->cnt[3]) return give_up();
+    // each task's sample with the neighbours resolved in pass 1 subtracted
+    // (their values are final), and the other neighbours listed
+    for (uint32_t t = tid; t < T; t += kDec) {
+        const uint64_t tk = P->task[t];
+        const uint32_t e = P->ulist[tk & 0xFFFFu], q = (uint32_t)(tk >> 16) & 0xFFu;
+        const uint64_t s = q * V.ms + (uint64_t)e * V.es;
+        const uint32_t w = V.grp[s];
+        const uint16_t* o = V.ord + (uint64_t)q * V.capz + (w >> 16);
+        const cx<double> ce{V.coef[2 * s], V.coef[2 * s + 1]};
+        const double n2 = ce.r * ce.r + ce.i * ce.i;
+        const cx<double> inv{ce.r / n2, -ce.i / n2};
+        cx<double> acc{0.0, 0.0};
+        uint32_t j = (uint32_t)(tk >> 32);
+#pragma unroll 4
+        for (uint32_t i = 0; i < (w & 0xFFFFu); ++i) {
+            const uint32_t e2 = o[i];
+            if (e2 == e) continue;
+            const uint64_t s2 = q * V.ms + (uint64_t)e2 * V.es;
+            const cx<double> c2{V.coef[2 * s2], V.coef[2 * s2 + 1]};
+            const uint16_t r2 = res[e2];
+            if (r2 == 1) {
+                acc = cadd(acc, cmul(c2, cx<double>{fin[2 * e2] - zv[2 * e2], fin[2 * e2 + 1] - zv[2 * e2 + 1]}));
+            } else {
+                const cx<double> ra = cmul(c2, inv);
+                P->ratio[j] = make_double2(ra.r, ra.i);
+                P->nbslot[j++] = (r2 & 0x8000u) ? (uint16_t)(r2 & 0x7FFFu) : kNoSlot;
+            }
+        }
+        const cx<double> d = cmul(acc, inv);
+        P->tsamp[t] = make_double2(V.est[2 * s] - d.r, V.est[2 * s + 1] - d.i);
+    }
+    __syncthreads();
+    const double* ts = reinterpret_cast<const double*>(P->tsamp);
+    auto subtract_resolved = [&](uint32_t t, uint64_t tk) {
+        const uint32_t c = (uint32_t)(tk >> 24) & 0xFFu, off = (uint32_t)(tk >> 32);
+        double2 v = P->tsamp[t];
+        for (uint32_t j = off; j < off + c; ++j) {
+            const uint16_t u2 = P->nbslot[j];
+            if (u2 == kNoSlot || P->ustate[u2] != 1) continue;
+            const double2 r = P->ratio[j], d = P->delta[u2];
+            v.x -= r.x * d.x - r.y * d.y;
+            v.y -= r.x * d.y + r.y * d.x;
+        }
+        P->tsamp[t] = v;
+    };
+    for (uint32_t pass = 2; pass <= kMaxPasses; ++pass) {
+        for (uint32_t u = tid; u < U; u += kDec) P->ready[u] = 0;
+        if (tid == 0) *misc = 0;
+        __syncthreads();
+        for (uint32_t t = tid; t < T; t += kDec) {
+            const uint64_t tk = P->task[t];
+            const uint32_t u = (uint32_t)(tk & 0xFFFFu);
+            if (P->ustate[u] != 0) continue;
+            const uint32_t c = (uint32_t)(tk >> 24) & 0xFFu, off = (uint32_t)(tk >> 32);
+            bool ok = true;
+            for (uint32_t j = off; j < off + c; ++j) ok &= P->nbslot[j] != kNoSlot && P->ustate[P->nbslot[j]] == 1;
+            if (ok) atomicOr(reinterpret_cast<unsigned long long*>(&P->ready[u]), 1ull << (t - P->tfirst[u]));
+        }
+        __syncthreads();
+        for (uint32_t t = tid; t < T; t += kDec) {
+            const uint64_t tk = P->task[t];
+            const uint32_t u = (uint32_t)(tk & 0xFFFFu);
+            if (P->ustate[u] == 0 && (P->ready[u] >> (t - P->tfirst[u]) & 1)) subtract_resolved(t, tk);
+        }
+        __syncthreads();
+        uint32_t mine = 0;
+        for (uint32_t u = tid; u < U; u += kDec) {
+            const uint64_t ready = P->ready[u];
+            if (P->ustate[u] != 0 || !ready) continue;
+            const cx<double> v = median_cx_mask<KMAX>(ts + 2 * (uint64_t)P->tfirst[u], ready, 2);
+            const uint32_t e = P->ulist[u];
+            fin[2 * e] = v.r;
+            fin[2 * e + 1] = v.i;
+            P->delta[u] = make_double2(v.r - P->zvu[u].x, v.i - P->zvu[u].y);
+            P->ustate[u] = 2;   // resolved in this pass: not yet read as resolved
+            ++mine;
+        }
+        if (mine) atomicAdd(misc, mine);
+        __syncthreads();
+        const uint32_t got = *misc;
+        for (uint32_t u = tid; u < U; u += kDec)
+            if (P->ustate[u] == 2) P->ustate[u] = 1;
+        __syncthreads();
+        if (!got) break;
+    }
+    // entries left: every shared valid measurement, resolved neighbours subtracted
+    for (uint32_t t = tid; t < T; t += kDec) {
+        const uint64_t tk = P->task[t];
+        if (P->ustate[tk & 0xFFFFu] == 0) subtract_resolved(t, tk);
+    }
+    __syncthreads();
+    for (uint32_t u = tid; u < U; u += kDec) {
+        if (P->ustate[u] != 0) continue;
+        const uint32_t nt = (uint32_t)__popcll(P->crowd[u]);
+        const uint64_t all = nt >= 64 ? ~0ull : (1ull << nt) - 1;
+        const cx<double> v = median_cx_mask<KMAX>(ts + 2 * (uint64_t)P->tfirst[u], all, 2);
+        const uint32_t e = P->ulist[u];
         fin[2 * e] = v.r;
         fin[2 * e + 1] = v.i;
     }
@@ -1060,7 +1336,7 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
     __syncthreads();
     const PeelView V{D.est + base * 2, D.eflag + base, D.egrp + base, D.eord + base, D.ecoef + base * 2,
                      D.capz, 1, D.capz, R};
-    peel_values(V, zc, zv, fin, L.hk, &L.misc[0]);
+    peel_values<kMaxRounds>(V, zc, zv, fin, L.hk, &L.misc[0], nullptr);
     uint32_t flags = L.sw[ST_FLAGS];
     const uint32_t nout = write_output(L, zi, fin, zc, false, 0.5 * D.theta, D.cap, D.out_scale,
                                        D.out_idx + (uint64_t)sig * D.cap, D.out_val + (uint64_t)sig * D.cap * 2,
@@ -1147,7 +1423,10 @@ __global__ void __launch_bounds__(kDec) k_exact_output(DecodeArgs D) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x;
     const uint32_t sig = blockIdx.x;
-    DecodeLds L = decode_lds(smem, D.capz, D.Bmax, D.gtmp + (uint64_t)sig * D.capz * 4, D.ecount + (uint64_t)sig * D.capz);
+    DecodeLds L;
+    unsigned char* peel_base;
+    output_lds_layout(D.capz, D.Bmax, false, smem, &L, &peel_base);
+    const PeelScratch P = peel_scratch(peel_base);
     uint32_t* st = D.state + (uint64_t)sig * kStateWords;
     load_state(L, st);
     const uint32_t R = L.sw[ST_ROUNDS];
@@ -1158,7 +1437,7 @@ __global__ void __launch_bounds__(kDec) k_exact_output(DecodeArgs D) {
     double* fin = D.fin + (uint64_t)sig * D.capz * 2;
     const PeelView V{D.est + base * 2, D.eflag + base, D.egrp + base, D.eord + base, D.ecoef + base * 2,
                      D.capz, 1, D.capz, R};
-    peel_values(V, zc, zv, fin, L.hk, &L.misc[0]);
+    peel_values<kMaxRounds>(V, zc, zv, fin, L.hk, &L.misc[0], &P);
     uint32_t flags = L.sw[ST_FLAGS];
     const uint32_t nout = write_output(L, zi, fin, zc, false, 0.5 * D.theta, D.cap, D.out_scale,
                                        D.out_idx + (uint64_t)sig * D.cap, D.out_val + (uint64_t)sig * D.cap * 2,
@@ -1550,7 +1829,10 @@ __global__ void __launch_bounds__(kDec) k_gen_output(GeneralArgs G) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t tid = threadIdx.x;
     const uint32_t sig = blockIdx.x;
-    DecodeLds L = decode_lds(smem, G.capz, G.Bmax, gen_spill(G, sig, 0), G.ecount + (uint64_t)sig * G.capz);
+    DecodeLds L;
+    unsigned char* peel_base;
+    output_lds_layout(G.capz, G.Bmax, true, smem, &L, &peel_base);
+    const PeelScratch P = peel_scratch(peel_base);
     uint32_t* st = G.state + (uint64_t)sig * kStateWords;
     load_state(L, st);
     const uint32_t R = L.sw[ST_ROUNDS];
@@ -1563,7 +1845,7 @@ __global__ void __launch_bounds__(kDec) k_gen_output(GeneralArgs G) {
     double* fin = G.fin + (uint64_t)sig * G.capz * 2;
     const PeelView V{G.est + base * 2, G.eflag + base, G.egrp + base, G.eord + base, G.ecoef + base * 2,
                      1, nmeas, G.capz, used};
-    peel_values(V, zc, zv, fin, L.hk, &L.misc[0]);
+    peel_values<kMaxMeas>(V, zc, zv, fin, L.hk, &L.misc[0], &P);
     uint32_t flags = L.sw[ST_FLAGS];
     const uint32_t nout = write_output(L, zi, fin, zc, true, 0.0, G.cap, G.out_scale,
                                        G.out_idx + (uint64_t)sig * G.cap, G.out_val + (uint64_t)sig * G.cap * 2,
@@ -1598,13 +1880,14 @@ hipError_t launch_exact_decode(const DecodeArgs& a, hipStream_t s) {
 hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s) {
     const size_t lds = decode_lds_bytes(a.capz, a.Bmax);
     const size_t rlds = reest_lds_bytes(a.capz, a.Bmax);
-    if (rlds <= kLdsLimit) {
+    const size_t olds = output_lds_bytes(a.capz, a.Bmax, false);
+    if (rlds <= kLdsLimit && olds <= kLdsLimit) {
         hipError_t e = allow_lds(k_exact_reest, rlds);
         if (e != hipSuccess) return e;
-        e = allow_lds(k_exact_output, lds);
+        e = allow_lds(k_exact_output, olds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_exact_reest, dim3(a.count * a.rounds), dim3(kDec), rlds, s, a);
-        hipLaunchKernelGGL(k_exact_output, dim3(a.count), dim3(kDec), lds, s, a);
+        hipLaunchKernelGGL(k_exact_output, dim3(a.count), dim3(kDec), olds, s, a);
         return hipGetLastError();
     }
     hipError_t e = allow_lds(k_exact_finish, lds);
@@ -1619,7 +1902,7 @@ hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_
         hipError_t e = allow_lds(k, lds);
         if (e != hipSuccess) return e;
     }
-    for (auto k : {k_gen_select, k_gen_reest, k_gen_output}) {
+    for (auto k : {k_gen_select, k_gen_reest}) {
         hipError_t e = allow_lds(k, lds);
         if (e != hipSuccess) return e;
     }
@@ -1640,12 +1923,13 @@ hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_
 
 hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s) {
     const size_t lds = decode_lds_bytes(a.capz, a.Bmax);
+    const size_t olds = output_lds_bytes(a.capz, a.Bmax, true);
     hipError_t e = allow_lds(k_gen_reest, lds);
     if (e != hipSuccess) return e;
-    e = allow_lds(k_gen_output, lds);
+    e = allow_lds(k_gen_output, olds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_gen_reest, dim3(a.count * a.R), dim3(kDec), lds, s, a);
-    hipLaunchKernelGGL(k_gen_output, dim3(a.count), dim3(kDec), lds, s, a);
+    hipLaunchKernelGGL(k_gen_output, dim3(a.count), dim3(kDec), olds, s, a);
     return hipGetLastError();
 }
 

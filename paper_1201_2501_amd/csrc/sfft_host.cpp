@@ -132,6 +132,10 @@ struct sfft_plan_s {
     // exact batched mode: ends of the round groups.  Group 0 is hashed for
     // every signal; each later group only for signals still decoding.
     std::vector<uint32_t> group_end;
+    // exact batched mode: rounds hashed in stream mode (hash_mode) and the
+    // workgroups per (signal, round) of those launches
+    std::vector<uint8_t> stream_round;
+    uint32_t stream_parts = 0;
     uint32_t Bmax = 0;
     uint32_t logBmax = 0;
     uint32_t capz = 0;
@@ -254,10 +258,11 @@ uint32_t pow2_ceil(uint64_t v) {
 bool general_mode(const sfft_plan_s* p) { return p->d.mode == SFFT_MODE_GENERAL; }
 
 // Round r of SparseFFT (Algorithm 2), practical schedule: k_r = k >> 2r,
-// B_r = max(B >> r, 4 k_r rounded up to a power of two), capped at B.
+// B_r = max(B >> r, 4 k_r rounded up to a power of two, b_min), capped at B
+// (b_min = B keeps B and w fixed in every round).
 void general_round_shape(const sfft_plan_desc_t& d, uint32_t r, uint32_t* k_r, uint32_t* B_r) {
     const uint32_t kr = std::max<uint32_t>(1u, r >= 16 ? 0u : (d.k >> (2 * r)));
-    const uint32_t floor_b = pow2_ceil(4ull * kr);
+    const uint32_t floor_b = std::max<uint32_t>(pow2_ceil(4ull * kr), d.b_min);
     const uint32_t shifted = r >= 31 ? 0u : (d.B >> r);
     *k_r = kr;
     *B_r = std::min<uint32_t>(d.B, std::max(shifted, floor_b));
@@ -375,6 +380,22 @@ sfft_status_t build_plan(sfft_plan_s* p) {
             p->group_end.push_back(e);
         }
     }
+    // stream mode: a round whose window covers at least an eighth of the
+    // signal reads the signal contiguously (n samples in full lines) instead
+    // of gathering w_r + 1 samples at a line each
+    p->stream_round.assign(p->R, 0);
+    if (!general_mode(p) && d.hash_mode != 0) {
+        uint32_t maxB = 0;
+        for (uint32_t r = 0; r < p->R; ++r)
+            if (d.hash_mode == 2 || 8 * p->geom[r].w >= d.n) {
+                p->stream_round[r] = 1;
+                maxB = std::max(maxB, p->geom[r].B);
+            }
+        // about 32 samples per thread and part, parts dividing n / B_r
+        uint64_t parts = std::max<uint64_t>(1, std::min<uint64_t>(32, d.n / 8192));
+        while (maxB && parts > 1 && parts > d.n / maxB) parts >>= 1;
+        p->stream_parts = (uint32_t)parts;
+    }
     std::vector<float> g32(g64.begin(), g64.end());
     // twiddles exp(-2 pi i m / Bmax), m < Bmax
     std::vector<double> tw64(2 * (size_t)p->Bmax);
@@ -441,11 +462,18 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     ST_TRY(dev_alloc(p, &p->gtmp, S * Z * 4));
     ST_TRY(dev_alloc(p, &p->ecount, S * Z));
     ST_TRY(dev_alloc(p, &p->state, S * kStateWords));
-    if (!general_mode(p) && d.hash_split > 1) {
-        size_t longest = 0;
-        for (size_t g = 0, r0 = 0; g < p->group_end.size(); r0 = p->group_end[g], ++g)
+    if (!general_mode(p) && (d.hash_split > 1 || p->stream_parts > 0)) {
+        // partial folds of the split and stream launches of one round group
+        size_t longest = 0, longest_stream = 0;
+        for (size_t g = 0, r0 = 0; g < p->group_end.size(); r0 = p->group_end[g], ++g) {
             longest = std::max<size_t>(longest, p->group_end[g] - r0);
-        ST_TRY(dev_alloc(p, &p->split_partial, S * longest * d.hash_split * 4 * Bm));
+            size_t ns = 0;
+            for (size_t r = r0; r < p->group_end[g]; ++r) ns += p->stream_round[r];
+            longest_stream = std::max(longest_stream, ns);
+        }
+        const size_t parts = std::max<size_t>(d.hash_split > 1 ? longest * d.hash_split : 0,
+                                              longest_stream * p->stream_parts);
+        ST_TRY(dev_alloc(p, &p->split_partial, S * parts * 4 * Bm));
     }
     // plain path (one signal): raw bins of every round, split partials
     p->p_parts_max = 64;
@@ -492,6 +520,7 @@ H2BArgs base_h2b(const sfft_plan_s* p, const void* x) {
     a.sqrt_n = std::sqrt((double)p->d.n);
     a.mcap = p->mcap;
     a.threads = p->d.hash_threads;
+    a.order = p->d.hash_order;
     return a;
 }
 
@@ -710,14 +739,30 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
         }
         return SFFT_OK;
     }
-    // one pair launch, or its split form (hash_split)
+    // the pairs of rounds [a.round_lo, + a.nrounds): the leading stream-mode
+    // rounds (windows shrink with the round, so they come first) in one
+    // stream launch, the others in one pair launch or its split form
     auto hash = [&](H2BArgs& a) -> sfft_status_t {
+        uint32_t ns = 0;
+        while (ns < a.nrounds && p->stream_round[a.round_lo + ns]) ++ns;
+        if (ns > 0) {
+            H2BArgs b = a;
+            b.nrounds = ns;
+            b.parts = p->stream_parts;
+            b.partial = p->split_partial;
+            HIP_TRY(launch_h2b_pair_stream(b, in_c128(p), loc_f64(p), s));
+        }
+        if (ns == a.nrounds) return SFFT_OK;
+        H2BArgs g = a;
+        g.round_lo = a.round_lo + ns;
+        g.nrounds = a.nrounds - ns;
+        g.threads = pair_threads(p, g.round_lo, g.round_lo + g.nrounds);
         if (p->d.hash_split > 1) {
-            a.parts = p->d.hash_split;
-            a.partial = p->split_partial;
-            HIP_TRY(launch_h2b_pair_split(a, in_c128(p), loc_f64(p), s));
+            g.parts = p->d.hash_split;
+            g.partial = p->split_partial;
+            HIP_TRY(launch_h2b_pair_split(g, in_c128(p), loc_f64(p), s));
         } else {
-            HIP_TRY(launch_h2b_pair(a, in_c128(p), loc_f64(p), s));
+            HIP_TRY(launch_h2b_pair(g, in_c128(p), loc_f64(p), s));
         }
         return SFFT_OK;
     };
@@ -852,10 +897,10 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->group0 = 0;
     d->ratio_tol = 0.0;
     d->group_step = 0;
-    d->reserved = 0;
+    d->hash_order = 0;
     d->alpha_decay = 0.0;
     d->hash_split = 0;
-    d->reserved2 = 0;
+    d->hash_mode = 0;
     return SFFT_OK;
 }
 
@@ -887,11 +932,13 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (d->group0 > kMaxRounds) return fail(SFFT_EINVAL, "group0 must be in [0, 32]");
     if (!(d->ratio_tol >= 0.0 && d->ratio_tol < 1.0)) return fail(SFFT_EINVAL, "ratio_tol must be in [0, 1)");
     if (d->group_step > kMaxRounds) return fail(SFFT_EINVAL, "group_step must be in [0, 32]");
-    if (d->reserved != 0) return fail(SFFT_EINVAL, "reserved must be 0");
+    if (d->hash_order > 2) return fail(SFFT_EINVAL, "hash_order must be 0, 1 or 2");
     if (!(d->alpha_decay >= 0.0 && d->alpha_decay <= 1.0)) return fail(SFFT_EINVAL, "alpha_decay must be in [0, 1]");
     if (d->mode == SFFT_MODE_GENERAL && d->alpha_decay != 0.0 && d->alpha_decay != 1.0)
         return fail(SFFT_EINVAL, "alpha_decay applies to exact mode only");
-    if (d->reserved2 != 0) return fail(SFFT_EINVAL, "reserved2 must be 0");
+    if (d->hash_mode > 2) return fail(SFFT_EINVAL, "hash_mode must be 0, 1 or 2");
+    if (d->hash_mode != 0 && (d->mode == SFFT_MODE_GENERAL || d->chunks > 1))
+        return fail(SFFT_EINVAL, "hash_mode applies to exact mode with at most one chunk");
     if (d->hash_split > 64) return fail(SFFT_EINVAL, "hash_split must be in [0, 64]");
     if (d->hash_split > 1 && (d->mode == SFFT_MODE_GENERAL || d->chunks > 1))
         return fail(SFFT_EINVAL, "hash_split applies to exact mode with at most one chunk");
@@ -952,10 +999,24 @@ uint64_t sfft_plan_samples(const sfft_plan_desc_t* desc) {
         for (uint32_t r = 0; r < p.R; ++r)
             samples += (2ull * p.groundv[r].nloc + d.R_est) * p.geom[r].w;
     } else {
-        // the pair of each round of group 0 (the rounds before the earliest stop)
-        for (uint32_t r = 0; r < p.group_end[0]; ++r) samples += p.geom[r].w + 1;
+        // the pair of each round of group 0 (the rounds before the earliest
+        // stop): w_r + 1 gathered samples, or the whole signal in stream mode
+        for (uint32_t r = 0; r < p.group_end[0]; ++r) samples += p.stream_round[r] ? d.n : p.geom[r].w + 1;
     }
     return samples;
+}
+
+uint32_t sfft_plan_stream_rounds(const sfft_plan_desc_t* desc) {
+    if (!desc) return 0;
+    sfft_plan_desc_t d = *desc;
+    if (resolve_and_validate(d) != SFFT_OK || d.w < d.B || d.w % d.B) return 0;
+    sfft_plan_s p;
+    p.d = d;
+    p.dry = true;
+    if (build_plan(&p) != SFFT_OK || general_mode(&p)) return 0;
+    uint32_t c = 0;
+    for (uint32_t r = 0; r < p.group_end[0]; ++r) c += p.stream_round[r];
+    return c;
 }
 
 sfft_status_t sfft_plan(uint64_t n, uint32_t k, uint32_t B, uint64_t w, uint64_t seed, sfft_plan_t* out) {

@@ -100,6 +100,7 @@ struct H2BArgs {
     // stopped (state word ST_DONE) return before gathering
     const uint32_t* state;     // [sig][kStateWords] or nullptr
     uint32_t threads;          // workgroup size of the pair launch: 256, 512, 1024 (0 = 256)
+    uint32_t order;            // exact batched: workgroup order (plan hash_order)
 };
 
 struct DecodeArgs {
@@ -193,6 +194,10 @@ hipError_t launch_h2b_reduce(const H2BArgs& a, uint32_t round, bool acc_f64, hip
 // exact batched pair launch split over a.parts workgroups per (signal,
 // round): partials in a.partial ([count * nrounds][parts][4 Bmax] doubles)
 hipError_t launch_h2b_pair_split(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s);
+// the same pair in stream mode: a.parts workgroups per (signal, round) read
+// contiguous shares of the signal (a.parts divides n / B_r); partials as above
+hipError_t launch_h2b_pair_stream(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s);
+size_t h2b_stream_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64);
 hipError_t launch_exact_init(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_exact_decode(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s);

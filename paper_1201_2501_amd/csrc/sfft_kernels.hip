@@ -11,6 +11,11 @@
 //  * k_h2b_split     the same accumulation split over many workgroups by
 //                    window range (one signal at a time), partial sums to HBM
 //  * k_h2b_reduce    fixed-order sum of the partials, modulation, FFT
+//  * k_h2b_pstream   stream mode of the batched exact pair: each of `parts`
+//                    workgroups per (signal, round) reads a contiguous share
+//                    of the whole signal and keeps the samples that fall in
+//                    the window (for windows that cover a large fraction of
+//                    a small signal); its partial folds go to k_h2b_rsplit
 //  * k_h2b_psplit,   the batched exact pair split over `parts` workgroups per
 //    k_h2b_rsplit    (signal, round) by window range, then one workgroup per
 //                    (signal, round) sums the partials in part order,
@@ -208,6 +213,24 @@ __device__ void store_bins(const cx<TA>* VA, const cx<TA>* VB, uint32_t B, uint3
     }
 }
 
+// (signal, round offset) of job j of a batched exact pair launch, in the
+// plan's workgroup order: round-major; signal-major; or signal-major within
+// each XCD (job j runs on XCD j mod 8, which takes the signals s = j mod 8).
+__device__ __forceinline__ void pair_job(const H2BArgs& A, uint32_t j, uint32_t* sig, uint32_t* rr) {
+    const uint32_t C = A.count, R = A.nrounds;
+    if (A.order == 2 && (C & 7u) == 0) {
+        const uint32_t q = j >> 3, s8 = q / R;
+        *rr = q - s8 * R;
+        *sig = s8 * 8 + (j & 7u);
+    } else if (A.order != 0) {
+        *sig = j / R;
+        *rr = j - *sig * R;
+    } else {
+        *rr = j / C;
+        *sig = j - *rr * C;
+    }
+}
+
 template <class TIn, class TA, uint32_t NT>
 __global__ void __launch_bounds__(NT) k_h2b_pair(H2BArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -245,8 +268,8 @@ __global__ void __launch_bounds__(NT) k_h2b_pair(H2BArgs A) {
             beta = 0;
         }
     } else {
-        const uint32_t rr = blockIdx.x / A.count;
-        sig = blockIdx.x - rr * A.count;
+        uint32_t rr;
+        pair_job(A, blockIdx.x, &sig, &rr);
         // the method stops a signal after `patience` empty rounds: its later
         // hashings are never decoded
         if (A.state && A.state[(uint64_t)sig * kStateWords + ST_DONE]) return;
@@ -361,8 +384,8 @@ struct SplitJob {
 };
 
 __device__ __forceinline__ bool split_job(const H2BArgs& A, uint32_t job, SplitJob& J) {
-    const uint32_t rr = job / A.count;
-    J.sig = job - rr * A.count;
+    uint32_t rr;
+    pair_job(A, job, &J.sig, &rr);
     if (A.state && A.state[(uint64_t)J.sig * kStateWords + ST_DONE]) return false;
     J.r = A.round_lo + rr;
     const uint64_t seed = A.seeds ? A.seeds[J.sig] : A.plan_seed;
@@ -410,6 +433,90 @@ __global__ void __launch_bounds__(kThreads) k_h2b_psplit(H2BArgs A) {
         for (uint32_t p = 1; p < sub; ++p) {
             sa = cadd(sa, VA[p * B + r]);
             sb = cadd(sb, VB[p * B + r]);
+        }
+        out[2 * r] = (double)sa.r;
+        out[2 * r + 1] = (double)sa.i;
+        out[2 * B + 2 * r] = (double)sb.r;
+        out[2 * B + 2 * r + 1] = (double)sb.i;
+    }
+}
+
+// Stage 1 of a stream-mode pair (k_h2b_pstream, then k_h2b_rsplit): part
+// blockIdx.x of job blockIdx.y reads its share of the signal contiguously
+// instead of gathering the window.  Sample m sits at t_A = sigma^{-1} m
+// (mod n, taken in [-n/2, n/2)) of the shift-0 hashing; every m of one
+// residue class rho = m mod B has the same residue r = t_A mod B (sigma is
+// odd), so the thread that owns class rho owns residue r and adds, in
+// ascending m, the samples whose t_A lies in the pair's window rows:
+// G_{t_A - t0} M_L x_m to hashing A and G_{t_A + 1 - t0} M_L x_m to hashing
+// B, as accumulate_pair does (the same partial folds, added in another
+// order).  With B < 256 the block's threads split each class into
+// 256 / B lanes of interleaved m, summed in lane order at the end; each
+// iteration of a block then reads 256 consecutive samples.
+template <class TIn, class TA>
+__global__ void __launch_bounds__(kThreads) k_h2b_pstream(H2BArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t job = blockIdx.y, part = blockIdx.x;
+    SplitJob J;
+    if (!split_job(A, job, J)) return;
+    const uint64_t n = A.n, mask = n - 1, half = n >> 1;
+    const RoundDev g = A.geom[J.r];
+    const TIn* x = A.xptrs ? reinterpret_cast<const TIn*>(A.xptrs[J.sig])
+                           : reinterpret_cast<const TIn*>(A.x) + (uint64_t)J.sig * A.sig_stride;
+    const TA* G = reinterpret_cast<const TA*>(A.gtab) + g.gofs;
+    const uint32_t B = g.B;
+    const uint32_t lanes = B >= kThreads ? 1u : kThreads / B;
+    cx<TA>* VA = reinterpret_cast<cx<TA>*>(smem);
+    cx<TA>* VB = VA + lanes * B;
+    cx<TA>* M = VB + lanes * B;
+    const int64_t iB = (int64_t)B, iw = (int64_t)g.w;
+    // window rows of t_A in [t0 - 1, t0 + w): the pair at shifts 0 and 1
+    const int64_t Llo = floordiv(g.t0 - 1, iB);
+    const int64_t Lhi = floordiv(g.t0 + iw - 1, iB);
+    const uint64_t c = (J.sigma * J.b) & mask;
+    const uint64_t cB = (c * (uint64_t)B) & mask;
+    for (int64_t L = Llo + threadIdx.x; L <= Lhi; L += kThreads)
+        M[L - Llo] = to_cx<TA>(omega_d((cB * (uint64_t)L) & mask, n));
+    __syncthreads();
+    const uint64_t sinv = inverse_odd(J.sigma) & mask;
+    const uint64_t rows = n / B;                                  // samples per class
+    const uint64_t per = rows / A.parts;                          // parts divide rows (powers of two)
+    const uint64_t j0 = (uint64_t)part * per;
+    const uint32_t nslot = lanes * B;
+    for (uint32_t slot = threadIdx.x; slot < nslot; slot += kThreads) {
+        const uint32_t rho = slot % B, lane = slot / B;
+        const uint32_t r = (uint32_t)((sinv * rho) & (B - 1));
+        TA aAr = 0, aAi = 0, aBr = 0, aBi = 0;
+#pragma unroll 4
+        for (uint64_t j = j0 + lane; j < j0 + per; j += lanes) {
+            const uint64_t m = rho + j * B;
+            const TIn xv = x[m];
+            const uint64_t t = (sinv * m) & mask;
+            const int64_t tA = t >= half ? (int64_t)t - (int64_t)n : (int64_t)t;
+            const int64_t uA = tA - g.t0;
+            if (uA < -1 || uA >= iw) continue;
+            const int64_t uB = uA + 1;
+            const TA gA = uA >= 0 ? G[uA] : (TA)0;
+            const TA gB = uB < iw ? G[uB] : (TA)0;
+            const cx<TA> mv = M[(tA - (int64_t)r) / iB - Llo];
+            const TA xr = (TA)xv.x, xi = (TA)xv.y;
+            const TA pr = mv.r * xr - mv.i * xi;
+            const TA pi = mv.r * xi + mv.i * xr;
+            aAr += gA * pr;
+            aAi += gA * pi;
+            aBr += gB * pr;
+            aBi += gB * pi;
+        }
+        VA[lane * B + r] = cx<TA>{aAr, aAi};
+        VB[lane * B + r] = cx<TA>{aBr, aBi};
+    }
+    __syncthreads();
+    double* out = A.partial + ((uint64_t)job * A.parts + part) * 4 * (uint64_t)A.Bmax;
+    for (uint32_t r = threadIdx.x; r < B; r += kThreads) {
+        cx<TA> sa = VA[r], sb = VB[r];
+        for (uint32_t l = 1; l < lanes; ++l) {
+            sa = cadd(sa, VA[l * B + r]);
+            sb = cadd(sb, VB[l * B + r]);
         }
         out[2 * r] = (double)sa.r;
         out[2 * r + 1] = (double)sa.i;
@@ -521,6 +628,37 @@ hipError_t launch_h2b_pair_split(const H2BArgs& a, bool in_c128, bool acc_f64, h
                                       : launch_psplit_t<double2, float>(a, jobs, lds, s))
                            : (acc_f64 ? launch_psplit_t<float2, double>(a, jobs, lds, s)
                                       : launch_psplit_t<float2, float>(a, jobs, lds, s));
+    if (e != hipSuccess) return e;
+    const size_t lds2 = 2 * (size_t)a.Bmax * (acc_f64 ? 16 : 8);
+    e = acc_f64 ? allow_lds(k_h2b_rsplit<double>, lds2) : allow_lds(k_h2b_rsplit<float>, lds2);
+    if (e != hipSuccess) return e;
+    if (acc_f64) hipLaunchKernelGGL((k_h2b_rsplit<double>), dim3(jobs), dim3(kThreads), lds2, s, a);
+    else hipLaunchKernelGGL((k_h2b_rsplit<float>), dim3(jobs), dim3(kThreads), lds2, s, a);
+    return hipGetLastError();
+}
+
+template <class TIn, class TA>
+static hipError_t launch_pstream_t(const H2BArgs& a, uint32_t jobs, size_t lds, hipStream_t s) {
+    hipError_t e = allow_lds(k_h2b_pstream<TIn, TA>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_h2b_pstream<TIn, TA>), dim3(a.parts, jobs), dim3(kThreads), lds, s, a);
+    return hipGetLastError();
+}
+
+size_t h2b_stream_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64) {
+    const size_t csz = acc_f64 ? 16 : 8;
+    const size_t slots = Bmax >= kThreads ? Bmax : kThreads;
+    return (2 * slots + max_mcount) * csz;
+}
+
+hipError_t launch_h2b_pair_stream(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s) {
+    const uint32_t jobs = a.count * a.nrounds;
+    if (jobs == 0 || jobs > 65535 || a.parts < 1 || !a.partial) return hipErrorInvalidValue;
+    const size_t lds = h2b_stream_lds_bytes(a.Bmax, a.mcap, acc_f64);
+    hipError_t e = in_c128 ? (acc_f64 ? launch_pstream_t<double2, double>(a, jobs, lds, s)
+                                      : launch_pstream_t<double2, float>(a, jobs, lds, s))
+                           : (acc_f64 ? launch_pstream_t<float2, double>(a, jobs, lds, s)
+                                      : launch_pstream_t<float2, float>(a, jobs, lds, s));
     if (e != hipSuccess) return e;
     const size_t lds2 = 2 * (size_t)a.Bmax * (acc_f64 ? 16 : 8);
     e = acc_f64 ? allow_lds(k_h2b_rsplit<double>, lds2) : allow_lds(k_h2b_rsplit<float>, lds2);

@@ -93,17 +93,23 @@ sfft_status_t shape_for(uint64_t n, uint32_t k, int32_t mode, const sfft_server_
         // on the batch); at n = 2^24, k = 1024 this takes a request alone
         // from 1.06 to 0.67 ms.
         d->hash_split = std::min<uint32_t>(16, std::max<uint32_t>(1, (uint32_t)B / 256));
+        // rounds whose window covers an eighth of the signal or more read it
+        // contiguously (stream mode) instead of gathering
+        d->hash_mode = 1;
     }
     d->cap = kb;
     d->max_batch = sd.slots;
     d->w = sfft_default_w(n, (uint32_t)B, d->alpha, d->delta);
     *dense = d->w >= n || sfft_validate_params(d) != SFFT_OK;
     if (!*dense && !(sd.flags & SFFT_SERVER_SPARSE_ONLY)) {
-        // each gathered sample is a random access costing a whole line, while
-        // the dense path streams the signal: past this many samples per
-        // signal sample the dense FFT is the faster path
+        // each gathered sample is a random access costing a whole 64-byte
+        // line, a streamed round reads n samples in n/8 lines, while the
+        // dense path streams the signal through several passes: past this
+        // many line reads per signal sample the dense FFT is the faster path
         const uint64_t samples = sfft_plan_samples(d);
-        *dense = samples == 0 || (double)samples > SFFT_SERVER_DENSE_SAMPLES_PER_N * (double)n;
+        const uint64_t streamed = (uint64_t)sfft_plan_stream_rounds(d) * n;
+        const double lines = (double)(samples - streamed) + (double)streamed / 8.0;
+        *dense = samples == 0 || lines > SFFT_SERVER_DENSE_SAMPLES_PER_N * (double)n;
     }
     if (sd.flags & SFFT_SERVER_DENSE_ONLY) *dense = 1;
     if (*dense) d->w = n;

@@ -32,7 +32,7 @@ INFO_ROUNDS, INFO_FLAGS, INFO_ZHAT, INFO_LOCATED = range(4)
 EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_plan_ex", "sfft_plan",
            "sfft_plan_get_desc", "sfft_destroy", "sfft_execute", "sfft_execute_batch",
            "sfft_hash_pair_raw", "sfft_plan_timings", "sfft_plan_h2b_bytes", "sfft_plan_round_groups",
-           "sfft_plan_raw_slot", "sfft_plan_device_bytes", "sfft_plan_samples",
+           "sfft_plan_raw_slot", "sfft_plan_device_bytes", "sfft_plan_samples", "sfft_plan_stream_rounds",
            "sfft_status_string",
            "sfft_last_error", "sfft_splitmix64",
            "sfft_dense_topk_scratch_bytes", "sfft_dense_topk", "sfft_dense_topk_noalloc_max_count",
@@ -51,8 +51,8 @@ class PlanDesc(ctypes.Structure):
                 ("flags", c_uint32), ("max_batch", c_uint32), ("hash_threads", c_uint32),
                 ("chunks", c_uint32), ("stop_count", c_uint32),
                 ("stop_patience", c_uint32), ("group0", c_uint32), ("ratio_tol", c_double),
-                ("group_step", c_uint32), ("reserved", c_uint32), ("alpha_decay", c_double),
-                ("hash_split", c_uint32), ("reserved2", c_uint32)]
+                ("group_step", c_uint32), ("hash_order", c_uint32), ("alpha_decay", c_double),
+                ("hash_split", c_uint32), ("hash_mode", c_uint32)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -119,6 +119,8 @@ def load():
     lib.sfft_plan_device_bytes.restype = c_uint64
     lib.sfft_plan_samples.argtypes = [POINTER(PlanDesc)]
     lib.sfft_plan_samples.restype = c_uint64
+    lib.sfft_plan_stream_rounds.argtypes = [POINTER(PlanDesc)]
+    lib.sfft_plan_stream_rounds.restype = c_uint32
     lib.sfft_dense_topk_noalloc_max_count.restype = c_uint32
     lib.sfft_server_desc_init.argtypes = [POINTER(ServerDesc)]
     lib.sfft_server_shape.argtypes = [POINTER(ServerDesc), c_uint64, c_uint32, c_int32, POINTER(PlanDesc),
@@ -137,7 +139,8 @@ def load():
     lib.sfft_server_destroy.argtypes = [P]
     for name in EXPORTS:
         if name not in ("sfft_default_w", "sfft_status_string", "sfft_last_error", "sfft_splitmix64",
-                        "sfft_plan_h2b_bytes", "sfft_plan_device_bytes", "sfft_dense_topk_noalloc_max_count"):
+                        "sfft_plan_h2b_bytes", "sfft_plan_device_bytes", "sfft_dense_topk_noalloc_max_count",
+                        "sfft_plan_samples", "sfft_plan_stream_rounds"):
             getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -367,6 +370,10 @@ def sfft_plan_device_bytes(desc):
 
 def sfft_plan_samples(desc):
     return int(load().sfft_plan_samples(ctypes.byref(desc)))
+
+
+def sfft_plan_stream_rounds(desc):
+    return int(load().sfft_plan_stream_rounds(ctypes.byref(desc)))
 
 
 def sfft_server_desc_init():

@@ -132,5 +132,5 @@ def test_hash_split_validation():
     assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
     d.chunks, d.mode = 1, sfft.SFFT_MODE_GENERAL
     assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
-    d.mode, d.reserved2 = sfft.SFFT_MODE_EXACT, 1
+    d.mode, d.hash_mode = sfft.SFFT_MODE_EXACT, 3
     assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL

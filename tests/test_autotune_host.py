@@ -51,7 +51,7 @@ def test_group0_offset_is_relative_to_the_library_default():
 
 @pytest.mark.parametrize("field,value", [("hash_threads", 128), ("hash_threads", 768), ("chunks", 9),
                                          ("stop_patience", 0), ("group0", 33), ("group_step", 33),
-                                         ("reserved", 1)])
+                                         ("hash_order", 3)])
 def test_launch_shape_fields_are_validated(field, value):
     lib = sfft.load()
     d = sfft.sfft_desc_init(1 << 20, 64, 512)

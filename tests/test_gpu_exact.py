@@ -246,24 +246,27 @@ def test_c3_shape_matches_oracle(torch_dev, seed, sched):
     plan.close()
 
 
-@pytest.mark.parametrize("threads,chunks,group0,step", [(512, 1, 0, 0), (1024, 1, 0, 0), (256, 2, 0, 0), (1024, 2, 0, 0),
-                                                       (256, 1, 6, 0), (512, 1, 12, 0), (256, 1, 0, 4)])
-def test_c3_launch_shapes_match_oracle(torch_dev, threads, chunks, group0, step):
+@pytest.mark.parametrize("threads,chunks,group0,step,order", [(512, 1, 0, 0, 0), (1024, 1, 0, 0, 0), (256, 2, 0, 0, 0),
+                                                             (1024, 2, 0, 0, 0), (256, 1, 6, 0, 0), (512, 1, 12, 0, 0),
+                                                             (256, 1, 0, 4, 0), (256, 1, 0, 0, 1), (256, 1, 12, 3, 2),
+                                                             (512, 2, 0, 0, 2)])
+def test_c3_launch_shapes_match_oracle(torch_dev, threads, chunks, group0, step, order):
     """The launch shape the autotuner picks from (HashToBins workgroup size,
-    batch chunks, size of the first round group) leaves supports and rounds
-    unchanged and values within the FP64 bar: with B_r < threads a bin's
-    partial sums are only added in another order."""
+    batch chunks, size of the first round group, workgroup order) leaves
+    supports and rounds unchanged and values within the FP64 bar: with
+    B_r < threads a bin's partial sums are only added in another order."""
     torch, dev = torch_dev
     n, k, B = 1 << 22, 256, 1024
     w = default_w(n, B, 0.5, 1e-9)
-    count = 4
-    say("c3-launch-shape", "threads", threads, "chunks", chunks, "group0", group0, "count", count)
+    count = 8 if order == 2 else 4       # a multiple of 8: the per-XCD order applies
+    say("c3-launch-shape", "threads", threads, "chunks", chunks, "group0", group0, "order", order, "count", count)
     plan = plan_for(n, k, B, w, 0, delta=1e-9, theta=0.02, loc_prec=1, max_batch=count, b_min=32, rounds=24,
-                    hash_threads=threads, chunks=chunks, group0=group0, group_step=step,
+                    hash_threads=threads, chunks=chunks, group0=group0, group_step=step, hash_order=order,
                     flags=2)     # SFFT_FLAG_TIMING: chunk count
-    assert plan.desc.hash_threads == threads and plan.desc.chunks == chunks
+    assert plan.desc.hash_threads == threads and plan.desc.chunks == chunks and plan.desc.hash_order == order
     g0 = group0 or 9
-    assert plan.round_groups() == ([g0, 13, 21, 24] if step == 4 else plan.round_groups())
+    assert plan.round_groups() == ([g0, 13, 21, 24] if step == 4 else [g0, 15, 21, 24] if step == 3 else
+                                   plan.round_groups())
     assert plan.round_groups()[0] == g0
     xs, sups, seeds = [], [], []
     for s in range(count):
@@ -521,6 +524,73 @@ def test_cached_tuned_c3_plan_matches_oracle(torch_dev):
         seeds.append(101 * s + 17)
     out = run_batch(torch, dev, plan, xs, seeds)
     for s in range(2):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        assert int(out[s][2][0]) == ref.rounds_used
+        compare(out[s][0], out[s][1], ref)
+        assert np.array_equal(out[s][0], sups[s])
+    plan.close()
+
+
+@pytest.mark.parametrize("n,k,B,mode,prec", [(1 << 16, 16, 256, 2, 1), (1 << 18, 100, 512, 1, 1),
+                                             (1 << 18, 100, 512, 1, 0), (1 << 14, 16, 64, 2, 1)])
+def test_stream_mode_raw_bins_match_oracle(torch_dev, n, k, B, mode, prec):
+    """Stream-mode HashToBins (hash_mode 1: rounds whose window covers n/8 or
+    more; 2: every round) reads the signal contiguously; the raw bins of every
+    round of group 0, at both shifts, match the oracle's HashToBins of the
+    same draws: FP64 within 1e-12 of the largest bin, FP32 within 2e-5."""
+    from oracle.rng import draw_b, draw_sigma
+    from paper_1201_2501_amd import sfft
+    torch, dev = torch_dev
+    dtype = np.complex128 if n == 1 << 14 else np.complex64
+    delta = 1e-12 if dtype == np.complex128 else 1e-9
+    w = default_w(n, B, 0.5, delta)
+    count = 2
+    plan = plan_for(n, k, B, w, 0, delta=delta, in_dtype=int(dtype == np.complex128), loc_prec=prec,
+                    max_batch=count, hash_mode=mode, rounds=12, group0=6)
+    nstream = sfft.sfft_plan_stream_rounds(plan.desc)
+    say("stream-raw", "n", n, "B", B, "w", w, "mode", mode, "prec", prec, "stream rounds", nstream)
+    assert nstream >= 1 and (mode != 2 or nstream == 6)
+    xs = [siggen.planted_signal(n, k, 870 + s, dtype, noise_ratio=0.01)[0] for s in range(count)]
+    seeds = [41, 977]
+    X = torch.from_numpy(np.stack(xs)).to(dev)
+    plan.execute_batch(X, torch.tensor(seeds, dtype=torch.int64, device=dev))
+    torch.cuda.synchronize()
+    p = oracle_params(plan)
+    tol = 1e-12 if prec == 1 else 2e-5
+    for s in range(count):
+        for r in range(6):
+            Br, wr = p.round_bins(r)
+            G = window_time(n, Br, wr, p.round_alpha(r), delta)
+            sigma, b = draw_sigma(seeds[s], n, r), draw_b(seeds[s], n, r)
+            e0 = hash_to_bins_raw(xs[s], sigma, 0, b, Br, G)
+            e1 = hash_to_bins_raw(xs[s], sigma, 1, b, Br, G)
+            g0, g1 = plan.raw_slot(s, r, dev)
+            sc = max(np.abs(e0).max(), np.abs(e1).max())
+            assert np.abs(g0 - e0).max() <= tol * sc, (s, r)
+            assert np.abs(g1 - e1).max() <= tol * sc, (s, r)
+    plan.close()
+
+
+@pytest.mark.parametrize("n,k,B,mode", [(1 << 18, 100, 512, 1), (1 << 16, 16, 256, 2), (1 << 20, 256, 1024, 2)])
+def test_stream_mode_recovery_matches_oracle(torch_dev, n, k, B, mode):
+    """The batched exact path with stream-mode rounds: supports bit-exact and
+    values within 1e-10 of the oracle, rounds decoded equal, for four
+    signals with their own seeds (the served shapes' schedule: b_min 32,
+    24 rounds, patience 5)."""
+    torch, dev = torch_dev
+    w = default_w(n, B, 0.5, 1e-9)
+    count = 4
+    plan = plan_for(n, k, B, w, 0, delta=1e-9, loc_prec=1, max_batch=count, hash_mode=mode, b_min=32,
+                    rounds=24, patience=5)
+    say("stream-recovery", "n", n, "k", k, "B", B, "mode", mode)
+    xs, sups, seeds = [], [], []
+    for s in range(count):
+        x, sup, _ = siggen.planted_signal(n, k, 880 + s, np.complex64)
+        xs.append(x)
+        sups.append(sup)
+        seeds.append(101 * s + 3)
+    out = run_batch(torch, dev, plan, xs, seeds)
+    for s in range(count):
         ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
         assert int(out[s][2][0]) == ref.rounds_used
         compare(out[s][0], out[s][1], ref)

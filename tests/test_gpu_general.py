@@ -42,7 +42,7 @@ def oracle_params(plan, seed=None):
     d = plan.desc
     return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=d.seed if seed is None else seed, alpha=d.alpha,
                       delta=d.delta, g_min=d.g_min, rounds=d.rounds, t=d.t, s=d.s, R_loc=d.R_loc,
-                      R_est=d.R_est, cap=d.cap)
+                      R_est=d.R_est, cap=d.cap, b_min=d.b_min)
 
 
 def check(idx, val, ref, rel, allow_near_tie=False):
@@ -257,4 +257,28 @@ def test_c4_precision_variants_match_oracle(torch_dev, c4_case, loc, est):
     same = check(idx, v, ref, 1e-10 if est == 1 else 1e-4, allow_near_tie=(loc == 0))
     if same:
         assert np.array_equal(idx, sup)
+    plan.close()
+
+
+@pytest.mark.parametrize("b_min", [256, 1024])
+def test_general_b_min_schedule_matches_oracle(torch_dev, b_min):
+    """General mode with a floor on the round bins (b_min = B: B and w fixed in
+    every round) at n = 2^20, k = 64, B = 1024, tail/head 0.05, FP64: the
+    batched path against the oracle, signal by signal."""
+    from paper_1201_2501_amd.sfft import Plan, SFFT_MODE_GENERAL
+    torch, dev = torch_dev
+    n, k, B, count = 1 << 20, 64, 1024, 2
+    say("general-b_min", b_min)
+    plan = Plan(n, k, B, 0, 0, mode=SFFT_MODE_GENERAL, delta=1e-6, loc_prec=1, est_prec=1, b_min=b_min,
+                max_batch=count)
+    assert plan.desc.b_min == b_min
+    xs = [siggen.planted_signal(n, k, 960 + s, np.complex64, noise_ratio=0.05)[0] for s in range(count)]
+    seeds = [7 + 3 * s for s in range(count)]
+    bufs = plan.execute_batch(torch.from_numpy(np.stack(xs)).to(dev), torch.tensor(seeds, dtype=torch.int64,
+                                                                                     device=dev))
+    torch.cuda.synchronize()
+    for s in range(count):
+        c = int(bufs["counts"][s])
+        ref = sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        check(bufs["idx"][s, :c].cpu().numpy(), bufs["val"][s, :c].cpu().numpy(), ref, 1e-10)
     plan.close()

@@ -22,7 +22,7 @@ def test_server_desc_defaults():
     (1 << 22, 8, sfft.SFFT_MODE_GENERAL, 256, False),
     (1 << 20, 64, sfft.SFFT_MODE_GENERAL, 1024, True),     # gathers 4.9 samples per bin
     (1 << 24, 1024, sfft.SFFT_MODE_EXACT, 4096, False),
-    (1 << 20, 1024, sfft.SFFT_MODE_EXACT, 4096, True),     # gathers 0.8 samples per bin
+    (1 << 20, 1024, sfft.SFFT_MODE_EXACT, 4096, False),    # two stream rounds: 0.48 lines per sample
     (1 << 16, 1024, sfft.SFFT_MODE_EXACT, 4096, True),     # window longer than the signal
     (1 << 16, 8, sfft.SFFT_MODE_EXACT, 64, False),
     (1 << 16, 200, sfft.SFFT_MODE_GENERAL, 4096, True),
@@ -36,11 +36,15 @@ def test_server_shape_policy(n, k, mode, B, dense):
     w = default_w(n, B, 0.5, delta)
     assert is_dense == dense
     if w < n:
-        # the sparse plan's gathered samples decide against half a sample per bin
+        # the sparse plan's memory lines decide against half a line per
+        # sample: a gathered sample is one line, a streamed round n/8
         sparse = sfft.PlanDesc.from_buffer_copy(d)
         sparse.w = w
         samples = sfft.sfft_plan_samples(sparse)
-        assert samples > 0 and dense == (samples > sfft.SFFT_SERVER_DENSE_SAMPLES_PER_N * n)
+        streamed = sfft.sfft_plan_stream_rounds(sparse) * n
+        assert sparse.hash_mode == (1 if mode == sfft.SFFT_MODE_EXACT else 0)
+        lines = samples - streamed + streamed / 8
+        assert samples > 0 and dense == (lines > sfft.SFFT_SERVER_DENSE_SAMPLES_PER_N * n)
     if not dense:
         assert d.w == w
         # one instance = the plan's workspace + the server's staging buffers
@@ -91,6 +95,27 @@ def test_plan_samples_closed_forms():
     assert sfft.sfft_plan_samples(g) == expect == 1285880
     bad = sfft.sfft_desc_init(1 << 20, 64, 500)
     assert sfft.sfft_plan_samples(bad) == 0
+
+
+def test_general_b_min_floors_the_round_schedule():
+    """General mode with b_min = B keeps B and w in every round (the fixed
+    schedule the practical one is measured against); the host's gathered
+    samples follow the oracle's round schedule either way."""
+    from oracle.general import round_schedule
+    from oracle.params import SfftParams
+    n, k, B, w = 1 << 20, 64, 1024, 64512
+    for b_min in (0, 256, B):
+        g = sfft.sfft_desc_init(n, k, B, w)
+        g.mode, g.rounds, g.b_min = sfft.SFFT_MODE_GENERAL, 7, b_min
+        p = SfftParams(n=n, k=k, B=B, w=w, seed=0, rounds=7, b_min=b_min)
+        expect = 0
+        for r in range(7):
+            k_r, B_r, w_r = round_schedule(p, r)
+            assert B_r == min(B, max(B >> r, 1 << (4 * k_r - 1).bit_length(), b_min)) and w_r == w // B * B_r
+            expect += (2 * level_count(n, B_r) * g.R_loc + g.R_est) * w_r
+        assert sfft.sfft_plan_samples(g) == expect
+        if b_min == B:
+            assert expect == 7 * (2 * level_count(n, B) * g.R_loc + g.R_est) * w
 
 
 def test_plan_device_bytes_scales_with_batch_and_rejects_bad_descs():
