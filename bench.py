@@ -411,6 +411,54 @@ def general_schedule_bench(args, torch, dev, sfft, siggen):
             "variants": out}
 
 
+def stream_mode_bench(args, torch, dev, sfft, siggen):
+    """Stream-mode HashToBins against the gather, batched exact mode, 512
+    signals per shape, unit magnitudes, complex64, delta = 1e-9, b_min 32,
+    24 rounds, patience 5 (the served exact schedule): hash_mode 0 (gather
+    every round), 1 (stream the rounds whose window covers n/8 or more), 2
+    (stream every round).  Reports the batch time, the samples one signal
+    reads in round group 0 (streamed rounds count n) and the supports
+    recovered."""
+    from paper_1201_2501_amd.sfft import Plan
+    out = []
+    S = 512
+    for n, k, B in ((1 << 16, 16, 64), (1 << 16, 64, 256), (1 << 18, 100, 512), (1 << 20, 256, 1024)):
+        X, sups, _ = siggen.torch_planted_batch(n, k, [60_000 + s for s in range(S)], dev, magnitude="unit")
+        seeds = torch.arange(S, dtype=torch.int64, device=dev) * 13 + 1
+        for mode in (0, 1, 2):
+            plan = Plan(n, k, B, 0, 0, delta=1e-9, b_min=32, rounds=24, patience=5, hash_mode=mode, max_batch=S,
+                        flags=sfft.SFFT_FLAG_TIMING)
+            bufs = plan.execute_batch(X, seeds)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                plan.execute_batch(X, seeds, bufs=bufs)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            tm = plan.timings()
+            counts, idx = bufs["counts"].cpu().numpy(), bufs["idx"].cpu().numpy()
+            ok = sum(int(np.array_equal(idx[s, :int(counts[s])], np.sort(sups[s]))) for s in range(S))
+            rec = {"n": n, "k": k, "B": B, "w": int(plan.desc.w), "hash_mode": mode,
+                   "stream_rounds": sfft.sfft_plan_stream_rounds(plan.desc),
+                   "samples_per_signal": sfft.sfft_plan_samples(plan.desc), "ms_per_batch": round(ms, 3),
+                   "hash_ms": round(float(tm[0]), 3), "sFFTs_per_s": round(S / (ms * 1e-3), 1),
+                   "supports": "%d/%d" % (ok, S)}
+            log("stream n=2^%d k=%d B=%d mode %d: %.3f ms/batch (hash %.3f), %d stream rounds, supports %d/%d" % (
+                n.bit_length() - 1, k, B, mode, ms, tm[0], rec["stream_rounds"], ok, S))
+            out.append(rec)
+            plan.close()
+        del X
+        torch.cuda.empty_cache()
+    head = out[0]
+    return {"metric": "batched exact sFFTs/s, stream-mode vs gathered HashToBins", "value": head["sFFTs_per_s"],
+            "unit": "sFFTs/s", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": head["ms_per_batch"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "512 exactly sparse signals per shape, n = 2^16..2^20, hash_mode 0/1/2"},
+            "variants": out}
+
+
 def section5_bench(args, torch, dev, sfft):
     """The Section 5 reduction as a workload: the k-point DFT of x_k computed
     through the n-point exactly sparse sFFT of its periodic extension
@@ -562,10 +610,11 @@ def main():
     ap.add_argument("--tune-out", default="", help="also store the autotuner's choice in this JSON file")
     ap.add_argument("--tune-confirm", type=int, default=6,
                     help="fresh batches the fastest accepted candidates must also pass")
-    ap.add_argument("--workload", choices=["c3", "c4", "section5", "gsched"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c4", "section5", "gsched", "stream"], default="c3",
                     help="c3: the batched exactly-sparse headline; c4: the general-mode precision split; "
                          "section5: k-point DFTs through the n-point sFFT against a direct k-point FFT; "
-                         "gsched: the general-mode round schedule against fixed B and w")
+                         "gsched: the general-mode round schedule against fixed B and w; stream: stream-mode "
+                         "HashToBins against the gather at small n")
     ap.add_argument("--config-key", action="store_true",
                     help="print the key that names this configuration in the traffic record, then exit")
     args = ap.parse_args()
@@ -594,6 +643,9 @@ def main():
         return
     if args.workload == "gsched":
         print(json.dumps(general_schedule_bench(args, torch, dev, sfft, siggen)), flush=True)
+        return
+    if args.workload == "stream":
+        print(json.dumps(stream_mode_bench(args, torch, dev, sfft, siggen)), flush=True)
         return
     n, k, S = 1 << args.log2n, args.k, args.signals
     loc_prec = sfft.SFFT_F64 if args.loc_prec == "f64" else sfft.SFFT_F32

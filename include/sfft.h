@@ -396,10 +396,15 @@ uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
  *     use b_min = max(32, B/32) (at most B), at most 24 rounds, patience 5,
  *     hash_split = B/256 (1 to 16 parts) and hash_mode 1 (stream mode for
  *     rounds whose window covers n/8 or more).  Where that window would
- *     cover the whole signal (w >= n), or the sparse plan would read more
- *     than SFFT_SERVER_DENSE_SAMPLES_PER_N x n memory lines per signal (a
- *     gathered sample is one line, a streamed round n/8; sfft_plan_samples,
- *     sfft_plan_stream_rounds), the request takes the dense path: a full-length
+ *     cover the whole signal (w >= n), or where a request served alone is
+ *     predicted to finish sooner on the dense path, the request takes the
+ *     dense path: predicted milliseconds, fitted to solo service times
+ *     measured on MI355X, sparse exact SFFT_SERVER_EXACT_MS +
+ *     SFFT_SERVER_GATHER_NS x gathered samples + SFFT_SERVER_STREAM_NS x
+ *     streamed samples, sparse general SFFT_SERVER_GENERAL_MS +
+ *     SFFT_SERVER_GENERAL_NS x samples (sfft_plan_samples,
+ *     sfft_plan_stream_rounds), dense SFFT_SERVER_DENSE_MS +
+ *     SFFT_SERVER_DENSE_NS x n.  The dense path is a full-length
  *     FP32 FFT (hipFFT, loaded on first use) and the k bins of largest
  *     magnitude (exact mode: those above theta/2);
  *   * each shape gets up to `instances` resident plan instances (workspace
@@ -429,10 +434,8 @@ typedef struct sfft_server_s* sfft_server_t;
                                         (for testing the scheduler without a GPU)      */
 #define SFFT_SERVER_DENSE_ONLY 0x2u  /* every request takes the dense path            */
 #define SFFT_SERVER_SPARSE_ONLY 0x4u /* every request whose sparse plan validates with
-                                        w < n takes the sparse path, whatever its
-                                        gathered samples (without either flag a shape
-                                        goes dense when its sparse plan gathers more
-                                        than SFFT_SERVER_DENSE_SAMPLES_PER_N x n samples) */
+                                        w < n takes the sparse path, whatever the path
+                                        model predicts                                  */
 #define SFFT_SERVER_EVICT_DENSE 0x8u /* also evict idle dense-path instances (by default
                                         they stay resident until the server is destroyed,
                                         and a shape that cannot fit beside them fails with
@@ -440,7 +443,14 @@ typedef struct sfft_server_s* sfft_server_t;
                                         that evicted and rebuilt hipFFT-backed instances
                                         under a small budget once stopped making progress,
                                         cause not found                                 */
-#define SFFT_SERVER_DENSE_SAMPLES_PER_N 0.5
+/* the path model (milliseconds and nanoseconds per sample) */
+#define SFFT_SERVER_EXACT_MS 0.13
+#define SFFT_SERVER_GATHER_NS 1.05
+#define SFFT_SERVER_STREAM_NS 0.03
+#define SFFT_SERVER_GENERAL_MS 0.75
+#define SFFT_SERVER_GENERAL_NS 0.13
+#define SFFT_SERVER_DENSE_MS 0.09
+#define SFFT_SERVER_DENSE_NS 0.027
 
 typedef struct {
     uint64_t budget_bytes;   /* device memory the server may hold (instances)   */

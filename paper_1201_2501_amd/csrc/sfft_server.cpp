@@ -5,7 +5,7 @@
 //    power of two (at least 8), B from that k, the default window for the
 //    mode's delta.  Where that window would cover the whole signal (w >= n)
 //    the request takes the dense path (full-length FFT + top-k), as it does
-//    where the sparse plan would gather more than half a sample per bin.
+//    where a request served alone is predicted to finish sooner on it.
 //  * Instances.  Each shape gets up to `instances` resident plan instances
 //    (window tables, workspace for `slots` signals, a stream and pinned
 //    staging), created on demand and kept; idle instances are evicted in
@@ -102,14 +102,19 @@ sfft_status_t shape_for(uint64_t n, uint32_t k, int32_t mode, const sfft_server_
     d->w = sfft_default_w(n, (uint32_t)B, d->alpha, d->delta);
     *dense = d->w >= n || sfft_validate_params(d) != SFFT_OK;
     if (!*dense && !(sd.flags & SFFT_SERVER_SPARSE_ONLY)) {
-        // each gathered sample is a random access costing a whole 64-byte
-        // line, a streamed round reads n samples in n/8 lines, while the
-        // dense path streams the signal through several passes: past this
-        // many line reads per signal sample the dense FFT is the faster path
+        // the path a request served alone finishes sooner on: the sparse
+        // path pays a launch chain (its floor) plus a cost per gathered or
+        // streamed sample, the dense FFT a floor plus a cost per sample of
+        // the signal (constants fitted to solo service times on MI355X)
         const uint64_t samples = sfft_plan_samples(d);
         const uint64_t streamed = (uint64_t)sfft_plan_stream_rounds(d) * n;
-        const double lines = (double)(samples - streamed) + (double)streamed / 8.0;
-        *dense = samples == 0 || lines > SFFT_SERVER_DENSE_SAMPLES_PER_N * (double)n;
+        const double sparse_ms =
+            mode == SFFT_MODE_EXACT
+                ? SFFT_SERVER_EXACT_MS + 1e-6 * (SFFT_SERVER_GATHER_NS * (double)(samples - streamed) +
+                                                 SFFT_SERVER_STREAM_NS * (double)streamed)
+                : SFFT_SERVER_GENERAL_MS + 1e-6 * SFFT_SERVER_GENERAL_NS * (double)samples;
+        const double dense_ms = SFFT_SERVER_DENSE_MS + 1e-6 * SFFT_SERVER_DENSE_NS * (double)n;
+        *dense = samples == 0 || sparse_ms > dense_ms;
     }
     if (sd.flags & SFFT_SERVER_DENSE_ONLY) *dense = 1;
     if (*dense) d->w = n;

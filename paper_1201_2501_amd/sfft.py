@@ -20,7 +20,10 @@ SFFT_SERVER_FAKE_DEVICE = 0x1
 SFFT_SERVER_DENSE_ONLY = 0x2
 SFFT_SERVER_SPARSE_ONLY = 0x4
 SFFT_SERVER_EVICT_DENSE = 0x8
-SFFT_SERVER_DENSE_SAMPLES_PER_N = 0.5
+# the serving path model (include/sfft.h)
+SFFT_SERVER_EXACT_MS, SFFT_SERVER_GATHER_NS, SFFT_SERVER_STREAM_NS = 0.13, 1.05, 0.03
+SFFT_SERVER_GENERAL_MS, SFFT_SERVER_GENERAL_NS = 0.75, 0.13
+SFFT_SERVER_DENSE_MS, SFFT_SERVER_DENSE_NS = 0.09, 0.027
 SFFT_MODE_EXACT, SFFT_MODE_GENERAL = 0, 1
 SFFT_C64, SFFT_C128 = 0, 1
 SFFT_F32, SFFT_F64 = 0, 1

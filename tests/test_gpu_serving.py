@@ -53,25 +53,38 @@ def oracle_for(d, seed):
 
 
 # (name, n, k, mode, signal seed, request seed)
-# dense: the window covers the signal (w >= n), or the sparse plan would
-# gather more than half a sample per bin (general mode at n = 2^18)
+# (name, n, k, mode, signal seed, request seed).  Under the default path
+# model only exact shapes with small k at large n are served sparse (a
+# request alone finishes sooner there); SPARSE_CASES go through a server
+# with SFFT_SERVER_SPARSE_ONLY so that the sparse path is exercised at the
+# small shapes too (general mode, and a stream-mode round at n = 2^18).
 CASES = [
-    ("exact-16-16", 1 << 16, 16, EXACT, 11, 101),
-    ("exact-18-100", 1 << 18, 100, EXACT, 12, 102),
-    ("general-22-8", 1 << 22, 8, GENERAL, 13, 103),
+    ("exact-22-8", 1 << 22, 8, EXACT, 11, 101),
+    ("exact-23-64", 1 << 23, 64, EXACT, 12, 102),
+    ("dense-18-100", 1 << 18, 100, EXACT, 17, 107),
     ("dense-18-20g", 1 << 18, 20, GENERAL, 14, 104),
     ("dense-16-300", 1 << 16, 300, EXACT, 15, 105),
     ("dense-16-200g", 1 << 16, 200, GENERAL, 16, 106),
 ]
+SPARSE_CASES = [
+    ("exact-16-16", 1 << 16, 16, EXACT, 21, 111),
+    ("exact-18-100", 1 << 18, 100, EXACT, 22, 112),
+    ("general-22-8", 1 << 22, 8, GENERAL, 23, 113),
+    ("general-18-20", 1 << 18, 20, GENERAL, 24, 114),
+    ("dense-16-300", 1 << 16, 300, EXACT, 25, 115),      # w >= n: dense whatever the flags
+]
 
 
-def test_served_results_match_oracle_or_dense_reference(env):
+@pytest.mark.parametrize("which", ["policy", "sparse-only"])
+def test_served_results_match_oracle_or_dense_reference(env, which):
     torch, dev, sfft = env
-    srv = sfft.Server(slots=4, instances=2, budget_bytes=4 << 30)
+    cases = CASES if which == "policy" else SPARSE_CASES
+    flags = 0 if which == "policy" else sfft.SFFT_SERVER_SPARSE_ONLY
+    srv = sfft.Server(slots=4, instances=2, budget_bytes=8 << 30, flags=flags)
     sd = srv.desc
     n_dense = 0
     try:
-        for name, n, k, mode, gseed, rseed in CASES:
+        for name, n, k, mode, gseed, rseed in cases:
             say("serve", name, "n", n, "k", k, "mode", mode)
             x, sup, val, xt = make_signal(torch, dev, n, k, gseed, mode)
             idx, v, res = srv.wait(srv.submit(xt, k, mode, rseed))
@@ -107,7 +120,8 @@ def test_served_results_match_oracle_or_dense_reference(env):
                 else:
                     assert np.all(np.abs(v - rv) <= rel * np.abs(rv) + 1e-12)
         st = srv.stats()
-        assert st.completed == len(CASES) and st.failed == 0 and st.dense == n_dense == 3
+        assert st.completed == len(cases) and st.failed == 0
+        assert st.dense == n_dense == sum(name.startswith("dense") for name, *_ in cases)
         assert 0 < st.p50_ms <= st.p99_ms
     finally:
         srv.close()
@@ -115,14 +129,14 @@ def test_served_results_match_oracle_or_dense_reference(env):
 
 def test_each_request_is_the_same_alone_and_in_a_mix(env):
     torch, dev, sfft = env
-    say("alone-vs-mix", len(CASES), "shapes x 3 requests")
+    say("alone-vs-mix", len(SPARSE_CASES), "shapes x 3 requests")
     reqs = []
-    for name, n, k, mode, gseed, rseed in CASES:
+    for name, n, k, mode, gseed, rseed in SPARSE_CASES:
         for j in range(3):
             _, _, _, xt = make_signal(torch, dev, n, k, gseed + 100 * j, mode)
             reqs.append((xt, k, mode, rseed + j))
     torch.cuda.synchronize()
-    srv = sfft.Server(slots=4, instances=1, budget_bytes=4 << 30)
+    srv = sfft.Server(slots=4, instances=1, budget_bytes=4 << 30, flags=sfft.SFFT_SERVER_SPARSE_ONLY)
     try:
         alone = [srv.wait(srv.submit(*r)) for r in reqs]
         srv.reset_stats()
@@ -152,11 +166,13 @@ def test_budget_eviction_of_dense_instances(env):
     shapes = [(1 << 16, 16, EXACT), (1 << 18, 100, EXACT), (1 << 16, 600, EXACT)]   # the last is dense
     sd = sfft.sfft_server_desc_init()
     sd.slots = 2
+    sd.flags = sfft.SFFT_SERVER_SPARSE_ONLY
     assert [sfft.sfft_server_shape(sd, n, k, m)[1] for n, k, m in shapes] == [False, False, True]
     sizes = [sfft.sfft_server_shape(sd, n, k, m)[2] for n, k, m in shapes]
     budget = max(sizes) + min(sizes) // 2
     say("dense-eviction budget", budget, "instance sizes", sizes)
-    srv = sfft.Server(slots=2, instances=1, budget_bytes=budget, flags=sfft.SFFT_SERVER_EVICT_DENSE)
+    srv = sfft.Server(slots=2, instances=1, budget_bytes=budget,
+                      flags=sfft.SFFT_SERVER_EVICT_DENSE | sfft.SFFT_SERVER_SPARSE_ONLY)
     try:
         sigs = [make_signal(torch, dev, n, k, 60 + i, m)[3] for i, (n, k, m) in enumerate(shapes)]
         tickets = [srv.submit(sigs[i], k, m, 700 + 10 * rep + i)
@@ -181,6 +197,7 @@ def test_dense_instances_stay_resident_while_sparse_ones_are_evicted(env):
     sparse = [(1 << 16, 16, EXACT), (1 << 18, 100, EXACT)]
     sd = sfft.sfft_server_desc_init()
     sd.slots = 2
+    sd.flags = sfft.SFFT_SERVER_SPARSE_ONLY     # the small exact shapes stay sparse (evictable)
     assert sfft.sfft_server_shape(sd, *dense)[1] and not any(sfft.sfft_server_shape(sd, *s)[1] for s in sparse)
     dbytes = sfft.sfft_server_shape(sd, *dense)[2]
     sizes = [sfft.sfft_server_shape(sd, *s)[2] for s in sparse]
@@ -188,7 +205,7 @@ def test_dense_instances_stay_resident_while_sparse_ones_are_evicted(env):
     say("resident-dense budget", budget, "dense", dbytes, "sparse", sizes)
     shapes = [dense] + sparse
     sigs = [make_signal(torch, dev, n, k, 80 + i, m)[3] for i, (n, k, m) in enumerate(shapes)]
-    srv = sfft.Server(slots=2, instances=1, budget_bytes=budget)
+    srv = sfft.Server(slots=2, instances=1, budget_bytes=budget, flags=sfft.SFFT_SERVER_SPARSE_ONLY)
     try:
         outs = []
         for rep in range(3):
@@ -197,7 +214,7 @@ def test_dense_instances_stay_resident_while_sparse_ones_are_evicted(env):
         st = srv.stats()
         assert st.completed == 9 and st.failed == 0 and st.dense == 3
         assert st.peak_bytes <= budget and st.evictions >= 2 and st.instances == 2
-        big = sfft.Server(slots=2, instances=1, budget_bytes=4 << 30)
+        big = sfft.Server(slots=2, instances=1, budget_bytes=4 << 30, flags=sfft.SFFT_SERVER_SPARSE_ONLY)
         try:
             for i, rep, o in outs:
                 n, k, m = shapes[i]
@@ -208,7 +225,8 @@ def test_dense_instances_stay_resident_while_sparse_ones_are_evicted(env):
     finally:
         srv.close()
     # a shape whose instance does not fit beside the dense one
-    small = sfft.Server(slots=2, instances=1, budget_bytes=dbytes + min(sizes) // 2)
+    small = sfft.Server(slots=2, instances=1, budget_bytes=dbytes + min(sizes) // 2,
+                        flags=sfft.SFFT_SERVER_SPARSE_ONLY)
     try:
         small.wait(small.submit(sigs[0], dense[1], dense[2], 1), 60000.0)
         t = small.submit(sigs[1], sparse[0][1], sparse[0][2], 2)   # fits the budget alone, not beside
@@ -223,13 +241,14 @@ def test_budget_below_the_working_set_evicts_and_never_overflows(env):
     torch, dev, sfft = env
     sd = sfft.sfft_server_desc_init()
     sd.slots = 2
+    sd.flags = sfft.SFFT_SERVER_SPARSE_ONLY
     # three sparse-path shapes
     shapes = [(1 << 16, 16, EXACT), (1 << 18, 100, EXACT), (1 << 22, 8, GENERAL)]
     assert not any(sfft.sfft_server_shape(sd, n, k, m)[1] for n, k, m in shapes)
     sizes = [sfft.sfft_server_shape(sd, n, k, m)[2] for n, k, m in shapes]
     budget = max(sizes) + min(sizes) // 2          # room for one instance at a time
     say("budget", budget, "instance sizes", sizes)
-    srv = sfft.Server(slots=2, instances=1, budget_bytes=budget)
+    srv = sfft.Server(slots=2, instances=1, budget_bytes=budget, flags=sfft.SFFT_SERVER_SPARSE_ONLY)
     try:
         sigs = [make_signal(torch, dev, n, k, 40 + i, m)[3] for i, (n, k, m) in enumerate(shapes)]
         tickets = []
@@ -241,7 +260,7 @@ def test_budget_below_the_working_set_evicts_and_never_overflows(env):
         assert st.completed == len(tickets) and st.failed == 0
         assert st.peak_bytes <= budget and st.evictions >= 1
         # same answers as with room for every shape
-        big = sfft.Server(slots=2, instances=1, budget_bytes=4 << 30)
+        big = sfft.Server(slots=2, instances=1, budget_bytes=4 << 30, flags=sfft.SFFT_SERVER_SPARSE_ONLY)
         try:
             for t_out, (rep, i) in zip(outs, [(r, i) for r in range(3) for i in range(len(shapes))]):
                 n, k, m = shapes[i]

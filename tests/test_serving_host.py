@@ -16,15 +16,25 @@ def test_server_desc_defaults():
     assert d.delta_exact == 1e-9 and d.delta_general == 1e-6 and d.theta == 0.25
 
 
+def path_model_dense(n, mode, samples, streamed):
+    """The server's path model: predicted solo milliseconds of each path."""
+    if mode == sfft.SFFT_MODE_EXACT:
+        sparse = sfft.SFFT_SERVER_EXACT_MS + 1e-6 * (sfft.SFFT_SERVER_GATHER_NS * (samples - streamed) +
+                                                    sfft.SFFT_SERVER_STREAM_NS * streamed)
+    else:
+        sparse = sfft.SFFT_SERVER_GENERAL_MS + 1e-6 * sfft.SFFT_SERVER_GENERAL_NS * samples
+    return sparse > sfft.SFFT_SERVER_DENSE_MS + 1e-6 * sfft.SFFT_SERVER_DENSE_NS * n
+
+
 @pytest.mark.parametrize("n,k,mode,B,dense", [
-    (1 << 22, 256, sfft.SFFT_MODE_EXACT, 1024, False),
-    (1 << 22, 200, sfft.SFFT_MODE_EXACT, 1024, False),     # k rounded up to 256
-    (1 << 22, 8, sfft.SFFT_MODE_GENERAL, 256, False),
-    (1 << 20, 64, sfft.SFFT_MODE_GENERAL, 1024, True),     # gathers 4.9 samples per bin
-    (1 << 24, 1024, sfft.SFFT_MODE_EXACT, 4096, False),
-    (1 << 20, 1024, sfft.SFFT_MODE_EXACT, 4096, False),    # two stream rounds: 0.48 lines per sample
+    (1 << 22, 8, sfft.SFFT_MODE_EXACT, 64, False),         # measured solo: sparse 0.14 ms, dense 0.20
+    (1 << 24, 256, sfft.SFFT_MODE_EXACT, 1024, False),     # sparse 0.38, dense 0.54
+    (1 << 24, 1024, sfft.SFFT_MODE_EXACT, 4096, True),     # sparse 1.03, dense 0.56
+    (1 << 22, 256, sfft.SFFT_MODE_EXACT, 1024, True),      # sparse 0.31, dense 0.22
+    (1 << 22, 8, sfft.SFFT_MODE_GENERAL, 256, True),       # sparse 0.84, dense 0.22
+    (1 << 20, 1024, sfft.SFFT_MODE_EXACT, 4096, True),
     (1 << 16, 1024, sfft.SFFT_MODE_EXACT, 4096, True),     # window longer than the signal
-    (1 << 16, 8, sfft.SFFT_MODE_EXACT, 64, False),
+    (1 << 16, 8, sfft.SFFT_MODE_EXACT, 64, True),          # sparse 0.15, dense 0.13
     (1 << 16, 200, sfft.SFFT_MODE_GENERAL, 4096, True),
 ])
 def test_server_shape_policy(n, k, mode, B, dense):
@@ -36,15 +46,14 @@ def test_server_shape_policy(n, k, mode, B, dense):
     w = default_w(n, B, 0.5, delta)
     assert is_dense == dense
     if w < n:
-        # the sparse plan's memory lines decide against half a line per
-        # sample: a gathered sample is one line, a streamed round n/8
+        # the path model decides, from the sparse plan's gathered and
+        # streamed samples
         sparse = sfft.PlanDesc.from_buffer_copy(d)
         sparse.w = w
         samples = sfft.sfft_plan_samples(sparse)
         streamed = sfft.sfft_plan_stream_rounds(sparse) * n
         assert sparse.hash_mode == (1 if mode == sfft.SFFT_MODE_EXACT else 0)
-        lines = samples - streamed + streamed / 8
-        assert samples > 0 and dense == (lines > sfft.SFFT_SERVER_DENSE_SAMPLES_PER_N * n)
+        assert samples > 0 and dense == path_model_dense(n, mode, samples, streamed)
     if not dense:
         assert d.w == w
         # one instance = the plan's workspace + the server's staging buffers
@@ -59,6 +68,8 @@ def test_server_flags_force_a_path():
     sd = sfft.sfft_server_desc_init()
     sd.flags = sfft.SFFT_SERVER_SPARSE_ONLY
     assert not sfft.sfft_server_shape(sd, n, k, sfft.SFFT_MODE_GENERAL)[1]
+    sd.flags = 0
+    assert sfft.sfft_server_shape(sd, n, k, sfft.SFFT_MODE_GENERAL)[1]
     assert sfft.sfft_server_shape(sd, 1 << 16, 1024, sfft.SFFT_MODE_EXACT)[1]    # w >= n: dense anyway
     sd.flags = sfft.SFFT_SERVER_DENSE_ONLY
     assert sfft.sfft_server_shape(sd, 1 << 24, 8, sfft.SFFT_MODE_EXACT)[1]
@@ -214,7 +225,8 @@ def test_fake_server_rejects_a_shape_larger_than_the_budget():
 def test_fake_server_budget_eviction_and_peak():
     sd = sfft.sfft_server_desc_init()
     sd.slots = 4
-    shapes = [(1 << 16, 16), (1 << 18, 100), (1 << 20, 64)]
+    shapes = [(1 << 22, 8), (1 << 23, 64), (1 << 24, 8)]     # sparse-path shapes under the path model
+    assert not any(sfft.sfft_server_shape(sd, n, k, 0)[1] for n, k in shapes)
     sizes = [sfft.sfft_server_shape(sd, n, k, 0)[2] for n, k in shapes]
     budget = max(sizes) + min(sizes) // 2
     srv = FakeServer(slots=4, instances=1, budget_bytes=budget, fake_service_ms=2.0)
@@ -280,7 +292,7 @@ def test_fake_server_keeps_dense_instances_resident():
     sd = sfft.sfft_server_desc_init()
     sd.slots = 2
     dense = (1 << 16, 600, 0)
-    sparse = [(1 << 20, 64, 0), (1 << 22, 100, 0)]
+    sparse = [(1 << 22, 8, 0), (1 << 23, 64, 0)]
     assert sfft.sfft_server_shape(sd, *dense)[1] and not any(sfft.sfft_server_shape(sd, *s)[1] for s in sparse)
     dbytes = sfft.sfft_server_shape(sd, *dense)[2]
     sizes = [sfft.sfft_server_shape(sd, *s)[2] for s in sparse]
@@ -307,7 +319,7 @@ def test_fake_server_fails_a_shape_that_cannot_fit_beside_dense_instances():
     sd = sfft.sfft_server_desc_init()
     sd.slots = 2
     dense = (1 << 16, 600, 0)
-    sparse = (1 << 22, 100, 0)
+    sparse = (1 << 22, 64, 0)
     dbytes = sfft.sfft_server_shape(sd, *dense)[2]
     sbytes = sfft.sfft_server_shape(sd, *sparse)[2]
     budget = max(dbytes, sbytes) + min(dbytes, sbytes) // 2
