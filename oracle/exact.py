@@ -11,6 +11,9 @@ w_r = w B_r / B window (params.round_bins):
     fraction of |u_j|^2): the phase of u_j / u'_j equals 2 pi sigma i / n for an isolated
     coefficient (the exact-estimation lemma of Section 3), so
         p = round(phi(u_j / u'_j) n / (2 pi)) mod n,   i = sigma^{-1} p mod n;
+    (with refine_shift = A > 0 a third hashing u_A = HashToBins(x, zhat,
+    P_{sigma,A,b}) refines p: the candidate c within refine_window of p whose
+    angle 2 pi (A c mod n) / n is nearest the phase of u_j / u_A,j);
     accept i only if h(i) = j and G'_{-o(i)} >= g_min, with value
         v = u_j / G'_{-o(i)}
     (the HashToBins lemma with a single term; equals the paper's round(u_j)
@@ -62,9 +65,10 @@ class Margins:
     gmin: float = math.inf        # | G' - g_min | for decoded candidates
     output: float = math.inf      # | |value| - theta/2 |
     ratio: float = math.inf       # | ||u'|^2 - |u|^2| / |u|^2 - ratio_tol | when the check is on
+    refine: float = math.inf      # gap between the best and second-best refinement candidates (radians)
 
     def smallest(self):
-        return min(self.threshold, self.rounding, self.gmin, self.output, self.ratio)
+        return min(self.threshold, self.rounding, self.gmin, self.output, self.ratio, self.refine)
 
 
 @dataclass
@@ -76,15 +80,38 @@ class ExactResult:
     zhat_decoded: dict
     round_log: list = field(default_factory=list)   # (|J|, accepted) per round
     raw: list = field(default_factory=list)         # (sigma, b, u0_raw, u1_raw) per round
+    raw_refine: list = field(default_factory=list)  # u_A raw bins per round (refine_shift > 0)
     margins: Margins = field(default_factory=Margins)
 
 
-def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Margins, alpha=None):
+def refine_position(p0, phase_a, A, n, E, margins: Margins):
+    """The position c in [p0 - E, p0 + E] whose angle 2 pi (A c mod n) / n is
+    nearest (circularly) to phase_a, the phase of u / u_A; ties keep the
+    smaller c.  An isolated coefficient at permuted position p has
+    u_A = u omega^{A p} (the exact-estimation lemma at shift A), so this
+    angle is exact in integers and the phase pins p once the coarse error
+    is within E and A (2E + 1) < n."""
+    best, bestd, second = None, math.inf, math.inf
+    for c in range(p0 - E, p0 + E + 1):
+        ang = TWO_PI * ((A * c) % n) / n
+        d = abs(ang - phase_a) % TWO_PI
+        d = min(d, TWO_PI - d)
+        if d < bestd:
+            second, bestd, best = bestd, d, c
+        elif d < second:
+            second = d
+    margins.refine = min(margins.refine, second - bestd)
+    return best % n
+
+
+def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Margins, alpha=None, uAj=None):
     """Location and value of bin j of a B-bin hashing; returns (i, v) or None.
     With ratio_tol > 0 a bin whose two hashings differ in magnitude by more
     than that fraction is not decoded: an isolated coefficient gives
     u'_j = u_j omega^{sigma i} (the exact-estimation lemma), equal in
-    magnitude, while a bin shared by several coefficients almost never does."""
+    magnitude, while a bin shared by several coefficients almost never does.
+    With refine_shift > 0 the position from the pair's phase is refined by the
+    third hashing uAj (refine_position)."""
     n = p.n
     if p.ratio_tol > 0.0:
         m0 = u0j.real * u0j.real + u0j.imag * u0j.imag
@@ -99,6 +126,12 @@ def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Marg
     q = phi / TWO_PI * n
     margins.rounding = min(margins.rounding, abs(q - math.floor(q) - 0.5))
     pos = int(math.floor(q + 0.5)) % n
+    if p.refine_shift:
+        zA = u0j * np.conj(uAj)
+        phA = math.atan2(zA.imag, zA.real)
+        if phA < 0.0:
+            phA += TWO_PI
+        pos = refine_position(pos, phA, p.refine_shift, n, p.refine_window, margins)
     i = (sigma_inv * pos) % n
     if p.literal:
         return i, complex(round(u0j.real), round(u0j.imag))
@@ -132,6 +165,11 @@ def noiseless_sparse_fft(x, p: SfftParams) -> ExactResult:
         res.raw.append((sigma, b, u0_raw, u1_raw))
         u0 = subtract_zhat(u0_raw, zhat, sigma, 0, b, Br, n, ar, p.delta)
         u1 = subtract_zhat(u1_raw, zhat, sigma, 1, b, Br, n, ar, p.delta)
+        uA = None
+        if p.refine_shift:
+            uA_raw = hash_to_bins_raw(x, sigma, p.refine_shift, b, Br, G)
+            res.raw_refine.append(uA_raw)
+            uA = subtract_zhat(uA_raw, zhat, sigma, p.refine_shift, b, Br, n, ar, p.delta)
         mag = np.abs(u0)
         res.margins.threshold = min(res.margins.threshold, float(np.min(np.abs(mag - p.theta))))
         J = [j for j in range(Br) if mag[j] > p.theta]
@@ -148,7 +186,8 @@ def noiseless_sparse_fft(x, p: SfftParams) -> ExactResult:
         updates = {}
         best = {}
         for j in J:
-            got = decode_bin(u0[j], u1[j], j, sigma, sigma_inv, b, Br, p, res.margins, ar)
+            got = decode_bin(u0[j], u1[j], j, sigma, sigma_inv, b, Br, p, res.margins, ar,
+                             None if uA is None else uA[j])
             if got is None:
                 continue
             i, v = got

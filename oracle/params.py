@@ -47,6 +47,12 @@ rounds    exact mode: maximum number of NoiselessSparseFFTInner rounds
 t, s      LocateInner region count and vote tolerance (Algorithm 3)
 R_loc     LocateInner measurements per level (Algorithm 3)
 R_est     EstimateValues measurements (Algorithm 2)
+refine_shift  exact mode: 0 (off) or a third hashing per round at shift a = A
+          (the multi-shift idea of LocateInner, Algorithm 3, used to estimate
+          the phase with a few more samples): the pair's phase gives a coarse
+          position p0, and the candidate c in [p0 - E, p0 + E] whose angle
+          2 pi (A c mod n) / n is nearest the phase of u / u_A is taken
+refine_window  E, the half-width of that candidate window
 cap       largest output size (defaults to k)
 literal   exact mode only: the paper-literal decode v = round(u_j) for integer
           spectra, without the bin and window checks
@@ -77,6 +83,8 @@ class SfftParams:
     s: float = 0.125
     R_loc: int = 3
     R_est: int = 7
+    refine_shift: int = 0
+    refine_window: int = 16
     cap: int = 0
     literal: bool = False
 

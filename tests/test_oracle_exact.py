@@ -268,3 +268,68 @@ def test_ratio_check_keeps_exact_recovery(seed):
     r = noiseless_sparse_fft(x, p)
     assert np.array_equal(r.indices, sup)
     assert np.max(np.abs(r.values - val)) < 1e-4
+
+
+def test_refine_position_recovers_p_within_the_window():
+    """refine_position: with the exact angle of A p (plus noise far below the
+    candidate spacing 2 pi A / n) every coarse start within E of p returns p,
+    and a start farther than E cannot."""
+    from oracle.exact import Margins, refine_position
+    rng = np.random.default_rng(5)
+    n, A, E = 1 << 20, 1 << 10, 16
+    for _ in range(50):
+        p = int(rng.integers(0, n))
+        ph = (2 * math.pi * ((A * p) % n) / n + rng.normal(0, 1e-6)) % (2 * math.pi)
+        for off in (-E, -7, -1, 0, 1, 9, E):
+            assert refine_position(p + off, ph, A, n, E, Margins()) == p
+        assert refine_position(p + E + 1, ph, A, n, E, Margins()) != p
+
+
+def test_refinement_corrects_a_coarse_phase_error():
+    """An isolated flat coefficient: with the pair's phase pushed off by up to
+    5 positions (as FP32 bins can push it at n = 2^22), the plain decode
+    names the wrong frequency, while the third hashing at shift A puts it
+    back (the exact-estimation lemma at shift A: u_A = u omega^{A sigma i})."""
+    from oracle.exact import Margins, decode_bin
+    n, B, alpha, delta = 1 << 16, 64, 0.5, 1e-12
+    w = default_w(n, B, alpha, delta)
+    G = window_time(n, B, w, alpha, delta)
+    A = 256
+    p_plain = SfftParams(n=n, k=1, B=B, w=w, seed=0, delta=delta)
+    p_ref = SfftParams(n=n, k=1, B=B, w=w, seed=0, delta=delta, refine_shift=A, refine_window=16)
+    rng = np.random.default_rng(11)
+    tried = 0
+    while tried < 12:
+        i0 = int(rng.integers(0, n))
+        X = np.zeros(n, complex)
+        X[i0] = complex(rng.standard_normal(), rng.standard_normal())
+        x = np.fft.ifft(X) * np.sqrt(n)
+        sigma, b = 2 * int(rng.integers(0, n // 2)) + 1, int(rng.integers(0, n))
+        h, o = bin_offset(i0, sigma, b, n, B)
+        if gprime(-o, n, B, alpha, delta) < 0.5:
+            continue
+        tried += 1
+        u0 = hash_to_bins_raw(x, sigma, 0, b, B, G)[h]
+        u1 = hash_to_bins_raw(x, sigma, 1, b, B, G)[h]
+        uA = hash_to_bins_raw(x, sigma, A, b, B, G)[h]
+        assert abs(uA - u0 * np.exp(-2j * np.pi * ((A * sigma * i0) % n) / n)) < 1e-9 * abs(u0)
+        sinv = pow(sigma, -1, n)
+        for shift in (-5, -2, 3, 5):
+            u1s = u1 * np.exp(-2j * np.pi * shift / n)          # the pair's phase off by `shift` positions
+            plain = decode_bin(u0, u1s, h, sigma, sinv, b, B, p_plain, Margins())
+            assert plain is None or plain[0] != i0
+            got = decode_bin(u0, u1s, h, sigma, sinv, b, B, p_ref, Margins(), uAj=uA)
+            assert got is not None and got[0] == i0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_planted_recovery_with_refinement(seed):
+    """The exact recovery with the third hashing per round: the same supports
+    and values as without it (FP64: the coarse position is already exact, so
+    the refinement must keep it)."""
+    p = c1_params(seed, refine_shift=64, refine_window=16)
+    x, sup, val = siggen.planted_signal(p.n, p.k, 100 + seed, np.complex128)
+    r = noiseless_sparse_fft(x, p)
+    assert np.array_equal(r.indices, sup)
+    assert np.max(np.abs(r.values - val)) < 1e-9
+    assert len(r.raw_refine) == len(r.raw)
