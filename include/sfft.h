@@ -173,6 +173,19 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *             the gathered lines; 2 streams every round.  The raw bins are
  *             the same up to the order of floating-point additions.  The
  *             plain path and general mode always gather
+ *   refine_shift  exact mode, batched path: 0 (off) or A, the shift of a
+ *             third hashing per round (the multi-shift idea of LocateInner,
+ *             Algorithm 3, used to estimate the phase with a few more
+ *             samples).  The pair's phase gives a coarse permuted position
+ *             p0; the position c in [p0 - E, p0 + E] whose angle
+ *             2 pi (A c mod n) / n is nearest the phase of u / u_A (ties: the
+ *             smaller c) replaces it, so FP32 bins (loc_prec SFFT_F32) locate
+ *             at n where the pair's FP32 phase alone cannot.  The same pair
+ *             workgroup accumulates the third hashing: A <= w_r reads
+ *             A more samples per round, A > w_r another w_r.  Needs
+ *             2 <= A < n, A (2E + 1) < n, hash_split <= 1 and hash_mode 0
+ *   refine_window  E, the half-width of the refinement's candidate window
+ *             (1..1024; default 16 when refine_shift is set)
  */
 typedef struct {
     uint64_t n;
@@ -209,6 +222,9 @@ typedef struct {
     double alpha_decay;
     uint32_t hash_split;
     uint32_t hash_mode;
+    uint64_t refine_shift;
+    uint32_t refine_window;
+    uint32_t reserved;
 } sfft_plan_desc_t;
 
 typedef struct sfft_plan_s* sfft_plan_t;
@@ -371,6 +387,21 @@ sfft_status_t sfft_plan_round_groups(sfft_plan_t p, uint32_t* ends_host, uint32_
  */
 sfft_status_t sfft_plan_raw_slot(sfft_plan_t p, uint32_t sig, uint32_t slot, double* out_dev, uint32_t* B_r_out,
                                  void* stream);
+
+/*
+ * Copy the raw bins of the refinement hashing (shift refine_shift) of exact
+ * round `round` of one signal from the batched workspace, after
+ * sfft_execute_batch has completed on `stream`.  out_dev is [B_r][2]
+ * doubles; *B_r_out receives B_r.  Rounds after a signal stopped hold stale
+ * bins.  Errors: SFFT_EINVAL for NULL arguments, a plan without
+ * refine_shift, or a signal or round out of range.
+ */
+sfft_status_t sfft_plan_raw_refine(sfft_plan_t p, uint32_t sig, uint32_t round, double* out_dev, uint32_t* B_r_out,
+                                   void* stream);
+
+/* sizeof(sfft_plan_desc_t) as this library was built, so a binding can
+ * check its copy of the struct. */
+uint32_t sfft_plan_desc_bytes(void);
 
 /* Human-readable name of a status code (static storage). */
 const char* sfft_status_string(sfft_status_t s);

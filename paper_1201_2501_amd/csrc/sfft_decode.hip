@@ -1036,7 +1036,7 @@ __device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, do
 
 // =================================================================== exact
 __device__ __forceinline__ const double* raw_bins(const DecodeArgs& D, uint32_t sig, uint32_t r, uint32_t a) {
-    return D.raw + (((uint64_t)sig * D.rounds + r) * 2 + a) * (uint64_t)D.Bmax * 2;
+    return D.raw + (((uint64_t)sig * D.rounds + r) * D.nhash + a) * (uint64_t)D.Bmax * 2;
 }
 
 // Per-entry terms of HashToBins step 4 under (sigma, b, B): the bin hk[e]
@@ -1068,12 +1068,70 @@ __device__ void stage_terms(DecodeLds& L, uint32_t zc, const double2 (&zp)[kUnro
     group_by_bin(L, zc, B);
 }
 
+// Multi-shift refinement of a coarse permuted position p0 (the LocateInner
+// idea of Algorithm 3 with one more hashing, at shift A = refine_shift):
+// bin j of the hashing at shift A, less the zhat terms of the bin (each
+// G'_{-o(i)} zhat_i omega^{A sigma i}, ascending index order), gives u_A;
+// an isolated coefficient at permuted position p has u_A = u omega^{A p}.
+// The position c in [p0 - E, p0 + E] whose angle 2 pi (A c mod n) / n is
+// nearest (circularly) to the phase of u / u_A wins; ties keep the first
+// (smallest) c.  Angles are exact in integers, so FP32 bins only need to
+// resolve the spacing 2 pi A / n.
+// With c = p0 - E + q, A c = base + A q (mod n) and A (2E + 1) < n, so A q
+// runs once through [0, n) without wrapping: the circular distance to the
+// target d0 = phase n / (2 pi) - base is smallest at q next to d0 / A or at
+// q = 0 or 2E.  Those candidates (with one more on each side of d0 / A, for
+// the rounding of d0) are scored in ascending q with the scan's formula;
+// every other q is at least 2 pi A / n farther, so the winner is the scan's.
+__device__ __noinline__ uint64_t refine_position(const DecodeArgs& D, const DecodeLds& L, uint32_t j, double u0r,
+                                                 double u0i, double2 aA, uint64_t sigma, uint64_t n, uint64_t p0) {
+    const double two_pi = 6.283185307179586;
+    const uint64_t mask = n - 1, A = D.refine_shift, E = D.refine_window;
+    double uAr = aA.x, uAi = aA.y;
+    for (uint32_t q = L.first[j]; q < L.first[j + 1]; ++q) {
+        const uint32_t e = L.ent[q];
+        const uint64_t i = L.zl[e];
+        const cx<double> cA = cmul(L.t[2 * e], omega_d((A * ((sigma * i) & mask)) & mask, n));
+        uAr -= cA.r;
+        uAi -= cA.i;
+    }
+    const double zr = u0r * uAr + u0i * uAi;
+    const double zim = u0i * uAr - u0r * uAi;
+    double ph = atan2(zim, zr);
+    if (ph < 0.0) ph += two_pi;
+    const uint64_t c0 = (p0 - E) & mask;
+    double d0 = ph / two_pi * (double)n - (double)((A * c0) & mask);
+    if (d0 < 0.0) d0 += (double)n;
+    const int64_t qm = (int64_t)floor(d0 / (double)A);
+    const int64_t top = (int64_t)(2 * E);
+    const int64_t cand[6] = {0, qm - 1, qm, qm + 1, qm + 2, top};
+    uint64_t best = p0;
+    double bestd = INFINITY;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int64_t q = cand[k] < 0 ? 0 : (cand[k] > top ? top : cand[k]);
+        const uint64_t c = (c0 + (uint64_t)q) & mask;
+        const double ang = two_pi * (double)((A * c) & mask) / (double)n;
+        double d = fabs(ang - ph);
+        d = d < two_pi - d ? d : two_pi - d;
+        if (d < bestd) {
+            bestd = d;
+            best = c;
+        }
+    }
+    return best;
+}
+
 // Decode bin j of one round from its raw pair (u0, u1): subtract the zhat
 // terms of the bin in ascending index order, then, when |u0| > theta, the
-// phase of u1 / u0 names the frequency.  Returns whether |u0| > theta.
+// phase of u1 / u0 names the frequency (refined by the hashing at shift
+// refine_shift when the plan has one, rA its raw bins).  Returns whether
+// |u0| > theta.  REF: the plan has the refinement hashing (a separate
+// instantiation, so the plain decode keeps its registers).
+template <bool REF>
 __device__ __forceinline__ bool exact_bin(const DecodeArgs& D, DecodeLds& L, uint32_t j, double2 a0, double2 a1,
                                           uint64_t sigma, uint64_t sinv, uint64_t b, uint64_t n, uint32_t B,
-                                          const WindowShape& ws, double* cv) {
+                                          const WindowShape& ws, double* cv, const double2* rA) {
     const double two_pi = 6.283185307179586;
     const uint64_t mask = n - 1;
     double u0r = a0.x, u0i = a0.y, u1r = a1.x, u1i = a1.y;
@@ -1097,7 +1155,8 @@ __device__ __forceinline__ bool exact_bin(const DecodeArgs& D, DecodeLds& L, uin
     double phi = atan2(zim, zr);
     if (phi < 0.0) phi += two_pi;
     const double qf = phi / two_pi * (double)n;
-    const uint64_t pos = ((uint64_t)floor(qf + 0.5)) & mask;
+    uint64_t pos = ((uint64_t)floor(qf + 0.5)) & mask;
+    if (REF) pos = refine_position(D, L, j, u0r, u0i, rA[j], sigma, n, pos);
     const uint64_t i = (sinv * pos) & mask;
     const BinOffset bo = bin_offset(i, sigma, b, n, B);
     if (bo.h != j) return true;
@@ -1112,6 +1171,7 @@ __device__ __forceinline__ bool exact_bin(const DecodeArgs& D, DecodeLds& L, uin
 // One round of NoiselessSparseFFTInner on signal `sig` (Algorithm 1).  The
 // HBM loads of the round (this lane's first raw bins and zhat values) are
 // issued first, so that their latency overlaps the staging.
+template <bool REF>
 __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uint32_t r, uint64_t seed) {
     const uint32_t tid = threadIdx.x;
     const RoundDev g = D.geom[r];
@@ -1122,6 +1182,7 @@ __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uin
     const uint64_t sinv = inverse_odd(sigma) & mask;
     const double2* r0 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 0));
     const double2* r1 = reinterpret_cast<const double2*>(raw_bins(D, sig, r, 1));
+    const double2* rA = REF ? reinterpret_cast<const double2*>(raw_bins(D, sig, r, 2)) : nullptr;
     double2 a0[kUnroll], a1[kUnroll];
 #pragma unroll
     for (uint32_t u = 0; u < kUnroll; ++u) {
@@ -1149,7 +1210,7 @@ __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uin
 #pragma unroll
     for (uint32_t u = 0; u < kUnroll; ++u) {
         const uint32_t j = tid + u * kDec;
-        if (j < B) myJ += exact_bin(D, L, j, a0[u], a1[u], sigma, sinv, b, n, B, g.ws, cv);
+        if (j < B) myJ += exact_bin<REF>(D, L, j, a0[u], a1[u], sigma, sinv, b, n, B, g.ws, cv, rA);
     }
     for (uint32_t j0 = tid + kUnroll * kDec; j0 < B; j0 += kUnroll * kDec) {
 #pragma unroll
@@ -1163,7 +1224,7 @@ __device__ void exact_round(const DecodeArgs& D, DecodeLds& L, uint32_t sig, uin
 #pragma unroll
         for (uint32_t u = 0; u < kUnroll; ++u) {
             const uint32_t j = j0 + u * kDec;
-            if (j < B) myJ += exact_bin(D, L, j, a0[u], a1[u], sigma, sinv, b, n, B, g.ws, cv);
+            if (j < B) myJ += exact_bin<REF>(D, L, j, a0[u], a1[u], sigma, sinv, b, n, B, g.ws, cv, rA);
         }
     }
     if (myJ) atomicAdd(&L.misc[0], myJ);
@@ -1214,6 +1275,7 @@ __global__ void __launch_bounds__(kDec) k_exact_init(DecodeArgs D) {
     for (uint32_t q = 0; q < kStateWords; ++q) st[q] = 0;
 }
 
+template <bool REF>
 __global__ void __launch_bounds__(kDec) k_exact_decode(DecodeArgs D) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t sig = blockIdx.x;
@@ -1226,7 +1288,7 @@ __global__ void __launch_bounds__(kDec) k_exact_decode(DecodeArgs D) {
     for (uint32_t r = D.r_begin; r < D.r_end; ++r) {
         __syncthreads();
         if (L.sw[ST_DONE]) break;
-        exact_round(D, L, sig, r, seed);
+        exact_round<REF>(D, L, sig, r, seed);
     }
     store_state(L, st);
 }
@@ -1869,9 +1931,15 @@ hipError_t launch_exact_init(const DecodeArgs& a, hipStream_t s) {
 
 hipError_t launch_exact_decode(const DecodeArgs& a, hipStream_t s) {
     const size_t lds = decode_lds_bytes(a.capz, a.Bmax);
-    hipError_t e = allow_lds(k_exact_decode, lds);
+    if (a.refine_shift) {
+        hipError_t e = allow_lds(k_exact_decode<true>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_exact_decode<true>, dim3(a.count), dim3(kDec), lds, s, a);
+        return hipGetLastError();
+    }
+    hipError_t e = allow_lds(k_exact_decode<false>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_exact_decode, dim3(a.count), dim3(kDec), lds, s, a);
+    hipLaunchKernelGGL(k_exact_decode<false>, dim3(a.count), dim3(kDec), lds, s, a);
     return hipGetLastError();
 }
 

@@ -141,6 +141,7 @@ struct sfft_plan_s {
     uint32_t capz = 0;
     uint32_t cap = 0;
     uint32_t mcap = 0;         // largest modulation table of the pair kernel
+    uint32_t nhash = 2;        // raw-bin slots per round: the pair, plus the refinement hashing
     std::vector<RoundDev> geom;
     RoundDev* d_geom = nullptr;
     // general mode
@@ -246,6 +247,7 @@ sfft_status_t resolve_and_validate(sfft_plan_desc_t& d) {
     if (d.cap == 0) d.cap = d.k;
     if (d.rounds == 0) d.rounds = d.mode == SFFT_MODE_GENERAL ? general_default_rounds(d.k) : 16;
     if (d.hash_threads == 0) d.hash_threads = 256;
+    if (d.refine_shift && d.refine_window == 0) d.refine_window = 16;
     return SFFT_OK;
 }
 
@@ -356,6 +358,14 @@ sfft_status_t build_plan(sfft_plan_s* p) {
         const int64_t Llo = floordiv(g.t0 - 1 - (iB - 1), iB);
         const int64_t Lhi = floordiv(g.t0 + (int64_t)g.w - 1, iB);
         p->mcap = std::max<uint32_t>(p->mcap, (uint32_t)(Lhi - Llo + 1));
+        if (!general_mode(p) && d.refine_shift) {
+            // the pair with the refinement hashing: one window [t0 - A, t0 + w)
+            // for A < w + 1, else [t0 - A, t0 - A + w) beside the pair's
+            const int64_t iA = (int64_t)d.refine_shift, iw = (int64_t)g.w;
+            const int64_t lo0 = g.t0 - iA, hi0 = iA < iw + 1 ? g.t0 + iw : lo0 + iw;
+            const int64_t L0 = floordiv(lo0 - (iB - 1), iB), L1 = floordiv(hi0 - 1, iB);
+            p->mcap = std::max<uint32_t>(p->mcap, (uint32_t)(L1 - L0 + 1));
+        }
         if (general_mode(p)) p->mcap = std::max<uint32_t>(p->mcap, (uint32_t)(2 * (g.w / g.B) + 4));
         p->geom.push_back(g);
     }
@@ -433,12 +443,16 @@ sfft_status_t build_plan(sfft_plan_s* p) {
                               hipMemcpyHostToDevice));
         }
     }
+    p->nhash = !general_mode(p) && d.refine_shift ? 3 : 2;
+    if (p->nhash == 3 && h2b_pair_lds_bytes(p->Bmax, p->mcap, d.loc_prec == SFFT_F64, d.hash_threads, true) > 160 * 1024)
+        return fail(SFFT_EUNSUPPORTED, "refinement hashing: the pair kernel's LDS would exceed 160 KiB (smaller B or FP32 bins)");
     // batched workspace
     const size_t S = d.max_batch;
     const size_t Bm = p->Bmax, R = p->R, Z = p->capz;
     const size_t raw_slots = general_mode(p) ? p->nslots : p->R;
     const size_t meas = general_mode(p) ? (size_t)p->R * d.R_est : p->R;
-    ST_TRY(dev_alloc(p, &p->raw, S * raw_slots * 4 * Bm));
+    const size_t per_slot = 2 * (size_t)p->nhash * Bm;   // doubles of one round's raw bins
+    ST_TRY(dev_alloc(p, &p->raw, S * raw_slots * per_slot));
     if (general_mode(p)) {
         ST_TRY(dev_alloc(p, &p->cand_e, S * d.R_est * 2 * Bm));
         ST_TRY(dev_alloc(p, &p->cand_n, S * Bm));
@@ -477,7 +491,7 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     }
     // plain path (one signal): raw bins of every round, split partials
     p->p_parts_max = 64;
-    ST_TRY(dev_alloc(p, &p->p_raw, raw_slots * 4 * Bm));
+    ST_TRY(dev_alloc(p, &p->p_raw, raw_slots * per_slot));
     ST_TRY(dev_alloc(p, &p->p_partial, (size_t)p->p_parts_max * 4 * Bm));
     ST_TRY(dev_alloc(p, &p->p_idx, p->cap));
     ST_TRY(dev_alloc(p, &p->p_val, 2 * (size_t)p->cap));
@@ -521,6 +535,8 @@ H2BArgs base_h2b(const sfft_plan_s* p, const void* x) {
     a.mcap = p->mcap;
     a.threads = p->d.hash_threads;
     a.order = p->d.hash_order;
+    a.nhash = p->nhash;
+    a.gamma = general_mode(p) ? 0 : p->d.refine_shift;
     return a;
 }
 
@@ -537,6 +553,9 @@ DecodeArgs base_decode(const sfft_plan_s* p, uint32_t count, const uint64_t* see
     D.stop_count = p->d.mode == SFFT_MODE_EXACT ? p->d.stop_count : 0;
     D.stop_patience = p->d.stop_patience;
     D.ratio_tol = p->d.ratio_tol;
+    D.nhash = p->nhash;
+    D.refine_shift = p->d.refine_shift;
+    D.refine_window = p->d.refine_window;
     D.Bmax = p->Bmax;
     D.capz = p->capz;
     D.cap = p->cap;
@@ -650,7 +669,7 @@ sfft_status_t enqueue_general_hash(sfft_plan_s* p, const void* x, uint32_t count
 // Per-signal workspace and output pointers advanced to signal `off`.
 void offset_decode(const sfft_plan_s* p, DecodeArgs& D, uint32_t off) {
     const uint64_t Bm = p->Bmax, Z = p->capz, o = off;
-    D.raw += o * p->R * 4 * Bm;
+    D.raw += o * p->R * 2 * p->nhash * Bm;
     D.work += o * 4 * Bm;
     D.cand_i += o * Bm;
     D.cand_v += o * 2 * Bm;
@@ -770,7 +789,7 @@ sfft_status_t enqueue_chunk(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt
     a.xptrs = xpc;
     a.seeds = sc;
     a.count = cnt;
-    a.raw = p->raw + (uint64_t)off * p->R * 4 * p->Bmax;
+    a.raw = p->raw + (uint64_t)off * p->R * 2 * p->nhash * p->Bmax;
     a.raw_rounds = p->R;
     if (part == 0) {
         HIP_TRY(launch_exact_init(D, s));
@@ -901,6 +920,9 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->alpha_decay = 0.0;
     d->hash_split = 0;
     d->hash_mode = 0;
+    d->refine_shift = 0;
+    d->refine_window = 0;
+    d->reserved = 0;
     return SFFT_OK;
 }
 
@@ -939,6 +961,15 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (d->hash_mode > 2) return fail(SFFT_EINVAL, "hash_mode must be 0, 1 or 2");
     if (d->hash_mode != 0 && (d->mode == SFFT_MODE_GENERAL || d->chunks > 1))
         return fail(SFFT_EINVAL, "hash_mode applies to exact mode with at most one chunk");
+    if (d->refine_window > 1024) return fail(SFFT_EINVAL, "refine_window must be in [0, 1024]");
+    if (d->refine_shift != 0) {
+        const uint64_t E = d->refine_window ? d->refine_window : 16;
+        if (d->mode == SFFT_MODE_GENERAL) return fail(SFFT_EINVAL, "refine_shift applies to exact mode only");
+        if (d->refine_shift < 2 || d->refine_shift >= d->n || d->refine_shift * (2 * E + 1) >= d->n)
+            return fail(SFFT_EINVAL, "refine_shift A needs 2 <= A and A (2 refine_window + 1) < n");
+        if (d->hash_split > 1 || d->hash_mode != 0)
+            return fail(SFFT_EINVAL, "refine_shift needs hash_split <= 1 and hash_mode 0");
+    }
     if (d->hash_split > 64) return fail(SFFT_EINVAL, "hash_split must be in [0, 64]");
     if (d->hash_split > 1 && (d->mode == SFFT_MODE_GENERAL || d->chunks > 1))
         return fail(SFFT_EINVAL, "hash_split applies to exact mode with at most one chunk");
@@ -985,6 +1016,14 @@ uint64_t sfft_plan_device_bytes(const sfft_plan_desc_t* desc) {
     return p.device_bytes;
 }
 
+// Gathered samples of exact round r's pair launch: w_r + 1, plus A (or w_r
+// for A > w_r) with the refinement hashing.
+uint64_t refined_samples(const sfft_plan_s* p, uint32_t r) {
+    const uint64_t w = p->geom[r].w, A = p->d.refine_shift;
+    if (general_mode(p) || A == 0) return w + 1;
+    return A < w + 1 ? w + A : 2 * w + 1;
+}
+
 uint64_t sfft_plan_samples(const sfft_plan_desc_t* desc) {
     if (!desc) return 0;
     sfft_plan_desc_t d = *desc;
@@ -1001,7 +1040,7 @@ uint64_t sfft_plan_samples(const sfft_plan_desc_t* desc) {
     } else {
         // the pair of each round of group 0 (the rounds before the earliest
         // stop): w_r + 1 gathered samples, or the whole signal in stream mode
-        for (uint32_t r = 0; r < p.group_end[0]; ++r) samples += p.stream_round[r] ? d.n : p.geom[r].w + 1;
+        for (uint32_t r = 0; r < p.group_end[0]; ++r) samples += p.stream_round[r] ? d.n : refined_samples(&p, r);
     }
     return samples;
 }
@@ -1084,7 +1123,7 @@ sfft_status_t sfft_plan_raw_slot(sfft_plan_t p, uint32_t sig, uint32_t slot, dou
             if (p->groundv[r].slot0 <= slot) round = r;
     }
     const uint32_t B = p->geom[round].B;
-    const double* src = p->raw + ((uint64_t)sig * nslots + slot) * 4 * (uint64_t)p->Bmax;
+    const double* src = p->raw + ((uint64_t)sig * nslots + slot) * 2 * p->nhash * (uint64_t)p->Bmax;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(out_dev, src, 2 * sizeof(double) * B, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(out_dev + 2 * (size_t)B, src + 2 * (size_t)p->Bmax, 2 * sizeof(double) * B,
@@ -1093,13 +1132,28 @@ sfft_status_t sfft_plan_raw_slot(sfft_plan_t p, uint32_t sig, uint32_t slot, dou
     return SFFT_OK;
 }
 
+sfft_status_t sfft_plan_raw_refine(sfft_plan_t p, uint32_t sig, uint32_t round, double* out_dev, uint32_t* B_r_out,
+                                   void* stream) {
+    if (!p || !out_dev || !B_r_out) return fail(SFFT_EINVAL, "NULL argument");
+    if (p->nhash != 3) return fail(SFFT_EINVAL, "the plan has no refinement hashing");
+    if (sig >= p->d.max_batch || round >= p->R) return fail(SFFT_EINVAL, "signal or round out of range");
+    const uint32_t B = p->geom[round].B;
+    const double* src = p->raw + (((uint64_t)sig * p->R + round) * 3 + 2) * 2 * (uint64_t)p->Bmax;
+    HIP_TRY(hipMemcpyAsync(out_dev, src, 2 * sizeof(double) * B, hipMemcpyDeviceToDevice,
+                           reinterpret_cast<hipStream_t>(stream)));
+    *B_r_out = B;
+    return SFFT_OK;
+}
+
+uint32_t sfft_plan_desc_bytes(void) { return (uint32_t)sizeof(sfft_plan_desc_t); }
+
 uint64_t sfft_plan_h2b_bytes(sfft_plan_t p, uint32_t count) {
     if (!p) return 0;
     const uint64_t s_in = p->d.in_dtype == SFFT_C128 ? 16 : 8;
     // exact mode: the first launch covers round group 0; general mode: every round
     const uint32_t R = p->group_end.empty() ? p->R : p->group_end[0];
     uint64_t per = 0;
-    for (uint32_t r = 0; r < R; ++r) per += (p->geom[r].w + 1) * s_in + 2ull * p->geom[r].B * 16ull;
+    for (uint32_t r = 0; r < R; ++r) per += refined_samples(p, r) * s_in + (uint64_t)p->nhash * p->geom[r].B * 16ull;
     return per * count;
 }
 
@@ -1143,6 +1197,7 @@ sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigm
     A.nrounds = 1;
     A.raw = p->p_raw;
     A.raw_rounds = 1;
+    A.gamma = 0;
     const int64_t iB = g.B, iw = (int64_t)g.w, ib = (int64_t)beta;
     uint64_t mc;
     if (beta < g.w) {
@@ -1166,6 +1221,7 @@ sfft_status_t sfft_hash_pair_raw(sfft_plan_t p, const void* x_dev, uint64_t sigm
 sfft_status_t sfft_execute(sfft_plan_t p, const void* x_dev, uint64_t* idx_host, double* val_host, uint32_t cap,
                            uint32_t* count_host, uint32_t* info_host, void* stream) {
     if (!p || !x_dev || !idx_host || !val_host || !count_host || cap < 1) return fail(SFFT_EINVAL, "bad argument");
+    if (p->d.refine_shift) return fail(SFFT_EUNSUPPORTED, "refine_shift needs the batched path (sfft_execute_batch)");
     std::lock_guard<std::mutex> lock(p->mu);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const uint64_t n = p->d.n;

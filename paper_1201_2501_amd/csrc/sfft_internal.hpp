@@ -101,6 +101,8 @@ struct H2BArgs {
     const uint32_t* state;     // [sig][kStateWords] or nullptr
     uint32_t threads;          // workgroup size of the pair launch: 256, 512, 1024 (0 = 256)
     uint32_t order;            // exact batched: workgroup order (plan hash_order)
+    uint32_t nhash;            // raw-bin slots per round: 2, or 3 with the refinement hashing
+    uint64_t gamma;            // exact batched: shift of the refinement hashing (0: none)
 };
 
 struct DecodeArgs {
@@ -117,7 +119,7 @@ struct DecodeArgs {
     const RoundDev* geom;
     const uint64_t* seeds;
     uint64_t plan_seed;
-    const double* raw;         // [sig][rounds][2][Bmax]
+    const double* raw;         // [sig][rounds][nhash][Bmax]
     double* work;              // [sig][2][Bmax] working bins
     uint64_t* cand_i;          // [sig][Bmax]
     double* cand_v;            // [sig][Bmax][2]
@@ -132,6 +134,9 @@ struct DecodeArgs {
     uint16_t* eord;            // [sig][rounds][capz] entries grouped by bin
     double* ecoef;             // [sig][rounds][capz][2] term coefficient G' of a shared entry
     uint32_t* state;           // [sig][kStateWords]
+    uint32_t nhash;            // raw-bin slots per round: 2, or 3 with the refinement hashing
+    uint32_t refine_window;    // half-width of the refinement's candidate window
+    uint64_t refine_shift;     // shift A of the refinement hashing (0: off)
     double theta, g_min;
     double ratio_tol;          // decode a bin only if its two squared magnitudes agree within this (0: off)
     double out_scale;
@@ -207,7 +212,7 @@ hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_t r_end, hipStream_t s);
 hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s);
 
-size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64, uint32_t threads);
+size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64, uint32_t threads, bool tri = false);
 bool h2b_threads_ok(uint32_t threads);
 size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax);
 

@@ -88,11 +88,17 @@ __device__ void lds_fft2(cx<TA>* VA, cx<TA>* VB, uint32_t B, uint32_t Bmax,
 // The modulation omega^{c t}, c = sigma b, is split as omega^{c r} (applied
 // per residue later) times M_L = omega^{c B L} (table in LDS).  Partial sums
 // are added into VA/VB[part * B + r].
-template <class TIn, class TA, uint32_t NT>
+//
+// TRI adds a third hashing at shift a + gamma (gamma > beta, beta < w), with
+// weight G_{t_A + gamma} into VC: for gamma < w + beta the samples t_A in
+// [t0 - gamma, t0 + w) feed all three; a larger gamma reads its own window
+// [t0 - gamma, t0 - gamma + w) beside the pair's [t0 - beta, t0 + w).
+template <class TIn, class TA, uint32_t NT, bool TRI = false>
 __device__ void accumulate_pair(const TIn* __restrict__ x, const TA* __restrict__ G, cx<TA>* VA,
                                 cx<TA>* VB, cx<TA>* M, uint64_t n, uint64_t sigma, uint64_t a,
                                 uint64_t beta, uint64_t b, uint32_t B, uint32_t logB, uint64_t w,
-                                int64_t t0, int64_t Lwin_lo, int64_t Lwin_hi, uint32_t parts) {
+                                int64_t t0, int64_t Lwin_lo, int64_t Lwin_hi, uint32_t parts,
+                                cx<TA>* VC = nullptr, uint64_t gamma = 0) {
     const uint32_t tid = threadIdx.x;
     const uint64_t mask = n - 1;
     const uint64_t c = (sigma * b) & mask;
@@ -101,9 +107,16 @@ __device__ void accumulate_pair(const TIn* __restrict__ x, const TA* __restrict_
     const int64_t iB = (int64_t)B;
     const int64_t iw = (int64_t)w;
     const int64_t ibeta = (int64_t)beta;
+    const int64_t igamma = (int64_t)gamma;
     int64_t lo[2], hi[2];
     int nseg;
-    if (beta < w) {
+    if (TRI) {
+        lo[0] = t0 - igamma;
+        hi[0] = igamma < iw + ibeta ? t0 + iw : lo[0] + iw;
+        lo[1] = t0 - ibeta;
+        hi[1] = t0 + iw;
+        nseg = igamma < iw + ibeta ? 1 : 2;
+    } else if (beta < w) {
         lo[0] = t0 - ibeta;
         hi[0] = t0 + iw;
         nseg = 1;
@@ -143,7 +156,7 @@ __device__ void accumulate_pair(const TIn* __restrict__ x, const TA* __restrict_
             if (L0 > L1) continue;
             int64_t tA = (int64_t)r + L0 * iB;
             uint64_t idx = ((uint64_t)(tA - (int64_t)a) * sigma) & mask;
-            TA aAr = 0, aAi = 0, aBr = 0, aBi = 0;
+            TA aAr = 0, aAi = 0, aBr = 0, aBi = 0, aCr = 0, aCi = 0;
             const cx<TA>* Mp = M + (L0 - Llo);
             const int64_t cnt = L1 - L0 + 1;
 #pragma unroll kGatherUnroll
@@ -163,11 +176,19 @@ __device__ void accumulate_pair(const TIn* __restrict__ x, const TA* __restrict_
                 aAi += gA * pi;
                 aBr += gB * pr;
                 aBi += gB * pi;
+                if (TRI) {
+                    const int64_t uC = uA + igamma;
+                    const bool inC = (uC >= 0) & (uC < iw);
+                    const TA gC = inC ? G[inC ? uC : 0] : (TA)0;
+                    aCr += gC * pr;
+                    aCi += gC * pi;
+                }
                 idx = (idx + sB) & mask;
                 tA += iB;
             }
             VA[slot] = cadd(VA[slot], cx<TA>{aAr, aAi});
             VB[slot] = cadd(VB[slot], cx<TA>{aBr, aBi});
+            if (TRI) VC[slot] = cadd(VC[slot], cx<TA>{aCr, aCi});
         }
     }
 }
@@ -194,6 +215,7 @@ __device__ void finalize_folds(cx<TA>* VA, cx<TA>* VB, uint64_t n, uint64_t sigm
 
 // After lds_fft2: bin j of A is VA[bitrev j]; hashing B was folded by the
 // residue of t_A, so its bin j carries the extra factor exp(-2 pi i j beta / B).
+// out0 == nullptr stores hashing B only.
 template <class TA, uint32_t NT>
 __device__ void store_bins(const cx<TA>* VA, const cx<TA>* VB, uint32_t B, uint32_t logB, uint32_t Bmax,
                            uint64_t beta, const typename TwTraits<TA>::V* tw, double sqrt_n,
@@ -206,8 +228,10 @@ __device__ void store_bins(const cx<TA>* VA, const cx<TA>* VB, uint32_t B, uint3
         const uint32_t e = (uint32_t)(((uint64_t)j * (beta & (B - 1))) & (B - 1));
         const auto t = tw[e * bstride];
         vb = cmul(vb, cx<TA>{t.x, t.y});
-        out0[2 * j] = (double)va.r * sqrt_n;
-        out0[2 * j + 1] = (double)va.i * sqrt_n;
+        if (out0) {
+            out0[2 * j] = (double)va.r * sqrt_n;
+            out0[2 * j + 1] = (double)va.i * sqrt_n;
+        }
         out1[2 * j] = (double)vb.r * sqrt_n;
         out1[2 * j + 1] = (double)vb.i * sqrt_n;
     }
@@ -231,7 +255,9 @@ __device__ __forceinline__ void pair_job(const H2BArgs& A, uint32_t j, uint32_t*
     }
 }
 
-template <class TIn, class TA, uint32_t NT>
+// TRI: the exact batched pair plus a third hashing at shift A.gamma (the
+// multi-shift phase refinement), stored in the round's third raw-bin slot.
+template <class TIn, class TA, uint32_t NT, bool TRI>
 __global__ void __launch_bounds__(NT) k_h2b_pair(H2BArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t sig, r, ro;
@@ -290,19 +316,30 @@ __global__ void __launch_bounds__(NT) k_h2b_pair(H2BArgs A) {
     const uint32_t parts = B >= NT ? 1u : NT / B;
     cx<TA>* VA = reinterpret_cast<cx<TA>*>(smem);
     cx<TA>* VB = VA + parts * B;
-    cx<TA>* M = VB + parts * B;
+    cx<TA>* VC = VB + parts * B;                  // TRI: the third hashing and a zero companion
+    cx<TA>* VD = VC + parts * B;
+    cx<TA>* M = TRI ? VD + parts * B : VC;
     for (uint32_t q = threadIdx.x; q < parts * B; q += NT) {
         VA[q] = cx<TA>{0, 0};
         VB[q] = cx<TA>{0, 0};
+        if (TRI) {
+            VC[q] = cx<TA>{0, 0};
+            VD[q] = cx<TA>{0, 0};
+        }
     }
-    accumulate_pair<TIn, TA, NT>(x, G, VA, VB, M, n, sigma, a, beta, b, B, g.logB, g.w, g.t0,
-                                 INT64_MIN / 4, INT64_MAX / 4, parts);
+    accumulate_pair<TIn, TA, NT, TRI>(x, G, VA, VB, M, n, sigma, a, beta, b, B, g.logB, g.w, g.t0,
+                                      INT64_MIN / 4, INT64_MAX / 4, parts, VC, A.gamma);
     __syncthreads();
     finalize_folds<TA, NT>(VA, VB, n, sigma, b, beta, B, parts);
+    if (TRI) finalize_folds<TA, NT>(VD, VC, n, sigma, b, A.gamma, B, parts);
     __syncthreads();
     lds_fft2<TA, NT>(VA, VB, B, A.Bmax, tw);
-    double* out0 = A.raw + (((uint64_t)sig * A.raw_rounds + ro) * 2) * (uint64_t)A.Bmax * 2;
+    if (TRI) lds_fft2<TA, NT>(VD, VC, B, A.Bmax, tw);
+    double* out0 = A.raw + (((uint64_t)sig * A.raw_rounds + ro) * A.nhash) * (uint64_t)A.Bmax * 2;
     store_bins<TA, NT>(VA, VB, B, g.logB, A.Bmax, beta, tw, A.sqrt_n, out0, out0 + 2 * (uint64_t)A.Bmax);
+    if (TRI)
+        store_bins<TA, NT>(VD, VC, B, g.logB, A.Bmax, A.gamma, tw, A.sqrt_n, nullptr,
+                           out0 + 4 * (uint64_t)A.Bmax);
 }
 
 // Plain path, stage 1: block p accumulates window chunk p (lchunk values of L)
@@ -371,7 +408,7 @@ __global__ void __launch_bounds__(kThreads) k_h2b_reduce(H2BArgs A, uint32_t rou
     finalize_folds<TA, kThreads>(VA, VB, A.n, A.sigma, A.b, A.beta, B, 1);
     __syncthreads();
     lds_fft2<TA, kThreads>(VA, VB, B, A.Bmax, tw);
-    double* out0 = A.raw + ((uint64_t)round * 2) * (uint64_t)A.Bmax * 2;
+    double* out0 = A.raw + ((uint64_t)round * A.nhash) * (uint64_t)A.Bmax * 2;
     store_bins<TA, kThreads>(VA, VB, B, g.logB, A.Bmax, A.beta, tw, A.sqrt_n, out0, out0 + 2 * (uint64_t)A.Bmax);
 }
 
@@ -555,25 +592,27 @@ __global__ void __launch_bounds__(kThreads) k_h2b_rsplit(H2BArgs A) {
     finalize_folds<TA, kThreads>(VA, VB, A.n, J.sigma, J.b, 1, B, 1);
     __syncthreads();
     lds_fft2<TA, kThreads>(VA, VB, B, A.Bmax, tw);
-    double* out0 = A.raw + (((uint64_t)J.sig * A.raw_rounds + J.r) * 2) * (uint64_t)A.Bmax * 2;
+    double* out0 = A.raw + (((uint64_t)J.sig * A.raw_rounds + J.r) * A.nhash) * (uint64_t)A.Bmax * 2;
     store_bins<TA, kThreads>(VA, VB, B, g.logB, A.Bmax, 1, tw, A.sqrt_n, out0, out0 + 2 * (uint64_t)A.Bmax);
 }
 
 // ------------------------------------------------------------------ launch --
 bool h2b_threads_ok(uint32_t threads) { return threads == 256 || threads == 512 || threads == 1024; }
 
-size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64, uint32_t threads) {
+size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64, uint32_t threads, bool tri) {
     const size_t csz = acc_f64 ? 16 : 8;
     const size_t slots = Bmax >= threads ? Bmax : threads;
-    return (2 * slots + max_mcount) * csz;
+    return ((tri ? 4 : 2) * slots + max_mcount) * csz;
 }
 
 template <class TIn, class TA, uint32_t NT>
 static hipError_t launch_pair_nt(const H2BArgs& a, uint32_t grid, hipStream_t s) {
-    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, sizeof(TA) == 8, NT);
-    hipError_t e = allow_lds(k_h2b_pair<TIn, TA, NT>, lds);
+    const bool tri = a.gamma != 0;
+    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, sizeof(TA) == 8, NT, tri);
+    hipError_t e = tri ? allow_lds(k_h2b_pair<TIn, TA, NT, true>, lds) : allow_lds(k_h2b_pair<TIn, TA, NT, false>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_h2b_pair<TIn, TA, NT>), dim3(grid), dim3(NT), lds, s, a);
+    if (tri) hipLaunchKernelGGL((k_h2b_pair<TIn, TA, NT, true>), dim3(grid), dim3(NT), lds, s, a);
+    else hipLaunchKernelGGL((k_h2b_pair<TIn, TA, NT, false>), dim3(grid), dim3(NT), lds, s, a);
     return hipGetLastError();
 }
 
@@ -606,7 +645,7 @@ hipError_t launch_h2b_pair(const H2BArgs& a, bool in_c128, bool acc_f64, hipStre
 }
 
 hipError_t launch_h2b_split(const H2BArgs& a, uint32_t round, bool in_c128, bool acc_f64, hipStream_t s) {
-    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, acc_f64, kThreads);
+    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, acc_f64, kThreads, false);
     if (in_c128) return acc_f64 ? launch_split_t<double2, double>(a, round, lds, s)
                                 : launch_split_t<double2, float>(a, round, lds, s);
     return acc_f64 ? launch_split_t<float2, double>(a, round, lds, s) : launch_split_t<float2, float>(a, round, lds, s);
@@ -623,7 +662,7 @@ static hipError_t launch_psplit_t(const H2BArgs& a, uint32_t jobs, size_t lds, h
 hipError_t launch_h2b_pair_split(const H2BArgs& a, bool in_c128, bool acc_f64, hipStream_t s) {
     const uint32_t jobs = a.count * a.nrounds;
     if (jobs == 0 || jobs > 65535 || a.parts < 2 || !a.partial) return hipErrorInvalidValue;
-    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, acc_f64, kThreads);
+    const size_t lds = h2b_pair_lds_bytes(a.Bmax, a.mcap, acc_f64, kThreads, false);
     hipError_t e = in_c128 ? (acc_f64 ? launch_psplit_t<double2, double>(a, jobs, lds, s)
                                       : launch_psplit_t<double2, float>(a, jobs, lds, s))
                            : (acc_f64 ? launch_psplit_t<float2, double>(a, jobs, lds, s)

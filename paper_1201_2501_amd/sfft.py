@@ -35,7 +35,7 @@ INFO_ROUNDS, INFO_FLAGS, INFO_ZHAT, INFO_LOCATED = range(4)
 EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_plan_ex", "sfft_plan",
            "sfft_plan_get_desc", "sfft_destroy", "sfft_execute", "sfft_execute_batch",
            "sfft_hash_pair_raw", "sfft_plan_timings", "sfft_plan_h2b_bytes", "sfft_plan_round_groups",
-           "sfft_plan_raw_slot", "sfft_plan_device_bytes", "sfft_plan_samples", "sfft_plan_stream_rounds",
+           "sfft_plan_raw_slot", "sfft_plan_raw_refine", "sfft_plan_desc_bytes", "sfft_plan_device_bytes", "sfft_plan_samples", "sfft_plan_stream_rounds",
            "sfft_status_string",
            "sfft_last_error", "sfft_splitmix64",
            "sfft_dense_topk_scratch_bytes", "sfft_dense_topk", "sfft_dense_topk_noalloc_max_count",
@@ -55,7 +55,8 @@ class PlanDesc(ctypes.Structure):
                 ("chunks", c_uint32), ("stop_count", c_uint32),
                 ("stop_patience", c_uint32), ("group0", c_uint32), ("ratio_tol", c_double),
                 ("group_step", c_uint32), ("hash_order", c_uint32), ("alpha_decay", c_double),
-                ("hash_split", c_uint32), ("hash_mode", c_uint32)]
+                ("hash_split", c_uint32), ("hash_mode", c_uint32), ("refine_shift", c_uint64),
+                ("refine_window", c_uint32), ("reserved", c_uint32)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -112,6 +113,9 @@ def load():
     lib.sfft_plan_h2b_bytes.restype = c_uint64
     lib.sfft_plan_round_groups.argtypes = [P, POINTER(c_uint32), c_uint32, POINTER(c_uint32)]
     lib.sfft_plan_raw_slot.argtypes = [P, c_uint32, c_uint32, P, P, P]
+    lib.sfft_plan_raw_refine.argtypes = [P, c_uint32, c_uint32, P, P, P]
+    lib.sfft_plan_desc_bytes.argtypes = []
+    lib.sfft_plan_desc_bytes.restype = c_uint32
     lib.sfft_status_string.argtypes = [c_int32]
     lib.sfft_status_string.restype = c_char_p
     lib.sfft_last_error.argtypes = []
@@ -143,8 +147,11 @@ def load():
     for name in EXPORTS:
         if name not in ("sfft_default_w", "sfft_status_string", "sfft_last_error", "sfft_splitmix64",
                         "sfft_plan_h2b_bytes", "sfft_plan_device_bytes", "sfft_dense_topk_noalloc_max_count",
-                        "sfft_plan_samples", "sfft_plan_stream_rounds"):
+                        "sfft_plan_samples", "sfft_plan_stream_rounds", "sfft_plan_desc_bytes"):
             getattr(lib, name).restype = c_int32
+    if lib.sfft_plan_desc_bytes() != ctypes.sizeof(PlanDesc):
+        raise RuntimeError("PlanDesc has %d bytes, the library's sfft_plan_desc_t %d"
+                           % (ctypes.sizeof(PlanDesc), lib.sfft_plan_desc_bytes()))
     _lib = lib
     return lib
 
@@ -230,6 +237,15 @@ def sfft_plan_raw_slot(plan, sig, slot, out, stream=None):
     br = np.zeros(1, dtype=np.uint32)
     _check(load().sfft_plan_raw_slot(plan, sig, slot, c_void_p(out.data_ptr()), br.ctypes.data_as(c_void_p),
                                      _stream_handle(stream)), "sfft_plan_raw_slot")
+    return int(br[0])
+
+
+def sfft_plan_raw_refine(plan, sig, rnd, out, stream=None):
+    """Copy the refinement hashing's raw bins of (signal, round) into out
+    (device complex128 [B_r]); returns B_r."""
+    br = np.zeros(1, dtype=np.uint32)
+    _check(load().sfft_plan_raw_refine(plan, sig, rnd, c_void_p(out.data_ptr()), br.ctypes.data_as(c_void_p),
+                                       _stream_handle(stream)), "sfft_plan_raw_refine")
     return int(br[0])
 
 
@@ -347,6 +363,15 @@ class Plan:
         torch.cuda.synchronize()
         o = out.cpu().numpy()
         return o[:br], o[br:2 * br]
+
+    def raw_refine(self, sig, rnd, device):
+        """Raw bins of the refinement hashing of (signal, round) (numpy complex128)."""
+        import torch
+
+        out = torch.zeros(self.desc.B, dtype=torch.complex128, device=device)
+        br = sfft_plan_raw_refine(self.handle, sig, rnd, out)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()[:br]
 
     def timings(self):
         return sfft_plan_timings(self.handle)

@@ -134,3 +134,47 @@ def test_hash_split_validation():
     assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
     d.mode, d.hash_mode = sfft.SFFT_MODE_EXACT, 3
     assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
+
+
+def test_plan_desc_layout_matches_the_library():
+    assert sfft.load().sfft_plan_desc_bytes() == __import__("ctypes").sizeof(sfft.PlanDesc)
+
+
+def test_refine_validation():
+    d = sfft.sfft_desc_init(1 << 22, 256, 1024)
+    d.refine_shift = 2048
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK              # E = 16 by default
+    d.refine_window = 1000
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK              # 2048 * 2001 < 2^22
+    d.refine_window = 1024
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL          # 2048 * 2049 >= 2^22
+    d.refine_shift = 16
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK
+    d.refine_window = 1025
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL          # E at most 1024
+    d.refine_window, d.refine_shift = 64, (1 << 22) // 129
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK              # A (2E + 1) = n - 127
+    d.refine_shift += 1
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL          # A (2E + 1) >= n
+    d.refine_shift = 1
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
+    d.refine_shift = 2048
+    for field, value in (("hash_split", 4), ("hash_mode", 1), ("mode", sfft.SFFT_MODE_GENERAL)):
+        setattr(d, field, value)
+        assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL, field
+        setattr(d, field, 0)
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK
+
+
+def test_refine_adds_its_samples():
+    """The refinement hashing reads A more samples per round for A < w_r + 1
+    (one window [t0 - A, t0 + w_r)), else another w_r."""
+    d = sfft.sfft_desc_init(1 << 22, 256, 1024, 0, 7)
+    d.b_min, d.rounds, d.group0 = 1024, 4, 4                         # four rounds of w
+    base = sfft.sfft_plan_samples(d)
+    w = sfft.sfft_default_w(1 << 22, 1024, 0.5, d.delta)
+    assert base == 4 * (w + 1)
+    d.refine_shift = 1000
+    assert sfft.sfft_plan_samples(d) == 4 * (w + 1000)
+    d.refine_shift, d.refine_window = w + 5, 2
+    assert sfft.sfft_plan_samples(d) == 4 * (2 * w + 1)

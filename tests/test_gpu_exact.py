@@ -39,7 +39,8 @@ def oracle_params(plan, seed=None):
     return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=d.seed if seed is None else seed, alpha=d.alpha,
                       delta=d.delta, theta=d.theta, g_min=d.g_min, rounds=d.rounds, b_min=d.b_min,
                       patience=d.patience, stop_count=d.stop_count, stop_patience=d.stop_patience,
-                      ratio_tol=d.ratio_tol, alpha_decay=d.alpha_decay, cap=d.cap)
+                      ratio_tol=d.ratio_tol, alpha_decay=d.alpha_decay, cap=d.cap, refine_shift=d.refine_shift,
+                      refine_window=d.refine_window or 16)
 
 
 RAW_CASES = [
@@ -595,4 +596,82 @@ def test_stream_mode_recovery_matches_oracle(torch_dev, n, k, B, mode):
         assert int(out[s][2][0]) == ref.rounds_used
         compare(out[s][0], out[s][1], ref)
         assert np.array_equal(out[s][0], sups[s])
+    plan.close()
+
+
+@pytest.mark.parametrize("n,k,B,A,prec", [(1 << 18, 100, 512, 300, 1), (1 << 18, 100, 512, 50001, 1),
+                                          (1 << 18, 100, 512, 300, 0), (1 << 22, 256, 1024, 2048, 0)])
+def test_refine_raw_bins_match_oracle(torch_dev, n, k, B, A, prec):
+    """The pair launch with the refinement hashing: the third hashing (shift
+    A) of every round of group 0 matches the oracle's HashToBins at shift A,
+    and the pair's own bins still match theirs (FP64 within 1e-12 of the
+    largest bin, FP32 within 2e-5); A within the windows (one window feeds
+    all three hashings) and beyond them (the third reads its own)."""
+    from oracle.rng import draw_b, draw_sigma
+    torch, dev = torch_dev
+    delta = 1e-9
+    w = default_w(n, B, 0.5, delta)
+    count = 2
+    plan = plan_for(n, k, B, w, 0, delta=delta, loc_prec=prec, max_batch=count, rounds=12, group0=6,
+                    refine_shift=A, refine_window=2)
+    say("refine-raw", "n", n, "B", B, "w", w, "A", A, "prec", prec)
+    xs = [siggen.planted_signal(n, k, 890 + s, np.complex64, noise_ratio=0.01)[0] for s in range(count)]
+    seeds = [43, 1001]
+    X = torch.from_numpy(np.stack(xs)).to(dev)
+    plan.execute_batch(X, torch.tensor(seeds, dtype=torch.int64, device=dev))
+    torch.cuda.synchronize()
+    p = oracle_params(plan)
+    tol = 1e-12 if prec == 1 else 2e-5
+    for s in range(count):
+        for r in range(6):
+            Br, wr = p.round_bins(r)
+            G = window_time(n, Br, wr, p.round_alpha(r), delta)
+            sigma, b = draw_sigma(seeds[s], n, r), draw_b(seeds[s], n, r)
+            e = [hash_to_bins_raw(xs[s], sigma, a, b, Br, G) for a in (0, 1, A)]
+            g0, g1 = plan.raw_slot(s, r, dev)
+            gA = plan.raw_refine(s, r, dev)
+            sc = max(np.abs(v).max() for v in e)
+            for got, exp in zip((g0, g1, gA), e):
+                assert np.abs(got - exp).max() <= tol * sc, (s, r)
+    plan.close()
+
+
+@pytest.mark.parametrize("n,k,B,A,E,prec", [(1 << 18, 100, 512, 300, 16, 1), (1 << 18, 100, 512, 50001, 2, 1),
+                                            (1 << 22, 256, 1024, 2048, 1000, 0)])
+def test_refine_recovery_matches_oracle(torch_dev, n, k, B, A, E, prec):
+    """The batched exact path with the multi-shift refinement: supports
+    bit-exact against the oracle (which refines the same way in FP64) and
+    the planted ones.  FP64 bins: rounds decoded equal and values within
+    1e-10 relative.  FP32 bins (n = 2^22, where the FP32 pair alone locates
+    nothing): values within 2e-5 of the largest magnitude, the FP32 rounding
+    of the bins; the rounds decoded may differ, since bin noise of a few
+    1e-7 of the largest bin changes which collided bins pass the checks in
+    a round (the oracle with such noise added to its bins does the same)."""
+    torch, dev = torch_dev
+    delta = 1e-9
+    w = default_w(n, B, 0.5, delta)
+    count = 2
+    mag = "loguniform" if n == 1 << 22 else "unit"
+    plan = plan_for(n, k, B, w, 0, delta=delta, theta=0.02 if mag == "loguniform" else 0.25, loc_prec=prec,
+                    max_batch=count, b_min=32, rounds=24, refine_shift=A, refine_window=E)
+    say("refine-recovery", "n", n, "k", k, "B", B, "A", A, "E", E, "prec", prec)
+    xs, sups, seeds = [], [], []
+    for s in range(count):
+        x, sup, _ = siggen.planted_signal(n, k, 900 + s, np.complex64, magnitude=mag)
+        xs.append(x)
+        sups.append(sup)
+        seeds.append(7 * s + 5)
+    out = run_batch(torch, dev, plan, xs, seeds)
+    for s in range(count):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        print("refine-recovery rounds", int(out[s][2][0]), "oracle", ref.rounds_used, flush=True)
+        assert prec == 0 or int(out[s][2][0]) == ref.rounds_used
+        assert np.array_equal(out[s][0], ref.indices)
+        assert np.array_equal(out[s][0], sups[s])
+        if prec == 1:
+            compare(out[s][0], out[s][1], ref)
+        else:
+            err = np.abs(out[s][1] - ref.values).max()
+            print("refine-recovery FP32 value error", err, "of", np.abs(ref.values).max(), flush=True)
+            assert err <= 2e-5 * np.abs(ref.values).max()
     plan.close()
