@@ -1322,10 +1322,15 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
             gc.o4 = info_dev;
         }
     }
-    // fork: the auxiliary stream follows everything already queued on s
+    // fork: the auxiliary stream follows everything already queued on s.  A
+    // single chunk has nothing to overlap: its decode follows on s itself
+    // (a cross-stream wait costs tens of microseconds per step)
+    hipStream_t ds = C > 1 ? p->aux_stream : s;
     if (timing) HIP_TRY(hipEventRecord(p->ev_t0, s));
-    HIP_TRY(hipEventRecord(p->ev_fork, s));
-    HIP_TRY(hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0));
+    if (C > 1) {
+        HIP_TRY(hipEventRecord(p->ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(p->aux_stream, p->ev_fork, 0));
+    }
     for (uint32_t c = 0; c < C; ++c) {
         const uint32_t off = c * per, cnt = std::min(per, count - off);
         if (timing) HIP_TRY(hipEventRecord(p->ev_h0[c], s));
@@ -1335,20 +1340,23 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
             ST_TRY(enqueue_chunk(p, 0, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev, s));
         }
         if (timing) HIP_TRY(hipEventRecord(p->ev_h1[c], s));
-        HIP_TRY(hipEventRecord(p->ev_ready[c], s));
-        HIP_TRY(hipStreamWaitEvent(p->aux_stream, p->ev_ready[c], 0));
-        if (timing) HIP_TRY(hipEventRecord(p->ev_d0[c], p->aux_stream));
-        if (use_graph) {
-            HIP_TRY(hipGraphLaunch(gc.exec_d[c], p->aux_stream));
-        } else {
-            ST_TRY(enqueue_chunk(p, 1, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
-                                 p->aux_stream));
+        if (C > 1) {
+            HIP_TRY(hipEventRecord(p->ev_ready[c], s));
+            HIP_TRY(hipStreamWaitEvent(p->aux_stream, p->ev_ready[c], 0));
         }
-        if (timing) HIP_TRY(hipEventRecord(p->ev_d1[c], p->aux_stream));
+        if (timing) HIP_TRY(hipEventRecord(p->ev_d0[c], ds));
+        if (use_graph) {
+            HIP_TRY(hipGraphLaunch(gc.exec_d[c], ds));
+        } else {
+            ST_TRY(enqueue_chunk(p, 1, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev, ds));
+        }
+        if (timing) HIP_TRY(hipEventRecord(p->ev_d1[c], ds));
     }
     // join: s waits for the last decode
-    HIP_TRY(hipEventRecord(p->ev_join, p->aux_stream));
-    HIP_TRY(hipStreamWaitEvent(s, p->ev_join, 0));
+    if (C > 1) {
+        HIP_TRY(hipEventRecord(p->ev_join, p->aux_stream));
+        HIP_TRY(hipStreamWaitEvent(s, p->ev_join, 0));
+    }
     if (timing) {
         HIP_TRY(hipEventRecord(p->ev_t1, s));
         p->timed_chunks = C;
