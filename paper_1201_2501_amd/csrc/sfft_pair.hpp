@@ -1,7 +1,6 @@
-// Device building blocks of the HashToBins pair (permuted gather, window x
-// modulation, fold into B residues, B-point FFT in LDS, scaled store), shared
-// by the pair kernels and by the exact decoder's in-loop hashing of later
-// rounds.
+// Device building blocks of the HashToBins pair kernels (permuted gather,
+// window x modulation, fold into B residues, B-point FFT in LDS, scaled
+// store).
 #pragma once
 #include "sfft_device.hpp"
 
