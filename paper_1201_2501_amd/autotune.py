@@ -54,7 +54,7 @@ import numpy as np
 from . import sfft
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-_SOURCES = ("sfft_kernels.hip", "sfft_decode.hip", "sfft_host.cpp", "sfft_common.hpp", "sfft_internal.hpp",
+_SOURCES = ("sfft_kernels.hip", "sfft_pair.hpp", "sfft_decode.hip", "sfft_host.cpp", "sfft_common.hpp", "sfft_internal.hpp",
             "sfft_device.hpp")
 
 

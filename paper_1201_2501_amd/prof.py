@@ -34,7 +34,8 @@ import sys
 from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(PKG, "csrc", f) for f in ("sfft_kernels.hip", "sfft_common.hpp", "sfft_internal.hpp")]
+KERNEL_SOURCES = [os.path.join(PKG, "csrc", f) for f in ("sfft_kernels.hip", "sfft_pair.hpp", "sfft_common.hpp",
+                                                          "sfft_internal.hpp")]
 COPY_BYTES = 1 << 30
 
 
