@@ -586,6 +586,9 @@ def main():
     ap.add_argument("--loc-prec", choices=["f32", "f64"], default=None,
                     help="arithmetic of the location pair's fold and FFT, over the chosen plan's (default FP64: "
                          "the phase step 2 pi / n at n = 2^22 is near FP32 resolution)")
+    ap.add_argument("--hash-split", type=int, default=None,
+                    help="exact mode: workgroups per (signal, round) of the HashToBins pair launches (over the "
+                         "chosen plan's)")
     ap.add_argument("--refine-shift", type=int, default=0,
                     help="exact mode: shift A of the multi-shift phase refinement (a third hashing per round; "
                          "0: off)")
@@ -704,6 +707,8 @@ def main():
         plan_kw["hash_order"] = args.hash_order
     if args.loc_prec is not None:
         plan_kw["loc_prec"] = loc_prec
+    if args.hash_split is not None:
+        plan_kw["hash_split"] = args.hash_split
     if args.refine_shift:
         plan_kw.update(refine_shift=args.refine_shift, refine_window=args.refine_window)
     log("plan: B=%d w=%d %s" % (B, w, ", ".join("%s=%s" % kv for kv in sorted(tuned.items()))))
@@ -719,6 +724,8 @@ def main():
         cfg_key += ",order=%d" % desc.hash_order
     if desc.refine_shift:
         cfg_key += ",refine=%d" % desc.refine_shift
+    if desc.hash_split > 1:
+        cfg_key += ",split=%d" % desc.hash_split
     if desc.loc_prec == sfft.SFFT_F32:
         cfg_key += ",f32"
     if args.config_key:
@@ -944,7 +951,8 @@ def main():
                    "alpha": desc.alpha, "theta": desc.theta, "g_min": desc.g_min,
                    "stop_count": desc.stop_count, "stop_patience": desc.stop_patience, "ratio_tol": desc.ratio_tol,
                    "alpha_decay": desc.alpha_decay, "samples_per_signal_group0": sfft.sfft_plan_samples(desc),
-                   "hash_threads": desc.hash_threads, "hash_order": desc.hash_order, "chunks": chunks,
+                   "hash_threads": desc.hash_threads, "hash_order": desc.hash_order,
+                   "hash_split": desc.hash_split, "chunks": chunks,
                    "loc_prec": "f64" if desc.loc_prec == sfft.SFFT_F64 else "f32",
                    "refine_shift": desc.refine_shift, "refine_window": desc.refine_window,
                    "input": "complex64"},
