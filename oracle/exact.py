@@ -104,7 +104,7 @@ def refine_position(p0, phase_a, A, n, E, margins: Margins):
     return best % n
 
 
-def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Margins, alpha=None, uAj=None):
+def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Margins, alpha=None, uAj=None, w=0):
     """Location and value of bin j of a B-bin hashing; returns (i, v) or None.
     With ratio_tol > 0 a bin whose two hashings differ in magnitude by more
     than that fraction is not decoded: an isolated coefficient gives
@@ -138,7 +138,7 @@ def decode_bin(u0j, u1j, j, sigma, sigma_inv, b, B, p: SfftParams, margins: Marg
     h, o = bin_offset(i, sigma, b, n, B)
     if h != j:
         return None
-    g = gprime(-o, n, B, p.alpha if alpha is None else alpha, p.delta)
+    g = gprime(-o, n, B, p.alpha if alpha is None else alpha, p.delta, p.window, w)
     margins.gmin = min(margins.gmin, abs(g - p.g_min))
     if g < p.g_min:
         return None
@@ -159,17 +159,17 @@ def noiseless_sparse_fft(x, p: SfftParams) -> ExactResult:
         sigma_inv = inverse_mod(sigma, n)
         Br, wr = p.round_bins(r)
         ar = p.round_alpha(r)
-        G = window_time(n, Br, wr, ar, p.delta)
+        G = window_time(n, Br, wr, ar, p.delta, p.window)
         u0_raw = hash_to_bins_raw(x, sigma, 0, b, Br, G)
         u1_raw = hash_to_bins_raw(x, sigma, 1, b, Br, G)
         res.raw.append((sigma, b, u0_raw, u1_raw))
-        u0 = subtract_zhat(u0_raw, zhat, sigma, 0, b, Br, n, ar, p.delta)
-        u1 = subtract_zhat(u1_raw, zhat, sigma, 1, b, Br, n, ar, p.delta)
+        u0 = subtract_zhat(u0_raw, zhat, sigma, 0, b, Br, n, ar, p.delta, p.window, wr)
+        u1 = subtract_zhat(u1_raw, zhat, sigma, 1, b, Br, n, ar, p.delta, p.window, wr)
         uA = None
         if p.refine_shift:
             uA_raw = hash_to_bins_raw(x, sigma, p.refine_shift, b, Br, G)
             res.raw_refine.append(uA_raw)
-            uA = subtract_zhat(uA_raw, zhat, sigma, p.refine_shift, b, Br, n, ar, p.delta)
+            uA = subtract_zhat(uA_raw, zhat, sigma, p.refine_shift, b, Br, n, ar, p.delta, p.window, wr)
         mag = np.abs(u0)
         res.margins.threshold = min(res.margins.threshold, float(np.min(np.abs(mag - p.theta))))
         J = [j for j in range(Br) if mag[j] > p.theta]
@@ -187,7 +187,7 @@ def noiseless_sparse_fft(x, p: SfftParams) -> ExactResult:
         best = {}
         for j in J:
             got = decode_bin(u0[j], u1[j], j, sigma, sigma_inv, b, Br, p, res.margins, ar,
-                             None if uA is None else uA[j])
+                             None if uA is None else uA[j], wr)
             if got is None:
                 continue
             i, v = got
@@ -214,12 +214,12 @@ def reestimate(zhat, raw, p: SfftParams):
     n = p.n
     meas = []
     for r, (sigma, b, u0_raw, _u1) in enumerate(raw):
-        B = len(u0_raw)
+        B, wr = p.round_bins(r)
         ar = p.round_alpha(r)
         terms = {}
         for i in zhat:
             h, o = bin_offset(i, sigma, b, n, B)
-            g = gprime(-o, n, B, ar, p.delta)
+            g = gprime(-o, n, B, ar, p.delta, p.window, wr)
             terms[i] = (h, g, g)
         meas.append((u0_raw, terms))
     return peel_reestimate(zhat, meas, p.g_min)

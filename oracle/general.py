@@ -159,7 +159,7 @@ def locate_signal(x, zhat, r, B, G, p: SfftParams, res: GeneralResult):
 def hash_to_bins(x, zhat, sigma, a, b, B, G, p):
     n = p.n
     raw = hash_to_bins_raw(x, sigma, a % n, b, B, G)
-    return subtract_zhat(raw, zhat, sigma, a % n, b, B, n, p.alpha, p.delta)
+    return subtract_zhat(raw, zhat, sigma, a % n, b, B, n, p.alpha, p.delta, p.window, len(G))
 
 
 def estimate_values(x, zhat, r, kprime, L, B, G, p: SfftParams, res: GeneralResult):
@@ -171,13 +171,13 @@ def estimate_values(x, zhat, r, kprime, L, B, G, p: SfftParams, res: GeneralResu
         b = draw_b(p.seed, n, r, LEVEL_EST, e)
         raw = hash_to_bins_raw(x, sigma, a, b, B, G)
         res.est_raw.append((sigma, a, b, B, raw))
-        meas.append((sigma, a, b, subtract_zhat(raw, zhat, sigma, a, b, B, n, p.alpha, p.delta)))
+        meas.append((sigma, a, b, subtract_zhat(raw, zhat, sigma, a, b, B, n, p.alpha, p.delta, p.window, len(G))))
     w = {}
     for i in L:
         vals = []
         for sigma, a, b, u in meas:
             h, o = bin_offset(i, sigma, b, n, B)
-            g = gprime(-o, n, B, p.alpha, p.delta)
+            g = gprime(-o, n, B, p.alpha, p.delta, p.window, len(G))
             if g < p.g_min:
                 continue
             vals.append(u[h] * omega_pow(-(a * sigma * i), n) / g)
@@ -199,7 +199,7 @@ def reestimate_general(zhat, est_raw, p: SfftParams):
         terms = {}
         for i in zhat:
             h, o = bin_offset(i, sigma, b, n, B)
-            g = gprime(-o, n, B, p.alpha, p.delta)
+            g = gprime(-o, n, B, p.alpha, p.delta, p.window, p.w // p.B * B)
             terms[i] = (h, g, g * omega_pow(a * sigma * i, n))
         meas.append((raw, terms))
     return peel_reestimate(zhat, meas, p.g_min)
@@ -213,7 +213,7 @@ def sparse_fft(x, p: SfftParams) -> GeneralResult:
     zhat = {}
     for r in range(p.rounds):
         k_r, B_r, w_r = round_schedule(p, r)
-        G = window_time(n, B_r, w_r, p.alpha, p.delta)
+        G = window_time(n, B_r, w_r, p.alpha, p.delta, p.window)
         L = locate_signal(x, zhat, r, B_r, G, p, res)
         res.located.append(L)
         upd = estimate_values(x, zhat, r, 3 * k_r, L, B_r, G, p, res)

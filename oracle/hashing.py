@@ -63,23 +63,25 @@ def hash_to_bins_raw(x, sigma, a, b, B, G):
     return np.sqrt(n) * fft_radix2(v)
 
 
-def zhat_contribution(i, zi, sigma, a, b, B, n, alpha, delta):
-    """(h(i), G'_{-o(i)} zhat_i omega^{a sigma i}) for one entry of zhat (step 4)."""
+def zhat_contribution(i, zi, sigma, a, b, B, n, alpha, delta, kind=0, w=0):
+    """(h(i), G'_{-o(i)} zhat_i omega^{a sigma i}) for one entry of zhat (step 4);
+    kind, w select the flat window (window.gprime)."""
     h, o = bin_offset(i, sigma, b, n, B)
-    g = gprime(-o, n, B, alpha, delta)
+    g = gprime(-o, n, B, alpha, delta, kind, w)
     return h, g * zi * omega_pow(int(a) * int(sigma) * int(i), n)
 
 
-def subtract_zhat(u, zhat, sigma, a, b, B, n, alpha, delta):
+def subtract_zhat(u, zhat, sigma, a, b, B, n, alpha, delta, kind=0, w=0):
     """Step 4 of HashToBins, entries of zhat taken in ascending index order."""
     u = np.array(u, dtype=np.complex128)
     for i in sorted(zhat):
-        h, c = zhat_contribution(i, zhat[i], sigma, a, b, B, n, alpha, delta)
+        h, c = zhat_contribution(i, zhat[i], sigma, a, b, B, n, alpha, delta, kind, w)
         u[h] -= c
     return u
 
 
-def hash_to_bins(x, zhat, sigma, a, b, B, G, alpha, delta):
+def hash_to_bins(x, zhat, sigma, a, b, B, G, alpha, delta, kind=0):
     """Full HashToBins(x, zhat, P_{sigma,a,b}, B, delta, alpha)."""
     n = np.asarray(x).shape[-1]
-    return subtract_zhat(hash_to_bins_raw(x, sigma, a, b, B, G), zhat, sigma, a, b, B, n, alpha, delta)
+    return subtract_zhat(hash_to_bins_raw(x, sigma, a, b, B, G), zhat, sigma, a, b, B, n, alpha, delta, kind,
+                         len(G))

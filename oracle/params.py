@@ -53,6 +53,9 @@ refine_shift  exact mode: 0 (off) or a third hashing per round at shift a = A
           position p0, and the candidate c in [p0 - E, p0 + E] whose angle
           2 pi (A c mod n) / n is nearest the phase of u / u_A is taken
 refine_window  E, the half-width of that candidate window
+window    0: the Gaussian flat window of the Section 7 lemma; 1: the
+          Kaiser-Bessel flat window (window.py kind 1), the same definition
+          with about half the support
 cap       largest output size (defaults to k)
 literal   exact mode only: the paper-literal decode v = round(u_j) for integer
           spectra, without the bin and window checks
@@ -85,6 +88,7 @@ class SfftParams:
     R_est: int = 7
     refine_shift: int = 0
     refine_window: int = 16
+    window: int = 0
     cap: int = 0
     literal: bool = False
 
