@@ -186,6 +186,14 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *             2 <= A < n, A (2E + 1) < n, hash_split <= 1 and hash_mode 0
  *   refine_window  E, the half-width of the refinement's candidate window
  *             (1..1024; default 16 when refine_shift is set)
+ *   window    the flat window (G, G') of the Section 2 definition: 0 the
+ *             Gaussian construction of the Section 7 lemma; 1 the ideal
+ *             low-pass with cut-off C = (1 - alpha/2)/(2B) tapered by a
+ *             Kaiser-Bessel window I0(beta sqrt(1 - (2t/w)^2)) / I0(beta),
+ *             beta and the default w from Kaiser's rules for a ripple of
+ *             delta/2 over the transition band (about half the Gaussian's
+ *             support at the same alpha and delta), G' in the transition
+ *             band the window's own response (tabulated at plan time)
  */
 typedef struct {
     uint64_t n;
@@ -224,7 +232,7 @@ typedef struct {
     uint32_t hash_mode;
     uint64_t refine_shift;
     uint32_t refine_window;
-    uint32_t reserved;
+    uint32_t window;
 } sfft_plan_desc_t;
 
 typedef struct sfft_plan_s* sfft_plan_t;
@@ -262,6 +270,12 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d);
 /* Default window length for (n, B, alpha, delta), as described for w above;
  * returns n when no shorter window meets delta.  Pure host function. */
 uint64_t sfft_default_w(uint64_t n, uint32_t B, double alpha, double delta);
+
+/* The same for the flat window `window` (0 Gaussian, as sfft_default_w; 1
+ * Kaiser-Bessel: Kaiser's length rule (A - 7.95) / (14.36 alpha / (2B)) + 1
+ * with A = -20 log10(delta / 2), rounded up to a multiple of B, at most n);
+ * 0 for an unknown window.  Pure host function. */
+uint64_t sfft_window_w(uint64_t n, uint32_t B, double alpha, double delta, uint32_t window);
 
 /* Create a plan: validates, builds the FP64 window tables G (Section 7
  * construction) and FFT twiddles on the host, copies them to the current

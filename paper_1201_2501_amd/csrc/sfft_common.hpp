@@ -89,12 +89,18 @@ struct WindowShape {
     double C;
     double alpha;
     uint32_t two_term;
+    uint32_t pad;
+    // Kaiser-Bessel window (plan field window = 1): G'_|f| for |f| <= n/(2B)
+    // (device table, the window's response computed at plan time); nullptr
+    // for the Gaussian window, whose G' has the closed form below
+    const double* ftab;
 };
 
 SFFT_HD double gprime(int64_t f, uint64_t n, uint64_t B, WindowShape ws) {
     const uint64_t af = (uint64_t)(f < 0 ? -f : f);
     if ((double)(af * 2 * B) <= (1.0 - ws.alpha) * (double)n) return 1.0;
     if (af * 2 * B >= n) return 0.0;
+    if (ws.ftab) return ws.ftab[af];
     const double s = (double)af / (double)n;
     const double r2 = 1.4142135623730951;
     const double lead = erfc(ws.sigma_g * (s - ws.C) / r2);

@@ -51,7 +51,7 @@ uint32_t log2u(uint64_t v) {
 // directly, which keeps ||Ghat - G'||_inf < delta with a shorter window.
 WindowShape window_shape(uint64_t n, uint64_t B, double alpha, double delta) {
     (void)n;
-    WindowShape ws;
+    WindowShape ws{};   // ftab = nullptr: the closed-form G' of the Gaussian window
     ws.sigma_g = (4.0 * (double)B / alpha) * std::sqrt(2.0 * std::log(3.0 / delta));
     ws.C = (1.0 - alpha / 2.0) / (2.0 * (double)B);
     ws.alpha = alpha;
@@ -88,6 +88,46 @@ uint64_t default_w(uint64_t n, uint64_t B, double alpha, double delta) {
         if (tail_mass(mid * B / 2, ws) <= delta) hi = mid; else lo = mid + 1;
     }
     return lo * B;
+}
+
+// Kaiser-Bessel flat window (plan field window = 1): the ideal low-pass
+// sin(2 pi C t)/(pi t) (the Gaussian construction's C) tapered by
+// I0(beta sqrt(1 - (2t/w)^2)) / I0(beta), with Kaiser's empirical rules for
+// a ripple of delta/2 over the transition band alpha/(2B) cycles per sample:
+// A = -20 log10(delta/2), beta = 0.1102 (A - 8.7) for A > 50, length
+// (A - 7.95) / (14.36 alpha / (2B)) + 1 rounded up to a multiple of B.
+double kaiser_beta(double delta) {
+    const double A = -20.0 * std::log10(delta / 2.0);
+    if (A > 50.0) return 0.1102 * (A - 8.7);
+    if (A >= 21.0) return 0.5842 * std::pow(A - 21.0, 0.4) + 0.07886 * (A - 21.0);
+    return 0.0;
+}
+
+uint64_t kaiser_w(uint64_t n, uint64_t B, double alpha, double delta) {
+    const double A = -20.0 * std::log10(delta / 2.0);
+    const double N = (A - 7.95) / (14.36 * alpha / (2.0 * (double)B)) + 1.0;
+    const uint64_t m = (uint64_t)std::ceil(N / (double)B);
+    return std::min<uint64_t>(n, m * B);
+}
+
+// I0 by its power series sum (x/2)^2k / (k!)^2.
+double bessel_i0(double x) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, total = 1.0;
+    for (int k = 1; k < 200; ++k) {
+        term *= q / ((double)k * (double)k);
+        total += term;
+        if (term <= 1e-17 * total) break;
+    }
+    return total;
+}
+
+// G_t of the Kaiser window of length w (t in [-w/2, w/2)).
+double kaiser_g(double t, uint64_t w, double C, double beta, double i0_beta) {
+    const double pi = 3.14159265358979323846;
+    const double box = t == 0.0 ? 2.0 * C : std::sin(2.0 * pi * C * t) / (pi * t);
+    const double r = 2.0 * t / (double)w;
+    return box * bessel_i0(beta * std::sqrt(std::max(1.0 - r * r, 0.0))) / i0_beta;
 }
 
 uint32_t exact_round_bins(const sfft_plan_desc_t& d, uint32_t r) {
@@ -155,6 +195,7 @@ struct sfft_plan_s {
     double* cand_e = nullptr;
     uint32_t* cand_n = nullptr;
     double* d_g64 = nullptr;
+    double* d_ftab = nullptr;  // Kaiser window: G' tables
     float* d_g32 = nullptr;
     double* d_tw64 = nullptr;  // Bmax complex
     float* d_tw32 = nullptr;
@@ -243,7 +284,7 @@ uint32_t general_default_rounds(uint32_t k) {
 sfft_status_t resolve_and_validate(sfft_plan_desc_t& d) {
     sfft_status_t s = sfft_validate_params(&d);
     if (s != SFFT_OK) return s;
-    if (d.w == 0) d.w = default_w(d.n, d.B, d.alpha, d.delta);
+    if (d.w == 0) d.w = d.window == 1 ? kaiser_w(d.n, d.B, d.alpha, d.delta) : default_w(d.n, d.B, d.alpha, d.delta);
     if (d.cap == 0) d.cap = d.k;
     if (d.rounds == 0) d.rounds = d.mode == SFFT_MODE_GENERAL ? general_default_rounds(d.k) : 16;
     if (d.hash_threads == 0) d.hash_threads = 256;
@@ -303,6 +344,12 @@ sfft_status_t build_plan(sfft_plan_s* p) {
     std::vector<double> g64;
     std::vector<std::pair<uint32_t, double>> seenB;   // (B_r, alpha_r) of each window table
     std::vector<uint64_t> seenOfs;
+    // Kaiser window: each window table's G' table (|f| <= n / (2 B_r)) at
+    // an offset of the G' tables, and the round's offset
+    std::vector<uint64_t> seenF, round_f;
+    uint64_t nftab = 0;
+    const bool kaiser = d.window == 1;
+    const double kbeta = kaiser_beta(d.delta), ki0 = bessel_i0(kbeta);
     p->mcap = 4;
     // exact mode with alpha_decay: alpha shrinks with B up to the first
     // round at the smallest bin count
@@ -345,11 +392,18 @@ sfft_status_t build_plan(sfft_plan_s* p) {
         auto it = std::find(seenB.begin(), seenB.end(), std::make_pair(g.B, alpha_r));
         if (it == seenB.end()) {
             g.gofs = g64.size();
-            for (uint64_t u = 0; u < g.w; ++u) g64.push_back(g_star((double)(g.t0 + (int64_t)u), g.ws));
+            for (uint64_t u = 0; u < g.w; ++u) {
+                const double t = (double)(g.t0 + (int64_t)u);
+                g64.push_back(kaiser ? kaiser_g(t, g.w, g.ws.C, kbeta, ki0) : g_star(t, g.ws));
+            }
             seenB.emplace_back(g.B, alpha_r);
             seenOfs.push_back(g.gofs);
+            seenF.push_back(nftab);
+            if (kaiser) nftab += d.n / (2 * g.B) + 1;
+            round_f.push_back(seenF.back());
         } else {
             g.gofs = seenOfs[it - seenB.begin()];
+            round_f.push_back(seenF[it - seenB.begin()]);
         }
         // modulation table length: the exact pair (a = 0, beta = 1); general
         // pairs need at most 2 w_r / B_r + 4 (beta below w) or w_r / B_r + 2
@@ -418,6 +472,10 @@ sfft_status_t build_plan(sfft_plan_s* p) {
         tw32[2 * m] = (float)tw64[2 * m];
         tw32[2 * m + 1] = (float)tw64[2 * m + 1];
     }
+    if (kaiser) {
+        ST_TRY(dev_alloc(p, &p->d_ftab, nftab));
+        for (uint32_t r = 0; r < p->R; ++r) p->geom[r].ws.ftab = p->d_ftab + round_f[r];
+    }
     ST_TRY(dev_alloc(p, &p->d_geom, p->geom.size()));
     ST_TRY(dev_alloc(p, &p->d_g64, g64.size()));
     ST_TRY(dev_alloc(p, &p->d_g32, g32.size()));
@@ -429,6 +487,16 @@ sfft_status_t build_plan(sfft_plan_s* p) {
         HIP_TRY(hipMemcpy(p->d_g32, g32.data(), g32.size() * sizeof(float), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(p->d_tw64, tw64.data(), tw64.size() * sizeof(double), hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(p->d_tw32, tw32.data(), tw32.size() * sizeof(float), hipMemcpyHostToDevice));
+        // G' of each Kaiser window table, from its G (the window's response)
+        for (size_t q = 0; kaiser && q < seenB.size(); ++q) {
+            const uint32_t Bq = seenB[q].first;
+            uint64_t wq = 0;
+            for (const RoundDev& g : p->geom)
+                if (g.gofs == seenOfs[q]) wq = g.w;
+            HIP_TRY(launch_window_response(p->d_g64 + seenOfs[q], wq, -(int64_t)(wq / 2), d.n, Bq, seenB[q].second,
+                                           p->d_ftab + seenF[q], d.n / (2 * Bq) + 1, nullptr));
+        }
+        if (kaiser) HIP_TRY(hipStreamSynchronize(nullptr));
     }
     if (general_mode(p)) {
         ST_TRY(dev_alloc(p, &p->d_groundv, p->groundv.size()));
@@ -878,6 +946,14 @@ const char* sfft_last_error(void) { return g_last_error.c_str(); }
 
 uint64_t sfft_splitmix64(uint64_t seed, uint64_t c) { return splitmix64(seed, c); }
 
+uint64_t sfft_window_w(uint64_t n, uint32_t B, double alpha, double delta, uint32_t window) {
+    if (window == 0) return sfft_default_w(n, B, alpha, delta);
+    if (window != 1 || !is_pow2(n) || !is_pow2(B) || B > n || !(alpha > 0.0 && alpha < 1.0) ||
+        !(delta > 0.0 && delta < 1.0))
+        return 0;
+    return kaiser_w(n, B, alpha, delta);
+}
+
 uint64_t sfft_default_w(uint64_t n, uint32_t B, double alpha, double delta) {
     if (!is_pow2(n) || !is_pow2(B) || B > n || !(alpha > 0 && alpha < 1) || !(delta > 0 && delta < 1)) return 0;
     return default_w(n, B, alpha, delta);
@@ -922,7 +998,7 @@ sfft_status_t sfft_desc_init(sfft_plan_desc_t* d, uint64_t n, uint32_t k, uint32
     d->hash_mode = 0;
     d->refine_shift = 0;
     d->refine_window = 0;
-    d->reserved = 0;
+    d->window = 0;
     return SFFT_OK;
 }
 
@@ -962,6 +1038,7 @@ sfft_status_t sfft_validate_params(const sfft_plan_desc_t* d) {
     if (d->hash_mode != 0 && (d->mode == SFFT_MODE_GENERAL || d->chunks > 1))
         return fail(SFFT_EINVAL, "hash_mode applies to exact mode with at most one chunk");
     if (d->refine_window > 1024) return fail(SFFT_EINVAL, "refine_window must be in [0, 1024]");
+    if (d->window > 1) return fail(SFFT_EINVAL, "window must be 0 (Gaussian) or 1 (Kaiser-Bessel)");
     if (d->refine_shift != 0) {
         const uint64_t E = d->refine_window ? d->refine_window : 16;
         if (d->mode == SFFT_MODE_GENERAL) return fail(SFFT_EINVAL, "refine_shift applies to exact mode only");

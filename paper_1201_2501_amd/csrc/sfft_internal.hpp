@@ -212,6 +212,11 @@ hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s);
 hipError_t launch_general_decode(const GeneralArgs& a, uint32_t r_begin, uint32_t r_end, hipStream_t s);
 hipError_t launch_general_finish(const GeneralArgs& a, hipStream_t s);
 
+// G'_f, f < count, of a window G (w samples from t0): 1 in the pass band,
+// 0 from n / (2B) on, its real response sum_t G_t cos(2 pi f t / n) clamped
+// to [0, 1] in between.
+hipError_t launch_window_response(const double* G, uint64_t w, int64_t t0, uint64_t n, uint32_t B, double alpha,
+                                  double* out, uint64_t count, hipStream_t s);
 size_t h2b_pair_lds_bytes(uint32_t Bmax, uint64_t max_mcount, bool acc_f64, uint32_t threads, bool tri = false);
 bool h2b_threads_ok(uint32_t threads);
 size_t decode_lds_bytes(uint32_t capz, uint32_t Bmax);

@@ -32,7 +32,7 @@ SFFT_FLAG_TIMING = 0x2
 INFO_ROUNDS, INFO_FLAGS, INFO_ZHAT, INFO_LOCATED = range(4)
 
 # every symbol declared in include/sfft.h
-EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_plan_ex", "sfft_plan",
+EXPORTS = ["sfft_desc_init", "sfft_validate_params", "sfft_default_w", "sfft_window_w", "sfft_plan_ex", "sfft_plan",
            "sfft_plan_get_desc", "sfft_destroy", "sfft_execute", "sfft_execute_batch",
            "sfft_hash_pair_raw", "sfft_plan_timings", "sfft_plan_h2b_bytes", "sfft_plan_round_groups",
            "sfft_plan_raw_slot", "sfft_plan_raw_refine", "sfft_plan_desc_bytes", "sfft_plan_device_bytes", "sfft_plan_samples", "sfft_plan_stream_rounds",
@@ -56,7 +56,7 @@ class PlanDesc(ctypes.Structure):
                 ("stop_patience", c_uint32), ("group0", c_uint32), ("ratio_tol", c_double),
                 ("group_step", c_uint32), ("hash_order", c_uint32), ("alpha_decay", c_double),
                 ("hash_split", c_uint32), ("hash_mode", c_uint32), ("refine_shift", c_uint64),
-                ("refine_window", c_uint32), ("reserved", c_uint32)]
+                ("refine_window", c_uint32), ("window", c_uint32)]
 
 
 class ServerDesc(ctypes.Structure):
@@ -101,6 +101,8 @@ def load():
     lib.sfft_validate_params.argtypes = [POINTER(PlanDesc)]
     lib.sfft_default_w.argtypes = [c_uint64, c_uint32, c_double, c_double]
     lib.sfft_default_w.restype = c_uint64
+    lib.sfft_window_w.argtypes = [c_uint64, c_uint32, c_double, c_double, c_uint32]
+    lib.sfft_window_w.restype = c_uint64
     lib.sfft_plan_ex.argtypes = [POINTER(PlanDesc), POINTER(P)]
     lib.sfft_plan.argtypes = [c_uint64, c_uint32, c_uint32, c_uint64, c_uint64, POINTER(P)]
     lib.sfft_plan_get_desc.argtypes = [P, POINTER(PlanDesc)]
@@ -145,7 +147,7 @@ def load():
     lib.sfft_server_reset_stats.argtypes = [P]
     lib.sfft_server_destroy.argtypes = [P]
     for name in EXPORTS:
-        if name not in ("sfft_default_w", "sfft_status_string", "sfft_last_error", "sfft_splitmix64",
+        if name not in ("sfft_default_w", "sfft_window_w", "sfft_status_string", "sfft_last_error", "sfft_splitmix64",
                         "sfft_plan_h2b_bytes", "sfft_plan_device_bytes", "sfft_dense_topk_noalloc_max_count",
                         "sfft_plan_samples", "sfft_plan_stream_rounds", "sfft_plan_desc_bytes"):
             getattr(lib, name).restype = c_int32
@@ -186,6 +188,10 @@ def sfft_validate_params(desc):
 
 def sfft_default_w(n, B, alpha=0.5, delta=1e-9):
     return int(load().sfft_default_w(n, B, alpha, delta))
+
+
+def sfft_window_w(n, B, alpha=0.5, delta=1e-9, window=0):
+    return int(load().sfft_window_w(n, B, alpha, delta, window))
 
 
 def sfft_plan_ex(desc):

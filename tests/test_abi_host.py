@@ -178,3 +178,24 @@ def test_refine_adds_its_samples():
     assert sfft.sfft_plan_samples(d) == 4 * (w + 1000)
     d.refine_shift, d.refine_window = w + 5, 2
     assert sfft.sfft_plan_samples(d) == 4 * (2 * w + 1)
+
+
+@pytest.mark.parametrize("n,B,alpha,delta", [(1 << 14, 64, 0.5, 1e-12), (1 << 22, 1024, 0.75, 1e-8),
+                                             (1 << 20, 256, 0.6, 1e-7), (1 << 26, 4096, 0.5, 1e-6),
+                                             (1 << 12, 1024, 0.5, 1e-9)])
+def test_kaiser_window_length_matches_oracle(n, B, alpha, delta):
+    from oracle.window import default_w
+    assert sfft.sfft_window_w(n, B, alpha, delta, 1) == default_w(n, B, alpha, delta, kind=1)
+    assert sfft.sfft_window_w(n, B, alpha, delta, 0) == sfft.sfft_default_w(n, B, alpha, delta)
+    assert sfft.sfft_window_w(n, B, alpha, delta, 2) == 0
+
+
+def test_window_field_validation_and_default_length():
+    d = sfft.sfft_desc_init(1 << 22, 256, 1024)
+    d.window = 2
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_EINVAL
+    d.window = 1
+    assert sfft.sfft_validate_params(d) == sfft.SFFT_OK
+    d.b_min, d.rounds, d.group0 = 1024, 4, 4
+    w = sfft.sfft_window_w(1 << 22, 1024, d.alpha, d.delta, 1)
+    assert sfft.sfft_plan_samples(d) == 4 * (w + 1)          # w = 0 resolves to the Kaiser length

@@ -41,7 +41,7 @@ def oracle_params(plan, seed=None):
                       delta=d.delta, theta=d.theta, g_min=d.g_min, rounds=d.rounds, b_min=d.b_min,
                       patience=d.patience, stop_count=d.stop_count, stop_patience=d.stop_patience,
                       ratio_tol=d.ratio_tol, alpha_decay=d.alpha_decay, cap=d.cap, refine_shift=d.refine_shift,
-                      refine_window=d.refine_window or 16)
+                      refine_window=d.refine_window or 16, window=d.window)
 
 
 RAW_CASES = [
@@ -722,3 +722,80 @@ def test_adversarial_collision_matches_oracle(torch_dev, n, B, dtype, extra):
         assert int(info[0]) == ref.rounds_used
         compare(idx, v, ref)
     plan.close()
+
+
+@pytest.mark.parametrize("n,B,dtype,prec,B_r", [(1 << 14, 64, np.complex128, 1, 64), (1 << 14, 64, np.complex128, 1, 16),
+                                               (1 << 22, 1024, np.complex64, 1, 1024),
+                                               (1 << 22, 1024, np.complex64, 1, 64),
+                                               (1 << 22, 1024, np.complex64, 0, 1024)])
+def test_kaiser_raw_bins_match_oracle(torch_dev, n, B, dtype, prec, B_r):
+    """The Kaiser-Bessel window (plan window = 1): the pair's raw bins match
+    the oracle's HashToBins with its own Kaiser window table (FP64 within
+    1e-12 of the bins' RMS, FP32 within 1e-5)."""
+    torch, dev = torch_dev
+    delta = 1e-12 if dtype == np.complex128 else 1e-8
+    alpha = 0.5 if n == 1 << 14 else 0.75
+    w = default_w(n, B, alpha, delta, kind=1)
+    x, sup, val = siggen.planted_signal(n, 40, 13, dtype, noise_ratio=0.01)
+    say("kaiser-raw", "n", n, "B", B, "B_r", B_r, "w", w, "prec", prec)
+    plan = plan_for(n, 40, B, w, 5, delta=delta, alpha=alpha, in_dtype=int(dtype == np.complex128), loc_prec=prec,
+                    b_min=16, window=1)
+    xd = torch.from_numpy(x).to(dev)
+    rng = np.random.default_rng(B_r + prec)
+    sigma = int(rng.integers(0, n // 2)) * 2 + 1
+    a = int(rng.integers(0, n))
+    b = int(rng.integers(0, n))
+    u0, u1 = plan.hash_pair_raw(xd, sigma, a, 1, b, B_r, prec)
+    torch.cuda.synchronize()
+    G = window_time(n, B_r, w * B_r // B, alpha, delta, kind=1)
+    e0 = hash_to_bins_raw(x, sigma, a, b, B_r, G)
+    e1 = hash_to_bins_raw(x, sigma, (a + 1) % n, b, B_r, G)
+    rms = np.sqrt(np.mean(np.abs(np.concatenate([e0, e1])) ** 2))
+    err = max(np.max(np.abs(u0.cpu().numpy() - e0)), np.max(np.abs(u1.cpu().numpy() - e1)))
+    print("kaiser raw-bin error of rms", err / rms, flush=True)
+    assert err <= (1e-12 if prec == 1 else 1e-5) * rms
+    plan.close()
+
+
+@pytest.mark.parametrize("shape", ["c1", "c3"])
+def test_kaiser_window_recovery_matches_oracle(torch_dev, shape):
+    """Exact mode with the Kaiser-Bessel window against the oracle with the
+    same window: supports bit-exact (and equal to the planted ones), values
+    within 1e-10, rounds decoded equal.  C1: n = 2^14, complex128, plain and
+    batched; C3: n = 2^22, k = 256, log-uniform magnitudes, the tuned
+    schedule's fields with the Kaiser length."""
+    torch, dev = torch_dev
+    if shape == "c1":
+        n, k, B, dtype, count = 1 << 14, 16, 64, np.complex128, 4
+        kw = dict(delta=1e-12, in_dtype=1, loc_prec=1)
+        alpha, mag = 0.5, "unit"
+    else:
+        n, k, B, dtype, count = 1 << 22, 256, 1024, np.complex64, 4
+        kw = dict(alpha=0.75, delta=1e-8, b_min=64, patience=5, rounds=24, theta=0.01, g_min=0.25, ratio_tol=0.002,
+                  stop_count=k, stop_patience=3, group0=12, group_step=3, loc_prec=1)
+        alpha, mag = 0.75, "loguniform"
+    w = default_w(n, B, alpha, kw["delta"], kind=1)
+    say("kaiser-recovery", shape, "n", n, "k", k, "B", B, "w", w)
+    plan = plan_for(n, k, B, w, 0, window=1, max_batch=count, **kw)
+    xs, sups, seeds = [], [], []
+    # C1: signals whose oracle runs have no decision within 1e-9 of a tie and
+    # recover (at this shape about 3 % of signals do not, with either window)
+    for s in ([0, 3, 4, 6] if shape == "c1" else range(count)):
+        x, sup, _ = siggen.planted_signal(n, k, 960 + s, dtype, magnitude=mag)
+        xs.append(x)
+        sups.append(sup)
+        seeds.append(13 * s + 1)
+    out = run_batch(torch, dev, plan, xs, seeds)
+    for s in range(count):
+        ref = noiseless_sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        assert int(out[s][2][0]) == ref.rounds_used
+        compare(out[s][0], out[s][1], ref)
+        assert np.array_equal(out[s][0], sups[s])
+    plan.close()
+    if shape == "c1":
+        plan = plan_for(n, k, B, w, seeds[0], window=1, **kw)
+        idx, v, info, st = plan.execute(torch.from_numpy(xs[0]).to(dev))
+        ref = noiseless_sparse_fft(xs[0], oracle_params(plan))
+        assert int(info[0]) == ref.rounds_used
+        compare(idx, v, ref)
+        plan.close()

@@ -30,19 +30,19 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def make_plan(n, k, B, seed, prec, max_batch=1, delta=1e-6, est_prec=None):
+def make_plan(n, k, B, seed, prec, max_batch=1, delta=1e-6, est_prec=None, window=0):
     """General-mode plan: LocateInner pairs in `prec` arithmetic (0 FP32, 1
     FP64), EstimateValues hashings in `est_prec` (default: the same)."""
     from paper_1201_2501_amd.sfft import Plan, SFFT_MODE_GENERAL
     return Plan(n, k, B, 0, seed, mode=SFFT_MODE_GENERAL, delta=delta, loc_prec=prec,
-                est_prec=prec if est_prec is None else est_prec, max_batch=max_batch)
+                est_prec=prec if est_prec is None else est_prec, max_batch=max_batch, window=window)
 
 
 def oracle_params(plan, seed=None):
     d = plan.desc
     return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=d.seed if seed is None else seed, alpha=d.alpha,
                       delta=d.delta, g_min=d.g_min, rounds=d.rounds, t=d.t, s=d.s, R_loc=d.R_loc,
-                      R_est=d.R_est, cap=d.cap, b_min=d.b_min)
+                      R_est=d.R_est, cap=d.cap, b_min=d.b_min, window=d.window)
 
 
 def check(idx, val, ref, rel, allow_near_tie=False):
@@ -276,6 +276,27 @@ def test_general_b_min_schedule_matches_oracle(torch_dev, b_min):
     seeds = [7 + 3 * s for s in range(count)]
     bufs = plan.execute_batch(torch.from_numpy(np.stack(xs)).to(dev), torch.tensor(seeds, dtype=torch.int64,
                                                                                      device=dev))
+    torch.cuda.synchronize()
+    for s in range(count):
+        c = int(bufs["counts"][s])
+        ref = sparse_fft(xs[s], oracle_params(plan, seeds[s]))
+        check(bufs["idx"][s, :c].cpu().numpy(), bufs["val"][s, :c].cpu().numpy(), ref, 1e-10)
+    plan.close()
+
+
+@pytest.mark.parametrize("noise", [0.0, 0.05])
+def test_general_kaiser_window_matches_oracle(torch_dev, noise):
+    """General mode with the Kaiser-Bessel window (window = 1), FP64, batched
+    over three signals with their own seeds: supports bit-exact and values
+    within 1e-10 of the oracle with the same window."""
+    torch, dev = torch_dev
+    n, k, B, count = 1 << 16, 12, 256, 3
+    say("general-kaiser", "n", n, "k", k, "B", B, "noise", noise)
+    plan = make_plan(n, k, B, 0, 1, max_batch=count, window=1)
+    xs = [siggen.planted_signal(n, k, 640 + s, np.complex64, noise_ratio=noise)[0] for s in range(count)]
+    seeds = [5, 6, 7]
+    X = torch.from_numpy(np.stack(xs)).to(dev)
+    bufs = plan.execute_batch(X, torch.tensor(seeds, dtype=torch.int64, device=dev))
     torch.cuda.synchronize()
     for s in range(count):
         c = int(bufs["counts"][s])
