@@ -550,7 +550,7 @@ def oracle_params(desc, seed):
                       patience=desc.patience, stop_count=desc.stop_count,
                       stop_patience=desc.stop_patience, ratio_tol=desc.ratio_tol, cap=desc.cap,
                       alpha_decay=desc.alpha_decay, refine_shift=desc.refine_shift,
-                      refine_window=desc.refine_window or 16)
+                      refine_window=desc.refine_window or 16, window=desc.window)
 
 
 def main():
@@ -589,6 +589,9 @@ def main():
     ap.add_argument("--hash-split", type=int, default=None,
                     help="exact mode: workgroups per (signal, round) of the HashToBins pair launches (over the "
                          "chosen plan's)")
+    ap.add_argument("--window", type=int, default=None,
+                    help="flat window over the chosen plan's: 0 Gaussian (Section 7 construction), 1 Kaiser-Bessel "
+                         "(the window length then follows Kaiser's rule unless --w is given)")
     ap.add_argument("--refine-shift", type=int, default=0,
                     help="exact mode: shift A of the multi-shift phase refinement (a third hashing per round; "
                          "0: off)")
@@ -699,7 +702,8 @@ def main():
             B = res.B
             tuned = {f: v for f, v in res.fields.items() if f != "mode"}
             tune_rec = res.as_dict()
-    w = args.w or sfft.sfft_default_w(n, B, tuned.get("alpha", 0.5), tuned.get("delta", 1e-9))
+    window = args.window if args.window is not None else tuned.get("window", 0)
+    w = args.w or sfft.sfft_window_w(n, B, tuned.get("alpha", 0.5), tuned.get("delta", 1e-9), window)
     plan_kw = dict(base_kw, **tuned, max_batch=S, flags=sfft.SFFT_FLAG_TIMING)
     if args.alpha_decay:
         plan_kw["alpha_decay"] = args.alpha_decay
@@ -709,6 +713,7 @@ def main():
         plan_kw["loc_prec"] = loc_prec
     if args.hash_split is not None:
         plan_kw["hash_split"] = args.hash_split
+    plan_kw["window"] = window
     if args.refine_shift:
         plan_kw.update(refine_shift=args.refine_shift, refine_window=args.refine_window)
     log("plan: B=%d w=%d %s" % (B, w, ", ".join("%s=%s" % kv for kv in sorted(tuned.items()))))
@@ -726,6 +731,8 @@ def main():
         cfg_key += ",refine=%d" % desc.refine_shift
     if desc.hash_split > 1:
         cfg_key += ",split=%d" % desc.hash_split
+    if desc.window:
+        cfg_key += ",window=%d" % desc.window
     if desc.loc_prec == sfft.SFFT_F32:
         cfg_key += ",f32"
     if args.config_key:
@@ -900,6 +907,8 @@ def main():
                 err = math.sqrt(sum(abs(est.get(int(i), 0) - v) ** 2 for i, v in zip(supports[s], values[s])) +
                                 sum(abs(v) ** 2 for i, v in est.items() if i not in sup_set))
                 l2.append(err / float(np.linalg.norm(values[s])))
+                if (s + 1) % 128 == 0:
+                    log("oracle: %d of %d signals checked, %d mismatches" % (s + 1, nchk, mism))
             # FP64 bins match the FP64 oracle to rounding; FP32 bins (loc_prec f32)
             # carry their own rounding into the values
             parity = {"signals_checked": nchk, "support_mismatches": mism, "max_rel_err": max_rel,
@@ -952,7 +961,8 @@ def main():
                    "stop_count": desc.stop_count, "stop_patience": desc.stop_patience, "ratio_tol": desc.ratio_tol,
                    "alpha_decay": desc.alpha_decay, "samples_per_signal_group0": sfft.sfft_plan_samples(desc),
                    "hash_threads": desc.hash_threads, "hash_order": desc.hash_order,
-                   "hash_split": desc.hash_split, "chunks": chunks,
+                   "hash_split": desc.hash_split, "window": ["gaussian", "kaiser-bessel"][desc.window],
+                   "chunks": chunks,
                    "loc_prec": "f64" if desc.loc_prec == sfft.SFFT_F64 else "f32",
                    "refine_shift": desc.refine_shift, "refine_window": desc.refine_window,
                    "input": "complex64"},

@@ -1,5 +1,6 @@
-"""Autotuner of the batched sparse FFT: chooses the bin count B, the window
-length w (through its accuracy delta), the round schedule and the launch
+"""Autotuner of the batched sparse FFT: chooses the bin count B, the flat
+window (Gaussian or Kaiser-Bessel) and its length w (through its accuracy
+delta), the round schedule and the launch
 shape of a batch of one shape by measuring candidate plans on calibration
 signals on the device.
 
@@ -89,7 +90,7 @@ def default_space(n, k, mode, theta=0.25):
         Bs = [b for b in Bs if b >= 512] or Bs[-2:]
         return {
             "bins": {"B": Bs},
-            "window": {"delta": [1e-10, 1e-9, 1e-8, 1e-7, 1e-6], "alpha": [0.5, 0.6, 0.7, 0.75]},
+            "window": {"window": [0, 1], "delta": [1e-10, 1e-9, 1e-8, 1e-7, 1e-6], "alpha": [0.5, 0.6, 0.7, 0.75]},
             "schedule": {"b_min": [16, 32, 64], "patience": [3, 4, 5]},
             "decode": {"theta": [theta, theta / 2], "g_min": [0.25, 0.4], "ratio_tol": [0.0, 0.002, 0.01]},
             "stop": {"stop_count": [0, k], "stop_patience": [2, 3], "patience": [3, 4, 5]},
@@ -100,7 +101,7 @@ def default_space(n, k, mode, theta=0.25):
     Bs = pow2_range(lo, min(4096, n // 16)) or [min(4096, max(2, n // 16))]
     return {
         "bins": {"B": Bs[:3]},
-        "window": {"delta": [1e-7, 1e-6]},
+        "window": {"window": [0, 1], "delta": [1e-7, 1e-6]},
         "schedule": {"R_est": [5, 7, 9], "R_loc": [3, 4]},
         "launch": {"hash_threads": [256, 512, 1024], "chunks": [1, 2]},
     }
@@ -155,6 +156,7 @@ def reference_candidate(space, mode, base):
     c = dict(base)
     c["B"] = max(space["bins"]["B"])
     c["delta"] = min(space["window"]["delta"])
+    c["window"] = 0
     if "alpha" in space["window"]:
         c["alpha"] = min(space["window"]["alpha"])
     if mode == sfft.SFFT_MODE_EXACT:
