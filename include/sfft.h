@@ -76,8 +76,10 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  * fixes Theta(.) constants):
  *   n, k      signal length (2^m, 2 <= m <= 40) and sparsity (1 <= k < n)
  *   B         bins of the first hashing round (power of two, 2 <= B <= n)
- *   w         window length, a multiple of B, B <= w <= n; 0 = the smallest
- *             multiple of B whose window tail sum_{|t| >= w/2} |G*(t)| <= delta
+ *   w         window length, a multiple of B, B <= w <= n; 0 = the window's
+ *             default (sfft_window_w): Gaussian, the smallest multiple of B
+ *             whose window tail sum_{|t| >= w/2} |G*(t)| <= delta;
+ *             Kaiser-Bessel, Kaiser's length rule
  *   seed      seed of the counter-based draws (SplitMix64; see below)
  *   mode      SFFT_MODE_EXACT (Algorithm 1) or SFFT_MODE_GENERAL (Algs 2, 3)
  *   in_dtype  storage type of the input signal
@@ -88,7 +90,8 @@ typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_prec_t;
  *   alpha     flat-window transition fraction (Section 2 definition)
  *   delta     window accuracy ||Ghat - G'||_inf < delta; sets the Gaussian
  *             width sigma_g = (4B/alpha) sqrt(2 ln(3/delta)) (Section 7
- *             construction without its delta -> delta/n normalisation step)
+ *             construction without its delta -> delta/n normalisation step),
+ *             or the Kaiser-Bessel window's shape beta and length (window)
  *   theta     bin threshold of the exact decode (the paper's 1/2 for
  *             integer spectra, Algorithm 1)
  *   g_min     smallest window value G'_{-o(i)} a bin value is divided by
@@ -437,7 +440,8 @@ uint64_t sfft_splitmix64(uint64_t seed, uint64_t c);
  * window tables kept resident):
  *   * a request (n, k, mode) maps to a shape: k rounded up to a power of two
  *     (at least 8), B = 4k' (exact) or 16k' (general) within [64 or 256,
- *     min(4096, n/16)], the default window for the mode's delta; exact shapes
+ *     min(4096, n/16)], the Kaiser-Bessel window (window = 1) at its default
+ *     length for the mode's delta; exact shapes
  *     use b_min = max(32, B/32) (at most B), at most 24 rounds, patience 5,
  *     hash_split = B/256 (1 to 16 parts) and hash_mode 1 (stream mode for
  *     rounds whose window covers n/8 or more).  Where that window would

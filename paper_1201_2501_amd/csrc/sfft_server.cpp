@@ -99,7 +99,10 @@ sfft_status_t shape_for(uint64_t n, uint32_t k, int32_t mode, const sfft_server_
     }
     d->cap = kb;
     d->max_batch = sd.slots;
-    d->w = sfft_default_w(n, (uint32_t)B, d->alpha, d->delta);
+    // the Kaiser-Bessel flat window: the same flatness with about half the
+    // Gaussian construction's samples
+    d->window = 1;
+    d->w = sfft_window_w(n, (uint32_t)B, d->alpha, d->delta, 1);
     *dense = d->w >= n || sfft_validate_params(d) != SFFT_OK;
     if (!*dense && !(sd.flags & SFFT_SERVER_SPARSE_ONLY)) {
         // the path a request served alone finishes sooner on: the sparse

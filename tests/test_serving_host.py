@@ -43,7 +43,8 @@ def test_server_shape_policy(n, k, mode, B, dense):
     kb = 1 << max(3, (k - 1).bit_length())
     assert d.k == kb and d.cap == kb and d.B == B and d.mode == mode and d.max_batch == sd.slots
     delta = sd.delta_exact if mode == sfft.SFFT_MODE_EXACT else sd.delta_general
-    w = default_w(n, B, 0.5, delta)
+    w = default_w(n, B, 0.5, delta, kind=1)      # served shapes use the Kaiser-Bessel window
+    assert d.window == 1
     assert is_dense == dense
     if w < n:
         # the path model decides, from the sparse plan's gathered and
