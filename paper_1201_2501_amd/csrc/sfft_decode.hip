@@ -51,6 +51,7 @@ struct DecodeLds {
     uint32_t* sw;      // [kStateWords] the signal's decode state while a kernel runs
     cx<double>* t;     // [capz][2]   per-entry terms of one hashing (LDS, or HBM when they do not fit)
     uint32_t* ec;      // [capz]      re-estimation sample counts (LDS, or HBM when they do not fit)
+    double* gp;        // [capz]      G'_{-o(i)} of each entry (per-round re-estimation)
 };
 
 // LDS work lists of the passes after the first.  A slot per entry not alone
@@ -186,8 +187,11 @@ __host__ __device__ inline size_t reest_lds_layout(uint32_t capz, uint32_t Bmax,
     off = align16(off + (kDec / 64) * 4);
     const size_t o_t = off;
     off = align16(off + (size_t)capz * 16);
+    const size_t o_gp = off;
+    off = align16(off + (size_t)capz * 8);
     if (base) {
         *L = DecodeLds{};
+        L->gp = reinterpret_cast<double*>(base + o_gp);
         L->hk = reinterpret_cast<uint16_t*>(base + o_hk);
         L->ent = reinterpret_cast<uint16_t*>(base + o_ent);
         L->first = reinterpret_cast<uint32_t*>(base + o_first);
@@ -1049,10 +1053,12 @@ __device__ __forceinline__ void term_entry(DecodeLds& L, uint32_t e, double2 z, 
     const uint64_t i = L.zl[e];
     const BinOffset bo = bin_offset(i, sigma, b, n, B);
     L.hk[e] = (uint16_t)bo.h;
+    // the phase factor first: its sincos overlaps the load of a tabulated G'
+    const cx<double> om = omega_d((sigma * i) & (n - 1), n);
     const double gp = gprime(-bo.o, n, B, ws);
     const cx<double> c0{gp * z.x, gp * z.y};
     L.t[2 * e] = c0;
-    L.t[2 * e + 1] = cmul(c0, omega_d((sigma * i) & (n - 1), n));
+    L.t[2 * e + 1] = cmul(c0, om);
 }
 
 __device__ void stage_terms(DecodeLds& L, uint32_t zc, const double2 (&zp)[kUnroll], const double2* zv2,
@@ -1446,6 +1452,7 @@ __global__ void __launch_bounds__(kDec) k_exact_reest(DecodeArgs D) {
         const double gp = gprime(-bo.o, n, B, g.ws);
         const double2 z = zv2[e];
         L.t[e] = cx<double>{gp * z.x, gp * z.y};
+        L.gp[e] = gp;
     }
     __syncthreads();
     group_by_bin(L, zc, B);
@@ -1457,7 +1464,7 @@ __global__ void __launch_bounds__(kDec) k_exact_reest(DecodeArgs D) {
     for (uint32_t e = tid; e < zc; e += kDec) {
         const uint32_t h = L.hk[e];
         const uint32_t p0 = L.first[h], p1 = L.first[h + 1];
-        const double ge = gprime(-bin_offset(zi[e], sigma, b, n, B).o, n, B, g.ws);
+        const double ge = L.gp[e];
         if (p1 - p0 > 1) {
             D.egrp[row + e] = p0 << 16 | (p1 - p0);
             D.ecoef[2 * (row + e)] = ge;

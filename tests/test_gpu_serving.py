@@ -49,7 +49,7 @@ def oracle_for(d, seed):
     return SfftParams(n=d.n, k=d.k, B=d.B, w=d.w, seed=seed, alpha=d.alpha, delta=d.delta, theta=d.theta,
                       g_min=d.g_min, rounds=rounds, b_min=d.b_min, patience=d.patience, stop_count=d.stop_count,
                       stop_patience=d.stop_patience, ratio_tol=d.ratio_tol, cap=d.cap, t=d.t,
-                      s=d.s, R_loc=d.R_loc, R_est=d.R_est)
+                      s=d.s, R_loc=d.R_loc, R_est=d.R_est, window=d.window)
 
 
 # (name, n, k, mode, signal seed, request seed)
