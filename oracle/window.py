@@ -162,8 +162,26 @@ def _kaiser_window(n, B, w, alpha, delta):
     return G, t
 
 
+@functools.lru_cache(maxsize=64)
+def _kaiser_gprime_table(n, B, w, alpha, delta):
+    """G'_f of the kind-1 window for f = 0 .. n/(2B): the same sum as
+    kaiser_gprime describes, evaluated once for every f of the band."""
+    G, t = _kaiser_window(n, B, w, alpha, delta)
+    f = np.arange(n // (2 * B) + 1, dtype=np.int64)
+    out = np.where(f * 2 * B <= (1.0 - alpha) * n, 1.0, 0.0)
+    band = np.nonzero((f * 2 * B > (1.0 - alpha) * n) & (f * 2 * B < n))[0]
+    step = max(1, (1 << 22) // max(w, 1))
+    for q in range(0, len(band), step):
+        fs = f[band[q:q + step]]
+        ang = 2.0 * math.pi * ((fs[:, None] * t[None, :]) % n).astype(np.float64) / n
+        out[band[q:q + step]] = np.clip(np.sum(G[None, :] * np.cos(ang), axis=1), 0.0, 1.0)
+    return out
+
+
 def kaiser_gprime(f, n, B, w, alpha, delta):
-    """G'_f of the kind-1 window (signed integer f, taken mod n)."""
+    """G'_f of the kind-1 window (signed integer f, taken mod n): 1 in the
+    pass band, 0 from n/(2B) on, sum_t G_t cos(2 pi f t / n) clamped to
+    [0, 1] in between (tabulated per window by _kaiser_gprime_table)."""
     f = int(f) % n
     if f >= n // 2:
         f -= n
@@ -172,9 +190,7 @@ def kaiser_gprime(f, n, B, w, alpha, delta):
         return 1.0
     if af * 2 * B >= n:
         return 0.0
-    G, t = _kaiser_window(n, B, w, alpha, delta)
-    ang = 2.0 * math.pi * ((af * t) % n).astype(np.float64) / n
-    return min(1.0, max(0.0, float(np.sum(G * np.cos(ang)))))
+    return float(_kaiser_gprime_table(n, B, w, alpha, delta)[af])
 
 
 def phi(x):
