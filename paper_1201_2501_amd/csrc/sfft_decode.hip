@@ -62,8 +62,12 @@ struct DecodeLds {
 // The lists are read from HBM once; the passes then work in LDS, and an
 // entry's value goes to HBM when it resolves.  Capacities are fixed; a
 // signal that exceeds one takes the direct path (peel_direct), with the
-// same results up to rounding.
-constexpr uint32_t kPeelU = 256, kPeelT = 1536, kPeelNb = 1536;
+// same results up to rounding.  The neighbour lists share kPeelNbBytes:
+// exact mode's term coefficients are real (G'), so its ratios are too and
+// take 8 bytes, general mode's 16.
+constexpr uint32_t kPeelU = 192, kPeelT = 1536;
+constexpr uint32_t kPeelNbBytes = 31040;
+constexpr uint32_t kPeelNbReal = kPeelNbBytes / (8 + 2), kPeelNbCx = kPeelNbBytes / (16 + 2);
 constexpr uint16_t kNoSlot = 0xFFFFu;
 struct PeelScratch {
     uint64_t* crowd;   // [kPeelU]  shared valid measurements of the slot's entry
@@ -72,17 +76,18 @@ struct PeelScratch {
     double2* delta;    // [kPeelU]  resolved value - decoded value
     uint64_t* task;    // [kPeelT]  slot | measurement << 16 | neighbours << 24 | first neighbour << 32
     double2* tsamp;    // [kPeelT]  the task's sample
-    double2* ratio;    // [kPeelNb] c_m(e') / c_m(e) of each listed neighbour
-    uint16_t* nbslot;  // [kPeelNb] its slot (kNoSlot: it never resolves)
+    double* ratio;     // [nbcap]   c_m(e') / c_m(e) of each listed neighbour (re, or re and im)
+    uint16_t* nbslot;  // [nbcap]   its slot (kNoSlot: it never resolves)
     uint16_t* ulist;   // [kPeelU]  entry of each slot
     uint16_t* tfirst;  // [kPeelU]  first task of each slot
     uint8_t* ustate;   // [kPeelU]  0 unresolved, 1 resolved, 2 resolved this pass
     uint32_t* cnt;     // [4]       slots, tasks, neighbours, overflow
+    uint32_t nbcap;    // neighbour list capacity
+    uint32_t real;     // real ratios (exact mode)
 };
 
 __host__ __device__ constexpr size_t peel_scratch_bytes() {
-    return (size_t)kPeelU * (8 + 8 + 16 + 16 + 2 + 2 + 1) + (size_t)kPeelT * (8 + 16) + (size_t)kPeelNb * (16 + 2) +
-           16 + 16;
+    return (size_t)kPeelU * (8 + 8 + 16 + 16 + 2 + 2 + 1) + (size_t)kPeelT * (8 + 16) + kPeelNbBytes + 16 + 16;
 }
 
 // Optional LDS parts, placed in this order while they fit.
@@ -736,17 +741,20 @@ struct PeelView {
 
 constexpr uint32_t kMaxPasses = 8;
 
-__device__ __forceinline__ PeelScratch peel_scratch(unsigned char* base) {
+// real: exact mode (real term coefficients).
+__device__ __forceinline__ PeelScratch peel_scratch(unsigned char* base, bool real) {
     PeelScratch P;
+    P.real = real;
+    P.nbcap = real ? kPeelNbReal : kPeelNbCx;
     P.zvu = reinterpret_cast<double2*>(base);
     P.delta = P.zvu + kPeelU;
     P.tsamp = P.delta + kPeelU;
-    P.ratio = P.tsamp + kPeelT;
-    P.crowd = reinterpret_cast<uint64_t*>(P.ratio + kPeelNb);
+    P.ratio = reinterpret_cast<double*>(P.tsamp + kPeelT);
+    P.crowd = reinterpret_cast<uint64_t*>(P.ratio + P.nbcap * (real ? 1u : 2u));
     P.ready = P.crowd + kPeelU;
     P.task = P.ready + kPeelU;
     P.nbslot = reinterpret_cast<uint16_t*>(P.task + kPeelT);
-    P.ulist = P.nbslot + kPeelNb;
+    P.ulist = P.nbslot + P.nbcap;
     P.tfirst = P.ulist + kPeelU;
     P.ustate = reinterpret_cast<uint8_t*>(P.tfirst + kPeelU);
     P.cnt = reinterpret_cast<uint32_t*>(base + ((reinterpret_cast<uintptr_t>(P.ustate + kPeelU) - reinterpret_cast<uintptr_t>(base) + 15) & ~(uintptr_t)15));
@@ -930,7 +938,7 @@ __device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, do
 #pragma unroll 4
         for (uint32_t i = 0; i < (w & 0xFFFFu); ++i) left += o[i] != e && res[o[i]] != 1;
         const uint32_t off = atomicAdd(&P->cnt[2], left);
-        if (left > 255 || off + left > kPeelNb) P->cnt[3] = 1;
+        if (left > 255 || off + left > P->nbcap) P->cnt[3] = 1;
         P->task[t] = tk | (uint64_t)(left & 0xFFu) << 24 | (uint64_t)off << 32;
     }
     __syncthreads();
@@ -959,7 +967,12 @@ __device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, do
                 acc = cadd(acc, cmul(c2, cx<double>{fin[2 * e2] - zv[2 * e2], fin[2 * e2 + 1] - zv[2 * e2 + 1]}));
             } else {
                 const cx<double> ra = cmul(c2, inv);
-                P->ratio[j] = make_double2(ra.r, ra.i);
+                if (P->real) {
+                    P->ratio[j] = ra.r;
+                } else {
+                    P->ratio[2 * j] = ra.r;
+                    P->ratio[2 * j + 1] = ra.i;
+                }
                 P->nbslot[j++] = (r2 & 0x8000u) ? (uint16_t)(r2 & 0x7FFFu) : kNoSlot;
             }
         }
@@ -974,9 +987,11 @@ __device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, do
         for (uint32_t j = off; j < off + c; ++j) {
             const uint16_t u2 = P->nbslot[j];
             if (u2 == kNoSlot || P->ustate[u2] != 1) continue;
-            const double2 r = P->ratio[j], d = P->delta[u2];
-            v.x -= r.x * d.x - r.y * d.y;
-            v.y -= r.x * d.y + r.y * d.x;
+            const double2 d = P->delta[u2];
+            const double rx = P->real ? P->ratio[j] : P->ratio[2 * j];
+            const double ry = P->real ? 0.0 : P->ratio[2 * j + 1];
+            v.x -= rx * d.x - ry * d.y;
+            v.y -= rx * d.y + ry * d.x;
         }
         P->tsamp[t] = v;
     };
@@ -1495,7 +1510,7 @@ __global__ void __launch_bounds__(kDec) k_exact_output(DecodeArgs D) {
     DecodeLds L;
     unsigned char* peel_base;
     output_lds_layout(D.capz, D.Bmax, false, smem, &L, &peel_base);
-    const PeelScratch P = peel_scratch(peel_base);
+    const PeelScratch P = peel_scratch(peel_base, true);
     uint32_t* st = D.state + (uint64_t)sig * kStateWords;
     load_state(L, st);
     const uint32_t R = L.sw[ST_ROUNDS];
@@ -1901,7 +1916,7 @@ __global__ void __launch_bounds__(kDec) k_gen_output(GeneralArgs G) {
     DecodeLds L;
     unsigned char* peel_base;
     output_lds_layout(G.capz, G.Bmax, true, smem, &L, &peel_base);
-    const PeelScratch P = peel_scratch(peel_base);
+    const PeelScratch P = peel_scratch(peel_base, false);
     uint32_t* st = G.state + (uint64_t)sig * kStateWords;
     load_state(L, st);
     const uint32_t R = L.sw[ST_ROUNDS];

@@ -390,34 +390,40 @@ __global__ void __launch_bounds__(kThreads) k_h2b_rsplit(H2BArgs A) {
 // ------------------------------------------------------------------ launch --
 bool h2b_threads_ok(uint32_t threads) { return threads == 256 || threads == 512 || threads == 1024; }
 
-// The Kaiser window's G' table (plan time): thread f sums the window's
-// response at integer frequency f in FP64, the phase from the exact integer
-// (f t) mod n.
+// The Kaiser window's G' table (plan time): one workgroup per frequency f
+// (grid-stride) sums the window's response at f in FP64, each thread a
+// strided share of the samples with the phase from the exact integer
+// (f t) mod n, then a fixed-order tree in LDS.
 __global__ void __launch_bounds__(256) k_window_response(const double* __restrict__ G, uint64_t w, int64_t t0,
                                                          uint64_t n, uint64_t B, double alpha, double* out,
                                                          uint64_t count) {
-    const uint64_t f = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= count) return;
-    double v;
-    if ((double)(f * 2 * B) <= (1.0 - alpha) * (double)n) {
-        v = 1.0;
-    } else if (f * 2 * B >= n) {
-        v = 0.0;
-    } else {
-        const uint64_t mask = n - 1;
+    __shared__ double part[256];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t mask = n - 1;
+    for (uint64_t f = blockIdx.x; f < count; f += gridDim.x) {
+        if ((double)(f * 2 * B) <= (1.0 - alpha) * (double)n || f * 2 * B >= n) {
+            if (tid == 0) out[f] = f * 2 * B >= n ? 0.0 : 1.0;
+            continue;   // uniform over the workgroup
+        }
         double acc = 0.0;
-        for (uint64_t u = 0; u < w; ++u) {
+        for (uint64_t u = tid; u < w; u += 256) {
             const uint64_t m = (f * (uint64_t)(t0 + (int64_t)u)) & mask;
             acc += G[u] * cospi(2.0 * (double)m / (double)n);
         }
-        v = fmin(1.0, fmax(0.0, acc));
+        part[tid] = acc;
+        __syncthreads();
+        for (uint32_t h = 128; h > 0; h >>= 1) {
+            if (tid < h) part[tid] += part[tid + h];
+            __syncthreads();
+        }
+        if (tid == 0) out[f] = fmin(1.0, fmax(0.0, part[0]));
+        __syncthreads();
     }
-    out[f] = v;
 }
 
 hipError_t launch_window_response(const double* G, uint64_t w, int64_t t0, uint64_t n, uint32_t B, double alpha,
                                   double* out, uint64_t count, hipStream_t s) {
-    const uint64_t blocks = (count + 255) / 256;
+    const uint64_t blocks = count < 65536 ? count : 65536;
     hipLaunchKernelGGL(k_window_response, dim3((uint32_t)blocks), dim3(256), 0, s, G, w, t0, n, (uint64_t)B, alpha,
                        out, count);
     return hipGetLastError();
