@@ -90,7 +90,7 @@ def default_space(n, k, mode, theta=0.25):
         Bs = [b for b in Bs if b >= 512] or Bs[-2:]
         return {
             "bins": {"B": Bs},
-            "window": {"window": [0, 1], "delta": [1e-10, 1e-9, 1e-8, 1e-7, 1e-6], "alpha": [0.5, 0.6, 0.7, 0.75]},
+            "window": {"window": [0, 1], "delta": [1e-10, 1e-9, 1e-8, 1e-7, 1e-6], "alpha": [0.5, 0.6, 0.7, 0.75, 0.8]},
             "schedule": {"b_min": [16, 32, 64], "patience": [3, 4, 5]},
             "decode": {"theta": [theta, theta / 2], "g_min": [0.25, 0.4], "ratio_tol": [0.0, 0.002, 0.01]},
             "stop": {"stop_count": [0, k], "stop_patience": [2, 3], "patience": [3, 4, 5]},
