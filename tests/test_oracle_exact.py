@@ -267,7 +267,9 @@ def test_ratio_check_keeps_exact_recovery(seed):
     x, sup, val = siggen.planted_signal(p.n, p.k, 100 + seed, np.complex128)
     r = noiseless_sparse_fft(x, p)
     assert np.array_equal(r.indices, sup)
-    assert np.max(np.abs(r.values - val)) < 1e-4
+    # the ratio check only removes decodes; the re-estimation resolved in
+    # passes is exact up to the window error delta = 1e-12
+    assert np.max(np.abs(r.values - val)) < 1e-9
 
 
 def test_refine_position_recovers_p_within_the_window():
