@@ -758,15 +758,32 @@ def main():
     log("inputs ready: %d x 2^%d complex64 (%.1f GiB) in %.1fs" % (S, args.log2n, X.numel() * 8 / 2**30, time.time() - t))
 
     bufs = plan.batch_buffers(S, dev)
+    # the throughput plan: the same description without phase events, so a
+    # one-chunk step replays as one graph
+    tplan = Plan(n, k, B, w, 0, **dict(plan_kw, flags=0))
+    tbufs = tplan.batch_buffers(S, dev)
 
     # ---------------------------------------------------------------- batched
+    # throughput: K steps queued back to back on one stream, bracketed by a
+    # synchronisation on each side
+    for _ in range(args.warmup):
+        tplan.execute_batch(X, seeds, bufs=tbufs)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        tplan.execute_batch(X, seeds, bufs=tbufs)
+    ev1.record()
+    torch.cuda.synchronize()
+    elapsed_ms = ev0.elapsed_time(ev1)
+    ms_per_step = elapsed_ms / args.steps
+    value = S * args.steps / (elapsed_ms / 1e3)
+    # phases and per-step latency: K more steps on the plan with phase
+    # events, each step waited for
     for _ in range(args.warmup):
         plan.execute_batch(X, seeds, bufs=bufs)
     torch.cuda.synchronize()
     h2b_ms, dec_ms, tail_ms, step_ms = [], [], [], []
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
     for _ in range(args.steps):
         plan.execute_batch(X, seeds, bufs=bufs)
         torch.cuda.synchronize()
@@ -776,13 +793,15 @@ def main():
         tail_ms.append(tm[2])
         step_ms.append(tm[3])
         chunks = int(tm[4])
-    ev1.record()
-    torch.cuda.synchronize()
-    elapsed_ms = ev0.elapsed_time(ev1)
-    ms_per_step = elapsed_ms / args.steps
-    value = S * args.steps / (elapsed_ms / 1e3)
-    log("batched: %.3f ms/step, %.0f sFFTs/s (hash %.3f ms, decode %.3f ms overlapped, tail %.3f ms, %d chunks)"
-        % (ms_per_step, value, np.mean(h2b_ms), np.mean(dec_ms), np.mean(tail_ms), chunks))
+    log("batched: %.3f ms/step, %.0f sFFTs/s; steps waited for one by one: %.3f ms (hash %.3f ms, decode %.3f ms "
+        "overlapped, tail %.3f ms, %d chunks)" % (ms_per_step, value, np.mean(step_ms), np.mean(h2b_ms),
+                                                   np.mean(dec_ms), np.mean(tail_ms), chunks))
+    same = all(torch.equal(tbufs[f], bufs[f]) for f in ("idx", "val", "counts"))
+    log("throughput and phase plans give identical outputs: %s" % same)
+    if not same:
+        raise SystemExit("the throughput plan's outputs differ from the phase plan's")
+    tplan.close()
+    del tbufs
 
     counts = bufs["counts"].cpu().numpy()
     info = bufs["info"].cpu().numpy()
@@ -969,7 +988,8 @@ def main():
         "autotune": tune_rec,
         "latency_ms": {"p10": round(percentile(step_ms, 10), 4), "p50": round(percentile(step_ms, 50), 4),
                        "p90": round(percentile(step_ms, 90), 4), "p99": round(percentile(step_ms, 99), 4),
-                       "steps": len(step_ms), "what": "per batch step (graph replay), HIP events"},
+                       "steps": len(step_ms),
+                       "what": "per batch step waited for alone (graph replays with phase events), HIP events"},
         "phases": phases,
         "plain": plain,
         "dense": dense,

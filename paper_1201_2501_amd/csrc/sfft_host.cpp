@@ -149,7 +149,8 @@ constexpr uint32_t kMaxChunks = 8;
 
 // Captured graphs of one batch shape: per chunk c, exec_h[c] = state reset +
 // HashToBins of the chunk (launch stream), exec_d[c] = decode + output of the
-// chunk (auxiliary stream), keyed by every argument pointer and the count.
+// chunk (auxiliary stream), keyed by every argument pointer and the count;
+// or (whole) exec_h[0] = the whole step of a one-chunk batch.
 struct GraphCache {
     hipGraphExec_t exec_h[kMaxChunks] = {};
     hipGraphExec_t exec_d[kMaxChunks] = {};
@@ -161,6 +162,7 @@ struct GraphCache {
     const void* o3 = nullptr;
     const void* o4 = nullptr;
     uint32_t count = 0;
+    bool whole = false;   // exec_h[0] holds the whole step (one chunk, no phase events)
 };
 
 struct sfft_plan_s {
@@ -900,12 +902,17 @@ uint32_t batch_chunks(const sfft_plan_s* p, uint32_t count) {
     return std::max(1u, std::min({c, kMaxChunks, count}));
 }
 
+// part 0 (state reset + first HashToBins launch), 1 (the rest) or 2 (both,
+// one graph).
 sfft_status_t capture_part(sfft_plan_s* p, int part, uint32_t off, uint32_t cnt, const void* x,
                            const uint64_t* seeds, uint64_t* idx, double* val, uint32_t* ocnt, uint32_t* info,
                            hipGraphExec_t* out) {
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
-    sfft_status_t st = enqueue_chunk(p, part, off, cnt, x, seeds, idx, val, ocnt, info, p->capture_stream);
+    sfft_status_t st = enqueue_chunk(p, part == 1 ? 1 : 0, off, cnt, x, seeds, idx, val, ocnt, info,
+                                     p->capture_stream);
+    if (st == SFFT_OK && part == 2)
+        st = enqueue_chunk(p, 1, off, cnt, x, seeds, idx, val, ocnt, info, p->capture_stream);
     hipError_t ee = hipStreamEndCapture(p->capture_stream, &graph);
     if (st != SFFT_OK) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -1370,9 +1377,12 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
     const bool use_graph = !(nog && nog[0] == '1');
     const uint32_t C = batch_chunks(p, count);
     const uint32_t per = (count + C - 1) / C;
+    // one chunk without phase events: the whole step is one graph, with no
+    // launch boundary between the first HashToBins launch and the decode
+    const bool whole = use_graph && C == 1 && !timing;
     GraphCache& gc = p->graph;
     if (use_graph) {
-        const bool hit = gc.exec_h[0] && gc.chunks == C && gc.x == x_dev && gc.count == count &&
+        const bool hit = gc.exec_h[0] && gc.chunks == C && gc.whole == whole && gc.x == x_dev && gc.count == count &&
                          gc.seeds == seeds_dev && gc.o1 == idx_dev && gc.o2 == val_dev && gc.o3 == count_dev &&
                          gc.o4 == info_dev;
         if (!hit) {
@@ -1382,13 +1392,19 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
                 gc.exec_h[c] = gc.exec_d[c] = nullptr;
             }
             gc.exec_h[0] = nullptr;
-            for (uint32_t c = 0; c < C; ++c) {
-                const uint32_t off = c * per, cnt = std::min(per, count - off);
-                ST_TRY(capture_part(p, 0, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
-                                    &gc.exec_h[c]));
-                ST_TRY(capture_part(p, 1, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
-                                    &gc.exec_d[c]));
+            if (whole) {
+                ST_TRY(capture_part(p, 2, 0, count, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
+                                    &gc.exec_h[0]));
+            } else {
+                for (uint32_t c = 0; c < C; ++c) {
+                    const uint32_t off = c * per, cnt = std::min(per, count - off);
+                    ST_TRY(capture_part(p, 0, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
+                                        &gc.exec_h[c]));
+                    ST_TRY(capture_part(p, 1, off, cnt, x_dev, seeds_dev, idx_dev, val_dev, count_dev, info_dev,
+                                        &gc.exec_d[c]));
+                }
             }
+            gc.whole = whole;
             gc.chunks = C;
             gc.x = x_dev;
             gc.count = count;
@@ -1403,6 +1419,10 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
     // single chunk has nothing to overlap: its decode follows on s itself
     // (a cross-stream wait costs tens of microseconds per step)
     hipStream_t ds = C > 1 ? p->aux_stream : s;
+    if (whole) {
+        HIP_TRY(hipGraphLaunch(gc.exec_h[0], s));
+        return SFFT_OK;
+    }
     if (timing) HIP_TRY(hipEventRecord(p->ev_t0, s));
     if (C > 1) {
         HIP_TRY(hipEventRecord(p->ev_fork, s));
