@@ -558,6 +558,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--inflight", type=int, default=4,
+                    help="batches in flight in the throughput measurement (one plan instance and stream each)")
     ap.add_argument("--signals", type=int, default=512)
     ap.add_argument("--log2n", type=int, default=22)
     ap.add_argument("--k", type=int, default=256)
@@ -758,25 +760,43 @@ def main():
     log("inputs ready: %d x 2^%d complex64 (%.1f GiB) in %.1fs" % (S, args.log2n, X.numel() * 8 / 2**30, time.time() - t))
 
     bufs = plan.batch_buffers(S, dev)
-    # the throughput plan: the same description without phase events, so a
-    # one-chunk step replays as one graph
-    tplan = Plan(n, k, B, w, 0, **dict(plan_kw, flags=0))
-    tbufs = tplan.batch_buffers(S, dev)
+    # throughput plans: the same description without phase events (a
+    # one-chunk step replays as one graph), one plan instance and stream per
+    # batch in flight; step i runs on instance i mod inflight, so the
+    # latency-bound decode of one batch overlaps the gathers of the next
+    inflight = max(1, args.inflight)
+    tplans = [Plan(n, k, B, w, 0, **dict(plan_kw, flags=0)) for _ in range(inflight)]
+    tbufs = [tp.batch_buffers(S, dev) for tp in tplans]
+    tstreams = [torch.cuda.Stream() for _ in range(inflight)]
+
+    def throughput(m):
+        """ms per step over K steps with m batches in flight, bracketed by a
+        synchronisation on each side (GPU events on the current stream, which
+        the instance streams join)."""
+        for i in range(max(args.warmup, m)):
+            tplans[i % m].execute_batch(X, seeds, stream=tstreams[i % m], bufs=tbufs[i % m])
+        torch.cuda.synchronize()
+        cur = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cur)
+        for st in tstreams[:m]:
+            st.wait_stream(cur)
+        for i in range(args.steps):
+            tplans[i % m].execute_batch(X, seeds, stream=tstreams[i % m], bufs=tbufs[i % m])
+        for st in tstreams[:m]:
+            cur.wait_stream(st)
+        e1.record(cur)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
 
     # ---------------------------------------------------------------- batched
-    # throughput: K steps queued back to back on one stream, bracketed by a
-    # synchronisation on each side
-    for _ in range(args.warmup):
-        tplan.execute_batch(X, seeds, bufs=tbufs)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        tplan.execute_batch(X, seeds, bufs=tbufs)
-    ev1.record()
-    torch.cuda.synchronize()
-    elapsed_ms = ev0.elapsed_time(ev1)
-    ms_per_step = elapsed_ms / args.steps
+    by_inflight = {}
+    for m in sorted({1, inflight}):
+        by_inflight[m] = throughput(m)
+        log("throughput with %d batch(es) in flight: %.3f ms/step, %.0f sFFTs/s"
+            % (m, by_inflight[m], S / by_inflight[m] * 1e3))
+    ms_per_step = by_inflight[inflight]
+    elapsed_ms = ms_per_step * args.steps
     value = S * args.steps / (elapsed_ms / 1e3)
     # phases and per-step latency: K more steps on the plan with phase
     # events, each step waited for
@@ -796,12 +816,13 @@ def main():
     log("batched: %.3f ms/step, %.0f sFFTs/s; steps waited for one by one: %.3f ms (hash %.3f ms, decode %.3f ms "
         "overlapped, tail %.3f ms, %d chunks)" % (ms_per_step, value, np.mean(step_ms), np.mean(h2b_ms),
                                                    np.mean(dec_ms), np.mean(tail_ms), chunks))
-    same = all(torch.equal(tbufs[f], bufs[f]) for f in ("idx", "val", "counts"))
+    same = all(torch.equal(tb[f], bufs[f]) for tb in tbufs for f in ("idx", "val", "counts"))
     log("throughput and phase plans give identical outputs: %s" % same)
     if not same:
-        raise SystemExit("the throughput plan's outputs differ from the phase plan's")
-    tplan.close()
-    del tbufs
+        raise SystemExit("the throughput plans' outputs differ from the phase plan's")
+    for tp in tplans:
+        tp.close()
+    del tbufs, tplans
 
     counts = bufs["counts"].cpu().numpy()
     info = bufs["info"].cpu().numpy()
@@ -981,11 +1002,14 @@ def main():
                    "alpha_decay": desc.alpha_decay, "samples_per_signal_group0": sfft.sfft_plan_samples(desc),
                    "hash_threads": desc.hash_threads, "hash_order": desc.hash_order,
                    "hash_split": desc.hash_split, "window": ["gaussian", "kaiser-bessel"][desc.window],
+                   "inflight": inflight,
                    "chunks": chunks,
                    "loc_prec": "f64" if desc.loc_prec == sfft.SFFT_F64 else "f32",
                    "refine_shift": desc.refine_shift, "refine_window": desc.refine_window,
                    "input": "complex64"},
         "autotune": tune_rec,
+        "throughput_by_inflight": {str(m): {"ms_per_step": round(t, 4), "sFFTs_per_s": round(S / t * 1e3, 1)}
+                                   for m, t in by_inflight.items()},
         "latency_ms": {"p10": round(percentile(step_ms, 10), 4), "p50": round(percentile(step_ms, 50), 4),
                        "p90": round(percentile(step_ms, 90), 4), "p99": round(percentile(step_ms, 99), 4),
                        "steps": len(step_ms),
