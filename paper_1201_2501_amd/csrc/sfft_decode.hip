@@ -928,36 +928,32 @@ __device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, do
     __syncthreads();
     const uint32_t T = P->cnt[1];
     if (T > kPeelT) return give_up();
-    // room for each task's unresolved neighbours
-    for (uint32_t t = tid; t < T; t += kDec) {
-        const uint64_t tk = P->task[t];
-        const uint32_t e = P->ulist[tk & 0xFFFFu], q = (uint32_t)(tk >> 16) & 0xFFu;
-        const uint32_t w = V.grp[q * V.ms + (uint64_t)e * V.es];
-        const uint16_t* o = V.ord + (uint64_t)q * V.capz + (w >> 16);
-        uint32_t left = 0;
-#pragma unroll 4
-        for (uint32_t i = 0; i < (w & 0xFFFFu); ++i) left += o[i] != e && res[o[i]] != 1;
-        const uint32_t off = atomicAdd(&P->cnt[2], left);
-        if (left > 255 || off + left > P->nbcap) P->cnt[3] = 1;
-        P->task[t] = tk | (uint64_t)(left & 0xFFu) << 24 | (uint64_t)off << 32;
-    }
-    __syncthreads();
-    if (P->cnt[3]) return give_up();
     // each task's sample with the neighbours resolved in pass 1 subtracted
-    // (their values are final), and the other neighbours listed
+    // (their values are final), and its other neighbours listed: one walk
+    // of the bin's members counts them and takes room in the neighbour
+    // lists, a second (cached) walk fills it
     for (uint32_t t = tid; t < T; t += kDec) {
         const uint64_t tk = P->task[t];
         const uint32_t e = P->ulist[tk & 0xFFFFu], q = (uint32_t)(tk >> 16) & 0xFFu;
         const uint64_t s = q * V.ms + (uint64_t)e * V.es;
         const uint32_t w = V.grp[s];
-        const uint16_t* o = V.ord + (uint64_t)q * V.capz + (w >> 16);
+        const double2 es = make_double2(V.est[2 * s], V.est[2 * s + 1]);
         const cx<double> ce{V.coef[2 * s], V.coef[2 * s + 1]};
+        const uint16_t* o = V.ord + (uint64_t)q * V.capz + (w >> 16);
+        const uint32_t nm = w & 0xFFFFu;
+        uint32_t left = 0;
+#pragma unroll 4
+        for (uint32_t i = 0; i < nm; ++i) left += o[i] != e && res[o[i]] != 1;
+        const uint32_t off = atomicAdd(&P->cnt[2], left);
+        const bool fits = left <= 255 && off + left <= P->nbcap;
+        if (!fits) P->cnt[3] = 1;
+        P->task[t] = tk | (uint64_t)(left & 0xFFu) << 24 | (uint64_t)off << 32;
         const double n2 = ce.r * ce.r + ce.i * ce.i;
         const cx<double> inv{ce.r / n2, -ce.i / n2};
         cx<double> acc{0.0, 0.0};
-        uint32_t j = (uint32_t)(tk >> 32);
+        uint32_t j = off;
 #pragma unroll 4
-        for (uint32_t i = 0; i < (w & 0xFFFFu); ++i) {
+        for (uint32_t i = 0; i < nm; ++i) {
             const uint32_t e2 = o[i];
             if (e2 == e) continue;
             const uint64_t s2 = q * V.ms + (uint64_t)e2 * V.es;
@@ -965,7 +961,7 @@ __device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, do
             const uint16_t r2 = res[e2];
             if (r2 == 1) {
                 acc = cadd(acc, cmul(c2, cx<double>{fin[2 * e2] - zv[2 * e2], fin[2 * e2 + 1] - zv[2 * e2 + 1]}));
-            } else {
+            } else if (fits) {
                 const cx<double> ra = cmul(c2, inv);
                 if (P->real) {
                     P->ratio[j] = ra.r;
@@ -977,9 +973,10 @@ __device__ void peel_values(const PeelView& V, uint32_t zc, const double* zv, do
             }
         }
         const cx<double> d = cmul(acc, inv);
-        P->tsamp[t] = make_double2(V.est[2 * s] - d.r, V.est[2 * s + 1] - d.i);
+        P->tsamp[t] = make_double2(es.x - d.r, es.y - d.i);
     }
     __syncthreads();
+    if (P->cnt[3]) return give_up();
     const double* ts = reinterpret_cast<const double*>(P->tsamp);
     auto subtract_resolved = [&](uint32_t t, uint64_t tk) {
         const uint32_t c = (uint32_t)(tk >> 24) & 0xFFu, off = (uint32_t)(tk >> 32);
