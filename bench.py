@@ -693,9 +693,16 @@ def main():
                                           99991 * (i + 1), sb)
                 return confirm_batches[i]
 
+            # the stored choice for this device and shape (any build) joins
+            # the search as an incumbent
+            prev = autotune.lookup(TUNE_FILE, n, k, sfft.SFFT_MODE_EXACT, S, sfft.SFFT_C64,
+                                   autotune.device_tag(dev), any_build=True)
+            incumbents = [dict(prev.fields, B=prev.B)] if prev is not None else []
+            if incumbents:
+                log("autotune: incumbent %s" % ", ".join("%s=%s" % kv for kv in sorted(incumbents[0].items())))
             res = autotune.tune(Xc, k, sfft.SFFT_MODE_EXACT, seeds=seeds_c, truth=sup_c, base=base_kw,
                                 budget_s=args.tune_budget, cache=args.tune_out or None, log=log, force=True,
-                                confirm=confirm, confirm_batches=args.tune_confirm)
+                                confirm=confirm, confirm_batches=args.tune_confirm, incumbents=incumbents)
             del Xc
             confirm_batches.clear()
             torch.cuda.empty_cache()

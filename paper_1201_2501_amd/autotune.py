@@ -350,14 +350,19 @@ class _Runner:
 
 def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, space=None, reps=3,
          budget_s=120.0, cache=None, recall_slack=0.005, log=None, force=False, confirm=None,
-         confirm_batches=4, confirm_top=16, beam=3, launch_margin=0.01, passes=2):
+         confirm_batches=4, confirm_top=16, beam=3, launch_margin=0.01, passes=2, incumbents=None):
     """Tune the plan of a batch x ([count, n] complex device tensor) with
     sparsity k.  base: plan fields kept fixed (e.g. theta, rounds, loc_prec,
     flags); space: {"bins": {...}, "window": {...}, "schedule": {...}, ...}
     lists of candidate values (default_space when None); truth: per-signal
     planted supports, else the reference candidate's supports are the
     target; confirm: i -> (x_i, seeds_i, truth_i or None), fresh batches of
-    the same shape for the confirmations (called again for the same i).  Returns a TuneResult; with
+    the same shape for the confirmations (called again for the same i);
+    incumbents: complete candidates (plan fields with "B") known to be good,
+    e.g. a stored choice of another library build: they are timed after the
+    reference and take part in the beam and the confirmations like any
+    other candidate, so that a search whose beam wanders (its order follows
+    measured times) still compares against them.  Returns a TuneResult; with
     `cache`, a stored result for the same key is returned without measuring
     (unless force)."""
     import torch
@@ -382,6 +387,10 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
         raise RuntimeError("autotune: the reference candidate %r is not a valid plan" % ref)
     ref_rec, ref_sups = out
     runner.ref_supports = ref_sups
+    for inc in incumbents or []:
+        cand = normalize(dict(base, **inc))
+        if not any(r.get("cand") == cand for r in runner.table):
+            runner.evaluate(cand)
     if truth is None:
         ref_rec["quality"] = 1.0
     floor = ref_rec["quality"] - (recall_slack if mode == sfft.SFFT_MODE_GENERAL else 0.0)

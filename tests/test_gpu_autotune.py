@@ -60,6 +60,41 @@ def test_autotune_small_exact_batch(tmp_path):
     plan.close()
 
 
+def test_autotune_incumbent_joins_the_search():
+    """A known-good candidate outside the search space (an incumbent, e.g. a
+    stored choice of another build) is timed right after the reference,
+    takes part in the confirmations, and the choice is no slower than it."""
+    import torch
+    from paper_1201_2501_amd import autotune, sfft
+
+    sfft.load()
+    dev = torch.device("cuda:0")
+    n, k, count = 1 << 18, 32, 32
+    say("autotune-incumbent", "n", n, "k", k, "count", count)
+    X, sups, _ = siggen.torch_planted_batch(n, k, [9000 + s for s in range(count)], dev, magnitude="loguniform")
+    seeds = torch.arange(count, dtype=torch.int64, device=dev) * 17 + 1
+    space = {"bins": {"B": [256]}, "window": {"delta": [1e-9]}, "schedule": {"b_min": [32], "patience": [4]}}
+    base = dict(theta=0.02, rounds=24, loc_prec=sfft.SFFT_F64)
+    kept = {}
+
+    def confirm(i):
+        if i not in kept:
+            xb, sb, _ = siggen.torch_planted_batch(n, k, [9500 + 100 * i + s for s in range(count)], dev,
+                                                   magnitude="loguniform")
+            kept[i] = (xb, torch.arange(count, dtype=torch.int64, device=dev) * 23 + 7 + i, sb)
+        return kept[i]
+
+    inc = dict(B=128, b_min=16, patience=4, delta=1e-9)
+    res = autotune.tune(X, k, sfft.SFFT_MODE_EXACT, seeds=seeds, truth=sups, base=base, space=space, reps=2,
+                        confirm=confirm, confirm_batches=2, incumbents=[inc])
+    rec = res.table[1]
+    assert rec["cand"]["B"] == 128 and rec["cand"]["b_min"] == 16 and "ms" in rec
+    assert res.quality == 1.0
+    assert res.ms <= res.table[0]["ms"]                  # no slower than the reference
+    if res.B == 128:                                     # the incumbent (or a launch variant of it) won
+        assert res.ms <= rec["ms"]
+
+
 def test_autotune_small_general_batch(tmp_path):
     """General mode: candidates are accepted on their recall of the planted
     heads (within the slack of the reference candidate's), the choice keeps
