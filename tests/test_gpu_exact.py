@@ -177,6 +177,47 @@ def test_graph_replays_are_identical_and_batch_independent(torch_dev):
     alone.close()
 
 
+@pytest.mark.parametrize("shape", ["c1", "c3"])
+def test_graph_replays_match_eager_launches(torch_dev, shape, monkeypatch):
+    """Every replay of the captured step (one graph without phase events,
+    the hash and decode graphs with them) equals the same step launched
+    kernel by kernel (SFFT_NO_GRAPH=1), with eager work and synchronisations
+    between the replays."""
+    from paper_1201_2501_amd import sfft
+
+    torch, dev = torch_dev
+    if shape == "c1":
+        n, k, B, w = c1_case(0)
+        count, kw = 6, dict(delta=1e-12, in_dtype=1, loc_prec=1)
+        xs = [siggen.planted_signal(n, k, 400 + s, np.complex128)[0] for s in range(count)]
+        X = torch.from_numpy(np.stack(xs)).to(dev)
+    else:
+        n, k, B, count = 1 << 22, 256, 1024, 4
+        kw = dict(delta=1e-7, alpha=0.7, window=1, theta=0.02, b_min=64, patience=4, ratio_tol=0.002,
+                  g_min=0.25, stop_count=256, stop_patience=3, group_step=3)
+        w = 0
+        X, _, _ = siggen.torch_planted_batch(n, k, [600 + s for s in range(count)], dev, magnitude="loguniform")
+    say("graph-vs-eager", shape, "n", n, "count", count)
+    S = torch.tensor([11 + s for s in range(count)], dtype=torch.int64, device=dev)
+    monkeypatch.setenv("SFFT_NO_GRAPH", "1")
+    eager_plan = plan_for(n, k, B, w, 0, max_batch=count, **kw)
+    b = eager_plan.execute_batch(X, S)
+    torch.cuda.synchronize()
+    want = {key: t.clone() for key, t in b.items()}
+    monkeypatch.delenv("SFFT_NO_GRAPH")
+    for flags in (0, sfft.SFFT_FLAG_TIMING):
+        plan = plan_for(n, k, B, w, 0, max_batch=count, flags=flags, **kw)
+        for rep in range(4):
+            b = plan.execute_batch(X, S)
+            torch.cuda.synchronize()
+            for key in want:
+                assert torch.equal(b[key], want[key]), (flags, rep, key)
+            _ = (X.abs() * 2).sum().item()       # eager work between replays
+            b["idx"].zero_()                     # the next replay rewrites every output
+        plan.close()
+    eager_plan.close()
+
+
 def test_plain_and_batched_agree(torch_dev):
     torch, dev = torch_dev
     n, k, B, w = c1_case(0)
