@@ -778,20 +778,23 @@ def main():
 
     def throughput(m):
         """ms per step over K steps with m batches in flight, bracketed by a
-        synchronisation on each side (GPU events on the current stream, which
-        the instance streams join)."""
-        for i in range(max(args.warmup, m)):
-            tplans[i % m].execute_batch(X, seeds, stream=tstreams[i % m], bufs=tbufs[i % m])
-        torch.cuda.synchronize()
+        synchronisation on each side (GPU events on the current stream; with
+        m > 1 the instance streams join it, with m = 1 the steps run on it)."""
         cur = torch.cuda.current_stream()
+        streams = [cur] if m == 1 else tstreams[:m]
+        for i in range(max(args.warmup, m)):
+            tplans[i % m].execute_batch(X, seeds, stream=streams[i % m], bufs=tbufs[i % m])
+        torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(cur)
-        for st in tstreams[:m]:
-            st.wait_stream(cur)
+        for st in streams:
+            if st is not cur:
+                st.wait_stream(cur)
         for i in range(args.steps):
-            tplans[i % m].execute_batch(X, seeds, stream=tstreams[i % m], bufs=tbufs[i % m])
-        for st in tstreams[:m]:
-            cur.wait_stream(st)
+            tplans[i % m].execute_batch(X, seeds, stream=streams[i % m], bufs=tbufs[i % m])
+        for st in streams:
+            if st is not cur:
+                cur.wait_stream(st)
         e1.record(cur)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / args.steps
@@ -803,7 +806,7 @@ def main():
     t_ramp = time.time()
     while time.time() - t_ramp < 0.3:
         for _ in range(20):
-            tplans[0].execute_batch(X, seeds, stream=tstreams[0], bufs=tbufs[0])
+            tplans[0].execute_batch(X, seeds, bufs=tbufs[0])
         torch.cuda.synchronize()
     by_inflight = {}
     for m in sorted({1, inflight}):
