@@ -329,6 +329,13 @@ sfft_status_t sfft_execute(sfft_plan_t p, const void* x_dev, uint64_t* idx_host,
  * runs on `stream`; `stream` waits for the last decode before the call's
  * work is complete.  Each chunk's launch sequences are captured once into
  * hipGraphs and replayed (keyed by the argument pointers and count).
+ * The capture (the first call with a new argument set) runs on a
+ * plan-private stream in thread-local capture mode; other threads of the
+ * process should not allocate, free or synchronise the device while it
+ * runs (a capture on one thread beside such calls on others has failed
+ * with a HIP error); replays carry no such condition.  With the
+ * environment variable SFFT_NO_GRAPH=1 every call launches the kernels
+ * directly, with the same results.  The serving runtime does not capture.
  * Asynchronous on `stream`; nothing is copied to the host.
  *   x_dev      [count][n] signals (in_dtype)
  *   count      1 <= count <= max_batch
