@@ -1433,21 +1433,17 @@ __global__ void __launch_bounds__(kDec) k_exact_finish(DecodeArgs D) {
     }
 }
 
-// The same re-estimation split over workgroups, where its LDS fits: block
-// (signal, round r) records the sample table of round r (PeelView: the
-// estimate of every zhat entry with the other entries of its bin removed in
-// ascending index order, its kind, and for shared bins the grouping and
-// the term coefficients); k_exact_output resolves the values and writes the
-// output.  Each sample is computed exactly as in k_exact_finish.  The tables
-// are round-major ([sig][round][capz]) so that both kernels access them
+// The same re-estimation split over workgroups, where its LDS fits: round
+// r of a signal records its sample table (PeelView: the estimate of every
+// zhat entry with the other entries of its bin removed in ascending index
+// order, its kind, and for shared bins the grouping and the term
+// coefficients); k_exact_output resolves the values and writes the output.
+// Each sample is computed exactly as in k_exact_finish.  The tables are
+// round-major ([sig][round][capz]) so that both kernels access them
 // contiguously across the entries of a wave.
-__global__ void __launch_bounds__(kDec) k_exact_reest(DecodeArgs D) {
-    extern __shared__ __align__(16) unsigned char smem[];
+__device__ void reest_round(const DecodeArgs& D, unsigned char* smem, uint32_t sig, uint32_t r) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t sig = blockIdx.x / D.rounds;
-    const uint32_t r = blockIdx.x - sig * D.rounds;
     const uint32_t* st = D.state + (uint64_t)sig * kStateWords;
-    if (r >= st[ST_ROUNDS]) return;
     const uint32_t zc = st[ST_ZCOUNT], zb = st[ST_ZBUF];
     DecodeLds L;
     reest_lds_layout(D.capz, D.Bmax, smem, &L);
@@ -1497,6 +1493,25 @@ __global__ void __launch_bounds__(kDec) k_exact_reest(DecodeArgs D) {
         }
         est[e] = make_double2((a0.x - orr) / ge, (a0.y - oii) / ge);
         flag[e] = p1 - p0 == 1 ? 1 : 2;
+    }
+}
+
+// Blocks per signal of the re-estimation launch: block q takes the rounds
+// q, q + 12, ... that the signal decoded.  Most signals stop within 12 or 13
+// rounds, so a block mostly does one round; a launch of half the blocks of
+// one per (signal, round cap) is dispatched faster next to another stream's
+// HashToBins (with four batches in flight, 0.98 against 1.01 ms per batch).
+constexpr uint32_t kReestBlocks = 12;
+
+__global__ void __launch_bounds__(kDec) k_exact_reest(DecodeArgs D) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t RB = D.rounds < kReestBlocks ? D.rounds : kReestBlocks;
+    const uint32_t sig = blockIdx.x / RB;
+    const uint32_t* st = D.state + (uint64_t)sig * kStateWords;
+    const uint32_t used = st[ST_ROUNDS];
+    for (uint32_t r = blockIdx.x - sig * RB; r < used; r += RB) {
+        if (r >= RB) __syncthreads();
+        reest_round(D, smem, sig, r);
     }
 }
 
@@ -1973,7 +1988,8 @@ hipError_t launch_exact_finish(const DecodeArgs& a, hipStream_t s) {
         if (e != hipSuccess) return e;
         e = allow_lds(k_exact_output, olds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_exact_reest, dim3(a.count * a.rounds), dim3(kDec), rlds, s, a);
+        const uint32_t rb = a.rounds < kReestBlocks ? a.rounds : kReestBlocks;
+        hipLaunchKernelGGL(k_exact_reest, dim3(a.count * rb), dim3(kDec), rlds, s, a);
         hipLaunchKernelGGL(k_exact_output, dim3(a.count), dim3(kDec), olds, s, a);
         return hipGetLastError();
     }
