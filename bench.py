@@ -800,14 +800,6 @@ def main():
         return e0.elapsed_time(e1) / args.steps
 
     # ---------------------------------------------------------------- batched
-    # untimed steps for at least 0.3 s before the first timed loop: a step
-    # timed right after the set-up ran up to 20 % slower (the whole step, not
-    # one kernel), as if the device had not reached its running clocks
-    t_ramp = time.time()
-    while time.time() - t_ramp < 0.3:
-        for _ in range(20):
-            tplans[0].execute_batch(X, seeds, bufs=tbufs[0])
-        torch.cuda.synchronize()
     by_inflight = {}
     for m in sorted({1, inflight}):
         by_inflight[m] = throughput(m)
