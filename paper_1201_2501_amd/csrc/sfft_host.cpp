@@ -163,6 +163,11 @@ struct GraphCache {
     const void* o4 = nullptr;
     uint32_t count = 0;
     bool whole = false;   // exec_h[0] holds the whole step (one chunk, no phase events)
+    // recorded after every replay: the graphs are destroyed (new arguments,
+    // plan destroyed) only once their last replay has finished, so a replay
+    // still queued on some stream never depends on how the runtime defers
+    // the destruction of an executable graph in flight
+    hipEvent_t launched = nullptr;
 };
 
 struct sfft_plan_s {
@@ -1156,6 +1161,10 @@ sfft_status_t sfft_plan_get_desc(sfft_plan_t p, sfft_plan_desc_t* out) {
 
 sfft_status_t sfft_destroy(sfft_plan_t p) {
     if (!p) return SFFT_OK;
+    if (p->graph.launched) {
+        (void)hipEventSynchronize(p->graph.launched);
+        (void)hipEventDestroy(p->graph.launched);
+    }
     for (uint32_t c = 0; c < kMaxChunks; ++c) {
         if (p->graph.exec_h[c]) (void)hipGraphExecDestroy(p->graph.exec_h[c]);
         if (p->graph.exec_d[c]) (void)hipGraphExecDestroy(p->graph.exec_d[c]);
@@ -1386,6 +1395,7 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
                          gc.seeds == seeds_dev && gc.o1 == idx_dev && gc.o2 == val_dev && gc.o3 == count_dev &&
                          gc.o4 == info_dev;
         if (!hit) {
+            if (gc.launched) HIP_TRY(hipEventSynchronize(gc.launched));
             for (uint32_t c = 0; c < kMaxChunks; ++c) {
                 if (gc.exec_h[c]) HIP_TRY(hipGraphExecDestroy(gc.exec_h[c]));
                 if (gc.exec_d[c]) HIP_TRY(hipGraphExecDestroy(gc.exec_d[c]));
@@ -1419,8 +1429,10 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
     // single chunk has nothing to overlap: its decode follows on s itself
     // (a cross-stream wait costs tens of microseconds per step)
     hipStream_t ds = C > 1 ? p->aux_stream : s;
+    if (use_graph && !gc.launched) HIP_TRY(hipEventCreateWithFlags(&gc.launched, hipEventDisableTiming));
     if (whole) {
         HIP_TRY(hipGraphLaunch(gc.exec_h[0], s));
+        HIP_TRY(hipEventRecord(gc.launched, s));
         return SFFT_OK;
     }
     if (timing) HIP_TRY(hipEventRecord(p->ev_t0, s));
@@ -1459,6 +1471,7 @@ sfft_status_t sfft_execute_batch(sfft_plan_t p, const void* x_dev, uint32_t coun
         p->timed_chunks = C;
         p->timed_once = true;
     }
+    if (use_graph) HIP_TRY(hipEventRecord(gc.launched, s));
     return SFFT_OK;
 }
 

@@ -218,6 +218,49 @@ def test_graph_replays_match_eager_launches(torch_dev, shape, monkeypatch):
     eager_plan.close()
 
 
+def test_plans_on_several_streams_match_one_plan(torch_dev):
+    """Several batches in flight (one plan instance and stream each, calls
+    queued without waiting, the way the throughput measurement runs them)
+    give, call by call, the results of one plan running the batches in turn."""
+    torch, dev = torch_dev
+    n, k, B, w = c1_case(0)
+    count, m, calls = 6, 3, 9
+    say("streams-in-flight", "n", n, "count", count, "plans", m)
+    kw = dict(delta=1e-12, in_dtype=1, loc_prec=1, max_batch=count)
+    batches = []
+    for c in range(calls):
+        xs = [siggen.planted_signal(n, k, 1300 + 10 * c + s, np.complex128)[0] for s in range(count)]
+        batches.append((torch.from_numpy(np.stack(xs)).to(dev),
+                        torch.tensor([71 * c + s for s in range(count)], dtype=torch.int64, device=dev)))
+    ref_plan = plan_for(n, k, B, w, 0, **kw)
+    want = []
+    for X, S in batches:
+        b = ref_plan.execute_batch(X, S)
+        torch.cuda.synchronize()
+        want.append({key: t.clone() for key, t in b.items()})
+    plans = [plan_for(n, k, B, w, 0, **kw) for _ in range(m)]
+    streams = [torch.cuda.Stream() for _ in range(m)]
+    # one output set per call (batch_buffers keeps one set per plan), so that
+    # no call waits for another's results
+    def out_set(plan):
+        return dict(idx=torch.zeros((count, plan.cap), dtype=torch.int64, device=dev),
+                    val=torch.zeros((count, plan.cap), dtype=torch.complex128, device=dev),
+                    counts=torch.zeros(count, dtype=torch.int32, device=dev),
+                    info=torch.zeros((count, 4), dtype=torch.int32, device=dev))
+    outs = [out_set(plans[c % m]) for c in range(calls)]
+    cur = torch.cuda.current_stream()
+    for st in streams:
+        st.wait_stream(cur)
+    for c, (X, S) in enumerate(batches):
+        plans[c % m].execute_batch(X, S, stream=streams[c % m], bufs=outs[c])
+    torch.cuda.synchronize()
+    for c in range(calls):
+        for key in ("idx", "val", "counts", "info"):
+            assert torch.equal(outs[c][key], want[c][key]), (c, key)
+    for p in plans + [ref_plan]:
+        p.close()
+
+
 def test_plain_and_batched_agree(torch_dev):
     torch, dev = torch_dev
     n, k, B, w = c1_case(0)
