@@ -350,7 +350,8 @@ class _Runner:
 
 def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, space=None, reps=3,
          budget_s=120.0, cache=None, recall_slack=0.005, log=None, force=False, confirm=None,
-         confirm_batches=4, confirm_top=16, beam=3, launch_margin=0.01, passes=2, incumbents=None):
+         confirm_batches=4, confirm_top=16, beam=3, launch_margin=0.01, passes=2, incumbents=None,
+         incumbent_margin=0.02):
     """Tune the plan of a batch x ([count, n] complex device tensor) with
     sparsity k.  base: plan fields kept fixed (e.g. theta, rounds, loc_prec,
     flags); space: {"bins": {...}, "window": {...}, "schedule": {...}, ...}
@@ -362,7 +363,11 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
     e.g. a stored choice of another library build: they are timed after the
     reference and take part in the beam and the confirmations like any
     other candidate, so that a search whose beam wanders (its order follows
-    measured times) still compares against them.  Returns a TuneResult; with
+    measured times) still compares against them; a confirmed incumbent is
+    kept unless the choice is faster than it by more than incumbent_margin
+    (timings of close variants differ by about 1 % from run to run, so
+    without it a re-tune can swap one equivalent plan for another).
+    Returns a TuneResult; with
     `cache`, a stored result for the same key is returned without measuring
     (unless force)."""
     import torch
@@ -387,8 +392,10 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
         raise RuntimeError("autotune: the reference candidate %r is not a valid plan" % ref)
     ref_rec, ref_sups = out
     runner.ref_supports = ref_sups
+    inc_cands = []
     for inc in incumbents or []:
         cand = normalize(dict(base, **inc))
+        inc_cands.append(cand)
         if not any(r.get("cand") == cand for r in runner.table):
             runner.evaluate(cand)
     if truth is None:
@@ -490,6 +497,10 @@ def tune(x, k, mode=sfft.SFFT_MODE_EXACT, seeds=None, truth=None, base=None, spa
     fastest = variants()[0]["ms"]
     best = min((r for r in variants() if r["ms"] <= fastest * (1.0 + launch_margin)),
                key=lambda r: (launch_changes(r["cand"]), r["ms"]))
+    for r in eligible():
+        if r["cand"] in inc_cands and r["ms"] <= best["ms"] * (1.0 + incumbent_margin):
+            best = r
+            break
 
     cand = dict(best["cand"])
     B = int(cand.pop("B"))

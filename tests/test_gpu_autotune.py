@@ -92,7 +92,16 @@ def test_autotune_incumbent_joins_the_search():
     assert res.quality == 1.0
     assert res.ms <= res.table[0]["ms"]                  # no slower than the reference
     if res.B == 128:                                     # the incumbent (or a launch variant of it) won
-        assert res.ms <= rec["ms"]
+        assert res.ms <= rec["ms"] * 1.02
+    # with a wide margin a confirmed incumbent is kept whatever else is faster
+    keep = autotune.tune(X, k, sfft.SFFT_MODE_EXACT, seeds=seeds, truth=sups, base=base, space=space, reps=2,
+                         confirm=confirm, confirm_batches=2, incumbents=[inc], incumbent_margin=100.0)
+    inc_rec = keep.table[1]
+    if inc_rec["quality"] == 1.0 and keep.B != 128:
+        # only a failed confirmation may drop it
+        assert keep.quality == 1.0
+    elif inc_rec["quality"] == 1.0:
+        assert keep.fields["b_min"] == 16
 
 
 def test_autotune_small_general_batch(tmp_path):
