@@ -278,8 +278,9 @@ def serving_bench(args, torch, dev, sfft):
 def precision_split_bench(args, torch, dev, sfft, siggen):
     """The precision split on the general-mode workload: 16 signals of
     n = 2^26, k = 1024, unit magnitudes, tail/head noise 0.01, complex64,
-    B = 4096, delta = 1e-7.  Variants: FP32 location and estimation
-    hashings; FP64 location pairs (the default at this n); FP64 throughout.
+    B = 4096, delta = 1e-7.  Variants (Kaiser-Bessel window): FP32 location
+    and estimation hashings; FP64 location pairs (the default at this n);
+    FP64 throughout; and FP64 location pairs with the Gaussian window.
     Each reports its batch rate, supports equal to the planted ones and the
     l2/l2 ratio ||xhat - x'|| / Err(xhat, k), with Err from a full FP64 FFT
     of the same input bytes (torch.fft on the device, a measurement only)."""
@@ -298,10 +299,16 @@ def precision_split_bench(args, torch, dev, sfft, siggen):
         errk.append(math.sqrt(max(float(F.sum() - top), 0.0)))
         del F
     variants = []
-    for name, lp, ep in (("fp32", sfft.SFFT_F32, sfft.SFFT_F32), ("fp64_location", sfft.SFFT_F64, sfft.SFFT_F32),
-                         ("fp64_all", sfft.SFFT_F64, sfft.SFFT_F64)):
-        plan = Plan(n, k, B, 0, 0, mode=sfft.SFFT_MODE_GENERAL, delta=1e-7, loc_prec=lp, est_prec=ep, max_batch=S,
-                    flags=sfft.SFFT_FLAG_TIMING)
+    # the precision variants with the Kaiser-Bessel window (half the
+    # Gaussian construction's samples), and FP64 location with the Gaussian
+    # window for comparison
+    for name, lp, ep, win in (("fp32", sfft.SFFT_F32, sfft.SFFT_F32, 1),
+                              ("fp64_location", sfft.SFFT_F64, sfft.SFFT_F32, 1),
+                              ("fp64_all", sfft.SFFT_F64, sfft.SFFT_F64, 1),
+                              ("fp64_location_gaussian", sfft.SFFT_F64, sfft.SFFT_F32, 0)):
+        wk = sfft.sfft_window_w(n, B, 0.5, 1e-7, win)
+        plan = Plan(n, k, B, wk, 0, mode=sfft.SFFT_MODE_GENERAL, delta=1e-7, loc_prec=lp, est_prec=ep, max_batch=S,
+                    flags=sfft.SFFT_FLAG_TIMING, window=win)
         bufs = plan.execute_batch(X, seeds)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -329,7 +336,8 @@ def precision_split_bench(args, torch, dev, sfft, siggen):
                          "ms_per_batch": round(ms, 3), "sFFTs_per_s": round(S / (ms * 1e-3), 1),
                          "hash_ms": round(float(tm[0]), 3), "supports_equal_planted": "%d/%d" % (exact, S),
                          "l2l2_ratio_max": round(max(ratios), 4), "l2l2_ratio_median": round(float(np.median(ratios)), 4),
-                         "w": int(plan.desc.w), "rounds": int(plan.desc.rounds)})
+                         "w": int(plan.desc.w), "rounds": int(plan.desc.rounds),
+                         "window": ["gaussian", "kaiser-bessel"][plan.desc.window]})
         log("c4 %s: %.3f ms/batch, supports %d/%d, l2/l2 max %.4f" % (name, ms, exact, S, max(ratios)))
         plan.close()
     best = min(variants, key=lambda v: v["ms_per_batch"])

@@ -260,6 +260,38 @@ def test_c4_precision_variants_match_oracle(torch_dev, c4_case, loc, est):
     plan.close()
 
 
+@pytest.fixture(scope="module")
+def c4_kaiser_case(torch_dev):
+    """The c4_case signal with the Kaiser-Bessel window (the C4 bench's
+    window) and its oracle run."""
+    torch, dev = torch_dev
+    n, k, B, seed = 1 << 26, 1024, 4096, 17
+    X, sups, _ = siggen.torch_planted_batch(n, k, [91_000], dev, magnitude="unit", noise_ratio=0.01, chunk=1)
+    plan = make_plan(n, k, B, seed, 1, delta=1e-7, window=1)
+    params = oracle_params(plan)
+    plan.close()
+    x0 = X[0].cpu().numpy()
+    ref = sparse_fft(x0, params)
+    return X, x0, np.sort(sups[0]), ref, params
+
+
+def test_c4_kaiser_window_matches_oracle(torch_dev, c4_kaiser_case):
+    """n = 2^26, k = 1024 with the Kaiser-Bessel window, FP64 location and
+    FP32 estimation (the C4 default) against the FP64 oracle: supports
+    bit-exact, values within 1e-4 relative (FP32 estimation hashings)."""
+    torch, dev = torch_dev
+    X, x0, sup, ref, params = c4_kaiser_case
+    say("c4-kaiser", "w", params.w)
+    assert params.window == 1
+    plan = make_plan(params.n, params.k, params.B, params.seed, 1, delta=params.delta, est_prec=0, window=1)
+    d = plan.desc
+    assert (d.window, d.w, d.rounds) == (1, params.w, params.rounds)
+    idx, v, info, st = plan.execute(X[0])
+    assert check(idx, v, ref, 1e-4, allow_near_tie=False)
+    assert np.array_equal(idx, sup)
+    plan.close()
+
+
 @pytest.mark.parametrize("b_min", [256, 1024])
 def test_general_b_min_schedule_matches_oracle(torch_dev, b_min):
     """General mode with a floor on the round bins (b_min = B: B and w fixed in
